@@ -1,0 +1,316 @@
+"""CPU oracle of the GIS graph-construction path -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, __graft_entry__.smoke() and the cpu_baseline leg of bench.py may
+import this package.  It wraps gis_oracle.c (plain single-threaded FP64 C,
+compiled with gcc -ffp-contract=off) through ctypes and composes its steps
+into the paper's iteration loop (Sec. 2 and Sec. 3.1 of Decardi-Nelson and
+Liu, arXiv 2202.06111).  It shares no code with the HIP library.
+
+Parity status per function (what pins each one is in tests/test_oracle_*.py):
+  step / images   pinned: RK4 closed form on linear fields, scipy integration
+                  of the stated ODEs, 4th-order error ratio
+  cover           pinned: exact rational brute force on dyadic grids
+  build           pinned: identity-map stencil, brute-force box/cell overlap
+  prune           pinned: brute-force subset enumeration, drift/contraction
+                  special cases, 1-D linear closed-form invariant interval,
+                  textbook non-leaving set via strongly connected components
+  boundary        pinned: the 5x5 worked example of Sec. 3.1.1 and Remark 1
+  subdivide/solve pinned: union preservation and monotone shrinking
+  query           pinned: brute-force point location over the cell list
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gis_oracle.c")
+_LIB = os.path.join(_HERE, "libgis_oracle.so")
+
+_KINDS = {"linear": 0, "vdp": 1, "lorenz": 2, "vdp2": 3}
+_SCHEMES = {"lattice3": 1, "corners_center": 2}
+_RULES = {"shell": 1, "corners": 2}
+
+
+def build() -> str:
+    """Compile the oracle with gcc (FP64, no contraction, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
+           "-ffp-contract=off", "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Sys(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("nsub", ctypes.c_int32), ("dt", ctypes.c_double), ("p", ctypes.c_double * 32)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n0", ctypes.c_int32 * 4),
+                ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I32, I64 = ctypes.c_int32, ctypes.c_int64
+        lib.or_step.argtypes = [P, P, P, P]
+        lib.or_num_samples.argtypes = [I32, I32]
+        lib.or_num_samples.restype = I32
+        lib.or_images.argtypes = [P, P, I32, P, P, I64, P, I32, P]
+        lib.or_cover.argtypes = [P, I32, P, P, P, P]
+        lib.or_cover.restype = I32
+        lib.or_max_level.argtypes = [P, I64]
+        lib.or_max_level.restype = I32
+        lib.or_build.argtypes = [P, P, I32, P, P, I64, P, I32, I32, P, I64, P, P, P]
+        lib.or_build.restype = I64
+        lib.or_free.argtypes = [P]
+        lib.or_bboxes.argtypes = [P, P, I32, P, P, P, I32, P, I64, P, P, P]
+        lib.or_prune.argtypes = [P, P, P, I64, I32, I32, P, P, I32]
+        lib.or_prune.restype = I32
+        lib.or_boundary.argtypes = [P, P, P, I64, P, I32, P]
+        lib.or_boundary.restype = I32
+        lib.or_subdivide.argtypes = [P, P, P, I64, P, P, P, P, I64]
+        lib.or_subdivide.restype = I64
+        lib.or_query.argtypes = [P, P, P, I64, P, P, I32, P, I64, P, P]
+        lib.or_query.restype = I32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _sys(system) -> _Sys:
+    s = _Sys()
+    s.kind = _KINDS[system.kind]
+    s.n, s.m, s.nsub, s.dt = system.n, system.m, system.nsub, system.dt
+    p = np.zeros(32)
+    p[: len(system.params)] = system.params
+    for i in range(32):
+        s.p[i] = p[i]
+    return s
+
+
+def _grid(grid) -> _Grid:
+    g = _Grid()
+    g.n = grid.n
+    for d in range(grid.n):
+        g.n0[d] = grid.n0[d]
+        g.lo[d] = grid.lo[d]
+        g.hi[d] = grid.hi[d]
+    return g
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def mask_words(K: int) -> int:
+    return (K + 63) // 64
+
+
+# ------------------------------------------------------------------ steps
+def step(system, x: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """x+ = f(x, u) of Eq. (1) for one state (nsub RK4 substeps)."""
+    lib = _load()
+    s = _sys(system)
+    x = _c(x, np.float64)
+    u = _c(u, np.float64)
+    y = np.zeros(system.n)
+    lib.or_step(ctypes.byref(s), _ptr(x), _ptr(u), _ptr(y))
+    return y
+
+
+def num_samples(samples: str, n: int) -> int:
+    return int(_load().or_num_samples(_SCHEMES[samples], n))
+
+
+def coarse_cells(grid):
+    """The full coarse covering C_{d_0}: every level-0 cell, row-major."""
+    axes = [np.arange(k, dtype=np.int32) for k in grid.n0]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    idx = np.stack([g.reshape(-1) for g in mesh], axis=1).astype(np.int32)
+    level = np.zeros(idx.shape[0], dtype=np.uint8)
+    return level, np.ascontiguousarray(idx)
+
+
+def images(system, grid, samples: str, level, idx, u) -> np.ndarray:
+    """Sample images of every row: array [n_cells*K, S, n]."""
+    lib = _load()
+    level, idx, u = _c(level, np.uint8), _c(idx, np.int32), _c(u, np.float64)
+    K = u.shape[0]
+    S = num_samples(samples, grid.n)
+    out = np.zeros((level.shape[0] * K, S, grid.n))
+    s, g = _sys(system), _grid(grid)
+    lib.or_images(ctypes.byref(s), ctypes.byref(g), _SCHEMES[samples], _ptr(level), _ptr(idx),
+                  level.shape[0], _ptr(u), K, _ptr(out))
+    return out
+
+
+def bboxes(system, grid, samples: str, level, idx, u, rows):
+    lib = _load()
+    level, idx, u = _c(level, np.uint8), _c(idx, np.int32), _c(u, np.float64)
+    rows = _c(rows, np.int64)
+    a = np.zeros((rows.shape[0], grid.n))
+    b = np.zeros((rows.shape[0], grid.n))
+    fin = np.zeros(rows.shape[0], dtype=np.uint8)
+    s, g = _sys(system), _grid(grid)
+    lib.or_bboxes(ctypes.byref(s), ctypes.byref(g), _SCHEMES[samples], _ptr(level), _ptr(idx),
+                  _ptr(u), u.shape[0], _ptr(rows), rows.shape[0], _ptr(a), _ptr(b), _ptr(fin))
+    return a, b, fin.astype(bool)
+
+
+def cover(grid, Lstar: int, a, b):
+    """Closed range R, interior range Ri (each [n,2] int64) and OUT_X of a box."""
+    lib = _load()
+    a, b = _c(a, np.float64), _c(b, np.float64)
+    R = np.zeros((grid.n, 2), dtype=np.int64)
+    Ri = np.zeros((grid.n, 2), dtype=np.int64)
+    g = _grid(grid)
+    outx = lib.or_cover(ctypes.byref(g), Lstar, _ptr(a), _ptr(b), _ptr(R), _ptr(Ri))
+    return R, Ri, bool(outx)
+
+
+def build_graph(system, grid, samples: str, level, idx, u, fast_out: bool = False, rows=None):
+    """Symbolic image of the covering (Definition 1) with OUT flags.
+
+    rows=None: every row; returns dict(row_ptr, col, out).
+    rows=array: only those rows; returns dict(cnt, col, out) with col the
+    concatenation of the rows' edge lists in the given order."""
+    lib = _load()
+    level, idx, u = _c(level, np.uint8), _c(idx, np.int32), _c(u, np.float64)
+    K = u.shape[0]
+    n_cells = level.shape[0]
+    if rows is not None:
+        rows = _c(rows, np.int64)
+        n_rows = rows.shape[0]
+    else:
+        n_rows = n_cells * K
+    cnt = np.zeros(n_rows, dtype=np.int64)
+    out = np.zeros(n_rows, dtype=np.uint8)
+    colp = ctypes.c_void_p()
+    s, g = _sys(system), _grid(grid)
+    total = lib.or_build(ctypes.byref(s), ctypes.byref(g), _SCHEMES[samples], _ptr(level),
+                         _ptr(idx), n_cells, _ptr(u), K, int(fast_out), _ptr(rows), n_rows,
+                         _ptr(cnt), _ptr(out), ctypes.byref(colp))
+    if total < 0:
+        raise ValueError(f"oracle build failed ({total}): invalid covering or out of memory")
+    col = np.zeros(total, dtype=np.int32)
+    if total > 0:
+        ctypes.memmove(col.ctypes.data, colp.value, total * 4)
+    lib.or_free(colp)
+    if rows is not None:
+        return {"cnt": cnt, "col": col, "out": out}
+    row_ptr = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(cnt, out=row_ptr[1:])
+    return {"row_ptr": row_ptr, "col": col, "out": out}
+
+
+_ANALYSES = {"controlled": 1, "nonleaving": 2}
+
+
+def prune(row_ptr, col, out, n_cells: int, K: int, analysis: str = "controlled"):
+    """Graph analysis of Sec. 2.3: kept cells K* and per-cell input masks.
+
+    analysis="controlled": largest set in which every cell has an input whose
+    image is not OUT and whose edges all end in the set.
+    analysis="nonleaving": vertices with an infinite admissible path in the
+    input-union symbolic image (Definitions 5-6)."""
+    lib = _load()
+    row_ptr, col, out = _c(row_ptr, np.int64), _c(col, np.int32), _c(out, np.uint8)
+    W = mask_words(K)
+    kept = np.zeros(n_cells, dtype=np.uint8)
+    mask = np.zeros((n_cells, W), dtype=np.uint64)
+    sweeps = lib.or_prune(_ptr(row_ptr), _ptr(col), _ptr(out), n_cells, K,
+                          _ANALYSES[analysis], _ptr(kept), _ptr(mask), W)
+    return kept, mask, int(sweeps)
+
+
+def boundary(grid, level, idx, kept, rule: str = "shell") -> np.ndarray:
+    lib = _load()
+    level, idx, kept = _c(level, np.uint8), _c(idx, np.int32), _c(kept, np.uint8)
+    bnd = np.zeros(level.shape[0], dtype=np.uint8)
+    g = _grid(grid)
+    rc = lib.or_boundary(ctypes.byref(g), _ptr(level), _ptr(idx), level.shape[0], _ptr(kept),
+                         _RULES[rule], _ptr(bnd))
+    if rc != 0:
+        raise ValueError(f"oracle boundary failed ({rc})")
+    return bnd
+
+
+def subdivide(grid, level, idx, kept, bnd):
+    lib = _load()
+    level, idx = _c(level, np.uint8), _c(idx, np.int32)
+    kept, bnd = _c(kept, np.uint8), _c(bnd, np.uint8)
+    g = _grid(grid)
+    need = lib.or_subdivide(ctypes.byref(g), _ptr(level), _ptr(idx), level.shape[0], _ptr(kept),
+                            _ptr(bnd), None, None, 0)
+    lv = np.zeros(max(need, 1), dtype=np.uint8)
+    ix = np.zeros((max(need, 1), grid.n), dtype=np.int32)
+    got = lib.or_subdivide(ctypes.byref(g), _ptr(level), _ptr(idx), level.shape[0], _ptr(kept),
+                           _ptr(bnd), _ptr(lv), _ptr(ix), need)
+    assert got == need
+    return lv[:need].copy(), ix[:need].copy()
+
+
+def query(grid, level, idx, kept, mask, states):
+    lib = _load()
+    level, idx, kept = _c(level, np.uint8), _c(idx, np.int32), _c(kept, np.uint8)
+    mask = _c(mask, np.uint64)
+    states = _c(states, np.float64)
+    W = mask.shape[1]
+    member = np.zeros(states.shape[0], dtype=np.uint8)
+    adm = np.zeros((states.shape[0], W), dtype=np.uint64)
+    g = _grid(grid)
+    rc = lib.or_query(ctypes.byref(g), _ptr(level), _ptr(idx), level.shape[0], _ptr(kept),
+                      _ptr(mask), W, _ptr(states), states.shape[0], _ptr(member), _ptr(adm))
+    if rc != 0:
+        raise ValueError(f"oracle query failed ({rc})")
+    return member, adm
+
+
+def solve(system, grid, samples: str, u, rounds: int, rule: str = "shell",
+          fast_out: bool = False, keep_graphs: bool = False, analysis: str = "controlled"):
+    """The iteration loop: build and prune on the coarse covering, then
+    `rounds` times subdivide the boundary cells (Sec. 3.1), rebuild and prune.
+    Stops early when nothing is kept."""
+    u = _c(u, np.float64)
+    K = u.shape[0]
+    level, idx = coarse_cells(grid)
+    stats = []
+    graphs = []
+    kept = mask = None
+    for r in range(rounds + 1):
+        if r > 0:
+            bnd = boundary(grid, level, idx, kept, rule)
+            level, idx = subdivide(grid, level, idx, kept, bnd)
+            stats[-1]["n_boundary"] = int(bnd.sum())
+        if level.shape[0] == 0:
+            break
+        g = build_graph(system, grid, samples, level, idx, u, fast_out=fast_out)
+        kept, mask, sweeps = prune(g["row_ptr"], g["col"], g["out"], level.shape[0], K, analysis)
+        stats.append({"round": r, "n_cells": int(level.shape[0]), "n_rows": int(level.shape[0] * K),
+                      "n_edges": int(g["col"].shape[0]), "n_out": int(g["out"].sum()),
+                      "n_kept": int(kept.sum()), "sweeps": sweeps})
+        if keep_graphs:
+            graphs.append(g)
+        if kept.sum() == 0:
+            break
+    res = {"level": level, "idx": idx, "kept": kept, "mask": mask, "stats": stats}
+    if keep_graphs:
+        res["graphs"] = graphs
+    return res

@@ -1,0 +1,232 @@
+"""Seeded synthetic workloads: systems, state boxes, input sets, query states.
+
+This module holds no arithmetic of the GIS method itself.  It only describes
+problems in the terms of the paper's problem statement (Eq. 1: a map
+x+ = f(x, u) with compact state set X and input set U) and draws the
+synthetic inputs that both the HIP library and the CPU oracle consume, so the
+two sides always see bit-identical arrays.
+
+The five named workloads are the controlled Van der Pol, Lorenz-type and
+coupled Van der Pol problems used to exercise the graph-construction path;
+the paper's own CSTR example (Sec. 4.1) is not among them.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Sequence, Tuple
+
+import numpy as np
+
+# system kinds (names; each side maps them to its own numbering)
+LINEAR = "linear"
+VDP = "vdp"
+LORENZ = "lorenz"
+VDP2 = "vdp2"
+
+LATTICE3 = "lattice3"            # 3^n points: offsets {0, 1/2, 1} of the cell width
+CORNERS_CENTER = "corners_center"  # 2^n corners + the centre
+
+SHELL = "shell"        # every finest cell adjacent to the cell (Remark 1 edge points included)
+CORNERS = "corners"    # the 2^n diagonal corners only (Algorithm 1 as printed)
+
+
+@dataclasses.dataclass(frozen=True)
+class System:
+    """x+ = RK4^nsub(x, u) over one sampling interval dt of an ODE x' = g(x, u)."""
+    kind: str
+    n: int
+    m: int
+    dt: float
+    nsub: int
+    params: Tuple[float, ...]
+
+    def param_array(self) -> np.ndarray:
+        p = np.zeros(32, dtype=np.float64)
+        p[: len(self.params)] = self.params
+        return p
+
+
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    """Closed state box X = prod [lo_d, hi_d] with n0_d coarse cells per dimension."""
+    n0: Tuple[int, ...]
+    lo: Tuple[float, ...]
+    hi: Tuple[float, ...]
+
+    @property
+    def n(self) -> int:
+        return len(self.n0)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    system: System
+    grid: Grid
+    u: np.ndarray            # K x m, float64
+    samples: str
+    rounds: int
+    precision: str           # "fp64" or "fp32_recheck"
+    boundary_rule: str = SHELL
+
+    @property
+    def K(self) -> int:
+        return int(self.u.shape[0])
+
+
+# ---------------------------------------------------------------- systems
+def vdp(mu: float = 1.0, dt: float = 0.1, nsub: int = 4) -> System:
+    """x1' = x2, x2' = mu (1 - x1^2) x2 - x1 + u."""
+    return System(VDP, 2, 1, dt, nsub, (float(mu),))
+
+
+def lorenz(sigma: float = 10.0, rho: float = 28.0, beta: float = 8.0 / 3.0,
+           dt: float = 0.01, nsub: int = 2) -> System:
+    """x1' = sigma (x2 - x1), x2' = x1 (rho - x3) - x2 + u, x3' = x1 x2 - beta x3."""
+    return System(LORENZ, 3, 1, dt, nsub, (float(sigma), float(rho), float(beta)))
+
+
+def vdp2(coupling: float = 0.2, dt: float = 0.1, nsub: int = 4) -> System:
+    """Two oscillators, state (x1, v1, x2, v2):
+    xi'' = (1 - xi^2) xi' - xi + c (xj - xi) + ui."""
+    return System(VDP2, 4, 2, dt, nsub, (float(coupling),))
+
+
+def linear(A: Sequence[Sequence[float]], B: Sequence[Sequence[float]], dt: float,
+           nsub: int) -> System:
+    """x' = A x + B u (n <= 4, m <= 2); parameters packed as A (stride 4) then B (stride 2)."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    n, m = A.shape[0], B.shape[1]
+    assert A.shape == (n, n) and B.shape[0] == n and n <= 4 and m <= 2
+    p = np.zeros(24)
+    for d in range(n):
+        p[4 * d: 4 * d + n] = A[d]
+        p[16 + 2 * d: 16 + 2 * d + m] = B[d]
+    return System(LINEAR, n, m, float(dt), int(nsub), tuple(float(v) for v in p))
+
+
+# ---------------------------------------------------------------- inputs
+def evenly_spaced(a: float, b: float, K: int) -> np.ndarray:
+    """K values a + (b - a) k / (K - 1), endpoints included (K x 1)."""
+    if K == 1:
+        return np.array([[float(a)]])
+    k = np.arange(K, dtype=np.float64)
+    return (((b - a) * k) / (K - 1) + a).reshape(K, 1)
+
+
+def input_grid(a: float, b: float, per_dim: int, m: int) -> np.ndarray:
+    """Cartesian product of evenly spaced values, row-major, first input slowest."""
+    axis = evenly_spaced(a, b, per_dim)[:, 0]
+    mesh = np.meshgrid(*([axis] * m), indexing="ij")
+    return np.stack([g.reshape(-1) for g in mesh], axis=1)
+
+
+# ---------------------------------------------------------------- named workloads
+VDP_BOX = ((-2.5, -3.0), (2.5, 3.0))
+
+
+def vdp_uniform_64() -> Workload:
+    """Controlled Van der Pol on a uniform 64x64 grid, 11 inputs on [-1, 1], FP64."""
+    return Workload("vdp_uniform_64x64", vdp(), Grid((64, 64), *VDP_BOX),
+                    evenly_spaced(-1.0, 1.0, 11), LATTICE3, 0, "fp64")
+
+
+def vdp_adaptive_32(precision: str = "fp32_recheck") -> Workload:
+    """Van der Pol, 32x32 coarse grid, 5 boundary-only refinement rounds, 21 inputs."""
+    return Workload("vdp_adaptive_32x32_r5", vdp(), Grid((32, 32), *VDP_BOX),
+                    evenly_spaced(-1.0, 1.0, 21), LATTICE3, 5, precision)
+
+
+def lorenz_uniform_128() -> Workload:
+    """Lorenz-type system on a uniform 128^3 grid, 21 inputs on [-10, 10]."""
+    return Workload("lorenz_uniform_128^3", lorenz(),
+                    Grid((128, 128, 128), (-20.0, -25.0, 0.0), (20.0, 25.0, 50.0)),
+                    evenly_spaced(-10.0, 10.0, 21), CORNERS_CENTER, 0, "fp32_recheck")
+
+
+def vdp2_adaptive_32() -> Workload:
+    """Two coupled Van der Pol oscillators, 32^4 coarse grid + 2 boundary rounds, 7x7 inputs."""
+    return Workload("vdp2_adaptive_32^4_r2", vdp2(),
+                    Grid((32, 32, 32, 32), (-2.5, -3.0, -2.5, -3.0), (2.5, 3.0, 2.5, 3.0)),
+                    input_grid(-1.0, 1.0, 7, 2), CORNERS_CENTER, 2, "fp32_recheck")
+
+
+def scaled_vdp_box(scale: float) -> Tuple[Tuple[float, ...], Tuple[float, ...]]:
+    return ((-2.5 * scale, -3.0 * scale), (2.5 * scale, 3.0 * scale))
+
+
+@dataclasses.dataclass(frozen=True)
+class ServeRequest:
+    rid: int
+    arrival_s: float
+    workload: Workload
+    queries: np.ndarray      # Q x n float64 states
+    kinds: np.ndarray        # Q uint8: 0 membership, 1 admissible-input mask
+
+
+def serving_stream(n_requests: int, rate_per_s: float, seed: int = 0,
+                   n_queries: int = 100_000,
+                   sides: Sequence[int] = (32, 64, 128, 256)) -> list:
+    """Poisson arrivals of Van der Pol solves with mu ~ U[0.5, 2], box scale
+    ~ U[0.6, 1], grid side uniform over `sides`, 11 inputs, and n_queries
+    uniform query states in the request's box alternating between the two
+    query kinds."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    reqs = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        mu = rng.uniform(0.5, 2.0)
+        s = rng.uniform(0.6, 1.0)
+        side = int(sides[rng.integers(0, len(sides))])
+        lo, hi = scaled_vdp_box(s)
+        wl = Workload(f"serve_{rid}", vdp(mu=mu), Grid((side, side), lo, hi),
+                      evenly_spaced(-1.0, 1.0, 11), LATTICE3, 0, "fp64")
+        q = query_states(wl.grid, n_queries, seed=seed * 1_000_003 + rid + 1)
+        kinds = (np.arange(n_queries) % 2).astype(np.uint8)
+        reqs.append(ServeRequest(rid, t, wl, q, kinds))
+    return reqs
+
+
+def query_states(grid: Grid, count: int, seed: int, margin: float = 0.0) -> np.ndarray:
+    """count states uniform in the box enlarged by `margin` (relative) per side."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = np.asarray(grid.lo, dtype=np.float64)
+    hi = np.asarray(grid.hi, dtype=np.float64)
+    w = hi - lo
+    return rng.uniform(lo - margin * w, hi + margin * w, size=(count, grid.n))
+
+
+def random_linear(seed: int, n: int, m: int) -> System:
+    """A seeded random linear system x' = A x + B u for property tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = rng.uniform(-1.0, 1.0, size=(n, n)) - 0.5 * np.eye(n)
+    B = rng.uniform(-1.0, 1.0, size=(n, m))
+    return linear(A, B, dt=0.1, nsub=2)
+
+
+ALL = {
+    "vdp_uniform_64x64": vdp_uniform_64,
+    "vdp_adaptive_32x32_r5": vdp_adaptive_32,
+    "lorenz_uniform_128^3": lorenz_uniform_128,
+    "vdp2_adaptive_32^4_r2": vdp2_adaptive_32,
+}
+
+
+def sample_count(samples: str, n: int) -> int:
+    return 3 ** n if samples == LATTICE3 else 2 ** n + 1
+
+
+def mask_words(K: int) -> int:
+    return (K + 63) // 64
+
+
+def canonical_flops_per_row(system: System, samples: str) -> int:
+    """Algorithmic flop count of one (cell, input) image: S samples x nsub
+    substeps x (4 F + 12 n), F = flops of one field evaluation in its
+    canonical operation order (an FMA counts two)."""
+    F = {VDP: 6, LORENZ: 9, VDP2: 16}.get(system.kind)
+    if F is None:  # linear: n (m + n) FMAs
+        F = 2 * system.n * (system.m + system.n)
+    return sample_count(samples, system.n) * system.nsub * (4 * F + 12 * system.n)
