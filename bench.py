@@ -1,0 +1,139 @@
+"""Benchmark of the GIS graph-construction path on one MI355X.
+
+A step is one whole solve of the workload: coarse covering, then per round
+build the symbolic image (RK4 images -> bounding boxes -> covering ranges ->
+CSR edges), analyse it (prune to the fixed point) and refine the boundary
+cells.  The reported value is (cell x input) rows imaged per second of
+wall-clock over the timed steps; inputs are resident on the device before the
+timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--precision fp64|fp32_recheck] [--no-cpu-baseline]
+Prints one JSON line on stdout.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X vector peaks (256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz):
+# FP64 FMA runs at full rate, 78.6 TFLOP/s.  FP32 reaches 157.3 TFLOP/s only through
+# packed (two-per-lane) FP32 instructions, which this build does not emit; its
+# unpacked FP32 FMA rate is the same 78.6 TFLOP/s.
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="vdp_adaptive_32x32_r5")
+    p.add_argument("--precision", default=None, help="fp64 or fp32_recheck (default: workload's)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-budget-s", type=float, default=12.0)
+    return p.parse_args()
+
+
+def cpu_baseline(wl, budget_s):
+    """The CPU oracle (single-threaded FP64) timed on whole solves of the same workload."""
+    import oracle
+    oracle._load()
+    reps, rows, t0 = 0, 0, time.perf_counter()
+    while True:
+        res = oracle.solve(wl.system, wl.grid, wl.samples, wl.u, wl.rounds,
+                           rule=wl.boundary_rule, analysis=wl.analysis)
+        rows += sum(s["n_rows"] for s in res["stats"])
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 50:
+            break
+    return {"value": rows / el, "unit": "images/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} whole solve(s) of {wl.name} in {el:.1f} s, single thread"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported by this build "
+              "(the path has no multi-GPU sharding).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2202_06111_amd import gis
+    from paper_2202_06111_amd import workloads as W
+
+    if a.workload not in W.ALL:
+        sys.exit(f"unknown workload {a.workload}; choose from {sorted(W.ALL)}")
+    wl = W.ALL[a.workload]()
+    precision = a.precision or wl.precision
+    ctx = gis.Context(0)
+    du = gis.to_device_u(ctx, wl.u)
+    opts = gis.workload_opts(wl, precision=precision, timing=True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sol = gis.solve(ctx, wl.system, wl.grid, du, wl.rounds, opts, stream)
+        info = sol.info()
+        sol.free()
+        return info
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos, lat = [], []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        infos.append(step())
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    rows = sum(r["n_rows"] for inf in infos for r in inf["rounds"])
+    flops_row = W.canonical_flops_per_row(wl.system, wl.samples)
+    img_ms = sum(r["ms_image"] for inf in infos for r in inf["rounds"])
+    launches = sum(len(inf["rounds"]) for inf in infos)
+    achieved = rows * flops_row / (img_ms * 1e-3) / 1e12 if img_ms > 0 else 0.0
+    last = infos[-1]
+    res = {
+        "metric": "cell x input images/s in graph build (whole solve)",
+        "value": rows / el,
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * el / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64recheck",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "system": wl.system.kind, "grid0": list(wl.grid.n0),
+                   "rounds": wl.rounds, "inputs": wl.K, "samples": wl.samples,
+                   "analysis": wl.analysis, "precision": precision,
+                   "rows_per_solve": rows // a.steps, "final_cells": last["n_cells"],
+                   "final_kept": last["n_kept"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "k_count_%s (image + bbox + cover + count)" %
+                               ("f64" if precision == "fp64" else "f32"),
+                     "avg_launch_ms": img_ms / max(launches, 1),
+                     "flops_per_row": flops_row},
+        "solves_per_s": a.steps / el,
+        "latency_ms": {"p50": 1e3 * statistics.median(lat),
+                       "p99": 1e3 * sorted(lat)[min(len(lat) - 1, int(0.99 * len(lat)))]},
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, a.cpu_budget_s)
+    ctx.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * gis.h -- C ABI of the MI355X (gfx950) graph-construction path of the
+ * graph-based invariant set (GIS) algorithm of Decardi-Nelson and Liu,
+ * "An efficient implementation of graph-based invariant set algorithm for
+ * constrained nonlinear dynamical systems", arXiv 2202.06111.
+ *
+ * Problem (Sec. 2, Eq. 1): a discrete-time system x+ = f(x, u) with a closed
+ * state box X = prod_d [lo_d, hi_d] and a finite sampled input set
+ * U = {u_0 .. u_{K-1}}.  Here f is nsub classical RK4 substeps of one of the
+ * built-in vector fields over a sampling interval dt.
+ *
+ * Covering (Sec. 2.1): cells are closed boxes; a cell of level L has the
+ * multi-index i (0 <= i_d < n0_d 2^L) and the box
+ *   [lo_d + i_d w_{L,d}, lo_d + (i_d + 1) w_{L,d}],  w_{L,d} = ((hi_d - lo_d) / n0_d) 2^-L.
+ * A cell list is in canonical order: ascending level, then ascending
+ * row-major multi-index (dimension 0 slowest); a cell's position in the list
+ * is its id.  Cells of one list never overlap.
+ *
+ * Symbolic image (Sec. 2.2, Eqs. 2-3, Definition 1): one row per
+ * (cell, input), row = cell * K + input.  The image F(B_i) under input u is
+ * approximated by the bounding box of the images of the cell's sample points
+ * (3^n lattice points or 2^n corners + centre).  The row's edges are the ids
+ * of every cell whose closed box meets that bounding box, ascending.  A row is
+ * OUT when the box leaves X, when some image is not finite, or when the box's
+ * interior meets a part of X that no cell of the list covers.
+ *
+ * Graph analysis (Sec. 2.3), two readings:
+ *   GIS_ANALYSIS_CONTROLLED  keep the largest cell set K in which every cell
+ *     has an input whose row is not OUT and whose edges all end in K;
+ *   GIS_ANALYSIS_NONLEAVING  keep the cells with an infinite admissible path
+ *     in the input-union symbolic image (Definitions 5-6): iterated removal of
+ *     cells none of whose edges ends in the kept set.
+ * The admissible-input mask of a kept cell has bit u set when row (cell, u)
+ * satisfies the analysis' condition at the fixed point.
+ *
+ * Adaptive subdivision (Sec. 3.1.1, Algorithm 1, Remark 1): a kept cell is a
+ * boundary cell when a finest-level cell adjacent to it lies outside X or is
+ * not covered by a kept cell (GIS_BOUNDARY_SHELL: all adjacent cells, which
+ * includes Remark 1's edge points; GIS_BOUNDARY_CORNERS: the 2^n diagonal
+ * corners only, Algorithm 1 as printed).  The next covering holds the 2^n
+ * children of every boundary cell and every other kept cell.
+ *
+ * Conventions for every function below:
+ *  - Return value: a gis_status code; on failure gis_last_error() gives a
+ *    message (thread-local).  Outputs are unspecified after a failure.
+ *  - Pointers named d_* are device memory of the context's device, owned by
+ *    the caller; the library never frees them.  Structs are host memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it; functions that report counts to the host synchronise it.
+ *  - Arrays are dense and row-major; int64 sizes.
+ */
+#ifndef GIS_H
+#define GIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GIS_OK = 0,
+  GIS_E_INVAL = 1,        /* invalid argument or invalid cell list */
+  GIS_E_NOMEM = 2,        /* device allocation failed */
+  GIS_E_HIP = 3,          /* HIP runtime error */
+  GIS_E_CAPACITY = 4,     /* a caller buffer is too small; the needed size is reported */
+  GIS_E_UNSUPPORTED = 5,  /* valid request outside this build's limits */
+  GIS_E_INTERNAL = 6      /* a device-side consistency check failed */
+} gis_status;
+
+enum { GIS_SYS_LINEAR = 0, GIS_SYS_VDP = 1, GIS_SYS_LORENZ = 2, GIS_SYS_VDP2 = 3 };
+enum { GIS_SAMPLES_LATTICE3 = 1, GIS_SAMPLES_CORNERS_CENTER = 2 };
+enum { GIS_PREC_FP64 = 1, GIS_PREC_FP32_RECHECK = 2 };
+enum { GIS_BOUNDARY_SHELL = 1, GIS_BOUNDARY_CORNERS = 2 };
+enum { GIS_ANALYSIS_CONTROLLED = 1, GIS_ANALYSIS_NONLEAVING = 2 };
+
+/* Vector field g of x' = g(x, u); f = nsub RK4 substeps of length dt/nsub.
+ *  LINEAR (n <= 4, m <= 2): g = A x + B u, A = params[4d + j], B = params[16 + 2d + k]
+ *  VDP    (n = 2, m = 1):   g = (x2, mu (1 - x1^2) x2 - x1 + u),          mu = params[0]
+ *  LORENZ (n = 3, m = 1):   g = (s (x2 - x1), x1 (r - x3) - x2 + u, x1 x2 - b x3),
+ *                           s, r, b = params[0..2]
+ *  VDP2   (n = 4, m = 2):   state (x1, v1, x2, v2),
+ *                           vi' = (1 - xi^2) vi - xi + c (xj - xi) + ui, c = params[0] */
+typedef struct gis_system {
+  int32_t kind, n, m, nsub;
+  double dt;
+  double params[32];
+} gis_system;
+
+/* Closed state box X and its coarse partition (n0_d level-0 cells per dimension). */
+typedef struct gis_grid {
+  int32_t n;
+  int32_t n0[4];
+  double lo[4], hi[4];
+} gis_grid;
+
+typedef struct gis_opts {
+  int32_t samples;        /* GIS_SAMPLES_* */
+  int32_t precision;      /* GIS_PREC_*: FP64 images, or FP32 images with an FP64 recheck of
+                             every row whose FP32 box extreme lies within band[d] of a
+                             finest-level face or of the border of X */
+  int32_t boundary_rule;  /* GIS_BOUNDARY_* */
+  int32_t analysis;       /* GIS_ANALYSIS_* */
+  int32_t fast_out;       /* nonzero: OUT rows get no edges (analysis results unchanged) */
+  int32_t timing;         /* nonzero: time the image kernels with HIP events (gis_round_stats) */
+  int32_t reserved[2];
+  double band[4];         /* absolute recheck band per dimension; 0 = calibrate (see
+                             gis_calibrate_band) */
+} gis_opts;
+
+/* A cell list in device memory. */
+typedef struct gis_cells {
+  int64_t n_cells;   /* number of cells (output of gis_subdivide) */
+  int64_t cap;       /* capacity in cells of level[] and idx[] */
+  uint8_t* level;    /* d [cap] */
+  int32_t* idx;      /* d [cap * n], cell-major */
+} gis_cells;
+
+/* The symbolic image as CSR over rows (cell * K + input). */
+typedef struct gis_graph {
+  int64_t n_rows;     /* out: n_cells * K */
+  int64_t n_edges;    /* out: number of edges (needed capacity on GIS_E_CAPACITY) */
+  int64_t n_out;      /* out: number of OUT rows */
+  int64_t n_recheck;  /* out: rows recomputed in FP64 by the FP32 path */
+  int64_t cap_edges;  /* in: capacity of col[] */
+  int64_t* row_ptr;   /* d [n_rows + 1] */
+  int32_t* col;       /* d [cap_edges] */
+  uint8_t* out;       /* d [n_rows] */
+} gis_graph;
+
+typedef struct gis_ctx gis_ctx;
+typedef struct gis_solution gis_solution;
+
+typedef struct gis_round_stats {
+  int64_t n_cells, n_rows, n_edges, n_out, n_kept, n_boundary, n_recheck;
+  int32_t max_level, reserved;
+  double ms_build, ms_prune, ms_subdivide;   /* device time between HIP events */
+  double ms_image, ms_recheck;               /* image kernel / FP64 recheck kernel (opts.timing) */
+} gis_round_stats;
+
+#define GIS_MAX_ROUNDS 32
+
+typedef struct gis_solve_info {
+  int32_t n_rounds;        /* rounds actually run (<= requested + 1) */
+  int32_t n, K, mask_words;
+  int64_t n_cells, n_kept; /* final covering and kept set */
+  double band[4];          /* recheck band used (FP32 path) */
+  gis_round_stats rounds[GIS_MAX_ROUNDS];
+} gis_solve_info;
+
+/* ---- context: device workspace, reusable across calls, one stream at a time ---- */
+int32_t gis_ctx_create(int32_t device, gis_ctx** out);
+void gis_ctx_destroy(gis_ctx* ctx);
+
+/* Symbolic image of a covering (Sec. 2.2, Definition 1).  d_u: K x m inputs
+ * (FP64).  Fills row_ptr, out and, when cap_edges suffices, col; synchronises
+ * to report n_edges, n_out and n_recheck.  GIS_E_CAPACITY: n_edges holds the
+ * needed capacity, row_ptr and out are valid, col is not. */
+int32_t gis_build_graph(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
+                        const double* d_u, int32_t K, const gis_cells* cells,
+                        const gis_opts* opts, gis_graph* graph, void* stream);
+
+/* Graph analysis (Sec. 2.3) of a graph from gis_build_graph.  d_kept [n_cells]
+ * (1 = kept), d_mask [n_cells * ceil(K/64)] admissible inputs (bit u of word
+ * u/64).  Synchronises to report *n_kept (may be NULL). */
+int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t K,
+                  int32_t analysis, uint8_t* d_kept, uint64_t* d_mask, int64_t* n_kept,
+                  void* stream);
+
+/* Boundary selection and subdivision (Sec. 3.1.1).  d_boundary [in->n_cells]
+ * receives the boundary flags (may be NULL).  Synchronises; out->n_cells is the
+ * new cell count, GIS_E_CAPACITY if it exceeds out->cap (nothing written). */
+int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
+                      const uint8_t* d_kept, int32_t boundary_rule, uint8_t* d_boundary,
+                      gis_cells* out, void* stream);
+
+/* The iteration loop: coarse covering -> build -> prune, then `rounds` times
+ * subdivide -> build -> prune; stops early when nothing is kept.  The result
+ * stays on the device in a library-owned handle (free with gis_solution_free). */
+int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, const double* d_u,
+                  int32_t K, int32_t rounds, const gis_opts* opts, gis_solution** out,
+                  void* stream);
+int32_t gis_solution_info(const gis_solution* sol, gis_solve_info* info);
+/* Copies the final covering, kept flags and masks into caller buffers
+ * (cells->cap >= n_cells; d_kept [n_cells]; d_mask [n_cells * mask_words]). */
+int32_t gis_solution_export(const gis_solution* sol, gis_cells* cells, uint8_t* d_kept,
+                            uint64_t* d_mask, void* stream);
+void gis_solution_free(gis_solution* sol);
+
+/* Point queries on a solution: d_states [n x dim] FP64.  Membership: 1 if the
+ * state lies in X and in a kept cell (a state on a face belongs to the cell
+ * above it, the upper border of X to the last cell).  Admissible: the mask of
+ * that cell, 0 words otherwise; d_mask_out [n x mask_words]. */
+int32_t gis_query_membership(const gis_solution* sol, const double* d_states, int64_t n,
+                             uint8_t* d_member, void* stream);
+int32_t gis_query_admissible(const gis_solution* sol, const double* d_states, int64_t n,
+                             uint64_t* d_mask_out, void* stream);
+
+/* Sample images of every row for parity checks: d_images [n_cells*K x S x n]
+ * FP64 (FP32 results widened when precision is GIS_PREC_FP32_RECHECK). */
+int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, const double* d_u,
+                   int32_t K, const gis_cells* cells, int32_t samples, int32_t precision,
+                   double* d_images, void* stream);
+
+/* Largest |FP32 image - FP64 image| per dimension over every sample of every
+ * row of a covering (band[d] = max(floor_rel * w_finest_d, safety * that)).
+ * Synchronises. */
+int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
+                           const double* d_u, int32_t K, const gis_cells* cells, int32_t samples,
+                           double safety, double floor_rel, double* band_out, void* stream);
+
+const char* gis_last_error(void);
+const char* gis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GIS_H */

@@ -1,0 +1,131 @@
+// Device-side dynamics: the built-in vector fields, the RK4 discretisation
+// x+ = f(x, u) of Eq. (1) and the sample points of a cell.
+//
+// The FP64 instantiation is the reference arithmetic of the library: every
+// operation is IEEE binary64 round-to-nearest, the only fused operations are
+// the explicit fma() calls below, and the translation unit is compiled with
+// -ffp-contract=off, so the results are reproducible operation by operation.
+// The FP32 instantiation runs the same operation sequence in binary32 with
+// the constants rounded to nearest; its results only steer which rows need
+// the FP64 recheck.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gis_internal.h"
+
+namespace gis {
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Vector field g(x, u) of x' = g(x, u).  N is the state dimension; m (inputs)
+// is only a runtime value for the linear field.
+template <int KIND, int N, typename R>
+__device__ __forceinline__ void field(const R* __restrict__ p, int m, const R* x, const R* u, R* dx) {
+  if constexpr (KIND == GIS_SYS_LINEAR) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      R acc = R(0);
+      for (int k = 0; k < m; ++k) acc = fmaT(p[16 + 2 * d + k], u[k], acc);
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = fmaT(p[4 * d + j], x[j], acc);
+      dx[d] = acc;
+    }
+  } else if constexpr (KIND == GIS_SYS_VDP) {
+    dx[0] = x[1];
+    dx[1] = fmaT(p[0] * fmaT(-x[0], x[0], R(1)), x[1], u[0] - x[0]);
+  } else if constexpr (KIND == GIS_SYS_LORENZ) {
+    dx[0] = p[0] * (x[1] - x[0]);
+    dx[1] = fmaT(x[0], p[1] - x[2], u[0] - x[1]);
+    dx[2] = fmaT(x[0], x[1], -(p[2] * x[2]));
+  } else {  // GIS_SYS_VDP2, state (x1, v1, x2, v2)
+    dx[0] = x[1];
+    dx[1] = fmaT(fmaT(-x[0], x[0], R(1)), x[1], fmaT(p[0], x[2] - x[0], u[0] - x[0]));
+    dx[2] = x[3];
+    dx[3] = fmaT(fmaT(-x[2], x[2], R(1)), x[3], fmaT(p[0], x[0] - x[2], u[1] - x[2]));
+  }
+}
+
+// Substep constants and parameters in the working precision.
+template <typename R>
+struct Rk4Consts {
+  R h, h2, h6;
+  R p[24];
+};
+
+template <typename R>
+__device__ __forceinline__ Rk4Consts<R> make_consts(const SysArgs& s) {
+  Rk4Consts<R> c;
+  c.h = R(s.h);
+  c.h2 = R(s.h2);
+  c.h6 = R(s.h6);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) c.p[i] = R(s.p[i]);
+  return c;
+}
+
+// nsub classical RK4 substeps, in place.
+template <int KIND, int N, typename R>
+__device__ __forceinline__ void rk4(const Rk4Consts<R>& c, int m, int nsub, R* x, const R* u) {
+  for (int q = 0; q < nsub; ++q) {
+    R k1[N], k2[N], k3[N], k4[N], y[N];
+    field<KIND, N, R>(c.p, m, x, u, k1);
+#pragma unroll
+    for (int d = 0; d < N; ++d) y[d] = fmaT(c.h2, k1[d], x[d]);
+    field<KIND, N, R>(c.p, m, y, u, k2);
+#pragma unroll
+    for (int d = 0; d < N; ++d) y[d] = fmaT(c.h2, k2[d], x[d]);
+    field<KIND, N, R>(c.p, m, y, u, k3);
+#pragma unroll
+    for (int d = 0; d < N; ++d) y[d] = fmaT(c.h, k3[d], x[d]);
+    field<KIND, N, R>(c.p, m, y, u, k4);
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      R s = k1[d] + k4[d];
+      R t = k2[d] + k3[d];
+      s = fmaT(R(2), t, s);
+      x[d] = fmaT(c.h6, s, x[d]);
+    }
+  }
+}
+
+__host__ __device__ constexpr int ipow3(int n) { return n <= 0 ? 1 : 3 * ipow3(n - 1); }
+
+__device__ __forceinline__ int num_samples(int scheme, int n) {
+  return scheme == GIS_SAMPLES_LATTICE3 ? ipow3(n) : (1 << n) + 1;
+}
+
+// Offset k_d in {0, 1, 2} (lower face, centre, upper face) of sample q:
+// LATTICE3 enumerates base-3 digits with dimension 0 most significant;
+// CORNERS_CENTER enumerates the corners by bits (dimension 0 most
+// significant) and puts the centre last.
+template <int N>
+__device__ __forceinline__ void sample_offsets(int scheme, int q, int* k) {
+  if (scheme == GIS_SAMPLES_LATTICE3) {
+#pragma unroll
+    for (int d = N - 1; d >= 0; --d) {
+      k[d] = q % 3;
+      q /= 3;
+    }
+  } else if (q == (1 << N)) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) k[d] = 1;
+  } else {
+#pragma unroll
+    for (int d = 0; d < N; ++d) k[d] = 2 * ((q >> (N - 1 - d)) & 1);
+  }
+}
+
+// Sample coordinates (FP64): lo_d + (2 i_d + k_d) * (w_{L,d} / 2).
+template <int N>
+__device__ __forceinline__ void sample_point(const GridArgs& g, int level, const int32_t* i,
+                                             const int* k, double* x) {
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    const double half = 0.5 * ldexp(g.w0[d], -level);
+    x[d] = __builtin_fma((double)(2 * (int64_t)i[d] + k[d]), half, g.lo[d]);
+  }
+}
+
+}  // namespace gis

@@ -1,0 +1,575 @@
+// Graph construction kernels: symbolic image of a covering (Sec. 2.2,
+// Definition 1) as CSR rows, one row per (cell, input).
+//
+//   count   : per row, the images of the sample points (nsub RK4 substeps),
+//             their bounding box, the closed index range of finest-level
+//             cells it meets, the OUT flag and the row's edge count; one
+//             int64 edge total per block of kRowBlock rows.
+//   recheck : FP64 redo of the rows the FP32 count kernel could not decide.
+//   emit    : block-local scan of the counts plus the block offset -> row_ptr;
+//             the row's target ids are enumerated into an LDS tile and copied
+//             to col[] with coalesced stores.
+//
+// Cell ids follow the canonical order of the covering (level, then row-major
+// index), so enumerating the covering index level by level, row-major inside
+// each level, yields every row's targets in ascending order with no sort and
+// no duplicates.
+#include <float.h>
+#include <math.h>
+
+#include "dynamics.h"
+#include "gis_internal.h"
+
+namespace gis {
+
+namespace {
+
+constexpr int kTile = 8192;  // LDS tile of the emitter (int32 ids, 32 KiB)
+
+// ------------------------------------------------------------------ cover logic
+// Position of v on the finest grid, clamped to [-2, N + 2] (the clamp keeps
+// the integer conversion defined and never changes a clamped range).
+__device__ __forceinline__ double grid_pos(double v, double lo, double hs, int32_t N) {
+  double t = (v - lo) / hs;
+  t = t < -2.0 ? -2.0 : t;
+  t = t > (double)N + 2.0 ? (double)N + 2.0 : t;
+  return t;
+}
+
+template <int N>
+struct Ranges {
+  int32_t lo[N], hi[N];     // closed range R
+  int32_t ilo[N], ihi[N];   // interior range (R when the interior range is empty)
+  bool empty, iempty, outx;
+};
+
+template <int N>
+__device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverIndex& ci,
+                                               const double* bl, const double* bh) {
+  Ranges<N> r;
+  r.empty = r.iempty = r.outx = false;
+  const int L = ci.lmax;
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    const int32_t Nd = ci.dims[L][d];
+    const double hs = ldexp(g.w0[d], -L);
+    const double ta = grid_pos(bl[d], g.lo[d], hs, Nd);
+    const double tb = grid_pos(bh[d], g.lo[d], hs, Nd);
+    int32_t rlo = (int32_t)ceil(ta) - 1, rhi = (int32_t)floor(tb);
+    int32_t ilo = (int32_t)floor(ta), ihi = (int32_t)ceil(tb) - 1;
+    rlo = rlo < 0 ? 0 : rlo;
+    rhi = rhi > Nd - 1 ? Nd - 1 : rhi;
+    ilo = ilo < 0 ? 0 : ilo;
+    ihi = ihi > Nd - 1 ? Nd - 1 : ihi;
+    if (ilo > ihi) {
+      ilo = rlo;
+      ihi = rhi;
+    }
+    r.lo[d] = rlo;
+    r.hi[d] = rhi;
+    r.ilo[d] = ilo;
+    r.ihi[d] = ihi;
+    r.empty |= rlo > rhi;
+    r.iempty |= ilo > ihi;
+    r.outx |= (bl[d] < g.lo[d]) || (bh[d] > g.hi[d]);
+  }
+  return r;
+}
+
+// Visits every slot of the covering index met by the finest-level box
+// [lo, hi], level by level (coarse to fine), row-major inside a level.
+// f(level, slot) returns false to stop early.
+template <int N, typename F>
+__device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t* lo,
+                                            const int32_t* hi, F&& f) {
+  for (int L = 0; L <= ci.lmax; ++L) {
+    const int s = ci.lmax - L;
+    int32_t blo[N], bhi[N], k[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      blo[d] = lo[d] >> s;
+      bhi[d] = hi[d] >> s;
+      k[d] = blo[d];
+    }
+    const int64_t base = ci.off[L];
+    for (;;) {
+      int64_t lin = 0;
+#pragma unroll
+      for (int d = 0; d < N; ++d) lin = lin * ci.dims[L][d] + k[d];
+      if (!f(L, base + lin)) return;
+      int d = N - 1;
+      while (d >= 0 && k[d] == bhi[d]) {
+        k[d] = blo[d];
+        --d;
+      }
+      if (d < 0) break;
+      ++k[d];
+    }
+  }
+}
+
+template <int N, bool UNIFORM>
+__device__ __forceinline__ bool has_hole(const CoverIndex& ci, const Ranges<N>& r) {
+  if (UNIFORM || r.iempty) return false;
+  bool hole = false;
+  walk_levels<N>(ci, r.ilo, r.ihi, [&](int, int64_t slot) {
+    if (ci.state[slot] == ST_HOLE) {
+      hole = true;
+      return false;
+    }
+    return true;
+  });
+  return hole;
+}
+
+template <int N, bool UNIFORM>
+__device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ranges<N>& r) {
+  if (r.empty) return 0;
+  if (UNIFORM) {
+    int32_t c = 1;
+#pragma unroll
+    for (int d = 0; d < N; ++d) c *= r.hi[d] - r.lo[d] + 1;
+    return c;
+  }
+  int32_t c = 0;
+  walk_levels<N>(ci, r.lo, r.hi, [&](int, int64_t slot) {
+    c += ci.state[slot] == ST_LEAF;
+    return true;
+  });
+  return c;
+}
+
+// Writes the row's cover decision; returns its edge count.
+template <int N, bool UNIFORM>
+__device__ __forceinline__ int32_t decide_row(const BuildArgs& a, int64_t r, bool finite,
+                                              const double* bl, const double* bh) {
+  int32_t count = 0;
+  bool out = true;
+  int32_t* rg = a.rng + r * (2 * N);
+  if (finite) {
+    const Ranges<N> rr = ranges_of<N>(a.grid, a.ci, bl, bh);
+    out = rr.outx || has_hole<N, UNIFORM>(a.ci, rr);
+    count = count_targets<N, UNIFORM>(a.ci, rr);
+    if (a.fast_out && out) count = 0;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      rg[2 * d] = rr.lo[d];
+      rg[2 * d + 1] = rr.hi[d];
+    }
+  }
+  a.cnt[r] = count;
+  a.out[r] = out ? 1 : 0;
+  return count;
+}
+
+// Bounding box of the sample images of row r in precision R.
+template <int KIND, int N, typename R>
+__device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Rk4Consts<R>& kc, int64_t r,
+                                         R* bl, R* bh) {
+  const int64_t c = r / a.K;
+  const int32_t j = (int32_t)(r - c * a.K);
+  const int level = a.level[c];
+  int32_t ci[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) ci[d] = a.idx[c * N + d];
+  R u[2];
+  u[0] = R(a.u[(int64_t)j * a.sys.m]);
+  u[1] = a.sys.m > 1 ? R(a.u[(int64_t)j * a.sys.m + 1]) : R(0);
+  bool finite = true;
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    bl[d] = R(INFINITY);
+    bh[d] = R(-INFINITY);
+  }
+  const int S = num_samples(a.samples, N);
+  for (int q = 0; q < S; ++q) {
+    int k[N];
+    double xd[N];
+    sample_offsets<N>(a.samples, q, k);
+    sample_point<N>(a.grid, level, ci, k, xd);
+    R x[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) x[d] = R(xd[d]);
+    rk4<KIND, N, R>(kc, a.sys.m, a.sys.nsub, x, u);
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      finite &= isfinite(x[d]);
+      bl[d] = x[d] < bl[d] ? x[d] : bl[d];
+      bh[d] = x[d] > bh[d] ? x[d] : bh[d];
+    }
+  }
+  return finite;
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  int64_t t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
+  return t;
+}
+
+// ------------------------------------------------------------------ kernels
+template <int KIND, int N, bool UNIFORM>
+__global__ __launch_bounds__(kRowBlock) void k_count_f64(BuildArgs a) {
+  __shared__ int64_t lds[kRowBlock / 64];
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  int64_t mine = 0;
+  if (r < a.n_rows) {
+    const Rk4Consts<double> kc = make_consts<double>(a.sys);
+    double bl[N], bh[N];
+    const bool finite = row_bbox<KIND, N, double>(a, kc, r, bl, bh);
+    mine = decide_row<N, UNIFORM>(a, r, finite, bl, bh);
+  }
+  const int64_t t = block_sum_i64(mine, lds);
+  if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
+}
+
+// FP32 images; a row is decided from its FP32 box only when every decision
+// taken from a box extreme (the finest-grid position's floor/ceil, the
+// comparisons with lo and hi) is the same anywhere within band[d] of it.
+// Since |y32 - y64| <= band[d] holds for every sample image, and min/max are
+// 1-Lipschitz, the FP64 box extremes then lead to the same decisions.
+// Other rows are queued for the FP64 recheck kernel.
+template <int KIND, int N, bool UNIFORM>
+__global__ __launch_bounds__(kRowBlock) void k_count_f32(BuildArgs a) {
+  __shared__ int64_t lds[kRowBlock / 64];
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  int64_t mine = 0;
+  if (r < a.n_rows) {
+    const Rk4Consts<float> kc = make_consts<float>(a.sys);
+    float bl[N], bh[N];
+    bool safe = row_bbox<KIND, N, float>(a, kc, r, bl, bh);
+    double dl[N], dh[N];
+    const int L = a.ci.lmax;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      dl[d] = (double)bl[d];
+      dh[d] = (double)bh[d];
+      const double hs = ldexp(a.grid.w0[d], -L);
+      const double eps = a.band[d];
+      const double ta = (dl[d] - a.grid.lo[d]) / hs;
+      const double tb = (dh[d] - a.grid.lo[d]) / hs;
+      const double tola = eps / hs + 1e-9 * (fabs(ta) + 1.0);
+      const double tolb = eps / hs + 1e-9 * (fabs(tb) + 1.0);
+      safe &= fabs(ta - rint(ta)) > tola;
+      safe &= fabs(tb - rint(tb)) > tolb;
+      safe &= fabs(dh[d] - a.grid.hi[d]) > eps;
+    }
+    if (safe) {
+      mine = decide_row<N, UNIFORM>(a, r, true, dl, dh);
+    } else {
+      const unsigned long long slot = atomicAdd((unsigned long long*)a.n_recheck, 1ull);
+      a.recheck[slot] = r;
+      a.cnt[r] = 0;
+    }
+  }
+  const int64_t t = block_sum_i64(mine, lds);
+  if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
+}
+
+template <int KIND, int N, bool UNIFORM>
+__global__ __launch_bounds__(kRowBlock) void k_recheck(BuildArgs a) {
+  const int64_t n = *a.n_recheck;
+  const Rk4Consts<double> kc = make_consts<double>(a.sys);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = a.recheck[i];
+    double bl[N], bh[N];
+    const bool finite = row_bbox<KIND, N, double>(a, kc, r, bl, bh);
+    const int32_t c = decide_row<N, UNIFORM>(a, r, finite, bl, bh);
+    if (c) atomicAdd((unsigned long long*)&a.bsum[r / kRowBlock], (unsigned long long)c);
+  }
+}
+
+template <int KIND, int N, typename R>
+__global__ __launch_bounds__(kRowBlock) void k_images(BuildArgs a, double* out) {
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  if (r >= a.n_rows) return;
+  const Rk4Consts<R> kc = make_consts<R>(a.sys);
+  const int64_t c = r / a.K;
+  const int32_t j = (int32_t)(r - c * a.K);
+  int32_t ci[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) ci[d] = a.idx[c * N + d];
+  R u[2];
+  u[0] = R(a.u[(int64_t)j * a.sys.m]);
+  u[1] = a.sys.m > 1 ? R(a.u[(int64_t)j * a.sys.m + 1]) : R(0);
+  const int S = num_samples(a.samples, N);
+  for (int q = 0; q < S; ++q) {
+    int k[N];
+    double xd[N];
+    sample_offsets<N>(a.samples, q, k);
+    sample_point<N>(a.grid, a.level[c], ci, k, xd);
+    R x[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) x[d] = R(xd[d]);
+    rk4<KIND, N, R>(kc, a.sys.m, a.sys.nsub, x, u);
+#pragma unroll
+    for (int d = 0; d < N; ++d) out[(r * S + q) * N + d] = (double)x[d];
+  }
+}
+
+// max |y32 - y64| per dimension (bit patterns of non-negative doubles order
+// like the values, so an integer atomicMax works).
+template <int KIND, int N>
+__global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned long long* maxerr) {
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  double e[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) e[d] = 0.0;
+  if (r < a.n_rows) {
+    const Rk4Consts<double> k64 = make_consts<double>(a.sys);
+    const Rk4Consts<float> k32 = make_consts<float>(a.sys);
+    const int64_t c = r / a.K;
+    const int32_t j = (int32_t)(r - c * a.K);
+    int32_t ci[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) ci[d] = a.idx[c * N + d];
+    double u64[2];
+    float u32[2];
+    u64[0] = a.u[(int64_t)j * a.sys.m];
+    u64[1] = a.sys.m > 1 ? a.u[(int64_t)j * a.sys.m + 1] : 0.0;
+    u32[0] = (float)u64[0];
+    u32[1] = (float)u64[1];
+    const int S = num_samples(a.samples, N);
+    for (int q = 0; q < S; ++q) {
+      int k[N];
+      double xd[N];
+      float xf[N];
+      sample_offsets<N>(a.samples, q, k);
+      sample_point<N>(a.grid, a.level[c], ci, k, xd);
+#pragma unroll
+      for (int d = 0; d < N; ++d) xf[d] = (float)xd[d];
+      rk4<KIND, N, double>(k64, a.sys.m, a.sys.nsub, xd, u64);
+      rk4<KIND, N, float>(k32, a.sys.m, a.sys.nsub, xf, u32);
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        double diff = fabs((double)xf[d] - xd[d]);
+        if (!(diff <= DBL_MAX)) diff = DBL_MAX;  // non-finite images force the largest band
+        e[d] = diff > e[d] ? diff : e[d];
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    double v = e[d];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double w = __shfl_down(v, o, 64);
+      v = w > v ? w : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(&maxerr[d], (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+// ------------------------------------------------------------------ emit
+template <int N, bool UNIFORM>
+__global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
+  __shared__ int32_t tile[kTile];
+  __shared__ int64_t wsum[kRowBlock / 64];
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  const int32_t c = r < a.n_rows ? a.cnt[r] : 0;
+  // block-exclusive scan of the counts
+  int64_t x = c;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  int64_t before = 0, total = 0;
+  for (int w = 0; w < kRowBlock / 64; ++w) {
+    before += w < wid ? wsum[w] : 0;
+    total += wsum[w];
+  }
+  const int64_t off = before + x - c;
+  const int64_t base = a.bscan[blockIdx.x];
+  if (r < a.n_rows) a.row_ptr[r] = base + off;
+  if (r == a.n_rows - 1) a.row_ptr[a.n_rows] = base + off + c;
+  if (base + total > a.cap_edges) return;  // capacity miss: col is not written
+  const bool staged = total <= kTile;
+  if (c > 0) {
+    const int32_t* rg = a.rng + r * (2 * N);
+    int32_t lo[N], hi[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      lo[d] = rg[2 * d];
+      hi[d] = rg[2 * d + 1];
+    }
+    int32_t* dst = staged ? tile + off : a.col + base + off;
+    if (UNIFORM) {
+      int32_t k[N];
+#pragma unroll
+      for (int d = 0; d < N; ++d) k[d] = lo[d];
+      int32_t w = 0;
+      for (;;) {
+        int32_t lin = 0;
+#pragma unroll
+        for (int d = 0; d < N; ++d) lin = lin * a.ci.dims[0][d] + k[d];
+        if (w < c) dst[w++] = lin;
+        int d = N - 1;
+        while (d >= 0 && k[d] == hi[d]) {
+          k[d] = lo[d];
+          --d;
+        }
+        if (d < 0) break;
+        ++k[d];
+      }
+    } else {
+      int32_t w = 0;
+      walk_levels<N>(a.ci, lo, hi, [&](int, int64_t slot) {
+        if (a.ci.state[slot] == ST_LEAF && w < c) dst[w++] = a.ci.id[slot];
+        return true;
+      });
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < total; i += kRowBlock) a.col[base + i] = tile[i];
+  }
+}
+
+__global__ void k_count_out(const uint8_t* out, int64_t n, unsigned long long* cnt) {
+  unsigned long long mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    mine += out[i];
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(cnt, mine);
+}
+
+// ------------------------------------------------------------------ dispatch
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kRowBlock - 1) / kRowBlock); }
+
+template <template <int, int, bool> class Launcher, typename... Args>
+int32_t dispatch_sys(int kind, int n, bool uniform, Args&&... args) {
+#define GIS_CASE(KIND, N)                                                         \
+  if (uniform) return Launcher<KIND, N, true>::run(args...);                      \
+  return Launcher<KIND, N, false>::run(args...);
+  switch (kind) {
+    case GIS_SYS_VDP:
+      if (n == 2) { GIS_CASE(GIS_SYS_VDP, 2) }
+      break;
+    case GIS_SYS_LORENZ:
+      if (n == 3) { GIS_CASE(GIS_SYS_LORENZ, 3) }
+      break;
+    case GIS_SYS_VDP2:
+      if (n == 4) { GIS_CASE(GIS_SYS_VDP2, 4) }
+      break;
+    case GIS_SYS_LINEAR:
+      if (n == 1) { GIS_CASE(GIS_SYS_LINEAR, 1) }
+      if (n == 2) { GIS_CASE(GIS_SYS_LINEAR, 2) }
+      if (n == 3) { GIS_CASE(GIS_SYS_LINEAR, 3) }
+      if (n == 4) { GIS_CASE(GIS_SYS_LINEAR, 4) }
+      break;
+  }
+#undef GIS_CASE
+  set_error("unsupported system kind / dimension");
+  return GIS_E_UNSUPPORTED;
+}
+
+template <int KIND, int N, bool U>
+struct CountF64 {
+  static int32_t run(const BuildArgs& a, hipStream_t s) {
+    if (a.n_rows == 0) return GIS_OK;
+    hipLaunchKernelGGL((k_count_f64<KIND, N, U>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a);
+    GIS_LAUNCH_CHECK("k_count_f64");
+    return GIS_OK;
+  }
+};
+template <int KIND, int N, bool U>
+struct CountF32 {
+  static int32_t run(const BuildArgs& a, hipStream_t s) {
+    if (a.n_rows == 0) return GIS_OK;
+    hipLaunchKernelGGL((k_count_f32<KIND, N, U>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a);
+    GIS_LAUNCH_CHECK("k_count_f32");
+    return GIS_OK;
+  }
+};
+template <int KIND, int N, bool U>
+struct Recheck {
+  static int32_t run(const BuildArgs& a, hipStream_t s) {
+    if (a.n_rows == 0) return GIS_OK;
+    const unsigned nb = blocks_for(a.n_rows) < 2048 ? blocks_for(a.n_rows) : 2048;
+    hipLaunchKernelGGL((k_recheck<KIND, N, U>), dim3(nb), dim3(kRowBlock), 0, s, a);
+    GIS_LAUNCH_CHECK("k_recheck");
+    return GIS_OK;
+  }
+};
+template <int KIND, int N, bool U>
+struct Images {
+  static int32_t run(const BuildArgs& a, int32_t precision, double* out, hipStream_t s) {
+    if (a.n_rows == 0) return GIS_OK;
+    if (precision == GIS_PREC_FP32_RECHECK)
+      hipLaunchKernelGGL((k_images<KIND, N, float>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a, out);
+    else
+      hipLaunchKernelGGL((k_images<KIND, N, double>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a, out);
+    GIS_LAUNCH_CHECK("k_images");
+    return GIS_OK;
+  }
+};
+template <int KIND, int N, bool U>
+struct Calibrate {
+  static int32_t run(const BuildArgs& a, unsigned long long* maxerr, hipStream_t s) {
+    if (a.n_rows == 0) return GIS_OK;
+    hipLaunchKernelGGL((k_calibrate<KIND, N>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a, maxerr);
+    GIS_LAUNCH_CHECK("k_calibrate");
+    return GIS_OK;
+  }
+};
+
+template <int N, bool U>
+int32_t emit_n(const EmitArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_emit<N, U>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a);
+  GIS_LAUNCH_CHECK("k_emit");
+  return GIS_OK;
+}
+
+}  // namespace
+
+int32_t launch_count(const BuildArgs& a, int32_t precision, hipStream_t s) {
+  const bool uniform = a.ci.uniform != 0;
+  if (precision == GIS_PREC_FP32_RECHECK)
+    return dispatch_sys<CountF32>(a.sys.kind, a.sys.n, uniform, a, s);
+  return dispatch_sys<CountF64>(a.sys.kind, a.sys.n, uniform, a, s);
+}
+
+int32_t launch_recheck(const BuildArgs& a, hipStream_t s) {
+  return dispatch_sys<Recheck>(a.sys.kind, a.sys.n, a.ci.uniform != 0, a, s);
+}
+
+int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s) {
+  return dispatch_sys<Images>(a.sys.kind, a.sys.n, true, a, precision, d_images, s);
+}
+
+int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, hipStream_t s) {
+  return dispatch_sys<Calibrate>(a.sys.kind, a.sys.n, true, a, d_maxerr, s);
+}
+
+int32_t launch_emit(const EmitArgs& a, hipStream_t s) {
+  if (a.n_rows == 0) return GIS_OK;
+  const bool u = a.ci.uniform != 0;
+  switch (a.n) {
+    case 1: return u ? emit_n<1, true>(a, s) : emit_n<1, false>(a, s);
+    case 2: return u ? emit_n<2, true>(a, s) : emit_n<2, false>(a, s);
+    case 3: return u ? emit_n<3, true>(a, s) : emit_n<3, false>(a, s);
+    case 4: return u ? emit_n<4, true>(a, s) : emit_n<4, false>(a, s);
+  }
+  set_error("unsupported dimension");
+  return GIS_E_UNSUPPORTED;
+}
+
+int32_t count_out(const uint8_t* out, int64_t n, unsigned long long* d_count, hipStream_t s) {
+  if (n == 0) return GIS_OK;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_count_out, dim3((unsigned)nb), dim3(256), 0, s, out, n, d_count);
+  GIS_LAUNCH_CHECK("k_count_out");
+  return GIS_OK;
+}
+
+}  // namespace gis

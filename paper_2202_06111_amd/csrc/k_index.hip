@@ -1,0 +1,203 @@
+// Covering index: the cells of a covering (Sec. 2.1) held as one dense
+// row-major state array per level -- LEAF where a cell of the list sits (with
+// its id), REFINED above a leaf, HOLE where a region of X has no cell, NONE
+// below a leaf or a hole.  It turns "which cells meet this box" and "is this
+// finest cell covered" into a short walk over at most lmax + 1 levels, with
+// no search structure to build (the role the paper gives an R*-tree, Sec. 2.4).
+#include "gis_internal.h"
+
+namespace gis {
+
+namespace {
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+int32_t fill(T* p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return GIS_OK;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)nb), dim3(256), 0, s, p, v, n);
+  GIS_LAUNCH_CHECK("k_fill");
+  return GIS_OK;
+}
+
+__global__ void k_max_level(const uint8_t* level, int64_t n, uint32_t* out) {
+  uint32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = level[i] > m ? level[i] : m;
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t w = __shfl_down(m, o, 64);
+    m = w > m ? w : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+// Slot of cell c in the index; -1 if its level or multi-index is out of range.
+__device__ __forceinline__ int64_t cell_slot(const CoverIndex& ci, const uint8_t* level,
+                                             const int32_t* idx, int64_t c, int64_t* key_lin) {
+  const int L = level[c];
+  if (L > ci.lmax) return -1;
+  int64_t lin = 0;
+  for (int d = 0; d < ci.n; ++d) {
+    const int32_t v = idx[c * ci.n + d];
+    if (v < 0 || v >= ci.dims[L][d]) return -1;
+    lin = lin * ci.dims[L][d] + v;
+  }
+  *key_lin = lin;
+  return ci.off[L] + lin;
+}
+
+// Range and canonical-order checks; with write_index, LEAF entries.
+__global__ void k_leaves(CoverIndex ci, const uint8_t* level, const int32_t* idx, int64_t n_cells,
+                         int write_index, uint32_t* err) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lin;
+    const int64_t slot = cell_slot(ci, level, idx, c, &lin);
+    if (slot < 0) {
+      atomicOr(err, 1u);
+      continue;
+    }
+    if (c > 0) {
+      int64_t plin;
+      const int64_t pslot = cell_slot(ci, level, idx, c - 1, &plin);
+      // canonical order = strictly increasing (level, row-major index) = slot order
+      if (pslot >= 0 && pslot >= slot) atomicOr(err, 2u);
+    }
+    if (write_index) {
+      ci.state[slot] = ST_LEAF;
+      ci.id[slot] = (int32_t)c;
+    }
+  }
+}
+
+// Marks every ancestor of every leaf REFINED; an ancestor that is itself a
+// leaf means two cells overlap.
+__global__ void k_ancestors(CoverIndex ci, const uint8_t* level, const int32_t* idx,
+                            int64_t n_cells, uint32_t* err) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lin0;
+    if (cell_slot(ci, level, idx, c, &lin0) < 0) continue;  // reported by k_leaves
+    int L = level[c];
+    int64_t k[kMaxDim];
+    for (int d = 0; d < ci.n; ++d) k[d] = idx[c * ci.n + d];
+    while (L > 0) {
+      --L;
+      int64_t lin = 0;
+      for (int d = 0; d < ci.n; ++d) {
+        k[d] >>= 1;
+        lin = lin * ci.dims[L][d] + k[d];
+      }
+      const int64_t slot = ci.off[L] + lin;
+      if (ci.state[slot] == ST_LEAF) {
+        atomicOr(err, 4u);
+        break;
+      }
+      ci.state[slot] = ST_REFINED;
+    }
+  }
+}
+
+// NONE slots at level 0, or below a REFINED parent, are holes.
+__global__ void k_holes(CoverIndex ci) {
+  const int64_t total = ci.off[ci.lmax + 1];
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    if (ci.state[s] != ST_NONE) continue;
+    int L = 0;
+    while (s >= ci.off[L + 1]) ++L;
+    if (L == 0) {
+      ci.state[s] = ST_HOLE;
+      continue;
+    }
+    int64_t rem = s - ci.off[L];
+    int64_t k[kMaxDim];
+    for (int d = ci.n - 1; d >= 0; --d) {
+      k[d] = rem % ci.dims[L][d];
+      rem /= ci.dims[L][d];
+    }
+    int64_t plin = 0;
+    for (int d = 0; d < ci.n; ++d) plin = plin * ci.dims[L - 1][d] + (k[d] >> 1);
+    if (ci.state[ci.off[L - 1] + plin] == ST_REFINED) ci.state[s] = ST_HOLE;
+  }
+}
+
+__global__ void k_mark_dropped(CoverIndex ci, const uint8_t* level, const int32_t* idx,
+                               int64_t n_cells, const uint8_t* kept) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (kept[c]) continue;
+    int64_t lin;
+    const int64_t slot = cell_slot(ci, level, idx, c, &lin);
+    if (slot >= 0) ci.state[slot] = ST_HOLE;
+  }
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t nb = (n + 255) / 256;
+  if (nb < 1) nb = 1;
+  if (nb > 8192) nb = 8192;
+  return (unsigned)nb;
+}
+
+}  // namespace
+
+int32_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+int32_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+int32_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+int32_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+
+int32_t max_level(const uint8_t* level, int64_t n_cells, uint32_t* d_out, hipStream_t s) {
+  int32_t rc = fill_u32(d_out, 0u, 1, s);
+  if (rc != GIS_OK || n_cells == 0) return rc;
+  hipLaunchKernelGGL(k_max_level, dim3(grid_for(n_cells)), dim3(256), 0, s, level, n_cells, d_out);
+  GIS_LAUNCH_CHECK("k_max_level");
+  return GIS_OK;
+}
+
+int32_t index_build(CoverIndex& ci, const GridArgs& g, const uint8_t* level, const int32_t* idx,
+                    int64_t n_cells, uint32_t* d_err, hipStream_t s) {
+  (void)g;
+  int32_t rc = fill_u32(d_err, 0u, 1, s);
+  if (rc != GIS_OK) return rc;
+  if (ci.uniform) {  // only the checks: the index arrays are implicit
+    if (n_cells == 0) return GIS_OK;
+    hipLaunchKernelGGL(k_leaves, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
+                       n_cells, 0, d_err);
+    GIS_LAUNCH_CHECK("k_leaves");
+    return GIS_OK;
+  }
+  const int64_t total = ci.off[ci.lmax + 1];
+  rc = fill_u8(ci.state, (uint8_t)ST_NONE, total, s);
+  if (rc != GIS_OK) return rc;
+  if (n_cells > 0) {
+    hipLaunchKernelGGL(k_leaves, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
+                       n_cells, 1, d_err);
+    GIS_LAUNCH_CHECK("k_leaves");
+    hipLaunchKernelGGL(k_ancestors, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
+                       n_cells, d_err);
+    GIS_LAUNCH_CHECK("k_ancestors");
+  }
+  hipLaunchKernelGGL(k_holes, dim3(grid_for(total)), dim3(256), 0, s, ci);
+  GIS_LAUNCH_CHECK("k_holes");
+  return GIS_OK;
+}
+
+int32_t index_mark_dropped(const CoverIndex& ci, const uint8_t* level, const int32_t* idx,
+                           int64_t n_cells, const uint8_t* kept, hipStream_t s) {
+  if (n_cells == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_mark_dropped, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
+                     n_cells, kept);
+  GIS_LAUNCH_CHECK("k_mark_dropped");
+  return GIS_OK;
+}
+
+}  // namespace gis

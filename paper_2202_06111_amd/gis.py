@@ -1,0 +1,409 @@
+"""Python binding of libgis (the C ABI of include/gis.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch provides device memory (tensors passed by data_ptr()) and streams
+(torch.cuda.current_stream().cuda_stream).  Importing this module loads the
+library and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import workloads as W
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgis.so")
+
+KIND = {W.LINEAR: 0, W.VDP: 1, W.LORENZ: 2, W.VDP2: 3}
+SAMPLES = {W.LATTICE3: 1, W.CORNERS_CENTER: 2}
+PRECISION = {"fp64": 1, "fp32_recheck": 2}
+RULE = {W.SHELL: 1, W.CORNERS: 2}
+ANALYSIS = {"controlled": 1, "nonleaving": 2}
+STATUS = {0: "GIS_OK", 1: "GIS_E_INVAL", 2: "GIS_E_NOMEM", 3: "GIS_E_HIP", 4: "GIS_E_CAPACITY",
+          5: "GIS_E_UNSUPPORTED", 6: "GIS_E_INTERNAL"}
+MAX_ROUNDS = 32
+
+P = ctypes.c_void_p
+I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class SystemT(ctypes.Structure):
+    _fields_ = [("kind", I32), ("n", I32), ("m", I32), ("nsub", I32), ("dt", F64),
+                ("params", F64 * 32)]
+
+
+class GridT(ctypes.Structure):
+    _fields_ = [("n", I32), ("n0", I32 * 4), ("lo", F64 * 4), ("hi", F64 * 4)]
+
+
+class OptsT(ctypes.Structure):
+    _fields_ = [("samples", I32), ("precision", I32), ("boundary_rule", I32), ("analysis", I32),
+                ("fast_out", I32), ("timing", I32), ("reserved", I32 * 2), ("band", F64 * 4)]
+
+
+class CellsT(ctypes.Structure):
+    _fields_ = [("n_cells", I64), ("cap", I64), ("level", P), ("idx", P)]
+
+
+class GraphT(ctypes.Structure):
+    _fields_ = [("n_rows", I64), ("n_edges", I64), ("n_out", I64), ("n_recheck", I64),
+                ("cap_edges", I64), ("row_ptr", P), ("col", P), ("out", P)]
+
+
+class RoundStatsT(ctypes.Structure):
+    _fields_ = [("n_cells", I64), ("n_rows", I64), ("n_edges", I64), ("n_out", I64),
+                ("n_kept", I64), ("n_boundary", I64), ("n_recheck", I64), ("max_level", I32),
+                ("reserved", I32), ("ms_build", F64), ("ms_prune", F64), ("ms_subdivide", F64),
+                ("ms_image", F64), ("ms_recheck", F64)]
+
+
+class SolveInfoT(ctypes.Structure):
+    _fields_ = [("n_rounds", I32), ("n", I32), ("K", I32), ("mask_words", I32),
+                ("n_cells", I64), ("n_kept", I64), ("band", F64 * 4),
+                ("rounds", RoundStatsT * MAX_ROUNDS)]
+
+
+class GisError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libgis.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "gis_ctx_create": ([I32, ctypes.POINTER(P)], I32),
+            "gis_ctx_destroy": ([P], None),
+            "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
+            "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
+            "gis_subdivide": ([P, P, P, P, I32, P, P, P], I32),
+            "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
+            "gis_solution_info": ([P, P], I32),
+            "gis_solution_export": ([P, P, P, P, P], I32),
+            "gis_solution_free": ([P], None),
+            "gis_query_membership": ([P, P, I64, P, P], I32),
+            "gis_query_admissible": ([P, P, I64, P, P], I32),
+            "gis_images": ([P, P, P, P, I32, P, I32, I32, P, P], I32),
+            "gis_calibrate_band": ([P, P, P, P, I32, P, I32, F64, F64, P, P], I32),
+            "gis_last_error": ([], ctypes.c_char_p),
+            "gis_version": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_build_graph", "gis_prune", "gis_subdivide",
+            "gis_solve", "gis_solution_info", "gis_solution_export", "gis_solution_free",
+            "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
+            "gis_last_error", "gis_version")
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise GisError(rc, lib().gis_last_error().decode())
+
+
+def _stream_ptr(stream=None) -> P:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return P(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> P:
+    return P(0 if t is None else t.data_ptr())
+
+
+# ------------------------------------------------------------------ structs
+def system_t(system: W.System) -> SystemT:
+    s = SystemT()
+    s.kind = KIND[system.kind]
+    s.n, s.m, s.nsub, s.dt = system.n, system.m, system.nsub, system.dt
+    for i, v in enumerate(system.param_array()):
+        s.params[i] = float(v)
+    return s
+
+
+def grid_t(grid: W.Grid) -> GridT:
+    g = GridT()
+    g.n = grid.n
+    for d in range(grid.n):
+        g.n0[d], g.lo[d], g.hi[d] = grid.n0[d], grid.lo[d], grid.hi[d]
+    return g
+
+
+def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: str = W.SHELL,
+           analysis: str = "controlled", fast_out: bool = False,
+           band: Optional[Sequence[float]] = None, timing: bool = False) -> OptsT:
+    o = OptsT()
+    o.samples = SAMPLES[samples]
+    o.precision = PRECISION[precision]
+    o.boundary_rule = RULE[boundary_rule]
+    o.analysis = ANALYSIS[analysis]
+    o.fast_out = int(bool(fast_out))
+    o.timing = int(bool(timing))
+    for d, v in enumerate([] if band is None else list(band)):
+        o.band[d] = float(v)
+    return o
+
+
+def workload_opts(wl: W.Workload, **over) -> OptsT:
+    kw = dict(samples=wl.samples, precision=wl.precision, boundary_rule=wl.boundary_rule,
+              analysis=wl.analysis)
+    kw.update(over)
+    return opts_t(**kw)
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """A libgis context (device workspace) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = P()
+        _check(lib().gis_ctx_create(device, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> P:
+        if self._h is None:
+            raise RuntimeError("context is closed")
+        return self._h
+
+    def close(self) -> None:
+        if self._h is not None:
+            lib().gis_ctx_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dev(self) -> torch.device:
+        return torch.device("cuda", self.device)
+
+
+def to_device_u(ctx: Context, u) -> torch.Tensor:
+    if isinstance(u, torch.Tensor):
+        return u.to(device=ctx.dev, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(u, dtype=np.float64), device=ctx.dev)
+
+
+def cells_t(level: torch.Tensor, idx: torch.Tensor, cap: Optional[int] = None) -> CellsT:
+    c = CellsT()
+    c.n_cells = int(level.shape[0])
+    c.cap = int(level.shape[0] if cap is None else cap)
+    c.level = _ptr(level)
+    c.idx = _ptr(idx)
+    return c
+
+
+@dataclasses.dataclass
+class Graph:
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    out: torch.Tensor
+    n_rows: int
+    n_edges: int
+    n_out: int
+    n_recheck: int
+
+    def graph_t(self) -> GraphT:
+        g = GraphT()
+        g.n_rows, g.n_edges, g.n_out, g.n_recheck = self.n_rows, self.n_edges, self.n_out, self.n_recheck
+        g.cap_edges = int(self.col.shape[0])
+        g.row_ptr, g.col, g.out = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.out)
+        return g
+
+
+def coarse_cells(ctx: Context, grid: W.Grid):
+    """The full level-0 covering as device tensors (canonical order)."""
+    axes = [torch.arange(k, dtype=torch.int32) for k in grid.n0]
+    mesh = torch.meshgrid(*axes, indexing="ij")
+    idx = torch.stack([m.reshape(-1) for m in mesh], dim=1).contiguous().to(ctx.dev)
+    level = torch.zeros(idx.shape[0], dtype=torch.uint8, device=ctx.dev)
+    return level, idx
+
+
+def build_graph(ctx: Context, system: W.System, grid: W.Grid, u, level: torch.Tensor,
+                idx: torch.Tensor, opts: OptsT, cap_edges: Optional[int] = None, stream=None) -> Graph:
+    """Symbolic image of a covering; grows col and retries once on a capacity miss."""
+    du = to_device_u(ctx, u)
+    K = int(du.shape[0])
+    n_rows = int(level.shape[0]) * K
+    row_ptr = torch.empty(n_rows + 1, dtype=torch.int64, device=ctx.dev)
+    out = torch.empty(max(n_rows, 1), dtype=torch.uint8, device=ctx.dev)
+    cap = int(cap_edges if cap_edges is not None else max(16, 12 * n_rows))
+    st, gt, ct = system_t(system), grid_t(grid), cells_t(level, idx)
+    for attempt in range(2):
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=ctx.dev)
+        g = GraphT()
+        g.cap_edges = cap
+        g.row_ptr, g.col, g.out = _ptr(row_ptr), _ptr(col), _ptr(out)
+        rc = lib().gis_build_graph(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du), K,
+                                   ctypes.byref(ct), ctypes.byref(opts), ctypes.byref(g),
+                                   _stream_ptr(stream))
+        if rc == 4 and attempt == 0:
+            cap = int(g.n_edges)
+            continue
+        _check(rc)
+        return Graph(row_ptr, col[: g.n_edges], out[:n_rows], n_rows, int(g.n_edges), int(g.n_out),
+                     int(g.n_recheck))
+    raise GisError(4, "capacity retry failed")
+
+
+def prune(ctx: Context, graph: Graph, n_cells: int, K: int, analysis: str = "controlled",
+          stream=None):
+    """Graph analysis; returns (kept uint8 [n_cells], mask int64 [n_cells, W], n_kept)."""
+    Wd = (K + 63) // 64
+    kept = torch.empty(max(n_cells, 1), dtype=torch.uint8, device=ctx.dev)
+    mask = torch.empty((max(n_cells, 1), Wd), dtype=torch.int64, device=ctx.dev)
+    nk = I64(0)
+    g = graph.graph_t()
+    _check(lib().gis_prune(ctx.handle, ctypes.byref(g), n_cells, K, ANALYSIS[analysis], _ptr(kept),
+                           _ptr(mask), ctypes.byref(nk), _stream_ptr(stream)))
+    return kept[:n_cells], mask[:n_cells], int(nk.value)
+
+
+def subdivide(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor,
+              kept: torch.Tensor, rule: str = W.SHELL, stream=None):
+    """Boundary selection and subdivision; returns (level, idx, boundary flags)."""
+    n_cells = int(level.shape[0])
+    cap = max(1, int(kept.sum().item()) << grid.n) if n_cells else 1
+    lv = torch.empty(cap, dtype=torch.uint8, device=ctx.dev)
+    ix = torch.empty((cap, grid.n), dtype=torch.int32, device=ctx.dev)
+    bnd = torch.empty(max(n_cells, 1), dtype=torch.uint8, device=ctx.dev)
+    cin = cells_t(level, idx)
+    cout = cells_t(lv, ix, cap)
+    gt = grid_t(grid)
+    _check(lib().gis_subdivide(ctx.handle, ctypes.byref(gt), ctypes.byref(cin), _ptr(kept),
+                               RULE[rule], _ptr(bnd), ctypes.byref(cout), _stream_ptr(stream)))
+    n = int(cout.n_cells)
+    return lv[:n], ix[:n], bnd[:n_cells]
+
+
+def images(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, samples: str,
+           precision: str = "fp64", stream=None) -> torch.Tensor:
+    du = to_device_u(ctx, u)
+    K = int(du.shape[0])
+    S = W.sample_count(samples, grid.n)
+    out = torch.empty((int(level.shape[0]) * K, S, grid.n), dtype=torch.float64, device=ctx.dev)
+    st, gt, ct = system_t(system), grid_t(grid), cells_t(level, idx)
+    _check(lib().gis_images(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du), K,
+                            ctypes.byref(ct), SAMPLES[samples], PRECISION[precision], _ptr(out),
+                            _stream_ptr(stream)))
+    return out
+
+
+def calibrate_band(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, samples: str,
+                   safety: float = 8.0, floor_rel: float = 1e-5, stream=None) -> np.ndarray:
+    du = to_device_u(ctx, u)
+    band = (F64 * 4)()
+    st, gt, ct = system_t(system), grid_t(grid), cells_t(level, idx)
+    _check(lib().gis_calibrate_band(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du),
+                                    int(du.shape[0]), ctypes.byref(ct), SAMPLES[samples], safety,
+                                    floor_rel, band, _stream_ptr(stream)))
+    return np.array(band[: grid.n])
+
+
+class Solution:
+    """A solve result resident on the device (library-owned handle)."""
+
+    def __init__(self, handle: P, device: int):
+        self._h = handle
+        self.device = device
+
+    @property
+    def handle(self) -> P:
+        if self._h is None:
+            raise RuntimeError("solution is freed")
+        return self._h
+
+    def info(self) -> dict:
+        inf = SolveInfoT()
+        _check(lib().gis_solution_info(self.handle, ctypes.byref(inf)))
+        rounds = []
+        for r in range(inf.n_rounds):
+            s = inf.rounds[r]
+            rounds.append({k: getattr(s, k) for k, _ in RoundStatsT._fields_ if k != "reserved"})
+        return {"n_rounds": inf.n_rounds, "n": inf.n, "K": inf.K, "mask_words": inf.mask_words,
+                "n_cells": inf.n_cells, "n_kept": inf.n_kept, "band": list(inf.band[: inf.n]),
+                "rounds": rounds}
+
+    def export(self, stream=None):
+        inf = self.info()
+        n, nc, Wd = inf["n"], inf["n_cells"], inf["mask_words"]
+        dev = torch.device("cuda", self.device)
+        lv = torch.empty(max(nc, 1), dtype=torch.uint8, device=dev)
+        ix = torch.empty((max(nc, 1), n), dtype=torch.int32, device=dev)
+        kept = torch.empty(max(nc, 1), dtype=torch.uint8, device=dev)
+        mask = torch.empty((max(nc, 1), Wd), dtype=torch.int64, device=dev)
+        c = cells_t(lv, ix, max(nc, 1))
+        _check(lib().gis_solution_export(self.handle, ctypes.byref(c), _ptr(kept), _ptr(mask),
+                                         _stream_ptr(stream)))
+        return lv[:nc], ix[:nc], kept[:nc], mask[:nc]
+
+    def query_membership(self, states: torch.Tensor, stream=None) -> torch.Tensor:
+        states = states.to(dtype=torch.float64).contiguous()
+        out = torch.empty(max(states.shape[0], 1), dtype=torch.uint8, device=states.device)
+        _check(lib().gis_query_membership(self.handle, _ptr(states), int(states.shape[0]),
+                                          _ptr(out), _stream_ptr(stream)))
+        return out[: states.shape[0]]
+
+    def query_admissible(self, states: torch.Tensor, stream=None) -> torch.Tensor:
+        states = states.to(dtype=torch.float64).contiguous()
+        Wd = self.info()["mask_words"]
+        out = torch.empty((max(states.shape[0], 1), Wd), dtype=torch.int64, device=states.device)
+        _check(lib().gis_query_admissible(self.handle, _ptr(states), int(states.shape[0]),
+                                          _ptr(out), _stream_ptr(stream)))
+        return out[: states.shape[0]]
+
+    def free(self) -> None:
+        if self._h is not None:
+            lib().gis_solution_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def solve(ctx: Context, system: W.System, grid: W.Grid, u, rounds: int, opts: OptsT,
+          stream=None) -> Solution:
+    du = to_device_u(ctx, u)
+    h = P()
+    st, gt = system_t(system), grid_t(grid)
+    _check(lib().gis_solve(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du),
+                           int(du.shape[0]), rounds, ctypes.byref(opts), ctypes.byref(h),
+                           _stream_ptr(stream)))
+    return Solution(h, ctx.device)
+
+
+def solve_workload(ctx: Context, wl: W.Workload, stream=None, **opt_over) -> Solution:
+    return solve(ctx, wl.system, wl.grid, wl.u, wl.rounds, workload_opts(wl, **opt_over), stream)

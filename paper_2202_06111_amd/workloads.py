@@ -68,6 +68,11 @@ class Workload:
     rounds: int
     precision: str           # "fp64" or "fp32_recheck"
     boundary_rule: str = SHELL
+    # graph analysis: "controlled" (every image of some input stays in the kept
+    # set) or "nonleaving" (cells with an infinite admissible path, the
+    # paper's analysis).  Boundary-only refinement needs the latter: under the
+    # controlled analysis a 32x32 Van der Pol covering keeps no cell at all.
+    analysis: str = "controlled"
 
     @property
     def K(self) -> int:
@@ -135,7 +140,8 @@ def vdp_uniform_64() -> Workload:
 def vdp_adaptive_32(precision: str = "fp32_recheck") -> Workload:
     """Van der Pol, 32x32 coarse grid, 5 boundary-only refinement rounds, 21 inputs."""
     return Workload("vdp_adaptive_32x32_r5", vdp(), Grid((32, 32), *VDP_BOX),
-                    evenly_spaced(-1.0, 1.0, 21), LATTICE3, 5, precision)
+                    evenly_spaced(-1.0, 1.0, 21), LATTICE3, 5, precision,
+                    analysis="nonleaving")
 
 
 def lorenz_uniform_128() -> Workload:
@@ -149,7 +155,8 @@ def vdp2_adaptive_32() -> Workload:
     """Two coupled Van der Pol oscillators, 32^4 coarse grid + 2 boundary rounds, 7x7 inputs."""
     return Workload("vdp2_adaptive_32^4_r2", vdp2(),
                     Grid((32, 32, 32, 32), (-2.5, -3.0, -2.5, -3.0), (2.5, 3.0, 2.5, 3.0)),
-                    input_grid(-1.0, 1.0, 7, 2), CORNERS_CENTER, 2, "fp32_recheck")
+                    input_grid(-1.0, 1.0, 7, 2), CORNERS_CENTER, 2, "fp32_recheck",
+                    analysis="nonleaving")
 
 
 def scaled_vdp_box(scale: float) -> Tuple[Tuple[float, ...], Tuple[float, ...]]:

@@ -1,0 +1,335 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar: integer, index and flag outputs (edges, OUT flags, kept cells, masks,
+cell lists, query answers) bit-exact; FP64 sample images within 1e-10
+relative (|a - b| <= 1e-10 max(|a|, |b|, hi_d - lo_d)) -- the canonical
+operation order is expected to give 0 ulp, which is asserted separately.
+The FP32-with-FP64-recheck path must give the very same graph as FP64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from conftest import gpu_available
+from paper_2202_06111_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2202_06111_amd import gis
+    return gis
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _cells(ctx, level, idx):
+    return (torch.as_tensor(np.ascontiguousarray(level, np.uint8), device=ctx.dev),
+            torch.as_tensor(np.ascontiguousarray(idx, np.int32), device=ctx.dev))
+
+
+def _adaptive_cells(rng, n0, splits, drop_frac=0.1):
+    import itertools
+    n = len(n0)
+    cells = {(0,) + c for c in itertools.product(*[range(k) for k in n0])}
+    for _ in range(splits):
+        c = sorted(cells)[rng.integers(0, len(cells))]
+        cells.remove(c)
+        for ch in itertools.product((0, 1), repeat=n):
+            cells.add((c[0] + 1,) + tuple(2 * c[1 + d] + ch[d] for d in range(n)))
+    cells = sorted(cells)
+    keep = rng.random(len(cells)) >= drop_frac
+    cells = [c for c, k in zip(cells, keep) if k]
+    return (np.array([c[0] for c in cells], np.uint8),
+            np.array([c[1:] for c in cells], np.int32).reshape(len(cells), n))
+
+
+SMALL = {
+    "vdp": (W.vdp(), W.Grid((24, 20), *W.VDP_BOX), W.evenly_spaced(-1, 1, 5), W.LATTICE3),
+    "lorenz": (W.lorenz(), W.Grid((10, 12, 9), (-20., -25., 0.), (20., 25., 50.)),
+               W.evenly_spaced(-10, 10, 4), W.CORNERS_CENTER),
+    "vdp2": (W.vdp2(), W.Grid((5, 6, 5, 6), (-2.5, -3., -2.5, -3.), (2.5, 3., 2.5, 3.)),
+             W.input_grid(-1, 1, 3, 2), W.CORNERS_CENTER),
+    "linear1": (W.linear([[0.7]], [[1.0]], 0.1, 3), W.Grid((37,), (-2.,), (2.,)),
+                W.evenly_spaced(-1, 1, 7), W.LATTICE3),
+    "linear3": (W.random_linear(5, 3, 2), W.Grid((7, 6, 5), (-1.,) * 3, (1.,) * 3),
+                W.input_grid(-1, 1, 2, 2), W.LATTICE3),
+}
+
+
+# ------------------------------------------------------------------ images
+@pytest.mark.parametrize("name", list(SMALL))
+def test_images_fp64_bitexact(G, ctx, name):
+    system, grid, u, samples = SMALL[name]
+    level, idx = oracle.coarse_cells(grid)
+    want = oracle.images(system, grid, samples, level, idx, u)
+    dl, di = _cells(ctx, level, idx)
+    got = _np(G.images(ctx, system, grid, u, dl, di, samples, "fp64"))
+    scale = np.maximum(np.maximum(np.abs(got), np.abs(want)),
+                       (np.array(grid.hi) - np.array(grid.lo))[None, None, :])
+    assert (np.abs(got - want) <= 1e-10 * scale).all()
+    assert np.array_equal(got.view(np.int64), want.view(np.int64)), "expected 0-ulp agreement"
+
+
+# ------------------------------------------------------------------ build
+def _check_graph(G, ctx, system, grid, u, samples, level, idx, precision="fp64", band=None,
+                 fast_out=False):
+    want = oracle.build_graph(system, grid, samples, level, idx, u, fast_out=fast_out)
+    dl, di = _cells(ctx, level, idx)
+    opts = G.opts_t(samples=samples, precision=precision, band=band, fast_out=fast_out)
+    g = G.build_graph(ctx, system, grid, u, dl, di, opts)
+    np.testing.assert_array_equal(_np(g.row_ptr), want["row_ptr"])
+    np.testing.assert_array_equal(_np(g.col), want["col"])
+    np.testing.assert_array_equal(_np(g.out), want["out"])
+    assert g.n_edges == want["col"].shape[0] and g.n_out == int(want["out"].sum())
+    return g, want
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_build_uniform_matches_oracle(G, ctx, name):
+    system, grid, u, samples = SMALL[name]
+    level, idx = oracle.coarse_cells(grid)
+    _check_graph(G, ctx, system, grid, u, samples, level, idx)
+
+
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_build_adaptive_matches_oracle(G, ctx, name, seed):
+    """Mixed-level coverings with holes: edges to coarse and fine cells, holes -> OUT."""
+    system, grid, u, samples = SMALL[name]
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    level, idx = _adaptive_cells(rng, grid.n0, splits=12 if grid.n < 4 else 6)
+    g, want = _check_graph(G, ctx, system, grid, u, samples, level, idx)
+    assert want["out"].sum() > 0
+
+
+def test_build_fast_out(G, ctx):
+    system, grid, u, samples = SMALL["vdp"]
+    level, idx = oracle.coarse_cells(grid)
+    _check_graph(G, ctx, system, grid, u, samples, level, idx, fast_out=True)
+
+
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2"])
+def test_build_fp32_recheck_equals_fp64(G, ctx, name):
+    system, grid, u, samples = SMALL[name]
+    rng = np.random.Generator(np.random.PCG64(7))
+    level, idx = _adaptive_cells(rng, grid.n0, splits=8 if grid.n < 4 else 4)
+    dl, di = _cells(ctx, level, idx)
+    band = G.calibrate_band(ctx, system, grid, u, dl, di, samples, safety=8.0, floor_rel=1e-7)
+    assert (band > 0).all()
+    g, _ = _check_graph(G, ctx, system, grid, u, samples, level, idx, precision="fp32_recheck",
+                        band=band)
+    assert 0 <= g.n_recheck < g.n_rows
+
+
+# ------------------------------------------------------------------ prune
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1"])
+def test_prune_matches_oracle(G, ctx, name, analysis):
+    system, grid, u, samples = SMALL[name]
+    rng = np.random.Generator(np.random.PCG64(3))
+    level, idx = _adaptive_cells(rng, grid.n0, splits=6, drop_frac=0.05)
+    g, want = _check_graph(G, ctx, system, grid, u, samples, level, idx)
+    kept_w, mask_w, _ = oracle.prune(want["row_ptr"], want["col"], want["out"], level.shape[0],
+                                     u.shape[0], analysis)
+    kept, mask, nk = G.prune(ctx, g, level.shape[0], u.shape[0], analysis)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+    assert nk == int(kept_w.sum())
+
+
+def test_prune_deep_peel(G, ctx):
+    """Pure drift: every cell is removed, one layer at a time (deep frontier)."""
+    grid = W.Grid((3000,), (-1.0,), (1.0,))
+    system = W.linear([[0.0]], [[1.0]], dt=0.0005, nsub=1)
+    u = np.array([[1.0]])
+    level, idx = oracle.coarse_cells(grid)
+    g, want = _check_graph(G, ctx, system, grid, u, W.LATTICE3, level, idx)
+    kept, mask, nk = G.prune(ctx, g, level.shape[0], 1, "controlled")
+    assert nk == 0 and _np(kept).sum() == 0
+
+
+# ------------------------------------------------------------------ subdivide
+@pytest.mark.parametrize("rule", ["shell", "corners"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "linear3"])
+def test_subdivide_matches_oracle(G, ctx, name, rule):
+    system, grid, u, samples = SMALL[name]
+    rng = np.random.Generator(np.random.PCG64(11))
+    level, idx = _adaptive_cells(rng, grid.n0, splits=5, drop_frac=0.0)
+    kept = (rng.random(level.shape[0]) < 0.8).astype(np.uint8)
+    bnd_w = oracle.boundary(grid, level, idx, kept, rule)
+    lv_w, ix_w = oracle.subdivide(grid, level, idx, kept, bnd_w)
+    dl, di = _cells(ctx, level, idx)
+    lv, ix, bnd = G.subdivide(ctx, grid, dl, di, torch.as_tensor(kept, device=ctx.dev), rule)
+    np.testing.assert_array_equal(_np(bnd), bnd_w)
+    np.testing.assert_array_equal(_np(lv), lv_w)
+    np.testing.assert_array_equal(_np(ix), ix_w)
+
+
+def test_worked_example_5x5_on_gpu(G, ctx):
+    grid = W.Grid((5, 5), (0.0, 0.0), (5.0, 5.0))
+    level, idx = oracle.coarse_cells(grid)
+    for removed, rule, want in [((25,), "corners", [1, 2, 3, 4, 5, 6, 10, 11, 15, 16, 19, 20, 21, 22, 23, 24]),
+                                ((4, 25), "corners", [1, 2, 3, 5, 6, 8, 10, 11, 15, 16, 19, 20, 21, 22, 23, 24]),
+                                ((4, 25), "shell", [1, 2, 3, 5, 6, 8, 9, 10, 11, 15, 16, 19, 20, 21, 22, 23, 24])]:
+        kept = np.ones(25, np.uint8)
+        kept[[b - 1 for b in removed]] = 0
+        dl, di = _cells(ctx, level, idx)
+        _, _, bnd = G.subdivide(ctx, grid, dl, di, torch.as_tensor(kept, device=ctx.dev), rule)
+        assert sorted((np.nonzero(_np(bnd))[0] + 1).tolist()) == want
+
+
+# ------------------------------------------------------------------ solve + queries
+def _oracle_solve(wl, **kw):
+    return oracle.solve(wl.system, wl.grid, wl.samples, wl.u, wl.rounds, rule=wl.boundary_rule,
+                        analysis=wl.analysis, **kw)
+
+
+def _check_solve(G, ctx, wl, precision=None):
+    want = _oracle_solve(wl)
+    over = {} if precision is None else {"precision": precision}
+    sol = G.solve_workload(ctx, wl, **over)
+    info = sol.info()
+    lv, ix, kept, mask = sol.export()
+    np.testing.assert_array_equal(_np(lv), want["level"])
+    np.testing.assert_array_equal(_np(ix), want["idx"])
+    np.testing.assert_array_equal(_np(kept), want["kept"])
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), want["mask"])
+    assert info["n_rounds"] == len(want["stats"])
+    for got_r, want_r in zip(info["rounds"], want["stats"]):
+        for k in ("n_cells", "n_rows", "n_edges", "n_out", "n_kept"):
+            assert got_r[k] == want_r[k], (k, got_r, want_r)
+    return sol, want, info
+
+
+def test_solve_vdp_uniform_64(G, ctx):
+    _check_solve(G, ctx, W.vdp_uniform_64())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_recheck"])
+def test_solve_vdp_adaptive_32_r5(G, ctx, precision):
+    sol, want, info = _check_solve(G, ctx, W.vdp_adaptive_32(precision), precision)
+    assert info["n_rounds"] == 6
+    if precision == "fp32_recheck":
+        assert all(b > 0 for b in info["band"])
+
+
+def test_solve_controlled_adaptive_small(G, ctx):
+    wl = W.Workload("vdp_48_r3_controlled", W.vdp(), W.Grid((48, 48), *W.VDP_BOX),
+                    W.evenly_spaced(-1, 1, 9), W.LATTICE3, 3, "fp64", analysis="controlled")
+    _check_solve(G, ctx, wl)
+
+
+def test_solve_corners_rule(G, ctx):
+    wl = W.Workload("vdp_32_r3_corners", W.vdp(), W.Grid((32, 32), *W.VDP_BOX),
+                    W.evenly_spaced(-1, 1, 7), W.LATTICE3, 3, "fp64", boundary_rule=W.CORNERS,
+                    analysis="nonleaving")
+    _check_solve(G, ctx, wl)
+
+
+def test_solve_vdp2_small_rounds(G, ctx):
+    wl = W.Workload("vdp2_8_r2", W.vdp2(), W.Grid((8, 8, 8, 8), (-2.5, -3, -2.5, -3), (2.5, 3, 2.5, 3)),
+                    W.input_grid(-1, 1, 3, 2), W.CORNERS_CENTER, 2, "fp32_recheck",
+                    analysis="nonleaving")
+    _check_solve(G, ctx, wl)
+
+
+def test_solve_lorenz_small(G, ctx):
+    wl = W.Workload("lorenz_24", W.lorenz(), W.Grid((24, 24, 24), (-20., -25., 0.), (20., 25., 50.)),
+                    W.evenly_spaced(-10, 10, 5), W.CORNERS_CENTER, 1, "fp32_recheck")
+    _check_solve(G, ctx, wl)
+
+
+@pytest.mark.parametrize("wl", [W.vdp_uniform_64(), W.vdp_adaptive_32("fp64")],
+                         ids=["uniform", "adaptive"])
+def test_queries_match_oracle(G, ctx, wl):
+    want = _oracle_solve(wl)
+    sol = G.solve_workload(ctx, wl)
+    states = W.query_states(wl.grid, 20000, seed=5, margin=0.05)
+    # exact faces and the upper border too
+    states[:50] = np.array(wl.grid.hi)[None, :]
+    states[50:100, 0] = wl.grid.lo[0]
+    m_w, a_w = oracle.query(wl.grid, want["level"], want["idx"], want["kept"], want["mask"], states)
+    ds = torch.as_tensor(states, device=ctx.dev)
+    np.testing.assert_array_equal(_np(sol.query_membership(ds)), m_w)
+    np.testing.assert_array_equal(_np(sol.query_admissible(ds)).view(np.uint64), a_w)
+
+
+def test_determinism(G, ctx):
+    wl = W.vdp_adaptive_32("fp32_recheck")
+    a = [_np(t) for t in G.solve_workload(ctx, wl).export()]
+    b = [_np(t) for t in G.solve_workload(ctx, wl).export()]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------------ ABI errors
+def test_abi_error_paths(G, ctx):
+    import ctypes
+    L = G.lib()
+    system, grid, u, samples = SMALL["vdp"]
+    level, idx = oracle.coarse_cells(grid)
+    dl, di = _cells(ctx, level, idx)
+    du = G.to_device_u(ctx, u)
+    st, gt, ct = G.system_t(system), G.grid_t(grid), G.cells_t(dl, di)
+    n_rows = level.shape[0] * u.shape[0]
+    row_ptr = torch.empty(n_rows + 1, dtype=torch.int64, device=ctx.dev)
+    out = torch.empty(n_rows, dtype=torch.uint8, device=ctx.dev)
+    col = torch.empty(8, dtype=torch.int32, device=ctx.dev)
+    g = G.GraphT()
+    g.cap_edges, g.row_ptr, g.col, g.out = 8, G._ptr(row_ptr), G._ptr(col), G._ptr(out)
+    opts = G.opts_t(samples=samples)
+    s = G._stream_ptr()
+    # capacity too small -> GIS_E_CAPACITY with the needed count
+    rc = L.gis_build_graph(ctx.handle, ctypes.byref(st), ctypes.byref(gt), G._ptr(du), u.shape[0],
+                           ctypes.byref(ct), ctypes.byref(opts), ctypes.byref(g), s)
+    assert rc == 4 and g.n_edges > 8
+    want = oracle.build_graph(system, grid, samples, level, idx, u)
+    assert g.n_edges == want["col"].shape[0]
+    np.testing.assert_array_equal(_np(row_ptr), want["row_ptr"])
+    # invalid system / grid / opts
+    bad = G.system_t(system)
+    bad.n = 3
+    assert L.gis_build_graph(ctx.handle, ctypes.byref(bad), ctypes.byref(gt), G._ptr(du), u.shape[0],
+                             ctypes.byref(ct), ctypes.byref(opts), ctypes.byref(g), s) == 1
+    badg = G.grid_t(grid)
+    badg.lo[0] = badg.hi[0]
+    assert L.gis_build_graph(ctx.handle, ctypes.byref(st), ctypes.byref(badg), G._ptr(du), u.shape[0],
+                             ctypes.byref(ct), ctypes.byref(opts), ctypes.byref(g), s) == 1
+    fp32 = G.opts_t(samples=samples, precision="fp32_recheck")   # no band -> invalid
+    assert L.gis_build_graph(ctx.handle, ctypes.byref(st), ctypes.byref(gt), G._ptr(du), u.shape[0],
+                             ctypes.byref(ct), ctypes.byref(fp32), ctypes.byref(g), s) == 1
+    assert b"band" in L.gis_last_error()
+    # non-canonical / out-of-range / overlapping cell lists
+    for lv_bad, ix_bad in [(level, idx[::-1].copy()),
+                           (level, np.where(idx == 0, 99, idx).astype(np.int32)),
+                           (np.array([0, 1], np.uint8), np.array([[0, 0], [1, 1]], np.int32))]:
+        bl, bi = _cells(ctx, lv_bad, ix_bad)
+        cb = G.cells_t(bl, bi)
+        g.n_rows = 0
+        rc = L.gis_build_graph(ctx.handle, ctypes.byref(st), ctypes.byref(gt), G._ptr(du),
+                               u.shape[0], ctypes.byref(cb), ctypes.byref(opts), ctypes.byref(g), s)
+        assert rc == 1, L.gis_last_error()
+    # an inconsistent caller graph is refused by gis_prune
+    gg = G.GraphT()
+    bad_rp = torch.zeros(n_rows + 1, dtype=torch.int64, device=ctx.dev)
+    bad_rp[-1] = 5
+    bad_col = torch.full((5,), 10 ** 6, dtype=torch.int32, device=ctx.dev)
+    gg.n_rows, gg.n_edges, gg.cap_edges = n_rows, 5, 5
+    gg.row_ptr, gg.col, gg.out = G._ptr(bad_rp), G._ptr(bad_col), G._ptr(out)
+    kept = torch.empty(level.shape[0], dtype=torch.uint8, device=ctx.dev)
+    mask = torch.empty(level.shape[0], dtype=torch.int64, device=ctx.dev)
+    assert L.gis_prune(ctx.handle, ctypes.byref(gg), level.shape[0], u.shape[0], 1, G._ptr(kept),
+                       G._ptr(mask), None, s) == 1
