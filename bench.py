@@ -125,6 +125,10 @@ def main():
                                ("f64" if precision == "fp64" else "f32"),
                      "avg_launch_ms": img_ms / max(launches, 1),
                      "flops_per_row": flops_row},
+        "phases_ms_per_solve": {
+            k: sum(r[k] for inf in infos for r in inf["rounds"]) / a.steps
+            for k in ("ms_build", "ms_image", "ms_recheck", "ms_prune", "ms_subdivide")},
+        "recheck_rows_per_solve": sum(r["n_recheck"] for inf in infos for r in inf["rounds"]) / a.steps,
         "solves_per_s": a.steps / el,
         "latency_ms": {"p50": 1e3 * statistics.median(lat),
                        "p99": 1e3 * sorted(lat)[min(len(lat) - 1, int(0.99 * len(lat)))]},

@@ -228,10 +228,12 @@ int32_t list_lmax(gis_ctx* ctx, const uint8_t* level, int64_t n_cells, int* lmax
 }
 
 // Builds (or, for the full level-0 grid, only checks) the covering index of
-// a cell list in the context's index buffers.  Synchronises to report an
-// invalid list.
+// a cell list in the context's index buffers.  With `validate` it
+// synchronises to report an invalid list; lists the library produced itself
+// are canonical by construction and skip that round trip.
 int32_t prepare_index(gis_ctx* ctx, const GridArgs& g, const uint8_t* level, const int32_t* idx,
-                      int64_t n_cells, int lmax, bool want_arrays, CoverIndex& ci, hipStream_t s) {
+                      int64_t n_cells, int lmax, bool want_arrays, CoverIndex& ci, hipStream_t s,
+                      bool validate = true) {
   int32_t rc = layout_index(ci, g, lmax);
   if (rc) return rc;
   ci.uniform = (!want_arrays && lmax == 0 && n_cells == prod_n0(g)) ? 1 : 0;
@@ -245,6 +247,7 @@ int32_t prepare_index(gis_ctx* ctx, const GridArgs& g, const uint8_t* level, con
     ci.id = (int32_t*)ctx->idx_id.ptr;
   }
   if ((rc = index_build(ci, g, level, idx, n_cells, &dcnt(ctx)->err, s))) return rc;
+  if (!validate) return GIS_OK;
   if ((rc = sync_counters(ctx, s))) return rc;
   const uint32_t e = ctx->h_counters->err;
   if (e & 1u) return inval("a cell's level or multi-index is out of range");
@@ -679,20 +682,16 @@ int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, con
       if ((rc = ensure(lvN, (size_t)cap + 16)) || (rc = ensure(ixN, (size_t)cap * n * 4 + 16))) return rc;
       if ((rc = ensure(ctx->bnd, (size_t)n_cells + 16))) return rc;
       if (ci.uniform) {  // the boundary walk needs the index arrays
-        if ((rc = prepare_index(ctx, ga, lv, ix, n_cells, lmax, true, ci, s))) return rc;
+        if ((rc = prepare_index(ctx, ga, lv, ix, n_cells, lmax, true, ci, s, false))) return rc;
       }
-      GIS_HIP(hipEventRecord(ev[0], s));
+      GIS_HIP(hipEventRecord(ev[3], s));
       int64_t n_new = 0, n_b = 0;
       int new_lmax = 0;
       if ((rc = run_subdivide(ctx, ga, ci, lv, ix, n_cells, (const uint8_t*)ctx->kept.ptr,
                               o.boundary_rule, (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
                               (int32_t*)ixN.ptr, cap, &n_new, &new_lmax, &n_b, s)))
         return rc;
-      GIS_HIP(hipEventRecord(ev[1], s));
-      GIS_HIP(hipEventSynchronize(ev[1]));
-      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[0], ev[1]));
       info.rounds[r - 1].n_boundary = n_b;
-      info.rounds[r - 1].ms_subdivide = ms_sub;
       cur_is_A = !cur_is_A;
       lv = (uint8_t*)lvN.ptr;
       ix = (int32_t*)ixN.ptr;
@@ -707,7 +706,7 @@ int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, con
     // build
     const int64_t n_rows = n_cells * K;
     GIS_HIP(hipEventRecord(ev[0], s));
-    if ((rc = prepare_index(ctx, ga, lv, ix, n_cells, lmax, false, ci, s))) return rc;
+    if ((rc = prepare_index(ctx, ga, lv, ix, n_cells, lmax, false, ci, s, r == 0))) return rc;
     if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)))
       return rc;
     if (ctx->col.bytes < 16 && (rc = ensure(ctx->col, (size_t)n_rows * 4 * 8))) return rc;
@@ -728,10 +727,14 @@ int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, con
                         (uint8_t*)ctx->kept.ptr, (uint64_t*)ctx->mask.ptr, &n_kept, s)))
       return rc;
     GIS_HIP(hipEventRecord(ev[2], s));
-    GIS_HIP(hipEventSynchronize(ev[2]));
+    GIS_HIP(hipEventSynchronize(ev[2]));  // run_prune synchronised: returns at once
     float ms_b = 0.f, ms_p = 0.f;
     GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
     GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
+    if (r > 0) {
+      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[3], ev[0]));
+      info.rounds[r - 1].ms_subdivide = ms_sub;
+    }
     st.n_cells = n_cells;
     st.n_rows = n_rows;
     st.n_edges = gr.n_edges;

@@ -76,27 +76,51 @@ __device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverInd
   return r;
 }
 
-// Visits every slot of the covering index met by the finest-level box
-// [lo, hi], level by level (coarse to fine), row-major inside a level.
-// f(level, slot) returns false to stop early.
+// Visits the slots of the covering index met by the finest-level box
+// [lo, hi], level by level (coarse to fine), row-major inside a level:
+// f(level, slot, state) returns false to stop early.  Below level 0 only the
+// children of REFINED slots can hold leaves or holes, so each level is
+// restricted to the box spanned by the children of the REFINED slots seen one
+// level up, and the walk ends at the first level without a REFINED slot.  The
+// visiting order (level-major, row-major) is the canonical id order.
 template <int N, typename F>
 __device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t* lo,
                                             const int32_t* hi, F&& f) {
+  int32_t plo[N], phi[N];  // REFINED bounding box one level up
   for (int L = 0; L <= ci.lmax; ++L) {
     const int s = ci.lmax - L;
-    int32_t blo[N], bhi[N], k[N];
+    int32_t blo[N], bhi[N], k[N], nlo[N], nhi[N];
+    bool empty = false;
 #pragma unroll
     for (int d = 0; d < N; ++d) {
       blo[d] = lo[d] >> s;
       bhi[d] = hi[d] >> s;
+      if (L > 0) {
+        blo[d] = blo[d] > 2 * plo[d] ? blo[d] : 2 * plo[d];
+        bhi[d] = bhi[d] < 2 * phi[d] + 1 ? bhi[d] : 2 * phi[d] + 1;
+      }
+      empty |= blo[d] > bhi[d];
       k[d] = blo[d];
+      nlo[d] = 0x7fffffff;
+      nhi[d] = -1;
     }
+    if (empty) return;
+    bool refined = false;
     const int64_t base = ci.off[L];
     for (;;) {
       int64_t lin = 0;
 #pragma unroll
       for (int d = 0; d < N; ++d) lin = lin * ci.dims[L][d] + k[d];
-      if (!f(L, base + lin)) return;
+      const uint8_t st = ci.state[base + lin];
+      if (!f(L, base + lin, st)) return;
+      if (st == ST_REFINED) {
+        refined = true;
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+          nlo[d] = k[d] < nlo[d] ? k[d] : nlo[d];
+          nhi[d] = k[d] > nhi[d] ? k[d] : nhi[d];
+        }
+      }
       int d = N - 1;
       while (d >= 0 && k[d] == bhi[d]) {
         k[d] = blo[d];
@@ -105,6 +129,12 @@ __device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t*
       if (d < 0) break;
       ++k[d];
     }
+    if (!refined) return;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      plo[d] = nlo[d];
+      phi[d] = nhi[d];
+    }
   }
 }
 
@@ -112,8 +142,8 @@ template <int N, bool UNIFORM>
 __device__ __forceinline__ bool has_hole(const CoverIndex& ci, const Ranges<N>& r) {
   if (UNIFORM || r.iempty) return false;
   bool hole = false;
-  walk_levels<N>(ci, r.ilo, r.ihi, [&](int, int64_t slot) {
-    if (ci.state[slot] == ST_HOLE) {
+  walk_levels<N>(ci, r.ilo, r.ihi, [&](int, int64_t, uint8_t st) {
+    if (st == ST_HOLE) {
       hole = true;
       return false;
     }
@@ -132,8 +162,8 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ran
     return c;
   }
   int32_t c = 0;
-  walk_levels<N>(ci, r.lo, r.hi, [&](int, int64_t slot) {
-    c += ci.state[slot] == ST_LEAF;
+  walk_levels<N>(ci, r.lo, r.hi, [&](int, int64_t, uint8_t st) {
+    c += st == ST_LEAF;
     return true;
   });
   return c;
@@ -421,8 +451,8 @@ __global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
       }
     } else {
       int32_t w = 0;
-      walk_levels<N>(a.ci, lo, hi, [&](int, int64_t slot) {
-        if (a.ci.state[slot] == ST_LEAF && w < c) dst[w++] = a.ci.id[slot];
+      walk_levels<N>(a.ci, lo, hi, [&](int, int64_t slot, uint8_t st) {
+        if (st == ST_LEAF && w < c) dst[w++] = a.ci.id[slot];
         return true;
       });
     }

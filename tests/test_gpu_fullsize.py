@@ -1,0 +1,108 @@
+"""Full-size GPU checks on the large workloads, where the oracle cannot
+evaluate every row:
+
+* the FP32-with-FP64-recheck graph equals the FP64 graph element by element
+  over the whole graph (on the device);
+* sampled rows (edges and OUT flags) equal the oracle's rows of the same
+  covering, computed one by one;
+* the kept set is the fixed point of the analysis reached from "all cells"
+  by synchronous sweeps, re-derived here with plain tensor operations on the
+  graph (a property that holds at any size).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from conftest import gpu_available
+from paper_2202_06111_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2202_06111_amd import gis
+    return gis
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _sample_rows_against_oracle(wl, level_np, idx_np, graph, n_sample, seed, fast_out=False):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_rows = graph.n_rows
+    rows = np.unique(np.concatenate([rng.integers(0, n_rows, size=n_sample),
+                                     [0, n_rows - 1]])).astype(np.int64)
+    want = oracle.build_graph(wl.system, wl.grid, wl.samples, level_np, idx_np, wl.u,
+                              fast_out=fast_out, rows=rows)
+    rp = graph.row_ptr.cpu().numpy()
+    out = graph.out.cpu().numpy()
+    col = graph.col
+    pos = 0
+    for i, r in enumerate(rows):
+        a, b = int(rp[r]), int(rp[r + 1])
+        got = col[a:b].cpu().numpy()
+        c = int(want["cnt"][i])
+        np.testing.assert_array_equal(got, want["col"][pos:pos + c], err_msg=f"row {r}")
+        pos += c
+        assert out[r] == want["out"][i], f"row {r}"
+    return rows
+
+
+def _fixed_point(row_ptr, col, out, n_cells, K, analysis):
+    """Synchronous sweeps K_{t+1} = {c in K_t : exists u good_t(c, u)} from every cell."""
+    dev = col.device
+    n_rows = n_cells * K
+    deg = (row_ptr[1:] - row_ptr[:-1])
+    src = torch.repeat_interleave(torch.arange(n_rows, device=dev), deg)
+    kept = torch.ones(n_cells, dtype=torch.bool, device=dev)
+    out_b = out.bool()
+    for _ in range(100000):
+        tk = kept[col.long()].to(torch.int32)
+        hit = torch.zeros(n_rows, dtype=torch.int32, device=dev).index_add_(0, src, tk)
+        if analysis == "controlled":
+            good = (~out_b) & (hit == deg.to(torch.int32))
+        else:
+            good = hit > 0
+        new = kept & good.view(n_cells, K).any(dim=1)
+        if torch.equal(new, kept):
+            return kept, good.view(n_cells, K)
+        kept = new
+    raise AssertionError("no fixed point")
+
+
+def test_lorenz_128_full_graph(G, ctx):
+    wl = W.lorenz_uniform_128()
+    level, idx = G.coarse_cells(ctx, wl.grid)
+    band = G.calibrate_band(ctx, wl.system, wl.grid, wl.u, level, idx, wl.samples, safety=8.0,
+                            floor_rel=1e-5)
+    g32 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
+                        G.opts_t(samples=wl.samples, precision="fp32_recheck", band=band))
+    g64 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
+                        G.opts_t(samples=wl.samples, precision="fp64"))
+    print(f"lorenz 128^3: rows {g64.n_rows} edges {g64.n_edges} out {g64.n_out} "
+          f"recheck {g32.n_recheck} band {band}", flush=True)
+    assert g32.n_edges == g64.n_edges
+    assert torch.equal(g32.row_ptr, g64.row_ptr)
+    assert torch.equal(g32.col, g64.col)
+    assert torch.equal(g32.out, g64.out)
+    del g32
+    torch.cuda.empty_cache()
+    lv_np, ix_np = oracle.coarse_cells(wl.grid)
+    assert np.array_equal(level.cpu().numpy(), lv_np) and np.array_equal(idx.cpu().numpy(), ix_np)
+    _sample_rows_against_oracle(wl, lv_np, ix_np, g64, 3000, seed=1)
+    for analysis in ("controlled", "nonleaving"):
+        kept, mask, nk = G.prune(ctx, g64, lv_np.shape[0], wl.K, analysis)
+        want_kept, want_good = _fixed_point(g64.row_ptr, g64.col, g64.out, lv_np.shape[0], wl.K,
+                                            analysis)
+        assert torch.equal(kept.bool(), want_kept), analysis
+        bits = (want_good & want_kept[:, None]).to(torch.int64)
+        want_mask = (bits << torch.arange(wl.K, device=bits.device)[None, :]).sum(dim=1)
+        assert torch.equal(mask[:, 0], want_mask), analysis
+        print(f"  {analysis}: kept {nk}", flush=True)
