@@ -180,6 +180,21 @@ int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
 int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, const double* d_u,
                   int32_t K, int32_t rounds, const gis_opts* opts, gis_solution** out,
                   void* stream);
+/* A batch of independent solves run through the same launches (one launch
+ * per kernel for all jobs and all refinement levels): the jobs share the
+ * system kind and dimensions, K and the options; each has its own system
+ * parameters, time step, state box, coarse grid and inputs (d_u: K x m).
+ * out_sols[j] receives job j's solution, identical to what gis_solve returns
+ * for that job alone. */
+typedef struct gis_job {
+  gis_system sys;
+  gis_grid grid;
+  const double* d_u;
+} gis_job;
+int32_t gis_solve_batch(gis_ctx* ctx, int32_t n_jobs, const gis_job* jobs, int32_t K,
+                        int32_t rounds, const gis_opts* opts, gis_solution** out_sols,
+                        void* stream);
+
 int32_t gis_solution_info(const gis_solution* sol, gis_solve_info* info);
 /* Copies the final covering, kept flags and masks into caller buffers
  * (cells->cap >= n_cells; d_kept [n_cells]; d_mask [n_cells * mask_words]). */

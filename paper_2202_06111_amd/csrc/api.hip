@@ -1,12 +1,15 @@
 // C ABI of libgis (declared in include/gis.h): argument checks, device
-// workspace, and the host-side sequencing of the kernels of one iteration of
-// the GIS loop (Sec. 2 and Sec. 3.1): build the symbolic image, analyse it,
-// select boundary cells and subdivide them.
+// workspace, and the host-side sequencing of the kernels of the GIS loop
+// (Sec. 2 and Sec. 3.1): build the symbolic image, analyse it, select boundary
+// cells and subdivide them.  Every path runs a batch of jobs (independent
+// solves sharing one system kind) through the same launches; the single-job
+// entry points are batches of one.
 #include <math.h>
 #include <string.h>
 
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "gis_internal.h"
 
@@ -52,9 +55,29 @@ struct Counters {
   uint32_t err;
   uint32_t maxlevel;
   int64_t n_next;
-  unsigned long long maxerr[kMaxDim];
   int32_t qctl[4];
-  int64_t level_start[kMaxLevels + 1];   // new cells before each level (subdivision)
+};
+
+// Pinned host staging of a device array of T.
+template <typename T>
+struct Pinned {
+  T* h = nullptr;
+  size_t n = 0;
+  int32_t ensure(size_t want) {
+    if (want <= n && h) return GIS_OK;
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+    n = 0;
+    hipError_t e = hipHostMalloc((void**)&h, want * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+    n = want;
+    return GIS_OK;
+  }
+  void free() {
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+    n = 0;
+  }
 };
 
 }  // namespace gis
@@ -64,15 +87,18 @@ using namespace gis;
 struct gis_ctx {
   int device = 0;
   DevBuf counters;
-  Counters* h_counters = nullptr;   // pinned
+  Counters* h_counters = nullptr;  // pinned
+  DevBuf jobs, stats, maxerr;
+  Pinned<Job> h_jobs;
+  Pinned<JobStats> h_stats;
+  Pinned<unsigned long long> h_maxerr;
   DevBuf rng, cnt, bsum, bscan, recheck, scan_tmp;
   DevBuf idx_state, idx_id, next_state, pos;
-  DevBuf rptr, rrow, rcur, good, alive, badbits, queue;
+  DevBuf rptr, rrow, rcur, good, alive, badbits, queue, qctl;
   DevBuf bnd;
-  // cell lists and graph of the solve loop
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
-  DevBuf ubuf;
-  gis::KernelTimer timer;
+  KernelTimer timer;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 struct gis_solution {
@@ -176,7 +202,9 @@ int64_t prod_n0(const GridArgs& g) {
   return t;
 }
 
-// Layout of a covering index with levels 0..lmax.
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Layout of a covering index with levels 0..lmax (pointers left unset).
 int32_t layout_index(CoverIndex& ci, const GridArgs& g, int lmax) {
   if (lmax < 0 || lmax >= kMaxLevels) return inval("too many refinement levels");
   ci.n = g.n;
@@ -204,6 +232,12 @@ int32_t layout_index(CoverIndex& ci, const GridArgs& g, int lmax) {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+Counters* dcnt(gis_ctx* ctx) { return (Counters*)ctx->counters.ptr; }
+
+int32_t zero_counters(gis_ctx* ctx, hipStream_t s) {
+  return fill_u32((uint32_t*)ctx->counters.ptr, 0u, (int64_t)(sizeof(Counters) / 4), s);
+}
+
 int32_t sync_counters(gis_ctx* ctx, hipStream_t s) {
   GIS_HIP(hipMemcpyAsync(ctx->h_counters, ctx->counters.ptr, sizeof(Counters),
                          hipMemcpyDeviceToHost, s));
@@ -211,42 +245,154 @@ int32_t sync_counters(gis_ctx* ctx, hipStream_t s) {
   return GIS_OK;
 }
 
-Counters* dcnt(gis_ctx* ctx) { return (Counters*)ctx->counters.ptr; }
+// ---------------------------------------------------------------- batches
+struct JobSpec {
+  SysArgs sys;
+  GridArgs grid;
+  const double* u;
+  double band[kMaxDim];
+};
 
-int32_t zero_counters(gis_ctx* ctx, hipStream_t s) {
-  return fill_u32((uint32_t*)ctx->counters.ptr, 0u, (int64_t)(sizeof(Counters) / 4), s);
-}
+// Host view of a batch: the job table mirrored to the device once per phase.
+struct Batch {
+  int n_jobs = 0;
+  int n = 0, K = 0;
+  std::vector<Job> jobs;
+  std::vector<int> lmax;
+  int64_t total_cells = 0;
+  int64_t blocks[LK_KINDS] = {0, 0, 0, 0};
+  Job* d_jobs = nullptr;
+  JobStats* d_stats = nullptr;
 
-// Finds the finest level of a cell list (synchronises).
-int32_t list_lmax(gis_ctx* ctx, const uint8_t* level, int64_t n_cells, int* lmax, hipStream_t s) {
-  int32_t rc = zero_counters(ctx, s);
-  if (rc) return rc;
-  if ((rc = max_level(level, n_cells, &dcnt(ctx)->maxlevel, s))) return rc;
-  if ((rc = sync_counters(ctx, s))) return rc;
-  *lmax = (int)ctx->h_counters->maxlevel;
+  BatchArgs args(const uint8_t* level, const int32_t* idx) const {
+    BatchArgs b{};
+    b.jobs = d_jobs;
+    b.n_jobs = n_jobs;
+    b.n = n;
+    b.K = K;
+    b.level = level;
+    b.idx = idx;
+    for (int k = 0; k < LK_KINDS; ++k) b.blocks[k] = blocks[k];
+    return b;
+  }
+};
+
+int32_t batch_init(gis_ctx* ctx, Batch& B, const std::vector<JobSpec>& specs, int K) {
+  B.n_jobs = (int)specs.size();
+  B.n = specs.empty() ? 1 : specs[0].grid.n;
+  B.K = K;
+  B.jobs.assign(B.n_jobs, Job{});
+  B.lmax.assign(B.n_jobs, 0);
+  for (int j = 0; j < B.n_jobs; ++j) {
+    B.jobs[j].sys = specs[j].sys;
+    B.jobs[j].grid = specs[j].grid;
+    B.jobs[j].u = specs[j].u;
+    for (int d = 0; d < kMaxDim; ++d) B.jobs[j].band[d] = specs[j].band[d];
+  }
+  int32_t rc;
+  if ((rc = ensure(ctx->jobs, sizeof(Job) * (size_t)(B.n_jobs + 1)))) return rc;
+  if ((rc = ensure(ctx->stats, sizeof(JobStats) * (size_t)(B.n_jobs + 1)))) return rc;
+  if ((rc = ctx->h_jobs.ensure(B.n_jobs + 1))) return rc;
+  if ((rc = ctx->h_stats.ensure(B.n_jobs + 1))) return rc;
+  B.d_jobs = (Job*)ctx->jobs.ptr;
+  B.d_stats = (JobStats*)ctx->stats.ptr;
   return GIS_OK;
 }
 
-// Builds (or, for the full level-0 grid, only checks) the covering index of
-// a cell list in the context's index buffers.  With `validate` it
-// synchronises to report an invalid list; lists the library produced itself
-// are canonical by construction and skip that round trip.
-int32_t prepare_index(gis_ctx* ctx, const GridArgs& g, const uint8_t* level, const int32_t* idx,
-                      int64_t n_cells, int lmax, bool want_arrays, CoverIndex& ci, hipStream_t s,
-                      bool validate = true) {
-  int32_t rc = layout_index(ci, g, lmax);
-  if (rc) return rc;
-  ci.uniform = (!want_arrays && lmax == 0 && n_cells == prod_n0(g)) ? 1 : 0;
-  ci.state = nullptr;
-  ci.id = nullptr;
-  if (!ci.uniform) {
-    const int64_t total = ci.off[lmax + 1];
-    if ((rc = ensure(ctx->idx_state, (size_t)total))) return rc;
-    if ((rc = ensure(ctx->idx_id, (size_t)total * 4))) return rc;
-    ci.state = (uint8_t*)ctx->idx_state.ptr;
-    ci.id = (int32_t*)ctx->idx_id.ptr;
+// Stages the host job table through pinned memory into the device table.
+// The staging buffer is rewritten only after the stream has been
+// synchronised (every phase ends with a synchronisation).
+int32_t upload_jobs(gis_ctx* ctx, const Batch& B, hipStream_t s) {
+  memcpy(ctx->h_jobs.h, B.jobs.data(), sizeof(Job) * B.n_jobs);
+  GIS_HIP(hipMemcpyAsync(B.d_jobs, ctx->h_jobs.h, sizeof(Job) * B.n_jobs, hipMemcpyHostToDevice, s));
+  return GIS_OK;
+}
+
+// Lays out one phase of the batch: cell offsets, index layouts (with arrays
+// unless the job is a full level-0 grid and `want_arrays` is false), the next
+// covering's flag layout for jobs in `with_next`, launch-block offsets;
+// allocates the index and flag buffers, clears the index states and uploads
+// the job table.
+int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells, bool want_arrays,
+                     const std::vector<char>& with_next, hipStream_t s) {
+  int32_t rc;
+  int64_t cell_off = 0, slot_off = 0, next_off = 0;
+  int64_t blk[LK_KINDS] = {0, 0, 0, 0};
+  std::vector<int64_t> so(B.n_jobs);
+  for (int j = 0; j < B.n_jobs; ++j) {
+    Job& J = B.jobs[j];
+    J.n_cells = n_cells[j];
+    J.cell_off = cell_off;
+    cell_off += J.n_cells;
+    if ((rc = layout_index(J.ci, J.grid, B.lmax[j]))) return rc;
+    J.ci.uniform = (!want_arrays && B.lmax[j] == 0 && J.n_cells == prod_n0(J.grid)) ? 1 : 0;
+    const int64_t slots = (J.ci.uniform || J.n_cells == 0) ? 0 : J.ci.off[J.ci.lmax + 1];
+    so[j] = slot_off;
+    int64_t nslots = 0;
+    if (with_next[j] && J.n_cells > 0) {
+      if ((rc = layout_index(J.next, J.grid, B.lmax[j] + 1))) return rc;
+      nslots = J.next.off[J.next.lmax + 1];
+    } else {
+      J.next = CoverIndex{};
+      J.next.n = J.grid.n;
+    }
+    J.next_off = next_off;
+    for (int k = 0; k < LK_KINDS; ++k) J.blk[k] = blk[k];
+    blk[LK_ROWS] += cdiv(J.n_cells * B.K, kRowBlock);
+    blk[LK_CELLS] += cdiv(J.n_cells, 256);
+    blk[LK_SLOTS] += cdiv(slots, 256);
+    blk[LK_NEXT] += cdiv(nslots, 256);
+    slot_off += slots;
+    next_off += nslots;
   }
-  if ((rc = index_build(ci, g, level, idx, n_cells, &dcnt(ctx)->err, s))) return rc;
+  B.total_cells = cell_off;
+  for (int k = 0; k < LK_KINDS; ++k) B.blocks[k] = blk[k];
+  if (slot_off > 0) {
+    if ((rc = ensure(ctx->idx_state, (size_t)slot_off))) return rc;
+    if ((rc = ensure(ctx->idx_id, (size_t)slot_off * 4))) return rc;
+  }
+  if (next_off > 0) {
+    if ((rc = ensure(ctx->next_state, (size_t)next_off + 16))) return rc;
+    if ((rc = ensure(ctx->pos, (size_t)(next_off + 1) * 8))) return rc;
+    if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(next_off)))) return rc;
+  }
+  for (int j = 0; j < B.n_jobs; ++j) {
+    Job& J = B.jobs[j];
+    const bool arrays = !J.ci.uniform && J.n_cells > 0;
+    J.ci.state = arrays ? (uint8_t*)ctx->idx_state.ptr + so[j] : nullptr;
+    J.ci.id = arrays ? (int32_t*)ctx->idx_id.ptr + so[j] : nullptr;
+    const bool nxt = with_next[j] && J.n_cells > 0;
+    J.next.state = nxt ? (uint8_t*)ctx->next_state.ptr + J.next_off : nullptr;
+  }
+  if ((rc = upload_jobs(ctx, B, s))) return rc;
+  if (slot_off > 0 && (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, slot_off, s)))
+    return rc;
+  return GIS_OK;
+}
+
+int64_t next_total(const Batch& B) {
+  int64_t t = 0;
+  for (const Job& J : B.jobs)
+    if (J.next.state) t = J.next_off + J.next.off[J.next.lmax + 1];
+  return t;
+}
+
+int32_t zero_stats(const Batch& B, hipStream_t s) {
+  return fill_u32((uint32_t*)B.d_stats, 0u, (int64_t)(sizeof(JobStats) * B.n_jobs / 4), s);
+}
+
+int32_t sync_stats(gis_ctx* ctx, const Batch& B, hipStream_t s) {
+  GIS_HIP(hipMemcpyAsync(ctx->h_stats.h, B.d_stats, sizeof(JobStats) * B.n_jobs,
+                         hipMemcpyDeviceToHost, s));
+  return sync_counters(ctx, s);
+}
+
+// Builds every job's covering index (or checks full level-0 grids).  With
+// `validate` it synchronises and reports an invalid list.
+int32_t batch_index(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx, bool validate,
+                    hipStream_t s) {
+  int32_t rc;
+  if ((rc = batch_index_build(B.args(level, idx), &dcnt(ctx)->err, s))) return rc;
   if (!validate) return GIS_OK;
   if ((rc = sync_counters(ctx, s))) return rc;
   const uint32_t e = ctx->h_counters->err;
@@ -265,47 +411,64 @@ struct Graph {
   float ms_image, ms_recheck;   // with opts.timing
 };
 
-
-BuildArgs make_build_args(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
-                          const double* d_u, int32_t K, const CoverIndex& ci, const uint8_t* level,
-                          const int32_t* idx, int64_t n_cells, const gis_opts* o) {
+BuildArgs build_args(gis_ctx* ctx, const Batch& B, const uint8_t* level, const int32_t* idx,
+                     const gis_opts* o) {
   BuildArgs a{};
-  a.sys = make_sys(sys);
-  a.grid = make_grid(grid);
-  a.ci = ci;
-  a.u = d_u;
-  a.K = K;
+  a.jobs = B.d_jobs;
+  a.n_jobs = B.n_jobs;
+  a.K = B.K;
   a.samples = o ? o->samples : GIS_SAMPLES_LATTICE3;
   a.fast_out = o ? o->fast_out : 0;
+  a.kind = B.n_jobs ? B.jobs[0].sys.kind : 0;
+  a.n = B.n;
+  a.n_blocks = B.blocks[LK_ROWS];
   a.level = level;
   a.idx = idx;
-  a.n_rows = n_cells * K;
-  for (int d = 0; d < kMaxDim; ++d) a.band[d] = o ? o->band[d] : 0.0;
   a.rng = (int32_t*)ctx->rng.ptr;
   a.cnt = (int32_t*)ctx->cnt.ptr;
   a.bsum = (int64_t*)ctx->bsum.ptr;
   a.recheck = (int64_t*)ctx->recheck.ptr;
   a.n_recheck = &dcnt(ctx)->n_recheck;
+  a.stats = B.d_stats;
   return a;
 }
 
-// count -> (recheck) -> scan -> emit; `col` may be too small (then only the
-// counts are valid).  Synchronises.
-int32_t run_build(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, const double* d_u,
-                  int32_t K, const CoverIndex& ci, const uint8_t* level, const int32_t* idx,
-                  int64_t n_cells, const gis_opts* o, Graph& gr, hipStream_t s) {
-  const int64_t n_rows = n_cells * K;
-  const int64_t nb = (n_rows + kRowBlock - 1) / kRowBlock;
+EmitArgs emit_args(gis_ctx* ctx, const Batch& B, const Graph& gr) {
+  EmitArgs e{};
+  e.jobs = B.d_jobs;
+  e.n_jobs = B.n_jobs;
+  e.K = B.K;
+  e.n = B.n;
+  e.n_blocks = B.blocks[LK_ROWS];
+  e.total_rows = B.total_cells * B.K;
+  e.rng = (const int32_t*)ctx->rng.ptr;
+  e.cnt = (const int32_t*)ctx->cnt.ptr;
+  e.bscan = (const int64_t*)ctx->bscan.ptr;
+  e.cap_edges = gr.cap_edges;
+  e.row_ptr = gr.row_ptr;
+  e.col = gr.col;
+  return e;
+}
+
+// count -> (recheck) -> scan -> emit over the whole batch; `col` may be too
+// small (then only the counts are valid).  Synchronises; per-job figures in
+// ctx->h_stats.
+int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
+                  const gis_opts* o, Graph& gr, hipStream_t s) {
+  const int64_t n_rows = B.total_cells * B.K;
+  const int64_t nb = B.blocks[LK_ROWS];
   int32_t rc;
-  if ((rc = ensure(ctx->rng, (size_t)n_rows * 2 * sys->n * 4 + 16))) return rc;
+  if ((rc = ensure(ctx->rng, (size_t)n_rows * 2 * B.n * 4 + 16))) return rc;
   if ((rc = ensure(ctx->cnt, (size_t)n_rows * 4 + 16))) return rc;
   if ((rc = ensure(ctx->bsum, (size_t)nb * 8 + 16))) return rc;
   if ((rc = ensure(ctx->bscan, (size_t)nb * 8 + 16))) return rc;
-  if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(nb > n_cells ? nb : n_cells + 1)))) return rc;
+  if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(nb > B.total_cells ? nb : B.total_cells + 1))))
+    return rc;
   if (o->precision == GIS_PREC_FP32_RECHECK && (rc = ensure(ctx->recheck, (size_t)n_rows * 8 + 16)))
     return rc;
   if ((rc = zero_counters(ctx, s))) return rc;
-  BuildArgs a = make_build_args(ctx, sys, grid, d_u, K, ci, level, idx, n_cells, o);
+  if ((rc = zero_stats(B, s))) return rc;
+  BuildArgs a = build_args(ctx, B, level, idx, o);
   a.out = gr.out;
   KernelTimer& tm = ctx->timer;
   const bool timing = o->timing && tm.ok;
@@ -317,54 +480,36 @@ int32_t run_build(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, con
   if ((rc = scan_exclusive_i64((const int64_t*)ctx->bsum.ptr, (int64_t*)ctx->bscan.ptr, nb,
                                &dcnt(ctx)->total_edges, ctx->scan_tmp.ptr, s)))
     return rc;
-  EmitArgs e{};
-  e.ci = ci;
-  e.n = sys->n;
-  e.n_rows = n_rows;
-  e.rng = a.rng;
-  e.cnt = a.cnt;
-  e.bscan = (const int64_t*)ctx->bscan.ptr;
-  e.total = &dcnt(ctx)->total_edges;
-  e.cap_edges = gr.cap_edges;
-  e.row_ptr = gr.row_ptr;
-  e.col = gr.col;
-  if ((rc = launch_emit(e, s))) return rc;
-  if ((rc = count_out(gr.out, n_rows, &dcnt(ctx)->n_out, s))) return rc;
-  if ((rc = sync_counters(ctx, s))) return rc;
+  if ((rc = launch_emit(emit_args(ctx, B, gr), s))) return rc;
+  if (n_rows == 0 && (rc = fill_i64(gr.row_ptr, 0, 1, s))) return rc;
+  if ((rc = launch_job_edges(B.d_jobs, B.n_jobs, B.K, gr.row_ptr, B.d_stats, s))) return rc;
+  if ((rc = batch_count_out(B.args(level, idx), gr.out, B.d_stats, s))) return rc;
+  if ((rc = sync_stats(ctx, B, s))) return rc;
   gr.n_edges = ctx->h_counters->total_edges;
-  gr.n_out = (int64_t)ctx->h_counters->n_out;
   gr.n_recheck = ctx->h_counters->n_recheck;
+  gr.n_out = 0;
+  for (int j = 0; j < B.n_jobs; ++j) gr.n_out += (int64_t)ctx->h_stats.h[j].n_out;
   gr.ms_image = gr.ms_recheck = 0.f;
   if (timing) {
     GIS_HIP(hipEventElapsedTime(&gr.ms_image, tm.ev[0], tm.ev[1]));
     GIS_HIP(hipEventElapsedTime(&gr.ms_recheck, tm.ev[1], tm.ev[2]));
   }
-  if (n_rows == 0) {  // row_ptr[0] = 0 for an empty graph
-    if ((rc = fill_i64(gr.row_ptr, 0, 1, s))) return rc;
-  }
   return GIS_OK;
 }
 
-// Re-runs only the emitter after col was grown.
-int32_t rerun_emit(gis_ctx* ctx, int n, const CoverIndex& ci, int64_t n_rows, Graph& gr,
-                   hipStream_t s) {
-  EmitArgs e{};
-  e.ci = ci;
-  e.n = n;
-  e.n_rows = n_rows;
-  e.rng = (const int32_t*)ctx->rng.ptr;
-  e.cnt = (const int32_t*)ctx->cnt.ptr;
-  e.bscan = (const int64_t*)ctx->bscan.ptr;
-  e.total = &dcnt(ctx)->total_edges;
-  e.cap_edges = gr.cap_edges;
-  e.row_ptr = gr.row_ptr;
-  e.col = gr.col;
-  return launch_emit(e, s);
+// Re-runs only the emitter and the per-job edge totals after col grew;
+// synchronises.
+int32_t rerun_emit(gis_ctx* ctx, Batch& B, Graph& gr, hipStream_t s) {
+  int32_t rc;
+  if ((rc = launch_emit(emit_args(ctx, B, gr), s))) return rc;
+  if ((rc = launch_job_edges(B.d_jobs, B.n_jobs, B.K, gr.row_ptr, B.d_stats, s))) return rc;
+  return sync_stats(ctx, B, s);
 }
 
 int32_t run_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                   int64_t n_cells, int32_t K, int64_t n_edges, int32_t analysis, uint8_t* kept,
-                  uint64_t* mask, int64_t* n_kept, hipStream_t s) {
+                  uint64_t* mask, int64_t* n_kept, hipStream_t s, const Batch* B = nullptr,
+                  const uint8_t* level = nullptr, const int32_t* idx = nullptr) {
   const int64_t n_rows = n_cells * K;
   const int32_t W = (K + 63) / 64;
   int32_t rc;
@@ -373,6 +518,7 @@ int32_t run_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, cons
   if ((rc = ensure(ctx->rcur, (size_t)n_cells * 4 + 16))) return rc;
   if ((rc = ensure(ctx->good, (size_t)n_cells * 4 + 16))) return rc;
   if ((rc = ensure(ctx->queue, (size_t)n_cells * 4 + 16))) return rc;
+  if ((rc = ensure(ctx->qctl, 128 * 4))) return rc;
   if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(n_cells + 1)))) return rc;
   if (analysis == GIS_ANALYSIS_NONLEAVING) {
     if ((rc = ensure(ctx->alive, (size_t)n_rows * 4 + 16))) return rc;
@@ -388,12 +534,19 @@ int32_t run_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, cons
   w.alive = (int32_t*)ctx->alive.ptr;
   w.badbits = (uint32_t*)ctx->badbits.ptr;
   w.queue = (int32_t*)ctx->queue.ptr;
-  w.qctl = dcnt(ctx)->qctl;
+  w.qctl = (int32_t*)ctx->qctl.ptr;
+  w.err_out = &dcnt(ctx)->qctl[3];
   w.scan_tmp = ctx->scan_tmp.ptr;
   if ((rc = launch_prune(row_ptr, col, out, n_cells, K, n_edges, analysis, w, kept, mask, W,
                          dcnt(ctx)->n_kept, s)))
     return rc;
-  if ((rc = sync_counters(ctx, s))) return rc;
+  if (B) {
+    if ((rc = zero_stats(*B, s))) return rc;
+    if ((rc = batch_count_kept(B->args(level, idx), kept, B->d_stats, s))) return rc;
+    if ((rc = sync_stats(ctx, *B, s))) return rc;
+  } else if ((rc = sync_counters(ctx, s))) {
+    return rc;
+  }
   if (ctx->h_counters->qctl[3]) {
     set_error("prune work queue did not drain within its time limit");
     return GIS_E_INTERNAL;
@@ -402,47 +555,331 @@ int32_t run_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, cons
   return GIS_OK;
 }
 
-// Boundary selection + next covering.  `ci` is the index of the current list
-// with its arrays built.  Writes the new list to (lv_out, ix_out) if cap
-// allows.  Synchronises.
-int32_t run_subdivide(gis_ctx* ctx, const GridArgs& g, CoverIndex& ci, const uint8_t* level,
-                      const int32_t* idx, int64_t n_cells, const uint8_t* kept, int32_t rule,
-                      uint8_t* boundary, uint8_t* lv_out, int32_t* ix_out, int64_t cap,
-                      int64_t* n_new, int* new_lmax, int64_t* n_boundary, hipStream_t s) {
+// Boundary selection + next covering of a laid-out batch (index arrays built,
+// next layouts set).  Writes the new global list to (lv_out, ix_out) if cap
+// allows.  Synchronises; per-job starts, levels and boundary counts in
+// ctx->h_stats.
+int32_t run_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
+                      const uint8_t* kept, int32_t rule, uint8_t* boundary, uint8_t* lv_out,
+                      int32_t* ix_out, int64_t cap, int64_t* n_new, hipStream_t s) {
   int32_t rc;
-  if ((rc = index_mark_dropped(ci, level, idx, n_cells, kept, s))) return rc;
-  if ((rc = launch_boundary(ci, g, level, idx, n_cells, kept, rule, boundary, s))) return rc;
-  CoverIndex next{};
-  if ((rc = layout_index(next, g, ci.lmax + 1))) return rc;
-  const int64_t total = next.off[next.lmax + 1];
-  if ((rc = ensure(ctx->next_state, (size_t)total + 16))) return rc;
-  if ((rc = ensure(ctx->pos, (size_t)(total + 1) * 8))) return rc;
-  if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(total)))) return rc;
-  next.state = (uint8_t*)ctx->next_state.ptr;
-  if ((rc = launch_next_flags(next, level, idx, n_cells, kept, boundary, s))) return rc;
-  int64_t* pos = (int64_t*)ctx->pos.ptr;
-  if ((rc = zero_counters(ctx, s))) return rc;
-  if ((rc = scan_exclusive_u8(next.state, pos, total, &dcnt(ctx)->n_next, ctx->scan_tmp.ptr, s)))
-    return rc;
-  if ((rc = launch_compact(next, pos, cap, lv_out, ix_out, s))) return rc;
-  if ((rc = count_out(boundary, n_cells, &dcnt(ctx)->n_out, s))) return rc;
-  // new cells before each level start -> the finest level present
-  if ((rc = launch_level_starts(next, pos, dcnt(ctx)->level_start, s))) return rc;
-  if ((rc = sync_counters(ctx, s))) return rc;
-  *n_new = ctx->h_counters->n_next;
-  *n_boundary = (int64_t)ctx->h_counters->n_out;
-  const int64_t* h_pos = ctx->h_counters->level_start;
-  int lm = 0;
-  for (int L = 0; L <= next.lmax; ++L) {
-    const int64_t end = L < next.lmax ? h_pos[L + 1] : *n_new;
-    if (end > h_pos[L]) lm = L;
+  const BatchArgs ba = B.args(level, idx);
+  if ((rc = zero_counters(ctx, s)) || (rc = zero_stats(B, s))) return rc;
+  if ((rc = batch_mark_dropped(ba, kept, s))) return rc;
+  if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
+  const int64_t total = next_total(B);
+  if (total > 0) {
+    if ((rc = fill_u8((uint8_t*)ctx->next_state.ptr, 0, total, s))) return rc;
+    if ((rc = batch_next_flags(ba, kept, boundary, s))) return rc;
+    if ((rc = scan_exclusive_u8((const uint8_t*)ctx->next_state.ptr, (int64_t*)ctx->pos.ptr, total,
+                                &dcnt(ctx)->n_next, ctx->scan_tmp.ptr, s)))
+      return rc;
+    if ((rc = batch_compact(ba, (const int64_t*)ctx->pos.ptr, cap, lv_out, ix_out, B.d_stats, s)))
+      return rc;
   }
-  *new_lmax = lm;
+  if ((rc = sync_stats(ctx, B, s))) return rc;
+  *n_new = total > 0 ? ctx->h_counters->n_next : 0;
   if (*n_new > cap) {
     set_error("output cell list capacity too small");
     return GIS_E_CAPACITY;
   }
   return GIS_OK;
+}
+
+// New per-job cell counts and finest levels from the subdivision's stats.
+void next_sizes(gis_ctx* ctx, Batch& B, int64_t n_new, std::vector<int64_t>& cells) {
+  for (int j = 0; j < B.n_jobs; ++j) {
+    const JobStats& st = ctx->h_stats.h[j];
+    if (!B.jobs[j].next.state) {
+      cells[j] = 0;
+      continue;
+    }
+    int64_t end = n_new;  // the next job with flags starts where this one ends
+    for (int k = j + 1; k < B.n_jobs; ++k)
+      if (B.jobs[k].next.state) {
+        end = ctx->h_stats.h[k].next_start;
+        break;
+      }
+    cells[j] = end - st.next_start;
+    int lm = 0;
+    const CoverIndex& nx = B.jobs[j].next;
+    for (int L = 0; L <= nx.lmax; ++L) {
+      const int64_t stop = L < nx.lmax ? st.level_start[L + 1] : end;
+      if (stop > st.level_start[L]) lm = L;
+    }
+    B.lmax[j] = lm;
+  }
+}
+
+// Copies job j's covering, kept flags, masks and index into a new solution.
+int32_t make_solution(gis_ctx* ctx, const Batch& B, int j, const uint8_t* level,
+                      const int32_t* idx, const uint8_t* kept, const uint64_t* mask,
+                      const gis_solve_info& info, gis_solution** out, hipStream_t s) {
+  const Job& J = B.jobs[j];
+  const int n = B.n;
+  const int32_t W = (B.K + 63) / 64;
+  gis_solution* sol = new gis_solution();
+  sol->device = ctx->device;
+  sol->grid = J.grid;
+  sol->K = B.K;
+  sol->W = W;
+  sol->n_cells = J.n_cells;
+  sol->info = info;
+  sol->info.n_cells = J.n_cells;
+  const int64_t nc = J.n_cells, c0 = J.cell_off;
+  int32_t rc;
+  auto fail = [&](int32_t code) {
+    gis_solution_free(sol);
+    return code;
+  };
+  if ((rc = ensure(sol->level, (size_t)nc + 16)) || (rc = ensure(sol->idx, (size_t)nc * n * 4 + 16)) ||
+      (rc = ensure(sol->kept, (size_t)nc + 16)) || (rc = ensure(sol->mask, (size_t)nc * W * 8 + 16)))
+    return fail(rc);
+  sol->ci = J.ci;
+  sol->ci.state = nullptr;
+  sol->ci.id = nullptr;
+  if (nc > 0) {
+    if (hipMemcpyAsync(sol->level.ptr, level + c0, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sol->idx.ptr, idx + c0 * n, nc * n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sol->kept.ptr, kept + c0, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sol->mask.ptr, mask + c0 * W, nc * W * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      set_error("copy of the solution failed");
+      return fail(GIS_E_HIP);
+    }
+    if (!J.ci.uniform) {
+      const int64_t total = J.ci.off[J.ci.lmax + 1];
+      if ((rc = ensure(sol->state, (size_t)total + 16)) || (rc = ensure(sol->id, (size_t)total * 4 + 16)))
+        return fail(rc);
+      if (hipMemcpyAsync(sol->state.ptr, J.ci.state, total, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(sol->id.ptr, J.ci.id, total * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("copy of the covering index failed");
+        return fail(GIS_E_HIP);
+      }
+      sol->ci.state = (uint8_t*)sol->state.ptr;
+      sol->ci.id = (int32_t*)sol->id.ptr;
+    }
+  }
+  *out = sol;
+  return GIS_OK;
+}
+
+// The iteration loop for a batch of jobs (Sec. 2 with Sec. 3.1's boundary-only
+// subdivision): build -> analyse, then `rounds` times subdivide -> build ->
+// analyse.  A job that keeps nothing stops; out[j] receives job j's solution.
+int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, int32_t rounds,
+                    const gis_opts* opts, gis_solution** out, hipStream_t s) {
+  const int nj = (int)specs.size();
+  gis_opts o = *opts;
+  const int n = specs[0].grid.n;
+  const int32_t W = (K + 63) / 64;
+  int32_t rc;
+  for (int j = 0; j < nj; ++j) out[j] = nullptr;
+  auto fail_all = [&](int32_t code) {
+    for (int j = 0; j < nj; ++j) {
+      gis_solution_free(out[j]);
+      out[j] = nullptr;
+    }
+    return code;
+  };
+
+  Batch B;
+  if ((rc = batch_init(ctx, B, specs, K))) return rc;
+  if (o.precision == GIS_PREC_FP32_RECHECK)
+    for (int j = 0; j < nj; ++j)
+      for (int d = 0; d < n; ++d) B.jobs[j].band[d] = o.band[d];
+  std::vector<int64_t> cells(nj);
+  int64_t total = 0;
+  for (int j = 0; j < nj; ++j) {
+    cells[j] = prod_n0(specs[j].grid);
+    total += cells[j];
+  }
+  if (total * (int64_t)K >= ((int64_t)1 << 31)) {
+    set_error("more than 2^31 - 1 rows");
+    return GIS_E_UNSUPPORTED;
+  }
+  std::vector<char> active(nj, 1);
+  std::vector<char> nxt(nj, rounds > 0 ? 1 : 0);
+  // round-0 covering: each job's full coarse grid
+  if ((rc = ensure(ctx->lvA, (size_t)total + 16)) || (rc = ensure(ctx->ixA, (size_t)total * n * 4 + 16)))
+    return rc;
+  if ((rc = batch_layout(ctx, B, cells, rounds > 0, nxt, s))) return rc;
+  if ((rc = batch_coarse(B.args(nullptr, nullptr), (uint8_t*)ctx->lvA.ptr, (int32_t*)ctx->ixA.ptr, s)))
+    return rc;
+
+  // FP32 recheck band: calibrate each job on its coarse covering unless given
+  if (o.precision == GIS_PREC_FP32_RECHECK) {
+    bool need = false;
+    for (int d = 0; d < n; ++d) need |= !(o.band[d] > 0.0);
+    if (need) {
+      if ((rc = ensure(ctx->maxerr, sizeof(unsigned long long) * kMaxDim * (size_t)(nj + 1)))) return rc;
+      if ((rc = ctx->h_maxerr.ensure((size_t)kMaxDim * (nj + 1)))) return rc;
+      if ((rc = fill_u32((uint32_t*)ctx->maxerr.ptr, 0u, (int64_t)2 * kMaxDim * nj, s))) return rc;
+      BuildArgs a = build_args(ctx, B, (const uint8_t*)ctx->lvA.ptr, (const int32_t*)ctx->ixA.ptr, &o);
+      if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, s))) return rc;
+      GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim * nj,
+                             hipMemcpyDeviceToHost, s));
+      GIS_HIP(hipStreamSynchronize(s));
+      // calibrated bands: the stream is idle, so the staging buffer is free
+      const double floor_rel = 1e-5 * ldexp(1.0, -rounds);
+      for (int j = 0; j < nj; ++j)
+        for (int d = 0; d < n; ++d) {
+          if (o.band[d] > 0.0) continue;
+          double e;
+          memcpy(&e, &ctx->h_maxerr.h[j * kMaxDim + d], 8);
+          const double fl = floor_rel * B.jobs[j].grid.w0[d];
+          B.jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
+        }
+      if ((rc = upload_jobs(ctx, B, s))) return rc;
+    }
+  }
+
+  std::vector<gis_solve_info> info(nj);
+  for (int j = 0; j < nj; ++j) {
+    info[j] = gis_solve_info{};
+    info[j].n = n;
+    info[j].K = K;
+    info[j].mask_words = W;
+    for (int d = 0; d < n; ++d)
+      info[j].band[d] = o.precision == GIS_PREC_FP32_RECHECK ? B.jobs[j].band[d] : 0.0;
+  }
+  hipEvent_t* ev = ctx->ev;
+  bool cur_is_A = true;
+  for (int r = 0; r <= rounds; ++r) {
+    const uint8_t* lv = (const uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
+    const int32_t* ix = (const int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
+    if (r > 0) {
+      for (int j = 0; j < nj; ++j) nxt[j] = (r < rounds && active[j]) ? 1 : 0;
+      if ((rc = batch_layout(ctx, B, cells, r < rounds, nxt, s))) return fail_all(rc);
+    }
+    const int64_t n_cells = B.total_cells;
+    const int64_t n_rows = n_cells * K;
+    // build
+    GIS_HIP(hipEventRecord(ev[0], s));
+    if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
+    if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)))
+      return fail_all(rc);
+    if (ctx->col.bytes < 16 && (rc = ensure(ctx->col, (size_t)n_rows * 4 * 8 + 64))) return fail_all(rc);
+    Graph gr{(int64_t*)ctx->row_ptr.ptr, (int32_t*)ctx->col.ptr, (uint8_t*)ctx->out.ptr,
+             (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f};
+    if ((rc = run_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
+    if (gr.n_edges > gr.cap_edges) {
+      if ((rc = ensure(ctx->col, (size_t)gr.n_edges * 4))) return fail_all(rc);
+      gr.col = (int32_t*)ctx->col.ptr;
+      gr.cap_edges = (int64_t)(ctx->col.bytes / 4);
+      if ((rc = rerun_emit(ctx, B, gr, s))) return fail_all(rc);
+    }
+    std::vector<JobStats> bstats(ctx->h_stats.h, ctx->h_stats.h + nj);
+    GIS_HIP(hipEventRecord(ev[1], s));
+    // analysis of the batch's union graph
+    if ((rc = ensure(ctx->kept, (size_t)n_cells + 16)) || (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)))
+      return fail_all(rc);
+    int64_t kept_total = 0;
+    if ((rc = run_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.n_edges, o.analysis,
+                        (uint8_t*)ctx->kept.ptr, (uint64_t*)ctx->mask.ptr, &kept_total, s, &B, lv, ix)))
+      return fail_all(rc);
+    GIS_HIP(hipEventRecord(ev[2], s));
+    GIS_HIP(hipEventSynchronize(ev[2]));
+    float ms_b = 0.f, ms_p = 0.f, ms_sub = 0.f;
+    GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
+    GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
+    for (int j = 0; j < nj; ++j) {
+      if (!active[j]) continue;
+      gis_round_stats& st = info[j].rounds[r];
+      st.n_cells = B.jobs[j].n_cells;
+      st.n_rows = B.jobs[j].n_cells * K;
+      st.n_edges = bstats[j].n_edges;
+      st.n_out = (int64_t)bstats[j].n_out;
+      st.n_recheck = (int64_t)bstats[j].n_recheck;
+      st.n_kept = (int64_t)ctx->h_stats.h[j].n_kept;
+      st.max_level = B.lmax[j];
+      st.ms_build = ms_b;
+      st.ms_prune = ms_p;
+      st.ms_image = gr.ms_image;
+      st.ms_recheck = gr.ms_recheck;
+      info[j].n_rounds = r + 1;
+      info[j].n_kept = st.n_kept;
+    }
+    // jobs that keep nothing, and every job after the last round, are done
+    for (int j = 0; j < nj; ++j) {
+      if (!active[j]) continue;
+      if (r == rounds || info[j].rounds[r].n_kept == 0) {
+        if ((rc = make_solution(ctx, B, j, lv, ix, (const uint8_t*)ctx->kept.ptr,
+                                (const uint64_t*)ctx->mask.ptr, info[j], &out[j], s)))
+          return fail_all(rc);
+        active[j] = 0;
+      }
+    }
+    bool any = false;
+    for (int j = 0; j < nj; ++j) any |= active[j] != 0;
+    if (!any) break;
+    // subdivide the kept boundary cells of the jobs still active; finished
+    // jobs keep their index but set no flags
+    bool dropped = false;
+    for (int j = 0; j < nj; ++j)
+      if (!active[j] && B.jobs[j].next.state) {
+        B.jobs[j].next.state = nullptr;
+        dropped = true;
+      }
+    if (dropped) {
+      int64_t off = 0, blk = 0;
+      for (int j = 0; j < nj; ++j) {
+        Job& J = B.jobs[j];
+        J.next_off = off;
+        J.blk[LK_NEXT] = blk;
+        if (!J.next.state) continue;
+        J.next.state = (uint8_t*)ctx->next_state.ptr + off;
+        const int64_t ns = J.next.off[J.next.lmax + 1];
+        off += ns;
+        blk += cdiv(ns, 256);
+      }
+      B.blocks[LK_NEXT] = blk;
+      if ((rc = upload_jobs(ctx, B, s))) return fail_all(rc);  // the stream is idle here
+    }
+    int64_t cap = 0;
+    for (int j = 0; j < nj; ++j)
+      if (active[j]) cap += info[j].rounds[r].n_kept << n;
+    DevBuf& lvN = cur_is_A ? ctx->lvB : ctx->lvA;
+    DevBuf& ixN = cur_is_A ? ctx->ixB : ctx->ixA;
+    if ((rc = ensure(lvN, (size_t)cap + 16)) || (rc = ensure(ixN, (size_t)cap * n * 4 + 16))) return fail_all(rc);
+    if ((rc = ensure(ctx->bnd, (size_t)n_cells + 16))) return fail_all(rc);
+    GIS_HIP(hipEventRecord(ev[3], s));
+    int64_t n_new = 0;
+    if ((rc = run_subdivide(ctx, B, lv, ix, (const uint8_t*)ctx->kept.ptr, o.boundary_rule,
+                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr, (int32_t*)ixN.ptr, cap,
+                            &n_new, s)))
+      return fail_all(rc);
+    GIS_HIP(hipEventRecord(ev[0], s));
+    GIS_HIP(hipEventSynchronize(ev[0]));
+    GIS_HIP(hipEventElapsedTime(&ms_sub, ev[3], ev[0]));
+    for (int j = 0; j < nj; ++j) {
+      if (!active[j]) continue;
+      info[j].rounds[r].n_boundary = (int64_t)ctx->h_stats.h[j].n_boundary;
+      info[j].rounds[r].ms_subdivide = ms_sub;
+    }
+    next_sizes(ctx, B, n_new, cells);
+    cur_is_A = !cur_is_A;
+    int64_t tot = 0;
+    for (int j = 0; j < nj; ++j) tot += cells[j];
+    if (tot * (int64_t)K >= ((int64_t)1 << 31)) {
+      set_error("more than 2^31 - 1 rows");
+      return fail_all(GIS_E_UNSUPPORTED);
+    }
+  }
+  for (int j = 0; j < nj; ++j)
+    if (!out[j]) {
+      set_error("internal: a job ended without a solution");
+      return fail_all(GIS_E_INTERNAL);
+    }
+  GIS_HIP(hipStreamSynchronize(s));
+  return GIS_OK;
+}
+
+JobSpec job_spec(const gis_system* sys, const gis_grid* grid, const double* d_u) {
+  JobSpec js{};
+  js.sys = make_sys(sys);
+  js.grid = make_grid(grid);
+  js.u = d_u;
+  return js;
 }
 
 }  // namespace
@@ -452,7 +889,7 @@ int32_t run_subdivide(gis_ctx* ctx, const GridArgs& g, CoverIndex& ci, const uin
 extern "C" {
 
 const char* gis_last_error(void) { return g_err.c_str(); }
-const char* gis_version(void) { return "gis-mi355x 0.1 (gfx950)"; }
+const char* gis_version(void) { return "gis-mi355x 0.2 (gfx950)"; }
 
 int32_t gis_ctx_create(int32_t device, gis_ctx** out) {
   if (!out) return inval("out is NULL");
@@ -477,6 +914,12 @@ int32_t gis_ctx_create(int32_t device, gis_ctx** out) {
   c->timer.ok = true;
   for (int i = 0; i < 3; ++i)
     if (hipEventCreate(&c->timer.ev[i]) != hipSuccess) c->timer.ok = false;
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+      gis_ctx_destroy(c);
+      set_error("hipEventCreate failed");
+      return GIS_E_HIP;
+    }
   *out = c;
   return GIS_OK;
 }
@@ -485,15 +928,20 @@ void gis_ctx_destroy(gis_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->counters, &c->rng, &c->cnt, &c->bsum, &c->bscan, &c->recheck,
-                    &c->scan_tmp, &c->idx_state, &c->idx_id, &c->next_state, &c->pos, &c->rptr,
-                    &c->rrow, &c->rcur, &c->good, &c->alive, &c->badbits, &c->queue, &c->bnd,
-                    &c->lvA, &c->ixA, &c->lvB, &c->ixB, &c->row_ptr, &c->col, &c->out,
-                    &c->kept, &c->mask, &c->ubuf};
+  DevBuf* bufs[] = {&c->counters, &c->jobs, &c->stats, &c->maxerr, &c->rng, &c->cnt, &c->bsum,
+                    &c->bscan, &c->recheck, &c->scan_tmp, &c->idx_state, &c->idx_id,
+                    &c->next_state, &c->pos, &c->rptr, &c->rrow, &c->rcur, &c->good, &c->alive,
+                    &c->badbits, &c->queue, &c->qctl, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
+                    &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
   for (DevBuf* b : bufs) release(*b);
   if (c->h_counters) (void)hipHostFree(c->h_counters);
+  c->h_jobs.free();
+  c->h_stats.free();
+  c->h_maxerr.free();
   for (int i = 0; i < 3; ++i)
     if (c->timer.ev[i]) (void)hipEventDestroy(c->timer.ev[i]);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;
 }
 
@@ -519,16 +967,18 @@ int32_t gis_build_graph(gis_ctx* ctx, const gis_system* sys, const gis_grid* gri
     return inval("graph buffers missing");
   DeviceGuard g(ctx->device);
   hipStream_t s = as_stream(stream);
-  const GridArgs ga = make_grid(grid);
-  int lmax = 0;
-  if ((rc = list_lmax(ctx, cells->level, cells->n_cells, &lmax, s))) return rc;
-  CoverIndex ci{};
-  if ((rc = prepare_index(ctx, ga, cells->level, cells->idx, cells->n_cells, lmax, false, ci, s)))
-    return rc;
+  JobSpec js = job_spec(sys, grid, d_u);
+  for (int d = 0; d < kMaxDim; ++d) js.band[d] = opts->band[d];
+  Batch B;
+  if ((rc = batch_init(ctx, B, {js}, K))) return rc;
+  if ((rc = zero_counters(ctx, s))) return rc;
+  if ((rc = max_level(cells->level, cells->n_cells, &dcnt(ctx)->maxlevel, s))) return rc;
+  if ((rc = sync_counters(ctx, s))) return rc;
+  B.lmax[0] = (int)ctx->h_counters->maxlevel;
+  if ((rc = batch_layout(ctx, B, {cells->n_cells}, false, {0}, s))) return rc;
+  if ((rc = batch_index(ctx, B, cells->level, cells->idx, true, s))) return rc;
   Graph gr{graph->row_ptr, graph->col, graph->out, graph->cap_edges, 0, 0, 0, 0.f, 0.f};
-  if ((rc = run_build(ctx, sys, grid, d_u, K, ci, cells->level, cells->idx, cells->n_cells, opts,
-                      gr, s)))
-    return rc;
+  if ((rc = run_build(ctx, B, cells->level, cells->idx, opts, gr, s))) return rc;
   graph->n_rows = n_rows;
   graph->n_edges = gr.n_edges;
   graph->n_out = gr.n_out;
@@ -591,20 +1041,25 @@ int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
     out->n_cells = 0;
     return GIS_OK;
   }
-  const GridArgs ga = make_grid(grid);
-  int lmax = 0;
-  if ((rc = list_lmax(ctx, in->level, in->n_cells, &lmax, s))) return rc;
-  CoverIndex ci{};
-  if ((rc = prepare_index(ctx, ga, in->level, in->idx, in->n_cells, lmax, true, ci, s))) return rc;
+  JobSpec js{};
+  js.grid = make_grid(grid);
+  js.sys.n = grid->n;
+  Batch B;
+  if ((rc = batch_init(ctx, B, {js}, 1))) return rc;
+  if ((rc = zero_counters(ctx, s))) return rc;
+  if ((rc = max_level(in->level, in->n_cells, &dcnt(ctx)->maxlevel, s))) return rc;
+  if ((rc = sync_counters(ctx, s))) return rc;
+  B.lmax[0] = (int)ctx->h_counters->maxlevel;
+  if ((rc = batch_layout(ctx, B, {in->n_cells}, true, {1}, s))) return rc;
+  if ((rc = batch_index(ctx, B, in->level, in->idx, true, s))) return rc;
   uint8_t* bnd = d_boundary;
   if (!bnd) {
     if ((rc = ensure(ctx->bnd, (size_t)in->n_cells))) return rc;
     bnd = (uint8_t*)ctx->bnd.ptr;
   }
-  int64_t n_new = 0, n_b = 0;
-  int new_lmax = 0;
-  rc = run_subdivide(ctx, ga, ci, in->level, in->idx, in->n_cells, d_kept, boundary_rule, bnd,
-                     out->level, out->idx, out->cap, &n_new, &new_lmax, &n_b, s);
+  int64_t n_new = 0;
+  rc = run_subdivide(ctx, B, in->level, in->idx, d_kept, boundary_rule, bnd, out->level, out->idx,
+                     out->cap, &n_new, s);
   out->n_cells = n_new;
   return rc;
 }
@@ -620,187 +1075,29 @@ int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, con
   if (!d_u || K < 1) return inval("inputs and K >= 1 are required");
   if (rounds < 0 || rounds >= GIS_MAX_ROUNDS) return inval("rounds must be 0..31");
   DeviceGuard dg(ctx->device);
-  hipStream_t s = as_stream(stream);
-  const GridArgs ga = make_grid(grid);
-  const int n = sys->n;
-  const int32_t W = (K + 63) / 64;
-  gis_opts o = *opts;
-  gis_solve_info info{};
-  info.n = n;
-  info.K = K;
-  info.mask_words = W;
+  return solve_batch(ctx, {job_spec(sys, grid, d_u)}, K, rounds, opts, out_sol, as_stream(stream));
+}
 
-  hipEvent_t ev[4];
-  for (int i = 0; i < 4; ++i) GIS_HIP(hipEventCreate(&ev[i]));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() {
-      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
-    }
-  } evg{ev};
-
-  // round-0 covering: the full coarse grid
-  int64_t n_cells = prod_n0(ga);
-  if (n_cells * (int64_t)K >= ((int64_t)1 << 31)) {
-    set_error("more than 2^31 - 1 rows");
-    return GIS_E_UNSUPPORTED;
+int32_t gis_solve_batch(gis_ctx* ctx, int32_t n_jobs, const gis_job* jobs, int32_t K,
+                        int32_t rounds, const gis_opts* opts, gis_solution** out_sols,
+                        void* stream) {
+  if (!ctx || !jobs || !out_sols || n_jobs < 1)
+    return inval("ctx, jobs (n_jobs >= 1) and out are required");
+  int32_t rc;
+  if ((rc = check_opts(opts))) return rc;
+  if (K < 1) return inval("K >= 1 is required");
+  if (rounds < 0 || rounds >= GIS_MAX_ROUNDS) return inval("rounds must be 0..31");
+  std::vector<JobSpec> specs(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) {
+    const gis_job& jb = jobs[j];
+    if ((rc = check_system(&jb.sys)) || (rc = check_grid(&jb.grid, jb.sys.n))) return rc;
+    if (!jb.d_u) return inval("every job needs its inputs");
+    if (jb.sys.kind != jobs[0].sys.kind || jb.sys.n != jobs[0].sys.n || jb.sys.m != jobs[0].sys.m)
+      return inval("jobs of one batch share the system kind and dimensions");
+    specs[j] = job_spec(&jb.sys, &jb.grid, jb.d_u);
   }
-  if ((rc = ensure(ctx->lvA, (size_t)n_cells + 16)) || (rc = ensure(ctx->ixA, (size_t)n_cells * n * 4 + 16)))
-    return rc;
-  if ((rc = launch_coarse(ga, (uint8_t*)ctx->lvA.ptr, (int32_t*)ctx->ixA.ptr, s))) return rc;
-  int lmax = 0;
-
-  // FP32 recheck band: calibrate on the coarse covering when not given
-  if (o.precision == GIS_PREC_FP32_RECHECK) {
-    bool need = false;
-    for (int d = 0; d < n; ++d) need |= !(o.band[d] > 0.0);
-    if (need) {
-      gis_cells cc{n_cells, n_cells, (uint8_t*)ctx->lvA.ptr, (int32_t*)ctx->ixA.ptr};
-      double band[kMaxDim] = {0, 0, 0, 0};
-      const double floor_rel = 1e-5 * ldexp(1.0, -rounds);
-      if ((rc = gis_calibrate_band(ctx, sys, grid, d_u, K, &cc, o.samples, 8.0, floor_rel, band, stream)))
-        return rc;
-      for (int d = 0; d < n; ++d)
-        if (!(o.band[d] > 0.0)) o.band[d] = band[d];
-    }
-  }
-  for (int d = 0; d < n; ++d) info.band[d] = o.precision == GIS_PREC_FP32_RECHECK ? o.band[d] : 0.0;
-
-  bool cur_is_A = true;
-  int64_t n_kept = 0;
-  CoverIndex ci{};
-  for (int r = 0; r <= rounds; ++r) {
-    uint8_t* lv = (uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
-    int32_t* ix = (int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
-    gis_round_stats& st = info.rounds[r];
-    float ms_sub = 0.f;
-    if (r > 0) {
-      // subdivide the previous round's kept boundary cells
-      const int64_t cap = n_kept << n;
-      DevBuf& lvN = cur_is_A ? ctx->lvB : ctx->lvA;
-      DevBuf& ixN = cur_is_A ? ctx->ixB : ctx->ixA;
-      if ((rc = ensure(lvN, (size_t)cap + 16)) || (rc = ensure(ixN, (size_t)cap * n * 4 + 16))) return rc;
-      if ((rc = ensure(ctx->bnd, (size_t)n_cells + 16))) return rc;
-      if (ci.uniform) {  // the boundary walk needs the index arrays
-        if ((rc = prepare_index(ctx, ga, lv, ix, n_cells, lmax, true, ci, s, false))) return rc;
-      }
-      GIS_HIP(hipEventRecord(ev[3], s));
-      int64_t n_new = 0, n_b = 0;
-      int new_lmax = 0;
-      if ((rc = run_subdivide(ctx, ga, ci, lv, ix, n_cells, (const uint8_t*)ctx->kept.ptr,
-                              o.boundary_rule, (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
-                              (int32_t*)ixN.ptr, cap, &n_new, &new_lmax, &n_b, s)))
-        return rc;
-      info.rounds[r - 1].n_boundary = n_b;
-      cur_is_A = !cur_is_A;
-      lv = (uint8_t*)lvN.ptr;
-      ix = (int32_t*)ixN.ptr;
-      n_cells = n_new;
-      lmax = new_lmax;
-      if (n_cells == 0) break;
-      if (n_cells * (int64_t)K >= ((int64_t)1 << 31)) {
-        set_error("more than 2^31 - 1 rows");
-        return GIS_E_UNSUPPORTED;
-      }
-    }
-    // build
-    const int64_t n_rows = n_cells * K;
-    GIS_HIP(hipEventRecord(ev[0], s));
-    if ((rc = prepare_index(ctx, ga, lv, ix, n_cells, lmax, false, ci, s, r == 0))) return rc;
-    if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)))
-      return rc;
-    if (ctx->col.bytes < 16 && (rc = ensure(ctx->col, (size_t)n_rows * 4 * 8))) return rc;
-    Graph gr{(int64_t*)ctx->row_ptr.ptr, (int32_t*)ctx->col.ptr, (uint8_t*)ctx->out.ptr,
-             (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f};
-    if ((rc = run_build(ctx, sys, grid, d_u, K, ci, lv, ix, n_cells, &o, gr, s))) return rc;
-    if (gr.n_edges > gr.cap_edges) {
-      if ((rc = ensure(ctx->col, (size_t)gr.n_edges * 4))) return rc;
-      gr.col = (int32_t*)ctx->col.ptr;
-      gr.cap_edges = (int64_t)(ctx->col.bytes / 4);
-      if ((rc = rerun_emit(ctx, n, ci, n_rows, gr, s))) return rc;
-    }
-    GIS_HIP(hipEventRecord(ev[1], s));
-    // prune
-    if ((rc = ensure(ctx->kept, (size_t)n_cells + 16)) || (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)))
-      return rc;
-    if ((rc = run_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.n_edges, o.analysis,
-                        (uint8_t*)ctx->kept.ptr, (uint64_t*)ctx->mask.ptr, &n_kept, s)))
-      return rc;
-    GIS_HIP(hipEventRecord(ev[2], s));
-    GIS_HIP(hipEventSynchronize(ev[2]));  // run_prune synchronised: returns at once
-    float ms_b = 0.f, ms_p = 0.f;
-    GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
-    GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
-    if (r > 0) {
-      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[3], ev[0]));
-      info.rounds[r - 1].ms_subdivide = ms_sub;
-    }
-    st.n_cells = n_cells;
-    st.n_rows = n_rows;
-    st.n_edges = gr.n_edges;
-    st.n_out = gr.n_out;
-    st.n_kept = n_kept;
-    st.n_recheck = gr.n_recheck;
-    st.max_level = lmax;
-    st.ms_build = ms_b;
-    st.ms_prune = ms_p;
-    st.ms_image = gr.ms_image;
-    st.ms_recheck = gr.ms_recheck;
-    info.n_rounds = r + 1;
-    if (n_kept == 0) break;
-  }
-
-  // result handle
-  gis_solution* sol = new gis_solution();
-  sol->device = ctx->device;
-  sol->grid = ga;
-  sol->K = K;
-  sol->W = W;
-  const int64_t nc = n_cells;
-  sol->n_cells = nc;
-  info.n_cells = nc;
-  info.n_kept = nc > 0 ? n_kept : 0;
-  sol->info = info;
-  auto fail = [&](int32_t code) {
-    gis_solution_free(sol);
-    return code;
-  };
-  const uint8_t* lv = (const uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
-  const int32_t* ix = (const int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
-  if ((rc = ensure(sol->level, (size_t)nc + 16)) || (rc = ensure(sol->idx, (size_t)nc * n * 4 + 16)) ||
-      (rc = ensure(sol->kept, (size_t)nc + 16)) || (rc = ensure(sol->mask, (size_t)nc * W * 8 + 16)))
-    return fail(rc);
-  if (nc > 0) {
-    if (hipMemcpyAsync(sol->level.ptr, lv, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sol->idx.ptr, ix, nc * n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sol->kept.ptr, ctx->kept.ptr, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sol->mask.ptr, ctx->mask.ptr, nc * W * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-      set_error("copy of the solution failed");
-      return fail(GIS_E_HIP);
-    }
-    sol->ci = ci;
-    if (!ci.uniform) {
-      const int64_t total = ci.off[ci.lmax + 1];
-      if ((rc = ensure(sol->state, (size_t)total + 16)) || (rc = ensure(sol->id, (size_t)total * 4 + 16)))
-        return fail(rc);
-      if (hipMemcpyAsync(sol->state.ptr, ci.state, total, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(sol->id.ptr, ci.id, total * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-        set_error("copy of the covering index failed");
-        return fail(GIS_E_HIP);
-      }
-      sol->ci.state = (uint8_t*)sol->state.ptr;
-      sol->ci.id = (int32_t*)sol->id.ptr;
-    }
-  } else {
-    sol->ci = ci;
-    sol->ci.uniform = 0;
-  }
-  if (hipStreamSynchronize(s) != hipSuccess) {
-    set_error("stream synchronisation failed");
-    return fail(GIS_E_HIP);
-  }
-  *out_sol = sol;
-  return GIS_OK;
+  DeviceGuard dg(ctx->device);
+  return solve_batch(ctx, specs, K, rounds, opts, out_sols, as_stream(stream));
 }
 
 int32_t gis_solution_info(const gis_solution* sol, gis_solve_info* info) {
@@ -882,12 +1179,16 @@ int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, co
     return inval("unknown sample scheme");
   if (precision != GIS_PREC_FP64 && precision != GIS_PREC_FP32_RECHECK) return inval("unknown precision");
   DeviceGuard g(ctx->device);
+  hipStream_t s = as_stream(stream);
+  Batch B;
+  if ((rc = batch_init(ctx, B, {job_spec(sys, grid, d_u)}, K))) return rc;
+  if ((rc = batch_layout(ctx, B, {cells->n_cells}, false, {0}, s))) return rc;
   gis_opts o{};
   o.samples = samples;
-  CoverIndex ci{};
-  BuildArgs a = make_build_args(ctx, sys, grid, d_u, K, ci, cells->level, cells->idx,
-                                cells->n_cells, &o);
-  return launch_images(a, precision, d_images, as_stream(stream));
+  BuildArgs a = build_args(ctx, B, cells->level, cells->idx, &o);
+  if ((rc = launch_images(a, precision, d_images, s))) return rc;
+  GIS_HIP(hipStreamSynchronize(s));  // the staged job table is consumed
+  return GIS_OK;
 }
 
 int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
@@ -901,18 +1202,23 @@ int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* 
     return inval("unknown sample scheme");
   DeviceGuard g(ctx->device);
   hipStream_t s = as_stream(stream);
+  Batch B;
+  if ((rc = batch_init(ctx, B, {job_spec(sys, grid, d_u)}, K))) return rc;
+  if ((rc = batch_layout(ctx, B, {cells->n_cells}, false, {0}, s))) return rc;
+  if ((rc = ensure(ctx->maxerr, sizeof(unsigned long long) * kMaxDim * 2))) return rc;
+  if ((rc = ctx->h_maxerr.ensure(kMaxDim * 2))) return rc;
+  if ((rc = fill_u32((uint32_t*)ctx->maxerr.ptr, 0u, 2 * kMaxDim, s))) return rc;
   gis_opts o{};
   o.samples = samples;
-  CoverIndex ci{};
-  if ((rc = zero_counters(ctx, s))) return rc;
-  BuildArgs a = make_build_args(ctx, sys, grid, d_u, K, ci, cells->level, cells->idx,
-                                cells->n_cells, &o);
-  if ((rc = launch_calibrate(a, dcnt(ctx)->maxerr, s))) return rc;
-  if ((rc = sync_counters(ctx, s))) return rc;
+  BuildArgs a = build_args(ctx, B, cells->level, cells->idx, &o);
+  if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, s))) return rc;
+  GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim,
+                         hipMemcpyDeviceToHost, s));
+  GIS_HIP(hipStreamSynchronize(s));
   const GridArgs ga = make_grid(grid);
   for (int d = 0; d < sys->n; ++d) {
     double e;
-    memcpy(&e, &ctx->h_counters->maxerr[d], 8);
+    memcpy(&e, &ctx->h_maxerr.h[d], 8);
     const double fl = floor_rel * ga.w0[d];
     const double b = safety * e;
     band_out[d] = b > fl ? b : fl;

@@ -98,55 +98,114 @@ int32_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, int64_t* 
                            hipStream_t s);
 
 // k_index.hip
-// Builds the covering index of a canonical cell list; flags invalid lists in
-// *d_err (bit 0: index out of range, bit 1: not canonical / duplicate,
-// bit 2: overlapping cells).
-int32_t index_build(CoverIndex& ci, const GridArgs& g, const uint8_t* level, const int32_t* idx,
-                    int64_t n_cells, uint32_t* d_err, hipStream_t s);
-int32_t index_mark_dropped(const CoverIndex& ci, const uint8_t* level, const int32_t* idx,
-                           int64_t n_cells, const uint8_t* kept, hipStream_t s);
 int32_t max_level(const uint8_t* level, int64_t n_cells, uint32_t* d_out, hipStream_t s);
 int32_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int32_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 int32_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 int32_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 
-// k_build.hip
-struct BuildArgs {
+// ---------------------------------------------------------------- jobs
+// A batch runs several independent solves (jobs) through the same launches.
+// Cells and rows are numbered globally, job after job (row = global cell * K
+// + input), so the graph of a batch is the disjoint union of the jobs'
+// graphs.  Each launch pads only its grid: every block belongs to one job,
+// found by a binary search over the jobs' first-block offsets for that kind
+// of launch, so all job parameters are wave-uniform.
+enum LaunchKind { LK_ROWS = 0, LK_CELLS = 1, LK_SLOTS = 2, LK_NEXT = 3, LK_KINDS = 4 };
+
+struct Job {
   SysArgs sys;
   GridArgs grid;
-  CoverIndex ci;
-  const double* u;        // K x m
+  CoverIndex ci;          // index of the job's current covering
+  CoverIndex next;        // layout (and flag array) of the next covering
+  const double* u;        // K x m inputs
+  int64_t n_cells;        // cells of the current covering
+  int64_t cell_off;       // global id of the job's first cell
+  int64_t next_off;       // offset of the job's flags in the batch's next-flag array
+  int64_t blk[LK_KINDS];  // first launch block of the job, per launch kind
+  double band[kMaxDim];   // FP32 recheck band
+};
+
+// Per-job counters, read back once per phase.
+struct JobStats {
+  unsigned long long n_out, n_kept, n_boundary, n_recheck;
+  int64_t n_edges;
+  int64_t next_start;                   // first new cell of the job (global position)
+  int64_t level_start[kMaxLevels + 1];  // new cells before each level (global position)
+};
+
+__device__ __forceinline__ int32_t job_of_block(const Job* jobs, int32_t n_jobs, int kind,
+                                                int64_t b) {
+  int32_t lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk[kind] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Copies a job's covering index into LDS (all threads of the block take
+// part).  Kernels then walk the index from LDS: reading it through the job
+// table in global memory would make the compiler reload it after every
+// global store, since it cannot rule out aliasing.
+__device__ __forceinline__ void stage_index(CoverIndex* dst, const CoverIndex* src) {
+  const int words = (int)(sizeof(CoverIndex) / 4);
+  for (int i = threadIdx.x; i < words; i += blockDim.x)
+    ((int32_t*)dst)[i] = ((const int32_t*)src)[i];
+  __syncthreads();
+}
+
+// Job owning a global row (binary search over the jobs' row offsets).
+__device__ __forceinline__ int32_t job_of_row(const Job* jobs, int32_t n_jobs, int32_t K,
+                                              int64_t row) {
+  int32_t lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].cell_off * K <= row) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- k_build.hip
+struct BuildArgs {
+  const Job* jobs;
+  int32_t n_jobs;
   int32_t K;
   int32_t samples;        // GIS_SAMPLES_*
   int32_t fast_out;
-  const uint8_t* level;
+  int32_t kind, n;        // system kind and state dimension shared by the batch
+  int64_t n_blocks;       // launch blocks (LK_ROWS)
+  const uint8_t* level;   // global cell list
   const int32_t* idx;
-  int64_t n_rows;
-  double band[kMaxDim];   // FP32 recheck band
-  // outputs
-  int32_t* rng;           // [n_rows * 2n] closed ranges on the finest grid (lo, hi per dim)
-  int32_t* cnt;           // [n_rows] edge counts
-  uint8_t* out;           // [n_rows] OUT flags
-  int64_t* bsum;          // [n_blocks] edge count per block of kRowBlock rows
-  int64_t* recheck;       // [n_rows] rows queued for the FP64 recheck
+  // outputs, indexed by global row
+  int32_t* rng;           // [rows * 2n] closed ranges on each job's finest grid
+  int32_t* cnt;           // [rows] edge counts
+  uint8_t* out;           // [rows] OUT flags
+  int64_t* bsum;          // [n_blocks] edge count per launch block
+  int64_t* recheck;       // [rows] global rows queued for the FP64 recheck
   int64_t* n_recheck;     // device counter
+  JobStats* stats;        // per-job counters
 };
 int32_t launch_count(const BuildArgs& a, int32_t precision, hipStream_t s);
 int32_t launch_recheck(const BuildArgs& a, hipStream_t s);
 struct EmitArgs {
-  CoverIndex ci;
-  int32_t n;
-  int64_t n_rows;
+  const Job* jobs;
+  int32_t n_jobs;
+  int32_t K, n;
+  int32_t any_adaptive;   // 0: every job is a full level-0 grid
+  int64_t n_blocks;
+  int64_t total_rows;
   const int32_t* rng;
   const int32_t* cnt;
   const int64_t* bscan;   // exclusive scan of bsum
-  const int64_t* total;   // device total edges
   int64_t cap_edges;
   int64_t* row_ptr;
   int32_t* col;
 };
 int32_t launch_emit(const EmitArgs& a, hipStream_t s);
+// Per-job edge totals from row_ptr (after emit) into stats[j].n_edges.
+int32_t launch_job_edges(const Job* jobs, int32_t n_jobs, int32_t K, const int64_t* row_ptr,
+                         JobStats* stats, hipStream_t s);
 int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s);
 int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, hipStream_t s);
 int32_t count_out(const uint8_t* out, int64_t n, unsigned long long* d_count, hipStream_t s);
@@ -160,7 +219,8 @@ struct PruneWork {
   int32_t* alive;    // [n_rows] remaining kept targets (non-leaving analysis)
   uint32_t* badbits; // [ceil(n_rows / 32)] (controlled analysis)
   int32_t* queue;    // [n_cells]
-  int32_t* qctl;     // [4]: alloc, head, pending, error
+  int32_t* qctl;     // [128]: queue counters, one 128-byte line each
+  int32_t* err_out;  // receives the drain's error word
   void* scan_tmp;
 };
 // Flags an inconsistent CSR graph in *d_err (bit 0 offsets, bit 1 targets).
@@ -171,21 +231,37 @@ int32_t launch_prune(const int64_t* row_ptr, const int32_t* col, const uint8_t* 
                      const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t mask_words,
                      unsigned long long* d_nkept, hipStream_t s);
 
-// k_refine.hip
-int32_t launch_boundary(const CoverIndex& ci, const GridArgs& g, const uint8_t* level,
-                        const int32_t* idx, int64_t n_cells, const uint8_t* kept, int32_t rule,
-                        uint8_t* boundary, hipStream_t s);
-// Dense "present" flags of the next covering over levels 0..lmax+1 (layout of
-// `next`), then compaction into a canonical cell list.
-int32_t launch_next_flags(const CoverIndex& next, const uint8_t* level, const int32_t* idx,
-                          int64_t n_cells, const uint8_t* kept, const uint8_t* boundary,
-                          hipStream_t s);
-int32_t launch_compact(const CoverIndex& next, const int64_t* pos, int64_t cap, uint8_t* level_out,
-                       int32_t* idx_out, hipStream_t s);
-int32_t launch_coarse(const GridArgs& g, uint8_t* level, int32_t* idx, hipStream_t s);
-// out[L] = pos[first slot of level L] for L <= next.lmax
-int32_t launch_level_starts(const CoverIndex& next, const int64_t* pos, int64_t* out,
-                            hipStream_t s);
+// k_index.hip, job-batched: covering indexes of every job's cell list (the
+// jobs' state arrays are cleared first by the caller).  Flags invalid lists in
+// *d_err (bit 0: index out of range, bit 1: not canonical / duplicate,
+// bit 2: overlapping cells).  Jobs whose ci.uniform is set only get checked.
+struct BatchArgs {
+  const Job* jobs;
+  int32_t n_jobs;
+  int32_t n;              // state dimension
+  int32_t K;
+  const uint8_t* level;   // global cell list
+  const int32_t* idx;
+  int64_t blocks[LK_KINDS];
+};
+int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, hipStream_t s);
+int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t s);
+
+// k_refine.hip, job-batched
+int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
+                       JobStats* stats, hipStream_t s);
+// Sets the next-covering flags (the caller cleared the jobs' next arrays).
+int32_t batch_next_flags(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
+                         hipStream_t s);
+// pos: exclusive scan of the batch's next-flag array; writes the new global
+// cell list (up to cap) and each job's next_start / level_start.
+int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,
+                      int32_t* idx_out, JobStats* stats, hipStream_t s);
+int32_t batch_coarse(const BatchArgs& b, uint8_t* level, int32_t* idx, hipStream_t s);
+// Kept cells per job into stats[j].n_kept.
+int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stats, hipStream_t s);
+// OUT rows per job into stats[j].n_out.
+int32_t batch_count_out(const BatchArgs& b, const uint8_t* out, JobStats* stats, hipStream_t s);
 
 // k_query.hip
 int32_t launch_query(const CoverIndex& ci, const GridArgs& g, const uint8_t* kept,

@@ -138,9 +138,9 @@ __device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t*
   }
 }
 
-template <int N, bool UNIFORM>
+template <int N>
 __device__ __forceinline__ bool has_hole(const CoverIndex& ci, const Ranges<N>& r) {
-  if (UNIFORM || r.iempty) return false;
+  if (ci.uniform || r.iempty) return false;
   bool hole = false;
   walk_levels<N>(ci, r.ilo, r.ihi, [&](int, int64_t, uint8_t st) {
     if (st == ST_HOLE) {
@@ -152,10 +152,10 @@ __device__ __forceinline__ bool has_hole(const CoverIndex& ci, const Ranges<N>& 
   return hole;
 }
 
-template <int N, bool UNIFORM>
+template <int N>
 __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ranges<N>& r) {
   if (r.empty) return 0;
-  if (UNIFORM) {
+  if (ci.uniform) {
     int32_t c = 1;
 #pragma unroll
     for (int d = 0; d < N; ++d) c *= r.hi[d] - r.lo[d] + 1;
@@ -169,17 +169,18 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ran
   return c;
 }
 
-// Writes the row's cover decision; returns its edge count.
-template <int N, bool UNIFORM>
-__device__ __forceinline__ int32_t decide_row(const BuildArgs& a, int64_t r, bool finite,
+// Writes the cover decision of global row g of job J; returns its edge count.
+template <int N>
+__device__ __forceinline__ int32_t decide_row(const BuildArgs& a, const Job& J,
+                                              const CoverIndex& ci, int64_t g, bool finite,
                                               const double* bl, const double* bh) {
   int32_t count = 0;
   bool out = true;
-  int32_t* rg = a.rng + r * (2 * N);
+  int32_t* rg = a.rng + g * (2 * N);
   if (finite) {
-    const Ranges<N> rr = ranges_of<N>(a.grid, a.ci, bl, bh);
-    out = rr.outx || has_hole<N, UNIFORM>(a.ci, rr);
-    count = count_targets<N, UNIFORM>(a.ci, rr);
+    const Ranges<N> rr = ranges_of<N>(J.grid, ci, bl, bh);
+    out = rr.outx || has_hole<N>(ci, rr);
+    count = count_targets<N>(ci, rr);
     if (a.fast_out && out) count = 0;
 #pragma unroll
     for (int d = 0; d < N; ++d) {
@@ -187,24 +188,26 @@ __device__ __forceinline__ int32_t decide_row(const BuildArgs& a, int64_t r, boo
       rg[2 * d + 1] = rr.hi[d];
     }
   }
-  a.cnt[r] = count;
-  a.out[r] = out ? 1 : 0;
+  a.cnt[g] = count;
+  a.out[g] = out ? 1 : 0;
   return count;
 }
 
-// Bounding box of the sample images of row r in precision R.
+// Bounding box of the sample images of local row lr of job J, in precision R.
 template <int KIND, int N, typename R>
-__device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Rk4Consts<R>& kc, int64_t r,
-                                         R* bl, R* bh) {
-  const int64_t c = r / a.K;
-  const int32_t j = (int32_t)(r - c * a.K);
-  const int level = a.level[c];
+__device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const Rk4Consts<R>& kc,
+                                         int64_t lr, R* bl, R* bh) {
+  const int64_t c = lr / a.K;
+  const int32_t j = (int32_t)(lr - c * a.K);
+  const int64_t gc = J.cell_off + c;
+  const int level = a.level[gc];
   int32_t ci[N];
 #pragma unroll
-  for (int d = 0; d < N; ++d) ci[d] = a.idx[c * N + d];
+  for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
+  const int m = J.sys.m;
   R u[2];
-  u[0] = R(a.u[(int64_t)j * a.sys.m]);
-  u[1] = a.sys.m > 1 ? R(a.u[(int64_t)j * a.sys.m + 1]) : R(0);
+  u[0] = R(J.u[(int64_t)j * m]);
+  u[1] = m > 1 ? R(J.u[(int64_t)j * m + 1]) : R(0);
   bool finite = true;
 #pragma unroll
   for (int d = 0; d < N; ++d) {
@@ -216,11 +219,11 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Rk4Consts<R>&
     int k[N];
     double xd[N];
     sample_offsets<N>(a.samples, q, k);
-    sample_point<N>(a.grid, level, ci, k, xd);
+    sample_point<N>(J.grid, level, ci, k, xd);
     R x[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) x[d] = R(xd[d]);
-    rk4<KIND, N, R>(kc, a.sys.m, a.sys.nsub, x, u);
+    rk4<KIND, N, R>(kc, m, J.sys.nsub, x, u);
 #pragma unroll
     for (int d = 0; d < N; ++d) {
       finite &= isfinite(x[d]);
@@ -243,16 +246,21 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* lds) {
 }
 
 // ------------------------------------------------------------------ kernels
-template <int KIND, int N, bool UNIFORM>
+// One thread per (cell, input) row; a block never straddles two jobs.
+template <int KIND, int N>
 __global__ __launch_bounds__(kRowBlock) void k_count_f64(BuildArgs a) {
   __shared__ int64_t lds[kRowBlock / 64];
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  __shared__ CoverIndex ci;
+  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
+  const Job& J = a.jobs[jb];
+  stage_index(&ci, &J.ci);
+  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
   int64_t mine = 0;
-  if (r < a.n_rows) {
-    const Rk4Consts<double> kc = make_consts<double>(a.sys);
+  if (lr < J.n_cells * a.K) {
+    const Rk4Consts<double> kc = make_consts<double>(J.sys);
     double bl[N], bh[N];
-    const bool finite = row_bbox<KIND, N, double>(a, kc, r, bl, bh);
-    mine = decide_row<N, UNIFORM>(a, r, finite, bl, bh);
+    const bool finite = row_bbox<KIND, N, double>(a, J, kc, lr, bl, bh);
+    mine = decide_row<N>(a, J, ci, J.cell_off * a.K + lr, finite, bl, bh);
   }
   const int64_t t = block_sum_i64(mine, lds);
   if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
@@ -264,82 +272,98 @@ __global__ __launch_bounds__(kRowBlock) void k_count_f64(BuildArgs a) {
 // Since |y32 - y64| <= band[d] holds for every sample image, and min/max are
 // 1-Lipschitz, the FP64 box extremes then lead to the same decisions.
 // Other rows are queued for the FP64 recheck kernel.
-template <int KIND, int N, bool UNIFORM>
+template <int KIND, int N>
 __global__ __launch_bounds__(kRowBlock) void k_count_f32(BuildArgs a) {
   __shared__ int64_t lds[kRowBlock / 64];
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  __shared__ CoverIndex ci;
+  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
+  const Job& J = a.jobs[jb];
+  stage_index(&ci, &J.ci);
+  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
   int64_t mine = 0;
-  if (r < a.n_rows) {
-    const Rk4Consts<float> kc = make_consts<float>(a.sys);
+  if (lr < J.n_cells * a.K) {
+    const int64_t g = J.cell_off * a.K + lr;
+    const Rk4Consts<float> kc = make_consts<float>(J.sys);
     float bl[N], bh[N];
-    bool safe = row_bbox<KIND, N, float>(a, kc, r, bl, bh);
+    bool safe = row_bbox<KIND, N, float>(a, J, kc, lr, bl, bh);
     double dl[N], dh[N];
-    const int L = a.ci.lmax;
+    const int L = ci.lmax;
 #pragma unroll
     for (int d = 0; d < N; ++d) {
       dl[d] = (double)bl[d];
       dh[d] = (double)bh[d];
-      const double hs = ldexp(a.grid.w0[d], -L);
-      const double eps = a.band[d];
-      const double ta = (dl[d] - a.grid.lo[d]) / hs;
-      const double tb = (dh[d] - a.grid.lo[d]) / hs;
+      const double hs = ldexp(J.grid.w0[d], -L);
+      const double eps = J.band[d];
+      const double ta = (dl[d] - J.grid.lo[d]) / hs;
+      const double tb = (dh[d] - J.grid.lo[d]) / hs;
       const double tola = eps / hs + 1e-9 * (fabs(ta) + 1.0);
       const double tolb = eps / hs + 1e-9 * (fabs(tb) + 1.0);
       safe &= fabs(ta - rint(ta)) > tola;
       safe &= fabs(tb - rint(tb)) > tolb;
-      safe &= fabs(dh[d] - a.grid.hi[d]) > eps;
+      safe &= fabs(dh[d] - J.grid.hi[d]) > eps;
     }
     if (safe) {
-      mine = decide_row<N, UNIFORM>(a, r, true, dl, dh);
+      mine = decide_row<N>(a, J, ci, g, true, dl, dh);
     } else {
       const unsigned long long slot = atomicAdd((unsigned long long*)a.n_recheck, 1ull);
-      a.recheck[slot] = r;
-      a.cnt[r] = 0;
+      a.recheck[slot] = g;
+      a.cnt[g] = 0;
+      atomicAdd(&a.stats[jb].n_recheck, 1ull);
     }
   }
   const int64_t t = block_sum_i64(mine, lds);
   if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
 }
 
-template <int KIND, int N, bool UNIFORM>
+template <int KIND, int N>
 __global__ __launch_bounds__(kRowBlock) void k_recheck(BuildArgs a) {
   const int64_t n = *a.n_recheck;
-  const Rk4Consts<double> kc = make_consts<double>(a.sys);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = a.recheck[i];
+    const int64_t g = a.recheck[i];
+    const int32_t jb = job_of_row(a.jobs, a.n_jobs, a.K, g);
+    const Job& J = a.jobs[jb];
+    const int64_t lr = g - J.cell_off * a.K;
+    const Rk4Consts<double> kc = make_consts<double>(J.sys);
     double bl[N], bh[N];
-    const bool finite = row_bbox<KIND, N, double>(a, kc, r, bl, bh);
-    const int32_t c = decide_row<N, UNIFORM>(a, r, finite, bl, bh);
-    if (c) atomicAdd((unsigned long long*)&a.bsum[r / kRowBlock], (unsigned long long)c);
+    const bool finite = row_bbox<KIND, N, double>(a, J, kc, lr, bl, bh);
+    const int32_t c = decide_row<N>(a, J, J.ci, g, finite, bl, bh);
+    if (c)
+      atomicAdd((unsigned long long*)&a.bsum[J.blk[LK_ROWS] + lr / kRowBlock],
+                (unsigned long long)c);
   }
 }
 
 template <int KIND, int N, typename R>
 __global__ __launch_bounds__(kRowBlock) void k_images(BuildArgs a, double* out) {
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-  if (r >= a.n_rows) return;
-  const Rk4Consts<R> kc = make_consts<R>(a.sys);
-  const int64_t c = r / a.K;
-  const int32_t j = (int32_t)(r - c * a.K);
+  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
+  const Job& J = a.jobs[jb];
+  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
+  if (lr >= J.n_cells * a.K) return;
+  const int64_t g = J.cell_off * a.K + lr;
+  const Rk4Consts<R> kc = make_consts<R>(J.sys);
+  const int64_t c = lr / a.K;
+  const int32_t j = (int32_t)(lr - c * a.K);
+  const int64_t gc = J.cell_off + c;
   int32_t ci[N];
 #pragma unroll
-  for (int d = 0; d < N; ++d) ci[d] = a.idx[c * N + d];
+  for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
+  const int m = J.sys.m;
   R u[2];
-  u[0] = R(a.u[(int64_t)j * a.sys.m]);
-  u[1] = a.sys.m > 1 ? R(a.u[(int64_t)j * a.sys.m + 1]) : R(0);
+  u[0] = R(J.u[(int64_t)j * m]);
+  u[1] = m > 1 ? R(J.u[(int64_t)j * m + 1]) : R(0);
   const int S = num_samples(a.samples, N);
   for (int q = 0; q < S; ++q) {
     int k[N];
     double xd[N];
     sample_offsets<N>(a.samples, q, k);
-    sample_point<N>(a.grid, a.level[c], ci, k, xd);
+    sample_point<N>(J.grid, a.level[gc], ci, k, xd);
     R x[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) x[d] = R(xd[d]);
-    rk4<KIND, N, R>(kc, a.sys.m, a.sys.nsub, x, u);
+    rk4<KIND, N, R>(kc, m, J.sys.nsub, x, u);
 #pragma unroll
-    for (int d = 0; d < N; ++d) out[(r * S + q) * N + d] = (double)x[d];
+    for (int d = 0; d < N; ++d) out[(g * S + q) * N + d] = (double)x[d];
   }
 }
 
@@ -347,22 +371,26 @@ __global__ __launch_bounds__(kRowBlock) void k_images(BuildArgs a, double* out) 
 // like the values, so an integer atomicMax works).
 template <int KIND, int N>
 __global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned long long* maxerr) {
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
+  const Job& J = a.jobs[jb];
+  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
   double e[N];
 #pragma unroll
   for (int d = 0; d < N; ++d) e[d] = 0.0;
-  if (r < a.n_rows) {
-    const Rk4Consts<double> k64 = make_consts<double>(a.sys);
-    const Rk4Consts<float> k32 = make_consts<float>(a.sys);
-    const int64_t c = r / a.K;
-    const int32_t j = (int32_t)(r - c * a.K);
+  if (lr < J.n_cells * a.K) {
+    const Rk4Consts<double> k64 = make_consts<double>(J.sys);
+    const Rk4Consts<float> k32 = make_consts<float>(J.sys);
+    const int64_t c = lr / a.K;
+    const int32_t j = (int32_t)(lr - c * a.K);
+    const int64_t gc = J.cell_off + c;
     int32_t ci[N];
 #pragma unroll
-    for (int d = 0; d < N; ++d) ci[d] = a.idx[c * N + d];
+    for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
+    const int m = J.sys.m;
     double u64[2];
     float u32[2];
-    u64[0] = a.u[(int64_t)j * a.sys.m];
-    u64[1] = a.sys.m > 1 ? a.u[(int64_t)j * a.sys.m + 1] : 0.0;
+    u64[0] = J.u[(int64_t)j * m];
+    u64[1] = m > 1 ? J.u[(int64_t)j * m + 1] : 0.0;
     u32[0] = (float)u64[0];
     u32[1] = (float)u64[1];
     const int S = num_samples(a.samples, N);
@@ -371,11 +399,11 @@ __global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned l
       double xd[N];
       float xf[N];
       sample_offsets<N>(a.samples, q, k);
-      sample_point<N>(a.grid, a.level[c], ci, k, xd);
+      sample_point<N>(J.grid, a.level[gc], ci, k, xd);
 #pragma unroll
       for (int d = 0; d < N; ++d) xf[d] = (float)xd[d];
-      rk4<KIND, N, double>(k64, a.sys.m, a.sys.nsub, xd, u64);
-      rk4<KIND, N, float>(k32, a.sys.m, a.sys.nsub, xf, u32);
+      rk4<KIND, N, double>(k64, m, J.sys.nsub, xd, u64);
+      rk4<KIND, N, float>(k32, m, J.sys.nsub, xf, u32);
 #pragma unroll
       for (int d = 0; d < N; ++d) {
         double diff = fabs((double)xf[d] - xd[d]);
@@ -391,17 +419,24 @@ __global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned l
       const double w = __shfl_down(v, o, 64);
       v = w > v ? w : v;
     }
-    if ((threadIdx.x & 63) == 0) atomicMax(&maxerr[d], (unsigned long long)__double_as_longlong(v));
+    if ((threadIdx.x & 63) == 0)
+      atomicMax(&maxerr[jb * kMaxDim + d], (unsigned long long)__double_as_longlong(v));
   }
 }
 
 // ------------------------------------------------------------------ emit
-template <int N, bool UNIFORM>
+template <int N>
 __global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
   __shared__ int32_t tile[kTile];
   __shared__ int64_t wsum[kRowBlock / 64];
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-  const int32_t c = r < a.n_rows ? a.cnt[r] : 0;
+  __shared__ CoverIndex ci;
+  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
+  const Job& J = a.jobs[jb];
+  stage_index(&ci, &J.ci);
+  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
+  const bool live = lr < J.n_cells * a.K;
+  const int64_t g = J.cell_off * a.K + lr;
+  const int32_t c = live ? a.cnt[g] : 0;
   // block-exclusive scan of the counts
   int64_t x = c;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -418,12 +453,12 @@ __global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
   }
   const int64_t off = before + x - c;
   const int64_t base = a.bscan[blockIdx.x];
-  if (r < a.n_rows) a.row_ptr[r] = base + off;
-  if (r == a.n_rows - 1) a.row_ptr[a.n_rows] = base + off + c;
+  if (live) a.row_ptr[g] = base + off;
+  if (live && g == a.total_rows - 1) a.row_ptr[a.total_rows] = base + off + c;
   if (base + total > a.cap_edges) return;  // capacity miss: col is not written
   const bool staged = total <= kTile;
   if (c > 0) {
-    const int32_t* rg = a.rng + r * (2 * N);
+    const int32_t* rg = a.rng + g * (2 * N);
     int32_t lo[N], hi[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) {
@@ -431,16 +466,17 @@ __global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
       hi[d] = rg[2 * d + 1];
     }
     int32_t* dst = staged ? tile + off : a.col + base + off;
-    if (UNIFORM) {
+    const int32_t id0 = (int32_t)J.cell_off;
+    int32_t w = 0;
+    if (ci.uniform) {
       int32_t k[N];
 #pragma unroll
       for (int d = 0; d < N; ++d) k[d] = lo[d];
-      int32_t w = 0;
       for (;;) {
         int32_t lin = 0;
 #pragma unroll
-        for (int d = 0; d < N; ++d) lin = lin * a.ci.dims[0][d] + k[d];
-        if (w < c) dst[w++] = lin;
+        for (int d = 0; d < N; ++d) lin = lin * ci.dims[0][d] + k[d];
+        if (w < c) dst[w++] = id0 + lin;
         int d = N - 1;
         while (d >= 0 && k[d] == hi[d]) {
           k[d] = lo[d];
@@ -450,9 +486,8 @@ __global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
         ++k[d];
       }
     } else {
-      int32_t w = 0;
-      walk_levels<N>(a.ci, lo, hi, [&](int, int64_t slot, uint8_t st) {
-        if (st == ST_LEAF && w < c) dst[w++] = a.ci.id[slot];
+      walk_levels<N>(ci, lo, hi, [&](int, int64_t slot, uint8_t st) {
+        if (st == ST_LEAF && w < c) dst[w++] = id0 + ci.id[slot];
         return true;
       });
     }
@@ -461,6 +496,14 @@ __global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
     __syncthreads();
     for (int64_t i = threadIdx.x; i < total; i += kRowBlock) a.col[base + i] = tile[i];
   }
+}
+
+__global__ void k_job_edges(const Job* jobs, int32_t n_jobs, int32_t K, const int64_t* row_ptr,
+                            JobStats* stats) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_jobs) return;
+  const int64_t r0 = jobs[j].cell_off * K, r1 = (jobs[j].cell_off + jobs[j].n_cells) * K;
+  stats[j].n_edges = r1 > r0 ? row_ptr[r1] - row_ptr[r0] : 0;
 }
 
 __global__ void k_count_out(const uint8_t* out, int64_t n, unsigned long long* cnt) {
@@ -473,88 +516,82 @@ __global__ void k_count_out(const uint8_t* out, int64_t n, unsigned long long* c
 }
 
 // ------------------------------------------------------------------ dispatch
-inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kRowBlock - 1) / kRowBlock); }
-
-template <template <int, int, bool> class Launcher, typename... Args>
-int32_t dispatch_sys(int kind, int n, bool uniform, Args&&... args) {
-#define GIS_CASE(KIND, N)                                                         \
-  if (uniform) return Launcher<KIND, N, true>::run(args...);                      \
-  return Launcher<KIND, N, false>::run(args...);
+template <template <int, int> class Launcher, typename... Args>
+int32_t dispatch_sys(int kind, int n, Args&&... args) {
   switch (kind) {
     case GIS_SYS_VDP:
-      if (n == 2) { GIS_CASE(GIS_SYS_VDP, 2) }
+      if (n == 2) return Launcher<GIS_SYS_VDP, 2>::run(args...);
       break;
     case GIS_SYS_LORENZ:
-      if (n == 3) { GIS_CASE(GIS_SYS_LORENZ, 3) }
+      if (n == 3) return Launcher<GIS_SYS_LORENZ, 3>::run(args...);
       break;
     case GIS_SYS_VDP2:
-      if (n == 4) { GIS_CASE(GIS_SYS_VDP2, 4) }
+      if (n == 4) return Launcher<GIS_SYS_VDP2, 4>::run(args...);
       break;
     case GIS_SYS_LINEAR:
-      if (n == 1) { GIS_CASE(GIS_SYS_LINEAR, 1) }
-      if (n == 2) { GIS_CASE(GIS_SYS_LINEAR, 2) }
-      if (n == 3) { GIS_CASE(GIS_SYS_LINEAR, 3) }
-      if (n == 4) { GIS_CASE(GIS_SYS_LINEAR, 4) }
+      if (n == 1) return Launcher<GIS_SYS_LINEAR, 1>::run(args...);
+      if (n == 2) return Launcher<GIS_SYS_LINEAR, 2>::run(args...);
+      if (n == 3) return Launcher<GIS_SYS_LINEAR, 3>::run(args...);
+      if (n == 4) return Launcher<GIS_SYS_LINEAR, 4>::run(args...);
       break;
   }
-#undef GIS_CASE
   set_error("unsupported system kind / dimension");
   return GIS_E_UNSUPPORTED;
 }
 
-template <int KIND, int N, bool U>
+template <int KIND, int N>
 struct CountF64 {
   static int32_t run(const BuildArgs& a, hipStream_t s) {
-    if (a.n_rows == 0) return GIS_OK;
-    hipLaunchKernelGGL((k_count_f64<KIND, N, U>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a);
+    if (a.n_blocks == 0) return GIS_OK;
+    hipLaunchKernelGGL((k_count_f64<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a);
     GIS_LAUNCH_CHECK("k_count_f64");
     return GIS_OK;
   }
 };
-template <int KIND, int N, bool U>
+template <int KIND, int N>
 struct CountF32 {
   static int32_t run(const BuildArgs& a, hipStream_t s) {
-    if (a.n_rows == 0) return GIS_OK;
-    hipLaunchKernelGGL((k_count_f32<KIND, N, U>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a);
+    if (a.n_blocks == 0) return GIS_OK;
+    hipLaunchKernelGGL((k_count_f32<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a);
     GIS_LAUNCH_CHECK("k_count_f32");
     return GIS_OK;
   }
 };
-template <int KIND, int N, bool U>
+template <int KIND, int N>
 struct Recheck {
   static int32_t run(const BuildArgs& a, hipStream_t s) {
-    if (a.n_rows == 0) return GIS_OK;
-    const unsigned nb = blocks_for(a.n_rows) < 2048 ? blocks_for(a.n_rows) : 2048;
-    hipLaunchKernelGGL((k_recheck<KIND, N, U>), dim3(nb), dim3(kRowBlock), 0, s, a);
+    if (a.n_blocks == 0) return GIS_OK;
+    const unsigned nb = a.n_blocks < 2048 ? (unsigned)a.n_blocks : 2048u;
+    hipLaunchKernelGGL((k_recheck<KIND, N>), dim3(nb), dim3(kRowBlock), 0, s, a);
     GIS_LAUNCH_CHECK("k_recheck");
     return GIS_OK;
   }
 };
-template <int KIND, int N, bool U>
+template <int KIND, int N>
 struct Images {
   static int32_t run(const BuildArgs& a, int32_t precision, double* out, hipStream_t s) {
-    if (a.n_rows == 0) return GIS_OK;
+    if (a.n_blocks == 0) return GIS_OK;
     if (precision == GIS_PREC_FP32_RECHECK)
-      hipLaunchKernelGGL((k_images<KIND, N, float>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a, out);
+      hipLaunchKernelGGL((k_images<KIND, N, float>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a, out);
     else
-      hipLaunchKernelGGL((k_images<KIND, N, double>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a, out);
+      hipLaunchKernelGGL((k_images<KIND, N, double>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a, out);
     GIS_LAUNCH_CHECK("k_images");
     return GIS_OK;
   }
 };
-template <int KIND, int N, bool U>
+template <int KIND, int N>
 struct Calibrate {
   static int32_t run(const BuildArgs& a, unsigned long long* maxerr, hipStream_t s) {
-    if (a.n_rows == 0) return GIS_OK;
-    hipLaunchKernelGGL((k_calibrate<KIND, N>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a, maxerr);
+    if (a.n_blocks == 0) return GIS_OK;
+    hipLaunchKernelGGL((k_calibrate<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a, maxerr);
     GIS_LAUNCH_CHECK("k_calibrate");
     return GIS_OK;
   }
 };
 
-template <int N, bool U>
+template <int N>
 int32_t emit_n(const EmitArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_emit<N, U>), dim3(blocks_for(a.n_rows)), dim3(kRowBlock), 0, s, a);
+  hipLaunchKernelGGL((k_emit<N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a);
   GIS_LAUNCH_CHECK("k_emit");
   return GIS_OK;
 }
@@ -562,35 +599,41 @@ int32_t emit_n(const EmitArgs& a, hipStream_t s) {
 }  // namespace
 
 int32_t launch_count(const BuildArgs& a, int32_t precision, hipStream_t s) {
-  const bool uniform = a.ci.uniform != 0;
-  if (precision == GIS_PREC_FP32_RECHECK)
-    return dispatch_sys<CountF32>(a.sys.kind, a.sys.n, uniform, a, s);
-  return dispatch_sys<CountF64>(a.sys.kind, a.sys.n, uniform, a, s);
+  if (precision == GIS_PREC_FP32_RECHECK) return dispatch_sys<CountF32>(a.kind, a.n, a, s);
+  return dispatch_sys<CountF64>(a.kind, a.n, a, s);
 }
 
 int32_t launch_recheck(const BuildArgs& a, hipStream_t s) {
-  return dispatch_sys<Recheck>(a.sys.kind, a.sys.n, a.ci.uniform != 0, a, s);
+  return dispatch_sys<Recheck>(a.kind, a.n, a, s);
 }
 
 int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s) {
-  return dispatch_sys<Images>(a.sys.kind, a.sys.n, true, a, precision, d_images, s);
+  return dispatch_sys<Images>(a.kind, a.n, a, precision, d_images, s);
 }
 
 int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, hipStream_t s) {
-  return dispatch_sys<Calibrate>(a.sys.kind, a.sys.n, true, a, d_maxerr, s);
+  return dispatch_sys<Calibrate>(a.kind, a.n, a, d_maxerr, s);
 }
 
 int32_t launch_emit(const EmitArgs& a, hipStream_t s) {
-  if (a.n_rows == 0) return GIS_OK;
-  const bool u = a.ci.uniform != 0;
+  if (a.n_blocks == 0) return GIS_OK;
   switch (a.n) {
-    case 1: return u ? emit_n<1, true>(a, s) : emit_n<1, false>(a, s);
-    case 2: return u ? emit_n<2, true>(a, s) : emit_n<2, false>(a, s);
-    case 3: return u ? emit_n<3, true>(a, s) : emit_n<3, false>(a, s);
-    case 4: return u ? emit_n<4, true>(a, s) : emit_n<4, false>(a, s);
+    case 1: return emit_n<1>(a, s);
+    case 2: return emit_n<2>(a, s);
+    case 3: return emit_n<3>(a, s);
+    case 4: return emit_n<4>(a, s);
   }
   set_error("unsupported dimension");
   return GIS_E_UNSUPPORTED;
+}
+
+int32_t launch_job_edges(const Job* jobs, int32_t n_jobs, int32_t K, const int64_t* row_ptr,
+                         JobStats* stats, hipStream_t s) {
+  if (n_jobs == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_job_edges, dim3((n_jobs + 63) / 64), dim3(64), 0, s, jobs, n_jobs, K,
+                     row_ptr, stats);
+  GIS_LAUNCH_CHECK("k_job_edges");
+  return GIS_OK;
 }
 
 int32_t count_out(const uint8_t* out, int64_t n, unsigned long long* d_count, hipStream_t s) {

@@ -39,106 +39,106 @@ __global__ void k_max_level(const uint8_t* level, int64_t n, uint32_t* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// Slot of cell c in the index; -1 if its level or multi-index is out of range.
+// Slot of local cell c of a job in the job's index; -1 if its level or
+// multi-index is out of range.
 __device__ __forceinline__ int64_t cell_slot(const CoverIndex& ci, const uint8_t* level,
-                                             const int32_t* idx, int64_t c, int64_t* key_lin) {
-  const int L = level[c];
+                                             const int32_t* idx, int64_t gc) {
+  const int L = level[gc];
   if (L > ci.lmax) return -1;
   int64_t lin = 0;
   for (int d = 0; d < ci.n; ++d) {
-    const int32_t v = idx[c * ci.n + d];
+    const int32_t v = idx[gc * ci.n + d];
     if (v < 0 || v >= ci.dims[L][d]) return -1;
     lin = lin * ci.dims[L][d] + v;
   }
-  *key_lin = lin;
   return ci.off[L] + lin;
 }
 
-// Range and canonical-order checks; with write_index, LEAF entries.
-__global__ void k_leaves(CoverIndex ci, const uint8_t* level, const int32_t* idx, int64_t n_cells,
-                         int write_index, uint32_t* err) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lin;
-    const int64_t slot = cell_slot(ci, level, idx, c, &lin);
-    if (slot < 0) {
-      atomicOr(err, 1u);
-      continue;
-    }
-    if (c > 0) {
-      int64_t plin;
-      const int64_t pslot = cell_slot(ci, level, idx, c - 1, &plin);
-      // canonical order = strictly increasing (level, row-major index) = slot order
-      if (pslot >= 0 && pslot >= slot) atomicOr(err, 2u);
-    }
-    if (write_index) {
-      ci.state[slot] = ST_LEAF;
-      ci.id[slot] = (int32_t)c;
-    }
+// Range and canonical-order checks; LEAF entries for jobs with index arrays.
+__global__ void k_leaves(BatchArgs b, uint32_t* err) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c >= J.n_cells) return;
+  const int64_t gc = J.cell_off + c;
+  const int64_t slot = cell_slot(J.ci, b.level, b.idx, gc);
+  if (slot < 0) {
+    atomicOr(err, 1u);
+    return;
+  }
+  if (c > 0) {
+    // canonical order = strictly increasing (level, row-major index) = slot order
+    const int64_t pslot = cell_slot(J.ci, b.level, b.idx, gc - 1);
+    if (pslot >= 0 && pslot >= slot) atomicOr(err, 2u);
+  }
+  if (!J.ci.uniform) {
+    J.ci.state[slot] = ST_LEAF;
+    J.ci.id[slot] = (int32_t)c;
   }
 }
 
 // Marks every ancestor of every leaf REFINED; an ancestor that is itself a
 // leaf means two cells overlap.
-__global__ void k_ancestors(CoverIndex ci, const uint8_t* level, const int32_t* idx,
-                            int64_t n_cells, uint32_t* err) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lin0;
-    if (cell_slot(ci, level, idx, c, &lin0) < 0) continue;  // reported by k_leaves
-    int L = level[c];
-    int64_t k[kMaxDim];
-    for (int d = 0; d < ci.n; ++d) k[d] = idx[c * ci.n + d];
-    while (L > 0) {
-      --L;
-      int64_t lin = 0;
-      for (int d = 0; d < ci.n; ++d) {
-        k[d] >>= 1;
-        lin = lin * ci.dims[L][d] + k[d];
-      }
-      const int64_t slot = ci.off[L] + lin;
-      if (ci.state[slot] == ST_LEAF) {
-        atomicOr(err, 4u);
-        break;
-      }
-      ci.state[slot] = ST_REFINED;
+__global__ void k_ancestors(BatchArgs b, uint32_t* err) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c >= J.n_cells || J.ci.uniform) return;
+  const int64_t gc = J.cell_off + c;
+  if (cell_slot(J.ci, b.level, b.idx, gc) < 0) return;  // reported by k_leaves
+  int L = b.level[gc];
+  int64_t k[kMaxDim];
+  for (int d = 0; d < J.ci.n; ++d) k[d] = b.idx[gc * J.ci.n + d];
+  while (L > 0) {
+    --L;
+    int64_t lin = 0;
+    for (int d = 0; d < J.ci.n; ++d) {
+      k[d] >>= 1;
+      lin = lin * J.ci.dims[L][d] + k[d];
     }
+    const int64_t slot = J.ci.off[L] + lin;
+    if (J.ci.state[slot] == ST_LEAF) {
+      atomicOr(err, 4u);
+      break;
+    }
+    J.ci.state[slot] = ST_REFINED;
   }
 }
 
 // NONE slots at level 0, or below a REFINED parent, are holes.
-__global__ void k_holes(CoverIndex ci) {
-  const int64_t total = ci.off[ci.lmax + 1];
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    if (ci.state[s] != ST_NONE) continue;
-    int L = 0;
-    while (s >= ci.off[L + 1]) ++L;
-    if (L == 0) {
-      ci.state[s] = ST_HOLE;
-      continue;
-    }
-    int64_t rem = s - ci.off[L];
-    int64_t k[kMaxDim];
-    for (int d = ci.n - 1; d >= 0; --d) {
-      k[d] = rem % ci.dims[L][d];
-      rem /= ci.dims[L][d];
-    }
-    int64_t plin = 0;
-    for (int d = 0; d < ci.n; ++d) plin = plin * ci.dims[L - 1][d] + (k[d] >> 1);
-    if (ci.state[ci.off[L - 1] + plin] == ST_REFINED) ci.state[s] = ST_HOLE;
+__global__ void k_holes(BatchArgs b) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_SLOTS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const CoverIndex& ci = J.ci;
+  if (ci.uniform) return;
+  const int64_t s = (blockIdx.x - J.blk[LK_SLOTS]) * blockDim.x + threadIdx.x;
+  if (s >= ci.off[ci.lmax + 1] || ci.state[s] != ST_NONE) return;
+  int L = 0;
+  while (s >= ci.off[L + 1]) ++L;
+  if (L == 0) {
+    ci.state[s] = ST_HOLE;
+    return;
   }
+  int64_t rem = s - ci.off[L];
+  int64_t k[kMaxDim];
+  for (int d = ci.n - 1; d >= 0; --d) {
+    k[d] = rem % ci.dims[L][d];
+    rem /= ci.dims[L][d];
+  }
+  int64_t plin = 0;
+  for (int d = 0; d < ci.n; ++d) plin = plin * ci.dims[L - 1][d] + (k[d] >> 1);
+  if (ci.state[ci.off[L - 1] + plin] == ST_REFINED) ci.state[s] = ST_HOLE;
 }
 
-__global__ void k_mark_dropped(CoverIndex ci, const uint8_t* level, const int32_t* idx,
-                               int64_t n_cells, const uint8_t* kept) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    if (kept[c]) continue;
-    int64_t lin;
-    const int64_t slot = cell_slot(ci, level, idx, c, &lin);
-    if (slot >= 0) ci.state[slot] = ST_HOLE;
-  }
+__global__ void k_mark_dropped(BatchArgs b, const uint8_t* kept) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c >= J.n_cells || J.ci.uniform) return;
+  const int64_t gc = J.cell_off + c;
+  if (kept[gc]) return;
+  const int64_t slot = cell_slot(J.ci, b.level, b.idx, gc);
+  if (slot >= 0) J.ci.state[slot] = ST_HOLE;
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -163,39 +163,25 @@ int32_t max_level(const uint8_t* level, int64_t n_cells, uint32_t* d_out, hipStr
   return GIS_OK;
 }
 
-int32_t index_build(CoverIndex& ci, const GridArgs& g, const uint8_t* level, const int32_t* idx,
-                    int64_t n_cells, uint32_t* d_err, hipStream_t s) {
-  (void)g;
+int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, hipStream_t s) {
   int32_t rc = fill_u32(d_err, 0u, 1, s);
   if (rc != GIS_OK) return rc;
-  if (ci.uniform) {  // only the checks: the index arrays are implicit
-    if (n_cells == 0) return GIS_OK;
-    hipLaunchKernelGGL(k_leaves, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
-                       n_cells, 0, d_err);
+  if (b.blocks[LK_CELLS] > 0) {
+    hipLaunchKernelGGL(k_leaves, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, d_err);
     GIS_LAUNCH_CHECK("k_leaves");
-    return GIS_OK;
-  }
-  const int64_t total = ci.off[ci.lmax + 1];
-  rc = fill_u8(ci.state, (uint8_t)ST_NONE, total, s);
-  if (rc != GIS_OK) return rc;
-  if (n_cells > 0) {
-    hipLaunchKernelGGL(k_leaves, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
-                       n_cells, 1, d_err);
-    GIS_LAUNCH_CHECK("k_leaves");
-    hipLaunchKernelGGL(k_ancestors, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
-                       n_cells, d_err);
+    hipLaunchKernelGGL(k_ancestors, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, d_err);
     GIS_LAUNCH_CHECK("k_ancestors");
   }
-  hipLaunchKernelGGL(k_holes, dim3(grid_for(total)), dim3(256), 0, s, ci);
-  GIS_LAUNCH_CHECK("k_holes");
+  if (b.blocks[LK_SLOTS] > 0) {
+    hipLaunchKernelGGL(k_holes, dim3((unsigned)b.blocks[LK_SLOTS]), dim3(256), 0, s, b);
+    GIS_LAUNCH_CHECK("k_holes");
+  }
   return GIS_OK;
 }
 
-int32_t index_mark_dropped(const CoverIndex& ci, const uint8_t* level, const int32_t* idx,
-                           int64_t n_cells, const uint8_t* kept, hipStream_t s) {
-  if (n_cells == 0) return GIS_OK;
-  hipLaunchKernelGGL(k_mark_dropped, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx,
-                     n_cells, kept);
+int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_mark_dropped, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept);
   GIS_LAUNCH_CHECK("k_mark_dropped");
   return GIS_OK;
 }

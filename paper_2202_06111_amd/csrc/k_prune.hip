@@ -18,8 +18,12 @@ namespace gis {
 
 namespace {
 
-// qctl layout
-constexpr int Q_ALLOC = 0, Q_HEAD = 1, Q_PENDING = 2, Q_ERROR = 3;
+// qctl layout: one 128-byte line per counter, so waves polling `pending`
+// do not contend with the increments of `alloc` and `head`
+constexpr int Q_ALLOC = 0, Q_HEAD = 32, Q_PENDING = 64, Q_ERROR = 96, Q_WORDS = 128;
+constexpr int32_t kSlotDone = -2;  // written into waiting slots once nothing is left
+constexpr int kHash = 2048;        // LDS hash slots of the reverse-CSR kernels
+constexpr int kProbe = 64;
 
 inline unsigned grid_for(int64_t n, int64_t cap = 8192) {
   int64_t nb = (n + 255) / 256;
@@ -28,38 +32,83 @@ inline unsigned grid_for(int64_t n, int64_t cap = 8192) {
   return (unsigned)nb;
 }
 
-__global__ void k_indegree(const int32_t* col, int64_t n_edges, int32_t* deg) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_edges;
-       e += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&deg[col[e]], 1);
+// Open-addressing hash of target ids in LDS; returns the slot of j or -1 if
+// the probe sequence is full.  insert=false only looks j up.
+__device__ __forceinline__ int lds_slot(int32_t* key, int32_t j, bool insert) {
+  int h = (int)(((uint32_t)j * 2654435761u) >> 21) & (kHash - 1);
+  for (int p = 0; p < kProbe; ++p, h = (h + 1) & (kHash - 1)) {
+    int32_t k = key[h];
+    if (k == j) return h;
+    if (k == -1) {
+      if (!insert) return -1;
+      k = atomicCAS(&key[h], -1, j);
+      if (k == -1 || k == j) return h;
+    }
+  }
+  return -1;
 }
 
-// Each block is one wave and takes 64 consecutive rows at a time; their
-// edges are contiguous in col[], so the lanes stride over that span
-// (coalesced) and find each edge's row by a binary search over the 65 row
-// offsets held in LDS.
-__global__ __launch_bounds__(64) void k_scatter(const int64_t* row_ptr, const int32_t* col,
-                                                int64_t n_rows, const int64_t* rptr,
-                                                int32_t* cursor, int32_t* rrow) {
-  __shared__ int64_t rp[65];
-  const int lane = threadIdx.x;
-  for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < n_rows; r0 += (int64_t)gridDim.x * 64) {
-    const int64_t nr = n_rows - r0 < 64 ? n_rows - r0 : 64;
-    if (lane <= nr) rp[lane] = row_ptr[r0 + lane];
-    if (lane == 0 && nr == 64) rp[64] = row_ptr[r0 + 64];
-    __syncthreads();
-    const int64_t e0 = rp[0], e1 = rp[nr];
-    for (int64_t e = e0 + lane; e < e1; e += 64) {
-      int lo = 0, hi = (int)nr - 1;  // last row with rp[row] <= e
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rp[mid] <= e) lo = mid; else hi = mid - 1;
-      }
+// In-degree histogram.  A block takes 256 consecutive rows (thread = row);
+// their targets overlap heavily (the inputs of one cell, neighbouring
+// cells), so counts are first aggregated per distinct target in LDS and
+// flushed with one global atomic per target.
+__global__ __launch_bounds__(256) void k_indegree(const int64_t* row_ptr, const int32_t* col,
+                                                  int64_t n_rows, int32_t* deg) {
+  __shared__ int32_t key[kHash];
+  __shared__ int32_t cnt[kHash];
+  for (int i = threadIdx.x; i < kHash; i += 256) {
+    key[i] = -1;
+    cnt[i] = 0;
+  }
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r < n_rows) {
+    const int64_t e1 = row_ptr[r + 1];
+    for (int64_t e = row_ptr[r]; e < e1; ++e) {
       const int32_t j = col[e];
-      const int32_t pos = atomicAdd(&cursor[j], 1);
-      rrow[rptr[j] + pos] = (int32_t)(r0 + lo);
+      const int sl = lds_slot(key, j, true);
+      if (sl >= 0) atomicAdd(&cnt[sl], 1);
+      else atomicAdd(&deg[j], 1);
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHash; i += 256)
+    if (key[i] >= 0) atomicAdd(&deg[key[i]], cnt[i]);
+}
+
+// Scatter of source rows into the reverse CSR, with the same blocks: each
+// distinct target reserves one range for the block (one global atomic), and
+// the block's edges fill it through LDS counters.
+__global__ __launch_bounds__(256) void k_scatter(const int64_t* row_ptr, const int32_t* col,
+                                                 int64_t n_rows, const int64_t* rptr,
+                                                 int32_t* cursor, int32_t* rrow) {
+  __shared__ int32_t key[kHash];
+  __shared__ int32_t cnt[kHash];
+  __shared__ int32_t base[kHash];
+  for (int i = threadIdx.x; i < kHash; i += 256) {
+    key[i] = -1;
+    cnt[i] = 0;
+  }
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = r < n_rows;
+  const int64_t e0 = live ? row_ptr[r] : 0, e1 = live ? row_ptr[r + 1] : 0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int sl = lds_slot(key, col[e], true);
+    if (sl >= 0) atomicAdd(&cnt[sl], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHash; i += 256)
+    if (key[i] >= 0) {
+      base[i] = atomicAdd(&cursor[key[i]], cnt[i]);
+      cnt[i] = 0;
+    }
+  __syncthreads();
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t j = col[e];
+    const int sl = lds_slot(key, j, false);
+    const int32_t pos = sl >= 0 ? base[sl] + atomicAdd(&cnt[sl], 1) : atomicAdd(&cursor[j], 1);
+    rrow[rptr[j] + pos] = (int32_t)r;
   }
 }
 
@@ -94,11 +143,19 @@ __global__ void k_badbits_init(const uint8_t* out, int64_t n_rows, uint32_t* bit
   }
 }
 
+// Every piece of state the drain shares (row flags, cell counters, the queue
+// and its counters) changes only through agent-scope atomics, so relaxed
+// ordering suffices and no cache-wide fence is issued (on this GPU an
+// acquire or release at agent scope invalidates or writes back an XCD's whole
+// L2).  Termination needs only the modification order of `pending`: a cell's
+// increment precedes the decrement of the item whose processing pushed it
+// (same thread, same location), so `pending` stays >= 1 until every pushed
+// cell has been processed.
 __device__ __forceinline__ void push_removed(int32_t* queue, int32_t* qctl, int32_t cell) {
-  __hip_atomic_fetch_add(&qctl[Q_PENDING], 1, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(&qctl[Q_PENDING], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int32_t slot =
-      __hip_atomic_fetch_add(&qctl[Q_ALLOC], 1, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&queue[slot], cell, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&qctl[Q_ALLOC], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&queue[slot], cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int MODE>
@@ -147,20 +204,20 @@ __global__ __launch_bounds__(64) void k_prune_run(const int64_t* rptr, const int
         __hip_atomic_fetch_add(&qctl[Q_HEAD], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if ((int64_t)i >= n_cells) break;
     int32_t c = -1;
-    for (uint32_t spin = 1;; ++spin) {
+    for (uint32_t spin = 0;; ++spin) {
       c = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(&queue[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-      if (c >= 0) break;
-      if ((spin & 15) == 0) {
+          __hip_atomic_load(&queue[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (c >= 0 || c == kSlotDone) break;
+      if ((spin & 63) == 0) {  // rarely: a slot claimed after the sentinels were written
         const int32_t pend = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&qctl[Q_PENDING], __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT));
+            __hip_atomic_load(&qctl[Q_PENDING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (pend == 0) break;
         if (wall_clock64() - t0 > limit) {
           __hip_atomic_fetch_or(&qctl[Q_ERROR], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
       }
-      __builtin_amdgcn_s_sleep(4);
+      __builtin_amdgcn_s_sleep(2);
     }
     if (c < 0) break;
     const int64_t b = rptr[c], e = rptr[c + 1];
@@ -178,15 +235,28 @@ __global__ __launch_bounds__(64) void k_prune_run(const int64_t* rptr, const int
         if (atomicSub(&good[cell], 1) == 1) push_removed(queue, qctl, cell);
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(&qctl[Q_PENDING], -one, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t before = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+        &qctl[Q_PENDING], -one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (before == 1) {
+      // nothing is in flight and nothing can be pushed any more: release the
+      // waves waiting on claimed but empty slots
+      const int32_t a0 = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&qctl[Q_ALLOC], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      int64_t h = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&qctl[Q_HEAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      h = h < n_cells ? h : n_cells;
+      for (int64_t q = a0 + lane; q < h; q += 64)
+        __hip_atomic_store(&queue[q], kSlotDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
 template <int MODE>
 __global__ void k_prune_final(int64_t n_cells, int32_t K, const uint32_t* bits,
                               const int32_t* alive, const int32_t* good, uint8_t* kept,
-                              uint64_t* mask, int32_t W, unsigned long long* nkept) {
+                              uint64_t* mask, int32_t W, unsigned long long* nkept,
+                              const int32_t* qctl, int32_t* err_out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *err_out = qctl[Q_ERROR];
   unsigned long long mine = 0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -217,22 +287,22 @@ int32_t prune_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
   const int64_t n_rows = n_cells * K;
   int32_t rc;
   // reverse CSR
+  const unsigned row_blocks = (unsigned)((n_rows + 255) / 256);
   if ((rc = fill_i32(w.rcur, 0, n_cells, s)) != GIS_OK) return rc;
   if (n_edges > 0) {
-    hipLaunchKernelGGL(k_indegree, dim3(grid_for(n_edges)), dim3(256), 0, s, col, n_edges, w.rcur);
+    hipLaunchKernelGGL(k_indegree, dim3(row_blocks), dim3(256), 0, s, row_ptr, col, n_rows, w.rcur);
     GIS_LAUNCH_CHECK("k_indegree");
   }
   if ((rc = scan_exclusive_i32(w.rcur, w.rptr, n_cells, w.rptr + n_cells, w.scan_tmp, s)) != GIS_OK)
     return rc;
   if ((rc = fill_i32(w.rcur, 0, n_cells, s)) != GIS_OK) return rc;
   if (n_edges > 0) {
-    const int64_t sblocks = (n_rows + 63) / 64 < 16384 ? (n_rows + 63) / 64 : 16384;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)sblocks), dim3(64), 0, s, row_ptr, col, n_rows,
-                       w.rptr, w.rcur, w.rrow);
+    hipLaunchKernelGGL(k_scatter, dim3(row_blocks), dim3(256), 0, s, row_ptr, col, n_rows, w.rptr,
+                       w.rcur, w.rrow);
     GIS_LAUNCH_CHECK("k_scatter");
   }
   // initial state
-  if ((rc = fill_i32(w.qctl, 0, 4, s)) != GIS_OK) return rc;
+  if ((rc = fill_i32(w.qctl, 0, Q_WORDS, s)) != GIS_OK) return rc;
   if ((rc = fill_i32(w.queue, -1, n_cells, s)) != GIS_OK) return rc;
   if (MODE == GIS_ANALYSIS_CONTROLLED) {
     hipLaunchKernelGGL(k_badbits_init, dim3(grid_for((n_rows + 31) / 32)), dim3(256), 0, s, out,
@@ -242,8 +312,8 @@ int32_t prune_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
   hipLaunchKernelGGL((k_prune_init<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr,
                      n_cells, K, (const uint32_t*)w.badbits, w.alive, w.good, w.queue, w.qctl);
   GIS_LAUNCH_CHECK("k_prune_init");
-  // persistent drain: one wave per block, enough waves to keep every CU busy
-  const int64_t waves = n_cells < 4096 ? (n_cells > 0 ? n_cells : 1) : 4096;
+  // persistent drain: one wave per block, two per SIMD
+  const int64_t waves = n_cells < 2048 ? (n_cells > 0 ? n_cells : 1) : 2048;
   hipLaunchKernelGGL((k_prune_run<MODE>), dim3((unsigned)waves), dim3(64), 0, s,
                      (const int64_t*)w.rptr, (const int32_t*)w.rrow, n_cells, K, w.badbits,
                      w.alive, w.good, w.queue, w.qctl);
@@ -251,7 +321,7 @@ int32_t prune_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
   if ((rc = fill_u32((uint32_t*)d_nkept, 0u, 2, s)) != GIS_OK) return rc;
   hipLaunchKernelGGL((k_prune_final<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, n_cells, K,
                      (const uint32_t*)w.badbits, (const int32_t*)w.alive, (const int32_t*)w.good,
-                     kept, mask, W, d_nkept);
+                     kept, mask, W, d_nkept, (const int32_t*)w.qctl, w.err_out);
   GIS_LAUNCH_CHECK("k_prune_final");
   return GIS_OK;
 }

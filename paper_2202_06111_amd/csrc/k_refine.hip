@@ -18,13 +18,6 @@ namespace gis {
 
 namespace {
 
-inline unsigned grid_for(int64_t n) {
-  int64_t nb = (n + 255) / 256;
-  if (nb < 1) nb = 1;
-  if (nb > 8192) nb = 8192;
-  return (unsigned)nb;
-}
-
 // Is finest cell k covered by a kept cell?  (k inside the grid)
 template <int N>
 __device__ __forceinline__ bool covered(const CoverIndex& ci, const int64_t* k) {
@@ -41,181 +34,217 @@ __device__ __forceinline__ bool covered(const CoverIndex& ci, const int64_t* k) 
 }
 
 template <int N>
-__global__ void k_boundary(CoverIndex ci, const uint8_t* level, const int32_t* idx,
-                           int64_t n_cells, const uint8_t* kept, int32_t rule, uint8_t* boundary) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    if (!kept[c]) {
-      boundary[c] = 0;
-      continue;
-    }
-    const int s = ci.lmax - level[c];
-    int64_t lo[N], hi[N], k[N], Nf[N];
+__global__ void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
+                           JobStats* stats) {
+  __shared__ CoverIndex ci;
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  stage_index(&ci, &J.ci);
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  bool bnd = false;
+  if (c < J.n_cells) {
+    const int64_t gc = J.cell_off + c;
+    if (kept[gc]) {
+      const int s = ci.lmax - b.level[gc];
+      int64_t lo[N], hi[N], k[N], Nf[N];
 #pragma unroll
-    for (int d = 0; d < N; ++d) {
-      lo[d] = ((int64_t)idx[c * N + d] << s) - 1;
-      hi[d] = ((int64_t)idx[c * N + d] + 1) << s;
-      k[d] = lo[d];
-      Nf[d] = ci.dims[ci.lmax][d];
-    }
-    bool bnd = false;
-    if (rule == GIS_BOUNDARY_CORNERS) {
-      for (int q = 0; q < (1 << N) && !bnd; ++q) {
-        bool outside = false;
-#pragma unroll
-        for (int d = 0; d < N; ++d) {
-          k[d] = ((q >> (N - 1 - d)) & 1) ? hi[d] : lo[d];
-          outside |= k[d] < 0 || k[d] >= Nf[d];
-        }
-        bnd = outside || !covered<N>(ci, k);
+      for (int d = 0; d < N; ++d) {
+        lo[d] = ((int64_t)b.idx[gc * N + d] << s) - 1;
+        hi[d] = ((int64_t)b.idx[gc * N + d] + 1) << s;
+        k[d] = lo[d];
+        Nf[d] = ci.dims[ci.lmax][d];
       }
-    } else {
-      // every cell of the box [lo, hi] that is on its surface; the interior of
-      // the last dimension is skipped when all other coordinates are inside
-      for (;;) {
-        bool outside = false, inner = true;
+      if (rule == GIS_BOUNDARY_CORNERS) {
+        for (int q = 0; q < (1 << N) && !bnd; ++q) {
+          bool outside = false;
 #pragma unroll
-        for (int d = 0; d < N; ++d) {
-          outside |= k[d] < 0 || k[d] >= Nf[d];
-          if (d < N - 1) inner &= k[d] != lo[d] && k[d] != hi[d];
+          for (int d = 0; d < N; ++d) {
+            k[d] = ((q >> (N - 1 - d)) & 1) ? hi[d] : lo[d];
+            outside |= k[d] < 0 || k[d] >= Nf[d];
+          }
+          bnd = outside || !covered<N>(ci, k);
         }
-        if (outside || !covered<N>(ci, k)) {
-          bnd = true;
-          break;
+      } else {
+        // every cell of the box [lo, hi] that is on its surface; the interior
+        // of the last dimension is skipped when all other coordinates are inside
+        for (;;) {
+          bool outside = false, inner = true;
+#pragma unroll
+          for (int d = 0; d < N; ++d) {
+            outside |= k[d] < 0 || k[d] >= Nf[d];
+            if (d < N - 1) inner &= k[d] != lo[d] && k[d] != hi[d];
+          }
+          if (outside || !covered<N>(ci, k)) {
+            bnd = true;
+            break;
+          }
+          if (inner && k[N - 1] == lo[N - 1]) {
+            k[N - 1] = hi[N - 1];
+            continue;
+          }
+          int d = N - 1;
+          while (d >= 0 && k[d] == hi[d]) {
+            k[d] = lo[d];
+            --d;
+          }
+          if (d < 0) break;
+          ++k[d];
         }
-        if (inner && k[N - 1] == lo[N - 1]) {
-          k[N - 1] = hi[N - 1];
-          continue;
-        }
-        int d = N - 1;
-        while (d >= 0 && k[d] == hi[d]) {
-          k[d] = lo[d];
-          --d;
-        }
-        if (d < 0) break;
-        ++k[d];
       }
     }
-    boundary[c] = bnd ? 1 : 0;
+    boundary[gc] = bnd ? 1 : 0;
   }
+  if (bnd) atomicAdd(&stats[jb].n_boundary, 1ull);
 }
 
 template <int N>
-__global__ void k_next_flags(CoverIndex next, const uint8_t* level, const int32_t* idx,
-                             int64_t n_cells, const uint8_t* kept, const uint8_t* boundary) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    if (!kept[c]) continue;
-    const int L = level[c];
-    if (!boundary[c]) {
-      int64_t lin = 0;
+__global__ void k_next_flags(BatchArgs b, const uint8_t* kept, const uint8_t* boundary) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const CoverIndex& next = J.next;
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c >= J.n_cells || !next.state) return;  // jobs that stopped set no flags
+  const int64_t gc = J.cell_off + c;
+  if (!kept[gc]) return;
+  const int L = b.level[gc];
+  if (!boundary[gc]) {
+    int64_t lin = 0;
 #pragma unroll
-      for (int d = 0; d < N; ++d) lin = lin * next.dims[L][d] + idx[c * N + d];
-      next.state[next.off[L] + lin] = 1;
-      continue;
-    }
-    for (int ch = 0; ch < (1 << N); ++ch) {
-      int64_t lin = 0;
+    for (int d = 0; d < N; ++d) lin = lin * next.dims[L][d] + b.idx[gc * N + d];
+    next.state[next.off[L] + lin] = 1;
+    return;
+  }
+  for (int ch = 0; ch < (1 << N); ++ch) {
+    int64_t lin = 0;
 #pragma unroll
-      for (int d = 0; d < N; ++d)
-        lin = lin * next.dims[L + 1][d] + (2 * (int64_t)idx[c * N + d] + ((ch >> (N - 1 - d)) & 1));
-      next.state[next.off[L + 1] + lin] = 1;
-    }
+    for (int d = 0; d < N; ++d)
+      lin = lin * next.dims[L + 1][d] + (2 * (int64_t)b.idx[gc * N + d] + ((ch >> (N - 1 - d)) & 1));
+    next.state[next.off[L + 1] + lin] = 1;
   }
 }
 
-__global__ void k_compact(CoverIndex next, const int64_t* pos, int64_t cap, uint8_t* level_out,
+// pos: exclusive scan of the batch's flag array (jobs' arrays back to back).
+__global__ void k_compact(BatchArgs b, const int64_t* pos, int64_t cap, uint8_t* level_out,
                           int32_t* idx_out) {
-  const int64_t total = next.off[next.lmax + 1];
-  for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < total;
-       sl += (int64_t)gridDim.x * blockDim.x) {
-    if (!next.state[sl]) continue;
-    const int64_t p = pos[sl];
-    if (p >= cap) continue;
-    int L = 0;
-    while (sl >= next.off[L + 1]) ++L;
-    int64_t rem = sl - next.off[L];
-    level_out[p] = (uint8_t)L;
-    for (int d = next.n - 1; d >= 0; --d) {
-      idx_out[p * next.n + d] = (int32_t)(rem % next.dims[L][d]);
-      rem /= next.dims[L][d];
-    }
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_NEXT, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const CoverIndex& next = J.next;
+  const int64_t sl = (blockIdx.x - J.blk[LK_NEXT]) * blockDim.x + threadIdx.x;
+  if (!next.state || sl >= next.off[next.lmax + 1] || !next.state[sl]) return;
+  const int64_t p = pos[J.next_off + sl];
+  if (p >= cap) return;
+  int L = 0;
+  while (sl >= next.off[L + 1]) ++L;
+  int64_t rem = sl - next.off[L];
+  level_out[p] = (uint8_t)L;
+  for (int d = next.n - 1; d >= 0; --d) {
+    idx_out[p * next.n + d] = (int32_t)(rem % next.dims[L][d]);
+    rem /= next.dims[L][d];
   }
 }
 
-__global__ void k_level_starts(CoverIndex next, const int64_t* pos, int64_t* out) {
+// For every job: its first new cell and the new cells before each level.
+__global__ void k_level_starts(BatchArgs b, const int64_t* pos, JobStats* stats) {
+  const int32_t jb = blockIdx.x;
+  const Job& J = b.jobs[jb];
   const int L = threadIdx.x;
-  if (L <= next.lmax) out[L] = pos[next.off[L]];
+  if (L == 0) stats[jb].next_start = pos[J.next_off];
+  if (L <= J.next.lmax) stats[jb].level_start[L] = pos[J.next_off + J.next.off[L]];
 }
 
-__global__ void k_coarse(GridArgs g, int64_t total, uint8_t* level, int32_t* idx) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rem = c;
-    level[c] = 0;
-    for (int d = g.n - 1; d >= 0; --d) {
-      idx[c * g.n + d] = (int32_t)(rem % g.n0[d]);
-      rem /= g.n0[d];
-    }
+__global__ void k_coarse(BatchArgs b, uint8_t* level, int32_t* idx) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c >= J.n_cells) return;
+  const int64_t gc = J.cell_off + c;
+  int64_t rem = c;
+  level[gc] = 0;
+  for (int d = J.grid.n - 1; d >= 0; --d) {
+    idx[gc * J.grid.n + d] = (int32_t)(rem % J.grid.n0[d]);
+    rem /= J.grid.n0[d];
   }
+}
+
+__global__ void k_count_kept(BatchArgs b, const uint8_t* kept, JobStats* stats) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c < J.n_cells && kept[J.cell_off + c]) atomicAdd(&stats[jb].n_kept, 1ull);
+}
+
+__global__ void k_count_out_rows(BatchArgs b, const uint8_t* out, JobStats* stats) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_ROWS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t r = (blockIdx.x - J.blk[LK_ROWS]) * blockDim.x + threadIdx.x;
+  if (r < J.n_cells * b.K && out[J.cell_off * b.K + r]) atomicAdd(&stats[jb].n_out, 1ull);
 }
 
 }  // namespace
 
-int32_t launch_boundary(const CoverIndex& ci, const GridArgs& g, const uint8_t* level,
-                        const int32_t* idx, int64_t n_cells, const uint8_t* kept, int32_t rule,
-                        uint8_t* boundary, hipStream_t s) {
-  (void)g;
-  if (n_cells == 0) return GIS_OK;
-  switch (ci.n) {
-    case 1: hipLaunchKernelGGL(k_boundary<1>, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx, n_cells, kept, rule, boundary); break;
-    case 2: hipLaunchKernelGGL(k_boundary<2>, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx, n_cells, kept, rule, boundary); break;
-    case 3: hipLaunchKernelGGL(k_boundary<3>, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx, n_cells, kept, rule, boundary); break;
-    case 4: hipLaunchKernelGGL(k_boundary<4>, dim3(grid_for(n_cells)), dim3(256), 0, s, ci, level, idx, n_cells, kept, rule, boundary); break;
-    default: set_error("unsupported dimension"); return GIS_E_UNSUPPORTED;
+#define GIS_DIM_SWITCH(N_, CALL)                                   \
+  switch (N_) {                                                    \
+    case 1: CALL(1); break;                                        \
+    case 2: CALL(2); break;                                        \
+    case 3: CALL(3); break;                                        \
+    case 4: CALL(4); break;                                        \
+    default: set_error("unsupported dimension"); return GIS_E_UNSUPPORTED; \
   }
+
+int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
+                       JobStats* stats, hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+#define GIS_CALL(N) hipLaunchKernelGGL(k_boundary<N>, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, rule, boundary, stats)
+  GIS_DIM_SWITCH(b.n, GIS_CALL)
+#undef GIS_CALL
   GIS_LAUNCH_CHECK("k_boundary");
   return GIS_OK;
 }
 
-int32_t launch_next_flags(const CoverIndex& next, const uint8_t* level, const int32_t* idx,
-                          int64_t n_cells, const uint8_t* kept, const uint8_t* boundary,
-                          hipStream_t s) {
-  int32_t rc = fill_u8(next.state, 0, next.off[next.lmax + 1], s);
-  if (rc != GIS_OK || n_cells == 0) return rc;
-  switch (next.n) {
-    case 1: hipLaunchKernelGGL(k_next_flags<1>, dim3(grid_for(n_cells)), dim3(256), 0, s, next, level, idx, n_cells, kept, boundary); break;
-    case 2: hipLaunchKernelGGL(k_next_flags<2>, dim3(grid_for(n_cells)), dim3(256), 0, s, next, level, idx, n_cells, kept, boundary); break;
-    case 3: hipLaunchKernelGGL(k_next_flags<3>, dim3(grid_for(n_cells)), dim3(256), 0, s, next, level, idx, n_cells, kept, boundary); break;
-    case 4: hipLaunchKernelGGL(k_next_flags<4>, dim3(grid_for(n_cells)), dim3(256), 0, s, next, level, idx, n_cells, kept, boundary); break;
-    default: set_error("unsupported dimension"); return GIS_E_UNSUPPORTED;
-  }
+int32_t batch_next_flags(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
+                         hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+#define GIS_CALL(N) hipLaunchKernelGGL(k_next_flags<N>, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, boundary)
+  GIS_DIM_SWITCH(b.n, GIS_CALL)
+#undef GIS_CALL
   GIS_LAUNCH_CHECK("k_next_flags");
   return GIS_OK;
 }
 
-int32_t launch_compact(const CoverIndex& next, const int64_t* pos, int64_t cap, uint8_t* level_out,
-                       int32_t* idx_out, hipStream_t s) {
-  const int64_t total = next.off[next.lmax + 1];
-  if (total == 0) return GIS_OK;
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(total)), dim3(256), 0, s, next, pos, cap, level_out,
-                     idx_out);
-  GIS_LAUNCH_CHECK("k_compact");
+int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,
+                      int32_t* idx_out, JobStats* stats, hipStream_t s) {
+  if (b.blocks[LK_NEXT] > 0) {
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)b.blocks[LK_NEXT]), dim3(256), 0, s, b, pos, cap,
+                       level_out, idx_out);
+    GIS_LAUNCH_CHECK("k_compact");
+  }
+  if (b.n_jobs > 0) {
+    hipLaunchKernelGGL(k_level_starts, dim3((unsigned)b.n_jobs), dim3(64), 0, s, b, pos, stats);
+    GIS_LAUNCH_CHECK("k_level_starts");
+  }
   return GIS_OK;
 }
 
-int32_t launch_level_starts(const CoverIndex& next, const int64_t* pos, int64_t* out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_level_starts, dim3(1), dim3(64), 0, s, next, pos, out);
-  GIS_LAUNCH_CHECK("k_level_starts");
-  return GIS_OK;
-}
-
-int32_t launch_coarse(const GridArgs& g, uint8_t* level, int32_t* idx, hipStream_t s) {
-  int64_t total = 1;
-  for (int d = 0; d < g.n; ++d) total *= g.n0[d];
-  hipLaunchKernelGGL(k_coarse, dim3(grid_for(total)), dim3(256), 0, s, g, total, level, idx);
+int32_t batch_coarse(const BatchArgs& b, uint8_t* level, int32_t* idx, hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_coarse, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, level, idx);
   GIS_LAUNCH_CHECK("k_coarse");
+  return GIS_OK;
+}
+
+int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stats, hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_count_kept, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept,
+                     stats);
+  GIS_LAUNCH_CHECK("k_count_kept");
+  return GIS_OK;
+}
+
+int32_t batch_count_out(const BatchArgs& b, const uint8_t* out, JobStats* stats, hipStream_t s) {
+  if (b.blocks[LK_ROWS] == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_count_out_rows, dim3((unsigned)b.blocks[LK_ROWS]), dim3(256), 0, s, b, out,
+                     stats);
+  GIS_LAUNCH_CHECK("k_count_out_rows");
   return GIS_OK;
 }
 

@@ -55,6 +55,10 @@ class GraphT(ctypes.Structure):
                 ("cap_edges", I64), ("row_ptr", P), ("col", P), ("out", P)]
 
 
+class JobT(ctypes.Structure):
+    _fields_ = [("sys", SystemT), ("grid", GridT), ("d_u", P)]
+
+
 class RoundStatsT(ctypes.Structure):
     _fields_ = [("n_cells", I64), ("n_rows", I64), ("n_edges", I64), ("n_out", I64),
                 ("n_kept", I64), ("n_boundary", I64), ("n_recheck", I64), ("max_level", I32),
@@ -91,6 +95,7 @@ def lib():
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
             "gis_subdivide": ([P, P, P, P, I32, P, P, P], I32),
             "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
+            "gis_solve_batch": ([P, I32, P, I32, I32, P, P, P], I32),
             "gis_solution_info": ([P, P], I32),
             "gis_solution_export": ([P, P, P, P, P], I32),
             "gis_solution_free": ([P], None),
@@ -110,7 +115,7 @@ def lib():
 
 
 EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_build_graph", "gis_prune", "gis_subdivide",
-            "gis_solve", "gis_solution_info", "gis_solution_export", "gis_solution_free",
+            "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
             "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
             "gis_last_error", "gis_version")
 
@@ -407,3 +412,24 @@ def solve(ctx: Context, system: W.System, grid: W.Grid, u, rounds: int, opts: Op
 
 def solve_workload(ctx: Context, wl: W.Workload, stream=None, **opt_over) -> Solution:
     return solve(ctx, wl.system, wl.grid, wl.u, wl.rounds, workload_opts(wl, **opt_over), stream)
+
+
+def solve_batch(ctx: Context, workloads, stream=None, **opt_over) -> list:
+    """Solves several workloads (same system kind, dimensions, K, rounds and
+    options) through shared launches; returns one Solution per workload."""
+    wls = list(workloads)
+    w0 = wls[0]
+    for w in wls:
+        assert (w.system.kind, w.system.n, w.system.m, w.K, w.rounds) == \
+            (w0.system.kind, w0.system.n, w0.system.m, w0.K, w0.rounds), "incompatible batch"
+    dus = [to_device_u(ctx, w.u) for w in wls]
+    jobs = (JobT * len(wls))()
+    for i, w in enumerate(wls):
+        jobs[i].sys = system_t(w.system)
+        jobs[i].grid = grid_t(w.grid)
+        jobs[i].d_u = _ptr(dus[i])
+    outs = (P * len(wls))()
+    opts = workload_opts(w0, **opt_over)
+    _check(lib().gis_solve_batch(ctx.handle, len(wls), jobs, w0.K, w0.rounds, ctypes.byref(opts),
+                                 outs, _stream_ptr(stream)))
+    return [Solution(P(outs[i]), ctx.device) for i in range(len(wls))]

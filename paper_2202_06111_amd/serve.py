@@ -1,0 +1,183 @@
+"""Continuous-batching serving loop for GIS solves.
+
+Requests (a system, a state box, a grid, an input set, and a batch of query
+states) arrive on a Poisson clock.  A request is admitted when a slot is free
+and its estimated device memory fits in the budget still free; admitted
+requests run concurrently, each slot owning a libgis context and its own HIP
+stream, so their kernels overlap on the device (the library releases the GIL
+inside every call).  A solve's result stays on the device until its
+membership and admissible-input queries are answered.  Latency is measured
+from the request's arrival to the answer of its last query.
+"""
+from __future__ import annotations
+
+import dataclasses
+import statistics
+import threading
+import time
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import gis
+from . import workloads as W
+
+
+def estimate_bytes(wl: W.Workload, edges_per_row: float = 8.0) -> int:
+    """Device memory one solve of `wl` needs at its largest round (upper
+    estimate): per row the ranges, counts, OUT flag, CSR offsets, edges and
+    reverse edges; per cell the list, index and prune state."""
+    cells = int(np.prod(wl.grid.n0)) << (wl.grid.n * max(wl.rounds, 0))
+    rows = cells * wl.K
+    per_row = 2 * 4 * wl.grid.n + 4 + 1 + 8 + 8 + 8 * edges_per_row
+    per_cell = 1 + 4 * wl.grid.n + 5 + 32 + 8 * ((wl.K + 63) // 64)
+    return int(rows * per_row + cells * per_cell + (1 << 20))
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival_s: float
+    start_s: float
+    done_s: float
+    slot: int
+    n_cells: int
+    n_kept: int
+    member: np.ndarray
+    admissible: np.ndarray
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class Admission:
+    """Slots plus a device-memory budget.  admit() blocks until a slot is free
+    and the request's estimate fits in what is left of the budget (a request
+    larger than the whole budget is admitted alone)."""
+
+    def __init__(self, n_slots: int, budget_bytes: int):
+        self.budget = int(budget_bytes)
+        self._cv = threading.Condition()
+        self._in_use = 0
+        self._free = list(range(n_slots))
+        self.max_in_use = 0
+        self.deferred = 0
+
+    def admit(self, need: int) -> int:
+        need = min(int(need), self.budget)
+        with self._cv:
+            waited = False
+            while not self._free or self._in_use + need > self.budget:
+                waited = True
+                self._cv.wait()
+            self.deferred += int(waited)
+            self._in_use += need
+            self.max_in_use = max(self.max_in_use, self._in_use)
+            return self._free.pop()
+
+    def release(self, slot: int, need: int) -> None:
+        need = min(int(need), self.budget)
+        with self._cv:
+            self._in_use -= need
+            self._free.append(slot)
+            self._cv.notify_all()
+
+    @property
+    def in_use(self) -> int:
+        with self._cv:
+            return self._in_use
+
+
+class Server:
+    def __init__(self, n_slots: int = 4, mem_budget_bytes: int = 8 << 30, device: int = 0):
+        self.n_slots = n_slots
+        self.device = device
+        self.adm = Admission(n_slots, mem_budget_bytes)
+        self.ctxs = [gis.Context(device) for _ in range(n_slots)]
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_slots)]
+
+    def close(self) -> None:
+        for c in self.ctxs:
+            c.close()
+
+    # -------------------------------------------------------------- one request
+    def _serve_one(self, slot: int, req: W.ServeRequest, t0: float) -> Result:
+        ctx, stream = self.ctxs[slot], self.streams[slot]
+        start = time.perf_counter() - t0
+        wl = req.workload
+        with torch.cuda.stream(stream):
+            du = gis.to_device_u(ctx, wl.u)
+            sol = gis.solve(ctx, wl.system, wl.grid, du, wl.rounds, gis.workload_opts(wl), stream)
+            try:
+                states = torch.as_tensor(req.queries, device=ctx.dev)
+                kinds = torch.as_tensor(req.kinds, device=ctx.dev)
+                mem_idx = torch.nonzero(kinds == 0).squeeze(1)
+                adm_idx = torch.nonzero(kinds == 1).squeeze(1)
+                member = sol.query_membership(states.index_select(0, mem_idx).contiguous(), stream)
+                adm = sol.query_admissible(states.index_select(0, adm_idx).contiguous(), stream)
+                member_h = member.cpu().numpy()
+                adm_h = adm.cpu().numpy().view(np.uint64)
+                info = sol.info()
+            finally:
+                sol.free()
+        done = time.perf_counter() - t0
+        return Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"], info["n_kept"],
+                      member_h, adm_h)
+
+    def run(self, requests: List[W.ServeRequest], realtime: bool = True) -> dict:
+        """Serves the stream; returns per-request results and summary stats."""
+        results: List[Optional[Result]] = [None] * len(requests)
+        errors: List[BaseException] = []
+        t0 = time.perf_counter()
+        torch.cuda.synchronize(self.device)
+
+        def worker(i: int, slot: int, need: int) -> None:
+            try:
+                results[i] = self._serve_one(slot, requests[i], t0)
+            except BaseException as e:  # reported after the run
+                errors.append(e)
+            finally:
+                self.adm.release(slot, need)
+
+        threads = []
+        for i, req in enumerate(requests):
+            if realtime:
+                delay = req.arrival_s - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            need = estimate_bytes(req.workload)
+            slot = self.adm.admit(need)
+            th = threading.Thread(target=worker, args=(i, slot, need), daemon=True)
+            th.start()
+            threads.append(th)
+        for th in threads:
+            th.join()
+        wall = time.perf_counter() - t0
+        if errors:
+            raise errors[0]
+        lat = sorted(r.latency_s for r in results)
+        q = sum(len(r.member) + len(r.admissible) for r in results)
+        return {
+            "results": results,
+            "wall_s": wall,
+            "solves_per_s": len(results) / wall,
+            "queries_per_s": q / wall,
+            "latency_ms": {"p50": 1e3 * statistics.median(lat),
+                           "p99": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+                           "max": 1e3 * lat[-1]},
+            "max_bytes_in_use": self.adm.max_in_use,
+            "budget_bytes": self.adm.budget,
+            "deferred": self.adm.deferred,
+        }
+
+
+def serve_alone(requests: List[W.ServeRequest], device: int = 0) -> List[Result]:
+    """Each request solved and queried by itself, one after the other."""
+    srv = Server(n_slots=1, device=device)
+    try:
+        t0 = time.perf_counter()
+        return [srv._serve_one(0, r, t0) for r in requests]
+    finally:
+        srv.close()

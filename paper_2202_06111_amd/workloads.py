@@ -168,17 +168,27 @@ class ServeRequest:
     rid: int
     arrival_s: float
     workload: Workload
-    queries: np.ndarray      # Q x n float64 states
-    kinds: np.ndarray        # Q uint8: 0 membership, 1 admissible-input mask
+    n_queries: int
+    query_seed: int
+
+    @property
+    def queries(self) -> np.ndarray:
+        """n_queries x n float64 states, uniform in the request's box (seeded)."""
+        return query_states(self.workload.grid, self.n_queries, seed=self.query_seed)
+
+    @property
+    def kinds(self) -> np.ndarray:
+        """Query kinds alternating 0 (membership) and 1 (admissible-input mask)."""
+        return (np.arange(self.n_queries) % 2).astype(np.uint8)
 
 
 def serving_stream(n_requests: int, rate_per_s: float, seed: int = 0,
                    n_queries: int = 100_000,
                    sides: Sequence[int] = (32, 64, 128, 256)) -> list:
     """Poisson arrivals of Van der Pol solves with mu ~ U[0.5, 2], box scale
-    ~ U[0.6, 1], grid side uniform over `sides`, 11 inputs, and n_queries
-    uniform query states in the request's box alternating between the two
-    query kinds."""
+    ~ U[0.6, 1], grid side uniform over `sides`, 11 inputs on [-1, 1], and
+    n_queries uniform query states in the request's box alternating between
+    the two query kinds (generated on demand from the recorded seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
     reqs = []
@@ -190,9 +200,7 @@ def serving_stream(n_requests: int, rate_per_s: float, seed: int = 0,
         lo, hi = scaled_vdp_box(s)
         wl = Workload(f"serve_{rid}", vdp(mu=mu), Grid((side, side), lo, hi),
                       evenly_spaced(-1.0, 1.0, 11), LATTICE3, 0, "fp64")
-        q = query_states(wl.grid, n_queries, seed=seed * 1_000_003 + rid + 1)
-        kinds = (np.arange(n_queries) % 2).astype(np.uint8)
-        reqs.append(ServeRequest(rid, t, wl, q, kinds))
+        reqs.append(ServeRequest(rid, t, wl, n_queries, seed * 1_000_003 + rid + 1))
     return reqs
 
 

@@ -333,3 +333,55 @@ def test_abi_error_paths(G, ctx):
     mask = torch.empty(level.shape[0], dtype=torch.int64, device=ctx.dev)
     assert L.gis_prune(ctx.handle, ctypes.byref(gg), level.shape[0], u.shape[0], 1, G._ptr(kept),
                        G._ptr(mask), None, s) == 1
+
+
+# ------------------------------------------------------------------ batches
+def _batch_workloads(kind):
+    rng = np.random.Generator(np.random.PCG64(77))
+    out = []
+    if kind == "vdp_uniform":          # rounds 0, mixed grid sizes and boxes
+        for i, side in enumerate((16, 40, 24, 64, 8)):
+            s = rng.uniform(0.6, 1.0)
+            out.append(W.Workload(f"b{i}", W.vdp(mu=rng.uniform(0.5, 2.0)),
+                                  W.Grid((side, side + 3), *W.scaled_vdp_box(s)),
+                                  W.evenly_spaced(-1, 1, 11), W.LATTICE3, 0, "fp64"))
+    elif kind == "vdp_controlled_r2":  # the small jobs keep nothing and stop after round 0
+        for i, side in enumerate((8, 48, 12, 56)):
+            out.append(W.Workload(f"c{i}", W.vdp(mu=rng.uniform(0.8, 1.2)),
+                                  W.Grid((side, side), *W.VDP_BOX),
+                                  W.evenly_spaced(-1, 1, 9), W.LATTICE3, 2, "fp64"))
+    else:                              # adaptive, non-leaving analysis, several levels
+        prec = "fp32_recheck" if kind == "vdp_adaptive32" else "fp64"
+        for i, side in enumerate((12, 32, 20, 4)):
+            out.append(W.Workload(f"a{i}", W.vdp(mu=rng.uniform(0.5, 2.0)),
+                                  W.Grid((side, side), *W.VDP_BOX),
+                                  W.evenly_spaced(-1, 1, 7), W.LATTICE3, 3, prec,
+                                  analysis="nonleaving"))
+    return out
+
+
+@pytest.mark.parametrize("kind", ["vdp_uniform", "vdp_controlled_r2", "vdp_adaptive",
+                                  "vdp_adaptive32"])
+def test_batch_equals_single_solves_and_oracle(G, ctx, kind):
+    wls = _batch_workloads(kind)
+    sols = G.solve_batch(ctx, wls)
+    for wl, sol in zip(wls, sols):
+        got = [_np(t) for t in sol.export()]
+        single = [_np(t) for t in G.solve_workload(ctx, wl).export()]
+        for a, b in zip(got, single):
+            np.testing.assert_array_equal(a, b, err_msg=wl.name)
+        want = _oracle_solve(wl)
+        np.testing.assert_array_equal(got[0], want["level"])
+        np.testing.assert_array_equal(got[1], want["idx"])
+        np.testing.assert_array_equal(got[2], want["kept"])
+        np.testing.assert_array_equal(got[3].view(np.uint64), want["mask"])
+        info = sol.info()
+        assert info["n_rounds"] == len(want["stats"]), wl.name
+        for got_r, want_r in zip(info["rounds"], want["stats"]):
+            for k in ("n_cells", "n_rows", "n_edges", "n_out", "n_kept"):
+                assert got_r[k] == want_r[k], (wl.name, k, got_r, want_r)
+        states = torch.as_tensor(W.query_states(wl.grid, 3000, seed=3, margin=0.02), device=ctx.dev)
+        m_w, a_w = oracle.query(wl.grid, want["level"], want["idx"], want["kept"], want["mask"],
+                                states.cpu().numpy())
+        np.testing.assert_array_equal(_np(sol.query_membership(states)), m_w)
+        np.testing.assert_array_equal(_np(sol.query_admissible(states)).view(np.uint64), a_w)
