@@ -458,6 +458,10 @@ int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* i
   const int64_t n_rows = B.total_cells * B.K;
   const int64_t nb = B.blocks[LK_ROWS];
   int32_t rc;
+  if (n_rows > (int64_t)INT32_MAX) {  // row and cell ids are 32-bit
+    set_error("a batch of more than 2^31-1 (cell, input) rows is not supported");
+    return GIS_E_UNSUPPORTED;
+  }
   if ((rc = ensure(ctx->rng, (size_t)n_rows * 2 * B.n * 4 + 16))) return rc;
   if ((rc = ensure(ctx->cnt, (size_t)n_rows * 4 + 16))) return rc;
   if ((rc = ensure(ctx->bsum, (size_t)nb * 8 + 16))) return rc;
@@ -513,6 +517,10 @@ int32_t run_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, cons
   const int64_t n_rows = n_cells * K;
   const int32_t W = (K + 63) / 64;
   int32_t rc;
+  if (n_rows > (int64_t)INT32_MAX) {  // the reverse CSR stores 32-bit row ids
+    set_error("a graph of more than 2^31-1 rows is not supported");
+    return GIS_E_UNSUPPORTED;
+  }
   if ((rc = ensure(ctx->rptr, (size_t)(n_cells + 1) * 8))) return rc;
   if ((rc = ensure(ctx->rrow, (size_t)n_edges * 4 + 16))) return rc;
   if ((rc = ensure(ctx->rcur, (size_t)n_cells * 4 + 16))) return rc;
