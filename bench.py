@@ -7,8 +7,13 @@ cells.  The reported value is (cell x input) rows imaged per second of
 wall-clock over the timed steps; inputs are resident on the device before the
 timed region starts.
 
+A second measurement, "serving", runs the mixed stream of smaller solves
+(with their membership and admissible-input queries) through the
+continuous-batching server and reports solves/s and p50/p99 latency.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--precision fp64|fp32_recheck] [--no-cpu-baseline]
+                       [--serve-requests N]
 Prints one JSON line on stdout.
 """
 import argparse
@@ -38,6 +43,11 @@ def parse():
     p.add_argument("--precision", default=None, help="fp64 or fp32_recheck (default: workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-budget-s", type=float, default=12.0)
+    p.add_argument("--serve-requests", type=int, default=64,
+                   help="requests per pass of the serving measurement (0: skip it)")
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="first run one plain device-to-device copy of this many MiB, as the "
+                        "reference kernel for scaling HBM byte counters")
     return p.parse_args()
 
 
@@ -58,6 +68,29 @@ def cpu_baseline(wl, budget_s):
             "sample": f"{reps} whole solve(s) of {wl.name} in {el:.1f} s, single thread"}
 
 
+def serving(n_req):
+    """The serving mix (Van der Pol solves with mu ~ U[0.5, 2], box scale ~ U[0.6, 1],
+    grids 32^2..256^2, 11 inputs, 10^5 queries each) through the continuous-batching
+    server: first all requests at once (saturation throughput), then a Poisson
+    stream at 0.7x that rate (latency)."""
+    from paper_2202_06111_amd import serve
+    from paper_2202_06111_amd import workloads as W
+    srv = serve.Server(n_slots=4, mem_budget_bytes=32 << 30)
+    try:
+        srv.run(W.serving_stream(8, 1e6, seed=99), realtime=False)  # warm-up
+        sat = srv.run(W.serving_stream(n_req, 1e6, seed=0), realtime=False)
+        rate = 0.7 * sat["solves_per_s"]
+        lat = srv.run(W.serving_stream(n_req, rate, seed=1), realtime=True)
+    finally:
+        srv.close()
+    return {"requests_per_pass": n_req, "queries_per_request": 100_000, "slots": 4,
+            "saturation": {"solves_per_s": sat["solves_per_s"],
+                           "queries_per_s": sat["queries_per_s"],
+                           "mean_batch": sat["mean_batch"], "latency_ms": sat["latency_ms"]},
+            "poisson": {"rate_per_s": rate, "solves_per_s": lat["solves_per_s"],
+                        "mean_batch": lat["mean_batch"], "latency_ms": lat["latency_ms"]}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -72,6 +105,13 @@ def main():
         sys.exit(f"unknown workload {a.workload}; choose from {sorted(W.ALL)}")
     wl = W.ALL[a.workload]()
     precision = a.precision or wl.precision
+    if a.copy_calibration_mib > 0:
+        n = a.copy_calibration_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = gis.Context(0)
     du = gis.to_device_u(ctx, wl.u)
     opts = gis.workload_opts(wl, precision=precision, timing=True)
@@ -121,21 +161,23 @@ def main():
                    "final_kept": last["n_kept"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
-                     "kernel": "k_count_%s (image + bbox + cover + count)" %
-                               ("f64" if precision == "fp64" else "f32"),
+                     "kernel": "k_build<%s> (images + boxes + cover + CSR emit, one pass)" %
+                               ("fp64" if precision == "fp64" else "fp32+fp64 recheck"),
                      "avg_launch_ms": img_ms / max(launches, 1),
                      "flops_per_row": flops_row},
         "phases_ms_per_solve": {
             k: sum(r[k] for inf in infos for r in inf["rounds"]) / a.steps
-            for k in ("ms_build", "ms_image", "ms_recheck", "ms_prune", "ms_subdivide")},
+            for k in ("ms_build", "ms_image", "ms_prune", "ms_subdivide")},
         "recheck_rows_per_solve": sum(r["n_recheck"] for inf in infos for r in inf["rounds"]) / a.steps,
         "solves_per_s": a.steps / el,
         "latency_ms": {"p50": 1e3 * statistics.median(lat),
                        "p99": 1e3 * sorted(lat)[min(len(lat) - 1, int(0.99 * len(lat)))]},
     }
+    ctx.close()
+    if a.serve_requests > 0:
+        res["serving"] = serving(a.serve_requests)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, a.cpu_budget_s)
-    ctx.close()
     print(json.dumps(res))
 
 

@@ -104,8 +104,10 @@ typedef struct gis_opts {
   int32_t fast_out;       /* nonzero: OUT rows get no edges (analysis results unchanged) */
   int32_t timing;         /* nonzero: time the image kernels with HIP events (gis_round_stats) */
   int32_t reserved[2];
-  double band[4];         /* absolute recheck band per dimension; 0 = calibrate (see
-                             gis_calibrate_band) */
+  double band[4];         /* absolute recheck band per dimension; 0 = gis_solve calibrates
+                             it on the round-0 covering (every row, or an evenly strided
+                             sample of about 2^20 rows of larger coverings; see
+                             gis_calibrate_band, which takes every row) */
 } gis_opts;
 
 /* A cell list in device memory. */
@@ -135,7 +137,9 @@ typedef struct gis_round_stats {
   int64_t n_cells, n_rows, n_edges, n_out, n_kept, n_boundary, n_recheck;
   int32_t max_level, reserved;
   double ms_build, ms_prune, ms_subdivide;   /* device time between HIP events */
-  double ms_image, ms_recheck;               /* image kernel / FP64 recheck kernel (opts.timing) */
+  double ms_image;    /* the one-pass build kernel: images, boxes, cover, FP64 recheck of the
+                         rows that need it, CSR emit (opts.timing) */
+  double ms_recheck;  /* 0: the recheck runs inside the build kernel */
 } gis_round_stats;
 
 #define GIS_MAX_ROUNDS 32

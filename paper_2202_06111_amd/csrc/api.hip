@@ -24,8 +24,9 @@ int32_t hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? GIS_E_NOMEM : GIS_E_HIP;
 }
 
-int32_t ensure(DevBuf& b, size_t bytes) {
+int32_t ensure(DevBuf& b, size_t bytes, bool* fresh) {
   if (bytes <= b.bytes && b.ptr) return GIS_OK;
+  if (fresh) *fresh = true;
   release(b);
   size_t want = bytes + bytes / 4 + 256;
   hipError_t e = hipMalloc(&b.ptr, want);
@@ -55,7 +56,8 @@ struct Counters {
   uint32_t err;
   uint32_t maxlevel;
   int64_t n_next;
-  int32_t qctl[4];
+  int32_t sweep_last;  // analysis: 1 + index of the last sweep that removed a cell
+  int32_t fcount[2];   // analysis: frontier list lengths
 };
 
 // Pinned host staging of a device array of T.
@@ -86,15 +88,24 @@ using namespace gis;
 
 struct gis_ctx {
   int device = 0;
+  // counters, then (at kStatsOff) the per-job stats: cleared by one fill and
+  // read back by one copy per phase
   DevBuf counters;
-  Counters* h_counters = nullptr;  // pinned
-  DevBuf jobs, stats, maxerr;
+  Pinned<uint8_t> h_cs;            // pinned mirror of `counters`
+  Counters* h_counters = nullptr;  // views into h_cs
+  JobStats* h_stats = nullptr;
+  DevBuf jobs, maxerr;
   Pinned<Job> h_jobs;
-  Pinned<JobStats> h_stats;
   Pinned<unsigned long long> h_maxerr;
-  DevBuf rng, cnt, bsum, bscan, recheck, scan_tmp;
+  // buffers kept in their initial state between calls by the kernels
+  // themselves (look-back words tagged by epoch; prune cursors and queue;
+  // next-covering flags); a flag is false when that may not hold
+  uint32_t lb_epoch = 0;
+  bool lb_clean = false, prune_clean = false, next_clean = false;
+  int32_t first_sweeps = 0;  // sweeps of the last enqueue_prune
+  DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_id, next_state, pos;
-  DevBuf rptr, rrow, rcur, good, alive, badbits, queue, qctl;
+  DevBuf removed, rptr, rrow, rcur, rowbad, cand, front;
   DevBuf bnd;
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
@@ -232,7 +243,21 @@ int32_t layout_index(CoverIndex& ci, const GridArgs& g, int lmax) {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+constexpr size_t kStatsOff = 256;  // byte offset of the job stats behind the counters
+static_assert(sizeof(Counters) <= kStatsOff, "counters overlap the job stats");
+
 Counters* dcnt(gis_ctx* ctx) { return (Counters*)ctx->counters.ptr; }
+JobStats* dstats(gis_ctx* ctx) { return (JobStats*)((char*)ctx->counters.ptr + kStatsOff); }
+
+// Room for the counters and the stats of n_jobs jobs, on both sides.
+int32_t ensure_counters(gis_ctx* ctx, int n_jobs) {
+  const size_t bytes = kStatsOff + sizeof(JobStats) * (size_t)(n_jobs + 1);
+  int32_t rc;
+  if ((rc = ensure(ctx->counters, bytes)) || (rc = ctx->h_cs.ensure(bytes))) return rc;
+  ctx->h_counters = (Counters*)ctx->h_cs.h;
+  ctx->h_stats = (JobStats*)(ctx->h_cs.h + kStatsOff);
+  return GIS_OK;
+}
 
 int32_t zero_counters(gis_ctx* ctx, hipStream_t s) {
   return fill_u32((uint32_t*)ctx->counters.ptr, 0u, (int64_t)(sizeof(Counters) / 4), s);
@@ -260,6 +285,7 @@ struct Batch {
   std::vector<Job> jobs;
   std::vector<int> lmax;
   int64_t total_cells = 0;
+  int64_t total_slots = 0;   // index slots of the jobs with index arrays
   int64_t blocks[LK_KINDS] = {0, 0, 0, 0};
   Job* d_jobs = nullptr;
   JobStats* d_stats = nullptr;
@@ -291,11 +317,10 @@ int32_t batch_init(gis_ctx* ctx, Batch& B, const std::vector<JobSpec>& specs, in
   }
   int32_t rc;
   if ((rc = ensure(ctx->jobs, sizeof(Job) * (size_t)(B.n_jobs + 1)))) return rc;
-  if ((rc = ensure(ctx->stats, sizeof(JobStats) * (size_t)(B.n_jobs + 1)))) return rc;
+  if ((rc = ensure_counters(ctx, B.n_jobs))) return rc;
   if ((rc = ctx->h_jobs.ensure(B.n_jobs + 1))) return rc;
-  if ((rc = ctx->h_stats.ensure(B.n_jobs + 1))) return rc;
   B.d_jobs = (Job*)ctx->jobs.ptr;
-  B.d_stats = (JobStats*)ctx->stats.ptr;
+  B.d_stats = dstats(ctx);
   return GIS_OK;
 }
 
@@ -346,13 +371,16 @@ int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells
     next_off += nslots;
   }
   B.total_cells = cell_off;
+  B.total_slots = slot_off;
   for (int k = 0; k < LK_KINDS; ++k) B.blocks[k] = blk[k];
   if (slot_off > 0) {
     if ((rc = ensure(ctx->idx_state, (size_t)slot_off))) return rc;
     if ((rc = ensure(ctx->idx_id, (size_t)slot_off * 4))) return rc;
   }
   if (next_off > 0) {
-    if ((rc = ensure(ctx->next_state, (size_t)next_off + 16))) return rc;
+    bool fresh = false;
+    if ((rc = ensure(ctx->next_state, (size_t)next_off + 16, &fresh))) return rc;
+    if (fresh) ctx->next_clean = false;
     if ((rc = ensure(ctx->pos, (size_t)(next_off + 1) * 8))) return rc;
     if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(next_off)))) return rc;
   }
@@ -377,14 +405,19 @@ int64_t next_total(const Batch& B) {
   return t;
 }
 
-int32_t zero_stats(const Batch& B, hipStream_t s) {
-  return fill_u32((uint32_t*)B.d_stats, 0u, (int64_t)(sizeof(JobStats) * B.n_jobs / 4), s);
+// Clears the counters and the batch's job stats (one fill).
+int32_t zero_all(gis_ctx* ctx, const Batch& B, hipStream_t s) {
+  return fill_u32((uint32_t*)ctx->counters.ptr, 0u,
+                  (int64_t)((kStatsOff + sizeof(JobStats) * B.n_jobs) / 4), s);
 }
 
+// Copies the counters and the batch's job stats to the host (one copy) and
+// synchronises.
 int32_t sync_stats(gis_ctx* ctx, const Batch& B, hipStream_t s) {
-  GIS_HIP(hipMemcpyAsync(ctx->h_stats.h, B.d_stats, sizeof(JobStats) * B.n_jobs,
+  GIS_HIP(hipMemcpyAsync(ctx->h_cs.h, ctx->counters.ptr, kStatsOff + sizeof(JobStats) * B.n_jobs,
                          hipMemcpyDeviceToHost, s));
-  return sync_counters(ctx, s);
+  GIS_HIP(hipStreamSynchronize(s));
+  return GIS_OK;
 }
 
 // Builds every job's covering index (or checks full level-0 grids).  With
@@ -409,6 +442,7 @@ struct Graph {
   int64_t cap_edges;
   int64_t n_edges, n_out, n_recheck;
   float ms_image, ms_recheck;   // with opts.timing
+  bool timed;
 };
 
 BuildArgs build_args(gis_ctx* ctx, const Batch& B, const uint8_t* level, const int32_t* idx,
@@ -422,39 +456,25 @@ BuildArgs build_args(gis_ctx* ctx, const Batch& B, const uint8_t* level, const i
   a.kind = B.n_jobs ? B.jobs[0].sys.kind : 0;
   a.n = B.n;
   a.n_blocks = B.blocks[LK_ROWS];
+  a.total_rows = B.total_cells * B.K;
+  a.all_uniform = 1;
+  for (const Job& J : B.jobs) a.all_uniform &= J.ci.uniform || J.n_cells == 0 ? 1 : 0;
   a.level = level;
   a.idx = idx;
-  a.rng = (int32_t*)ctx->rng.ptr;
-  a.cnt = (int32_t*)ctx->cnt.ptr;
-  a.bsum = (int64_t*)ctx->bsum.ptr;
-  a.recheck = (int64_t*)ctx->recheck.ptr;
-  a.n_recheck = &dcnt(ctx)->n_recheck;
+  a.n_recheck = (unsigned long long*)&dcnt(ctx)->n_recheck;
+  a.d_total = &dcnt(ctx)->total_edges;
+  a.err = &dcnt(ctx)->err;
   a.stats = B.d_stats;
   return a;
 }
 
-EmitArgs emit_args(gis_ctx* ctx, const Batch& B, const Graph& gr) {
-  EmitArgs e{};
-  e.jobs = B.d_jobs;
-  e.n_jobs = B.n_jobs;
-  e.K = B.K;
-  e.n = B.n;
-  e.n_blocks = B.blocks[LK_ROWS];
-  e.total_rows = B.total_cells * B.K;
-  e.rng = (const int32_t*)ctx->rng.ptr;
-  e.cnt = (const int32_t*)ctx->cnt.ptr;
-  e.bscan = (const int64_t*)ctx->bscan.ptr;
-  e.cap_edges = gr.cap_edges;
-  e.row_ptr = gr.row_ptr;
-  e.col = gr.col;
-  return e;
-}
-
-// count -> (recheck) -> scan -> emit over the whole batch; `col` may be too
-// small (then only the counts are valid).  Synchronises; per-job figures in
-// ctx->h_stats.
-int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
-                  const gis_opts* o, Graph& gr, hipStream_t s) {
+// The symbolic image of the whole batch in one launch, enqueued only: the
+// caller has cleared the counters and the job stats and synchronises before
+// finish_build.  `col` may be too small (then only row_ptr, the OUT flags and
+// the edge totals are valid, and the device edge total says how much is
+// needed).
+int32_t enqueue_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
+                      const gis_opts* o, Graph& gr, hipStream_t s) {
   const int64_t n_rows = B.total_cells * B.K;
   const int64_t nb = B.blocks[LK_ROWS];
   int32_t rc;
@@ -462,122 +482,217 @@ int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* i
     set_error("a batch of more than 2^31-1 (cell, input) rows is not supported");
     return GIS_E_UNSUPPORTED;
   }
-  if ((rc = ensure(ctx->rng, (size_t)n_rows * 2 * B.n * 4 + 16))) return rc;
-  if ((rc = ensure(ctx->cnt, (size_t)n_rows * 4 + 16))) return rc;
-  if ((rc = ensure(ctx->bsum, (size_t)nb * 8 + 16))) return rc;
-  if ((rc = ensure(ctx->bscan, (size_t)nb * 8 + 16))) return rc;
-  if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(nb > B.total_cells ? nb : B.total_cells + 1))))
-    return rc;
-  if (o->precision == GIS_PREC_FP32_RECHECK && (rc = ensure(ctx->recheck, (size_t)n_rows * 8 + 16)))
-    return rc;
-  if ((rc = zero_counters(ctx, s))) return rc;
-  if ((rc = zero_stats(B, s))) return rc;
+  // the block ticket (on its own 128-byte line), then the look-back words;
+  // both are left ready for the next launch by the kernel itself, so they
+  // are cleared only when fresh, after a launch that did not complete, or
+  // when the 24-bit epoch wraps
+  bool fresh = false;
+  if ((rc = ensure(ctx->lookback, (size_t)(nb + 16) * 8, &fresh))) return rc;
+  if (fresh || !ctx->lb_clean || ctx->lb_epoch >= (1u << 24) - 1) {
+    if ((rc = fill_u32((uint32_t*)ctx->lookback.ptr, 0u, (int64_t)(ctx->lookback.bytes / 4), s)))
+      return rc;
+    ctx->lb_epoch = 0;
+  }
+  ctx->lb_epoch += 1;
+  ctx->lb_clean = false;  // until finish_build has seen the launch complete
   BuildArgs a = build_args(ctx, B, level, idx, o);
   a.out = gr.out;
+  a.row_ptr = gr.row_ptr;
+  a.col = gr.col;
+  a.cap_edges = gr.cap_edges;
+  a.ticket = (uint32_t*)ctx->lookback.ptr;
+  a.lb = (uint64_t*)ctx->lookback.ptr + 16;
+  a.epoch = ctx->lb_epoch;
   KernelTimer& tm = ctx->timer;
-  const bool timing = o->timing && tm.ok;
-  if (timing) GIS_HIP(hipEventRecord(tm.ev[0], s));
-  if ((rc = launch_count(a, o->precision, s))) return rc;
-  if (timing) GIS_HIP(hipEventRecord(tm.ev[1], s));
-  if (o->precision == GIS_PREC_FP32_RECHECK && (rc = launch_recheck(a, s))) return rc;
-  if (timing) GIS_HIP(hipEventRecord(tm.ev[2], s));
-  if ((rc = scan_exclusive_i64((const int64_t*)ctx->bsum.ptr, (int64_t*)ctx->bscan.ptr, nb,
-                               &dcnt(ctx)->total_edges, ctx->scan_tmp.ptr, s)))
-    return rc;
-  if ((rc = launch_emit(emit_args(ctx, B, gr), s))) return rc;
+  gr.timed = o->timing && tm.ok;
+  if (gr.timed) GIS_HIP(hipEventRecord(tm.ev[0], s));
+  if ((rc = launch_build(a, o->precision, s))) return rc;
+  if (gr.timed) GIS_HIP(hipEventRecord(tm.ev[1], s));
   if (n_rows == 0 && (rc = fill_i64(gr.row_ptr, 0, 1, s))) return rc;
-  if ((rc = launch_job_edges(B.d_jobs, B.n_jobs, B.K, gr.row_ptr, B.d_stats, s))) return rc;
-  if ((rc = batch_count_out(B.args(level, idx), gr.out, B.d_stats, s))) return rc;
-  if ((rc = sync_stats(ctx, B, s))) return rc;
+  return GIS_OK;
+}
+
+// Build figures after the stream was synchronised (counters and job stats
+// copied to the host).
+int32_t finish_build(gis_ctx* ctx, const Batch& B, Graph& gr) {
   gr.n_edges = ctx->h_counters->total_edges;
   gr.n_recheck = ctx->h_counters->n_recheck;
   gr.n_out = 0;
-  for (int j = 0; j < B.n_jobs; ++j) gr.n_out += (int64_t)ctx->h_stats.h[j].n_out;
+  for (int j = 0; j < B.n_jobs; ++j) gr.n_out += (int64_t)ctx->h_stats[j].n_out;
   gr.ms_image = gr.ms_recheck = 0.f;
-  if (timing) {
-    GIS_HIP(hipEventElapsedTime(&gr.ms_image, tm.ev[0], tm.ev[1]));
-    GIS_HIP(hipEventElapsedTime(&gr.ms_recheck, tm.ev[1], tm.ev[2]));
+  if (gr.timed) GIS_HIP(hipEventElapsedTime(&gr.ms_image, ctx->timer.ev[0], ctx->timer.ev[1]));
+  if (ctx->h_counters->err & 256u) {
+    set_error("graph build: a block's look-back wait reached its time limit");
+    return GIS_E_INTERNAL;
   }
+  if (ctx->h_counters->err & 512u) {
+    set_error("graph build: more than 2^38 edges");
+    return GIS_E_UNSUPPORTED;
+  }
+  ctx->lb_clean = true;
   return GIS_OK;
 }
 
-// Re-runs only the emitter and the per-job edge totals after col grew;
-// synchronises.
-int32_t rerun_emit(gis_ctx* ctx, Batch& B, Graph& gr, hipStream_t s) {
+int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
+                  const gis_opts* o, Graph& gr, hipStream_t s) {
   int32_t rc;
-  if ((rc = launch_emit(emit_args(ctx, B, gr), s))) return rc;
-  if ((rc = launch_job_edges(B.d_jobs, B.n_jobs, B.K, gr.row_ptr, B.d_stats, s))) return rc;
-  return sync_stats(ctx, B, s);
+  if ((rc = zero_all(ctx, B, s))) return rc;
+  if ((rc = enqueue_build(ctx, B, level, idx, o, gr, s))) return rc;
+  if ((rc = sync_stats(ctx, B, s))) return rc;
+  return finish_build(ctx, B, gr);
 }
 
-int32_t run_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
-                  int64_t n_cells, int32_t K, int64_t n_edges, int32_t analysis, uint8_t* kept,
-                  uint64_t* mask, int64_t* n_kept, hipStream_t s, const Batch* B = nullptr,
-                  const uint8_t* level = nullptr, const int32_t* idx = nullptr) {
-  const int64_t n_rows = n_cells * K;
-  const int32_t W = (K + 63) / 64;
-  int32_t rc;
-  if (n_rows > (int64_t)INT32_MAX) {  // the reverse CSR stores 32-bit row ids
-    set_error("a graph of more than 2^31-1 rows is not supported");
-    return GIS_E_UNSUPPORTED;
-  }
-  if ((rc = ensure(ctx->rptr, (size_t)(n_cells + 1) * 8))) return rc;
-  if ((rc = ensure(ctx->rrow, (size_t)n_edges * 4 + 16))) return rc;
-  if ((rc = ensure(ctx->rcur, (size_t)n_cells * 4 + 16))) return rc;
-  if ((rc = ensure(ctx->good, (size_t)n_cells * 4 + 16))) return rc;
-  if ((rc = ensure(ctx->queue, (size_t)n_cells * 4 + 16))) return rc;
-  if ((rc = ensure(ctx->qctl, 128 * 4))) return rc;
-  if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(n_cells + 1)))) return rc;
-  if (analysis == GIS_ANALYSIS_NONLEAVING) {
-    if ((rc = ensure(ctx->alive, (size_t)n_rows * 4 + 16))) return rc;
-  } else if ((rc = ensure(ctx->badbits, (size_t)((n_rows + 31) / 32) * 4 + 16))) {
-    return rc;
-  }
-  if ((rc = zero_counters(ctx, s))) return rc;
+constexpr int32_t kFirstSweeps = 16;    // sweeps enqueued before the first convergence check
+constexpr int32_t kSweepBatch = 32;     // sweeps between later convergence checks
+constexpr int32_t kMaxSweeps = 256;     // then the frontier phase takes over
+constexpr int64_t kSweepEdges = 8 << 20;  // larger graphs go to the frontier phase directly
+constexpr int32_t kFrontierBatch = 16;  // frontier steps between convergence checks
+
+// The analysis of a graph.  enqueue_prune enqueues the first batch of sweeps
+// and the final pass (kept flags, masks, kept counts), which does its work
+// only if the sweeps converged; after the caller's synchronisation,
+// prune_converged tells whether they did, and if not, continue_prune runs
+// more sweeps (small graphs) or the frontier phase to the end, synchronising
+// after every batch, and then the final pass.  The caller cleared the
+// counters and, for a batch, the job stats.  With d_total set, the kernels
+// that read col skip their work when *d_total > cap_edges (an emit that ran
+// out of room wrote no col); the caller then redoes the round.
+PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   PruneWork w{};
+  w.removed = (uint8_t*)ctx->removed.ptr;
+  w.last = &dcnt(ctx)->sweep_last;
   w.rptr = (int64_t*)ctx->rptr.ptr;
   w.rrow = (int32_t*)ctx->rrow.ptr;
   w.rcur = (int32_t*)ctx->rcur.ptr;
-  w.good = (int32_t*)ctx->good.ptr;
-  w.alive = (int32_t*)ctx->alive.ptr;
-  w.badbits = (uint32_t*)ctx->badbits.ptr;
-  w.queue = (int32_t*)ctx->queue.ptr;
-  w.qctl = (int32_t*)ctx->qctl.ptr;
-  w.err_out = &dcnt(ctx)->qctl[3];
+  w.rowbad = (uint8_t*)ctx->rowbad.ptr;
+  w.cand = (uint8_t*)ctx->cand.ptr;
+  w.front = (int32_t*)ctx->front.ptr;
+  w.fcount = dcnt(ctx)->fcount;
   w.scan_tmp = ctx->scan_tmp.ptr;
-  if ((rc = launch_prune(row_ptr, col, out, n_cells, K, n_edges, analysis, w, kept, mask, W,
-                         dcnt(ctx)->n_kept, s)))
+  w.d_total = d_total;
+  w.cap_edges = cap_edges;
+  return w;
+}
+
+int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
+                               const uint8_t* out, int64_t n_cells, int32_t K, int32_t analysis,
+                               const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t sweeps,
+                               hipStream_t s, const Batch* B, const uint8_t* level,
+                               const int32_t* idx) {
+  int32_t rc;
+  if ((rc = prune_final(row_ptr, col, out, n_cells, K, analysis, w, kept, mask, (K + 63) / 64,
+                        dcnt(ctx)->n_kept, sweeps, s)))
     return rc;
-  if (B) {
-    if ((rc = zero_stats(*B, s))) return rc;
-    if ((rc = batch_count_kept(B->args(level, idx), kept, B->d_stats, s))) return rc;
-    if ((rc = sync_stats(ctx, *B, s))) return rc;
-  } else if ((rc = sync_counters(ctx, s))) {
-    return rc;
-  }
-  if (ctx->h_counters->qctl[3]) {
-    set_error("prune work queue did not drain within its time limit");
-    return GIS_E_INTERNAL;
-  }
-  if (n_kept) *n_kept = (int64_t)ctx->h_counters->n_kept[0];
+  if (B) return batch_count_kept(B->args(level, idx), kept, B->d_stats, s);
   return GIS_OK;
 }
 
+bool sweeps_fit(int64_t n_edges, int32_t K) { return K <= 256 && n_edges <= kSweepEdges; }
+
+// est_edges: the graph's edge count, or an estimate of it (it only chooses
+// between the two phases).
+int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                      int64_t n_cells, int32_t K, int64_t cap_edges, const int64_t* d_total,
+                      int64_t est_edges, int32_t analysis, uint8_t* kept, uint64_t* mask,
+                      hipStream_t s, const Batch* B = nullptr, const uint8_t* level = nullptr,
+                      const int32_t* idx = nullptr) {
+  int32_t rc;
+  if (n_cells * (int64_t)K > (int64_t)INT32_MAX) {  // the reverse CSR stores 32-bit row ids
+    set_error("a graph of more than 2^31-1 rows is not supported");
+    return GIS_E_UNSUPPORTED;
+  }
+  if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
+  if ((rc = fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s))) return rc;
+  ctx->first_sweeps = sweeps_fit(est_edges, K) ? kFirstSweeps : 0;
+  if (ctx->first_sweeps == 0) return GIS_OK;
+  const PruneWork w = prune_work(ctx, cap_edges, d_total);
+  if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps, s)))
+    return rc;
+  return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask,
+                                ctx->first_sweeps, s, B, level, idx);
+}
+
+// After the synchronisation that follows enqueue_prune.
+bool prune_converged(gis_ctx* ctx, int64_t n_cells) {
+  return n_cells == 0 ||
+         (ctx->first_sweeps > 0 && ctx->h_counters->sweep_last < ctx->first_sweeps);
+}
+
+// More sweeps, or the frontier phase, from the state the first sweeps left,
+// to the fixed point, then the final pass.  Synchronises; the caller cleared
+// the kept counters.
+int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                       int64_t n_cells, int32_t K, int64_t n_edges, int64_t cap_edges,
+                       int32_t analysis, uint8_t* kept, uint64_t* mask, hipStream_t s,
+                       const Batch* B = nullptr, const uint8_t* level = nullptr,
+                       const int32_t* idx = nullptr) {
+  const int64_t n_rows = n_cells * K;
+  int32_t rc;
+  PruneWork w = prune_work(ctx, cap_edges, nullptr);
+  // sweeps restart their numbering from 0 on the current removed flags
+  if ((rc = fill_i32(w.last, 0, 1, s))) return rc;
+  int32_t done = 0;
+  bool converged = false;
+  if (sweeps_fit(n_edges, K)) {
+    for (; done < kMaxSweeps && !converged; done += kSweepBatch) {
+      if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, done, kSweepBatch, s)))
+        return rc;
+      if ((rc = sync_counters(ctx, s))) return rc;
+      converged = ctx->h_counters->sweep_last < done + kSweepBatch;
+    }
+  }
+  if (!converged) {
+    bool fresh = false;
+    if ((rc = ensure(ctx->rptr, (size_t)(n_cells + 1) * 8)) ||
+        (rc = ensure(ctx->rrow, (size_t)cap_edges * 4 + 16)) ||
+        (rc = ensure(ctx->rcur, (size_t)n_cells * 4 + 16, &fresh)) ||
+        (rc = ensure(ctx->cand, (size_t)n_cells + 16, &fresh)) ||
+        (rc = ensure(ctx->rowbad, (size_t)n_rows + 16)) ||
+        (rc = ensure(ctx->front, (size_t)n_cells * 8 + 16)) ||
+        (rc = ensure(ctx->scan_tmp, scan_tmp_bytes(n_cells + 1))))
+      return rc;
+    w = prune_work(ctx, cap_edges, nullptr);
+    if (fresh || !ctx->prune_clean) {
+      // whole buffers: later calls with more cells rely on them too
+      if ((rc = fill_i32(w.rcur, 0, (int64_t)(ctx->rcur.bytes / 4), s)) ||
+          (rc = fill_u8(w.cand, 0, (int64_t)ctx->cand.bytes, s)))
+        return rc;
+    }
+    ctx->prune_clean = false;  // until the frontier has run out
+    if ((rc = prune_frontier_start(row_ptr, col, out, n_cells, K, analysis, w, s))) return rc;
+    for (int32_t t = 0;; t += kFrontierBatch) {
+      if ((rc = prune_frontier_steps(row_ptr, col, n_cells, K, analysis, w, t, kFrontierBatch, s)))
+        return rc;
+      if ((rc = sync_counters(ctx, s))) return rc;
+      if (ctx->h_counters->fcount[(t + kFrontierBatch) & 1] == 0) break;
+      if (t > n_cells + kFrontierBatch) {  // every step removes a cell: cannot happen
+        set_error("internal: the frontier phase did not terminate");
+        return GIS_E_INTERNAL;
+      }
+    }
+    ctx->prune_clean = true;
+  }
+  if ((rc = fill_u32((uint32_t*)dcnt(ctx)->n_kept, 0u, 4, s))) return rc;
+  return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask, 0, s,
+                                B, level, idx);
+}
+
 // Boundary selection + next covering of a laid-out batch (index arrays built,
-// next layouts set).  Writes the new global list to (lv_out, ix_out) if cap
-// allows.  Synchronises; per-job starts, levels and boundary counts in
-// ctx->h_stats.
-int32_t run_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
-                      const uint8_t* kept, int32_t rule, uint8_t* boundary, uint8_t* lv_out,
-                      int32_t* ix_out, int64_t cap, int64_t* n_new, hipStream_t s) {
+// next layouts set), enqueued only (the caller cleared the counters and job
+// stats).  Writes the new global list to (lv_out, ix_out) up to cap cells.
+int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
+                          const uint8_t* kept, int32_t rule, uint8_t* boundary, uint8_t* lv_out,
+                          int32_t* ix_out, int64_t cap, hipStream_t s) {
   int32_t rc;
   const BatchArgs ba = B.args(level, idx);
-  if ((rc = zero_counters(ctx, s)) || (rc = zero_stats(B, s))) return rc;
   if ((rc = batch_mark_dropped(ba, kept, s))) return rc;
   if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
   const int64_t total = next_total(B);
   if (total > 0) {
-    if ((rc = fill_u8((uint8_t*)ctx->next_state.ptr, 0, total, s))) return rc;
+    if (!ctx->next_clean &&
+        (rc = fill_u8((uint8_t*)ctx->next_state.ptr, 0, (int64_t)ctx->next_state.bytes, s)))
+      return rc;
+    ctx->next_clean = false;  // until finish_subdivide has seen the compaction complete
     if ((rc = batch_next_flags(ba, kept, boundary, s))) return rc;
     if ((rc = scan_exclusive_u8((const uint8_t*)ctx->next_state.ptr, (int64_t*)ctx->pos.ptr, total,
                                 &dcnt(ctx)->n_next, ctx->scan_tmp.ptr, s)))
@@ -585,8 +700,13 @@ int32_t run_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_
     if ((rc = batch_compact(ba, (const int64_t*)ctx->pos.ptr, cap, lv_out, ix_out, B.d_stats, s)))
       return rc;
   }
-  if ((rc = sync_stats(ctx, B, s))) return rc;
-  *n_new = total > 0 ? ctx->h_counters->n_next : 0;
+  return GIS_OK;
+}
+
+// After the synchronisation that follows enqueue_subdivide.
+int32_t finish_subdivide(gis_ctx* ctx, const Batch& B, int64_t cap, int64_t* n_new) {
+  ctx->next_clean = true;
+  *n_new = next_total(B) > 0 ? ctx->h_counters->n_next : 0;
   if (*n_new > cap) {
     set_error("output cell list capacity too small");
     return GIS_E_CAPACITY;
@@ -597,7 +717,7 @@ int32_t run_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_
 // New per-job cell counts and finest levels from the subdivision's stats.
 void next_sizes(gis_ctx* ctx, Batch& B, int64_t n_new, std::vector<int64_t>& cells) {
   for (int j = 0; j < B.n_jobs; ++j) {
-    const JobStats& st = ctx->h_stats.h[j];
+    const JobStats& st = ctx->h_stats[j];
     if (!B.jobs[j].next.state) {
       cells[j] = 0;
       continue;
@@ -605,7 +725,7 @@ void next_sizes(gis_ctx* ctx, Batch& B, int64_t n_new, std::vector<int64_t>& cel
     int64_t end = n_new;  // the next job with flags starts where this one ends
     for (int k = j + 1; k < B.n_jobs; ++k)
       if (B.jobs[k].next.state) {
-        end = ctx->h_stats.h[k].next_start;
+        end = ctx->h_stats[k].next_start;
         break;
       }
     cells[j] = end - st.next_start;
@@ -723,7 +843,10 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if ((rc = ctx->h_maxerr.ensure((size_t)kMaxDim * (nj + 1)))) return rc;
       if ((rc = fill_u32((uint32_t*)ctx->maxerr.ptr, 0u, (int64_t)2 * kMaxDim * nj, s))) return rc;
       BuildArgs a = build_args(ctx, B, (const uint8_t*)ctx->lvA.ptr, (const int32_t*)ctx->ixA.ptr, &o);
-      if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, s))) return rc;
+      // every row of small coverings, every stride-th block of 256 rows of
+      // larger ones (about 2^20 rows)
+      const int64_t stride = (B.total_cells * K) >> 20;
+      if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, stride, s))) return rc;
       GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim * nj,
                              hipMemcpyDeviceToHost, s));
       GIS_HIP(hipStreamSynchronize(s));
@@ -750,69 +873,145 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     for (int d = 0; d < n; ++d)
       info[j].band[d] = o.precision == GIS_PREC_FP32_RECHECK ? B.jobs[j].band[d] : 0.0;
   }
+  // Each round enqueues build -> analysis -> subdivision with no host
+  // round trip in between and synchronises once at its end.  The edge buffer
+  // is sized from an estimate; if the emit ran out of room (the device edge
+  // total says so), the analysis kernels skipped their work, and the round's
+  // emit, analysis and subdivision are enqueued again after the buffer grew.
   hipEvent_t* ev = ctx->ev;
   bool cur_is_A = true;
+  double edges_per_row = 8.0;
   for (int r = 0; r <= rounds; ++r) {
     const uint8_t* lv = (const uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
     const int32_t* ix = (const int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
+    const bool last = r == rounds;
     if (r > 0) {
-      for (int j = 0; j < nj; ++j) nxt[j] = (r < rounds && active[j]) ? 1 : 0;
-      if ((rc = batch_layout(ctx, B, cells, r < rounds, nxt, s))) return fail_all(rc);
+      for (int j = 0; j < nj; ++j) nxt[j] = (!last && active[j]) ? 1 : 0;
+      if ((rc = batch_layout(ctx, B, cells, !last, nxt, s))) return fail_all(rc);
     }
     const int64_t n_cells = B.total_cells;
     const int64_t n_rows = n_cells * K;
-    // build
+    const size_t want_col = (size_t)((double)n_rows * edges_per_row * 1.25) + 64;
+    if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)) ||
+        (rc = ensure(ctx->col, want_col * 4)) || (rc = ensure(ctx->kept, (size_t)n_cells + 16)) ||
+        (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)))
+      return fail_all(rc);
+    // the next covering has at most 2^n children per current cell
+    const int64_t cap = last ? 0 : (n_cells << n);
+    DevBuf& lvN = cur_is_A ? ctx->lvB : ctx->lvA;
+    DevBuf& ixN = cur_is_A ? ctx->ixB : ctx->ixA;
+    if (!last && ((rc = ensure(lvN, (size_t)cap + 16)) || (rc = ensure(ixN, (size_t)cap * n * 4 + 16)) ||
+                  (rc = ensure(ctx->bnd, (size_t)n_cells + 16))))
+      return fail_all(rc);
+    Graph gr{(int64_t*)ctx->row_ptr.ptr, (int32_t*)ctx->col.ptr, (uint8_t*)ctx->out.ptr,
+             (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f, false};
+    uint8_t* kept = (uint8_t*)ctx->kept.ptr;
+    uint64_t* mask = (uint64_t*)ctx->mask.ptr;
+    auto analyse_and_refine = [&]() -> int32_t {
+      int32_t e;
+      if ((e = enqueue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.cap_edges,
+                             &dcnt(ctx)->total_edges, (int64_t)(edges_per_row * (double)n_rows),
+                             o.analysis, kept, mask, s, &B, lv, ix)))
+        return e;
+      GIS_HIP(hipEventRecord(ev[2], s));
+      if (!last && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
+                                          (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
+                                          (int32_t*)ixN.ptr, cap, s)))
+        return e;
+      GIS_HIP(hipEventRecord(ev[3], s));
+      return sync_stats(ctx, B, s);
+    };
+    if ((rc = zero_all(ctx, B, s))) return fail_all(rc);
     GIS_HIP(hipEventRecord(ev[0], s));
     if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
-    if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)))
-      return fail_all(rc);
-    if (ctx->col.bytes < 16 && (rc = ensure(ctx->col, (size_t)n_rows * 4 * 8 + 64))) return fail_all(rc);
-    Graph gr{(int64_t*)ctx->row_ptr.ptr, (int32_t*)ctx->col.ptr, (uint8_t*)ctx->out.ptr,
-             (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f};
-    if ((rc = run_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
+    if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
+    GIS_HIP(hipEventRecord(ev[1], s));
+    if ((rc = analyse_and_refine())) return fail_all(rc);
+    if ((rc = finish_build(ctx, B, gr))) return fail_all(rc);
     if (gr.n_edges > gr.cap_edges) {
+      // grow the edge buffer and redo the round
       if ((rc = ensure(ctx->col, (size_t)gr.n_edges * 4))) return fail_all(rc);
       gr.col = (int32_t*)ctx->col.ptr;
       gr.cap_edges = (int64_t)(ctx->col.bytes / 4);
-      if ((rc = rerun_emit(ctx, B, gr, s))) return fail_all(rc);
+      if ((rc = zero_all(ctx, B, s))) return fail_all(rc);
+      // the subdivision marked dropped cells in the index: rebuild it for the emit
+      if (B.total_slots > 0 &&
+          (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, B.total_slots, s)))
+        return fail_all(rc);
+      if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
+      GIS_HIP(hipEventRecord(ev[0], s));
+      if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
+      GIS_HIP(hipEventRecord(ev[1], s));
+      if ((rc = analyse_and_refine())) return fail_all(rc);
+      if ((rc = finish_build(ctx, B, gr))) return fail_all(rc);
     }
-    std::vector<JobStats> bstats(ctx->h_stats.h, ctx->h_stats.h + nj);
-    GIS_HIP(hipEventRecord(ev[1], s));
-    // analysis of the batch's union graph
-    if ((rc = ensure(ctx->kept, (size_t)n_cells + 16)) || (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)))
-      return fail_all(rc);
-    int64_t kept_total = 0;
-    if ((rc = run_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.n_edges, o.analysis,
-                        (uint8_t*)ctx->kept.ptr, (uint64_t*)ctx->mask.ptr, &kept_total, s, &B, lv, ix)))
-      return fail_all(rc);
-    GIS_HIP(hipEventRecord(ev[2], s));
-    GIS_HIP(hipEventSynchronize(ev[2]));
     float ms_b = 0.f, ms_p = 0.f, ms_sub = 0.f;
     GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
     GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
+    GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+    if (!prune_converged(ctx, n_cells)) {
+      // long removal chains: finish the analysis with the frontier phase and
+      // redo the subdivision (it ran on the unfinished kept set and marked
+      // its dropped cells in the index, which is rebuilt first)
+      const Counters keep = *ctx->h_counters;
+      std::vector<JobStats> build_stats(ctx->h_stats, ctx->h_stats + nj);
+      if ((rc = zero_all(ctx, B, s))) return fail_all(rc);
+      if (B.total_slots > 0 &&
+          (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, B.total_slots, s)))
+        return fail_all(rc);
+      if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
+      GIS_HIP(hipEventRecord(ev[1], s));
+      if ((rc = continue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.n_edges,
+                               gr.cap_edges, o.analysis, kept, mask, s, &B, lv, ix)))
+        return fail_all(rc);
+      GIS_HIP(hipEventRecord(ev[2], s));
+      if (!last && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
+                                           (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
+                                           (int32_t*)ixN.ptr, cap, s)))
+        return fail_all(rc);
+      GIS_HIP(hipEventRecord(ev[3], s));
+      if ((rc = sync_stats(ctx, B, s))) return fail_all(rc);
+      float ms_p2 = 0.f;
+      GIS_HIP(hipEventElapsedTime(&ms_p2, ev[1], ev[2]));
+      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+      ms_p += ms_p2;
+      ctx->h_counters->total_edges = keep.total_edges;
+      ctx->h_counters->n_recheck = keep.n_recheck;
+      for (int j = 0; j < nj; ++j) {
+        ctx->h_stats[j].n_edges = build_stats[j].n_edges;
+        ctx->h_stats[j].n_out = build_stats[j].n_out;
+        ctx->h_stats[j].n_recheck = build_stats[j].n_recheck;
+      }
+    }
+    if (n_rows > 0) edges_per_row = (double)gr.n_edges / (double)n_rows;
+    if (edges_per_row < 1.0) edges_per_row = 1.0;
     for (int j = 0; j < nj; ++j) {
       if (!active[j]) continue;
+      const JobStats& js = ctx->h_stats[j];
       gis_round_stats& st = info[j].rounds[r];
       st.n_cells = B.jobs[j].n_cells;
       st.n_rows = B.jobs[j].n_cells * K;
-      st.n_edges = bstats[j].n_edges;
-      st.n_out = (int64_t)bstats[j].n_out;
-      st.n_recheck = (int64_t)bstats[j].n_recheck;
-      st.n_kept = (int64_t)ctx->h_stats.h[j].n_kept;
+      st.n_edges = js.n_edges;
+      st.n_out = (int64_t)js.n_out;
+      st.n_recheck = (int64_t)js.n_recheck;
+      st.n_kept = (int64_t)js.n_kept;
+      st.n_boundary = last ? 0 : (int64_t)js.n_boundary;
       st.max_level = B.lmax[j];
       st.ms_build = ms_b;
       st.ms_prune = ms_p;
+      st.ms_subdivide = last ? 0.f : ms_sub;
       st.ms_image = gr.ms_image;
       st.ms_recheck = gr.ms_recheck;
       info[j].n_rounds = r + 1;
       info[j].n_kept = st.n_kept;
     }
     // jobs that keep nothing, and every job after the last round, are done
+    // (a job that keeps nothing set no flags for the next covering)
     for (int j = 0; j < nj; ++j) {
       if (!active[j]) continue;
-      if (r == rounds || info[j].rounds[r].n_kept == 0) {
-        if ((rc = make_solution(ctx, B, j, lv, ix, (const uint8_t*)ctx->kept.ptr,
-                                (const uint64_t*)ctx->mask.ptr, info[j], &out[j], s)))
+      if (last || info[j].rounds[r].n_kept == 0) {
+        info[j].rounds[r].n_boundary = 0;
+        if ((rc = make_solution(ctx, B, j, lv, ix, kept, mask, info[j], &out[j], s)))
           return fail_all(rc);
         active[j] = 0;
       }
@@ -820,51 +1019,11 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     bool any = false;
     for (int j = 0; j < nj; ++j) any |= active[j] != 0;
     if (!any) break;
-    // subdivide the kept boundary cells of the jobs still active; finished
-    // jobs keep their index but set no flags
-    bool dropped = false;
-    for (int j = 0; j < nj; ++j)
-      if (!active[j] && B.jobs[j].next.state) {
-        B.jobs[j].next.state = nullptr;
-        dropped = true;
-      }
-    if (dropped) {
-      int64_t off = 0, blk = 0;
-      for (int j = 0; j < nj; ++j) {
-        Job& J = B.jobs[j];
-        J.next_off = off;
-        J.blk[LK_NEXT] = blk;
-        if (!J.next.state) continue;
-        J.next.state = (uint8_t*)ctx->next_state.ptr + off;
-        const int64_t ns = J.next.off[J.next.lmax + 1];
-        off += ns;
-        blk += cdiv(ns, 256);
-      }
-      B.blocks[LK_NEXT] = blk;
-      if ((rc = upload_jobs(ctx, B, s))) return fail_all(rc);  // the stream is idle here
-    }
-    int64_t cap = 0;
-    for (int j = 0; j < nj; ++j)
-      if (active[j]) cap += info[j].rounds[r].n_kept << n;
-    DevBuf& lvN = cur_is_A ? ctx->lvB : ctx->lvA;
-    DevBuf& ixN = cur_is_A ? ctx->ixB : ctx->ixA;
-    if ((rc = ensure(lvN, (size_t)cap + 16)) || (rc = ensure(ixN, (size_t)cap * n * 4 + 16))) return fail_all(rc);
-    if ((rc = ensure(ctx->bnd, (size_t)n_cells + 16))) return fail_all(rc);
-    GIS_HIP(hipEventRecord(ev[3], s));
     int64_t n_new = 0;
-    if ((rc = run_subdivide(ctx, B, lv, ix, (const uint8_t*)ctx->kept.ptr, o.boundary_rule,
-                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr, (int32_t*)ixN.ptr, cap,
-                            &n_new, s)))
-      return fail_all(rc);
-    GIS_HIP(hipEventRecord(ev[0], s));
-    GIS_HIP(hipEventSynchronize(ev[0]));
-    GIS_HIP(hipEventElapsedTime(&ms_sub, ev[3], ev[0]));
-    for (int j = 0; j < nj; ++j) {
-      if (!active[j]) continue;
-      info[j].rounds[r].n_boundary = (int64_t)ctx->h_stats.h[j].n_boundary;
-      info[j].rounds[r].ms_subdivide = ms_sub;
-    }
+    if ((rc = finish_subdivide(ctx, B, cap, &n_new))) return fail_all(rc);
     next_sizes(ctx, B, n_new, cells);
+    for (int j = 0; j < nj; ++j)
+      if (!active[j]) cells[j] = 0;
     cur_is_A = !cur_is_A;
     int64_t tot = 0;
     for (int j = 0; j < nj; ++j) tot += cells[j];
@@ -908,16 +1067,12 @@ int32_t gis_ctx_create(int32_t device, gis_ctx** out) {
   DeviceGuard g(device);
   gis_ctx* c = new gis_ctx();
   c->device = device;
-  int32_t rc = ensure(c->counters, sizeof(Counters));
+  int32_t rc = ensure_counters(c, 1);
   if (rc) {
+    release(c->counters);
+    c->h_cs.free();
     delete c;
     return rc;
-  }
-  hipError_t e = hipHostMalloc((void**)&c->h_counters, sizeof(Counters), hipHostMallocDefault);
-  if (e != hipSuccess) {
-    release(c->counters);
-    delete c;
-    return hip_fail(e, "hipHostMalloc");
   }
   c->timer.ok = true;
   for (int i = 0; i < 3; ++i)
@@ -936,15 +1091,14 @@ void gis_ctx_destroy(gis_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->counters, &c->jobs, &c->stats, &c->maxerr, &c->rng, &c->cnt, &c->bsum,
-                    &c->bscan, &c->recheck, &c->scan_tmp, &c->idx_state, &c->idx_id,
-                    &c->next_state, &c->pos, &c->rptr, &c->rrow, &c->rcur, &c->good, &c->alive,
-                    &c->badbits, &c->queue, &c->qctl, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
+  DevBuf* bufs[] = {&c->counters, &c->jobs, &c->maxerr, &c->lookback, &c->scan_tmp,
+                    &c->idx_state, &c->idx_id,
+                    &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rcur,
+                    &c->rowbad, &c->cand, &c->front, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
   for (DevBuf* b : bufs) release(*b);
-  if (c->h_counters) (void)hipHostFree(c->h_counters);
+  c->h_cs.free();
   c->h_jobs.free();
-  c->h_stats.free();
   c->h_maxerr.free();
   for (int i = 0; i < 3; ++i)
     if (c->timer.ev[i]) (void)hipEventDestroy(c->timer.ev[i]);
@@ -985,7 +1139,7 @@ int32_t gis_build_graph(gis_ctx* ctx, const gis_system* sys, const gis_grid* gri
   B.lmax[0] = (int)ctx->h_counters->maxlevel;
   if ((rc = batch_layout(ctx, B, {cells->n_cells}, false, {0}, s))) return rc;
   if ((rc = batch_index(ctx, B, cells->level, cells->idx, true, s))) return rc;
-  Graph gr{graph->row_ptr, graph->col, graph->out, graph->cap_edges, 0, 0, 0, 0.f, 0.f};
+  Graph gr{graph->row_ptr, graph->col, graph->out, graph->cap_edges, 0, 0, 0, 0.f, 0.f, false};
   if ((rc = run_build(ctx, B, cells->level, cells->idx, opts, gr, s))) return rc;
   graph->n_rows = n_rows;
   graph->n_edges = gr.n_edges;
@@ -1027,8 +1181,18 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
   if ((rc = sync_counters(ctx, s))) return rc;
   if (ctx->h_counters->err & 1u) return inval("graph row offsets are inconsistent");
   if (ctx->h_counters->err & 2u) return inval("graph targets are not cell ids");
-  return run_prune(ctx, graph->row_ptr, graph->col, graph->out, n_cells, K, graph->n_edges,
-                   analysis, d_kept, d_mask, n_kept, s);
+  if ((rc = zero_counters(ctx, s))) return rc;
+  if ((rc = enqueue_prune(ctx, graph->row_ptr, graph->col, graph->out, n_cells, K, graph->n_edges,
+                          nullptr, graph->n_edges, analysis, d_kept, d_mask, s)))
+    return rc;
+  if ((rc = sync_counters(ctx, s))) return rc;
+  if (!prune_converged(ctx, n_cells) &&
+      (rc = continue_prune(ctx, graph->row_ptr, graph->col, graph->out, n_cells, K, graph->n_edges,
+                           graph->n_edges, analysis, d_kept, d_mask, s)))
+    return rc;
+  if ((rc = sync_counters(ctx, s))) return rc;
+  if (n_kept) *n_kept = (int64_t)ctx->h_counters->n_kept[0];
+  return GIS_OK;
 }
 
 int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
@@ -1066,8 +1230,12 @@ int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
     bnd = (uint8_t*)ctx->bnd.ptr;
   }
   int64_t n_new = 0;
-  rc = run_subdivide(ctx, B, in->level, in->idx, d_kept, boundary_rule, bnd, out->level, out->idx,
-                     out->cap, &n_new, s);
+  if ((rc = zero_all(ctx, B, s))) return rc;
+  if ((rc = enqueue_subdivide(ctx, B, in->level, in->idx, d_kept, boundary_rule, bnd, out->level,
+                              out->idx, out->cap, s)))
+    return rc;
+  if ((rc = sync_stats(ctx, B, s))) return rc;
+  rc = finish_subdivide(ctx, B, out->cap, &n_new);
   out->n_cells = n_new;
   return rc;
 }
@@ -1219,7 +1387,7 @@ int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* 
   gis_opts o{};
   o.samples = samples;
   BuildArgs a = build_args(ctx, B, cells->level, cells->idx, &o);
-  if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, s))) return rc;
+  if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, 1, s))) return rc;
   GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim,
                          hipMemcpyDeviceToHost, s));
   GIS_HIP(hipStreamSynchronize(s));

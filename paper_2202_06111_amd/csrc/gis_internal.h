@@ -75,7 +75,9 @@ struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
 };
-int32_t ensure(DevBuf& b, size_t bytes);
+// Grows b to at least `bytes` (contents are lost when it grows; *fresh is
+// set then).
+int32_t ensure(DevBuf& b, size_t bytes, bool* fresh = nullptr);
 void release(DevBuf& b);
 
 // HIP events bracketing the image kernels (created once per context).
@@ -174,62 +176,72 @@ struct BuildArgs {
   int32_t samples;        // GIS_SAMPLES_*
   int32_t fast_out;
   int32_t kind, n;        // system kind and state dimension shared by the batch
+  int32_t all_uniform;    // every job's covering is its full level-0 grid
   int64_t n_blocks;       // launch blocks (LK_ROWS)
+  int64_t total_rows;
   const uint8_t* level;   // global cell list
   const int32_t* idx;
-  // outputs, indexed by global row
-  int32_t* rng;           // [rows * 2n] closed ranges on each job's finest grid
-  int32_t* cnt;           // [rows] edge counts
+  // outputs of k_build, indexed by global row
   uint8_t* out;           // [rows] OUT flags
-  int64_t* bsum;          // [n_blocks] edge count per launch block
-  int64_t* recheck;       // [rows] global rows queued for the FP64 recheck
-  int64_t* n_recheck;     // device counter
-  JobStats* stats;        // per-job counters
-};
-int32_t launch_count(const BuildArgs& a, int32_t precision, hipStream_t s);
-int32_t launch_recheck(const BuildArgs& a, hipStream_t s);
-struct EmitArgs {
-  const Job* jobs;
-  int32_t n_jobs;
-  int32_t K, n;
-  int32_t any_adaptive;   // 0: every job is a full level-0 grid
-  int64_t n_blocks;
-  int64_t total_rows;
-  const int32_t* rng;
-  const int32_t* cnt;
-  const int64_t* bscan;   // exclusive scan of bsum
+  int64_t* row_ptr;       // [rows + 1]
+  int32_t* col;           // [cap_edges]
   int64_t cap_edges;
-  int64_t* row_ptr;
-  int32_t* col;
+  uint64_t* lb;           // [n_blocks] look-back words (tagged with `epoch`)
+  uint32_t* ticket;       // block ticket: 0 before the launch, reset to 0 by the last block
+  uint32_t epoch;         // 1 .. 2^24-1, different from every word left in lb
+  int64_t* d_total;       // edge total of the batch
+  unsigned long long* n_recheck;  // rows the FP32 test sent to FP64
+  uint32_t* err;          // bit 8: a look-back wait reached its time limit
+  JobStats* stats;        // per-job n_edges, n_out, n_recheck (accumulated)
 };
-int32_t launch_emit(const EmitArgs& a, hipStream_t s);
-// Per-job edge totals from row_ptr (after emit) into stats[j].n_edges.
-int32_t launch_job_edges(const Job* jobs, int32_t n_jobs, int32_t K, const int64_t* row_ptr,
-                         JobStats* stats, hipStream_t s);
+// Symbolic image of the batch's coverings into (row_ptr, col, out); col is
+// written only if the edge total fits in cap_edges.
+int32_t launch_build(const BuildArgs& a, int32_t precision, hipStream_t s);
 int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s);
-int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, hipStream_t s);
-int32_t count_out(const uint8_t* out, int64_t n, unsigned long long* d_count, hipStream_t s);
+// max |y32 - y64| per job and dimension over the rows of every stride-th
+// launch block of each job (all rows when stride <= 1).
+int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64_t stride,
+                         hipStream_t s);
 
 // k_prune.hip
 struct PruneWork {
-  int64_t* rptr;     // [n_cells + 1]
-  int32_t* rrow;     // [n_edges] in-rows per target cell
-  int32_t* rcur;     // [n_cells] scatter cursors / in-degrees
-  int32_t* good;     // [n_cells]
-  int32_t* alive;    // [n_rows] remaining kept targets (non-leaving analysis)
-  uint32_t* badbits; // [ceil(n_rows / 32)] (controlled analysis)
-  int32_t* queue;    // [n_cells]
-  int32_t* qctl;     // [128]: queue counters, one 128-byte line each
-  int32_t* err_out;  // receives the drain's error word
+  uint8_t* removed;  // [n_cells] 0 on entry to the sweeps
+  int32_t* last;     // 1 + index of the last sweep that removed a cell (0 on entry)
+  // frontier phase
+  int64_t* rptr;     // [n_cells + 1] reverse-CSR offsets
+  int32_t* rrow;     // [cap_edges] in-rows per target cell
+  int32_t* rcur;     // [n_cells] in-degree cursors: zero on entry, left zero
+  uint8_t* rowbad;   // [n_rows]
+  uint8_t* cand;     // [n_cells] zero on entry, left zero
+  int32_t* front;    // [2 * n_cells] the two frontier lists
+  int32_t* fcount;   // [2] their lengths
   void* scan_tmp;
+  const int64_t* d_total;  // device edge total, or null: reverse-CSR kernels do no work
+  int64_t cap_edges;       // when *d_total > cap_edges (col was not written)
 };
 // Flags an inconsistent CSR graph in *d_err (bit 0 offsets, bit 1 targets).
 int32_t launch_check_graph(const int64_t* row_ptr, const int32_t* col, int64_t n_rows,
                            int64_t n_edges, int64_t n_cells, uint32_t* d_err, hipStream_t s);
-int32_t launch_prune(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
-                     int64_t n_cells, int32_t K, int64_t n_edges, int32_t analysis,
-                     const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t mask_words,
-                     unsigned long long* d_nkept, hipStream_t s);
+// Sweeps first .. first+count-1 (K <= 256).  Converged when *last < first+count.
+int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                     int32_t first, int32_t count, hipStream_t s);
+// Reverse CSR and the first frontier (every removed cell, and every cell
+// whose rows are all bad from the start); fcount[0] = its length.
+int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                             int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                             hipStream_t s);
+// Frontier steps first .. first+count-1; step t expands list t & 1.  Done
+// when fcount[(first+count) & 1] == 0.
+int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                             int32_t analysis, const PruneWork& w, int32_t first, int32_t count,
+                             hipStream_t s);
+// kept flags, masks (mask_words per cell) and the kept count (added to
+// *d_nkept); with sweeps > 0, only if sweep sweeps-1 removed nothing.
+int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                    int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                    uint8_t* kept, uint64_t* mask, int32_t mask_words,
+                    unsigned long long* d_nkept, int32_t sweeps, hipStream_t s);
 
 // k_index.hip, job-batched: covering indexes of every job's cell list (the
 // jobs' state arrays are cleared first by the caller).  Flags invalid lists in
@@ -250,7 +262,8 @@ int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t 
 // k_refine.hip, job-batched
 int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
                        JobStats* stats, hipStream_t s);
-// Sets the next-covering flags (the caller cleared the jobs' next arrays).
+// Sets the next-covering flags (the jobs' next arrays are zero on entry;
+// batch_compact leaves them zero again).
 int32_t batch_next_flags(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
                          hipStream_t s);
 // pos: exclusive scan of the batch's next-flag array; writes the new global
@@ -260,8 +273,6 @@ int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8
 int32_t batch_coarse(const BatchArgs& b, uint8_t* level, int32_t* idx, hipStream_t s);
 // Kept cells per job into stats[j].n_kept.
 int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stats, hipStream_t s);
-// OUT rows per job into stats[j].n_out.
-int32_t batch_count_out(const BatchArgs& b, const uint8_t* out, JobStats* stats, hipStream_t s);
 
 // k_query.hip
 int32_t launch_query(const CoverIndex& ci, const GridArgs& g, const uint8_t* kept,

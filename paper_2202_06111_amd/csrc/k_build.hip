@@ -1,14 +1,20 @@
-// Graph construction kernels: symbolic image of a covering (Sec. 2.2,
-// Definition 1) as CSR rows, one row per (cell, input).
+// Graph construction: the symbolic image of a covering (Sec. 2.2,
+// Definition 1) as CSR rows, one row per (cell, input), in one pass.
 //
-//   count   : per row, the images of the sample points (nsub RK4 substeps),
-//             their bounding box, the closed index range of finest-level
-//             cells it meets, the OUT flag and the row's edge count; one
-//             int64 edge total per block of kRowBlock rows.
-//   recheck : FP64 redo of the rows the FP32 count kernel could not decide.
-//   emit    : block-local scan of the counts plus the block offset -> row_ptr;
-//             the row's target ids are enumerated into an LDS tile and copied
-//             to col[] with coalesced stores.
+// k_build, one thread per row, a block of kRowBlock consecutive rows:
+//   1. images of the sample points (nsub RK4 substeps) and their bounding box,
+//      in FP64, or in FP32 with the row redone in FP64 when a decision taken
+//      from its box is not safe within the recheck band;
+//   2. the closed index range of finest-level cells the box meets, the OUT
+//      flag, and the row's edge count from a walk of the covering index (the
+//      first few target ids are kept in LDS for step 5);
+//   3. a block-wide exclusive scan of the counts;
+//   4. the block's global edge offset by decoupled look-back: blocks take
+//      their index from an atomic ticket, publish their edge total, and the
+//      first wave sums the totals of the blocks before it 64 at a time until
+//      it meets one that has published its inclusive prefix;
+//   5. row_ptr, and the target ids written into an LDS tile and copied to col
+//      with coalesced stores, tile by tile.
 //
 // Cell ids follow the canonical order of the covering (level, then row-major
 // index), so enumerating the covering index level by level, row-major inside
@@ -24,7 +30,19 @@ namespace gis {
 
 namespace {
 
-constexpr int kTile = 8192;  // LDS tile of the emitter (int32 ids, 32 KiB)
+constexpr int kTile = 4096;   // LDS staging tile of the emitter (int32 ids, 16 KiB)
+constexpr int kCache = 6;     // target ids kept in LDS per row between count and emit
+constexpr int kLdsIndex = 6144;  // bytes of LDS for the coarse levels of the covering index
+
+// Look-back words: the launch's epoch in bits 40-63, a status in bits 38-39
+// and an edge total in bits 0-37.  A word written by an earlier launch
+// carries another epoch and reads as "not yet published".
+constexpr uint64_t kLbAgg = 1ull << 38;   // the block's own total
+constexpr uint64_t kLbInc = 2ull << 38;   // total of this block and all before it
+constexpr uint64_t kLbVal = (1ull << 38) - 1;
+__device__ __forceinline__ uint32_t lb_status(uint64_t w, uint32_t epoch) {
+  return (uint32_t)(w >> 40) == epoch ? (uint32_t)(w >> 38) & 3u : 0u;
+}
 
 // ------------------------------------------------------------------ cover logic
 // Position of v on the finest grid, clamped to [-2, N + 2] (the clamp keeps
@@ -78,14 +96,20 @@ __device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverInd
 
 // Visits the slots of the covering index met by the finest-level box
 // [lo, hi], level by level (coarse to fine), row-major inside a level:
-// f(level, slot, state) returns false to stop early.  Below level 0 only the
-// children of REFINED slots can hold leaves or holes, so each level is
-// restricted to the box spanned by the children of the REFINED slots seen one
-// level up, and the walk ends at the first level without a REFINED slot.  The
-// visiting order (level-major, row-major) is the canonical id order.
+// f(level, slot, state, k) (k the slot's multi-index) returns false to stop
+// early.  Below level 0 only the children of REFINED slots can hold leaves or
+// holes, so each level is restricted to the box spanned by the children of
+// the REFINED slots seen one level up, and the walk ends at the first level
+// without a REFINED slot.  The visiting order (level-major, row-major) is the
+// canonical id order.  States are read kWalk slots at a time (independent
+// loads, one wait), from `lst` (an LDS copy of the first `lslots` slots) for
+// the levels that lie there.
+constexpr int kWalk = 4;
+
 template <int N, typename F>
-__device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t* lo,
-                                            const int32_t* hi, F&& f) {
+__device__ __forceinline__ void walk_levels(const CoverIndex& ci, const uint8_t* lst,
+                                            int64_t lslots, const int32_t* lo, const int32_t* hi,
+                                            F&& f) {
   int32_t plo[N], phi[N];  // REFINED bounding box one level up
   for (int L = 0; L <= ci.lmax; ++L) {
     const int s = ci.lmax - L;
@@ -107,27 +131,50 @@ __device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t*
     if (empty) return;
     bool refined = false;
     const int64_t base = ci.off[L];
-    for (;;) {
-      int64_t lin = 0;
+    const bool in_lds = ci.off[L + 1] <= lslots;
+    bool done = false;
+    while (!done) {
+      int64_t sl[kWalk];
+      int32_t kc[kWalk][N];
+      int m = 0;
 #pragma unroll
-      for (int d = 0; d < N; ++d) lin = lin * ci.dims[L][d] + k[d];
-      const uint8_t st = ci.state[base + lin];
-      if (!f(L, base + lin, st)) return;
-      if (st == ST_REFINED) {
-        refined = true;
+      for (int q = 0; q < kWalk; ++q) {
+        if (!done) {
+          int64_t lin = 0;
 #pragma unroll
-        for (int d = 0; d < N; ++d) {
-          nlo[d] = k[d] < nlo[d] ? k[d] : nlo[d];
-          nhi[d] = k[d] > nhi[d] ? k[d] : nhi[d];
+          for (int d = 0; d < N; ++d) {
+            lin = lin * ci.dims[L][d] + k[d];
+            kc[q][d] = k[d];
+          }
+          sl[q] = base + lin;
+          m = q + 1;
+          int d = N - 1;
+          while (d >= 0 && k[d] == bhi[d]) {
+            k[d] = blo[d];
+            --d;
+          }
+          if (d < 0) done = true;
+          else ++k[d];
         }
       }
-      int d = N - 1;
-      while (d >= 0 && k[d] == bhi[d]) {
-        k[d] = blo[d];
-        --d;
+      uint8_t st[kWalk];
+#pragma unroll
+      for (int q = 0; q < kWalk; ++q)
+        st[q] = q < m ? (in_lds ? lst[sl[q]] : ci.state[sl[q]]) : (uint8_t)ST_NONE;
+#pragma unroll
+      for (int q = 0; q < kWalk; ++q) {
+        if (q < m) {
+          if (!f(L, sl[q], st[q], kc[q])) return;
+          if (st[q] == ST_REFINED) {
+            refined = true;
+#pragma unroll
+            for (int d = 0; d < N; ++d) {
+              nlo[d] = kc[q][d] < nlo[d] ? kc[q][d] : nlo[d];
+              nhi[d] = kc[q][d] > nhi[d] ? kc[q][d] : nhi[d];
+            }
+          }
+        }
       }
-      if (d < 0) break;
-      ++k[d];
     }
     if (!refined) return;
 #pragma unroll
@@ -136,61 +183,6 @@ __device__ __forceinline__ void walk_levels(const CoverIndex& ci, const int32_t*
       phi[d] = nhi[d];
     }
   }
-}
-
-template <int N>
-__device__ __forceinline__ bool has_hole(const CoverIndex& ci, const Ranges<N>& r) {
-  if (ci.uniform || r.iempty) return false;
-  bool hole = false;
-  walk_levels<N>(ci, r.ilo, r.ihi, [&](int, int64_t, uint8_t st) {
-    if (st == ST_HOLE) {
-      hole = true;
-      return false;
-    }
-    return true;
-  });
-  return hole;
-}
-
-template <int N>
-__device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ranges<N>& r) {
-  if (r.empty) return 0;
-  if (ci.uniform) {
-    int32_t c = 1;
-#pragma unroll
-    for (int d = 0; d < N; ++d) c *= r.hi[d] - r.lo[d] + 1;
-    return c;
-  }
-  int32_t c = 0;
-  walk_levels<N>(ci, r.lo, r.hi, [&](int, int64_t, uint8_t st) {
-    c += st == ST_LEAF;
-    return true;
-  });
-  return c;
-}
-
-// Writes the cover decision of global row g of job J; returns its edge count.
-template <int N>
-__device__ __forceinline__ int32_t decide_row(const BuildArgs& a, const Job& J,
-                                              const CoverIndex& ci, int64_t g, bool finite,
-                                              const double* bl, const double* bh) {
-  int32_t count = 0;
-  bool out = true;
-  int32_t* rg = a.rng + g * (2 * N);
-  if (finite) {
-    const Ranges<N> rr = ranges_of<N>(J.grid, ci, bl, bh);
-    out = rr.outx || has_hole<N>(ci, rr);
-    count = count_targets<N>(ci, rr);
-    if (a.fast_out && out) count = 0;
-#pragma unroll
-    for (int d = 0; d < N; ++d) {
-      rg[2 * d] = rr.lo[d];
-      rg[2 * d + 1] = rr.hi[d];
-    }
-  }
-  a.cnt[g] = count;
-  a.out[g] = out ? 1 : 0;
-  return count;
 }
 
 // Bounding box of the sample images of local row lr of job J, in precision R.
@@ -234,103 +226,285 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
   return finite;
 }
 
-__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* lds) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) lds[wid] = v;
-  __syncthreads();
-  int64_t t = 0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
-  return t;
-}
 
-// ------------------------------------------------------------------ kernels
-// One thread per (cell, input) row; a block never straddles two jobs.
-template <int KIND, int N>
-__global__ __launch_bounds__(kRowBlock) void k_count_f64(BuildArgs a) {
-  __shared__ int64_t lds[kRowBlock / 64];
-  __shared__ CoverIndex ci;
-  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
-  const Job& J = a.jobs[jb];
-  stage_index(&ci, &J.ci);
-  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
-  int64_t mine = 0;
-  if (lr < J.n_cells * a.K) {
-    const Rk4Consts<double> kc = make_consts<double>(J.sys);
-    double bl[N], bh[N];
-    const bool finite = row_bbox<KIND, N, double>(a, J, kc, lr, bl, bh);
-    mine = decide_row<N>(a, J, ci, J.cell_off * a.K + lr, finite, bl, bh);
-  }
-  const int64_t t = block_sum_i64(mine, lds);
-  if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
-}
-
-// FP32 images; a row is decided from its FP32 box only when every decision
-// taken from a box extreme (the finest-grid position's floor/ceil, the
-// comparisons with lo and hi) is the same anywhere within band[d] of it.
+// Decisions of a row whose FP32 box is [fl, fh] (fh >= fl): safe when every
+// decision taken from a box extreme (the finest-grid position's floor/ceil,
+// the comparisons with lo and hi) is the same anywhere within band[d] of it.
 // Since |y32 - y64| <= band[d] holds for every sample image, and min/max are
 // 1-Lipschitz, the FP64 box extremes then lead to the same decisions.
-// Other rows are queued for the FP64 recheck kernel.
-template <int KIND, int N>
-__global__ __launch_bounds__(kRowBlock) void k_count_f32(BuildArgs a) {
-  __shared__ int64_t lds[kRowBlock / 64];
-  __shared__ CoverIndex ci;
-  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
-  const Job& J = a.jobs[jb];
-  stage_index(&ci, &J.ci);
-  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
-  int64_t mine = 0;
-  if (lr < J.n_cells * a.K) {
-    const int64_t g = J.cell_off * a.K + lr;
-    const Rk4Consts<float> kc = make_consts<float>(J.sys);
-    float bl[N], bh[N];
-    bool safe = row_bbox<KIND, N, float>(a, J, kc, lr, bl, bh);
-    double dl[N], dh[N];
-    const int L = ci.lmax;
+template <int N>
+__device__ __forceinline__ bool band_safe(const Job& J, const CoverIndex& ci, const float* fl,
+                                          const float* fh, double* dl, double* dh) {
+  bool safe = true;
+  const int L = ci.lmax;
 #pragma unroll
-    for (int d = 0; d < N; ++d) {
-      dl[d] = (double)bl[d];
-      dh[d] = (double)bh[d];
-      const double hs = ldexp(J.grid.w0[d], -L);
-      const double eps = J.band[d];
-      const double ta = (dl[d] - J.grid.lo[d]) / hs;
-      const double tb = (dh[d] - J.grid.lo[d]) / hs;
-      const double tola = eps / hs + 1e-9 * (fabs(ta) + 1.0);
-      const double tolb = eps / hs + 1e-9 * (fabs(tb) + 1.0);
-      safe &= fabs(ta - rint(ta)) > tola;
-      safe &= fabs(tb - rint(tb)) > tolb;
-      safe &= fabs(dh[d] - J.grid.hi[d]) > eps;
-    }
-    if (safe) {
-      mine = decide_row<N>(a, J, ci, g, true, dl, dh);
-    } else {
-      const unsigned long long slot = atomicAdd((unsigned long long*)a.n_recheck, 1ull);
-      a.recheck[slot] = g;
-      a.cnt[g] = 0;
-      atomicAdd(&a.stats[jb].n_recheck, 1ull);
-    }
+  for (int d = 0; d < N; ++d) {
+    dl[d] = (double)fl[d];
+    dh[d] = (double)fh[d];
+    const double hs = ldexp(J.grid.w0[d], -L);
+    const double eps = J.band[d];
+    const double ta = (dl[d] - J.grid.lo[d]) / hs;
+    const double tb = (dh[d] - J.grid.lo[d]) / hs;
+    const double tola = eps / hs + 1e-9 * (fabs(ta) + 1.0);
+    const double tolb = eps / hs + 1e-9 * (fabs(tb) + 1.0);
+    safe &= fabs(ta - rint(ta)) > tola;
+    safe &= fabs(tb - rint(tb)) > tolb;
+    safe &= fabs(dh[d] - J.grid.hi[d]) > eps;
   }
-  const int64_t t = block_sum_i64(mine, lds);
-  if (threadIdx.x == 0) a.bsum[blockIdx.x] = t;
+  return safe;
 }
 
-template <int KIND, int N>
-__global__ __launch_bounds__(kRowBlock) void k_recheck(BuildArgs a) {
-  const int64_t n = *a.n_recheck;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = a.recheck[i];
-    const int32_t jb = job_of_row(a.jobs, a.n_jobs, a.K, g);
-    const Job& J = a.jobs[jb];
-    const int64_t lr = g - J.cell_off * a.K;
-    const Rk4Consts<double> kc = make_consts<double>(J.sys);
+// Edge count of a row and the first kCache target ids (local ids), stored
+// with stride kRowBlock from `cache`; *hole is set when a hole of the
+// covering meets the interior range (one walk of the closed range serves
+// both: every slot meeting the interior range lies in it).
+template <int N, bool UNI>
+__device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const uint8_t* lst,
+                                                 int64_t lslots, const Ranges<N>& r,
+                                                 int32_t* cache, bool* hole) {
+  *hole = false;
+  if (r.empty) return 0;
+  if (UNI || ci.uniform) {
+    int32_t c = 1;
+#pragma unroll
+    for (int d = 0; d < N; ++d) c *= r.hi[d] - r.lo[d] + 1;
+    return c;
+  }
+  int32_t c = 0;
+  bool h = false;
+  walk_levels<N>(ci, lst, lslots, r.lo, r.hi,
+                 [&](int L, int64_t slot, uint8_t st, const int32_t* k) {
+                   if (st == ST_LEAF) {
+                     if (c < kCache) cache[c * kRowBlock] = ci.id[slot];
+                     ++c;
+                   } else if (st == ST_HOLE && !h) {
+                     const int s = ci.lmax - L;
+                     bool in = true;
+#pragma unroll
+                     for (int d = 0; d < N; ++d)
+                       in &= k[d] >= (r.ilo[d] >> s) && k[d] <= (r.ihi[d] >> s);
+                     h = in;
+                   }
+                   return true;
+                 });
+  *hole = h;
+  return c;
+}
+
+// Targets p0 .. p1-1 of a row (0-based positions in its ascending target
+// list) as global ids into dst[0 .. p1-p0).
+template <int N, bool UNI>
+__device__ __forceinline__ void emit_targets(const CoverIndex& ci, const uint8_t* lst,
+                                             int64_t lslots, const int32_t* lo,
+                                             const int32_t* hi, int32_t count,
+                                             const int32_t* cache, int32_t id0, int32_t p0,
+                                             int32_t p1, int32_t* dst) {
+  if (UNI || ci.uniform) {
+    // position -> multi-index in the box, last dimension fastest
+    int32_t k[N];
+    int32_t rem = p0;
+#pragma unroll
+    for (int d = N - 1; d >= 0; --d) {
+      const int32_t w = hi[d] - lo[d] + 1;
+      k[d] = lo[d] + rem % w;
+      rem /= w;
+    }
+    for (int32_t p = p0; p < p1; ++p) {
+      int32_t lin = 0;
+#pragma unroll
+      for (int d = 0; d < N; ++d) lin = lin * ci.dims[0][d] + k[d];
+      dst[p - p0] = id0 + lin;
+      int d = N - 1;
+      while (d > 0 && k[d] == hi[d]) {
+        k[d] = lo[d];
+        --d;
+      }
+      ++k[d];
+    }
+    return;
+  }
+  if constexpr (UNI) return;
+  if (count <= kCache) {
+    for (int32_t p = p0; p < p1; ++p) dst[p - p0] = id0 + cache[p * kRowBlock];
+    return;
+  }
+  int32_t w = 0;
+  walk_levels<N>(ci, lst, lslots, lo, hi, [&](int, int64_t slot, uint8_t st, const int32_t*) {
+    if (st == ST_LEAF) {
+      if (w >= p0) dst[w - p0] = id0 + ci.id[slot];
+      if (++w >= p1) return false;
+    }
+    return true;
+  });
+}
+
+// UNI: every job of the launch is a full level-0 grid (no index walk is
+// compiled in, which keeps the register count, and so the occupancy, of the
+// image loop higher).
+template <int KIND, int N, bool F32, bool UNI>
+__global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
+  __shared__ CoverIndex ci;
+  __shared__ int32_t tile[kTile];
+  __shared__ int32_t cache[kCache * kRowBlock];
+  __shared__ uint8_t lst[kLdsIndex];
+  __shared__ int64_t wsum[kRowBlock / 64];
+  __shared__ int64_t s_prefix;
+  __shared__ uint32_t s_bid, s_out, s_rchk;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) {
+    const uint32_t t = atomicAdd(a.ticket, 1u);
+    // every other block has its ticket: reset the counter for the next launch
+    if (t == (uint32_t)a.n_blocks - 1)
+      __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_bid = t;
+    s_out = 0;
+    s_rchk = 0;
+  }
+  __syncthreads();
+  const int64_t bid = s_bid;
+  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, bid);
+  const Job& J = a.jobs[jb];
+  stage_index(&ci, &J.ci);
+  // the coarse levels of the index that fit go to LDS
+  int64_t lslots = 0;
+  if (!UNI && !ci.uniform) {
+    int Ls = 0;
+    while (Ls <= ci.lmax && ci.off[Ls + 1] <= kLdsIndex) ++Ls;
+    lslots = ci.off[Ls];
+    for (int64_t i = tid; i < lslots; i += kRowBlock) lst[i] = ci.state[i];
+    __syncthreads();
+  }
+
+  // ---- 1-2: images, box, cover decision, count
+  const int64_t lr = (bid - J.blk[LK_ROWS]) * kRowBlock + tid;
+  const bool live = lr < J.n_cells * a.K;
+  const int64_t g = J.cell_off * a.K + lr;
+  int32_t lo[N], hi[N];
+  int32_t c = 0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) lo[d] = hi[d] = 0;
+  if (live) {
     double bl[N], bh[N];
-    const bool finite = row_bbox<KIND, N, double>(a, J, kc, lr, bl, bh);
-    const int32_t c = decide_row<N>(a, J, J.ci, g, finite, bl, bh);
-    if (c)
-      atomicAdd((unsigned long long*)&a.bsum[J.blk[LK_ROWS] + lr / kRowBlock],
-                (unsigned long long)c);
+    bool finite;
+    if constexpr (F32) {
+      const Rk4Consts<float> kc = make_consts<float>(J.sys);
+      float fl[N], fh[N];
+      const bool fin32 = row_bbox<KIND, N, float>(a, J, kc, lr, fl, fh);
+      finite = fin32 && band_safe<N>(J, ci, fl, fh, bl, bh);
+      if (!finite) {
+        const Rk4Consts<double> kd = make_consts<double>(J.sys);
+        finite = row_bbox<KIND, N, double>(a, J, kd, lr, bl, bh);
+        atomicAdd(&s_rchk, 1u);
+      }
+    } else {
+      const Rk4Consts<double> kd = make_consts<double>(J.sys);
+      finite = row_bbox<KIND, N, double>(a, J, kd, lr, bl, bh);
+    }
+    bool out = true;
+    if (finite) {
+      const Ranges<N> rr = ranges_of<N>(J.grid, ci, bl, bh);
+      bool hole;
+      c = count_targets<N, UNI>(ci, lst, lslots, rr, cache + tid, &hole);
+      out = rr.outx || hole;
+      if (a.fast_out && out) c = 0;
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        lo[d] = rr.lo[d];
+        hi[d] = rr.hi[d];
+      }
+    }
+    a.out[g] = out ? 1 : 0;
+    if (out) atomicAdd(&s_out, 1u);
+  }
+
+  // ---- 3: block-exclusive scan of the counts
+  int64_t x = c;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  int64_t before = 0, T = 0;
+  for (int w = 0; w < kRowBlock / 64; ++w) {
+    before += w < wid ? wsum[w] : 0;
+    T += wsum[w];
+  }
+  const int64_t off = before + x - c;
+
+  // ---- 4: decoupled look-back (first wave; control flow wave-uniform)
+  if (wid == 0) {
+    const uint64_t tag = (uint64_t)a.epoch << 40;
+    int64_t prefix = 0;
+    if (bid == 0) {
+      if (lane == 0)
+        __hip_atomic_store(&a.lb[0], tag | kLbInc | (uint64_t)T, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (lane == 0)
+        __hip_atomic_store(&a.lb[bid], tag | kLbAgg | (uint64_t)T, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t t0 = wall_clock64();
+      int64_t top = bid - 1;  // lane i looks at block top - i
+      for (;;) {
+        const int64_t q = top - lane;
+        uint64_t w = 0;
+        for (uint32_t spin = 0;; ++spin) {
+          w = q >= 0 ? __hip_atomic_load(&a.lb[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : tag | kLbInc;
+          if (__ballot(lb_status(w, a.epoch) == 0) == 0) break;
+          if ((spin & 255) == 255 && wall_clock64() - t0 > 10ull * 100000000ull) {
+            // never expected: record it and leave with a wrong prefix (the
+            // capacity test below keeps every store in bounds)
+            if (lane == 0) atomicOr(a.err, 256u);
+            w = tag | kLbInc;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        const uint64_t inc = __ballot(lb_status(w, a.epoch) == 2);
+        const int first = inc ? __builtin_ctzll(inc) : 64;
+        int64_t v = lane <= first ? (int64_t)(w & kLbVal) : 0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        prefix += v;
+        if (inc) break;
+        top -= 64;
+      }
+      if (lane == 0) {
+        if ((uint64_t)(prefix + T) > kLbVal) atomicOr(a.err, 512u);  // beyond 2^38 edges
+        __hip_atomic_store(&a.lb[bid], tag | kLbInc | ((uint64_t)(prefix + T) & kLbVal),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (lane == 0) {
+      s_prefix = prefix;
+      if (bid == a.n_blocks - 1) *a.d_total = prefix + T;
+      atomicAdd((unsigned long long*)&a.stats[jb].n_edges, (unsigned long long)T);
+      if (s_out) atomicAdd(&a.stats[jb].n_out, (unsigned long long)s_out);
+      if (s_rchk) {
+        atomicAdd(&a.stats[jb].n_recheck, (unsigned long long)s_rchk);
+        atomicAdd(a.n_recheck, (unsigned long long)s_rchk);
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t prefix = s_prefix;
+
+  // ---- 5: row offsets and target ids
+  if (live) a.row_ptr[g] = prefix + off;
+  if (live && g == a.total_rows - 1) a.row_ptr[a.total_rows] = prefix + off + c;
+  if (prefix + T > a.cap_edges) return;  // capacity miss: col is not written
+  const int32_t id0 = (int32_t)J.cell_off;
+  for (int64_t w0 = 0; w0 < T; w0 += kTile) {
+    const int64_t w1 = T < w0 + kTile ? T : w0 + kTile;
+    const int64_t s0 = off > w0 ? off : w0;
+    const int64_t s1 = off + c < w1 ? off + c : w1;
+    if (s0 < s1)
+      emit_targets<N, UNI>(ci, lst, lslots, lo, hi, c, cache + tid, id0, (int32_t)(s0 - off),
+                      (int32_t)(s1 - off), tile + (s0 - w0));
+    __syncthreads();
+    for (int64_t i = tid; i < w1 - w0; i += kRowBlock) a.col[prefix + w0 + i] = tile[i];
+    __syncthreads();
   }
 }
 
@@ -370,10 +544,13 @@ __global__ __launch_bounds__(kRowBlock) void k_images(BuildArgs a, double* out) 
 // max |y32 - y64| per dimension (bit patterns of non-negative doubles order
 // like the values, so an integer atomicMax works).
 template <int KIND, int N>
-__global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned long long* maxerr) {
+__global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned long long* maxerr,
+                                                        int64_t stride) {
   const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
   const Job& J = a.jobs[jb];
-  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
+  const int64_t lb = blockIdx.x - J.blk[LK_ROWS];
+  if (lb % stride != 0) return;  // sample whole blocks: every lane of a wave does work
+  const int64_t lr = lb * kRowBlock + threadIdx.x;
   double e[N];
 #pragma unroll
   for (int d = 0; d < N; ++d) e[d] = 0.0;
@@ -424,97 +601,6 @@ __global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned l
   }
 }
 
-// ------------------------------------------------------------------ emit
-template <int N>
-__global__ __launch_bounds__(kRowBlock) void k_emit(EmitArgs a) {
-  __shared__ int32_t tile[kTile];
-  __shared__ int64_t wsum[kRowBlock / 64];
-  __shared__ CoverIndex ci;
-  const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, blockIdx.x);
-  const Job& J = a.jobs[jb];
-  stage_index(&ci, &J.ci);
-  const int64_t lr = (blockIdx.x - J.blk[LK_ROWS]) * kRowBlock + threadIdx.x;
-  const bool live = lr < J.n_cells * a.K;
-  const int64_t g = J.cell_off * a.K + lr;
-  const int32_t c = live ? a.cnt[g] : 0;
-  // block-exclusive scan of the counts
-  int64_t x = c;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wsum[wid] = x;
-  __syncthreads();
-  int64_t before = 0, total = 0;
-  for (int w = 0; w < kRowBlock / 64; ++w) {
-    before += w < wid ? wsum[w] : 0;
-    total += wsum[w];
-  }
-  const int64_t off = before + x - c;
-  const int64_t base = a.bscan[blockIdx.x];
-  if (live) a.row_ptr[g] = base + off;
-  if (live && g == a.total_rows - 1) a.row_ptr[a.total_rows] = base + off + c;
-  if (base + total > a.cap_edges) return;  // capacity miss: col is not written
-  const bool staged = total <= kTile;
-  if (c > 0) {
-    const int32_t* rg = a.rng + g * (2 * N);
-    int32_t lo[N], hi[N];
-#pragma unroll
-    for (int d = 0; d < N; ++d) {
-      lo[d] = rg[2 * d];
-      hi[d] = rg[2 * d + 1];
-    }
-    int32_t* dst = staged ? tile + off : a.col + base + off;
-    const int32_t id0 = (int32_t)J.cell_off;
-    int32_t w = 0;
-    if (ci.uniform) {
-      int32_t k[N];
-#pragma unroll
-      for (int d = 0; d < N; ++d) k[d] = lo[d];
-      for (;;) {
-        int32_t lin = 0;
-#pragma unroll
-        for (int d = 0; d < N; ++d) lin = lin * ci.dims[0][d] + k[d];
-        if (w < c) dst[w++] = id0 + lin;
-        int d = N - 1;
-        while (d >= 0 && k[d] == hi[d]) {
-          k[d] = lo[d];
-          --d;
-        }
-        if (d < 0) break;
-        ++k[d];
-      }
-    } else {
-      walk_levels<N>(ci, lo, hi, [&](int, int64_t slot, uint8_t st) {
-        if (st == ST_LEAF && w < c) dst[w++] = id0 + ci.id[slot];
-        return true;
-      });
-    }
-  }
-  if (staged) {
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < total; i += kRowBlock) a.col[base + i] = tile[i];
-  }
-}
-
-__global__ void k_job_edges(const Job* jobs, int32_t n_jobs, int32_t K, const int64_t* row_ptr,
-                            JobStats* stats) {
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_jobs) return;
-  const int64_t r0 = jobs[j].cell_off * K, r1 = (jobs[j].cell_off + jobs[j].n_cells) * K;
-  stats[j].n_edges = r1 > r0 ? row_ptr[r1] - row_ptr[r0] : 0;
-}
-
-__global__ void k_count_out(const uint8_t* out, int64_t n, unsigned long long* cnt) {
-  unsigned long long mine = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    mine += out[i];
-  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
-  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(cnt, mine);
-}
-
 // ------------------------------------------------------------------ dispatch
 template <template <int, int> class Launcher, typename... Args>
 int32_t dispatch_sys(int kind, int n, Args&&... args) {
@@ -540,30 +626,18 @@ int32_t dispatch_sys(int kind, int n, Args&&... args) {
 }
 
 template <int KIND, int N>
-struct CountF64 {
-  static int32_t run(const BuildArgs& a, hipStream_t s) {
+struct Build {
+  static int32_t run(const BuildArgs& a, int32_t precision, hipStream_t s) {
     if (a.n_blocks == 0) return GIS_OK;
-    hipLaunchKernelGGL((k_count_f64<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a);
-    GIS_LAUNCH_CHECK("k_count_f64");
-    return GIS_OK;
-  }
-};
-template <int KIND, int N>
-struct CountF32 {
-  static int32_t run(const BuildArgs& a, hipStream_t s) {
-    if (a.n_blocks == 0) return GIS_OK;
-    hipLaunchKernelGGL((k_count_f32<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a);
-    GIS_LAUNCH_CHECK("k_count_f32");
-    return GIS_OK;
-  }
-};
-template <int KIND, int N>
-struct Recheck {
-  static int32_t run(const BuildArgs& a, hipStream_t s) {
-    if (a.n_blocks == 0) return GIS_OK;
-    const unsigned nb = a.n_blocks < 2048 ? (unsigned)a.n_blocks : 2048u;
-    hipLaunchKernelGGL((k_recheck<KIND, N>), dim3(nb), dim3(kRowBlock), 0, s, a);
-    GIS_LAUNCH_CHECK("k_recheck");
+    const dim3 g((unsigned)a.n_blocks), b(kRowBlock);
+    if (precision == GIS_PREC_FP32_RECHECK) {
+      if (a.all_uniform) hipLaunchKernelGGL((k_build<KIND, N, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_build<KIND, N, true, false>), g, b, 0, s, a);
+    } else {
+      if (a.all_uniform) hipLaunchKernelGGL((k_build<KIND, N, false, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_build<KIND, N, false, false>), g, b, 0, s, a);
+    }
+    GIS_LAUNCH_CHECK("k_build");
     return GIS_OK;
   }
 };
@@ -581,68 +655,28 @@ struct Images {
 };
 template <int KIND, int N>
 struct Calibrate {
-  static int32_t run(const BuildArgs& a, unsigned long long* maxerr, hipStream_t s) {
+  static int32_t run(const BuildArgs& a, unsigned long long* maxerr, int64_t stride, hipStream_t s) {
     if (a.n_blocks == 0) return GIS_OK;
-    hipLaunchKernelGGL((k_calibrate<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a, maxerr);
+    hipLaunchKernelGGL((k_calibrate<KIND, N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a,
+                       maxerr, stride < 1 ? (int64_t)1 : stride);
     GIS_LAUNCH_CHECK("k_calibrate");
     return GIS_OK;
   }
 };
 
-template <int N>
-int32_t emit_n(const EmitArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_emit<N>), dim3((unsigned)a.n_blocks), dim3(kRowBlock), 0, s, a);
-  GIS_LAUNCH_CHECK("k_emit");
-  return GIS_OK;
-}
-
 }  // namespace
 
-int32_t launch_count(const BuildArgs& a, int32_t precision, hipStream_t s) {
-  if (precision == GIS_PREC_FP32_RECHECK) return dispatch_sys<CountF32>(a.kind, a.n, a, s);
-  return dispatch_sys<CountF64>(a.kind, a.n, a, s);
-}
-
-int32_t launch_recheck(const BuildArgs& a, hipStream_t s) {
-  return dispatch_sys<Recheck>(a.kind, a.n, a, s);
+int32_t launch_build(const BuildArgs& a, int32_t precision, hipStream_t s) {
+  return dispatch_sys<Build>(a.kind, a.n, a, precision, s);
 }
 
 int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s) {
   return dispatch_sys<Images>(a.kind, a.n, a, precision, d_images, s);
 }
 
-int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, hipStream_t s) {
-  return dispatch_sys<Calibrate>(a.kind, a.n, a, d_maxerr, s);
-}
-
-int32_t launch_emit(const EmitArgs& a, hipStream_t s) {
-  if (a.n_blocks == 0) return GIS_OK;
-  switch (a.n) {
-    case 1: return emit_n<1>(a, s);
-    case 2: return emit_n<2>(a, s);
-    case 3: return emit_n<3>(a, s);
-    case 4: return emit_n<4>(a, s);
-  }
-  set_error("unsupported dimension");
-  return GIS_E_UNSUPPORTED;
-}
-
-int32_t launch_job_edges(const Job* jobs, int32_t n_jobs, int32_t K, const int64_t* row_ptr,
-                         JobStats* stats, hipStream_t s) {
-  if (n_jobs == 0) return GIS_OK;
-  hipLaunchKernelGGL(k_job_edges, dim3((n_jobs + 63) / 64), dim3(64), 0, s, jobs, n_jobs, K,
-                     row_ptr, stats);
-  GIS_LAUNCH_CHECK("k_job_edges");
-  return GIS_OK;
-}
-
-int32_t count_out(const uint8_t* out, int64_t n, unsigned long long* d_count, hipStream_t s) {
-  if (n == 0) return GIS_OK;
-  int64_t nb = (n + 255) / 256;
-  if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_count_out, dim3((unsigned)nb), dim3(256), 0, s, out, n, d_count);
-  GIS_LAUNCH_CHECK("k_count_out");
-  return GIS_OK;
+int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64_t stride,
+                         hipStream_t s) {
+  return dispatch_sys<Calibrate>(a.kind, a.n, a, d_maxerr, stride, s);
 }
 
 }  // namespace gis

@@ -1,27 +1,28 @@
-// Graph analysis (Sec. 2.3) as a frontier computation on the device.
+// Graph analysis (Sec. 2.3) on the device.
 //
 // Both readings remove cells until a fixed point; the removed set is the least
 // fixed point of a monotone operator, so any removal order reaches it:
-//   controlled : row (c, u) turns bad when it is OUT or one of its targets is
+//   controlled : row (c, u) is bad when it is OUT or one of its targets is
 //                removed; a cell is removed when all its rows are bad;
-//   nonleaving : row (c, u) dies when all its targets are removed; a cell is
-//                removed when all its rows are dead (a cell with no path to a
-//                cycle of the input-union symbolic image, Definition 6).
-// Steps: in-degree histogram -> offsets -> scatter of source rows (reverse
-// CSR) -> initial counts and first removals -> one persistent launch that
-// drains a device work queue (a wave per removed cell, its lanes over the
-// cell's in-rows) and stops by itself when no work is left in flight ->
-// kept flags and admissible-input masks.
+//   nonleaving : row (c, u) is dead when all its targets are removed; a cell
+//                is removed when all its rows are dead (a cell with no path
+//                to a cycle of the input-union symbolic image, Definition 6).
+// Two phases, both pulling each row's state from the removed flags of its
+// targets (no per-edge atomics):
+//   sweeps   : whole-graph passes, in place, until one removes nothing -- few
+//              launches when the removal chains are short, and no reverse
+//              graph to build;
+//   frontier : for long chains, a breadth-first peel over the reverse CSR
+//              (in-degree histogram -> offsets -> scatter), each step
+//              expanding the cells removed in the step before.
+// The host runs a batch of sweeps and switches to the frontier phase when
+// they have not converged.  The final pass writes kept flags and masks.
 #include "gis_internal.h"
 
 namespace gis {
 
 namespace {
 
-// qctl layout: one 128-byte line per counter, so waves polling `pending`
-// do not contend with the increments of `alloc` and `head`
-constexpr int Q_ALLOC = 0, Q_HEAD = 32, Q_PENDING = 64, Q_ERROR = 96, Q_WORDS = 128;
-constexpr int32_t kSlotDone = -2;  // written into waiting slots once nothing is left
 constexpr int kHash = 2048;        // LDS hash slots of the reverse-CSR kernels
 constexpr int kProbe = 64;
 
@@ -53,7 +54,9 @@ __device__ __forceinline__ int lds_slot(int32_t* key, int32_t j, bool insert) {
 // cells), so counts are first aggregated per distinct target in LDS and
 // flushed with one global atomic per target.
 __global__ __launch_bounds__(256) void k_indegree(const int64_t* row_ptr, const int32_t* col,
-                                                  int64_t n_rows, int32_t* deg) {
+                                                  int64_t n_rows, int32_t* deg,
+                                                  const int64_t* d_total, int64_t cap_edges) {
+  if (d_total && *d_total > cap_edges) return;  // col was not written
   __shared__ int32_t key[kHash];
   __shared__ int32_t cnt[kHash];
   for (int i = threadIdx.x; i < kHash; i += 256) {
@@ -81,7 +84,9 @@ __global__ __launch_bounds__(256) void k_indegree(const int64_t* row_ptr, const 
 // the block's edges fill it through LDS counters.
 __global__ __launch_bounds__(256) void k_scatter(const int64_t* row_ptr, const int32_t* col,
                                                  int64_t n_rows, const int64_t* rptr,
-                                                 int32_t* cursor, int32_t* rrow) {
+                                                 int32_t* cursor, int32_t* rrow,
+                                                 const int64_t* d_total, int64_t cap_edges) {
+  if (d_total && *d_total > cap_edges) return;  // col was not written
   __shared__ int32_t key[kHash];
   __shared__ int32_t cnt[kHash];
   __shared__ int32_t base[kHash];
@@ -98,16 +103,18 @@ __global__ __launch_bounds__(256) void k_scatter(const int64_t* row_ptr, const i
     if (sl >= 0) atomicAdd(&cnt[sl], 1);
   }
   __syncthreads();
+  // cursors count down from the in-degree, so they end at zero (the state
+  // the in-degree histogram of the next call starts from)
   for (int i = threadIdx.x; i < kHash; i += 256)
     if (key[i] >= 0) {
-      base[i] = atomicAdd(&cursor[key[i]], cnt[i]);
+      base[i] = atomicSub(&cursor[key[i]], cnt[i]) - cnt[i];
       cnt[i] = 0;
     }
   __syncthreads();
   for (int64_t e = e0; e < e1; ++e) {
     const int32_t j = col[e];
     const int sl = lds_slot(key, j, false);
-    const int32_t pos = sl >= 0 ? base[sl] + atomicAdd(&cnt[sl], 1) : atomicAdd(&cursor[j], 1);
+    const int32_t pos = sl >= 0 ? base[sl] + atomicAdd(&cnt[sl], 1) : atomicSub(&cursor[j], 1) - 1;
     rrow[rptr[j] + pos] = (int32_t)r;
   }
 }
@@ -129,150 +136,186 @@ __global__ void k_check_graph(const int64_t* row_ptr, const int32_t* col, int64_
   }
 }
 
-// bad bits of the controlled analysis: a row starts bad when it is OUT.
-__global__ void k_badbits_init(const uint8_t* out, int64_t n_rows, uint32_t* bits) {
-  const int64_t words = (n_rows + 31) / 32;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
-       w += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t b = 0;
-    for (int i = 0; i < 32; ++i) {
-      const int64_t r = w * 32 + i;
-      if (r < n_rows && out[r]) b |= 1u << i;
-    }
-    bits[w] = b;
-  }
-}
-
-// Every piece of state the drain shares (row flags, cell counters, the queue
-// and its counters) changes only through agent-scope atomics, so relaxed
-// ordering suffices and no cache-wide fence is issued (on this GPU an
-// acquire or release at agent scope invalidates or writes back an XCD's whole
-// L2).  Termination needs only the modification order of `pending`: a cell's
-// increment precedes the decrement of the item whose processing pushed it
-// (same thread, same location), so `pending` stays >= 1 until every pushed
-// cell has been processed.
-__device__ __forceinline__ void push_removed(int32_t* queue, int32_t* qctl, int32_t cell) {
-  __hip_atomic_fetch_add(&qctl[Q_PENDING], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int32_t slot =
-      __hip_atomic_fetch_add(&qctl[Q_ALLOC], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&queue[slot], cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// Is row r good, given the removed flags of the cells?
+//   controlled : not OUT and no target removed;
+//   nonleaving : some target not removed.
 template <int MODE>
-__global__ void k_prune_init(const int64_t* row_ptr, int64_t n_cells, int32_t K,
-                             const uint32_t* bits, int32_t* alive, int32_t* good, int32_t* queue,
-                             int32_t* qctl) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    int32_t g = 0;
-    for (int32_t u = 0; u < K; ++u) {
-      const int64_t r = c * K + u;
-      if (MODE == GIS_ANALYSIS_CONTROLLED) {
-        g += !((bits[r >> 5] >> (r & 31)) & 1u);
-      } else {
-        const int32_t deg = (int32_t)(row_ptr[r + 1] - row_ptr[r]);
-        alive[r] = deg;
-        g += deg > 0;
-      }
-    }
-    good[c] = g;
-    if (g == 0) push_removed(queue, qctl, (int32_t)c);
+__device__ __forceinline__ bool row_good(const int64_t* row_ptr, const int32_t* col,
+                                         const uint8_t* out, const uint8_t* removed, int64_t r) {
+  const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+  if (MODE == GIS_ANALYSIS_CONTROLLED) {
+    if (out[r]) return false;
+    for (int64_t e = a; e < b; ++e)
+      if (removed[col[e]]) return false;
+    return true;
   }
+  for (int64_t e = a; e < b; ++e)
+    if (!removed[col[e]]) return true;
+  return false;
 }
 
-// Persistent drain of the removal queue, one wave per block.  The loop
-// skeleton has no lane-dependent branch: the queue counters are updated by
-// atomics every lane executes (lane 0 contributes the increment, the others
-// add 0), the claimed slot and the removed cell are read into scalar
-// registers (readfirstlane), and every exit tests a scalar.  So all lanes of
-// the wave run the same iterations; only the loop over a cell's in-rows is
-// lane-divergent, and it has no early exit.  Exit conditions every wave
-// reaches: the claimed slot is past the last possible slot, or it is still
-// empty while nothing is in flight (no further removal can happen), or a
-// wall-clock limit (sets the error word; never expected).
+// One sweep over every cell still present: a thread per row evaluates it,
+// then a thread per cell removes the cell if none of its rows is good.  A
+// block takes cpb = floor(256 / K) whole cells at a time.  Updates are made
+// in place, so a sweep may already see removals of the same sweep; the
+// result does not depend on that, because removal is monotone: a sweep that
+// removes nothing has evaluated every cell against a constant set, which is
+// then the fixed point.  `last` holds 1 + the index of the last sweep that
+// removed a cell; sweep s starts only if sweep s-1 removed one.
 template <int MODE>
-__global__ __launch_bounds__(64) void k_prune_run(const int64_t* rptr, const int32_t* rrow,
-                                                  int64_t n_cells, int32_t K, uint32_t* bits,
-                                                  int32_t* alive, int32_t* good, int32_t* queue,
-                                                  int32_t* qctl) {
-  const int lane = threadIdx.x;
-  const int32_t one = lane == 0 ? 1 : 0;
-  const uint64_t t0 = wall_clock64();
-  const uint64_t limit = 60ull * 100000000ull;  // 60 s of the 100 MHz constant clock
-  for (;;) {
-    const int32_t i = __builtin_amdgcn_readfirstlane(
-        __hip_atomic_fetch_add(&qctl[Q_HEAD], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if ((int64_t)i >= n_cells) break;
-    int32_t c = -1;
-    for (uint32_t spin = 0;; ++spin) {
-      c = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(&queue[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      if (c >= 0 || c == kSlotDone) break;
-      if ((spin & 63) == 0) {  // rarely: a slot claimed after the sentinels were written
-        const int32_t pend = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&qctl[Q_PENDING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        if (pend == 0) break;
-        if (wall_clock64() - t0 > limit) {
-          __hip_atomic_fetch_or(&qctl[Q_ERROR], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
+__global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int32_t* col,
+                                               const uint8_t* out, int64_t n_cells, int32_t K,
+                                               int32_t cpb, uint8_t* removed, int32_t* last,
+                                               int32_t s, const int64_t* d_total,
+                                               int64_t cap_edges) {
+  if (d_total && *d_total > cap_edges) return;  // col was not written
+  if (s > 0 && *last < s) return;               // converged already
+  __shared__ uint8_t ok[256];
+  bool changed = false;
+  const int t = threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * cpb;
+  for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
+    const int64_t c = g0 + t / K;
+    bool good = false;
+    if (t < cpb * K && c < n_cells && !removed[c])
+      good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
+    ok[t] = good ? 1 : 0;
+    __syncthreads();
+    if (t < cpb) {
+      const int64_t cc = g0 + t;
+      if (cc < n_cells && !removed[cc]) {
+        bool any = false;
+        for (int u = 0; u < K; ++u) any |= ok[t * K + u] != 0;
+        if (!any) {
+          removed[cc] = 1;
+          changed = true;
         }
       }
-      __builtin_amdgcn_s_sleep(2);
     }
-    if (c < 0) break;
-    const int64_t b = rptr[c], e = rptr[c + 1];
-    for (int64_t p = b + lane; p < e; p += 64) {
-      const int32_t r = rrow[p];
-      bool died;
-      if (MODE == GIS_ANALYSIS_CONTROLLED) {
-        const uint32_t bit = 1u << (r & 31);
-        died = !(atomicOr(&bits[r >> 5], bit) & bit);
-      } else {
-        died = atomicSub(&alive[r], 1) == 1;
+    __syncthreads();
+  }
+  if (__ballot(changed) && (t & 63) == 0) atomicMax(last, s + 1);
+}
+
+// ---- frontier phase (long removal chains): a breadth-first peel over the
+// reverse CSR, every step two launches, no per-edge atomics.  It runs only
+// after a synchronisation has shown the graph complete.
+// rowbad: controlled -> row is OUT or has a removed target; nonleaving -> all
+// targets removed.  Initial values, and the first frontier: every removed
+// cell plus every cell whose rows are all bad already.
+template <int MODE>
+__global__ void k_front_init(const int64_t* row_ptr, const uint8_t* out, int64_t n_cells,
+                             int32_t K, uint8_t* removed, uint8_t* rowbad, int32_t* front,
+                             int32_t* count) {
+  for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
+       c0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    bool rem = false;
+    if (c < n_cells) {
+      bool all = true;
+      for (int32_t u = 0; u < K; ++u) {
+        const int64_t r = c * K + u;
+        const bool bad =
+            MODE == GIS_ANALYSIS_CONTROLLED ? out[r] != 0 : row_ptr[r + 1] == row_ptr[r];
+        rowbad[r] = bad ? 1 : 0;
+        all &= bad;
       }
-      if (died) {
-        const int32_t cell = r / K;
-        if (atomicSub(&good[cell], 1) == 1) push_removed(queue, qctl, cell);
-      }
+      if (all) removed[c] = 1;
+      rem = removed[c] != 0;
     }
-    const int32_t before = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
-        &qctl[Q_PENDING], -one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (before == 1) {
-      // nothing is in flight and nothing can be pushed any more: release the
-      // waves waiting on claimed but empty slots
-      const int32_t a0 = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(&qctl[Q_ALLOC], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      int64_t h = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(&qctl[Q_HEAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      h = h < n_cells ? h : n_cells;
-      for (int64_t q = a0 + lane; q < h; q += 64)
-        __hip_atomic_store(&queue[q], kSlotDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t m = __ballot(rem);  // one counter atomic per wave
+    if (m) {
+      const int lane = threadIdx.x & 63;
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(count, (int32_t)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (rem) front[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)c;
     }
   }
 }
 
+// Expand: a wave per frontier cell, its lanes over the cell's in-rows; a row
+// that turns bad marks its cell as a candidate.  Also clears the count of
+// the list the following evaluate launch appends to.
 template <int MODE>
-__global__ void k_prune_final(int64_t n_cells, int32_t K, const uint32_t* bits,
-                              const int32_t* alive, const int32_t* good, uint8_t* kept,
+__global__ __launch_bounds__(64) void k_front_expand(const int64_t* rptr, const int32_t* rrow,
+                                                     const int64_t* row_ptr, const int32_t* col,
+                                                     int32_t K, const uint8_t* removed,
+                                                     uint8_t* rowbad, uint8_t* cand,
+                                                     const int32_t* front, const int32_t* count,
+                                                     int32_t* next_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+  const int32_t n = *count;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int32_t c = front[i];
+    const int64_t b = rptr[c], e = rptr[c + 1];
+    for (int64_t p = b + threadIdx.x; p < e; p += 64) {
+      const int32_t r = rrow[p];
+      if (rowbad[r]) continue;
+      if (MODE == GIS_ANALYSIS_CONTROLLED || !row_good<MODE>(row_ptr, col, nullptr, removed, r)) {
+        rowbad[r] = 1;
+        cand[r / K] = 1;
+      }
+    }
+  }
+}
+
+// Evaluate the candidates: a cell all of whose rows are bad is removed and
+// joins the next frontier (one counter atomic per wave).
+__global__ void k_front_eval(int64_t n_cells, int32_t K, uint8_t* removed, const uint8_t* rowbad,
+                             uint8_t* cand, const int32_t* count, int32_t* next_front,
+                             int32_t* next_count) {
+  if (*count == 0) return;  // nothing was expanded, so no candidate was marked
+  for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
+       c0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    bool rem = false;
+    if (c < n_cells && cand[c]) {
+      cand[c] = 0;
+      if (!removed[c]) {
+        // no early exit: the loads of a batch are independent
+        int32_t nbad = 0;
+        const uint8_t* rb = rowbad + c * K;
+#pragma unroll 8
+        for (int32_t u = 0; u < K; ++u) nbad += rb[u];
+        if (nbad == K) {
+          removed[c] = 1;
+          rem = true;
+        }
+      }
+    }
+    const uint64_t m = __ballot(rem);
+    if (m) {
+      const int lane = threadIdx.x & 63;
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(next_count, (int32_t)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (rem) next_front[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)c;
+    }
+  }
+}
+
+// kept flags, admissible-input masks and the kept count from the removed
+// flags (rows evaluated against the final set).
+template <int MODE>
+__global__ void k_prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                              int64_t n_cells, int32_t K, const uint8_t* removed, uint8_t* kept,
                               uint64_t* mask, int32_t W, unsigned long long* nkept,
-                              const int32_t* qctl, int32_t* err_out) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *err_out = qctl[Q_ERROR];
+                              const int64_t* d_total, int64_t cap_edges, const int32_t* last,
+                              int32_t sweeps) {
+  if (d_total && *d_total > cap_edges) return;  // col was not written
+  if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
   unsigned long long mine = 0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
        c += (int64_t)gridDim.x * blockDim.x) {
-    const bool k = good[c] > 0;
+    const bool k = !removed[c];
     kept[c] = k ? 1 : 0;
     mine += k;
     for (int w = 0; w < W; ++w) {
       uint64_t m = 0;
-      if (k) {
-        for (int b = 0; b < 64 && w * 64 + b < K; ++b) {
-          const int64_t r = c * K + w * 64 + b;
-          const bool ok = MODE == GIS_ANALYSIS_CONTROLLED ? !((bits[r >> 5] >> (r & 31)) & 1u)
-                                                           : alive[r] > 0;
-          m |= (uint64_t)ok << b;
-        }
-      }
+      if (k)
+        for (int b = 0; b < 64 && w * 64 + b < K; ++b)
+          m |= (uint64_t)row_good<MODE>(row_ptr, col, out, removed, c * K + w * 64 + b) << b;
       mask[c * W + w] = m;
     }
   }
@@ -280,48 +323,81 @@ __global__ void k_prune_final(int64_t n_cells, int32_t K, const uint32_t* bits,
   if ((threadIdx.x & 63) == 0 && mine) atomicAdd(nkept, mine);
 }
 
-template <int MODE>
-int32_t prune_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* out, int64_t n_cells,
-                   int32_t K, int64_t n_edges, const PruneWork& w, uint8_t* kept, uint64_t* mask,
-                   int32_t W, unsigned long long* d_nkept, hipStream_t s) {
+// reverse CSR of a graph: in-degree histogram -> offsets -> scatter (the
+// cursors count down to zero again)
+int32_t reverse_csr(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                    const PruneWork& w, hipStream_t s) {
   const int64_t n_rows = n_cells * K;
-  int32_t rc;
-  // reverse CSR
   const unsigned row_blocks = (unsigned)((n_rows + 255) / 256);
-  if ((rc = fill_i32(w.rcur, 0, n_cells, s)) != GIS_OK) return rc;
-  if (n_edges > 0) {
-    hipLaunchKernelGGL(k_indegree, dim3(row_blocks), dim3(256), 0, s, row_ptr, col, n_rows, w.rcur);
+  int32_t rc;
+  if (n_rows > 0) {
+    hipLaunchKernelGGL(k_indegree, dim3(row_blocks), dim3(256), 0, s, row_ptr, col, n_rows, w.rcur,
+                       w.d_total, w.cap_edges);
     GIS_LAUNCH_CHECK("k_indegree");
   }
   if ((rc = scan_exclusive_i32(w.rcur, w.rptr, n_cells, w.rptr + n_cells, w.scan_tmp, s)) != GIS_OK)
     return rc;
-  if ((rc = fill_i32(w.rcur, 0, n_cells, s)) != GIS_OK) return rc;
-  if (n_edges > 0) {
+  if (n_rows > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(row_blocks), dim3(256), 0, s, row_ptr, col, n_rows, w.rptr,
-                       w.rcur, w.rrow);
+                       w.rcur, w.rrow, w.d_total, w.cap_edges);
     GIS_LAUNCH_CHECK("k_scatter");
   }
-  // initial state
-  if ((rc = fill_i32(w.qctl, 0, Q_WORDS, s)) != GIS_OK) return rc;
-  if ((rc = fill_i32(w.queue, -1, n_cells, s)) != GIS_OK) return rc;
-  if (MODE == GIS_ANALYSIS_CONTROLLED) {
-    hipLaunchKernelGGL(k_badbits_init, dim3(grid_for((n_rows + 31) / 32)), dim3(256), 0, s, out,
-                       n_rows, w.badbits);
-    GIS_LAUNCH_CHECK("k_badbits_init");
+  return GIS_OK;
+}
+
+template <int MODE>
+int32_t sweeps_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                    int64_t n_cells, int32_t K, const PruneWork& w, int32_t s0, int32_t count,
+                    hipStream_t s) {
+  const int32_t cpb = 256 / K;
+  const int64_t groups = (n_cells + cpb - 1) / cpb;
+  const unsigned nb = (unsigned)(groups < 4096 ? (groups > 0 ? groups : 1) : 4096);
+  for (int32_t i = 0; i < count; ++i) {
+    hipLaunchKernelGGL((k_sweep<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out, n_cells, K,
+                       cpb, w.removed, w.last, s0 + i, w.d_total, w.cap_edges);
+    GIS_LAUNCH_CHECK("k_sweep");
   }
-  hipLaunchKernelGGL((k_prune_init<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr,
-                     n_cells, K, (const uint32_t*)w.badbits, w.alive, w.good, w.queue, w.qctl);
-  GIS_LAUNCH_CHECK("k_prune_init");
-  // persistent drain: one wave per block, two per SIMD
-  const int64_t waves = n_cells < 2048 ? (n_cells > 0 ? n_cells : 1) : 2048;
-  hipLaunchKernelGGL((k_prune_run<MODE>), dim3((unsigned)waves), dim3(64), 0, s,
-                     (const int64_t*)w.rptr, (const int32_t*)w.rrow, n_cells, K, w.badbits,
-                     w.alive, w.good, w.queue, w.qctl);
-  GIS_LAUNCH_CHECK("k_prune_run");
-  if ((rc = fill_u32((uint32_t*)d_nkept, 0u, 2, s)) != GIS_OK) return rc;
-  hipLaunchKernelGGL((k_prune_final<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, n_cells, K,
-                     (const uint32_t*)w.badbits, (const int32_t*)w.alive, (const int32_t*)w.good,
-                     kept, mask, W, d_nkept, (const int32_t*)w.qctl, w.err_out);
+  return GIS_OK;
+}
+
+template <int MODE>
+int32_t frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                       const PruneWork& w, int32_t t0, int32_t count, hipStream_t s) {
+  for (int32_t i = 0; i < count; ++i) {
+    const int t = (t0 + i) & 1;
+    int32_t* cur = w.front + (t ? n_cells : 0);
+    int32_t* nxt = w.front + (t ? 0 : n_cells);
+    hipLaunchKernelGGL((k_front_expand<MODE>), dim3(2048), dim3(64), 0, s, (const int64_t*)w.rptr,
+                       (const int32_t*)w.rrow, row_ptr, col, K, (const uint8_t*)w.removed,
+                       w.rowbad, w.cand, (const int32_t*)cur, (const int32_t*)(w.fcount + t),
+                       w.fcount + (1 - t));
+    GIS_LAUNCH_CHECK("k_front_expand");
+    hipLaunchKernelGGL(k_front_eval, dim3(grid_for(n_cells, 4096)), dim3(256), 0, s, n_cells, K,
+                       w.removed, (const uint8_t*)w.rowbad, w.cand, (const int32_t*)(w.fcount + t),
+                       nxt, w.fcount + (1 - t));
+    GIS_LAUNCH_CHECK("k_front_eval");
+  }
+  return GIS_OK;
+}
+
+template <int MODE>
+int32_t frontier_init(const int64_t* row_ptr, const uint8_t* out, int64_t n_cells, int32_t K,
+                      const PruneWork& w, hipStream_t s) {
+  int32_t rc;
+  if ((rc = fill_i32(w.fcount, 0, 2, s)) != GIS_OK) return rc;
+  hipLaunchKernelGGL((k_front_init<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr, out,
+                     n_cells, K, w.removed, w.rowbad, w.front, w.fcount);
+  GIS_LAUNCH_CHECK("k_front_init");
+  return GIS_OK;
+}
+
+template <int MODE>
+int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                   int64_t n_cells, int32_t K, const PruneWork& w, uint8_t* kept, uint64_t* mask,
+                   int32_t W, unsigned long long* d_nkept, int32_t sweeps, hipStream_t s) {
+  hipLaunchKernelGGL((k_prune_final<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr, col,
+                     out, n_cells, K, (const uint8_t*)w.removed, kept, mask, W, d_nkept, w.d_total,
+                     w.cap_edges, (const int32_t*)w.last, sweeps);
   GIS_LAUNCH_CHECK("k_prune_final");
   return GIS_OK;
 }
@@ -338,15 +414,45 @@ int32_t launch_check_graph(const int64_t* row_ptr, const int32_t* col, int64_t n
   return GIS_OK;
 }
 
-int32_t launch_prune(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
-                     int64_t n_cells, int32_t K, int64_t n_edges, int32_t analysis,
-                     const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t mask_words,
-                     unsigned long long* d_nkept, hipStream_t s) {
+int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                     int32_t first, int32_t count, hipStream_t s) {
+  if (n_cells == 0 || count <= 0) return GIS_OK;
   if (analysis == GIS_ANALYSIS_NONLEAVING)
-    return prune_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, n_edges, w, kept, mask,
-                                               mask_words, d_nkept, s);
-  return prune_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, n_edges, w, kept, mask,
-                                             mask_words, d_nkept, s);
+    return sweeps_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, first, count, s);
+  return sweeps_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, first, count, s);
+}
+
+int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                             int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                             hipStream_t s) {
+  if (n_cells == 0) return GIS_OK;
+  int32_t rc;
+  if ((rc = reverse_csr(row_ptr, col, n_cells, K, w, s)) != GIS_OK) return rc;
+  if (analysis == GIS_ANALYSIS_NONLEAVING)
+    return frontier_init<GIS_ANALYSIS_NONLEAVING>(row_ptr, out, n_cells, K, w, s);
+  return frontier_init<GIS_ANALYSIS_CONTROLLED>(row_ptr, out, n_cells, K, w, s);
+}
+
+int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                             int32_t analysis, const PruneWork& w, int32_t first, int32_t count,
+                             hipStream_t s) {
+  if (n_cells == 0 || count <= 0) return GIS_OK;
+  if (analysis == GIS_ANALYSIS_NONLEAVING)
+    return frontier_steps<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, n_cells, K, w, first, count, s);
+  return frontier_steps<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, n_cells, K, w, first, count, s);
+}
+
+int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                    int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                    uint8_t* kept, uint64_t* mask, int32_t mask_words,
+                    unsigned long long* d_nkept, int32_t sweeps, hipStream_t s) {
+  if (n_cells == 0) return GIS_OK;
+  if (analysis == GIS_ANALYSIS_NONLEAVING)
+    return final_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, kept, mask,
+                                               mask_words, d_nkept, sweeps, s);
+  return final_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, kept, mask,
+                                             mask_words, d_nkept, sweeps, s);
 }
 
 }  // namespace gis

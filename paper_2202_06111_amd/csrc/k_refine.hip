@@ -94,7 +94,8 @@ __global__ void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule, uint8
     }
     boundary[gc] = bnd ? 1 : 0;
   }
-  if (bnd) atomicAdd(&stats[jb].n_boundary, 1ull);
+  const uint64_t m = __ballot(bnd);  // one atomic per wave (blocks never straddle jobs)
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_boundary, (unsigned long long)__popcll(m));
 }
 
 template <int N>
@@ -124,6 +125,7 @@ __global__ void k_next_flags(BatchArgs b, const uint8_t* kept, const uint8_t* bo
 }
 
 // pos: exclusive scan of the batch's flag array (jobs' arrays back to back).
+// Clears every flag it consumes, so the array is zero for the next call.
 __global__ void k_compact(BatchArgs b, const int64_t* pos, int64_t cap, uint8_t* level_out,
                           int32_t* idx_out) {
   const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_NEXT, blockIdx.x);
@@ -131,6 +133,7 @@ __global__ void k_compact(BatchArgs b, const int64_t* pos, int64_t cap, uint8_t*
   const CoverIndex& next = J.next;
   const int64_t sl = (blockIdx.x - J.blk[LK_NEXT]) * blockDim.x + threadIdx.x;
   if (!next.state || sl >= next.off[next.lmax + 1] || !next.state[sl]) return;
+  next.state[sl] = 0;
   const int64_t p = pos[J.next_off + sl];
   if (p >= cap) return;
   int L = 0;
@@ -170,14 +173,9 @@ __global__ void k_count_kept(BatchArgs b, const uint8_t* kept, JobStats* stats) 
   const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
   const Job& J = b.jobs[jb];
   const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
-  if (c < J.n_cells && kept[J.cell_off + c]) atomicAdd(&stats[jb].n_kept, 1ull);
-}
-
-__global__ void k_count_out_rows(BatchArgs b, const uint8_t* out, JobStats* stats) {
-  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_ROWS, blockIdx.x);
-  const Job& J = b.jobs[jb];
-  const int64_t r = (blockIdx.x - J.blk[LK_ROWS]) * blockDim.x + threadIdx.x;
-  if (r < J.n_cells * b.K && out[J.cell_off * b.K + r]) atomicAdd(&stats[jb].n_out, 1ull);
+  // one atomic per wave (a block never straddles two jobs)
+  const uint64_t m = __ballot(c < J.n_cells && kept[J.cell_off + c]);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_kept, (unsigned long long)__popcll(m));
 }
 
 }  // namespace
@@ -237,14 +235,6 @@ int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stat
   hipLaunchKernelGGL(k_count_kept, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept,
                      stats);
   GIS_LAUNCH_CHECK("k_count_kept");
-  return GIS_OK;
-}
-
-int32_t batch_count_out(const BatchArgs& b, const uint8_t* out, JobStats* stats, hipStream_t s) {
-  if (b.blocks[LK_ROWS] == 0) return GIS_OK;
-  hipLaunchKernelGGL(k_count_out_rows, dim3((unsigned)b.blocks[LK_ROWS]), dim3(256), 0, s, b, out,
-                     stats);
-  GIS_LAUNCH_CHECK("k_count_out_rows");
   return GIS_OK;
 }
 

@@ -1,16 +1,21 @@
 """Continuous-batching serving loop for GIS solves.
 
 Requests (a system, a state box, a grid, an input set, and a batch of query
-states) arrive on a Poisson clock.  A request is admitted when a slot is free
-and its estimated device memory fits in the budget still free; admitted
-requests run concurrently, each slot owning a libgis context and its own HIP
-stream, so their kernels overlap on the device (the library releases the GIL
-inside every call).  A solve's result stays on the device until its
-membership and admissible-input queries are answered.  Latency is measured
-from the request's arrival to the answer of its last query.
+states) arrive on a Poisson clock.  Whenever one of the server's slots is
+free, the dispatcher takes the requests waiting at that moment, in arrival
+order, as long as their estimated device memory fits in what is left of the
+budget, and runs them as one batch: one gis_solve_batch call pushes all of
+them through shared kernel launches.  Each slot owns a libgis context and its
+own HIP stream, so batches of different slots overlap on the device (the
+library releases the GIL inside every call), and requests arriving while
+batches run join the next batch as soon as a slot and memory free up.  A
+solve's result stays on the device until its membership and admissible-input
+queries are answered.  Latency is measured from the request's arrival to the
+answer of its last query.
 """
 from __future__ import annotations
 
+import collections
 import dataclasses
 import statistics
 import threading
@@ -77,6 +82,27 @@ class Admission:
             self.max_in_use = max(self.max_in_use, self._in_use)
             return self._free.pop()
 
+    def acquire_slot(self) -> int:
+        """Blocks until a slot is free and takes it."""
+        with self._cv:
+            while not self._free:
+                self._cv.wait()
+            return self._free.pop()
+
+    def reserve(self, need: int, block: bool) -> bool:
+        """Takes `need` bytes of the budget; without `block`, only if they fit now."""
+        need = min(int(need), self.budget)
+        with self._cv:
+            if self._in_use + need > self.budget:
+                self.deferred += 1
+                if not block:
+                    return False
+                while self._in_use + need > self.budget:
+                    self._cv.wait()
+            self._in_use += need
+            self.max_in_use = max(self.max_in_use, self._in_use)
+            return True
+
     def release(self, slot: int, need: int) -> None:
         need = min(int(need), self.budget)
         with self._cv:
@@ -126,30 +152,86 @@ class Server:
         return Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"], info["n_kept"],
                       member_h, adm_h)
 
-    def run(self, requests: List[W.ServeRequest], realtime: bool = True) -> dict:
+    @staticmethod
+    def _compatible(a: W.Workload, b: W.Workload) -> bool:
+        key = lambda w: (w.system.kind, w.system.n, w.system.m, w.K, w.rounds, w.samples,
+                         w.precision, w.boundary_rule, w.analysis)
+        return key(a) == key(b)
+
+    def _serve_batch(self, slot: int, reqs: List[W.ServeRequest], t0: float) -> List[Result]:
+        ctx, stream = self.ctxs[slot], self.streams[slot]
+        start = time.perf_counter() - t0
+        out = []
+        with torch.cuda.stream(stream):
+            sols = gis.solve_batch(ctx, [r.workload for r in reqs], stream)
+            try:
+                for req, sol in zip(reqs, sols):
+                    states = torch.as_tensor(req.queries, device=ctx.dev)
+                    kinds = torch.as_tensor(req.kinds, device=ctx.dev)
+                    mem_idx = torch.nonzero(kinds == 0).squeeze(1)
+                    adm_idx = torch.nonzero(kinds == 1).squeeze(1)
+                    member = sol.query_membership(states.index_select(0, mem_idx).contiguous(), stream)
+                    adm = sol.query_admissible(states.index_select(0, adm_idx).contiguous(), stream)
+                    member_h = member.cpu().numpy()
+                    adm_h = adm.cpu().numpy().view(np.uint64)
+                    info = sol.info()
+                    done = time.perf_counter() - t0
+                    out.append(Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"],
+                                      info["n_kept"], member_h, adm_h))
+            finally:
+                for sol in sols:
+                    sol.free()
+        return out
+
+    def run(self, requests: List[W.ServeRequest], realtime: bool = True,
+            max_batch: int = 16) -> dict:
         """Serves the stream; returns per-request results and summary stats."""
         results: List[Optional[Result]] = [None] * len(requests)
         errors: List[BaseException] = []
-        t0 = time.perf_counter()
+        pending = collections.deque(sorted(range(len(requests)),
+                                           key=lambda i: requests[i].arrival_s))
+        waiting: collections.deque = collections.deque()
+        batch_sizes: List[int] = []
         torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
 
-        def worker(i: int, slot: int, need: int) -> None:
+        def arrivals() -> None:
+            now = time.perf_counter() - t0
+            while pending and (not realtime or requests[pending[0]].arrival_s <= now):
+                waiting.append(pending.popleft())
+
+        def worker(slot: int, idx: List[int], need: int) -> None:
             try:
-                results[i] = self._serve_one(slot, requests[i], t0)
+                for i, r in zip(idx, self._serve_batch(slot, [requests[i] for i in idx], t0)):
+                    results[i] = r
             except BaseException as e:  # reported after the run
                 errors.append(e)
             finally:
                 self.adm.release(slot, need)
 
         threads = []
-        for i, req in enumerate(requests):
-            if realtime:
-                delay = req.arrival_s - (time.perf_counter() - t0)
-                if delay > 0:
-                    time.sleep(delay)
-            need = estimate_bytes(req.workload)
-            slot = self.adm.admit(need)
-            th = threading.Thread(target=worker, args=(i, slot, need), daemon=True)
+        while pending or waiting:
+            arrivals()
+            if not waiting:
+                time.sleep(max(0.0, requests[pending[0]].arrival_s - (time.perf_counter() - t0)))
+                continue
+            slot = self.adm.acquire_slot()
+            arrivals()  # requests that came while every slot was busy join this batch
+            first = waiting.popleft()
+            need = min(estimate_bytes(requests[first].workload), self.adm.budget)
+            self.adm.reserve(need, block=True)
+            idx = [first]
+            while waiting and len(idx) < max_batch:
+                nxt = waiting[0]
+                if not self._compatible(requests[nxt].workload, requests[first].workload):
+                    break
+                nd = min(estimate_bytes(requests[nxt].workload), self.adm.budget)
+                if not self.adm.reserve(nd, block=False):
+                    break
+                need += nd
+                idx.append(waiting.popleft())
+            batch_sizes.append(len(idx))
+            th = threading.Thread(target=worker, args=(slot, idx, need), daemon=True)
             th.start()
             threads.append(th)
         for th in threads:
@@ -167,6 +249,8 @@ class Server:
             "latency_ms": {"p50": 1e3 * statistics.median(lat),
                            "p99": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
                            "max": 1e3 * lat[-1]},
+            "batches": len(batch_sizes),
+            "mean_batch": sum(batch_sizes) / max(len(batch_sizes), 1),
             "max_bytes_in_use": self.adm.max_in_use,
             "budget_bytes": self.adm.budget,
             "deferred": self.adm.deferred,

@@ -246,6 +246,23 @@ def test_solve_vdp2_small_rounds(G, ctx):
     _check_solve(G, ctx, wl)
 
 
+@pytest.mark.parametrize("analysis", ["nonleaving", "controlled"])
+def test_solve_edge_buffer_regrowth(G, analysis):
+    """A fresh context sizes its edge buffer from an estimate (8 edges per row)
+    that a coarse 4-D covering exceeds: the round is re-emitted, re-analysed
+    and re-subdivided after the buffer grows, and the result is unchanged."""
+    c = G.Context(0)
+    try:
+        wl = W.Workload("vdp2_5_r1", W.vdp2(),
+                        W.Grid((5, 5, 5, 5), (-2.5, -3, -2.5, -3), (2.5, 3, 2.5, 3)),
+                        W.input_grid(-1, 1, 3, 2), W.CORNERS_CENTER, 1, "fp64", analysis=analysis)
+        sol, want, info = _check_solve(G, c, wl)
+        assert want["stats"][0]["n_edges"] > 10 * want["stats"][0]["n_rows"]
+        sol.free()
+    finally:
+        c.close()
+
+
 def test_solve_lorenz_small(G, ctx):
     wl = W.Workload("lorenz_24", W.lorenz(), W.Grid((24, 24, 24), (-20., -25., 0.), (20., 25., 50.)),
                     W.evenly_spaced(-10, 10, 5), W.CORNERS_CENTER, 1, "fp32_recheck")
