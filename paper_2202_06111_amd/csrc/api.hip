@@ -28,7 +28,9 @@ int32_t ensure(DevBuf& b, size_t bytes, bool* fresh) {
   if (bytes <= b.bytes && b.ptr) return GIS_OK;
   if (fresh) *fresh = true;
   release(b);
-  size_t want = bytes + bytes / 4 + 256;
+  // 25% room to grow, at most 2 GiB (the largest buffers run to tens of GiB)
+  const size_t slack = bytes / 4 < ((size_t)2 << 30) ? bytes / 4 : ((size_t)2 << 30);
+  size_t want = bytes + slack + 256;
   hipError_t e = hipMalloc(&b.ptr, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();

@@ -159,6 +159,12 @@ def vdp2_adaptive_32() -> Workload:
                     analysis="nonleaving")
 
 
+def vdp2_adaptive_32_r1() -> Workload:
+    """The coupled Van der Pol workload with one boundary round instead of two."""
+    wl = vdp2_adaptive_32()
+    return dataclasses.replace(wl, name="vdp2_adaptive_32^4_r1", rounds=1)
+
+
 def scaled_vdp_box(scale: float) -> Tuple[Tuple[float, ...], Tuple[float, ...]]:
     return ((-2.5 * scale, -3.0 * scale), (2.5 * scale, 3.0 * scale))
 
@@ -226,6 +232,7 @@ ALL = {
     "vdp_adaptive_32x32_r5": vdp_adaptive_32,
     "lorenz_uniform_128^3": lorenz_uniform_128,
     "vdp2_adaptive_32^4_r2": vdp2_adaptive_32,
+    "vdp2_adaptive_32^4_r1": vdp2_adaptive_32_r1,
 }
 
 
