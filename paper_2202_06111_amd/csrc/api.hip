@@ -106,7 +106,7 @@ struct gis_ctx {
   bool lb_clean = false, prune_clean = false, next_clean = false;
   int32_t first_sweeps = 0;  // sweeps of the last enqueue_prune
   DevBuf lookback, scan_tmp;
-  DevBuf idx_state, idx_id, next_state, pos;
+  DevBuf idx_state, idx_pfx, next_state, pos;
   DevBuf removed, rptr, rrow, rcur, rowbad, cand, front;
   DevBuf bnd;
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
@@ -120,7 +120,7 @@ struct gis_solution {
   CoverIndex ci{};
   int32_t K = 0, W = 0;
   int64_t n_cells = 0;
-  DevBuf level, idx, kept, mask, state, id;
+  DevBuf level, idx, kept, mask, state, pfx;
   gis_solve_info info{};
 };
 
@@ -377,7 +377,8 @@ int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells
   for (int k = 0; k < LK_KINDS; ++k) B.blocks[k] = blk[k];
   if (slot_off > 0) {
     if ((rc = ensure(ctx->idx_state, (size_t)slot_off))) return rc;
-    if ((rc = ensure(ctx->idx_id, (size_t)slot_off * 4))) return rc;
+    if ((rc = ensure(ctx->idx_pfx, (size_t)(slot_off + 1) * 8))) return rc;
+    if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(slot_off)))) return rc;
   }
   if (next_off > 0) {
     bool fresh = false;
@@ -386,11 +387,14 @@ int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells
     if ((rc = ensure(ctx->pos, (size_t)(next_off + 1) * 8))) return rc;
     if ((rc = ensure(ctx->scan_tmp, scan_tmp_bytes(next_off)))) return rc;
   }
+  int64_t leaves_before = 0;  // the prefix counts run over the whole batch
   for (int j = 0; j < B.n_jobs; ++j) {
     Job& J = B.jobs[j];
     const bool arrays = !J.ci.uniform && J.n_cells > 0;
     J.ci.state = arrays ? (uint8_t*)ctx->idx_state.ptr + so[j] : nullptr;
-    J.ci.id = arrays ? (int32_t*)ctx->idx_id.ptr + so[j] : nullptr;
+    J.ci.pfx = arrays ? (int64_t*)ctx->idx_pfx.ptr + so[j] : nullptr;
+    J.ci.pbase = leaves_before;
+    if (arrays) leaves_before += J.n_cells;
     const bool nxt = with_next[j] && J.n_cells > 0;
     J.next.state = nxt ? (uint8_t*)ctx->next_state.ptr + J.next_off : nullptr;
   }
@@ -427,7 +431,10 @@ int32_t sync_stats(gis_ctx* ctx, const Batch& B, hipStream_t s) {
 int32_t batch_index(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx, bool validate,
                     hipStream_t s) {
   int32_t rc;
-  if ((rc = batch_index_build(B.args(level, idx), &dcnt(ctx)->err, s))) return rc;
+  if ((rc = batch_index_build(B.args(level, idx), &dcnt(ctx)->err, (const uint8_t*)ctx->idx_state.ptr,
+                               (int64_t*)ctx->idx_pfx.ptr, B.total_slots, ctx->scan_tmp.ptr, validate,
+                               s)))
+    return rc;
   if (!validate) return GIS_OK;
   if ((rc = sync_counters(ctx, s))) return rc;
   const uint32_t e = ctx->h_counters->err;
@@ -545,7 +552,7 @@ int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* i
 }
 
 constexpr int32_t kFirstSweeps = 16;    // sweeps enqueued before the first convergence check
-constexpr int32_t kSweepBatch = 32;     // sweeps between later convergence checks
+constexpr int32_t kSweepBatch = 8;      // sweeps between later convergence checks
 constexpr int32_t kMaxSweeps = 256;     // then the frontier phase takes over
 constexpr int64_t kSweepEdges = 8 << 20;  // larger graphs go to the frontier phase directly
 constexpr int32_t kFrontierBatch = 16;  // frontier steps between convergence checks
@@ -593,11 +600,12 @@ bool sweeps_fit(int64_t n_edges, int32_t K) { return K <= 256 && n_edges <= kSwe
 
 // est_edges: the graph's edge count, or an estimate of it (it only chooses
 // between the two phases).
+// first: the number of sweeps to enqueue before the first check.
 int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                       int64_t n_cells, int32_t K, int64_t cap_edges, const int64_t* d_total,
                       int64_t est_edges, int32_t analysis, uint8_t* kept, uint64_t* mask,
                       hipStream_t s, const Batch* B = nullptr, const uint8_t* level = nullptr,
-                      const int32_t* idx = nullptr) {
+                      const int32_t* idx = nullptr, int32_t first = kFirstSweeps) {
   int32_t rc;
   if (n_cells * (int64_t)K > (int64_t)INT32_MAX) {  // the reverse CSR stores 32-bit row ids
     set_error("a graph of more than 2^31-1 rows is not supported");
@@ -605,7 +613,7 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   }
   if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
   if ((rc = fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s))) return rc;
-  ctx->first_sweeps = sweeps_fit(est_edges, K) ? kFirstSweeps : 0;
+  ctx->first_sweeps = sweeps_fit(est_edges, K) ? first : 0;
   if (ctx->first_sweeps == 0) return GIS_OK;
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
   if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps, s)))
@@ -687,15 +695,16 @@ int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const in
                           int32_t* ix_out, int64_t cap, hipStream_t s) {
   int32_t rc;
   const BatchArgs ba = B.args(level, idx);
-  if ((rc = batch_mark_dropped(ba, kept, s))) return rc;
-  if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
   const int64_t total = next_total(B);
   if (total > 0) {
     if (!ctx->next_clean &&
         (rc = fill_u8((uint8_t*)ctx->next_state.ptr, 0, (int64_t)ctx->next_state.bytes, s)))
       return rc;
     ctx->next_clean = false;  // until finish_subdivide has seen the compaction complete
-    if ((rc = batch_next_flags(ba, kept, boundary, s))) return rc;
+  }
+  if ((rc = batch_mark_dropped(ba, kept, s))) return rc;
+  if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
+  if (total > 0) {
     if ((rc = scan_exclusive_u8((const uint8_t*)ctx->next_state.ptr, (int64_t*)ctx->pos.ptr, total,
                                 &dcnt(ctx)->n_next, ctx->scan_tmp.ptr, s)))
       return rc;
@@ -767,7 +776,7 @@ int32_t make_solution(gis_ctx* ctx, const Batch& B, int j, const uint8_t* level,
     return fail(rc);
   sol->ci = J.ci;
   sol->ci.state = nullptr;
-  sol->ci.id = nullptr;
+  sol->ci.pfx = nullptr;
   if (nc > 0) {
     if (hipMemcpyAsync(sol->level.ptr, level + c0, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(sol->idx.ptr, idx + c0 * n, nc * n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -778,15 +787,17 @@ int32_t make_solution(gis_ctx* ctx, const Batch& B, int j, const uint8_t* level,
     }
     if (!J.ci.uniform) {
       const int64_t total = J.ci.off[J.ci.lmax + 1];
-      if ((rc = ensure(sol->state, (size_t)total + 16)) || (rc = ensure(sol->id, (size_t)total * 4 + 16)))
+      if ((rc = ensure(sol->state, (size_t)total + 16)) ||
+          (rc = ensure(sol->pfx, (size_t)(total + 1) * 8 + 16)))
         return fail(rc);
       if (hipMemcpyAsync(sol->state.ptr, J.ci.state, total, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(sol->id.ptr, J.ci.id, total * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+          hipMemcpyAsync(sol->pfx.ptr, J.ci.pfx, (total + 1) * 8, hipMemcpyDeviceToDevice, s) !=
+              hipSuccess) {
         set_error("copy of the covering index failed");
         return fail(GIS_E_HIP);
       }
       sol->ci.state = (uint8_t*)sol->state.ptr;
-      sol->ci.id = (int32_t*)sol->id.ptr;
+      sol->ci.pfx = (int64_t*)sol->pfx.ptr;
     }
   }
   *out = sol;
@@ -883,6 +894,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   hipEvent_t* ev = ctx->ev;
   bool cur_is_A = true;
   double edges_per_row = 8.0;
+  // sweeps enqueued with a round: what the previous round needed, plus two
+  int32_t sweep_hint = kFirstSweeps;
   for (int r = 0; r <= rounds; ++r) {
     const uint8_t* lv = (const uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
     const int32_t* ix = (const int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
@@ -913,7 +926,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       int32_t e;
       if ((e = enqueue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.cap_edges,
                              &dcnt(ctx)->total_edges, (int64_t)(edges_per_row * (double)n_rows),
-                             o.analysis, kept, mask, s, &B, lv, ix)))
+                             o.analysis, kept, mask, s, &B, lv, ix, sweep_hint)))
         return e;
       GIS_HIP(hipEventRecord(ev[2], s));
       if (!last && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
@@ -951,7 +964,17 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
     GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
     GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
-    if (!prune_converged(ctx, n_cells)) {
+    const bool conv = prune_converged(ctx, n_cells);
+    if (conv && ctx->first_sweeps > 0) {
+      // rounds of one solve need similar numbers; a miss costs a host round
+      // trip and a second subdivision, so keep a margin
+      const int32_t need = ctx->h_counters->sweep_last + 1;  // incl. the sweep that found no change
+      const int32_t want = need + 4;
+      sweep_hint = want < 10 ? 10 : (want > kFirstSweeps ? kFirstSweeps : want);
+    } else {
+      sweep_hint = kFirstSweeps;
+    }
+    if (!conv) {
       // long removal chains: finish the analysis with the frontier phase and
       // redo the subdivision (it ran on the unfinished kept set and marked
       // its dropped cells in the index, which is rebuilt first)
@@ -1094,7 +1117,7 @@ void gis_ctx_destroy(gis_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&c->counters, &c->jobs, &c->maxerr, &c->lookback, &c->scan_tmp,
-                    &c->idx_state, &c->idx_id,
+                    &c->idx_state, &c->idx_pfx,
                     &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rcur,
                     &c->rowbad, &c->cand, &c->front, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
@@ -1314,7 +1337,7 @@ void gis_solution_free(gis_solution* sol) {
   release(sol->kept);
   release(sol->mask);
   release(sol->state);
-  release(sol->id);
+  release(sol->pfx);
   delete sol;
 }
 

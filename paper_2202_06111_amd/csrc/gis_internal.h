@@ -36,14 +36,20 @@ struct GridArgs {
 };
 
 // Dense per-level index of a covering: for every level L <= lmax a row-major
-// array of states (and of cell ids where the state is LEAF).
+// array of states, and prefix counts of its leaves and holes.
 struct CoverIndex {
   int32_t n, lmax;
   int32_t uniform;                       // 1: full level-0 grid, no arrays needed
   int32_t dims[kMaxLevels][kMaxDim];     // n0_d << L
-  int64_t off[kMaxLevels + 1];           // offset of level L in state/id
+  int64_t off[kMaxLevels + 1];           // offset of level L in state / pfx
+  int64_t pbase;          // leaves before the job's first slot (see pfx)
   uint8_t* state;
-  int32_t* id;
+  // [slots + 1] over the slots in canonical order (level, then row-major):
+  // (number of LEAF slots before it) | (number of HOLE slots before it) << 32,
+  // counted from the start of the batch's index.  A run of slots holds
+  // pfx[b+1] - pfx[a] leaves and holes, and its leaves have the consecutive
+  // local ids (pfx[a] & 0xffffffff) - pbase, ...
+  int64_t* pfx;
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -98,6 +104,9 @@ int32_t scan_exclusive_u8(const uint8_t* in, int64_t* out, int64_t n, int64_t* d
                           hipStream_t s);
 int32_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, int64_t* d_total, void* tmp,
                            hipStream_t s);
+// Exclusive scan of packed (leaf, hole << 32) indicators of index states into
+// out[0..n], out[n] = total.
+int32_t scan_leaf_hole(const uint8_t* state, int64_t* out, int64_t n, void* tmp, hipStream_t s);
 
 // k_index.hip
 int32_t max_level(const uint8_t* level, int64_t n_cells, uint32_t* d_out, hipStream_t s);
@@ -256,16 +265,21 @@ struct BatchArgs {
   const int32_t* idx;
   int64_t blocks[LK_KINDS];
 };
-int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, hipStream_t s);
+// ... and the prefix counts of the jobs with index arrays: pfx_all receives
+// total_slots + 1 values over the batch's concatenated state arrays state_all.
+// Without `validate` the list is taken as valid (produced by the library)
+// and no check is made.
+int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, const uint8_t* state_all,
+                          int64_t* pfx_all, int64_t total_slots, void* scan_tmp, bool validate,
+                          hipStream_t s);
 int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t s);
 
 // k_refine.hip, job-batched
+// Boundary flags of the kept cells (Sec. 3.1.1) and, for jobs with a next
+// layout, the next-covering flags (those arrays are zero on entry;
+// batch_compact leaves them zero again).
 int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
                        JobStats* stats, hipStream_t s);
-// Sets the next-covering flags (the jobs' next arrays are zero on entry;
-// batch_compact leaves them zero again).
-int32_t batch_next_flags(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
-                         hipStream_t s);
 // pos: exclusive scan of the batch's next-flag array; writes the new global
 // cell list (up to cap) and each job's next_start / level_start.
 int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,

@@ -32,7 +32,6 @@ namespace {
 
 constexpr int kTile = 4096;   // LDS staging tile of the emitter (int32 ids, 16 KiB)
 constexpr int kCache = 6;     // target ids kept in LDS per row between count and emit
-constexpr int kLdsIndex = 6144;  // bytes of LDS for the coarse levels of the covering index
 
 // Look-back words: the launch's epoch in bits 40-63, a status in bits 38-39
 // and an edge total in bits 0-37.  A word written by an earlier launch
@@ -94,61 +93,57 @@ __device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverInd
   return r;
 }
 
-// Visits the slots of the covering index met by the finest-level box
-// [lo, hi], level by level (coarse to fine), row-major inside a level:
-// f(level, slot, state, k) (k the slot's multi-index) returns false to stop
-// early.  Below level 0 only the children of REFINED slots can hold leaves or
-// holes, so each level is restricted to the box spanned by the children of
-// the REFINED slots seen one level up, and the walk ends at the first level
-// without a REFINED slot.  The visiting order (level-major, row-major) is the
-// canonical id order.  States are read kWalk slots at a time (independent
-// loads, one wait), from `lst` (an LDS copy of the first `lslots` slots) for
-// the levels that lie there.
-constexpr int kWalk = 4;
+// Visits the runs of index slots met by the finest-level box [lo, hi]: for
+// every level L (coarse to fine) and every row of the box at that level (all
+// coordinates but the last fixed, row-major), the slots a .. b of that row
+// between the box's first and last column.  Per run f(p0, p1, inner, q0, q1)
+// gets the prefix counts P[a] and P[b+1] and, when the row lies in the
+// interior box [ilo, ihi] (and `interior` is set), the prefix counts at that
+// box's first column and one past its last; f returns false to stop.
+// Level-major, row-major order is the canonical id order, so the leaves come
+// out ascending.  The cost is one call per row of the box and level, whatever
+// the box's width and however the covering is refined inside it; the loads
+// of kRuns runs are issued together.
+constexpr int kRuns = 4;
 
 template <int N, typename F>
-__device__ __forceinline__ void walk_levels(const CoverIndex& ci, const uint8_t* lst,
-                                            int64_t lslots, const int32_t* lo, const int32_t* hi,
-                                            F&& f) {
-  int32_t plo[N], phi[N];  // REFINED bounding box one level up
+__device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* lo,
+                                          const int32_t* hi, const int32_t* ilo,
+                                          const int32_t* ihi, bool interior, F&& f) {
+  const int64_t* P = ci.pfx;
   for (int L = 0; L <= ci.lmax; ++L) {
     const int s = ci.lmax - L;
-    int32_t blo[N], bhi[N], k[N], nlo[N], nhi[N];
-    bool empty = false;
+    int32_t blo[N], bhi[N], k[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) {
       blo[d] = lo[d] >> s;
       bhi[d] = hi[d] >> s;
-      if (L > 0) {
-        blo[d] = blo[d] > 2 * plo[d] ? blo[d] : 2 * plo[d];
-        bhi[d] = bhi[d] < 2 * phi[d] + 1 ? bhi[d] : 2 * phi[d] + 1;
-      }
-      empty |= blo[d] > bhi[d];
       k[d] = blo[d];
-      nlo[d] = 0x7fffffff;
-      nhi[d] = -1;
     }
-    if (empty) return;
-    bool refined = false;
+    const int32_t cl = (ilo[N - 1] >> s) - blo[N - 1];  // interior columns inside the run
+    const int32_t cr = bhi[N - 1] - (ihi[N - 1] >> s);
     const int64_t base = ci.off[L];
-    const bool in_lds = ci.off[L + 1] <= lslots;
     bool done = false;
     while (!done) {
-      int64_t sl[kWalk];
-      int32_t kc[kWalk][N];
+      int64_t ra[kRuns], rb[kRuns];
+      bool in[kRuns];
       int m = 0;
 #pragma unroll
-      for (int q = 0; q < kWalk; ++q) {
+      for (int q = 0; q < kRuns; ++q) {
         if (!done) {
           int64_t lin = 0;
+          bool inner = interior;
 #pragma unroll
-          for (int d = 0; d < N; ++d) {
+          for (int d = 0; d < N - 1; ++d) {
             lin = lin * ci.dims[L][d] + k[d];
-            kc[q][d] = k[d];
+            inner &= k[d] >= (ilo[d] >> s) && k[d] <= (ihi[d] >> s);
           }
-          sl[q] = base + lin;
+          const int64_t row = base + lin * ci.dims[L][N - 1];
+          ra[q] = row + blo[N - 1];
+          rb[q] = row + bhi[N - 1];
+          in[q] = inner;
           m = q + 1;
-          int d = N - 1;
+          int d = N - 2;
           while (d >= 0 && k[d] == bhi[d]) {
             k[d] = blo[d];
             --d;
@@ -157,30 +152,17 @@ __device__ __forceinline__ void walk_levels(const CoverIndex& ci, const uint8_t*
           else ++k[d];
         }
       }
-      uint8_t st[kWalk];
+      int64_t p0[kRuns], p1[kRuns], q0[kRuns], q1[kRuns];
 #pragma unroll
-      for (int q = 0; q < kWalk; ++q)
-        st[q] = q < m ? (in_lds ? lst[sl[q]] : ci.state[sl[q]]) : (uint8_t)ST_NONE;
-#pragma unroll
-      for (int q = 0; q < kWalk; ++q) {
-        if (q < m) {
-          if (!f(L, sl[q], st[q], kc[q])) return;
-          if (st[q] == ST_REFINED) {
-            refined = true;
-#pragma unroll
-            for (int d = 0; d < N; ++d) {
-              nlo[d] = kc[q][d] < nlo[d] ? kc[q][d] : nlo[d];
-              nhi[d] = kc[q][d] > nhi[d] ? kc[q][d] : nhi[d];
-            }
-          }
-        }
+      for (int q = 0; q < kRuns; ++q) {
+        p0[q] = q < m ? P[ra[q]] : 0;
+        p1[q] = q < m ? P[rb[q] + 1] : 0;
+        q0[q] = q < m && in[q] ? P[ra[q] + cl] : 0;
+        q1[q] = q < m && in[q] ? P[rb[q] - cr + 1] : 0;
       }
-    }
-    if (!refined) return;
 #pragma unroll
-    for (int d = 0; d < N; ++d) {
-      plo[d] = nlo[d];
-      phi[d] = nhi[d];
+      for (int q = 0; q < kRuns; ++q)
+        if (q < m && !f(p0[q], p1[q], in[q], q0[q], q1[q])) return;
     }
   }
 }
@@ -254,13 +236,15 @@ __device__ __forceinline__ bool band_safe(const Job& J, const CoverIndex& ci, co
   return safe;
 }
 
+constexpr int64_t kLo32 = 0xffffffffll;
+
 // Edge count of a row and the first kCache target ids (local ids), stored
 // with stride kRowBlock from `cache`; *hole is set when a hole of the
-// covering meets the interior range (one walk of the closed range serves
-// both: every slot meeting the interior range lies in it).
+// covering meets the interior range.  Per run the prefix counts give the
+// leaves (ids consecutive from the first) and, on rows of the interior box,
+// the holes between the interior columns.
 template <int N, bool UNI>
-__device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const uint8_t* lst,
-                                                 int64_t lslots, const Ranges<N>& r,
+__device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ranges<N>& r,
                                                  int32_t* cache, bool* hole) {
   *hole = false;
   if (r.empty) return 0;
@@ -272,21 +256,18 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const uin
   }
   int32_t c = 0;
   bool h = false;
-  walk_levels<N>(ci, lst, lslots, r.lo, r.hi,
-                 [&](int L, int64_t slot, uint8_t st, const int32_t* k) {
-                   if (st == ST_LEAF) {
-                     if (c < kCache) cache[c * kRowBlock] = ci.id[slot];
-                     ++c;
-                   } else if (st == ST_HOLE && !h) {
-                     const int s = ci.lmax - L;
-                     bool in = true;
-#pragma unroll
-                     for (int d = 0; d < N; ++d)
-                       in &= k[d] >= (r.ilo[d] >> s) && k[d] <= (r.ihi[d] >> s);
-                     h = in;
-                   }
-                   return true;
-                 });
+  walk_runs<N>(ci, r.lo, r.hi, r.ilo, r.ihi, true,
+               [&](int64_t p0, int64_t p1, bool inner, int64_t q0, int64_t q1) {
+                 const int32_t nl = (int32_t)((p1 & kLo32) - (p0 & kLo32));
+                 if (nl > 0) {
+                   const int32_t first = (int32_t)((p0 & kLo32) - ci.pbase);
+                   for (int32_t i = 0; i < nl && c + i < kCache; ++i)
+                     cache[(c + i) * kRowBlock] = first + i;
+                   c += nl;
+                 }
+                 h |= inner && (q1 >> 32) != (q0 >> 32);
+                 return true;
+               });
   *hole = h;
   return c;
 }
@@ -294,8 +275,7 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const uin
 // Targets p0 .. p1-1 of a row (0-based positions in its ascending target
 // list) as global ids into dst[0 .. p1-p0).
 template <int N, bool UNI>
-__device__ __forceinline__ void emit_targets(const CoverIndex& ci, const uint8_t* lst,
-                                             int64_t lslots, const int32_t* lo,
+__device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t* lo,
                                              const int32_t* hi, int32_t count,
                                              const int32_t* cache, int32_t id0, int32_t p0,
                                              int32_t p1, int32_t* dst) {
@@ -328,13 +308,15 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const uint8_t
     for (int32_t p = p0; p < p1; ++p) dst[p - p0] = id0 + cache[p * kRowBlock];
     return;
   }
-  int32_t w = 0;
-  walk_levels<N>(ci, lst, lslots, lo, hi, [&](int, int64_t slot, uint8_t st, const int32_t*) {
-    if (st == ST_LEAF) {
-      if (w >= p0) dst[w - p0] = id0 + ci.id[slot];
-      if (++w >= p1) return false;
-    }
-    return true;
+  int32_t w = 0;  // position of the run's first leaf in the row's list
+  walk_runs<N>(ci, lo, hi, lo, hi, false, [&](int64_t v0, int64_t v1, bool, int64_t, int64_t) {
+    const int32_t nl = (int32_t)((v1 & kLo32) - (v0 & kLo32));
+    const int32_t first = id0 + (int32_t)((v0 & kLo32) - ci.pbase);
+    const int32_t i0 = p0 > w ? p0 - w : 0;
+    const int32_t i1 = p1 - w < nl ? p1 - w : nl;
+    for (int32_t i = i0; i < i1; ++i) dst[w + i - p0] = first + i;
+    w += nl;
+    return w < p1;
   });
 }
 
@@ -346,7 +328,6 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   __shared__ CoverIndex ci;
   __shared__ int32_t tile[kTile];
   __shared__ int32_t cache[kCache * kRowBlock];
-  __shared__ uint8_t lst[kLdsIndex];
   __shared__ int64_t wsum[kRowBlock / 64];
   __shared__ int64_t s_prefix;
   __shared__ uint32_t s_bid, s_out, s_rchk;
@@ -365,16 +346,6 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, bid);
   const Job& J = a.jobs[jb];
   stage_index(&ci, &J.ci);
-  // the coarse levels of the index that fit go to LDS
-  int64_t lslots = 0;
-  if (!UNI && !ci.uniform) {
-    int Ls = 0;
-    while (Ls <= ci.lmax && ci.off[Ls + 1] <= kLdsIndex) ++Ls;
-    lslots = ci.off[Ls];
-    for (int64_t i = tid; i < lslots; i += kRowBlock) lst[i] = ci.state[i];
-    __syncthreads();
-  }
-
   // ---- 1-2: images, box, cover decision, count
   const int64_t lr = (bid - J.blk[LK_ROWS]) * kRowBlock + tid;
   const bool live = lr < J.n_cells * a.K;
@@ -404,7 +375,7 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
     if (finite) {
       const Ranges<N> rr = ranges_of<N>(J.grid, ci, bl, bh);
       bool hole;
-      c = count_targets<N, UNI>(ci, lst, lslots, rr, cache + tid, &hole);
+      c = count_targets<N, UNI>(ci, rr, cache + tid, &hole);
       out = rr.outx || hole;
       if (a.fast_out && out) c = 0;
 #pragma unroll
@@ -500,8 +471,8 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
     const int64_t s0 = off > w0 ? off : w0;
     const int64_t s1 = off + c < w1 ? off + c : w1;
     if (s0 < s1)
-      emit_targets<N, UNI>(ci, lst, lslots, lo, hi, c, cache + tid, id0, (int32_t)(s0 - off),
-                      (int32_t)(s1 - off), tile + (s0 - w0));
+      emit_targets<N, UNI>(ci, lo, hi, c, cache + tid, id0, (int32_t)(s0 - off),
+                           (int32_t)(s1 - off), tile + (s0 - w0));
     __syncthreads();
     for (int64_t i = tid; i < w1 - w0; i += kRowBlock) a.col[prefix + w0 + i] = tile[i];
     __syncthreads();

@@ -1,9 +1,14 @@
 // Covering index: the cells of a covering (Sec. 2.1) held as one dense
-// row-major state array per level -- LEAF where a cell of the list sits (with
-// its id), REFINED above a leaf, HOLE where a region of X has no cell, NONE
-// below a leaf or a hole.  It turns "which cells meet this box" and "is this
-// finest cell covered" into a short walk over at most lmax + 1 levels, with
-// no search structure to build (the role the paper gives an R*-tree, Sec. 2.4).
+// row-major state array per level -- LEAF where a cell of the list sits,
+// REFINED above a leaf, HOLE where a region of X has no cell, NONE below a
+// leaf or a hole -- plus prefix counts of leaves and holes in slot order.
+// Since the slot order (level, then row-major) is the canonical cell order,
+// the leaves of any run of slots along the last dimension are cells with
+// consecutive ids, and two prefix values give a run's leaves and holes.  This
+// turns "which cells meet this box" into a few loads per row of the box and
+// level, and "is this finest cell covered" into a walk over at most lmax + 1
+// levels, with no search structure to build (the role the paper gives an
+// R*-tree, Sec. 2.4).
 #include "gis_internal.h"
 
 namespace gis {
@@ -71,10 +76,7 @@ __global__ void k_leaves(BatchArgs b, uint32_t* err) {
     const int64_t pslot = cell_slot(J.ci, b.level, b.idx, gc - 1);
     if (pslot >= 0 && pslot >= slot) atomicOr(err, 2u);
   }
-  if (!J.ci.uniform) {
-    J.ci.state[slot] = ST_LEAF;
-    J.ci.id[slot] = (int32_t)c;
-  }
+  if (!J.ci.uniform) J.ci.state[slot] = ST_LEAF;
 }
 
 // Marks every ancestor of every leaf REFINED; an ancestor that is itself a
@@ -102,6 +104,34 @@ __global__ void k_ancestors(BatchArgs b, uint32_t* err) {
       break;
     }
     J.ci.state[slot] = ST_REFINED;
+  }
+}
+
+// For lists known to be valid (the library's own): LEAF for every cell and
+// REFINED for its ancestors in one pass, no checks.  Cells sharing an
+// ancestor write the same value; a valid list has no cell inside another.
+__global__ void k_leaves_up(BatchArgs b) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  if (c >= J.n_cells || J.ci.uniform) return;
+  const int64_t gc = J.cell_off + c;
+  int L = b.level[gc];
+  int64_t k[kMaxDim];
+  int64_t lin = 0;
+  for (int d = 0; d < J.ci.n; ++d) {
+    k[d] = b.idx[gc * J.ci.n + d];
+    lin = lin * J.ci.dims[L][d] + k[d];
+  }
+  J.ci.state[J.ci.off[L] + lin] = ST_LEAF;
+  while (L > 0) {
+    --L;
+    lin = 0;
+    for (int d = 0; d < J.ci.n; ++d) {
+      k[d] >>= 1;
+      lin = lin * J.ci.dims[L][d] + k[d];
+    }
+    J.ci.state[J.ci.off[L] + lin] = ST_REFINED;
   }
 }
 
@@ -163,7 +193,21 @@ int32_t max_level(const uint8_t* level, int64_t n_cells, uint32_t* d_out, hipStr
   return GIS_OK;
 }
 
-int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, hipStream_t s) {
+int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, const uint8_t* state_all,
+                          int64_t* pfx_all, int64_t total_slots, void* scan_tmp, bool validate,
+                          hipStream_t s) {
+  if (!validate) {
+    if (b.blocks[LK_CELLS] > 0) {
+      hipLaunchKernelGGL(k_leaves_up, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b);
+      GIS_LAUNCH_CHECK("k_leaves_up");
+    }
+    if (b.blocks[LK_SLOTS] > 0) {
+      hipLaunchKernelGGL(k_holes, dim3((unsigned)b.blocks[LK_SLOTS]), dim3(256), 0, s, b);
+      GIS_LAUNCH_CHECK("k_holes");
+    }
+    if (total_slots > 0) return scan_leaf_hole(state_all, pfx_all, total_slots, scan_tmp, s);
+    return GIS_OK;
+  }
   int32_t rc = fill_u32(d_err, 0u, 1, s);
   if (rc != GIS_OK) return rc;
   if (b.blocks[LK_CELLS] > 0) {
@@ -176,6 +220,7 @@ int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, hipStream_t s) {
     hipLaunchKernelGGL(k_holes, dim3((unsigned)b.blocks[LK_SLOTS]), dim3(256), 0, s, b);
     GIS_LAUNCH_CHECK("k_holes");
   }
+  if (total_slots > 0) return scan_leaf_hole(state_all, pfx_all, total_slots, scan_tmp, s);
   return GIS_OK;
 }
 

@@ -296,15 +296,61 @@ __global__ void k_front_eval(int64_t n_cells, int32_t K, uint8_t* removed, const
 }
 
 // kept flags, admissible-input masks and the kept count from the removed
-// flags (rows evaluated against the final set).
+// flags (rows evaluated against the final set).  Like a sweep, a block takes
+// cpb = floor(256 / K) whole cells: a thread per row evaluates it, then a
+// thread per (cell, mask word) assembles the word.
 template <int MODE>
-__global__ void k_prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
-                              int64_t n_cells, int32_t K, const uint8_t* removed, uint8_t* kept,
-                              uint64_t* mask, int32_t W, unsigned long long* nkept,
-                              const int64_t* d_total, int64_t cap_edges, const int32_t* last,
-                              int32_t sweeps) {
+__global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, const int32_t* col,
+                                                     const uint8_t* out, int64_t n_cells,
+                                                     int32_t K, int32_t cpb,
+                                                     const uint8_t* removed, uint8_t* kept,
+                                                     uint64_t* mask, int32_t W,
+                                                     unsigned long long* nkept,
+                                                     const int64_t* d_total, int64_t cap_edges,
+                                                     const int32_t* last, int32_t sweeps) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
   if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
+  __shared__ uint8_t ok[256];
+  const int t = threadIdx.x;
+  unsigned long long mine = 0;
+  const int64_t stride = (int64_t)gridDim.x * cpb;
+  for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
+    const int64_t c = g0 + t / K;
+    bool good = false;
+    if (t < cpb * K && c < n_cells && !removed[c])
+      good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
+    ok[t] = good ? 1 : 0;
+    __syncthreads();
+    if (t < cpb * W) {
+      const int64_t cc = g0 + t / W;
+      const int w = t % W;
+      if (cc < n_cells) {
+        const bool k = !removed[cc];
+        uint64_t m = 0;
+        const int j0 = (t / W) * K + w * 64;
+        for (int b = 0; b < 64 && w * 64 + b < K; ++b) m |= (uint64_t)ok[j0 + b] << b;
+        mask[cc * W + w] = m;
+        if (w == 0) {
+          kept[cc] = k ? 1 : 0;
+          mine += k;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
+  if ((t & 63) == 0 && mine) atomicAdd(nkept, mine);
+}
+
+// The same for K > 256 inputs: a thread per cell.
+template <int MODE>
+__global__ void k_prune_final_wide(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                                   int64_t n_cells, int32_t K, const uint8_t* removed,
+                                   uint8_t* kept, uint64_t* mask, int32_t W,
+                                   unsigned long long* nkept, const int64_t* d_total,
+                                   int64_t cap_edges, const int32_t* last, int32_t sweeps) {
+  if (d_total && *d_total > cap_edges) return;
+  if (sweeps > 0 && *last >= sweeps) return;
   unsigned long long mine = 0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -395,10 +441,20 @@ template <int MODE>
 int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                    int64_t n_cells, int32_t K, const PruneWork& w, uint8_t* kept, uint64_t* mask,
                    int32_t W, unsigned long long* d_nkept, int32_t sweeps, hipStream_t s) {
-  hipLaunchKernelGGL((k_prune_final<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr, col,
-                     out, n_cells, K, (const uint8_t*)w.removed, kept, mask, W, d_nkept, w.d_total,
-                     w.cap_edges, (const int32_t*)w.last, sweeps);
-  GIS_LAUNCH_CHECK("k_prune_final");
+  if (K <= 256) {
+    const int32_t cpb = 256 / K;
+    const int64_t groups = (n_cells + cpb - 1) / cpb;
+    const unsigned nb = (unsigned)(groups < 4096 ? (groups > 0 ? groups : 1) : 4096);
+    hipLaunchKernelGGL((k_prune_final<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
+                       n_cells, K, cpb, (const uint8_t*)w.removed, kept, mask, W, d_nkept,
+                       w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
+    GIS_LAUNCH_CHECK("k_prune_final");
+  } else {
+    hipLaunchKernelGGL((k_prune_final_wide<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s,
+                       row_ptr, col, out, n_cells, K, (const uint8_t*)w.removed, kept, mask, W,
+                       d_nkept, w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
+    GIS_LAUNCH_CHECK("k_prune_final_wide");
+  }
   return GIS_OK;
 }
 

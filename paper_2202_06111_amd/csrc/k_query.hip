@@ -38,7 +38,7 @@ __global__ void k_query(CoverIndex ci, GridArgs g, const uint8_t* kept, const ui
           for (int d = 0; d < g.n; ++d) lin = lin * ci.dims[L][d] + (k[d] >> s);
           const uint8_t st = ci.state[ci.off[L] + lin];
           if (st == ST_LEAF) {
-            cell = ci.id[ci.off[L] + lin];
+            cell = (ci.pfx[ci.off[L] + lin] & 0xffffffffll) - ci.pbase;
             break;
           }
           if (st != ST_REFINED) break;

@@ -93,35 +93,30 @@ __global__ void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule, uint8
       }
     }
     boundary[gc] = bnd ? 1 : 0;
+    // the next covering: the cell itself, or its 2^n children if it is a
+    // boundary cell (jobs that stopped have no flag array)
+    const CoverIndex& next = J.next;
+    if (kept[gc] && next.state) {
+      const int L = b.level[gc];
+      if (!bnd) {
+        int64_t lin = 0;
+#pragma unroll
+        for (int d = 0; d < N; ++d) lin = lin * next.dims[L][d] + b.idx[gc * N + d];
+        next.state[next.off[L] + lin] = 1;
+      } else {
+        for (int ch = 0; ch < (1 << N); ++ch) {
+          int64_t lin = 0;
+#pragma unroll
+          for (int d = 0; d < N; ++d)
+            lin = lin * next.dims[L + 1][d] +
+                  (2 * (int64_t)b.idx[gc * N + d] + ((ch >> (N - 1 - d)) & 1));
+          next.state[next.off[L + 1] + lin] = 1;
+        }
+      }
+    }
   }
   const uint64_t m = __ballot(bnd);  // one atomic per wave (blocks never straddle jobs)
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_boundary, (unsigned long long)__popcll(m));
-}
-
-template <int N>
-__global__ void k_next_flags(BatchArgs b, const uint8_t* kept, const uint8_t* boundary) {
-  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
-  const Job& J = b.jobs[jb];
-  const CoverIndex& next = J.next;
-  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
-  if (c >= J.n_cells || !next.state) return;  // jobs that stopped set no flags
-  const int64_t gc = J.cell_off + c;
-  if (!kept[gc]) return;
-  const int L = b.level[gc];
-  if (!boundary[gc]) {
-    int64_t lin = 0;
-#pragma unroll
-    for (int d = 0; d < N; ++d) lin = lin * next.dims[L][d] + b.idx[gc * N + d];
-    next.state[next.off[L] + lin] = 1;
-    return;
-  }
-  for (int ch = 0; ch < (1 << N); ++ch) {
-    int64_t lin = 0;
-#pragma unroll
-    for (int d = 0; d < N; ++d)
-      lin = lin * next.dims[L + 1][d] + (2 * (int64_t)b.idx[gc * N + d] + ((ch >> (N - 1 - d)) & 1));
-    next.state[next.off[L + 1] + lin] = 1;
-  }
 }
 
 // pos: exclusive scan of the batch's flag array (jobs' arrays back to back).
@@ -199,15 +194,6 @@ int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, ui
   return GIS_OK;
 }
 
-int32_t batch_next_flags(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
-                         hipStream_t s) {
-  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
-#define GIS_CALL(N) hipLaunchKernelGGL(k_next_flags<N>, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, boundary)
-  GIS_DIM_SWITCH(b.n, GIS_CALL)
-#undef GIS_CALL
-  GIS_LAUNCH_CHECK("k_next_flags");
-  return GIS_OK;
-}
 
 int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,
                       int32_t* idx_out, JobStats* stats, hipStream_t s) {

@@ -29,20 +29,32 @@ __device__ __forceinline__ int64_t block_exclusive(int64_t v, int64_t* lds, int6
   return before + x - v;
 }
 
+// Element -> summand: the element itself, or for covering-index states the
+// packed pair (leaf, hole << 32).
 template <typename T>
+struct Plain {
+  __device__ static int64_t get(T v) { return (int64_t)v; }
+};
+struct LeafHole {
+  __device__ static int64_t get(uint8_t st) {
+    return (int64_t)(st == ST_LEAF) + ((int64_t)(st == ST_HOLE) << 32);
+  }
+};
+
+template <typename T, typename C = Plain<T>>
 __global__ __launch_bounds__(kScanBlock) void k_tile_sums(const T* in, int64_t n, int64_t* sums) {
   __shared__ int64_t lds[kScanBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kTileElems + (int64_t)threadIdx.x * kScanItems;
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) s += (int64_t)in[base + i];
+    if (base + i < n) s += C::get(in[base + i]);
   int64_t total;
   block_exclusive(s, lds, total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-template <typename T>
+template <typename T, typename C = Plain<T>>
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const T* in, int64_t n,
                                                           const int64_t* offsets, int64_t* out,
                                                           int64_t* d_total) {
@@ -52,7 +64,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const T* in, int64_t n
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = base + i < n ? (int64_t)in[base + i] : 0;
+    v[i] = base + i < n ? C::get(in[base + i]) : 0;
     s += v[i];
   }
   int64_t total;
@@ -71,12 +83,12 @@ size_t tmp_elems(int64_t n) {
   return (size_t)(2 * nb) + tmp_elems(nb);
 }
 
-template <typename T>
+template <typename T, typename C = Plain<T>>
 int32_t scan_impl(const T* in, int64_t* out, int64_t n, int64_t* d_total, int64_t* tmp,
                   hipStream_t s) {
   if (n <= 0) return d_total ? fill_i64(d_total, 0, 1, s) : GIS_OK;
   if (n <= kTileElems) {
-    hipLaunchKernelGGL((k_tile_scan<T>), dim3(1), dim3(kScanBlock), 0, s, in, n,
+    hipLaunchKernelGGL((k_tile_scan<T, C>), dim3(1), dim3(kScanBlock), 0, s, in, n,
                        (const int64_t*)nullptr, out, d_total);
     GIS_LAUNCH_CHECK("k_tile_scan");
     return GIS_OK;
@@ -84,11 +96,11 @@ int32_t scan_impl(const T* in, int64_t* out, int64_t n, int64_t* d_total, int64_
   const int64_t nb = (n + kTileElems - 1) / kTileElems;
   int64_t* sums = tmp;
   int64_t* offs = tmp + nb;
-  hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, sums);
+  hipLaunchKernelGGL((k_tile_sums<T, C>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, sums);
   GIS_LAUNCH_CHECK("k_tile_sums");
   int32_t rc = scan_impl<int64_t>(sums, offs, nb, nullptr, tmp + 2 * nb, s);
   if (rc != GIS_OK) return rc;
-  hipLaunchKernelGGL((k_tile_scan<T>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
+  hipLaunchKernelGGL((k_tile_scan<T, C>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
                      (const int64_t*)offs, out, d_total);
   GIS_LAUNCH_CHECK("k_tile_scan");
   return GIS_OK;
@@ -109,6 +121,9 @@ int32_t scan_exclusive_u8(const uint8_t* in, int64_t* out, int64_t n, int64_t* d
 int32_t scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, int64_t* d_total, void* tmp,
                            hipStream_t s) {
   return scan_impl<int32_t>(in, out, n, d_total, (int64_t*)tmp, s);
+}
+int32_t scan_leaf_hole(const uint8_t* state, int64_t* out, int64_t n, void* tmp, hipStream_t s) {
+  return scan_impl<uint8_t, LeafHole>(state, out, n, out + n, (int64_t*)tmp, s);
 }
 
 }  // namespace gis
