@@ -341,7 +341,7 @@ int32_t upload_jobs(gis_ctx* ctx, const Batch& B, hipStream_t s) {
 // allocates the index and flag buffers, clears the index states and uploads
 // the job table.
 int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells, bool want_arrays,
-                     const std::vector<char>& with_next, hipStream_t s) {
+                     const std::vector<char>& with_next, hipStream_t s, bool clear_states = true) {
   int32_t rc;
   int64_t cell_off = 0, slot_off = 0, next_off = 0;
   int64_t blk[LK_KINDS] = {0, 0, 0, 0};
@@ -399,7 +399,8 @@ int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells
     J.next.state = nxt ? (uint8_t*)ctx->next_state.ptr + J.next_off : nullptr;
   }
   if ((rc = upload_jobs(ctx, B, s))) return rc;
-  if (slot_off > 0 && (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, slot_off, s)))
+  if (clear_states && slot_off > 0 &&
+      (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, slot_off, s)))
     return rc;
   return GIS_OK;
 }
@@ -588,12 +589,11 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
                                const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t sweeps,
                                hipStream_t s, const Batch* B, const uint8_t* level,
                                const int32_t* idx) {
-  int32_t rc;
-  if ((rc = prune_final(row_ptr, col, out, n_cells, K, analysis, w, kept, mask, (K + 63) / 64,
-                        dcnt(ctx)->n_kept, sweeps, s)))
-    return rc;
-  if (B) return batch_count_kept(B->args(level, idx), kept, B->d_stats, s);
-  return GIS_OK;
+  (void)level;
+  (void)idx;
+  return prune_final(row_ptr, col, out, n_cells, K, analysis, w, kept, mask, (K + 63) / 64,
+                     dcnt(ctx)->n_kept, sweeps, B ? B->d_jobs : nullptr, B ? B->n_jobs : 0,
+                     B ? B->d_stats : nullptr, s);
 }
 
 bool sweeps_fit(int64_t n_edges, int32_t K) { return K <= 256 && n_edges <= kSweepEdges; }
@@ -605,14 +605,15 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
                       int64_t n_cells, int32_t K, int64_t cap_edges, const int64_t* d_total,
                       int64_t est_edges, int32_t analysis, uint8_t* kept, uint64_t* mask,
                       hipStream_t s, const Batch* B = nullptr, const uint8_t* level = nullptr,
-                      const int32_t* idx = nullptr, int32_t first = kFirstSweeps) {
+                      const int32_t* idx = nullptr, int32_t first = kFirstSweeps,
+                      bool clear_removed = true) {
   int32_t rc;
   if (n_cells * (int64_t)K > (int64_t)INT32_MAX) {  // the reverse CSR stores 32-bit row ids
     set_error("a graph of more than 2^31-1 rows is not supported");
     return GIS_E_UNSUPPORTED;
   }
   if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
-  if ((rc = fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s))) return rc;
+  if (clear_removed && (rc = fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s))) return rc;
   ctx->first_sweeps = sweeps_fit(est_edges, K) ? first : 0;
   if (ctx->first_sweeps == 0) return GIS_OK;
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
@@ -843,7 +844,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   // round-0 covering: each job's full coarse grid
   if ((rc = ensure(ctx->lvA, (size_t)total + 16)) || (rc = ensure(ctx->ixA, (size_t)total * n * 4 + 16)))
     return rc;
-  if ((rc = batch_layout(ctx, B, cells, rounds > 0, nxt, s))) return rc;
+  if ((rc = batch_layout(ctx, B, cells, rounds > 0, nxt, s, false))) return rc;
   if ((rc = batch_coarse(B.args(nullptr, nullptr), (uint8_t*)ctx->lvA.ptr, (int32_t*)ctx->ixA.ptr, s)))
     return rc;
 
@@ -902,15 +903,29 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     const bool last = r == rounds;
     if (r > 0) {
       for (int j = 0; j < nj; ++j) nxt[j] = (!last && active[j]) ? 1 : 0;
-      if ((rc = batch_layout(ctx, B, cells, !last, nxt, s))) return fail_all(rc);
+      if ((rc = batch_layout(ctx, B, cells, !last, nxt, s, false))) return fail_all(rc);
     }
     const int64_t n_cells = B.total_cells;
     const int64_t n_rows = n_cells * K;
     const size_t want_col = (size_t)((double)n_rows * edges_per_row * 1.25) + 64;
     if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)) ||
         (rc = ensure(ctx->col, want_col * 4)) || (rc = ensure(ctx->kept, (size_t)n_cells + 16)) ||
-        (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)))
+        (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)) ||
+        (rc = ensure(ctx->removed, (size_t)n_cells + 16)))
       return fail_all(rc);
+    // one launch clears the counters and job stats, the index states (NONE
+    // is 0) and the analysis' removed flags
+    auto clear_round = [&]() -> int32_t {
+      ZeroRanges z{};
+      z.p[0] = (uint32_t*)ctx->counters.ptr;
+      z.words[0] = (int64_t)((kStatsOff + sizeof(JobStats) * B.n_jobs) / 4);
+      z.p[1] = (uint32_t*)ctx->idx_state.ptr;
+      z.words[1] = B.total_slots > 0 ? (B.total_slots + 3) / 4 : 0;
+      z.p[2] = (uint32_t*)ctx->removed.ptr;
+      z.words[2] = (n_cells + 3) / 4;
+      z.n = 3;
+      return zero_ranges(z, s);
+    };
     // the next covering has at most 2^n children per current cell
     const int64_t cap = last ? 0 : (n_cells << n);
     DevBuf& lvN = cur_is_A ? ctx->lvB : ctx->lvA;
@@ -926,7 +941,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       int32_t e;
       if ((e = enqueue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.cap_edges,
                              &dcnt(ctx)->total_edges, (int64_t)(edges_per_row * (double)n_rows),
-                             o.analysis, kept, mask, s, &B, lv, ix, sweep_hint)))
+                             o.analysis, kept, mask, s, &B, lv, ix, sweep_hint, false)))
         return e;
       GIS_HIP(hipEventRecord(ev[2], s));
       if (!last && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
@@ -936,7 +951,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       GIS_HIP(hipEventRecord(ev[3], s));
       return sync_stats(ctx, B, s);
     };
-    if ((rc = zero_all(ctx, B, s))) return fail_all(rc);
+    if ((rc = clear_round())) return fail_all(rc);
     GIS_HIP(hipEventRecord(ev[0], s));
     if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
     if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
@@ -948,11 +963,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if ((rc = ensure(ctx->col, (size_t)gr.n_edges * 4))) return fail_all(rc);
       gr.col = (int32_t*)ctx->col.ptr;
       gr.cap_edges = (int64_t)(ctx->col.bytes / 4);
-      if ((rc = zero_all(ctx, B, s))) return fail_all(rc);
-      // the subdivision marked dropped cells in the index: rebuild it for the emit
-      if (B.total_slots > 0 &&
-          (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, B.total_slots, s)))
-        return fail_all(rc);
+      // counters, removed flags, and the index (the subdivision marked the
+      // dropped cells in it): all rebuilt for the emit
+      if ((rc = clear_round())) return fail_all(rc);
       if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
       GIS_HIP(hipEventRecord(ev[0], s));
       if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);

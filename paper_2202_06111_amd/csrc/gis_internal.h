@@ -114,6 +114,13 @@ int32_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int32_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 int32_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 int32_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+// Up to four buffers cleared by one launch (sizes in 32-bit words).
+struct ZeroRanges {
+  uint32_t* p[4];
+  int64_t words[4];
+  int n;
+};
+int32_t zero_ranges(const ZeroRanges& z, hipStream_t s);
 
 // ---------------------------------------------------------------- jobs
 // A batch runs several independent solves (jobs) through the same launches.
@@ -164,6 +171,16 @@ __device__ __forceinline__ void stage_index(CoverIndex* dst, const CoverIndex* s
   for (int i = threadIdx.x; i < words; i += blockDim.x)
     ((int32_t*)dst)[i] = ((const int32_t*)src)[i];
   __syncthreads();
+}
+
+// Job owning a global cell (binary search over the jobs' cell offsets).
+__device__ __forceinline__ int32_t job_of_cell(const Job* jobs, int32_t n_jobs, int64_t cell) {
+  int32_t lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].cell_off <= cell) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // Job owning a global row (binary search over the jobs' row offsets).
@@ -246,11 +263,13 @@ int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t
                              int32_t analysis, const PruneWork& w, int32_t first, int32_t count,
                              hipStream_t s);
 // kept flags, masks (mask_words per cell) and the kept count (added to
-// *d_nkept); with sweeps > 0, only if sweep sweeps-1 removed nothing.
+// *d_nkept, and per job to stats[j].n_kept when stats is set); with
+// sweeps > 0, only if sweep sweeps-1 removed nothing.
 int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
-                    unsigned long long* d_nkept, int32_t sweeps, hipStream_t s);
+                    unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
+                    JobStats* stats, hipStream_t s);
 
 // k_index.hip, job-batched: covering indexes of every job's cell list (the
 // jobs' state arrays are cleared first by the caller).  Flags invalid lists in
@@ -287,6 +306,9 @@ int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8
 int32_t batch_coarse(const BatchArgs& b, uint8_t* level, int32_t* idx, hipStream_t s);
 // Kept cells per job into stats[j].n_kept.
 int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stats, hipStream_t s);
+// The same from the job table alone (any launch layout).
+int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
+                               const uint8_t* kept, JobStats* stats, hipStream_t s);
 
 // k_query.hip
 int32_t launch_query(const CoverIndex& ci, const GridArgs& g, const uint8_t* kept,

@@ -32,6 +32,13 @@ int32_t fill(T* p, T v, int64_t n, hipStream_t s) {
   return GIS_OK;
 }
 
+__global__ void k_zero_ranges(ZeroRanges z) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int r = 0; r < z.n; ++r)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.words[r]; i += stride)
+      z.p[r][i] = 0u;
+}
+
 __global__ void k_max_level(const uint8_t* level, int64_t n, uint32_t* out) {
   uint32_t m = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -184,6 +191,17 @@ int32_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) { return fil
 int32_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 int32_t fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 int32_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+
+int32_t zero_ranges(const ZeroRanges& z, hipStream_t s) {
+  int64_t most = 0;
+  for (int r = 0; r < z.n; ++r) most = z.words[r] > most ? z.words[r] : most;
+  if (most == 0) return GIS_OK;
+  int64_t nb = (most + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_zero_ranges, dim3((unsigned)nb), dim3(256), 0, s, z);
+  GIS_LAUNCH_CHECK("k_zero_ranges");
+  return GIS_OK;
+}
 
 int32_t max_level(const uint8_t* level, int64_t n_cells, uint32_t* d_out, hipStream_t s) {
   int32_t rc = fill_u32(d_out, 0u, 1, s);

@@ -307,10 +307,13 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
                                                      uint64_t* mask, int32_t W,
                                                      unsigned long long* nkept,
                                                      const int64_t* d_total, int64_t cap_edges,
-                                                     const int32_t* last, int32_t sweeps) {
+                                                     const int32_t* last, int32_t sweeps,
+                                                     const Job* jobs, int32_t n_jobs,
+                                                     JobStats* stats) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
   if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
   __shared__ uint8_t ok[256];
+  __shared__ unsigned int grp_kept;
   const int t = threadIdx.x;
   unsigned long long mine = 0;
   const int64_t stride = (int64_t)gridDim.x * cpb;
@@ -320,7 +323,12 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
     if (t < cpb * K && c < n_cells && !removed[c])
       good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
     ok[t] = good ? 1 : 0;
+    if (t == 0) grp_kept = 0;
     __syncthreads();
+    // per-job kept counts: one atomic per group when the group lies in one job
+    const int64_t glast = g0 + cpb - 1 < n_cells ? g0 + cpb - 1 : n_cells - 1;
+    const int32_t jfirst = stats ? job_of_cell(jobs, n_jobs, g0) : 0;
+    const bool one_job = stats && job_of_cell(jobs, n_jobs, glast) == jfirst;
     if (t < cpb * W) {
       const int64_t cc = g0 + t / W;
       const int w = t % W;
@@ -333,10 +341,15 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
         if (w == 0) {
           kept[cc] = k ? 1 : 0;
           mine += k;
+          if (k && stats) {
+            if (one_job) atomicAdd(&grp_kept, 1u);
+            else atomicAdd(&stats[job_of_cell(jobs, n_jobs, cc)].n_kept, 1ull);
+          }
         }
       }
     }
     __syncthreads();
+    if (t == 0 && one_job && grp_kept) atomicAdd(&stats[jfirst].n_kept, (unsigned long long)grp_kept);
   }
   for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
   if ((t & 63) == 0 && mine) atomicAdd(nkept, mine);
@@ -440,21 +453,25 @@ int32_t frontier_init(const int64_t* row_ptr, const uint8_t* out, int64_t n_cell
 template <int MODE>
 int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                    int64_t n_cells, int32_t K, const PruneWork& w, uint8_t* kept, uint64_t* mask,
-                   int32_t W, unsigned long long* d_nkept, int32_t sweeps, hipStream_t s) {
+                   int32_t W, unsigned long long* d_nkept, int32_t sweeps, const Job* jobs,
+                   int32_t n_jobs, JobStats* stats, hipStream_t s) {
   if (K <= 256) {
     const int32_t cpb = 256 / K;
     const int64_t groups = (n_cells + cpb - 1) / cpb;
     const unsigned nb = (unsigned)(groups < 4096 ? (groups > 0 ? groups : 1) : 4096);
     hipLaunchKernelGGL((k_prune_final<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
                        n_cells, K, cpb, (const uint8_t*)w.removed, kept, mask, W, d_nkept,
-                       w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
+                       w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats);
     GIS_LAUNCH_CHECK("k_prune_final");
+    return GIS_OK;
   } else {
     hipLaunchKernelGGL((k_prune_final_wide<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s,
                        row_ptr, col, out, n_cells, K, (const uint8_t*)w.removed, kept, mask, W,
                        d_nkept, w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
     GIS_LAUNCH_CHECK("k_prune_final_wide");
   }
+  // per-job kept counts for the wide variant
+  if (stats) return batch_count_kept_cells(jobs, n_jobs, n_cells, kept, stats, s);
   return GIS_OK;
 }
 
@@ -502,13 +519,14 @@ int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t
 int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
-                    unsigned long long* d_nkept, int32_t sweeps, hipStream_t s) {
+                    unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
+                    JobStats* stats, hipStream_t s) {
   if (n_cells == 0) return GIS_OK;
   if (analysis == GIS_ANALYSIS_NONLEAVING)
     return final_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, kept, mask,
-                                               mask_words, d_nkept, sweeps, s);
+                                               mask_words, d_nkept, sweeps, jobs, n_jobs, stats, s);
   return final_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, kept, mask,
-                                             mask_words, d_nkept, sweeps, s);
+                                             mask_words, d_nkept, sweeps, jobs, n_jobs, stats, s);
 }
 
 }  // namespace gis

@@ -18,17 +18,30 @@ namespace gis {
 
 namespace {
 
-// Is finest cell k covered by a kept cell?  (k inside the grid)
+// Is finest cell k covered by a kept cell?  (k inside the grid)  A leaf's
+// ancestors are all REFINED, so k is covered exactly when one of its
+// ancestor slots is a LEAF; the slots of four levels are read together
+// (independent loads) instead of one level after the other.
 template <int N>
 __device__ __forceinline__ bool covered(const CoverIndex& ci, const int64_t* k) {
-  for (int L = 0; L <= ci.lmax; ++L) {
-    const int s = ci.lmax - L;
-    int64_t lin = 0;
+  for (int L0 = 0; L0 <= ci.lmax; L0 += 4) {
+    uint8_t st[4];
 #pragma unroll
-    for (int d = 0; d < N; ++d) lin = lin * ci.dims[L][d] + (k[d] >> s);
-    const uint8_t st = ci.state[ci.off[L] + lin];
-    if (st == ST_LEAF) return true;
-    if (st != ST_REFINED) return false;
+    for (int q = 0; q < 4; ++q) {
+      const int L = L0 + q;
+      st[q] = ST_NONE;
+      if (L <= ci.lmax) {
+        const int s = ci.lmax - L;
+        int64_t lin = 0;
+#pragma unroll
+        for (int d = 0; d < N; ++d) lin = lin * ci.dims[L][d] + (k[d] >> s);
+        st[q] = ci.state[ci.off[L] + lin];
+      }
+    }
+    bool leaf = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) leaf |= st[q] == ST_LEAF;
+    if (leaf) return true;
   }
   return false;
 }
@@ -121,33 +134,31 @@ __global__ void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule, uint8
 
 // pos: exclusive scan of the batch's flag array (jobs' arrays back to back).
 // Clears every flag it consumes, so the array is zero for the next call.
+// Also records each job's first new cell and the new cells before each of
+// its levels (from the threads at the first slot of the job and of each level).
 __global__ void k_compact(BatchArgs b, const int64_t* pos, int64_t cap, uint8_t* level_out,
-                          int32_t* idx_out) {
+                          int32_t* idx_out, JobStats* stats) {
   const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_NEXT, blockIdx.x);
   const Job& J = b.jobs[jb];
   const CoverIndex& next = J.next;
   const int64_t sl = (blockIdx.x - J.blk[LK_NEXT]) * blockDim.x + threadIdx.x;
-  if (!next.state || sl >= next.off[next.lmax + 1] || !next.state[sl]) return;
+  if (!next.state || sl >= next.off[next.lmax + 1]) return;
+  int L = 0;
+  while (sl >= next.off[L + 1]) ++L;
+  if (sl == next.off[L]) {
+    stats[jb].level_start[L] = pos[J.next_off + sl];
+    if (L == 0) stats[jb].next_start = pos[J.next_off + sl];
+  }
+  if (!next.state[sl]) return;
   next.state[sl] = 0;
   const int64_t p = pos[J.next_off + sl];
   if (p >= cap) return;
-  int L = 0;
-  while (sl >= next.off[L + 1]) ++L;
   int64_t rem = sl - next.off[L];
   level_out[p] = (uint8_t)L;
   for (int d = next.n - 1; d >= 0; --d) {
     idx_out[p * next.n + d] = (int32_t)(rem % next.dims[L][d]);
     rem /= next.dims[L][d];
   }
-}
-
-// For every job: its first new cell and the new cells before each level.
-__global__ void k_level_starts(BatchArgs b, const int64_t* pos, JobStats* stats) {
-  const int32_t jb = blockIdx.x;
-  const Job& J = b.jobs[jb];
-  const int L = threadIdx.x;
-  if (L == 0) stats[jb].next_start = pos[J.next_off];
-  if (L <= J.next.lmax) stats[jb].level_start[L] = pos[J.next_off + J.next.off[L]];
 }
 
 __global__ void k_coarse(BatchArgs b, uint8_t* level, int32_t* idx) {
@@ -173,7 +184,25 @@ __global__ void k_count_kept(BatchArgs b, const uint8_t* kept, JobStats* stats) 
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_kept, (unsigned long long)__popcll(m));
 }
 
+__global__ void k_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
+                                   const uint8_t* kept, JobStats* stats) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+       c += (int64_t)gridDim.x * blockDim.x)
+    if (kept[c]) atomicAdd(&stats[job_of_cell(jobs, n_jobs, c)].n_kept, 1ull);
+}
+
 }  // namespace
+
+int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
+                               const uint8_t* kept, JobStats* stats, hipStream_t s) {
+  if (n_cells == 0) return GIS_OK;
+  int64_t nb = (n_cells + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_count_kept_cells, dim3((unsigned)nb), dim3(256), 0, s, jobs, n_jobs, n_cells,
+                     kept, stats);
+  GIS_LAUNCH_CHECK("k_count_kept_cells");
+  return GIS_OK;
+}
 
 #define GIS_DIM_SWITCH(N_, CALL)                                   \
   switch (N_) {                                                    \
@@ -199,12 +228,8 @@ int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8
                       int32_t* idx_out, JobStats* stats, hipStream_t s) {
   if (b.blocks[LK_NEXT] > 0) {
     hipLaunchKernelGGL(k_compact, dim3((unsigned)b.blocks[LK_NEXT]), dim3(256), 0, s, b, pos, cap,
-                       level_out, idx_out);
+                       level_out, idx_out, stats);
     GIS_LAUNCH_CHECK("k_compact");
-  }
-  if (b.n_jobs > 0) {
-    hipLaunchKernelGGL(k_level_starts, dim3((unsigned)b.n_jobs), dim3(64), 0, s, b, pos, stats);
-    GIS_LAUNCH_CHECK("k_level_starts");
   }
   return GIS_OK;
 }
