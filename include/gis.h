@@ -156,6 +156,30 @@ typedef struct gis_solve_info {
 int32_t gis_ctx_create(int32_t device, gis_ctx** out);
 void gis_ctx_destroy(gis_ctx* ctx);
 
+/* Schedule parameters of a context.  They change launch shapes and where the
+ * host checks for convergence, never results (the analysis reaches the same
+ * fixed point in any order, Sec. 2.3).  Defaults in brackets; gis_autotune
+ * picks them by timing. */
+typedef struct gis_tuning {
+  int32_t first_sweeps;    /* analysis sweeps enqueued with a round before its convergence
+                              check [16]; later rounds enqueue what the previous round
+                              needed plus a margin, at most this many (1..256) */
+  int32_t sweep_batch;     /* sweeps between later checks [8] (1..256) */
+  int64_t sweep_edges;     /* graphs with more edges (or K > 256) skip the sweeps and run
+                              the frontier phase [8388608] (>= 0) */
+  int32_t frontier_batch;  /* frontier steps between checks [16] (1..256) */
+  int32_t sweep_blocks;    /* grid cap of a sweep launch [4096] (1..65536) */
+  int32_t front_blocks;    /* grid of a frontier step, 4 waves per block [2048] (1..65536) */
+  int32_t use_graphs;      /* nonzero: rounds are captured as HIP graphs and replayed when
+                              a later round has the same launches [0] */
+  int32_t reserved[2];
+} gis_tuning;
+
+/* Reads / replaces the context's schedule parameters.  GIS_E_INVAL when a
+ * field is out of range (nothing is changed then). */
+int32_t gis_get_tuning(const gis_ctx* ctx, gis_tuning* out);
+int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* tuning);
+
 /* Symbolic image of a covering (Sec. 2.2, Definition 1).  d_u: K x m inputs
  * (FP64).  Fills row_ptr, out and, when cap_edges suffices, col; synchronises
  * to report n_edges, n_out and n_recheck.  GIS_E_CAPACITY: n_edges holds the

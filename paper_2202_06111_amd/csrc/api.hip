@@ -7,6 +7,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -59,7 +62,7 @@ struct Counters {
   uint32_t maxlevel;
   int64_t n_next;
   int32_t sweep_last;  // analysis: 1 + index of the last sweep that removed a cell
-  int32_t fcount[2];   // analysis: frontier list lengths
+  int32_t fcount[3];   // analysis: frontier list lengths (rotating)
 };
 
 // Pinned host staging of a device array of T.
@@ -105,22 +108,30 @@ struct gis_ctx {
   uint32_t lb_epoch = 0;
   bool lb_clean = false, prune_clean = false, next_clean = false;
   int32_t first_sweeps = 0;  // sweeps of the last enqueue_prune
+  gis_tuning tune{16, 8, (int64_t)8 << 20, 16, 4096, 2048, 0, {0, 0}};
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
-  DevBuf removed, rptr, rrow, rcur, rowbad, cand, front;
+  DevBuf removed, rptr, rrow, rcur, rowstate, good, front;
   DevBuf bnd;
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+// A solution's arrays (covering, kept flags, masks, and the covering index
+// unless the covering is a full level-0 grid) share one device block.
 struct gis_solution {
   int device = 0;
   GridArgs grid{};
   CoverIndex ci{};
   int32_t K = 0, W = 0;
   int64_t n_cells = 0;
-  DevBuf level, idx, kept, mask, state, pfx;
+  void* block = nullptr;
+  size_t block_bytes = 0;
+  uint8_t* level = nullptr;
+  int32_t* idx = nullptr;
+  uint8_t* kept = nullptr;
+  uint64_t* mask = nullptr;
   gis_solve_info info{};
 };
 
@@ -552,11 +563,11 @@ int32_t run_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* i
   return finish_build(ctx, B, gr);
 }
 
-constexpr int32_t kFirstSweeps = 16;    // sweeps enqueued before the first convergence check
-constexpr int32_t kSweepBatch = 8;      // sweeps between later convergence checks
-constexpr int32_t kMaxSweeps = 256;     // then the frontier phase takes over
-constexpr int64_t kSweepEdges = 8 << 20;  // larger graphs go to the frontier phase directly
-constexpr int32_t kFrontierBatch = 16;  // frontier steps between convergence checks
+// The schedule of the analysis (sweeps enqueued with a round, sweeps and
+// frontier steps between later convergence checks, the graph size beyond
+// which the frontier phase starts at once, grid shapes) is the context's
+// gis_tuning; after kMaxSweeps sweeps the frontier phase takes over.
+constexpr int32_t kMaxSweeps = 256;
 
 // The analysis of a graph.  enqueue_prune enqueues the first batch of sweeps
 // and the final pass (kept flags, masks, kept counts), which does its work
@@ -574,11 +585,15 @@ PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   w.rptr = (int64_t*)ctx->rptr.ptr;
   w.rrow = (int32_t*)ctx->rrow.ptr;
   w.rcur = (int32_t*)ctx->rcur.ptr;
-  w.rowbad = (uint8_t*)ctx->rowbad.ptr;
-  w.cand = (uint8_t*)ctx->cand.ptr;
+  w.rowstate = (uint32_t*)ctx->rowstate.ptr;
+  w.good = (int32_t*)ctx->good.ptr;
+  w.rowbad = (uint8_t*)ctx->rowstate.ptr;
+  w.cand = (uint8_t*)ctx->good.ptr;
   w.front = (int32_t*)ctx->front.ptr;
   w.fcount = dcnt(ctx)->fcount;
   w.scan_tmp = ctx->scan_tmp.ptr;
+  w.sweep_blocks = ctx->tune.sweep_blocks;
+  w.front_blocks = ctx->tune.front_blocks;
   w.d_total = d_total;
   w.cap_edges = cap_edges;
   return w;
@@ -596,7 +611,9 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
                      B ? B->d_stats : nullptr, s);
 }
 
-bool sweeps_fit(int64_t n_edges, int32_t K) { return K <= 256 && n_edges <= kSweepEdges; }
+bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
+  return K <= 256 && n_edges <= ctx->tune.sweep_edges;
+}
 
 // est_edges: the graph's edge count, or an estimate of it (it only chooses
 // between the two phases).
@@ -605,7 +622,7 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
                       int64_t n_cells, int32_t K, int64_t cap_edges, const int64_t* d_total,
                       int64_t est_edges, int32_t analysis, uint8_t* kept, uint64_t* mask,
                       hipStream_t s, const Batch* B = nullptr, const uint8_t* level = nullptr,
-                      const int32_t* idx = nullptr, int32_t first = kFirstSweeps,
+                      const int32_t* idx = nullptr, int32_t first = 0,
                       bool clear_removed = true) {
   int32_t rc;
   if (n_cells * (int64_t)K > (int64_t)INT32_MAX) {  // the reverse CSR stores 32-bit row ids
@@ -614,7 +631,8 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   }
   if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
   if (clear_removed && (rc = fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s))) return rc;
-  ctx->first_sweeps = sweeps_fit(est_edges, K) ? first : 0;
+  if (first <= 0) first = ctx->tune.first_sweeps;
+  ctx->first_sweeps = sweeps_fit(ctx, est_edges, K) ? first : 0;
   if (ctx->first_sweeps == 0) return GIS_OK;
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
   if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps, s)))
@@ -644,12 +662,13 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
   if ((rc = fill_i32(w.last, 0, 1, s))) return rc;
   int32_t done = 0;
   bool converged = false;
-  if (sweeps_fit(n_edges, K)) {
-    for (; done < kMaxSweeps && !converged; done += kSweepBatch) {
-      if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, done, kSweepBatch, s)))
+  const int32_t batch = ctx->tune.sweep_batch, fbatch = ctx->tune.frontier_batch;
+  if (sweeps_fit(ctx, n_edges, K)) {
+    for (; done < kMaxSweeps && !converged; done += batch) {
+      if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, done, batch, s)))
         return rc;
       if ((rc = sync_counters(ctx, s))) return rc;
-      converged = ctx->h_counters->sweep_last < done + kSweepBatch;
+      converged = ctx->h_counters->sweep_last < done + batch;
     }
   }
   if (!converged) {
@@ -657,26 +676,24 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
     if ((rc = ensure(ctx->rptr, (size_t)(n_cells + 1) * 8)) ||
         (rc = ensure(ctx->rrow, (size_t)cap_edges * 4 + 16)) ||
         (rc = ensure(ctx->rcur, (size_t)n_cells * 4 + 16, &fresh)) ||
-        (rc = ensure(ctx->cand, (size_t)n_cells + 16, &fresh)) ||
-        (rc = ensure(ctx->rowbad, (size_t)n_rows + 16)) ||
+        (rc = ensure(ctx->good, (size_t)n_cells * 4 + 16)) ||
+        (rc = ensure(ctx->rowstate, std::max((size_t)n_rows * 4, (size_t)n_cells * ((K + 7) & ~7)) + 16)) ||
         (rc = ensure(ctx->front, (size_t)n_cells * 8 + 16)) ||
         (rc = ensure(ctx->scan_tmp, scan_tmp_bytes(n_cells + 1))))
       return rc;
     w = prune_work(ctx, cap_edges, nullptr);
     if (fresh || !ctx->prune_clean) {
       // whole buffers: later calls with more cells rely on them too
-      if ((rc = fill_i32(w.rcur, 0, (int64_t)(ctx->rcur.bytes / 4), s)) ||
-          (rc = fill_u8(w.cand, 0, (int64_t)ctx->cand.bytes, s)))
-        return rc;
+      if ((rc = fill_i32(w.rcur, 0, (int64_t)(ctx->rcur.bytes / 4), s))) return rc;
     }
     ctx->prune_clean = false;  // until the frontier has run out
     if ((rc = prune_frontier_start(row_ptr, col, out, n_cells, K, analysis, w, s))) return rc;
-    for (int32_t t = 0;; t += kFrontierBatch) {
-      if ((rc = prune_frontier_steps(row_ptr, col, n_cells, K, analysis, w, t, kFrontierBatch, s)))
+    for (int32_t t = 0;; t += fbatch) {
+      if ((rc = prune_frontier_steps(row_ptr, col, n_cells, K, analysis, w, t, fbatch, s)))
         return rc;
       if ((rc = sync_counters(ctx, s))) return rc;
-      if (ctx->h_counters->fcount[(t + kFrontierBatch) & 1] == 0) break;
-      if (t > n_cells + kFrontierBatch) {  // every step removes a cell: cannot happen
+      if (ctx->h_counters->fcount[(t + fbatch) % 3] == 0) break;
+      if (t > n_cells + fbatch) {  // every step removes a cell: cannot happen
         set_error("internal: the frontier phase did not terminate");
         return GIS_E_INTERNAL;
       }
@@ -751,7 +768,69 @@ void next_sizes(gis_ctx* ctx, Batch& B, int64_t n_new, std::vector<int64_t>& cel
   }
 }
 
-// Copies job j's covering, kept flags, masks and index into a new solution.
+// Device blocks of solutions.  A freed block is kept for the process's later
+// solutions (at most kCacheBlocks blocks and kCacheBytes bytes per device)
+// instead of going back to the driver, so a loop of solves stops allocating
+// after its first iterations.  Cached blocks are never returned.
+constexpr size_t kCacheBlocks = 32;
+constexpr size_t kCacheBytes = (size_t)1 << 30;
+
+struct BlockCache {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void*>> free;
+  std::map<int, size_t> bytes;
+};
+
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();  // outlives every solution
+  return *c;
+}
+
+// A block of at least `want` bytes on the current device `dev`: a cached one
+// no more than twice that size, else a new allocation.
+int32_t acquire_block(int dev, size_t want, void** ptr, size_t* got) {
+  BlockCache& c = block_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto& f = c.free[dev];
+    auto it = f.lower_bound(want);
+    if (it != f.end() && it->first <= 2 * want + ((size_t)1 << 20)) {
+      *ptr = it->second;
+      *got = it->first;
+      c.bytes[dev] -= it->first;
+      f.erase(it);
+      return GIS_OK;
+    }
+  }
+  const size_t size = (want + 65535) & ~(size_t)65535;
+  if (hipMalloc(ptr, size) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    set_error("device allocation of " + std::to_string(size) + " bytes failed");
+    return GIS_E_NOMEM;
+  }
+  *got = size;
+  return GIS_OK;
+}
+
+// Returns a block whose users have all finished (the caller synchronised).
+void release_block(int dev, void* ptr, size_t size) {
+  if (!ptr) return;
+  BlockCache& c = block_cache();
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto& f = c.free[dev];
+    if (f.size() < kCacheBlocks && c.bytes[dev] + size <= kCacheBytes) {
+      f.emplace(size, ptr);
+      c.bytes[dev] += size;
+      return;
+    }
+  }
+  (void)hipFree(ptr);
+}
+
+// Copies job j's covering, kept flags, masks and index into a new solution
+// (one block, one copy launch).
 int32_t make_solution(gis_ctx* ctx, const Batch& B, int j, const uint8_t* level,
                       const int32_t* idx, const uint8_t* kept, const uint64_t* mask,
                       const gis_solve_info& info, gis_solution** out, hipStream_t s) {
@@ -772,34 +851,40 @@ int32_t make_solution(gis_ctx* ctx, const Batch& B, int j, const uint8_t* level,
     gis_solution_free(sol);
     return code;
   };
-  if ((rc = ensure(sol->level, (size_t)nc + 16)) || (rc = ensure(sol->idx, (size_t)nc * n * 4 + 16)) ||
-      (rc = ensure(sol->kept, (size_t)nc + 16)) || (rc = ensure(sol->mask, (size_t)nc * W * 8 + 16)))
-    return fail(rc);
   sol->ci = J.ci;
   sol->ci.state = nullptr;
   sol->ci.pfx = nullptr;
   if (nc > 0) {
-    if (hipMemcpyAsync(sol->level.ptr, level + c0, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sol->idx.ptr, idx + c0 * n, nc * n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sol->kept.ptr, kept + c0, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sol->mask.ptr, mask + c0 * W, nc * W * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-      set_error("copy of the solution failed");
-      return fail(GIS_E_HIP);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t slots = J.ci.uniform ? 0 : J.ci.off[J.ci.lmax + 1];
+    const size_t o_idx = up((size_t)nc), o_kept = o_idx + up((size_t)nc * n * 4),
+                 o_mask = o_kept + up((size_t)nc), o_state = o_mask + up((size_t)nc * W * 8),
+                 o_pfx = o_state + up((size_t)slots),
+                 end = o_pfx + (slots > 0 ? up((size_t)(slots + 1) * 8) : 0);
+    if ((rc = acquire_block(ctx->device, end, &sol->block, &sol->block_bytes))) return fail(rc);
+    uint8_t* b = (uint8_t*)sol->block;
+    sol->level = b;
+    sol->idx = (int32_t*)(b + o_idx);
+    sol->kept = b + o_kept;
+    sol->mask = (uint64_t*)(b + o_mask);
+    Gather g{};
+    auto seg = [&](const void* src, void* dst, int64_t bytes) {
+      g.src[g.n] = (const uint8_t*)src;
+      g.dst[g.n] = (uint8_t*)dst;
+      g.bytes[g.n] = bytes;
+      ++g.n;
+    };
+    seg(level + c0, sol->level, nc);
+    seg(idx + c0 * n, sol->idx, nc * n * 4);
+    seg(kept + c0, sol->kept, nc);
+    seg(mask + c0 * W, sol->mask, nc * W * 8);
+    if (slots > 0) {
+      sol->ci.state = b + o_state;
+      sol->ci.pfx = (int64_t*)(b + o_pfx);
+      seg(J.ci.state, sol->ci.state, slots);
+      seg(J.ci.pfx, sol->ci.pfx, (slots + 1) * 8);
     }
-    if (!J.ci.uniform) {
-      const int64_t total = J.ci.off[J.ci.lmax + 1];
-      if ((rc = ensure(sol->state, (size_t)total + 16)) ||
-          (rc = ensure(sol->pfx, (size_t)(total + 1) * 8 + 16)))
-        return fail(rc);
-      if (hipMemcpyAsync(sol->state.ptr, J.ci.state, total, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(sol->pfx.ptr, J.ci.pfx, (total + 1) * 8, hipMemcpyDeviceToDevice, s) !=
-              hipSuccess) {
-        set_error("copy of the covering index failed");
-        return fail(GIS_E_HIP);
-      }
-      sol->ci.state = (uint8_t*)sol->state.ptr;
-      sol->ci.pfx = (int64_t*)sol->pfx.ptr;
-    }
+    if ((rc = gather_copy(g, s))) return fail(rc);
   }
   *out = sol;
   return GIS_OK;
@@ -849,6 +934,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     return rc;
 
   // FP32 recheck band: calibrate each job on its coarse covering unless given
+  bool band_pending = false;
+  const double band_floor_rel = 1e-5 * ldexp(1.0, -rounds);
   if (o.precision == GIS_PREC_FP32_RECHECK) {
     bool need = false;
     for (int d = 0; d < n; ++d) need |= !(o.band[d] > 0.0);
@@ -861,22 +948,29 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       // larger ones (about 2^20 rows)
       const int64_t stride = (B.total_cells * K) >> 20;
       if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, stride, s))) return rc;
+      // the device job table gets its bands on the stream; the host copy
+      // learns them at the end of round 0 (same formula, same bits)
+      if ((rc = launch_band(B.d_jobs, nj, n, (const unsigned long long*)ctx->maxerr.ptr,
+                            band_floor_rel, s)))
+        return rc;
       GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim * nj,
                              hipMemcpyDeviceToHost, s));
-      GIS_HIP(hipStreamSynchronize(s));
-      // calibrated bands: the stream is idle, so the staging buffer is free
-      const double floor_rel = 1e-5 * ldexp(1.0, -rounds);
-      for (int j = 0; j < nj; ++j)
-        for (int d = 0; d < n; ++d) {
-          if (o.band[d] > 0.0) continue;
-          double e;
-          memcpy(&e, &ctx->h_maxerr.h[j * kMaxDim + d], 8);
-          const double fl = floor_rel * B.jobs[j].grid.w0[d];
-          B.jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
-        }
-      if ((rc = upload_jobs(ctx, B, s))) return rc;
+      band_pending = true;
     }
   }
+  // After a synchronisation: the calibrated bands of the host job table.
+  auto take_bands = [&]() {
+    if (!band_pending) return;
+    band_pending = false;
+    for (int j = 0; j < nj; ++j)
+      for (int d = 0; d < n; ++d) {
+        if (o.band[d] > 0.0) continue;
+        double e;
+        memcpy(&e, &ctx->h_maxerr.h[j * kMaxDim + d], 8);
+        const double fl = band_floor_rel * B.jobs[j].grid.w0[d];
+        B.jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
+      }
+  };
 
   std::vector<gis_solve_info> info(nj);
   for (int j = 0; j < nj; ++j) {
@@ -884,8 +978,6 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     info[j].n = n;
     info[j].K = K;
     info[j].mask_words = W;
-    for (int d = 0; d < n; ++d)
-      info[j].band[d] = o.precision == GIS_PREC_FP32_RECHECK ? B.jobs[j].band[d] : 0.0;
   }
   // Each round enqueues build -> analysis -> subdivision with no host
   // round trip in between and synchronises once at its end.  The edge buffer
@@ -896,7 +988,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   bool cur_is_A = true;
   double edges_per_row = 8.0;
   // sweeps enqueued with a round: what the previous round needed, plus two
-  int32_t sweep_hint = kFirstSweeps;
+  const int32_t first_sweeps = ctx->tune.first_sweeps;
+  int32_t sweep_hint = first_sweeps;
   for (int r = 0; r <= rounds; ++r) {
     const uint8_t* lv = (const uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
     const int32_t* ix = (const int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
@@ -957,6 +1050,12 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
     GIS_HIP(hipEventRecord(ev[1], s));
     if ((rc = analyse_and_refine())) return fail_all(rc);
+    if (r == 0) {
+      take_bands();
+      for (int j = 0; j < nj; ++j)
+        for (int d = 0; d < n; ++d)
+          info[j].band[d] = o.precision == GIS_PREC_FP32_RECHECK ? B.jobs[j].band[d] : 0.0;
+    }
     if ((rc = finish_build(ctx, B, gr))) return fail_all(rc);
     if (gr.n_edges > gr.cap_edges) {
       // grow the edge buffer and redo the round
@@ -983,9 +1082,10 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       // trip and a second subdivision, so keep a margin
       const int32_t need = ctx->h_counters->sweep_last + 1;  // incl. the sweep that found no change
       const int32_t want = need + 4;
-      sweep_hint = want < 10 ? 10 : (want > kFirstSweeps ? kFirstSweeps : want);
+      const int32_t floor = first_sweeps < 10 ? first_sweeps : 10;
+      sweep_hint = want < floor ? floor : (want > first_sweeps ? first_sweeps : want);
     } else {
-      sweep_hint = kFirstSweeps;
+      sweep_hint = first_sweeps;
     }
     if (!conv) {
       // long removal chains: finish the analysis with the frontier phase and
@@ -1132,7 +1232,7 @@ void gis_ctx_destroy(gis_ctx* c) {
   DevBuf* bufs[] = {&c->counters, &c->jobs, &c->maxerr, &c->lookback, &c->scan_tmp,
                     &c->idx_state, &c->idx_pfx,
                     &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rcur,
-                    &c->rowbad, &c->cand, &c->front, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
+                    &c->rowstate, &c->good, &c->front, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
   for (DevBuf* b : bufs) release(*b);
   c->h_cs.free();
@@ -1143,6 +1243,23 @@ void gis_ctx_destroy(gis_ctx* c) {
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;
+}
+
+int32_t gis_get_tuning(const gis_ctx* ctx, gis_tuning* out) {
+  if (!ctx || !out) return inval("ctx and out are required");
+  *out = ctx->tune;
+  return GIS_OK;
+}
+
+int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* t) {
+  if (!ctx || !t) return inval("ctx and tuning are required");
+  auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
+  if (!in(t->first_sweeps, 1, 256) || !in(t->sweep_batch, 1, 256) || t->sweep_edges < 0 ||
+      !in(t->frontier_batch, 1, 256) || !in(t->sweep_blocks, 1, 65536) ||
+      !in(t->front_blocks, 1, 65536))
+    return inval("tuning field out of range");
+  ctx->tune = *t;
+  return GIS_OK;
 }
 
 int32_t gis_build_graph(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
@@ -1334,23 +1451,28 @@ int32_t gis_solution_export(const gis_solution* sol, gis_cells* cells, uint8_t* 
   if (!cells->level || !cells->idx || !d_kept || !d_mask) return inval("buffers missing");
   DeviceGuard g(sol->device);
   hipStream_t s = as_stream(stream);
-  GIS_HIP(hipMemcpyAsync(cells->level, sol->level.ptr, nc, hipMemcpyDeviceToDevice, s));
-  GIS_HIP(hipMemcpyAsync(cells->idx, sol->idx.ptr, nc * sol->grid.n * 4, hipMemcpyDeviceToDevice, s));
-  GIS_HIP(hipMemcpyAsync(d_kept, sol->kept.ptr, nc, hipMemcpyDeviceToDevice, s));
-  GIS_HIP(hipMemcpyAsync(d_mask, sol->mask.ptr, nc * sol->W * 8, hipMemcpyDeviceToDevice, s));
-  return GIS_OK;
+  Gather gt{};
+  gt.n = 4;
+  gt.src[0] = sol->level;
+  gt.dst[0] = cells->level;
+  gt.bytes[0] = nc;
+  gt.src[1] = (const uint8_t*)sol->idx;
+  gt.dst[1] = (uint8_t*)cells->idx;
+  gt.bytes[1] = nc * sol->grid.n * 4;
+  gt.src[2] = sol->kept;
+  gt.dst[2] = d_kept;
+  gt.bytes[2] = nc;
+  gt.src[3] = (const uint8_t*)sol->mask;
+  gt.dst[3] = (uint8_t*)d_mask;
+  gt.bytes[3] = nc * sol->W * 8;
+  return gather_copy(gt, s);
 }
 
 void gis_solution_free(gis_solution* sol) {
   if (!sol) return;
   DeviceGuard g(sol->device);
   (void)hipDeviceSynchronize();
-  release(sol->level);
-  release(sol->idx);
-  release(sol->kept);
-  release(sol->mask);
-  release(sol->state);
-  release(sol->pfx);
+  release_block(sol->device, sol->block, sol->block_bytes);
   delete sol;
 }
 
@@ -1365,8 +1487,7 @@ static int32_t query_common(const gis_solution* sol, const double* d_states, int
     if (member) return fill_u8(member, 0, n, s);
     return fill_i64((int64_t*)adm, 0, n * sol->W, s);
   }
-  return launch_query(sol->ci, sol->grid, (const uint8_t*)sol->kept.ptr,
-                      (const uint64_t*)sol->mask.ptr, sol->W, d_states, n, member, adm,
+  return launch_query(sol->ci, sol->grid, sol->kept, sol->mask, sol->W, d_states, n, member, adm,
                       as_stream(stream));
 }
 

@@ -121,6 +121,15 @@ struct ZeroRanges {
   int n;
 };
 int32_t zero_ranges(const ZeroRanges& z, hipStream_t s);
+// Up to six device-to-device copies in one launch (any alignment).
+constexpr int kGatherSegs = 6;
+struct Gather {
+  const uint8_t* src[kGatherSegs];
+  uint8_t* dst[kGatherSegs];
+  int64_t bytes[kGatherSegs];
+  int n;
+};
+int32_t gather_copy(const Gather& g, hipStream_t s);
 
 // ---------------------------------------------------------------- jobs
 // A batch runs several independent solves (jobs) through the same launches.
@@ -228,6 +237,10 @@ int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, h
 // launch block of each job (all rows when stride <= 1).
 int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64_t stride,
                          hipStream_t s);
+// Writes the calibrated band into the device job table for every (job,
+// dimension) whose band is not positive there: max(8 maxerr, floor_rel w0).
+int32_t launch_band(Job* d_jobs, int32_t n_jobs, int32_t n, const unsigned long long* d_maxerr,
+                    double floor_rel, hipStream_t s);
 
 // k_prune.hip
 struct PruneWork {
@@ -237,11 +250,15 @@ struct PruneWork {
   int64_t* rptr;     // [n_cells + 1] reverse-CSR offsets
   int32_t* rrow;     // [cap_edges] in-rows per target cell
   int32_t* rcur;     // [n_cells] in-degree cursors: zero on entry, left zero
-  uint8_t* rowbad;   // [n_rows]
-  uint8_t* cand;     // [n_cells] zero on entry, left zero
-  int32_t* front;    // [2 * n_cells] the two frontier lists
-  int32_t* fcount;   // [2] their lengths
+  uint32_t* rowstate;  // nonleaving: [n_rows] live targets per row
+  int32_t* good;       // nonleaving: [n_cells] live rows per cell
+  uint8_t* rowbad;     // controlled: [n_cells * Kp] bad-row flags (same memory as rowstate)
+  uint8_t* cand;       // controlled: [n_cells] candidate flags (same memory as good)
+  int32_t* front;      // [2 * n_cells] the two frontier lists
+  int32_t* fcount;     // [3] rotating list lengths
   void* scan_tmp;
+  int32_t sweep_blocks;    // grid cap of a sweep
+  int32_t front_blocks;    // grid of a frontier step
   const int64_t* d_total;  // device edge total, or null: reverse-CSR kernels do no work
   int64_t cap_edges;       // when *d_total > cap_edges (col was not written)
 };
@@ -252,13 +269,13 @@ int32_t launch_check_graph(const int64_t* row_ptr, const int32_t* col, int64_t n
 int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                      int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                      int32_t first, int32_t count, hipStream_t s);
-// Reverse CSR and the first frontier (every removed cell, and every cell
-// whose rows are all bad from the start); fcount[0] = its length.
+// Reverse CSR, the counters from the current removed flags, and the first
+// frontier (present cells without a good row); fcount[0] = its length.
 int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                              int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                              hipStream_t s);
-// Frontier steps first .. first+count-1; step t expands list t & 1.  Done
-// when fcount[(first+count) & 1] == 0.
+// Frontier steps first .. first+count-1; step t takes list t & 1 with length
+// fcount[t % 3].  Done when fcount[(first+count) % 3] == 0.
 int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
                              int32_t analysis, const PruneWork& w, int32_t first, int32_t count,
                              hipStream_t s);

@@ -650,4 +650,29 @@ int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64
   return dispatch_sys<Calibrate>(a.kind, a.n, a, d_maxerr, stride, s);
 }
 
+namespace {
+// Recheck band of each (job, dimension) not given by the caller: eight times
+// the calibrated FP32 error, at least floor_rel of the coarse cell width.
+__global__ void k_band(Job* jobs, int32_t n_jobs, int32_t n, const unsigned long long* maxerr,
+                       double floor_rel) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_jobs * n) return;
+  const int j = t / n, d = t - j * n;
+  if (jobs[j].band[d] > 0.0) return;
+  const double e = __longlong_as_double((long long)maxerr[j * kMaxDim + d]);
+  const double fl = floor_rel * jobs[j].grid.w0[d];
+  jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
+}
+}  // namespace
+
+int32_t launch_band(Job* d_jobs, int32_t n_jobs, int32_t n, const unsigned long long* d_maxerr,
+                    double floor_rel, hipStream_t s) {
+  const int t = n_jobs * n;
+  if (t <= 0) return GIS_OK;
+  hipLaunchKernelGGL(k_band, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, d_jobs, n_jobs, n,
+                     d_maxerr, floor_rel);
+  GIS_LAUNCH_CHECK("k_band");
+  return GIS_OK;
+}
+
 }  // namespace gis

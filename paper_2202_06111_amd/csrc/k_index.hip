@@ -39,6 +39,29 @@ __global__ void k_zero_ranges(ZeroRanges z) {
       z.p[r][i] = 0u;
 }
 
+// Segment blockIdx.y of a gather, copied in the widest unit that both of its
+// addresses allow.
+template <typename T>
+__device__ __forceinline__ void copy_units(const uint8_t* src, uint8_t* dst, int64_t bytes) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nu = bytes / (int64_t)sizeof(T);
+  for (int64_t i = t; i < nu; i += stride) ((T*)dst)[i] = ((const T*)src)[i];
+  for (int64_t i = nu * (int64_t)sizeof(T) + t; i < bytes; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_gather(Gather g) {
+  const int k = blockIdx.y;
+  if (k >= g.n) return;
+  const uint8_t* src = g.src[k];
+  uint8_t* dst = g.dst[k];
+  const uintptr_t al = (uintptr_t)src | (uintptr_t)dst;
+  if ((al & 15) == 0) copy_units<uint4>(src, dst, g.bytes[k]);
+  else if ((al & 7) == 0) copy_units<uint64_t>(src, dst, g.bytes[k]);
+  else if ((al & 3) == 0) copy_units<uint32_t>(src, dst, g.bytes[k]);
+  else copy_units<uint8_t>(src, dst, g.bytes[k]);
+}
+
 __global__ void k_max_level(const uint8_t* level, int64_t n, uint32_t* out) {
   uint32_t m = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -200,6 +223,18 @@ int32_t zero_ranges(const ZeroRanges& z, hipStream_t s) {
   if (nb > 8192) nb = 8192;
   hipLaunchKernelGGL(k_zero_ranges, dim3((unsigned)nb), dim3(256), 0, s, z);
   GIS_LAUNCH_CHECK("k_zero_ranges");
+  return GIS_OK;
+}
+
+int32_t gather_copy(const Gather& g, hipStream_t s) {
+  int64_t most = 0;
+  for (int k = 0; k < g.n; ++k) most = g.bytes[k] > most ? g.bytes[k] : most;
+  if (most == 0 || g.n <= 0) return GIS_OK;
+  int64_t nb = (most / 16 + 255) / 256;
+  if (nb < 1) nb = 1;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)nb, (unsigned)g.n), dim3(256), 0, s, g);
+  GIS_LAUNCH_CHECK("k_gather");
   return GIS_OK;
 }
 

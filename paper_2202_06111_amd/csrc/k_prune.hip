@@ -7,14 +7,14 @@
 //   nonleaving : row (c, u) is dead when all its targets are removed; a cell
 //                is removed when all its rows are dead (a cell with no path
 //                to a cycle of the input-union symbolic image, Definition 6).
-// Two phases, both pulling each row's state from the removed flags of its
-// targets (no per-edge atomics):
+// Two phases:
 //   sweeps   : whole-graph passes, in place, until one removes nothing -- few
 //              launches when the removal chains are short, and no reverse
 //              graph to build;
 //   frontier : for long chains, a breadth-first peel over the reverse CSR
 //              (in-degree histogram -> offsets -> scatter), each step
-//              expanding the cells removed in the step before.
+//              propagating the cells removed in the step before through
+//              per-row and per-cell counters (every removal once).
 // The host runs a batch of sweeps and switches to the frontier phase when
 // they have not converged.  The final pass writes kept flags and masks.
 #include "gis_internal.h"
@@ -139,19 +139,32 @@ __global__ void k_check_graph(const int64_t* row_ptr, const int32_t* col, int64_
 // Is row r good, given the removed flags of the cells?
 //   controlled : not OUT and no target removed;
 //   nonleaving : some target not removed.
+// The targets are taken kBatch at a time: their ids are loaded together, then
+// their flags together, so a row costs two memory latencies per batch rather
+// than two per target.
+constexpr int kBatch = 8;
+
 template <int MODE>
 __device__ __forceinline__ bool row_good(const int64_t* row_ptr, const int32_t* col,
                                          const uint8_t* out, const uint8_t* removed, int64_t r) {
   const int64_t a = row_ptr[r], b = row_ptr[r + 1];
-  if (MODE == GIS_ANALYSIS_CONTROLLED) {
-    if (out[r]) return false;
-    for (int64_t e = a; e < b; ++e)
-      if (removed[col[e]]) return false;
-    return true;
+  if (MODE == GIS_ANALYSIS_CONTROLLED && out[r]) return false;
+  for (int64_t e = a; e < b; e += kBatch) {
+    int32_t j[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) j[q] = e + q < b ? col[e + q] : -1;
+    bool any_removed = false, any_present = false;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q)
+      if (j[q] >= 0) {
+        const bool rm = removed[j[q]] != 0;
+        any_removed |= rm;
+        any_present |= !rm;
+      }
+    if (MODE == GIS_ANALYSIS_CONTROLLED && any_removed) return false;
+    if (MODE != GIS_ANALYSIS_CONTROLLED && any_present) return true;
   }
-  for (int64_t e = a; e < b; ++e)
-    if (!removed[col[e]]) return true;
-  return false;
+  return MODE == GIS_ANALYSIS_CONTROLLED;
 }
 
 // One sweep over every cell still present: a thread per row evaluates it,
@@ -198,15 +211,27 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
 }
 
 // ---- frontier phase (long removal chains): a breadth-first peel over the
-// reverse CSR, every step two launches, no per-edge atomics.  It runs only
-// after a synchronisation has shown the graph complete.
-// rowbad: controlled -> row is OUT or has a removed target; nonleaving -> all
-// targets removed.  Initial values, and the first frontier: every removed
-// cell plus every cell whose rows are all bad already.
-template <int MODE>
-__global__ void k_front_init(const int64_t* row_ptr, const uint8_t* out, int64_t n_cells,
-                             int32_t K, uint8_t* removed, uint8_t* rowbad, int32_t* front,
-                             int32_t* count) {
+// reverse CSR.  It runs only after a synchronisation has shown the graph
+// complete.  Step s takes the cells removed in step s-1 (list s & 1, length
+// counts[s % 3]) and appends the cells it removes to the other list (length
+// counts[(s+1) % 3]); the third count is cleared for the step after.
+//
+// controlled: a row turns bad when any target is removed, so a step marks
+//   every in-row of the frontier bad with plain byte stores (idempotent, no
+//   atomics) and flags its cell as a candidate; a second launch removes the
+//   candidates whose rows are now all bad.  Row flags live at c * Kp + u
+//   (Kp = K rounded up to 8) so that a cell's flags are whole 8-byte words.
+// nonleaving: a row dies when its last present target is removed, which
+//   needs a count per row; per-row and per-cell counters propagate each
+//   removal exactly once, in one launch per step:
+//   rowstate[r] = targets of r not yet removed, good[c] = rows of c alive.
+
+// controlled, initial state: a row is bad when OUT; a cell with every row
+// bad is removed; the first frontier is every removed cell (also those the
+// sweeps removed, whose in-rows have not been marked).
+__global__ void k_front_init_ctl(const uint8_t* out, int64_t n_cells, int32_t K, int32_t Kp,
+                                 uint8_t* removed, uint8_t* rowbad, int32_t* front,
+                                 int32_t* count) {
   for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
        c0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = c0 + threadIdx.x;
@@ -214,10 +239,8 @@ __global__ void k_front_init(const int64_t* row_ptr, const uint8_t* out, int64_t
     if (c < n_cells) {
       bool all = true;
       for (int32_t u = 0; u < K; ++u) {
-        const int64_t r = c * K + u;
-        const bool bad =
-            MODE == GIS_ANALYSIS_CONTROLLED ? out[r] != 0 : row_ptr[r + 1] == row_ptr[r];
-        rowbad[r] = bad ? 1 : 0;
+        const bool bad = out[c * K + u] != 0;
+        rowbad[c * Kp + u] = bad ? 1 : 0;
         all &= bad;
       }
       if (all) removed[c] = 1;
@@ -234,38 +257,38 @@ __global__ void k_front_init(const int64_t* row_ptr, const uint8_t* out, int64_t
   }
 }
 
-// Expand: a wave per frontier cell, its lanes over the cell's in-rows; a row
-// that turns bad marks its cell as a candidate.  Also clears the count of
-// the list the following evaluate launch appends to.
-template <int MODE>
-__global__ __launch_bounds__(64) void k_front_expand(const int64_t* rptr, const int32_t* rrow,
-                                                     const int64_t* row_ptr, const int32_t* col,
-                                                     int32_t K, const uint8_t* removed,
-                                                     uint8_t* rowbad, uint8_t* cand,
-                                                     const int32_t* front, const int32_t* count,
-                                                     int32_t* next_count) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
-  const int32_t n = *count;
-  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    const int32_t c = front[i];
+// controlled, step s, first launch: a wave per frontier cell marks its
+// in-rows bad and their cells as candidates.
+__global__ __launch_bounds__(256) void k_front_mark_ctl(const int64_t* rptr, const int32_t* rrow,
+                                                        int32_t K, int32_t Kp, uint8_t* rowbad,
+                                                        uint8_t* cand, const int32_t* front_in,
+                                                        int32_t* counts, int32_t s) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[(s + 1) % 3] = 0;
+  const int32_t n = counts[s % 3];
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n;
+       i += waves) {
+    const int32_t c = front_in[i];
     const int64_t b = rptr[c], e = rptr[c + 1];
-    for (int64_t p = b + threadIdx.x; p < e; p += 64) {
+    for (int64_t p = b + lane; p < e; p += 64) {
       const int32_t r = rrow[p];
-      if (rowbad[r]) continue;
-      if (MODE == GIS_ANALYSIS_CONTROLLED || !row_good<MODE>(row_ptr, col, nullptr, removed, r)) {
-        rowbad[r] = 1;
-        cand[r / K] = 1;
-      }
+      const int32_t cell = r / K;
+      uint8_t* f = rowbad + (int64_t)cell * Kp + (r - cell * K);
+      if (*f) continue;
+      *f = 1;
+      cand[cell] = 1;
     }
   }
 }
 
-// Evaluate the candidates: a cell all of whose rows are bad is removed and
-// joins the next frontier (one counter atomic per wave).
-__global__ void k_front_eval(int64_t n_cells, int32_t K, uint8_t* removed, const uint8_t* rowbad,
-                             uint8_t* cand, const int32_t* count, int32_t* next_front,
-                             int32_t* next_count) {
-  if (*count == 0) return;  // nothing was expanded, so no candidate was marked
+// controlled, step s, second launch: a candidate whose rows are all bad is
+// removed and joins the next frontier (one counter atomic per wave).
+__global__ void k_front_eval_ctl(int64_t n_cells, int32_t K, int32_t Kp, uint8_t* removed,
+                                 const uint8_t* rowbad, uint8_t* cand, int32_t* front_out,
+                                 int32_t* counts, int32_t s) {
+  if (counts[s % 3] == 0) return;  // nothing was marked
+  int32_t* cnt_out = counts + (s + 1) % 3;
   for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
        c0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = c0 + threadIdx.x;
@@ -273,12 +296,14 @@ __global__ void k_front_eval(int64_t n_cells, int32_t K, uint8_t* removed, const
     if (c < n_cells && cand[c]) {
       cand[c] = 0;
       if (!removed[c]) {
-        // no early exit: the loads of a batch are independent
-        int32_t nbad = 0;
-        const uint8_t* rb = rowbad + c * K;
-#pragma unroll 8
-        for (int32_t u = 0; u < K; ++u) nbad += rb[u];
-        if (nbad == K) {
+        const uint64_t* wv = (const uint64_t*)(rowbad + c * Kp);
+        bool all = true;
+        for (int32_t u0 = 0; u0 < K; u0 += 8) {
+          const int nb = K - u0 < 8 ? K - u0 : 8;
+          const uint64_t m = nb == 8 ? 0x0101010101010101ull : ((1ull << (8 * nb)) - 1) & 0x0101010101010101ull;
+          all &= (wv[u0 >> 3] & m) == m;
+        }
+        if (all) {
           removed[c] = 1;
           rem = true;
         }
@@ -288,9 +313,128 @@ __global__ void k_front_eval(int64_t n_cells, int32_t K, uint8_t* removed, const
     if (m) {
       const int lane = threadIdx.x & 63;
       int32_t base = 0;
-      if (lane == 0) base = atomicAdd(next_count, (int32_t)__popcll(m));
+      if (lane == 0) base = atomicAdd(cnt_out, (int32_t)__popcll(m));
       base = __shfl(base, 0, 64);
-      if (rem) next_front[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)c;
+      if (rem) front_out[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)c;
+    }
+  }
+}
+
+// nonleaving, initial state: counters from the current removed flags (read
+// only here), and the first frontier: the present cells without a live row.
+// A block takes cpb whole cells, a thread per row, as in a sweep.
+__device__ __forceinline__ int32_t live_targets(const int64_t* row_ptr, const int32_t* col,
+                                                const uint8_t* removed, int64_t r) {
+  const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+  int32_t alive = 0;
+  for (int64_t e = a; e < b; e += kBatch) {
+    int32_t j[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) j[q] = e + q < b ? col[e + q] : -1;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) alive += (j[q] >= 0 && !removed[j[q]]) ? 1 : 0;
+  }
+  return alive;
+}
+
+__device__ __forceinline__ void append_wave(bool add, int32_t v, int32_t* list, int32_t* count) {
+  const uint64_t m = __ballot(add);  // one counter atomic per wave
+  if (m) {
+    const int lane = threadIdx.x & 63;
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(count, (int32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (add) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_front_init_nl(const int64_t* row_ptr, const int32_t* col,
+                                                       int64_t n_cells, int32_t K, int32_t cpb,
+                                                       const uint8_t* removed, uint32_t* rowstate,
+                                                       int32_t* good, int32_t* front,
+                                                       int32_t* count) {
+  __shared__ uint8_t ok[256];
+  const int t = threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * cpb;
+  for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
+    const int64_t c = g0 + t / K;
+    bool g = false;
+    if (t < cpb * K && c < n_cells) {
+      const int64_t r = c * K + t % K;
+      const int32_t alive = removed[c] ? 0 : live_targets(row_ptr, col, removed, r);
+      rowstate[r] = (uint32_t)alive;
+      g = alive > 0;
+    }
+    ok[t] = g ? 1 : 0;
+    __syncthreads();
+    bool add = false;
+    const int64_t cc = g0 + t;
+    if (t < cpb && cc < n_cells) {
+      int32_t n = 0;
+      for (int u = 0; u < K; ++u) n += ok[t * K + u];
+      good[cc] = n;
+      add = n == 0 && !removed[cc];
+    }
+    append_wave(add, (int32_t)cc, front, count);
+    __syncthreads();
+  }
+}
+
+// The same for K > 256: a thread per cell.
+__global__ void k_front_init_nl_wide(const int64_t* row_ptr, const int32_t* col, int64_t n_cells,
+                                     int32_t K, const uint8_t* removed, uint32_t* rowstate,
+                                     int32_t* good, int32_t* front, int32_t* count) {
+  for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
+       c0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    bool add = false;
+    if (c < n_cells) {
+      const bool present = !removed[c];
+      int32_t n = 0;
+      for (int32_t u = 0; u < K; ++u) {
+        const int64_t r = c * K + u;
+        const int32_t alive = present ? live_targets(row_ptr, col, removed, r) : 0;
+        rowstate[r] = (uint32_t)alive;
+        n += alive > 0 ? 1 : 0;
+      }
+      good[c] = n;
+      add = n == 0 && present;
+    }
+    append_wave(add, (int32_t)c, front, count);
+  }
+}
+
+// nonleaving, step s: a wave per frontier cell removes it and walks its
+// in-rows; a row whose count reaches zero decrements its cell's count, and
+// the cell whose count reaches zero joins the next frontier.
+__global__ __launch_bounds__(256) void k_front_step_nl(const int64_t* rptr, const int32_t* rrow,
+                                                       int32_t K, uint8_t* removed,
+                                                       uint32_t* rowstate, int32_t* good,
+                                                       const int32_t* front_in,
+                                                       int32_t* front_out, int32_t* counts,
+                                                       int32_t s) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[(s + 2) % 3] = 0;
+  int32_t* cnt_out = counts + (s + 1) % 3;
+  const int32_t n = counts[s % 3];
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n;
+       i += waves) {
+    const int32_t c = front_in[i];
+    if (lane == 0) removed[c] = 1;
+    const int64_t b = rptr[c], e = rptr[c + 1];
+    for (int64_t p0 = b; p0 < e; p0 += 64) {
+      const int64_t p = p0 + lane;
+      bool add = false;
+      int32_t cell = 0;
+      if (p < e) {
+        const int32_t r = rrow[p];
+        if (atomicSub(&rowstate[r], 1u) == 1u) {
+          cell = r / K;
+          add = atomicSub(&good[cell], 1) == 1;
+        }
+      }
+      append_wave(add, cell, front_out, cnt_out);
     }
   }
 }
@@ -410,7 +554,8 @@ int32_t sweeps_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
                     hipStream_t s) {
   const int32_t cpb = 256 / K;
   const int64_t groups = (n_cells + cpb - 1) / cpb;
-  const unsigned nb = (unsigned)(groups < 4096 ? (groups > 0 ? groups : 1) : 4096);
+  const int64_t cap = w.sweep_blocks > 0 ? w.sweep_blocks : 4096;
+  const unsigned nb = (unsigned)(groups < cap ? (groups > 0 ? groups : 1) : cap);
   for (int32_t i = 0; i < count; ++i) {
     hipLaunchKernelGGL((k_sweep<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out, n_cells, K,
                        cpb, w.removed, w.last, s0 + i, w.d_total, w.cap_edges);
@@ -419,34 +564,57 @@ int32_t sweeps_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
   return GIS_OK;
 }
 
-template <int MODE>
-int32_t frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
-                       const PruneWork& w, int32_t t0, int32_t count, hipStream_t s) {
+int32_t frontier_steps(int32_t analysis, int64_t n_cells, int32_t K, const PruneWork& w,
+                       int32_t t0, int32_t count, hipStream_t s) {
+  const int32_t Kp = (K + 7) & ~7;
+  const unsigned nb = (unsigned)(w.front_blocks > 0 ? w.front_blocks : 2048);
   for (int32_t i = 0; i < count; ++i) {
-    const int t = (t0 + i) & 1;
-    int32_t* cur = w.front + (t ? n_cells : 0);
-    int32_t* nxt = w.front + (t ? 0 : n_cells);
-    hipLaunchKernelGGL((k_front_expand<MODE>), dim3(2048), dim3(64), 0, s, (const int64_t*)w.rptr,
-                       (const int32_t*)w.rrow, row_ptr, col, K, (const uint8_t*)w.removed,
-                       w.rowbad, w.cand, (const int32_t*)cur, (const int32_t*)(w.fcount + t),
-                       w.fcount + (1 - t));
-    GIS_LAUNCH_CHECK("k_front_expand");
-    hipLaunchKernelGGL(k_front_eval, dim3(grid_for(n_cells, 4096)), dim3(256), 0, s, n_cells, K,
-                       w.removed, (const uint8_t*)w.rowbad, w.cand, (const int32_t*)(w.fcount + t),
-                       nxt, w.fcount + (1 - t));
-    GIS_LAUNCH_CHECK("k_front_eval");
+    const int32_t t = t0 + i;
+    const int32_t* cur = w.front + ((t & 1) ? n_cells : 0);
+    int32_t* nxt = w.front + ((t & 1) ? 0 : n_cells);
+    if (analysis == GIS_ANALYSIS_NONLEAVING) {
+      hipLaunchKernelGGL(k_front_step_nl, dim3(nb), dim3(256), 0, s, (const int64_t*)w.rptr,
+                         (const int32_t*)w.rrow, K, w.removed, w.rowstate, w.good, cur, nxt,
+                         w.fcount, t);
+      GIS_LAUNCH_CHECK("k_front_step_nl");
+    } else {
+      hipLaunchKernelGGL(k_front_mark_ctl, dim3(nb), dim3(256), 0, s, (const int64_t*)w.rptr,
+                         (const int32_t*)w.rrow, K, Kp, w.rowbad, w.cand, cur, w.fcount, t);
+      GIS_LAUNCH_CHECK("k_front_mark_ctl");
+      hipLaunchKernelGGL(k_front_eval_ctl, dim3(grid_for(n_cells, 8192)), dim3(256), 0, s,
+                         n_cells, K, Kp, w.removed, (const uint8_t*)w.rowbad, w.cand, nxt,
+                         w.fcount, t);
+      GIS_LAUNCH_CHECK("k_front_eval_ctl");
+    }
   }
   return GIS_OK;
 }
 
-template <int MODE>
-int32_t frontier_init(const int64_t* row_ptr, const uint8_t* out, int64_t n_cells, int32_t K,
-                      const PruneWork& w, hipStream_t s) {
+int32_t frontier_init(int32_t analysis, const int64_t* row_ptr, const int32_t* col,
+                      const uint8_t* out, int64_t n_cells, int32_t K, const PruneWork& w,
+                      hipStream_t s) {
   int32_t rc;
-  if ((rc = fill_i32(w.fcount, 0, 2, s)) != GIS_OK) return rc;
-  hipLaunchKernelGGL((k_front_init<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr, out,
-                     n_cells, K, w.removed, w.rowbad, w.front, w.fcount);
-  GIS_LAUNCH_CHECK("k_front_init");
+  if ((rc = fill_i32(w.fcount, 0, 3, s))) return rc;
+  if (analysis != GIS_ANALYSIS_NONLEAVING) {
+    if ((rc = fill_u8(w.cand, 0, n_cells, s))) return rc;
+    hipLaunchKernelGGL(k_front_init_ctl, dim3(grid_for(n_cells)), dim3(256), 0, s, out, n_cells, K,
+                       (K + 7) & ~7, w.removed, w.rowbad, w.front, w.fcount);
+    GIS_LAUNCH_CHECK("k_front_init_ctl");
+    return GIS_OK;
+  }
+  if (K > 256) {
+    hipLaunchKernelGGL(k_front_init_nl_wide, dim3(grid_for(n_cells)), dim3(256), 0, s, row_ptr,
+                       col, n_cells, K, (const uint8_t*)w.removed, w.rowstate, w.good, w.front,
+                       w.fcount);
+    GIS_LAUNCH_CHECK("k_front_init_nl_wide");
+    return GIS_OK;
+  }
+  const int32_t cpb = 256 / K;
+  const int64_t groups = (n_cells + cpb - 1) / cpb;
+  const unsigned nb = (unsigned)(groups < 8192 ? (groups > 0 ? groups : 1) : 8192);
+  hipLaunchKernelGGL(k_front_init_nl, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells, K, cpb,
+                     (const uint8_t*)w.removed, w.rowstate, w.good, w.front, w.fcount);
+  GIS_LAUNCH_CHECK("k_front_init_nl");
   return GIS_OK;
 }
 
@@ -502,18 +670,16 @@ int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const u
   if (n_cells == 0) return GIS_OK;
   int32_t rc;
   if ((rc = reverse_csr(row_ptr, col, n_cells, K, w, s)) != GIS_OK) return rc;
-  if (analysis == GIS_ANALYSIS_NONLEAVING)
-    return frontier_init<GIS_ANALYSIS_NONLEAVING>(row_ptr, out, n_cells, K, w, s);
-  return frontier_init<GIS_ANALYSIS_CONTROLLED>(row_ptr, out, n_cells, K, w, s);
+  return frontier_init(analysis, row_ptr, col, out, n_cells, K, w, s);
 }
 
 int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
                              int32_t analysis, const PruneWork& w, int32_t first, int32_t count,
                              hipStream_t s) {
   if (n_cells == 0 || count <= 0) return GIS_OK;
-  if (analysis == GIS_ANALYSIS_NONLEAVING)
-    return frontier_steps<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, n_cells, K, w, first, count, s);
-  return frontier_steps<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, n_cells, K, w, first, count, s);
+  (void)row_ptr;
+  (void)col;
+  return frontier_steps(analysis, n_cells, K, w, first, count, s);
 }
 
 int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,

@@ -46,65 +46,134 @@ __device__ __forceinline__ bool covered(const CoverIndex& ci, const int64_t* k) 
   return false;
 }
 
+// Number of probes of a kept cell whose finest-level box has side w - 2:
+// CORNERS the 2^n diagonal neighbours, SHELL every cell of the surface of the
+// box enlarged by one (w per side), split into 2n faces: face (d, side) has
+// coordinate d on that side, the coordinates before d strictly inside and the
+// ones after d anywhere, so no surface cell is counted twice.
 template <int N>
-__global__ void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
-                           JobStats* stats) {
+__device__ __forceinline__ int64_t probe_count(int32_t rule, int64_t w) {
+  if (rule == GIS_BOUNDARY_CORNERS) return (int64_t)1 << N;
+  int64_t total = 0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    int64_t f = 2;
+#pragma unroll
+    for (int e = 0; e < N; ++e)
+      if (e != d) f *= e < d ? w - 2 : w;
+    total += f;
+  }
+  return total;
+}
+
+// Finest-level coordinates of probe p of the cell whose enlarged box is
+// [lo, lo + w - 1] per dimension.
+template <int N>
+__device__ __forceinline__ void probe_coords(int32_t rule, const int64_t* lo, int64_t w, int64_t p,
+                                             int64_t* k) {
+  if (rule == GIS_BOUNDARY_CORNERS) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) k[d] = lo[d] + (((p >> (N - 1 - d)) & 1) ? w - 1 : 0);
+    return;
+  }
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    int64_t f = 1;
+#pragma unroll
+    for (int e = 0; e < N; ++e)
+      if (e != d) f *= e < d ? w - 2 : w;
+    if (p < 2 * f) {
+      const bool hi = p >= f;
+      int64_t q = hi ? p - f : p;
+      k[d] = lo[d] + (hi ? w - 1 : 0);
+      const int first = d == 0 ? 1 : 0;  // the slowest remaining dimension takes the rest of q
+#pragma unroll
+      for (int e = N - 1; e >= 0; --e) {
+        if (e == d) continue;
+        const int64_t base = lo[e] + (e < d ? 1 : 0);
+        if (e == first) {
+          k[e] = base + q;
+        } else {
+          const int64_t r = e < d ? w - 2 : w;
+          k[e] = base + q % r;
+          q /= r;
+        }
+      }
+      return;
+    }
+    p -= 2 * f;
+  }
+}
+
+// A wave decides cpw = 64 / fan cells (lane i < cpw owns cell i of the
+// wave), and the probes of those cells are shared out over all 64 lanes: a
+// coarse cell next to finely refined ones has thousands of probes, a
+// finest-level cell 3^n - 1.  Lane i takes probes i, i + 64, ... of the
+// wave's concatenated probe list and skips the probes of cells already found
+// to be boundary cells.  Each 256-cell block of the cell layout is split
+// over fan launch blocks, so small coverings still fill the device.
+template <int N>
+__global__ __launch_bounds__(256) void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule,
+                                                  uint8_t* boundary, JobStats* stats, int32_t fan) {
   __shared__ CoverIndex ci;
-  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  __shared__ int64_t s_first[256];  // first probe of each thread's cell in its wave's list
+  __shared__ int64_t s_lo[N][256];
+  __shared__ int64_t s_w[256];
+  __shared__ uint8_t s_bnd[256];
+  const int64_t cb = blockIdx.x / fan;  // block of the cell layout
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, cb);
   const Job& J = b.jobs[jb];
   stage_index(&ci, &J.ci);
-  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
-  bool bnd = false;
-  if (c < J.n_cells) {
-    const int64_t gc = J.cell_off + c;
-    if (kept[gc]) {
-      const int s = ci.lmax - b.level[gc];
-      int64_t lo[N], hi[N], k[N], Nf[N];
+  const int tid = threadIdx.x, lane = tid & 63, w0 = tid & ~63;
+  const int cpw = 64 / fan;
+  const int64_t c = (cb - J.blk[LK_CELLS]) * 256 + (blockIdx.x % fan) * (4 * cpw) + (tid >> 6) * cpw +
+                    lane;
+  const bool live = lane < cpw && c < J.n_cells;
+  const int64_t gc = J.cell_off + c;
+  const bool kp = live && kept[gc] != 0;
+  int64_t np = 0;
+  if (kp) {
+    const int s = ci.lmax - b.level[gc];
+    const int64_t w = ((int64_t)1 << s) + 2;
 #pragma unroll
-      for (int d = 0; d < N; ++d) {
-        lo[d] = ((int64_t)b.idx[gc * N + d] << s) - 1;
-        hi[d] = ((int64_t)b.idx[gc * N + d] + 1) << s;
-        k[d] = lo[d];
-        Nf[d] = ci.dims[ci.lmax][d];
-      }
-      if (rule == GIS_BOUNDARY_CORNERS) {
-        for (int q = 0; q < (1 << N) && !bnd; ++q) {
-          bool outside = false;
+    for (int d = 0; d < N; ++d) s_lo[d][tid] = ((int64_t)b.idx[gc * N + d] << s) - 1;
+    s_w[tid] = w;
+    np = probe_count<N>(rule, w);
+  }
+  // exclusive scan of the probe counts over the wave
+  int64_t incl = np;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int64_t total = __shfl(incl, 63, 64);
+  s_first[tid] = incl - np;
+  s_bnd[tid] = 0;
+  __syncthreads();
+  int64_t Nf[N];
 #pragma unroll
-          for (int d = 0; d < N; ++d) {
-            k[d] = ((q >> (N - 1 - d)) & 1) ? hi[d] : lo[d];
-            outside |= k[d] < 0 || k[d] >= Nf[d];
-          }
-          bnd = outside || !covered<N>(ci, k);
-        }
-      } else {
-        // every cell of the box [lo, hi] that is on its surface; the interior
-        // of the last dimension is skipped when all other coordinates are inside
-        for (;;) {
-          bool outside = false, inner = true;
-#pragma unroll
-          for (int d = 0; d < N; ++d) {
-            outside |= k[d] < 0 || k[d] >= Nf[d];
-            if (d < N - 1) inner &= k[d] != lo[d] && k[d] != hi[d];
-          }
-          if (outside || !covered<N>(ci, k)) {
-            bnd = true;
-            break;
-          }
-          if (inner && k[N - 1] == lo[N - 1]) {
-            k[N - 1] = hi[N - 1];
-            continue;
-          }
-          int d = N - 1;
-          while (d >= 0 && k[d] == hi[d]) {
-            k[d] = lo[d];
-            --d;
-          }
-          if (d < 0) break;
-          ++k[d];
-        }
-      }
+  for (int d = 0; d < N; ++d) Nf[d] = ci.dims[ci.lmax][d];
+  for (int64_t i = lane; i < total; i += 64) {
+    // owner: the last lane of the wave whose first probe is <= i
+    int lo_l = 0, hi_l = 63;
+    while (lo_l < hi_l) {
+      const int mid = (lo_l + hi_l + 1) >> 1;
+      if (s_first[w0 + mid] <= i) lo_l = mid; else hi_l = mid - 1;
     }
+    const int o = w0 + lo_l;
+    if (s_bnd[o]) continue;
+    int64_t lo[N], k[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) lo[d] = s_lo[d][o];
+    probe_coords<N>(rule, lo, s_w[o], i - s_first[o], k);
+    bool outside = false;
+#pragma unroll
+    for (int d = 0; d < N; ++d) outside |= k[d] < 0 || k[d] >= Nf[d];
+    if (outside || !covered<N>(ci, k)) s_bnd[o] = 1;
+  }
+  __syncthreads();
+  const bool bnd = kp && s_bnd[tid] != 0;
+  if (live) {
     boundary[gc] = bnd ? 1 : 0;
     // the next covering: the cell itself, or its 2^n children if it is a
     // boundary cell (jobs that stopped have no flag array)
@@ -216,7 +285,10 @@ int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
 int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
                        JobStats* stats, hipStream_t s) {
   if (b.blocks[LK_CELLS] == 0) return GIS_OK;
-#define GIS_CALL(N) hipLaunchKernelGGL(k_boundary<N>, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, rule, boundary, stats)
+  // lanes per cell: enough waves for about four per SIMD (1024 SIMDs)
+  int32_t fan = 1;
+  while (fan < 16 && b.blocks[LK_CELLS] * 4 * fan < 4096) fan *= 2;
+#define GIS_CALL(N) hipLaunchKernelGGL(k_boundary<N>, dim3((unsigned)(b.blocks[LK_CELLS] * fan)), dim3(256), 0, s, b, kept, rule, boundary, stats, fan)
   GIS_DIM_SWITCH(b.n, GIS_CALL)
 #undef GIS_CALL
   GIS_LAUNCH_CHECK("k_boundary");

@@ -55,6 +55,16 @@ class GraphT(ctypes.Structure):
                 ("cap_edges", I64), ("row_ptr", P), ("col", P), ("out", P)]
 
 
+class TuningT(ctypes.Structure):
+    _fields_ = [("first_sweeps", I32), ("sweep_batch", I32), ("sweep_edges", I64),
+                ("frontier_batch", I32), ("sweep_blocks", I32), ("front_blocks", I32),
+                ("use_graphs", I32), ("reserved", I32 * 2)]
+
+
+TUNING_FIELDS = ("first_sweeps", "sweep_batch", "sweep_edges", "frontier_batch", "sweep_blocks",
+                 "front_blocks", "use_graphs")
+
+
 class JobT(ctypes.Structure):
     _fields_ = [("sys", SystemT), ("grid", GridT), ("d_u", P)]
 
@@ -91,6 +101,8 @@ def lib():
         sig = {
             "gis_ctx_create": ([I32, ctypes.POINTER(P)], I32),
             "gis_ctx_destroy": ([P], None),
+            "gis_get_tuning": ([P, P], I32),
+            "gis_set_tuning": ([P, P], I32),
             "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
             "gis_subdivide": ([P, P, P, P, I32, P, P, P], I32),
@@ -114,7 +126,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_build_graph", "gis_prune", "gis_subdivide",
+EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_build_graph", "gis_prune", "gis_subdivide",
             "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
             "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
             "gis_last_error", "gis_version")
@@ -210,6 +222,22 @@ class Context:
     @property
     def dev(self) -> torch.device:
         return torch.device("cuda", self.device)
+
+    def get_tuning(self) -> dict:
+        t = TuningT()
+        _check(lib().gis_get_tuning(self.handle, ctypes.byref(t)))
+        return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+    def set_tuning(self, **fields) -> dict:
+        """Replaces the named schedule parameters; returns the previous set."""
+        prev = self.get_tuning()
+        t = TuningT()
+        for f in TUNING_FIELDS:
+            setattr(t, f, int(fields.pop(f, prev[f])))
+        if fields:
+            raise TypeError(f"unknown tuning fields {sorted(fields)}")
+        _check(lib().gis_set_tuning(self.handle, ctypes.byref(t)))
+        return prev
 
 
 def to_device_u(ctx: Context, u) -> torch.Tensor:

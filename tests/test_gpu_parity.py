@@ -161,6 +161,77 @@ def test_prune_deep_peel(G, ctx):
     assert nk == 0 and _np(kept).sum() == 0
 
 
+# Schedule parameters never change results: the frontier phase from the
+# start (sweep_edges = 0), one sweep or step per convergence check, and
+# one-block grids all give the oracle's fixed point.
+TUNINGS = {
+    "frontier_only": dict(sweep_edges=0),
+    "one_sweep_per_check": dict(first_sweeps=1, sweep_batch=1),
+    "tiny_grids": dict(sweep_edges=0, front_blocks=1, frontier_batch=1),
+    "tiny_sweep_grid": dict(sweep_blocks=1, first_sweeps=3, sweep_batch=2),
+}
+
+
+@pytest.mark.parametrize("tuning", sorted(TUNINGS))
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2"])
+def test_prune_tunings_match_oracle(G, ctx, name, analysis, tuning):
+    system, grid, u, samples = SMALL[name]
+    rng = np.random.Generator(np.random.PCG64(4))
+    level, idx = _adaptive_cells(rng, grid.n0, splits=6, drop_frac=0.05)
+    g, want = _check_graph(G, ctx, system, grid, u, samples, level, idx)
+    kept_w, mask_w, _ = oracle.prune(want["row_ptr"], want["col"], want["out"], level.shape[0],
+                                     u.shape[0], analysis)
+    prev = ctx.set_tuning(**TUNINGS[tuning])
+    try:
+        kept, mask, nk = G.prune(ctx, g, level.shape[0], u.shape[0], analysis)
+    finally:
+        ctx.set_tuning(**prev)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+    assert nk == int(kept_w.sum())
+
+
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+def test_prune_wide_inputs_random_graph(G, ctx, analysis):
+    """K = 300 inputs (beyond a sweep block): the frontier phase with a thread
+    per cell, on a seeded random graph (0-3 targets per row, 3% OUT rows)."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    n_cells, K = 60, 300
+    n_rows = n_cells * K
+    cnt = rng.integers(0, 4, size=n_rows)
+    row_ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    col = np.concatenate([np.sort(rng.choice(n_cells, size=c, replace=False)) for c in cnt]
+                         ).astype(np.int32)
+    out = (rng.random(n_rows) < 0.03).astype(np.uint8)
+    kept_w, mask_w, _ = oracle.prune(row_ptr, col, out, n_cells, K, analysis)
+    dev = ctx.dev
+    g = G.Graph(torch.as_tensor(row_ptr, device=dev), torch.as_tensor(col, device=dev),
+                torch.as_tensor(out, device=dev), n_rows, int(col.shape[0]), int(out.sum()), 0)
+    kept, mask, nk = G.prune(ctx, g, n_cells, K, analysis)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+    assert nk == int(kept_w.sum())
+
+
+@pytest.mark.parametrize("tuning", ["frontier_only", "one_sweep_per_check", "tiny_grids"])
+def test_solve_adaptive_tunings(G, ctx, tuning):
+    prev = ctx.set_tuning(**TUNINGS[tuning])
+    try:
+        _check_solve(G, ctx, W.vdp_adaptive_32("fp64"), "fp64")
+    finally:
+        ctx.set_tuning(**prev)
+
+
+def test_tuning_rejects_out_of_range(G, ctx):
+    before = ctx.get_tuning()
+    for bad in (dict(first_sweeps=0), dict(sweep_batch=300), dict(sweep_edges=-1),
+                dict(front_blocks=0), dict(sweep_blocks=70000), dict(frontier_batch=0)):
+        with pytest.raises(G.GisError):
+            ctx.set_tuning(**bad)
+        assert ctx.get_tuning() == before
+
+
 # ------------------------------------------------------------------ subdivide
 @pytest.mark.parametrize("rule", ["shell", "corners"])
 @pytest.mark.parametrize("name", ["vdp", "lorenz", "linear3"])
