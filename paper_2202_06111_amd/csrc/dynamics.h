@@ -124,7 +124,8 @@ __device__ __forceinline__ void sample_point(const GridArgs& g, int level, const
 #pragma unroll
   for (int d = 0; d < N; ++d) {
     const double half = 0.5 * ldexp(g.w0[d], -level);
-    x[d] = __builtin_fma((double)(2 * (int64_t)i[d] + k[d]), half, g.lo[d]);
+    // 2 i + k < 2^32 for every index below 2^31 - 1: one exact u32 -> f64 conversion
+    x[d] = __builtin_fma((double)(2u * (uint32_t)i[d] + (uint32_t)k[d]), half, g.lo[d]);
   }
 }
 

@@ -200,9 +200,12 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
     rk4<KIND, N, R>(kc, m, J.sys.nsub, x, u);
 #pragma unroll
     for (int d = 0; d < N; ++d) {
+      // min/max instructions: they differ from compare-and-select only for
+      // NaN (the row is then decided by `finite`) and in the sign of a zero
+      // (which changes no cover decision: (-0) - lo == (+0) - lo)
       finite &= isfinite(x[d]);
-      bl[d] = x[d] < bl[d] ? x[d] : bl[d];
-      bh[d] = x[d] > bh[d] ? x[d] : bh[d];
+      bl[d] = fmin(x[d], bl[d]);
+      bh[d] = fmax(x[d], bh[d]);
     }
   }
   return finite;
@@ -280,7 +283,9 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
                                              const int32_t* cache, int32_t id0, int32_t p0,
                                              int32_t p1, int32_t* dst) {
   if (UNI || ci.uniform) {
-    // position -> multi-index in the box, last dimension fastest
+    // position -> multi-index in the box, last dimension fastest; ids along
+    // the last dimension are consecutive, so the id is recomputed only when
+    // a slower coordinate moves
     int32_t k[N];
     int32_t rem = p0;
 #pragma unroll
@@ -289,17 +294,31 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
       k[d] = lo[d] + rem % w;
       rem /= w;
     }
-    for (int32_t p = p0; p < p1; ++p) {
+    auto lin_of = [&]() {
       int32_t lin = 0;
 #pragma unroll
       for (int d = 0; d < N; ++d) lin = lin * ci.dims[0][d] + k[d];
-      dst[p - p0] = id0 + lin;
-      int d = N - 1;
-      while (d > 0 && k[d] == hi[d]) {
-        k[d] = lo[d];
-        --d;
+      return id0 + lin;
+    };
+    int32_t id = lin_of();
+    for (int32_t p = p0; p < p1;) {
+      // the rest of the current run along the last dimension
+      const int32_t run = hi[N - 1] - k[N - 1] + 1;
+      const int32_t q1 = p1 - p < run ? p1 : p + run;
+      for (; p < q1; ++p) dst[p - p0] = id++;
+      if (p >= p1) break;
+      if constexpr (N > 1) {  // (with one dimension the run always reaches p1)
+        k[N - 1] = lo[N - 1];
+        int d = N - 2;
+        while (d > 0 && k[d] == hi[d]) {
+          k[d] = lo[d];
+          --d;
+        }
+        ++k[d];
+        id = lin_of();
+      } else {
+        break;
       }
-      ++k[d];
     }
     return;
   }

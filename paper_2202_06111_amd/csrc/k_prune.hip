@@ -226,10 +226,29 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
 //   removal exactly once, in one launch per step:
 //   rowstate[r] = targets of r not yet removed, good[c] = rows of c alive.
 
+// Appends v to list for every thread with add set, with one global atomic
+// per block (a frontier list's counter is shared by the whole device, and
+// per-wave atomics on it serialise).  Every thread of the block must call it
+// the same number of times.
+__device__ __forceinline__ void append_block(bool add, int32_t v, int32_t* list, int32_t* count) {
+  __shared__ int32_t s_cnt, s_base;
+  const uint64_t m = __ballot(add);
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int32_t woff = 0;
+  if (lane == 0 && m) woff = atomicAdd(&s_cnt, (int32_t)__popcll(m));
+  woff = __shfl(woff, 0, 64);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(count, s_cnt);
+  __syncthreads();
+  if (add) list[s_base + woff + __popcll(m & ((1ull << lane) - 1))] = v;
+}
+
 // controlled, initial state: a row is bad when OUT; a cell with every row
 // bad is removed; the first frontier is every removed cell (also those the
 // sweeps removed, whose in-rows have not been marked).
-__global__ void k_front_init_ctl(const uint8_t* out, int64_t n_cells, int32_t K, int32_t Kp,
+__global__ __launch_bounds__(1024) void k_front_init_ctl(const uint8_t* out, int64_t n_cells, int32_t K, int32_t Kp,
                                  uint8_t* removed, uint8_t* rowbad, int32_t* front,
                                  int32_t* count) {
   for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
@@ -246,14 +265,7 @@ __global__ void k_front_init_ctl(const uint8_t* out, int64_t n_cells, int32_t K,
       if (all) removed[c] = 1;
       rem = removed[c] != 0;
     }
-    const uint64_t m = __ballot(rem);  // one counter atomic per wave
-    if (m) {
-      const int lane = threadIdx.x & 63;
-      int32_t base = 0;
-      if (lane == 0) base = atomicAdd(count, (int32_t)__popcll(m));
-      base = __shfl(base, 0, 64);
-      if (rem) front[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)c;
-    }
+    append_block(rem, (int32_t)c, front, count);
   }
 }
 
@@ -284,7 +296,7 @@ __global__ __launch_bounds__(256) void k_front_mark_ctl(const int64_t* rptr, con
 
 // controlled, step s, second launch: a candidate whose rows are all bad is
 // removed and joins the next frontier (one counter atomic per wave).
-__global__ void k_front_eval_ctl(int64_t n_cells, int32_t K, int32_t Kp, uint8_t* removed,
+__global__ __launch_bounds__(1024) void k_front_eval_ctl(int64_t n_cells, int32_t K, int32_t Kp, uint8_t* removed,
                                  const uint8_t* rowbad, uint8_t* cand, int32_t* front_out,
                                  int32_t* counts, int32_t s) {
   if (counts[s % 3] == 0) return;  // nothing was marked
@@ -309,14 +321,7 @@ __global__ void k_front_eval_ctl(int64_t n_cells, int32_t K, int32_t Kp, uint8_t
         }
       }
     }
-    const uint64_t m = __ballot(rem);
-    if (m) {
-      const int lane = threadIdx.x & 63;
-      int32_t base = 0;
-      if (lane == 0) base = atomicAdd(cnt_out, (int32_t)__popcll(m));
-      base = __shfl(base, 0, 64);
-      if (rem) front_out[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)c;
-    }
+    append_block(rem, (int32_t)c, front_out, cnt_out);
   }
 }
 
@@ -335,17 +340,6 @@ __device__ __forceinline__ int32_t live_targets(const int64_t* row_ptr, const in
     for (int q = 0; q < kBatch; ++q) alive += (j[q] >= 0 && !removed[j[q]]) ? 1 : 0;
   }
   return alive;
-}
-
-__device__ __forceinline__ void append_wave(bool add, int32_t v, int32_t* list, int32_t* count) {
-  const uint64_t m = __ballot(add);  // one counter atomic per wave
-  if (m) {
-    const int lane = threadIdx.x & 63;
-    int32_t base = 0;
-    if (lane == 0) base = atomicAdd(count, (int32_t)__popcll(m));
-    base = __shfl(base, 0, 64);
-    if (add) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
-  }
 }
 
 __global__ __launch_bounds__(256) void k_front_init_nl(const int64_t* row_ptr, const int32_t* col,
@@ -375,13 +369,13 @@ __global__ __launch_bounds__(256) void k_front_init_nl(const int64_t* row_ptr, c
       good[cc] = n;
       add = n == 0 && !removed[cc];
     }
-    append_wave(add, (int32_t)cc, front, count);
+    append_block(add, (int32_t)cc, front, count);
     __syncthreads();
   }
 }
 
 // The same for K > 256: a thread per cell.
-__global__ void k_front_init_nl_wide(const int64_t* row_ptr, const int32_t* col, int64_t n_cells,
+__global__ __launch_bounds__(256) void k_front_init_nl_wide(const int64_t* row_ptr, const int32_t* col, int64_t n_cells,
                                      int32_t K, const uint8_t* removed, uint32_t* rowstate,
                                      int32_t* good, int32_t* front, int32_t* count) {
   for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
@@ -400,11 +394,11 @@ __global__ void k_front_init_nl_wide(const int64_t* row_ptr, const int32_t* col,
       good[c] = n;
       add = n == 0 && present;
     }
-    append_wave(add, (int32_t)c, front, count);
+    append_block(add, (int32_t)c, front, count);
   }
 }
 
-// nonleaving, step s: a wave per frontier cell removes it and walks its
+// nonleaving, step s: a block per frontier cell removes it and walks its
 // in-rows; a row whose count reaches zero decrements its cell's count, and
 // the cell whose count reaches zero joins the next frontier.
 __global__ __launch_bounds__(256) void k_front_step_nl(const int64_t* rptr, const int32_t* rrow,
@@ -416,15 +410,12 @@ __global__ __launch_bounds__(256) void k_front_step_nl(const int64_t* rptr, cons
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[(s + 2) % 3] = 0;
   int32_t* cnt_out = counts + (s + 1) % 3;
   const int32_t n = counts[s % 3];
-  const int lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n;
-       i += waves) {
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
     const int32_t c = front_in[i];
-    if (lane == 0) removed[c] = 1;
+    if (threadIdx.x == 0) removed[c] = 1;
     const int64_t b = rptr[c], e = rptr[c + 1];
-    for (int64_t p0 = b; p0 < e; p0 += 64) {
-      const int64_t p = p0 + lane;
+    for (int64_t p0 = b; p0 < e; p0 += blockDim.x) {
+      const int64_t p = p0 + threadIdx.x;
       bool add = false;
       int32_t cell = 0;
       if (p < e) {
@@ -434,7 +425,7 @@ __global__ __launch_bounds__(256) void k_front_step_nl(const int64_t* rptr, cons
           add = atomicSub(&good[cell], 1) == 1;
         }
       }
-      append_wave(add, cell, front_out, cnt_out);
+      append_block(add, cell, front_out, cnt_out);
     }
   }
 }
@@ -581,7 +572,7 @@ int32_t frontier_steps(int32_t analysis, int64_t n_cells, int32_t K, const Prune
       hipLaunchKernelGGL(k_front_mark_ctl, dim3(nb), dim3(256), 0, s, (const int64_t*)w.rptr,
                          (const int32_t*)w.rrow, K, Kp, w.rowbad, w.cand, cur, w.fcount, t);
       GIS_LAUNCH_CHECK("k_front_mark_ctl");
-      hipLaunchKernelGGL(k_front_eval_ctl, dim3(grid_for(n_cells, 8192)), dim3(256), 0, s,
+      hipLaunchKernelGGL(k_front_eval_ctl, dim3((unsigned)((n_cells + 1023) / 1024 < 2048 ? (n_cells + 1023) / 1024 : 2048)), dim3(1024), 0, s,
                          n_cells, K, Kp, w.removed, (const uint8_t*)w.rowbad, w.cand, nxt,
                          w.fcount, t);
       GIS_LAUNCH_CHECK("k_front_eval_ctl");
@@ -597,7 +588,7 @@ int32_t frontier_init(int32_t analysis, const int64_t* row_ptr, const int32_t* c
   if ((rc = fill_i32(w.fcount, 0, 3, s))) return rc;
   if (analysis != GIS_ANALYSIS_NONLEAVING) {
     if ((rc = fill_u8(w.cand, 0, n_cells, s))) return rc;
-    hipLaunchKernelGGL(k_front_init_ctl, dim3(grid_for(n_cells)), dim3(256), 0, s, out, n_cells, K,
+    hipLaunchKernelGGL(k_front_init_ctl, dim3((unsigned)((n_cells + 1023) / 1024 < 2048 ? (n_cells + 1023) / 1024 : 2048)), dim3(1024), 0, s, out, n_cells, K,
                        (K + 7) & ~7, w.removed, w.rowbad, w.front, w.fcount);
     GIS_LAUNCH_CHECK("k_front_init_ctl");
     return GIS_OK;
