@@ -13,7 +13,11 @@ continuous-batching server and reports solves/s and p50/p99 latency.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--precision fp64|fp32_recheck] [--no-cpu-baseline]
-                       [--serve-requests N]
+                       [--no-autotune] [--serve-requests N]
+
+Before the warm-up, the library's autotuner picks the schedule parameters
+(sweep and frontier batching, grid shapes) for the workload by timing whole
+solves; the chosen parameters are reported under "schedule".
 Prints one JSON line on stdout.
 """
 import argparse
@@ -42,6 +46,9 @@ def parse():
     p.add_argument("--workload", default="vdp_adaptive_32x32_r5")
     p.add_argument("--precision", default=None, help="fp64 or fp32_recheck (default: workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the default schedule parameters instead of running the autotuner "
+                        "(gis_autotune, untimed, before the warm-up)")
     p.add_argument("--cpu-budget-s", type=float, default=12.0)
     p.add_argument("--serve-requests", type=int, default=64,
                    help="requests per pass of the serving measurement (0: skip it)")
@@ -116,6 +123,10 @@ def main():
     du = gis.to_device_u(ctx, wl.u)
     opts = gis.workload_opts(wl, precision=precision, timing=True)
     stream = torch.cuda.current_stream()
+    schedule = {"autotuned": False, **ctx.get_tuning()}
+    if not a.no_autotune:
+        best, tuned_ms = gis.autotune(ctx, wl, repeats=3, precision=precision)
+        schedule = {"autotuned": True, "tuned_ms_per_solve": tuned_ms, **best}
 
     def step():
         sol = gis.solve(ctx, wl.system, wl.grid, du, wl.rounds, opts, stream)
@@ -165,9 +176,13 @@ def main():
                                ("fp64" if precision == "fp64" else "fp32+fp64 recheck"),
                      "avg_launch_ms": img_ms / max(launches, 1),
                      "flops_per_row": flops_row},
+        "schedule": schedule,
         "phases_ms_per_solve": {
             k: sum(r[k] for inf in infos for r in inf["rounds"]) / a.steps
             for k in ("ms_build", "ms_image", "ms_prune", "ms_subdivide")},
+        "host_ms_per_solve": {
+            "busy": sum(r["ms_host"] for inf in infos for r in inf["rounds"]) / a.steps,
+            "blocked_in_sync": sum(r["ms_host_wait"] for inf in infos for r in inf["rounds"]) / a.steps},
         "recheck_rows_per_solve": sum(r["n_recheck"] for inf in infos for r in inf["rounds"]) / a.steps,
         "solves_per_s": a.steps / el,
         "latency_ms": {"p50": 1e3 * statistics.median(lat),

@@ -140,6 +140,8 @@ typedef struct gis_round_stats {
   double ms_image;    /* the one-pass build kernel: images, boxes, cover, FP64 recheck of the
                          rows that need it, CSR emit (opts.timing) */
   double ms_recheck;  /* 0: the recheck runs inside the build kernel */
+  double ms_host;       /* host time of the round outside synchronisations (launches, bookkeeping) */
+  double ms_host_wait;  /* host time blocked in the round's synchronisations */
 } gis_round_stats;
 
 #define GIS_MAX_ROUNDS 32
@@ -179,6 +181,18 @@ typedef struct gis_tuning {
  * field is out of range (nothing is changed then). */
 int32_t gis_get_tuning(const gis_ctx* ctx, gis_tuning* out);
 int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* tuning);
+
+/* Autotuner: chooses the context's schedule parameters for one problem by
+ * timing whole gis_solve calls of it (arguments as for gis_solve).  Starting
+ * from the current parameters it tries, one field at a time, a few values
+ * per field and keeps a value when the median wall time of `repeats` solves
+ * (1..16) drops by more than 2%.  Every trial must reproduce the first trial's
+ * kept-cell count (GIS_E_INTERNAL otherwise).  The chosen parameters are set
+ * on ctx and returned in *best (may be NULL), their median time in *best_ms
+ * (may be NULL).  Synchronises; allocates like gis_solve. */
+int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
+                     const double* d_u, int32_t K, int32_t rounds, const gis_opts* opts,
+                     int32_t repeats, gis_tuning* best, double* best_ms, void* stream);
 
 /* Symbolic image of a covering (Sec. 2.2, Definition 1).  d_u: K x m inputs
  * (FP64).  Fills row_ptr, out and, when cap_edges suffices, col; synchronises

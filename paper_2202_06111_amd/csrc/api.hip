@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <string>
@@ -109,6 +110,7 @@ struct gis_ctx {
   bool lb_clean = false, prune_clean = false, next_clean = false;
   int32_t first_sweeps = 0;  // sweeps of the last enqueue_prune
   gis_tuning tune{16, 8, (int64_t)8 << 20, 16, 4096, 2048, 0, {0, 0}};
+  double wait_ms = 0.0;  // host time spent blocked in stream synchronisations
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
   DevBuf removed, rptr, rrow, rcur, rowstate, good, front;
@@ -276,11 +278,18 @@ int32_t zero_counters(gis_ctx* ctx, hipStream_t s) {
   return fill_u32((uint32_t*)ctx->counters.ptr, 0u, (int64_t)(sizeof(Counters) / 4), s);
 }
 
+int32_t wait_stream(gis_ctx* ctx, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const hipError_t e = hipStreamSynchronize(s);
+  ctx->wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return GIS_OK;
+}
+
 int32_t sync_counters(gis_ctx* ctx, hipStream_t s) {
   GIS_HIP(hipMemcpyAsync(ctx->h_counters, ctx->counters.ptr, sizeof(Counters),
                          hipMemcpyDeviceToHost, s));
-  GIS_HIP(hipStreamSynchronize(s));
-  return GIS_OK;
+  return wait_stream(ctx, s);
 }
 
 // ---------------------------------------------------------------- batches
@@ -434,8 +443,7 @@ int32_t zero_all(gis_ctx* ctx, const Batch& B, hipStream_t s) {
 int32_t sync_stats(gis_ctx* ctx, const Batch& B, hipStream_t s) {
   GIS_HIP(hipMemcpyAsync(ctx->h_cs.h, ctx->counters.ptr, kStatsOff + sizeof(JobStats) * B.n_jobs,
                          hipMemcpyDeviceToHost, s));
-  GIS_HIP(hipStreamSynchronize(s));
-  return GIS_OK;
+  return wait_stream(ctx, s);
 }
 
 // Builds every job's covering index (or checks full level-0 grids).  With
@@ -990,6 +998,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   // sweeps enqueued with a round: what the previous round needed, plus two
   const int32_t first_sweeps = ctx->tune.first_sweeps;
   int32_t sweep_hint = first_sweeps;
+  // host time per round: from the previous round's statistics to this one's
+  auto t_mark = std::chrono::steady_clock::now();
+  double wait_mark = ctx->wait_ms;
   for (int r = 0; r <= rounds; ++r) {
     const uint8_t* lv = (const uint8_t*)(cur_is_A ? ctx->lvA.ptr : ctx->lvB.ptr);
     const int32_t* ix = (const int32_t*)(cur_is_A ? ctx->ixA.ptr : ctx->ixB.ptr);
@@ -1123,6 +1134,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     }
     if (n_rows > 0) edges_per_row = (double)gr.n_edges / (double)n_rows;
     if (edges_per_row < 1.0) edges_per_row = 1.0;
+    const auto t_now = std::chrono::steady_clock::now();
     for (int j = 0; j < nj; ++j) {
       if (!active[j]) continue;
       const JobStats& js = ctx->h_stats[j];
@@ -1140,9 +1152,13 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       st.ms_subdivide = last ? 0.f : ms_sub;
       st.ms_image = gr.ms_image;
       st.ms_recheck = gr.ms_recheck;
+      st.ms_host_wait = ctx->wait_ms - wait_mark;
+      st.ms_host = std::chrono::duration<double, std::milli>(t_now - t_mark).count() - st.ms_host_wait;
       info[j].n_rounds = r + 1;
       info[j].n_kept = st.n_kept;
     }
+    t_mark = t_now;
+    wait_mark = ctx->wait_ms;
     // jobs that keep nothing, and every job after the last round, are done
     // (a job that keeps nothing set no flags for the next covering)
     for (int j = 0; j < nj; ++j) {
@@ -1429,6 +1445,82 @@ int32_t gis_solve_batch(gis_ctx* ctx, int32_t n_jobs, const gis_job* jobs, int32
   }
   DeviceGuard dg(ctx->device);
   return solve_batch(ctx, specs, K, rounds, opts, out_sols, as_stream(stream));
+}
+
+int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
+                     const double* d_u, int32_t K, int32_t rounds, const gis_opts* opts,
+                     int32_t repeats, gis_tuning* best, double* best_ms, void* stream) {
+  if (!ctx) return inval("ctx is NULL");
+  if (repeats < 1 || repeats > 16) return inval("repeats must be in 1..16");
+  const gis_tuning start = ctx->tune;
+  int64_t kept0 = -1;
+  // median wall time of `repeats` solves under tuning t
+  auto trial = [&](const gis_tuning& t, double* ms) -> int32_t {
+    ctx->tune = t;
+    std::vector<double> v;
+    for (int i = 0; i < repeats; ++i) {
+      gis_solution* sol = nullptr;
+      const auto t0 = std::chrono::steady_clock::now();
+      const int32_t rc = gis_solve(ctx, sys, grid, d_u, K, rounds, opts, &sol, stream);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rc != GIS_OK) return rc;
+      const int64_t kept = sol->info.n_kept;
+      gis_solution_free(sol);
+      if (kept0 < 0) kept0 = kept;
+      if (kept != kept0) {
+        set_error("internal: the kept set changed with the schedule parameters");
+        return GIS_E_INTERNAL;
+      }
+      v.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    std::sort(v.begin(), v.end());
+    *ms = v[v.size() / 2];
+    return GIS_OK;
+  };
+  gis_tuning cur = start;
+  double cur_ms = 0.0;
+  int32_t rc = trial(cur, &cur_ms);
+  if (rc != GIS_OK) {
+    ctx->tune = start;
+    return rc;
+  }
+  struct Field {
+    int64_t (*get)(const gis_tuning&);
+    void (*set)(gis_tuning&, int64_t);
+    std::vector<int64_t> values;
+  };
+  const std::vector<Field> fields = {
+      {[](const gis_tuning& t) { return (int64_t)t.first_sweeps; },
+       [](gis_tuning& t, int64_t v) { t.first_sweeps = (int32_t)v; }, {6, 10, 16, 24}},
+      {[](const gis_tuning& t) { return (int64_t)t.sweep_batch; },
+       [](gis_tuning& t, int64_t v) { t.sweep_batch = (int32_t)v; }, {4, 8, 16}},
+      {[](const gis_tuning& t) { return t.sweep_edges; },
+       [](gis_tuning& t, int64_t v) { t.sweep_edges = v; }, {1 << 20, 8 << 20, 64 << 20}},
+      {[](const gis_tuning& t) { return (int64_t)t.sweep_blocks; },
+       [](gis_tuning& t, int64_t v) { t.sweep_blocks = (int32_t)v; }, {1024, 4096, 16384}},
+      {[](const gis_tuning& t) { return (int64_t)t.front_blocks; },
+       [](gis_tuning& t, int64_t v) { t.front_blocks = (int32_t)v; }, {1024, 4096, 16384}},
+  };
+  for (const Field& f : fields) {
+    for (int64_t v : f.values) {
+      if (f.get(cur) == v) continue;
+      gis_tuning t = cur;
+      f.set(t, v);
+      double ms = 0.0;
+      if ((rc = trial(t, &ms)) != GIS_OK) {
+        ctx->tune = start;
+        return rc;
+      }
+      if (ms < 0.98 * cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  }
+  ctx->tune = cur;
+  if (best) *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return GIS_OK;
 }
 
 int32_t gis_solution_info(const gis_solution* sol, gis_solve_info* info) {

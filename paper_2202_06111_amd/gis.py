@@ -73,7 +73,7 @@ class RoundStatsT(ctypes.Structure):
     _fields_ = [("n_cells", I64), ("n_rows", I64), ("n_edges", I64), ("n_out", I64),
                 ("n_kept", I64), ("n_boundary", I64), ("n_recheck", I64), ("max_level", I32),
                 ("reserved", I32), ("ms_build", F64), ("ms_prune", F64), ("ms_subdivide", F64),
-                ("ms_image", F64), ("ms_recheck", F64)]
+                ("ms_image", F64), ("ms_recheck", F64), ("ms_host", F64), ("ms_host_wait", F64)]
 
 
 class SolveInfoT(ctypes.Structure):
@@ -103,6 +103,7 @@ def lib():
             "gis_ctx_destroy": ([P], None),
             "gis_get_tuning": ([P, P], I32),
             "gis_set_tuning": ([P, P], I32),
+            "gis_autotune": ([P, P, P, P, I32, I32, P, I32, P, P, P], I32),
             "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
             "gis_subdivide": ([P, P, P, P, I32, P, P, P], I32),
@@ -126,7 +127,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_build_graph", "gis_prune", "gis_subdivide",
+EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_subdivide",
             "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
             "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
             "gis_last_error", "gis_version")
@@ -436,6 +437,20 @@ def solve(ctx: Context, system: W.System, grid: W.Grid, u, rounds: int, opts: Op
                            int(du.shape[0]), rounds, ctypes.byref(opts), ctypes.byref(h),
                            _stream_ptr(stream)))
     return Solution(h, ctx.device)
+
+
+def autotune(ctx: Context, wl: W.Workload, repeats: int = 3, stream=None, **opt_over):
+    """Chooses ctx's schedule parameters for the workload by timing whole solves
+    (gis_autotune); returns (parameters, median ms per solve)."""
+    du = to_device_u(ctx, wl.u)
+    st, gt = system_t(wl.system), grid_t(wl.grid)
+    opts = workload_opts(wl, **opt_over)
+    best = TuningT()
+    ms = F64(0.0)
+    _check(lib().gis_autotune(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du),
+                              int(du.shape[0]), wl.rounds, ctypes.byref(opts), int(repeats),
+                              ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)))
+    return {f: int(getattr(best, f)) for f in TUNING_FIELDS}, float(ms.value)
 
 
 def solve_workload(ctx: Context, wl: W.Workload, stream=None, **opt_over) -> Solution:

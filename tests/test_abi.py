@@ -54,12 +54,13 @@ def test_struct_layouts_match_the_header(built, tmp_path):
     src = str(tmp_path / "sizeof.c")
     exe = str(tmp_path / "sizeof")
     with open(src, "w") as f:
-        f.write('#include <stdio.h>\n#include "gis.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
+        f.write('#include <stdio.h>\n#include "gis.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                 'sizeof(gis_system),sizeof(gis_grid),sizeof(gis_opts),sizeof(gis_cells),'
-                'sizeof(gis_graph),sizeof(gis_round_stats),sizeof(gis_solve_info));return 0;}\n')
+                'sizeof(gis_graph),sizeof(gis_round_stats),sizeof(gis_solve_info),'
+                'sizeof(gis_tuning));return 0;}\n')
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src], check=True)
     sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
                                             check=True).stdout.split()]
     mirrors = [gis.SystemT, gis.GridT, gis.OptsT, gis.CellsT, gis.GraphT, gis.RoundStatsT,
-               gis.SolveInfoT]
+               gis.SolveInfoT, gis.TuningT]
     assert sizes == [ctypes.sizeof(m) for m in mirrors]

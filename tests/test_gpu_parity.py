@@ -223,6 +223,22 @@ def test_solve_adaptive_tunings(G, ctx, tuning):
         ctx.set_tuning(**prev)
 
 
+def test_autotune_keeps_results(G):
+    """The autotuner only picks schedule parameters: after it, the solve still
+    equals the oracle, and the context holds the parameters it returned."""
+    c = G.Context(0)
+    try:
+        wl = W.vdp_adaptive_32("fp64")
+        best, ms = G.autotune(c, wl, repeats=1, precision="fp64")
+        assert ms > 0
+        assert c.get_tuning() == best
+        _check_solve(G, c, wl, "fp64")
+        with pytest.raises(G.GisError):
+            G.autotune(c, wl, repeats=0, precision="fp64")
+    finally:
+        c.close()
+
+
 def test_tuning_rejects_out_of_range(G, ctx):
     before = ctx.get_tuning()
     for bad in (dict(first_sweeps=0), dict(sweep_batch=300), dict(sweep_edges=-1),
