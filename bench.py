@@ -21,6 +21,7 @@ solves; the chosen parameters are reported under "schedule".
 Prints one JSON line on stdout.
 """
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -56,6 +57,37 @@ def parse():
                    help="first run one plain device-to-device copy of this many MiB, as the "
                         "reference kernel for scaling HBM byte counters")
     return p.parse_args()
+
+
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "traffic_k_build.md")
+KERNEL_SOURCES = ("k_build.hip", "dynamics.h", "gis_internal.h")
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2202_06111_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per build-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), provided
+    it was taken for this workload and precision with the current kernel
+    sources; None otherwise."""
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None
+    digest = kernel_sources_digest()
+    with open(TRAFFIC_TABLE) as fh:
+        for line in fh:
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 8 and cells[0] == workload and cells[1] == precision and cells[2] == digest:
+                try:
+                    return float(cells[7])
+                except ValueError:
+                    return None
+    return None
 
 
 def cpu_baseline(wl, budget_s):
@@ -120,31 +152,32 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = gis.Context(0)
-    du = gis.to_device_u(ctx, wl.u)
-    opts = gis.workload_opts(wl, precision=precision, timing=True)
-    stream = torch.cuda.current_stream()
+    # a stream of its own (default priority): the null stream cannot be captured as a graph
+    stream = torch.cuda.Stream()
     schedule = {"autotuned": False, **ctx.get_tuning()}
     if not a.no_autotune:
-        best, tuned_ms = gis.autotune(ctx, wl, repeats=3, precision=precision)
+        best, tuned_ms = gis.autotune(ctx, wl, repeats=3, stream=stream, precision=precision)
         schedule = {"autotuned": True, "tuned_ms_per_solve": tuned_ms, **best}
+    solver = gis.Solver(ctx, wl, stream=stream, precision=precision, timing=True)
 
     def step():
-        sol = gis.solve(ctx, wl.system, wl.grid, du, wl.rounds, opts, stream)
-        info = sol.info()
+        sol = solver()  # gis_solve synchronises its stream before returning
+        raw = sol.info_raw()
         sol.free()
-        return info
+        return raw
 
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    infos, lat = [], []
+    raws, lat = [], []
     t0 = time.perf_counter()
     for _ in range(a.steps):
         ts = time.perf_counter()
-        infos.append(step())
+        raws.append(step())
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    infos = [gis.info_dict(r) for r in raws]
 
     rows = sum(r["n_rows"] for inf in infos for r in inf["rounds"])
     flops_row = W.canonical_flops_per_row(wl.system, wl.samples)
@@ -171,7 +204,8 @@ def main():
                    "rows_per_solve": rows // a.steps, "final_cells": last["n_cells"],
                    "final_kept": last["n_kept"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": recorded_traffic(wl.name, precision),
                      "kernel": "k_build<%s> (images + boxes + cover + CSR emit, one pass)" %
                                ("fp64" if precision == "fp64" else "fp32+fp64 recheck"),
                      "avg_launch_ms": img_ms / max(launches, 1),

@@ -172,9 +172,12 @@ typedef struct gis_tuning {
   int32_t frontier_batch;  /* frontier steps between checks [16] (1..256) */
   int32_t sweep_blocks;    /* grid cap of a sweep launch [4096] (1..65536) */
   int32_t front_blocks;    /* grid of a frontier step, 4 waves per block [2048] (1..65536) */
-  int32_t use_graphs;      /* nonzero: rounds are captured as HIP graphs and replayed when
-                              a later round has the same launches [0] */
-  int32_t reserved[2];
+  int32_t use_graphs;      /* nonzero: a round's analysis launch sequence is captured as a
+                              HIP graph at its second sighting and replayed later [0] */
+  int32_t edge_hint;       /* edges per row assumed for the first build of a solve, which
+                              sizes the edge buffer (0: 2^(n+1)); too small a value costs
+                              one rebuild of that round, never a wrong result (0..4096) */
+  int32_t reserved;
 } gis_tuning;
 
 /* Reads / replaces the context's schedule parameters.  GIS_E_INVAL when a
@@ -186,7 +189,7 @@ int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* tuning);
  * timing whole gis_solve calls of it (arguments as for gis_solve).  Starting
  * from the current parameters it tries, one field at a time, a few values
  * per field and keeps a value when the median wall time of `repeats` solves
- * (1..16) drops by more than 2%.  Every trial must reproduce the first trial's
+ * (1..16, each trial after two untimed solves) drops by more than 2%.  Every trial must reproduce the first trial's
  * kept-cell count (GIS_E_INTERNAL otherwise).  The chosen parameters are set
  * on ctx and returned in *best (may be NULL), their median time in *best_ms
  * (may be NULL).  Synchronises; allocates like gis_solve. */

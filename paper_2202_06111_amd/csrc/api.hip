@@ -92,6 +92,22 @@ struct Pinned {
 
 using namespace gis;
 
+// Launch sequences replayed as HIP graphs.  A sequence is identified by a key
+// that holds every value its launches depend on (pointers, sizes, counts);
+// the second sighting of a key captures the sequence and instantiates it,
+// later sightings replay the executable graph, and one-off sequences run
+// eagerly.  At most kGraphs executables are kept (least recently used go).
+struct GraphCache {
+  struct Entry {
+    hipGraphExec_t exec = nullptr;
+    uint32_t seen = 0;
+    uint64_t used = 0;
+  };
+  std::map<std::string, Entry> map;
+  uint64_t tick = 0;
+};
+constexpr size_t kGraphs = 64;
+
 struct gis_ctx {
   int device = 0;
   // counters, then (at kStatsOff) the per-job stats: cleared by one fill and
@@ -109,8 +125,12 @@ struct gis_ctx {
   uint32_t lb_epoch = 0;
   bool lb_clean = false, prune_clean = false, next_clean = false;
   int32_t first_sweeps = 0;  // sweeps of the last enqueue_prune
-  gis_tuning tune{16, 8, (int64_t)8 << 20, 16, 4096, 2048, 0, {0, 0}};
+  gis_tuning tune{16, 8, (int64_t)8 << 20, 16, 4096, 2048, 0, 0, 0};
   double wait_ms = 0.0;  // host time spent blocked in stream synchronisations
+  // per round of the last solve: its cell count and the sweeps its analysis
+  // needed (0: it did not converge within the first batch)
+  std::vector<std::pair<int64_t, int32_t>> sweep_memo;
+  GraphCache graphs;
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
   DevBuf removed, rptr, rrow, rcur, rowstate, good, front;
@@ -623,6 +643,53 @@ bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
   return K <= 256 && n_edges <= ctx->tune.sweep_edges;
 }
 
+// Runs enqueue() on stream s, through the context's graph cache when
+// tune.use_graphs is set and s is not the null stream (which cannot be
+// captured).  enqueue() may only launch kernels on s.
+template <typename F>
+int32_t run_cached(gis_ctx* ctx, const void* key, size_t key_bytes, hipStream_t s, F&& enqueue) {
+  if (!ctx->tune.use_graphs || s == nullptr) return enqueue();
+  GraphCache& gc = ctx->graphs;
+  const std::string k((const char*)key, key_bytes);
+  auto it = gc.map.find(k);
+  if (it == gc.map.end()) {
+    if (gc.map.size() >= 4 * kGraphs) {  // forget one-off keys and old executables
+      auto old = gc.map.begin();
+      for (auto j = gc.map.begin(); j != gc.map.end(); ++j)
+        if (j->second.used < old->second.used) old = j;
+      if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
+      gc.map.erase(old);
+    }
+    it = gc.map.emplace(k, GraphCache::Entry{}).first;
+  }
+  GraphCache::Entry& e = it->second;
+  e.used = ++gc.tick;
+  if (e.exec) {
+    GIS_HIP(hipGraphLaunch(e.exec, s));
+    return GIS_OK;
+  }
+  if (e.seen++ == 0) return enqueue();
+  size_t live = 0;
+  for (auto& kv : gc.map) live += kv.second.exec ? 1 : 0;
+  if (live >= kGraphs) return enqueue();
+  GIS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  const int32_t rc = enqueue();
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(s, &g);
+  if (rc != GIS_OK || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != GIS_OK ? rc : hip_fail(ce, "hipStreamEndCapture");
+  }
+  const hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    e.exec = nullptr;
+    return hip_fail(ie, "hipGraphInstantiate");
+  }
+  GIS_HIP(hipGraphLaunch(e.exec, s));
+  return GIS_OK;
+}
+
 // est_edges: the graph's edge count, or an estimate of it (it only chooses
 // between the two phases).
 // first: the number of sweeps to enqueue before the first check.
@@ -638,15 +705,38 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
     return GIS_E_UNSUPPORTED;
   }
   if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
-  if (clear_removed && (rc = fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s))) return rc;
   if (first <= 0) first = ctx->tune.first_sweeps;
   ctx->first_sweeps = sweeps_fit(ctx, est_edges, K) ? first : 0;
-  if (ctx->first_sweeps == 0) return GIS_OK;
+  if (ctx->first_sweeps == 0)
+    return clear_removed ? fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s) : GIS_OK;
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
-  if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps, s)))
-    return rc;
-  return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask,
-                                ctx->first_sweeps, s, B, level, idx);
+  // the sweeps and the final pass: one launch sequence, replayed as a graph
+  struct Key {
+    const void* p[12];
+    int64_t n_cells, cap_edges;
+    int32_t K, analysis, first, sweep_blocks, n_jobs, clear;
+  } key;
+  memset(&key, 0, sizeof key);
+  const void* ptrs[12] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
+                          dcnt(ctx)->n_kept, B ? B->d_jobs : nullptr, B ? B->d_stats : nullptr,
+                          nullptr};
+  memcpy(key.p, ptrs, sizeof ptrs);
+  key.n_cells = n_cells;
+  key.cap_edges = cap_edges;
+  key.K = K;
+  key.analysis = analysis;
+  key.first = ctx->first_sweeps;
+  key.sweep_blocks = w.sweep_blocks;
+  key.n_jobs = B ? B->n_jobs : 0;
+  key.clear = clear_removed ? 1 : 0;
+  return run_cached(ctx, &key, sizeof key, s, [&]() -> int32_t {
+    int32_t e;
+    if (clear_removed && (e = fill_u8(w.removed, 0, n_cells, s))) return e;
+    if ((e = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps, s)))
+      return e;
+    return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask,
+                                  ctx->first_sweeps, s, B, level, idx);
+  });
 }
 
 // After the synchronisation that follows enqueue_prune.
@@ -994,7 +1084,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   // emit, analysis and subdivision are enqueued again after the buffer grew.
   hipEvent_t* ev = ctx->ev;
   bool cur_is_A = true;
-  double edges_per_row = 8.0;
+  // edges per row before the first build: a box of about one cell meets
+  // 2^n cells; twice that, so that round 0 rarely has to grow the buffer
+  double edges_per_row = ctx->tune.edge_hint > 0 ? (double)ctx->tune.edge_hint : (double)(2 << n);
   // sweeps enqueued with a round: what the previous round needed, plus two
   const int32_t first_sweeps = ctx->tune.first_sweeps;
   int32_t sweep_hint = first_sweeps;
@@ -1011,6 +1103,11 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     }
     const int64_t n_cells = B.total_cells;
     const int64_t n_rows = n_cells * K;
+    // a round of the same size as in the previous solve needs about as many
+    // sweeps as it did then (in-place sweeps may differ by one or two)
+    if ((size_t)r < ctx->sweep_memo.size() && ctx->sweep_memo[r].first == n_cells &&
+        ctx->sweep_memo[r].second > 0)
+      sweep_hint = std::min(ctx->sweep_memo[r].second + 2, 64);
     const size_t want_col = (size_t)((double)n_rows * edges_per_row * 1.25) + 64;
     if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)) ||
         (rc = ensure(ctx->col, want_col * 4)) || (rc = ensure(ctx->kept, (size_t)n_cells + 16)) ||
@@ -1088,6 +1185,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
     GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
     const bool conv = prune_converged(ctx, n_cells);
+    if (ctx->sweep_memo.size() <= (size_t)r) ctx->sweep_memo.resize(r + 1);
+    ctx->sweep_memo[r] = {n_cells, conv && ctx->first_sweeps > 0 ? ctx->h_counters->sweep_last + 1 : 0};
     if (conv && ctx->first_sweeps > 0) {
       // rounds of one solve need similar numbers; a miss costs a host round
       // trip and a second subdivision, so keep a margin
@@ -1251,6 +1350,8 @@ void gis_ctx_destroy(gis_ctx* c) {
                     &c->rowstate, &c->good, &c->front, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
   for (DevBuf* b : bufs) release(*b);
+  for (auto& kv : c->graphs.map)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   c->h_cs.free();
   c->h_jobs.free();
   c->h_maxerr.free();
@@ -1272,7 +1373,7 @@ int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* t) {
   auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
   if (!in(t->first_sweeps, 1, 256) || !in(t->sweep_batch, 1, 256) || t->sweep_edges < 0 ||
       !in(t->frontier_batch, 1, 256) || !in(t->sweep_blocks, 1, 65536) ||
-      !in(t->front_blocks, 1, 65536))
+      !in(t->front_blocks, 1, 65536) || !in(t->edge_hint, 0, 4096))
     return inval("tuning field out of range");
   ctx->tune = *t;
   return GIS_OK;
@@ -1458,7 +1559,9 @@ int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
   auto trial = [&](const gis_tuning& t, double* ms) -> int32_t {
     ctx->tune = t;
     std::vector<double> v;
-    for (int i = 0; i < repeats; ++i) {
+    // two untimed solves first: a launch sequence is captured as a graph at
+    // its second sighting, so the timed solves replay it
+    for (int i = -2; i < repeats; ++i) {
       gis_solution* sol = nullptr;
       const auto t0 = std::chrono::steady_clock::now();
       const int32_t rc = gis_solve(ctx, sys, grid, d_u, K, rounds, opts, &sol, stream);
@@ -1471,7 +1574,7 @@ int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
         set_error("internal: the kept set changed with the schedule parameters");
         return GIS_E_INTERNAL;
       }
-      v.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+      if (i >= 0) v.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
     }
     std::sort(v.begin(), v.end());
     *ms = v[v.size() / 2];
@@ -1500,6 +1603,8 @@ int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
        [](gis_tuning& t, int64_t v) { t.sweep_blocks = (int32_t)v; }, {1024, 4096, 16384}},
       {[](const gis_tuning& t) { return (int64_t)t.front_blocks; },
        [](gis_tuning& t, int64_t v) { t.front_blocks = (int32_t)v; }, {1024, 4096, 16384}},
+      {[](const gis_tuning& t) { return (int64_t)t.use_graphs; },
+       [](gis_tuning& t, int64_t v) { t.use_graphs = (int32_t)v; }, {0, 1}},
   };
   for (const Field& f : fields) {
     for (int64_t v : f.values) {

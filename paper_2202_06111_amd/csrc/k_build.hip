@@ -31,7 +31,7 @@ namespace gis {
 namespace {
 
 constexpr int kTile = 4096;   // LDS staging tile of the emitter (int32 ids, 16 KiB)
-constexpr int kCache = 6;     // target ids kept in LDS per row between count and emit
+constexpr int kCache = 6;     // runs of target ids kept in LDS per row between count and emit
 
 // Look-back words: the launch's epoch in bits 40-63, a status in bits 38-39
 // and an edge total in bits 0-37.  A word written by an earlier launch
@@ -125,11 +125,12 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
     const int64_t base = ci.off[L];
     bool done = false;
     while (!done) {
-      int64_t ra[kRuns], rb[kRuns];
-      bool in[kRuns];
+      constexpr int R = kRuns;
+      int64_t ra[R], rb[R];
+      bool in[R];
       int m = 0;
 #pragma unroll
-      for (int q = 0; q < kRuns; ++q) {
+      for (int q = 0; q < R; ++q) {
         if (!done) {
           int64_t lin = 0;
           bool inner = interior;
@@ -152,16 +153,16 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
           else ++k[d];
         }
       }
-      int64_t p0[kRuns], p1[kRuns], q0[kRuns], q1[kRuns];
+      int64_t p0[R], p1[R], q0[R], q1[R];
 #pragma unroll
-      for (int q = 0; q < kRuns; ++q) {
+      for (int q = 0; q < R; ++q) {
         p0[q] = q < m ? P[ra[q]] : 0;
         p1[q] = q < m ? P[rb[q] + 1] : 0;
         q0[q] = q < m && in[q] ? P[ra[q] + cl] : 0;
         q1[q] = q < m && in[q] ? P[rb[q] - cr + 1] : 0;
       }
 #pragma unroll
-      for (int q = 0; q < kRuns; ++q)
+      for (int q = 0; q < R; ++q)
         if (q < m && !f(p0[q], p1[q], in[q], q0[q], q1[q])) return;
     }
   }
@@ -241,14 +242,16 @@ __device__ __forceinline__ bool band_safe(const Job& J, const CoverIndex& ci, co
 
 constexpr int64_t kLo32 = 0xffffffffll;
 
-// Edge count of a row and the first kCache target ids (local ids), stored
-// with stride kRowBlock from `cache`; *hole is set when a hole of the
-// covering meets the interior range.  Per run the prefix counts give the
-// leaves (ids consecutive from the first) and, on rows of the interior box,
-// the holes between the interior columns.
+// Edge count of a row; *hole is set when a hole of the covering meets the
+// interior range.  Per run of index slots the prefix counts give the leaves
+// (ids consecutive from the first) and, on rows of the interior box, the holes
+// between the interior columns.  The first kCache runs that hold leaves are
+// kept as (first local id, length) pairs with stride kRowBlock from `cache`
+// (length 0 after the last one), so that the emit need not walk the index
+// again for rows with no more runs than that.
 template <int N, bool UNI>
 __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ranges<N>& r,
-                                                 int32_t* cache, bool* hole) {
+                                                 int2* cache, bool* hole) {
   *hole = false;
   if (r.empty) return 0;
   if (UNI || ci.uniform) {
@@ -257,20 +260,22 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ran
     for (int d = 0; d < N; ++d) c *= r.hi[d] - r.lo[d] + 1;
     return c;
   }
-  int32_t c = 0;
+  int32_t c = 0, nr = 0;
   bool h = false;
   walk_runs<N>(ci, r.lo, r.hi, r.ilo, r.ihi, true,
                [&](int64_t p0, int64_t p1, bool inner, int64_t q0, int64_t q1) {
                  const int32_t nl = (int32_t)((p1 & kLo32) - (p0 & kLo32));
                  if (nl > 0) {
-                   const int32_t first = (int32_t)((p0 & kLo32) - ci.pbase);
-                   for (int32_t i = 0; i < nl && c + i < kCache; ++i)
-                     cache[(c + i) * kRowBlock] = first + i;
+                   if (nr < kCache)
+                     cache[nr * kRowBlock] = make_int2((int32_t)((p0 & kLo32) - ci.pbase), nl);
+                   ++nr;
                    c += nl;
                  }
                  h |= inner && (q1 >> 32) != (q0 >> 32);
                  return true;
                });
+  if (nr < kCache) cache[nr * kRowBlock] = make_int2(0, 0);
+  else if (nr > kCache) cache[0] = make_int2(0, -1);  // too many runs: walk again
   *hole = h;
   return c;
 }
@@ -280,7 +285,7 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ran
 template <int N, bool UNI>
 __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t* lo,
                                              const int32_t* hi, int32_t count,
-                                             const int32_t* cache, int32_t id0, int32_t p0,
+                                             const int2* cache, int32_t id0, int32_t p0,
                                              int32_t p1, int32_t* dst) {
   if (UNI || ci.uniform) {
     // position -> multi-index in the box, last dimension fastest; ids along
@@ -323,8 +328,16 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
     return;
   }
   if constexpr (UNI) return;
-  if (count <= kCache) {
-    for (int32_t p = p0; p < p1; ++p) dst[p - p0] = id0 + cache[p * kRowBlock];
+  if (cache[0].y >= 0) {  // the row's runs are cached
+    int32_t w = 0;        // position of the run's first leaf in the row's list
+    for (int k = 0; k < kCache && w < p1; ++k) {
+      const int2 run = cache[k * kRowBlock];
+      if (run.y == 0) break;
+      const int32_t i0 = p0 > w ? p0 - w : 0;
+      const int32_t i1 = p1 - w < run.y ? p1 - w : run.y;
+      for (int32_t i = i0; i < i1; ++i) dst[w + i - p0] = id0 + run.x + i;
+      w += run.y;
+    }
     return;
   }
   int32_t w = 0;  // position of the run's first leaf in the row's list
@@ -346,7 +359,7 @@ template <int KIND, int N, bool F32, bool UNI>
 __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   __shared__ CoverIndex ci;
   __shared__ int32_t tile[kTile];
-  __shared__ int32_t cache[kCache * kRowBlock];
+  __shared__ int2 cache[UNI ? 1 : kCache * kRowBlock];
   __shared__ int64_t wsum[kRowBlock / 64];
   __shared__ int64_t s_prefix;
   __shared__ uint32_t s_bid, s_out, s_rchk;
@@ -394,7 +407,7 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
     if (finite) {
       const Ranges<N> rr = ranges_of<N>(J.grid, ci, bl, bh);
       bool hole;
-      c = count_targets<N, UNI>(ci, rr, cache + tid, &hole);
+      c = count_targets<N, UNI>(ci, rr, UNI ? cache : cache + tid, &hole);
       out = rr.outx || hole;
       if (a.fast_out && out) c = 0;
 #pragma unroll
@@ -490,7 +503,7 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
     const int64_t s0 = off > w0 ? off : w0;
     const int64_t s1 = off + c < w1 ? off + c : w1;
     if (s0 < s1)
-      emit_targets<N, UNI>(ci, lo, hi, c, cache + tid, id0, (int32_t)(s0 - off),
+      emit_targets<N, UNI>(ci, lo, hi, c, UNI ? cache : cache + tid, id0, (int32_t)(s0 - off),
                            (int32_t)(s1 - off), tile + (s0 - w0));
     __syncthreads();
     for (int64_t i = tid; i < w1 - w0; i += kRowBlock) a.col[prefix + w0 + i] = tile[i];

@@ -186,8 +186,11 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
   __shared__ uint8_t ok[256];
   bool changed = false;
   const int t = threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * cpb;
-  for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
+  // odd sweeps take the groups in reverse order (blocks start roughly in
+  // index order), so removals propagate in place along both directions
+  const int64_t groups = (n_cells + cpb - 1) / cpb;
+  for (int64_t gi = blockIdx.x; gi < groups; gi += gridDim.x) {
+    const int64_t g0 = ((s & 1) ? groups - 1 - gi : gi) * cpb;
     const int64_t c = g0 + t / K;
     bool good = false;
     if (t < cpb * K && c < n_cells && !removed[c])

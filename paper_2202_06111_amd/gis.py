@@ -58,11 +58,11 @@ class GraphT(ctypes.Structure):
 class TuningT(ctypes.Structure):
     _fields_ = [("first_sweeps", I32), ("sweep_batch", I32), ("sweep_edges", I64),
                 ("frontier_batch", I32), ("sweep_blocks", I32), ("front_blocks", I32),
-                ("use_graphs", I32), ("reserved", I32 * 2)]
+                ("use_graphs", I32), ("edge_hint", I32), ("reserved", I32)]
 
 
 TUNING_FIELDS = ("first_sweeps", "sweep_batch", "sweep_edges", "frontier_batch", "sweep_blocks",
-                 "front_blocks", "use_graphs")
+                 "front_blocks", "use_graphs", "edge_hint")
 
 
 class JobT(ctypes.Structure):
@@ -364,6 +364,17 @@ def calibrate_band(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, 
     return np.array(band[: grid.n])
 
 
+def info_dict(inf: SolveInfoT) -> dict:
+    """gis_solve_info as a dict with one dict per round."""
+    rounds = []
+    for r in range(inf.n_rounds):
+        s = inf.rounds[r]
+        rounds.append({k: getattr(s, k) for k, _ in RoundStatsT._fields_ if k != "reserved"})
+    return {"n_rounds": inf.n_rounds, "n": inf.n, "K": inf.K, "mask_words": inf.mask_words,
+            "n_cells": inf.n_cells, "n_kept": inf.n_kept, "band": list(inf.band[: inf.n]),
+            "rounds": rounds}
+
+
 class Solution:
     """A solve result resident on the device (library-owned handle)."""
 
@@ -377,16 +388,14 @@ class Solution:
             raise RuntimeError("solution is freed")
         return self._h
 
-    def info(self) -> dict:
+    def info_raw(self) -> SolveInfoT:
+        """The solve statistics as the C struct (no conversion)."""
         inf = SolveInfoT()
         _check(lib().gis_solution_info(self.handle, ctypes.byref(inf)))
-        rounds = []
-        for r in range(inf.n_rounds):
-            s = inf.rounds[r]
-            rounds.append({k: getattr(s, k) for k, _ in RoundStatsT._fields_ if k != "reserved"})
-        return {"n_rounds": inf.n_rounds, "n": inf.n, "K": inf.K, "mask_words": inf.mask_words,
-                "n_cells": inf.n_cells, "n_kept": inf.n_kept, "band": list(inf.band[: inf.n]),
-                "rounds": rounds}
+        return inf
+
+    def info(self) -> dict:
+        return info_dict(self.info_raw())
 
     def export(self, stream=None):
         inf = self.info()
@@ -451,6 +460,26 @@ def autotune(ctx: Context, wl: W.Workload, repeats: int = 3, stream=None, **opt_
                               int(du.shape[0]), wl.rounds, ctypes.byref(opts), int(repeats),
                               ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)))
     return {f: int(getattr(best, f)) for f in TUNING_FIELDS}, float(ms.value)
+
+
+class Solver:
+    """One workload's solve with its arguments marshalled once: each call is a
+    single gis_solve on the given stream (for loops of identical solves)."""
+
+    def __init__(self, ctx: Context, wl: W.Workload, stream=None, **opt_over):
+        self.ctx = ctx
+        self.du = to_device_u(ctx, wl.u)
+        self.st, self.gt = system_t(wl.system), grid_t(wl.grid)
+        self.opts = workload_opts(wl, **opt_over)
+        self.rounds = wl.rounds
+        self.sp = _stream_ptr(stream)
+        self._args = (ctx.handle, ctypes.byref(self.st), ctypes.byref(self.gt), _ptr(self.du),
+                      int(self.du.shape[0]), self.rounds, ctypes.byref(self.opts))
+
+    def __call__(self) -> Solution:
+        h = P()
+        _check(lib().gis_solve(*self._args, ctypes.byref(h), self.sp))
+        return Solution(h, self.ctx.device)
 
 
 def solve_workload(ctx: Context, wl: W.Workload, stream=None, **opt_over) -> Solution:

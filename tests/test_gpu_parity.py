@@ -193,6 +193,29 @@ def test_prune_tunings_match_oracle(G, ctx, name, analysis, tuning):
 
 
 @pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+def test_prune_frontier_dense_rows(G, ctx, analysis):
+    """A coarse 4-D covering whose rows have tens of targets: a 256-row block
+    of the reverse-CSR scatter holds more edges than its LDS stage, so the
+    scatter takes its direct path; the frontier result equals the oracle."""
+    system = W.vdp2()
+    grid = W.Grid((5, 5, 5, 5), (-2.5, -3, -2.5, -3), (2.5, 3, 2.5, 3))
+    u = W.input_grid(-1, 1, 3, 2)
+    level, idx = oracle.coarse_cells(grid)
+    g, want = _check_graph(G, ctx, system, grid, u, W.CORNERS_CENTER, level, idx)
+    rp = want["row_ptr"]
+    assert max(rp[min(b + 256, len(rp) - 1)] - rp[b] for b in range(0, len(rp) - 1, 256)) > 6144
+    kept_w, mask_w, _ = oracle.prune(want["row_ptr"], want["col"], want["out"], level.shape[0],
+                                     u.shape[0], analysis)
+    prev = ctx.set_tuning(sweep_edges=0)
+    try:
+        kept, mask, nk = G.prune(ctx, g, level.shape[0], u.shape[0], analysis)
+    finally:
+        ctx.set_tuning(**prev)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+
+
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
 def test_prune_wide_inputs_random_graph(G, ctx, analysis):
     """K = 300 inputs (beyond a sweep block): the frontier phase with a thread
     per cell, on a seeded random graph (0-3 targets per row, 3% OUT rows)."""
@@ -223,6 +246,34 @@ def test_solve_adaptive_tunings(G, ctx, tuning):
         ctx.set_tuning(**prev)
 
 
+def test_graph_replays_match_eager_and_oracle(G):
+    """With use_graphs the analysis launch sequence of a round is captured on
+    its second sighting and replayed afterwards: solves of two workloads,
+    interleaved on a non-default stream with eager work and synchronisations
+    between them, all equal the oracle (replays 2, 3 and 4 of each round)."""
+    c = G.Context(0)
+    st = torch.cuda.Stream()
+    try:
+        c.set_tuning(use_graphs=1)
+        wls = [W.vdp_adaptive_32("fp64"), W.vdp_uniform_64()]
+        wants = [_oracle_solve(w) for w in wls]
+        for it in range(4):
+            for wl, want in zip(wls, wants):
+                with torch.cuda.stream(st):
+                    sol = G.solve_workload(c, wl, precision="fp64")
+                    lv, ix, kept, mask = sol.export()
+                    torch.cuda.synchronize()
+                    junk = torch.ones(1 << 20, device=c.dev).sum().item()  # eager work between replays
+                assert junk == float(1 << 20)
+                np.testing.assert_array_equal(_np(lv), want["level"], err_msg=f"iteration {it}")
+                np.testing.assert_array_equal(_np(ix), want["idx"])
+                np.testing.assert_array_equal(_np(kept), want["kept"])
+                np.testing.assert_array_equal(_np(mask).view(np.uint64), want["mask"])
+                sol.free()
+    finally:
+        c.close()
+
+
 def test_autotune_keeps_results(G):
     """The autotuner only picks schedule parameters: after it, the solve still
     equals the oracle, and the context holds the parameters it returned."""
@@ -242,7 +293,8 @@ def test_autotune_keeps_results(G):
 def test_tuning_rejects_out_of_range(G, ctx):
     before = ctx.get_tuning()
     for bad in (dict(first_sweeps=0), dict(sweep_batch=300), dict(sweep_edges=-1),
-                dict(front_blocks=0), dict(sweep_blocks=70000), dict(frontier_batch=0)):
+                dict(front_blocks=0), dict(sweep_blocks=70000), dict(frontier_batch=0),
+                dict(edge_hint=-1), dict(edge_hint=5000)):
         with pytest.raises(G.GisError):
             ctx.set_tuning(**bad)
         assert ctx.get_tuning() == before
@@ -335,11 +387,13 @@ def test_solve_vdp2_small_rounds(G, ctx):
 
 @pytest.mark.parametrize("analysis", ["nonleaving", "controlled"])
 def test_solve_edge_buffer_regrowth(G, analysis):
-    """A fresh context sizes its edge buffer from an estimate (8 edges per row)
-    that a coarse 4-D covering exceeds: the round is re-emitted, re-analysed
-    and re-subdivided after the buffer grows, and the result is unchanged."""
+    """A fresh context sizes its edge buffer from an estimate (here set to 8
+    edges per row) that a coarse 4-D covering exceeds: the round is
+    re-emitted, re-analysed and re-subdivided after the buffer grows, and the
+    result is unchanged."""
     c = G.Context(0)
     try:
+        c.set_tuning(edge_hint=8)
         wl = W.Workload("vdp2_5_r1", W.vdp2(),
                         W.Grid((5, 5, 5, 5), (-2.5, -3, -2.5, -3), (2.5, 3, 2.5, 3)),
                         W.input_grid(-1, 1, 3, 2), W.CORNERS_CENTER, 1, "fp64", analysis=analysis)
