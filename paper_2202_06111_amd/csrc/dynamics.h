@@ -90,6 +90,46 @@ __device__ __forceinline__ void rk4(const Rk4Consts<R>& c, int m, int nsub, R* x
   }
 }
 
+// The same for P independent states advanced in lockstep: the P dependency
+// chains interleave, which hides arithmetic latency at low occupancy.  Each
+// state sees exactly the operation sequence of rk4().
+template <int KIND, int N, int P, typename R>
+__device__ __forceinline__ void rk4_multi(const Rk4Consts<R>& c, int m, int nsub, R (*x)[N],
+                                          const R* u) {
+  for (int q = 0; q < nsub; ++q) {
+    R k1[P][N], k2[P][N], k3[P][N], k4[P][N], y[P][N];
+#pragma unroll
+    for (int i = 0; i < P; ++i) field<KIND, N, R>(c.p, m, x[i], u, k1[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int d = 0; d < N; ++d) y[i][d] = fmaT(c.h2, k1[i][d], x[i][d]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) field<KIND, N, R>(c.p, m, y[i], u, k2[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int d = 0; d < N; ++d) y[i][d] = fmaT(c.h2, k2[i][d], x[i][d]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) field<KIND, N, R>(c.p, m, y[i], u, k3[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int d = 0; d < N; ++d) y[i][d] = fmaT(c.h, k3[i][d], x[i][d]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) field<KIND, N, R>(c.p, m, y[i], u, k4[i]);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        R s = k1[i][d] + k4[i][d];
+        R t = k2[i][d] + k3[i][d];
+        s = fmaT(R(2), t, s);
+        x[i][d] = fmaT(c.h6, s, x[i][d]);
+      }
+  }
+}
+
 __host__ __device__ constexpr int ipow3(int n) { return n <= 0 ? 1 : 3 * ipow3(n - 1); }
 
 __device__ __forceinline__ int num_samples(int scheme, int n) {

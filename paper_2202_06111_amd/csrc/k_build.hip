@@ -190,24 +190,37 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
     bh[d] = R(-INFINITY);
   }
   const int S = num_samples(a.samples, N);
-  for (int q = 0; q < S; ++q) {
-    int k[N];
-    double xd[N];
-    sample_offsets<N>(a.samples, q, k);
-    sample_point<N>(J.grid, level, ci, k, xd);
-    R x[N];
+  // four-dimensional systems advance two samples at a time (independent
+  // chains for a kernel whose registers allow few waves); measured: 3% faster
+  // there, slower for the smaller systems (their occupancy drops)
+  constexpr int P = N >= 4 ? 2 : 1;
+  for (int q0 = 0; q0 < S; q0 += P) {
+    const int np = S - q0 < P ? S - q0 : P;
+    R x[P][N];
 #pragma unroll
-    for (int d = 0; d < N; ++d) x[d] = R(xd[d]);
-    rk4<KIND, N, R>(kc, m, J.sys.nsub, x, u);
+    for (int i = 0; i < P; ++i) {
+      int k[N];
+      double xd[N];
+      sample_offsets<N>(a.samples, q0 + (i < np ? i : 0), k);
+      sample_point<N>(J.grid, level, ci, k, xd);
 #pragma unroll
-    for (int d = 0; d < N; ++d) {
-      // min/max instructions: they differ from compare-and-select only for
-      // NaN (the row is then decided by `finite`) and in the sign of a zero
-      // (which changes no cover decision: (-0) - lo == (+0) - lo)
-      finite &= isfinite(x[d]);
-      bl[d] = fmin(x[d], bl[d]);
-      bh[d] = fmax(x[d], bh[d]);
+      for (int d = 0; d < N; ++d) x[i][d] = R(xd[d]);
     }
+    if (np == P) rk4_multi<KIND, N, P, R>(kc, m, J.sys.nsub, x, u);
+    else rk4<KIND, N, R>(kc, m, J.sys.nsub, x[0], u);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (i < np) {
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+          // min/max instructions: they differ from compare-and-select only
+          // for NaN (the row is then decided by `finite`) and in the sign of
+          // a zero (which changes no cover decision: (-0) - lo == (+0) - lo)
+          finite &= isfinite(x[i][d]);
+          bl[d] = fmin(x[i][d], bl[d]);
+          bh[d] = fmax(x[i][d], bh[d]);
+        }
+      }
   }
   return finite;
 }
