@@ -1,7 +1,9 @@
 // Device-wide exclusive prefix sums (int64 results) used for CSR offsets,
 // reverse-CSR offsets and cell compaction.  Tiles of kScanBlock * kScanItems
-// elements: reduce each tile, scan the tile sums (recursively), rescan each
-// tile with its offset.
+// elements: reduce each tile, then rescan each tile with its offset.  Up to
+// kDirect tiles, each block of the second launch sums the tile totals before
+// its own (L2-resident, a few loads per thread); beyond that the tile totals
+// are scanned recursively first.
 #include "gis_internal.h"
 
 namespace gis {
@@ -54,11 +56,23 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_sums(const T* in, int64_t n
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+constexpr int64_t kDirect = 8192;
+
 template <typename T, typename C = Plain<T>>
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const T* in, int64_t n,
-                                                          const int64_t* offsets, int64_t* out,
+                                                          const int64_t* offsets,
+                                                          const int64_t* sums, int64_t* out,
                                                           int64_t* d_total) {
   __shared__ int64_t lds[kScanBlock / 64];
+  __shared__ int64_t s_off;
+  if (sums) {  // this tile's offset: the totals of the tiles before it
+    int64_t part = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanBlock) part += sums[i];
+    int64_t tot;
+    block_exclusive(part, lds, tot);
+    if (threadIdx.x == 0) s_off = tot;
+    __syncthreads();
+  }
   const int64_t base = (int64_t)blockIdx.x * kTileElems + (int64_t)threadIdx.x * kScanItems;
   int64_t v[kScanItems];
   int64_t s = 0;
@@ -68,7 +82,8 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(const T* in, int64_t n
     s += v[i];
   }
   int64_t total;
-  int64_t run = block_exclusive(s, lds, total) + (offsets ? offsets[blockIdx.x] : 0);
+  int64_t run = block_exclusive(s, lds, total) + (offsets ? offsets[blockIdx.x] : 0) +
+                (sums ? s_off : 0);
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     if (base + i < n) out[base + i] = run;
@@ -89,7 +104,7 @@ int32_t scan_impl(const T* in, int64_t* out, int64_t n, int64_t* d_total, int64_
   if (n <= 0) return d_total ? fill_i64(d_total, 0, 1, s) : GIS_OK;
   if (n <= kTileElems) {
     hipLaunchKernelGGL((k_tile_scan<T, C>), dim3(1), dim3(kScanBlock), 0, s, in, n,
-                       (const int64_t*)nullptr, out, d_total);
+                       (const int64_t*)nullptr, (const int64_t*)nullptr, out, d_total);
     GIS_LAUNCH_CHECK("k_tile_scan");
     return GIS_OK;
   }
@@ -98,10 +113,16 @@ int32_t scan_impl(const T* in, int64_t* out, int64_t n, int64_t* d_total, int64_
   int64_t* offs = tmp + nb;
   hipLaunchKernelGGL((k_tile_sums<T, C>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, sums);
   GIS_LAUNCH_CHECK("k_tile_sums");
+  if (nb <= kDirect) {
+    hipLaunchKernelGGL((k_tile_scan<T, C>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
+                       (const int64_t*)nullptr, (const int64_t*)sums, out, d_total);
+    GIS_LAUNCH_CHECK("k_tile_scan");
+    return GIS_OK;
+  }
   int32_t rc = scan_impl<int64_t>(sums, offs, nb, nullptr, tmp + 2 * nb, s);
   if (rc != GIS_OK) return rc;
   hipLaunchKernelGGL((k_tile_scan<T, C>), dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n,
-                     (const int64_t*)offs, out, d_total);
+                     (const int64_t*)offs, (const int64_t*)nullptr, out, d_total);
   GIS_LAUNCH_CHECK("k_tile_scan");
   return GIS_OK;
 }
