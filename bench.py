@@ -158,7 +158,8 @@ def main():
     if not a.no_autotune:
         best, tuned_ms = gis.autotune(ctx, wl, repeats=3, stream=stream, precision=precision)
         schedule = {"autotuned": True, "tuned_ms_per_solve": tuned_ms, **best}
-    solver = gis.Solver(ctx, wl, stream=stream, precision=precision, timing=True)
+    # timing 1: HIP events around the build kernel only (the roofline needs them)
+    solver = gis.Solver(ctx, wl, stream=stream, precision=precision, timing=1)
 
     def step():
         sol = solver()  # gis_solve synchronises its stream before returning
@@ -178,6 +179,14 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     infos = [gis.info_dict(r) for r in raws]
+    # per-phase device times from a few more solves with events between phases
+    # (outside the timed region: each event record costs host time)
+    phased = gis.Solver(ctx, wl, stream=stream, precision=precision, timing=2)
+    phase_infos = []
+    for _ in range(3):
+        sol = phased()
+        phase_infos.append(sol.info())
+        sol.free()
 
     rows = sum(r["n_rows"] for inf in infos for r in inf["rounds"])
     flops_row = W.canonical_flops_per_row(wl.system, wl.samples)
@@ -212,7 +221,7 @@ def main():
                      "flops_per_row": flops_row},
         "schedule": schedule,
         "phases_ms_per_solve": {
-            k: sum(r[k] for inf in infos for r in inf["rounds"]) / a.steps
+            k: sum(r[k] for inf in phase_infos for r in inf["rounds"]) / len(phase_infos)
             for k in ("ms_build", "ms_image", "ms_prune", "ms_subdivide")},
         "host_ms_per_solve": {
             "busy": sum(r["ms_host"] for inf in infos for r in inf["rounds"]) / a.steps,

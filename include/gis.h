@@ -102,7 +102,8 @@ typedef struct gis_opts {
   int32_t boundary_rule;  /* GIS_BOUNDARY_* */
   int32_t analysis;       /* GIS_ANALYSIS_* */
   int32_t fast_out;       /* nonzero: OUT rows get no edges (analysis results unchanged) */
-  int32_t timing;         /* nonzero: time the image kernels with HIP events (gis_round_stats) */
+  int32_t timing;         /* HIP-event timings in gis_round_stats: 1 the build kernel (ms_image),
+                             2 also the phases (ms_build, ms_prune, ms_subdivide); 0 none */
   int32_t reserved[2];
   double band[4];         /* absolute recheck band per dimension; 0 = gis_solve calibrates
                              it on the round-0 covering (every row, or an evenly strided
@@ -136,7 +137,7 @@ typedef struct gis_solution gis_solution;
 typedef struct gis_round_stats {
   int64_t n_cells, n_rows, n_edges, n_out, n_kept, n_boundary, n_recheck;
   int32_t max_level, reserved;
-  double ms_build, ms_prune, ms_subdivide;   /* device time between HIP events */
+  double ms_build, ms_prune, ms_subdivide;   /* device time between HIP events (opts.timing 2) */
   double ms_image;    /* the one-pass build kernel: images, boxes, cover, FP64 recheck of the
                          rows that need it, CSR emit (opts.timing) */
   double ms_recheck;  /* 0: the recheck runs inside the build kernel */

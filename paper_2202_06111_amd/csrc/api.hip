@@ -632,11 +632,11 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
                                const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t sweeps,
                                hipStream_t s, const Batch* B, const uint8_t* level,
                                const int32_t* idx) {
-  (void)level;
-  (void)idx;
+  // with the batch's covering index at hand, the final pass also turns the
+  // removed cells into holes (the boundary selection reads them)
   return prune_final(row_ptr, col, out, n_cells, K, analysis, w, kept, mask, (K + 63) / 64,
                      dcnt(ctx)->n_kept, sweeps, B ? B->d_jobs : nullptr, B ? B->n_jobs : 0,
-                     B ? B->d_stats : nullptr, s);
+                     B ? B->d_stats : nullptr, B ? level : nullptr, B ? idx : nullptr, s);
 }
 
 bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
@@ -712,14 +712,14 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
   // the sweeps and the final pass: one launch sequence, replayed as a graph
   struct Key {
-    const void* p[12];
+    const void* p[14];
     int64_t n_cells, cap_edges;
     int32_t K, analysis, first, sweep_blocks, n_jobs, clear;
   } key;
   memset(&key, 0, sizeof key);
-  const void* ptrs[12] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
+  const void* ptrs[14] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
                           dcnt(ctx)->n_kept, B ? B->d_jobs : nullptr, B ? B->d_stats : nullptr,
-                          nullptr};
+                          level, idx, nullptr};
   memcpy(key.p, ptrs, sizeof ptrs);
   key.n_cells = n_cells;
   key.cap_edges = cap_edges;
@@ -806,9 +806,11 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
 // Boundary selection + next covering of a laid-out batch (index arrays built,
 // next layouts set), enqueued only (the caller cleared the counters and job
 // stats).  Writes the new global list to (lv_out, ix_out) up to cap cells.
+// holes_marked: the analysis' final pass already turned the removed cells
+// into holes of the covering index (it does for K <= 256).
 int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
                           const uint8_t* kept, int32_t rule, uint8_t* boundary, uint8_t* lv_out,
-                          int32_t* ix_out, int64_t cap, hipStream_t s) {
+                          int32_t* ix_out, int64_t cap, hipStream_t s, bool holes_marked = false) {
   int32_t rc;
   const BatchArgs ba = B.args(level, idx);
   const int64_t total = next_total(B);
@@ -818,7 +820,7 @@ int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const in
       return rc;
     ctx->next_clean = false;  // until finish_subdivide has seen the compaction complete
   }
-  if ((rc = batch_mark_dropped(ba, kept, s))) return rc;
+  if (!holes_marked && (rc = batch_mark_dropped(ba, kept, s))) return rc;
   if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
   if (total > 0) {
     if ((rc = scan_exclusive_u8((const uint8_t*)ctx->next_state.ptr, (int64_t*)ctx->pos.ptr, total,
@@ -1083,6 +1085,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   // total says so), the analysis kernels skipped their work, and the round's
   // emit, analysis and subdivision are enqueued again after the buffer grew.
   hipEvent_t* ev = ctx->ev;
+  const bool phases = o.timing >= 2;  // per-phase HIP events (each record costs host time)
   bool cur_is_A = true;
   // edges per row before the first build: a box of about one cell meets
   // 2^n cells; twice that, so that round 0 rarely has to grow the buffer
@@ -1144,19 +1147,19 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
                              &dcnt(ctx)->total_edges, (int64_t)(edges_per_row * (double)n_rows),
                              o.analysis, kept, mask, s, &B, lv, ix, sweep_hint, false)))
         return e;
-      GIS_HIP(hipEventRecord(ev[2], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[2], s));
       if (!last && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                           (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
-                                          (int32_t*)ixN.ptr, cap, s)))
+                                          (int32_t*)ixN.ptr, cap, s, K <= 256)))
         return e;
-      GIS_HIP(hipEventRecord(ev[3], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[3], s));
       return sync_stats(ctx, B, s);
     };
     if ((rc = clear_round())) return fail_all(rc);
-    GIS_HIP(hipEventRecord(ev[0], s));
+    if (phases) GIS_HIP(hipEventRecord(ev[0], s));
     if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
     if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
-    GIS_HIP(hipEventRecord(ev[1], s));
+    if (phases) GIS_HIP(hipEventRecord(ev[1], s));
     if ((rc = analyse_and_refine())) return fail_all(rc);
     if (r == 0) {
       take_bands();
@@ -1174,16 +1177,18 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       // dropped cells in it): all rebuilt for the emit
       if ((rc = clear_round())) return fail_all(rc);
       if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
-      GIS_HIP(hipEventRecord(ev[0], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[0], s));
       if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
-      GIS_HIP(hipEventRecord(ev[1], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[1], s));
       if ((rc = analyse_and_refine())) return fail_all(rc);
       if ((rc = finish_build(ctx, B, gr))) return fail_all(rc);
     }
     float ms_b = 0.f, ms_p = 0.f, ms_sub = 0.f;
-    GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
-    GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
-    GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+    if (phases) {
+      GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
+      GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
+      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+    }
     const bool conv = prune_converged(ctx, n_cells);
     if (ctx->sweep_memo.size() <= (size_t)r) ctx->sweep_memo.resize(r + 1);
     ctx->sweep_memo[r] = {n_cells, conv && ctx->first_sweeps > 0 ? ctx->h_counters->sweep_last + 1 : 0};
@@ -1208,20 +1213,22 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
           (rc = fill_u8((uint8_t*)ctx->idx_state.ptr, (uint8_t)ST_NONE, B.total_slots, s)))
         return fail_all(rc);
       if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
-      GIS_HIP(hipEventRecord(ev[1], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[1], s));
       if ((rc = continue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.n_edges,
                                gr.cap_edges, o.analysis, kept, mask, s, &B, lv, ix)))
         return fail_all(rc);
-      GIS_HIP(hipEventRecord(ev[2], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[2], s));
       if (!last && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
-                                           (int32_t*)ixN.ptr, cap, s)))
+                                           (int32_t*)ixN.ptr, cap, s, K <= 256)))
         return fail_all(rc);
-      GIS_HIP(hipEventRecord(ev[3], s));
+      if (phases) GIS_HIP(hipEventRecord(ev[3], s));
       if ((rc = sync_stats(ctx, B, s))) return fail_all(rc);
       float ms_p2 = 0.f;
-      GIS_HIP(hipEventElapsedTime(&ms_p2, ev[1], ev[2]));
-      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+      if (phases) {
+        GIS_HIP(hipEventElapsedTime(&ms_p2, ev[1], ev[2]));
+        GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+      }
       ms_p += ms_p2;
       ctx->h_counters->total_edges = keep.total_edges;
       ctx->h_counters->n_recheck = keep.n_recheck;

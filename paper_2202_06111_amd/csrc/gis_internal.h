@@ -182,6 +182,21 @@ __device__ __forceinline__ void stage_index(CoverIndex* dst, const CoverIndex* s
   __syncthreads();
 }
 
+// Slot of global cell gc in its job's covering index ci; -1 if its level or
+// multi-index is out of range.
+__device__ __forceinline__ int64_t cell_slot(const CoverIndex& ci, const uint8_t* level,
+                                             const int32_t* idx, int64_t gc) {
+  const int L = level[gc];
+  if (L > ci.lmax) return -1;
+  int64_t lin = 0;
+  for (int d = 0; d < ci.n; ++d) {
+    const int32_t v = idx[gc * ci.n + d];
+    if (v < 0 || v >= ci.dims[L][d]) return -1;
+    lin = lin * ci.dims[L][d] + v;
+  }
+  return ci.off[L] + lin;
+}
+
 // Job owning a global cell (binary search over the jobs' cell offsets).
 __device__ __forceinline__ int32_t job_of_cell(const Job* jobs, int32_t n_jobs, int64_t cell) {
   int32_t lo = 0, hi = n_jobs - 1;
@@ -281,12 +296,14 @@ int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t
                              hipStream_t s);
 // kept flags, masks (mask_words per cell) and the kept count (added to
 // *d_nkept, and per job to stats[j].n_kept when stats is set); with
-// sweeps > 0, only if sweep sweeps-1 removed nothing.
+// sweeps > 0, only if sweep sweeps-1 removed nothing.  With level (and idx)
+// set and K <= 256 it also turns every removed cell into a hole of its
+// job's covering index.
 int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
                     unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
-                    JobStats* stats, hipStream_t s);
+                    JobStats* stats, const uint8_t* level, const int32_t* idx, hipStream_t s);
 
 // k_index.hip, job-batched: covering indexes of every job's cell list (the
 // jobs' state arrays are cleared first by the caller).  Flags invalid lists in

@@ -74,21 +74,6 @@ __global__ void k_max_level(const uint8_t* level, int64_t n, uint32_t* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// Slot of local cell c of a job in the job's index; -1 if its level or
-// multi-index is out of range.
-__device__ __forceinline__ int64_t cell_slot(const CoverIndex& ci, const uint8_t* level,
-                                             const int32_t* idx, int64_t gc) {
-  const int L = level[gc];
-  if (L > ci.lmax) return -1;
-  int64_t lin = 0;
-  for (int d = 0; d < ci.n; ++d) {
-    const int32_t v = idx[gc * ci.n + d];
-    if (v < 0 || v >= ci.dims[L][d]) return -1;
-    lin = lin * ci.dims[L][d] + v;
-  }
-  return ci.off[L] + lin;
-}
-
 // Range and canonical-order checks; LEAF entries for jobs with index arrays.
 __global__ void k_leaves(BatchArgs b, uint32_t* err) {
   const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);

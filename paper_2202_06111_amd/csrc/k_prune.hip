@@ -447,7 +447,8 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
                                                      const int64_t* d_total, int64_t cap_edges,
                                                      const int32_t* last, int32_t sweeps,
                                                      const Job* jobs, int32_t n_jobs,
-                                                     JobStats* stats) {
+                                                     JobStats* stats, const uint8_t* level,
+                                                     const int32_t* idx) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
   if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
   __shared__ uint8_t ok[256];
@@ -482,6 +483,15 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
           if (k && stats) {
             if (one_job) atomicAdd(&grp_kept, 1u);
             else atomicAdd(&stats[job_of_cell(jobs, n_jobs, cc)].n_kept, 1ull);
+          }
+          // a removed cell becomes a hole of its job's covering index, which
+          // the boundary selection that follows reads
+          if (!k && level) {
+            const CoverIndex& ci = jobs[job_of_cell(jobs, n_jobs, cc)].ci;
+            if (!ci.uniform) {
+              const int64_t sl = cell_slot(ci, level, idx, cc);
+              if (sl >= 0) ci.state[sl] = ST_HOLE;
+            }
           }
         }
       }
@@ -616,14 +626,16 @@ template <int MODE>
 int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                    int64_t n_cells, int32_t K, const PruneWork& w, uint8_t* kept, uint64_t* mask,
                    int32_t W, unsigned long long* d_nkept, int32_t sweeps, const Job* jobs,
-                   int32_t n_jobs, JobStats* stats, hipStream_t s) {
+                   int32_t n_jobs, JobStats* stats, const uint8_t* level, const int32_t* idx,
+                   hipStream_t s) {
   if (K <= 256) {
     const int32_t cpb = 256 / K;
     const int64_t groups = (n_cells + cpb - 1) / cpb;
     const unsigned nb = (unsigned)(groups < 4096 ? (groups > 0 ? groups : 1) : 4096);
     hipLaunchKernelGGL((k_prune_final<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
                        n_cells, K, cpb, (const uint8_t*)w.removed, kept, mask, W, d_nkept,
-                       w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats);
+                       w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats,
+                       level, idx);
     GIS_LAUNCH_CHECK("k_prune_final");
     return GIS_OK;
   } else {
@@ -680,13 +692,15 @@ int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
                     unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
-                    JobStats* stats, hipStream_t s) {
+                    JobStats* stats, const uint8_t* level, const int32_t* idx, hipStream_t s) {
   if (n_cells == 0) return GIS_OK;
   if (analysis == GIS_ANALYSIS_NONLEAVING)
     return final_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, kept, mask,
-                                               mask_words, d_nkept, sweeps, jobs, n_jobs, stats, s);
+                                               mask_words, d_nkept, sweeps, jobs, n_jobs, stats,
+                                               level, idx, s);
   return final_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, kept, mask,
-                                             mask_words, d_nkept, sweeps, jobs, n_jobs, stats, s);
+                                             mask_words, d_nkept, sweeps, jobs, n_jobs, stats,
+                                             level, idx, s);
 }
 
 }  // namespace gis

@@ -167,14 +167,14 @@ def grid_t(grid: W.Grid) -> GridT:
 
 def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: str = W.SHELL,
            analysis: str = "controlled", fast_out: bool = False,
-           band: Optional[Sequence[float]] = None, timing: bool = False) -> OptsT:
+           band: Optional[Sequence[float]] = None, timing: int = 0) -> OptsT:
     o = OptsT()
     o.samples = SAMPLES[samples]
     o.precision = PRECISION[precision]
     o.boundary_rule = RULE[boundary_rule]
     o.analysis = ANALYSIS[analysis]
     o.fast_out = int(bool(fast_out))
-    o.timing = int(bool(timing))
+    o.timing = int(timing)
     for d, v in enumerate([] if band is None else list(band)):
         o.band[d] = float(v)
     return o
