@@ -631,12 +631,13 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
                                const uint8_t* out, int64_t n_cells, int32_t K, int32_t analysis,
                                const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t sweeps,
                                hipStream_t s, const Batch* B, const uint8_t* level,
-                               const int32_t* idx) {
+                               const int32_t* idx, bool after_frontier = false) {
   // with the batch's covering index at hand, the final pass also turns the
   // removed cells into holes (the boundary selection reads them)
   return prune_final(row_ptr, col, out, n_cells, K, analysis, w, kept, mask, (K + 63) / 64,
                      dcnt(ctx)->n_kept, sweeps, B ? B->d_jobs : nullptr, B ? B->n_jobs : 0,
-                     B ? B->d_stats : nullptr, B ? level : nullptr, B ? idx : nullptr, s);
+                     B ? B->d_stats : nullptr, B ? level : nullptr, B ? idx : nullptr,
+                     after_frontier, s);
 }
 
 bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
@@ -800,7 +801,7 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
   }
   if ((rc = fill_u32((uint32_t*)dcnt(ctx)->n_kept, 0u, 4, s))) return rc;
   return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask, 0, s,
-                                B, level, idx);
+                                B, level, idx, !converged);
 }
 
 // Boundary selection + next covering of a laid-out batch (index arrays built,

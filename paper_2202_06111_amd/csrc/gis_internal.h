@@ -298,12 +298,14 @@ int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t
 // *d_nkept, and per job to stats[j].n_kept when stats is set); with
 // sweeps > 0, only if sweep sweeps-1 removed nothing.  With level (and idx)
 // set and K <= 256 it also turns every removed cell into a hole of its
-// job's covering index.
+// job's covering index.  after_frontier: the frontier phase ran to its end,
+// so its per-row state gives the good rows (K <= 256; no target is read).
 int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
                     unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
-                    JobStats* stats, const uint8_t* level, const int32_t* idx, hipStream_t s);
+                    JobStats* stats, const uint8_t* level, const int32_t* idx,
+                    bool after_frontier, hipStream_t s);
 
 // k_index.hip, job-batched: covering indexes of every job's cell list (the
 // jobs' state arrays are cleared first by the caller).  Flags invalid lists in

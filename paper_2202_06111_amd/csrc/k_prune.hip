@@ -448,9 +448,13 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
                                                      const int32_t* last, int32_t sweeps,
                                                      const Job* jobs, int32_t n_jobs,
                                                      JobStats* stats, const uint8_t* level,
-                                                     const int32_t* idx) {
+                                                     const int32_t* idx, const void* rowinfo) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
   if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
+  // after the frontier phase its per-row state already tells which rows are
+  // good (live-target counts, or bad-row flags at c * Kp + u); otherwise
+  // every row is evaluated against the removed flags
+  const int32_t Kp = (K + 7) & ~7;
   __shared__ uint8_t ok[256];
   __shared__ unsigned int grp_kept;
   const int t = threadIdx.x;
@@ -459,8 +463,14 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
   for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
     const int64_t c = g0 + t / K;
     bool good = false;
-    if (t < cpb * K && c < n_cells && !removed[c])
-      good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
+    if (t < cpb * K && c < n_cells && !removed[c]) {
+      if (!rowinfo)
+        good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
+      else if (MODE == GIS_ANALYSIS_NONLEAVING)
+        good = ((const uint32_t*)rowinfo)[c * K + t % K] > 0;
+      else
+        good = ((const uint8_t*)rowinfo)[c * Kp + t % K] == 0;
+    }
     ok[t] = good ? 1 : 0;
     if (t == 0) grp_kept = 0;
     __syncthreads();
@@ -627,7 +637,7 @@ int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
                    int64_t n_cells, int32_t K, const PruneWork& w, uint8_t* kept, uint64_t* mask,
                    int32_t W, unsigned long long* d_nkept, int32_t sweeps, const Job* jobs,
                    int32_t n_jobs, JobStats* stats, const uint8_t* level, const int32_t* idx,
-                   hipStream_t s) {
+                   const void* rowinfo, hipStream_t s) {
   if (K <= 256) {
     const int32_t cpb = 256 / K;
     const int64_t groups = (n_cells + cpb - 1) / cpb;
@@ -635,7 +645,7 @@ int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
     hipLaunchKernelGGL((k_prune_final<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
                        n_cells, K, cpb, (const uint8_t*)w.removed, kept, mask, W, d_nkept,
                        w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats,
-                       level, idx);
+                       level, idx, rowinfo);
     GIS_LAUNCH_CHECK("k_prune_final");
     return GIS_OK;
   } else {
@@ -692,15 +702,19 @@ int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
                     unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
-                    JobStats* stats, const uint8_t* level, const int32_t* idx, hipStream_t s) {
+                    JobStats* stats, const uint8_t* level, const int32_t* idx,
+                    bool after_frontier, hipStream_t s) {
   if (n_cells == 0) return GIS_OK;
   if (analysis == GIS_ANALYSIS_NONLEAVING)
     return final_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, kept, mask,
                                                mask_words, d_nkept, sweeps, jobs, n_jobs, stats,
-                                               level, idx, s);
+                                               level, idx,
+                                               after_frontier ? (const void*)w.rowstate : nullptr,
+                                               s);
   return final_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, kept, mask,
                                              mask_words, d_nkept, sweeps, jobs, n_jobs, stats,
-                                             level, idx, s);
+                                             level, idx,
+                                             after_frontier ? (const void*)w.rowbad : nullptr, s);
 }
 
 }  // namespace gis
