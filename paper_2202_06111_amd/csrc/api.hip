@@ -15,7 +15,7 @@
 #include <utility>
 #include <vector>
 
-#include "gis_internal.h"
+#include "gis_launch.h"
 
 namespace gis {
 

@@ -1,0 +1,103 @@
+// Host launchers of the analysis, covering-index, refinement and query
+// translation units (the build kernel's unit does not include this header).
+#pragma once
+
+#include "gis_internal.h"
+
+namespace gis {
+
+// k_prune.hip
+struct PruneWork {
+  uint8_t* removed;  // [n_cells] 0 on entry to the sweeps
+  int32_t* last;     // 1 + index of the last sweep that removed a cell (0 on entry)
+  // frontier phase
+  int64_t* rptr;     // [n_cells + 1] reverse-CSR offsets
+  int32_t* rrow;     // [cap_edges] in-rows per target cell
+  int32_t* rcur;     // [n_cells] in-degree cursors: zero on entry, left zero
+  uint32_t* rowstate;  // nonleaving: [n_rows] live targets per row
+  int32_t* good;       // nonleaving: [n_cells] live rows per cell
+  uint8_t* rowbad;     // controlled: [n_cells * Kp] bad-row flags (same memory as rowstate)
+  uint8_t* cand;       // controlled: [n_cells] candidate flags (same memory as good)
+  int32_t* front;      // [2 * n_cells] the two frontier lists
+  int32_t* fcount;     // [3] rotating list lengths
+  void* scan_tmp;
+  int32_t sweep_blocks;    // grid cap of a sweep
+  int32_t front_blocks;    // grid of a frontier step
+  const int64_t* d_total;  // device edge total, or null: reverse-CSR kernels do no work
+  int64_t cap_edges;       // when *d_total > cap_edges (col was not written)
+};
+// Flags an inconsistent CSR graph in *d_err (bit 0 offsets, bit 1 targets).
+int32_t launch_check_graph(const int64_t* row_ptr, const int32_t* col, int64_t n_rows,
+                           int64_t n_edges, int64_t n_cells, uint32_t* d_err, hipStream_t s);
+// Sweeps first .. first+count-1 (K <= 256).  Converged when *last < first+count.
+int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                     int32_t first, int32_t count, hipStream_t s);
+// Reverse CSR, the counters from the current removed flags, and the first
+// frontier (present cells without a good row); fcount[0] = its length.
+int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                             int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                             hipStream_t s);
+// Frontier steps first .. first+count-1; step t takes list t & 1 with length
+// fcount[t % 3].  Done when fcount[(first+count) % 3] == 0.
+int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                             int32_t analysis, const PruneWork& w, int32_t first, int32_t count,
+                             hipStream_t s);
+// kept flags, masks (mask_words per cell) and the kept count (added to
+// *d_nkept, and per job to stats[j].n_kept when stats is set); with
+// sweeps > 0, only if sweep sweeps-1 removed nothing.  With level (and idx)
+// set and K <= 256 it also turns every removed cell into a hole of its
+// job's covering index.  after_frontier: the frontier phase ran to its end,
+// so its per-row state gives the good rows (K <= 256; no target is read).
+int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                    int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
+                    uint8_t* kept, uint64_t* mask, int32_t mask_words,
+                    unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
+                    JobStats* stats, const uint8_t* level, const int32_t* idx,
+                    bool after_frontier, hipStream_t s);
+
+// k_index.hip, job-batched: covering indexes of every job's cell list (the
+// jobs' state arrays are cleared first by the caller).  Flags invalid lists in
+// *d_err (bit 0: index out of range, bit 1: not canonical / duplicate,
+// bit 2: overlapping cells).  Jobs whose ci.uniform is set only get checked.
+struct BatchArgs {
+  const Job* jobs;
+  int32_t n_jobs;
+  int32_t n;              // state dimension
+  int32_t K;
+  const uint8_t* level;   // global cell list
+  const int32_t* idx;
+  int64_t blocks[LK_KINDS];
+};
+// ... and the prefix counts of the jobs with index arrays: pfx_all receives
+// total_slots + 1 values over the batch's concatenated state arrays state_all.
+// Without `validate` the list is taken as valid (produced by the library)
+// and no check is made.
+int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, const uint8_t* state_all,
+                          int64_t* pfx_all, int64_t total_slots, void* scan_tmp, bool validate,
+                          hipStream_t s);
+int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t s);
+
+// k_refine.hip, job-batched
+// Boundary flags of the kept cells (Sec. 3.1.1) and, for jobs with a next
+// layout, the next-covering flags (those arrays are zero on entry;
+// batch_compact leaves them zero again).
+int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
+                       JobStats* stats, hipStream_t s);
+// pos: exclusive scan of the batch's next-flag array; writes the new global
+// cell list (up to cap) and each job's next_start / level_start.
+int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,
+                      int32_t* idx_out, JobStats* stats, hipStream_t s);
+int32_t batch_coarse(const BatchArgs& b, uint8_t* level, int32_t* idx, hipStream_t s);
+// Kept cells per job into stats[j].n_kept.
+int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stats, hipStream_t s);
+// The same from the job table alone (any launch layout).
+int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
+                               const uint8_t* kept, JobStats* stats, hipStream_t s);
+
+// k_query.hip
+int32_t launch_query(const CoverIndex& ci, const GridArgs& g, const uint8_t* kept,
+                     const uint64_t* mask, int32_t mask_words, const double* states, int64_t n,
+                     uint8_t* member, uint64_t* adm, hipStream_t s);
+
+}  // namespace gis

@@ -9,7 +9,7 @@
 // level, and "is this finest cell covered" into a walk over at most lmax + 1
 // levels, with no search structure to build (the role the paper gives an
 // R*-tree, Sec. 2.4).
-#include "gis_internal.h"
+#include "gis_launch.h"
 
 namespace gis {
 

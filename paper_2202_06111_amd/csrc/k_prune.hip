@@ -17,7 +17,7 @@
 //              per-row and per-cell counters (every removal once).
 // The host runs a batch of sweeps and switches to the frontier phase when
 // they have not converged.  The final pass writes kept flags and masks.
-#include "gis_internal.h"
+#include "gis_launch.h"
 
 namespace gis {
 

@@ -2,7 +2,7 @@
 // inputs are admissible in its cell.  A state in X maps to the finest-level
 // cell floor((x - lo) / w) (the last cell for x = hi); the covering index walk
 // then finds the leaf that contains it, if any.
-#include "gis_internal.h"
+#include "gis_launch.h"
 
 namespace gis {
 

@@ -12,7 +12,7 @@
 // 2^n children of a boundary cell) sets a flag in a dense per-level array laid
 // out like the covering index; a scan of the flags in level-major, row-major
 // order is exactly the canonical numbering of the new cell list.
-#include "gis_internal.h"
+#include "gis_launch.h"
 
 namespace gis {
 
