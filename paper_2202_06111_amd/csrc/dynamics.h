@@ -19,6 +19,32 @@ namespace gis {
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Minimum and maximum as single VALU instructions.  fmin/fmax compile to the
+// same instructions preceded by a copy of each operand that quiets signalling
+// NaNs (the compiler cannot see that loop-carried values are already quiet),
+// three extra instructions per coordinate and sample.  A NaN image is decided
+// by the caller's finiteness test either way.
+__device__ __forceinline__ double vmin(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmax(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Vector field g(x, u) of x' = g(x, u).  N is the state dimension; m (inputs)
 // is only a runtime value for the linear field.
 template <int KIND, int N, typename R>

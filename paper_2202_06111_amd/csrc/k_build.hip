@@ -217,8 +217,8 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
           // for NaN (the row is then decided by `finite`) and in the sign of
           // a zero (which changes no cover decision: (-0) - lo == (+0) - lo)
           finite &= isfinite(x[i][d]);
-          bl[d] = fmin(x[i][d], bl[d]);
-          bh[d] = fmax(x[i][d], bh[d]);
+          bl[d] = vmin(x[i][d], bl[d]);
+          bh[d] = vmax(x[i][d], bh[d]);
         }
       }
   }
@@ -305,12 +305,16 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
     // the last dimension are consecutive, so the id is recomputed only when
     // a slower coordinate moves
     int32_t k[N];
-    int32_t rem = p0;
 #pragma unroll
-    for (int d = N - 1; d >= 0; --d) {
-      const int32_t w = hi[d] - lo[d] + 1;
-      k[d] = lo[d] + rem % w;
-      rem /= w;
+    for (int d = 0; d < N; ++d) k[d] = lo[d];
+    if (p0 > 0) {  // only rows that straddle a tile boundary divide
+      int32_t rem = p0;
+#pragma unroll
+      for (int d = N - 1; d >= 0; --d) {
+        const int32_t w = hi[d] - lo[d] + 1;
+        k[d] += rem % w;
+        rem /= w;
+      }
     }
     auto lin_of = [&]() {
       int32_t lin = 0;
