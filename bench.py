@@ -13,7 +13,7 @@ continuous-batching server and reports solves/s and p50/p99 latency.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--precision fp64|fp32_recheck] [--no-cpu-baseline]
-                       [--no-autotune] [--serve-requests N]
+                       [--no-autotune] [--tuning field=value,...] [--serve-requests N]
 
 Before the warm-up, the library's autotuner picks the schedule parameters
 (sweep and frontier batching, grid shapes) for the workload by timing whole
@@ -50,6 +50,9 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default schedule parameters instead of running the autotuner "
                         "(gis_autotune, untimed, before the warm-up)")
+    p.add_argument("--tuning", default="",
+                   help="schedule parameters to start from, as field=value[,field=value...] "
+                        "(fields of gis_tuning)")
     p.add_argument("--cpu-budget-s", type=float, default=12.0)
     p.add_argument("--serve-requests", type=int, default=64,
                    help="requests per pass of the serving measurement (0: skip it)")
@@ -154,6 +157,8 @@ def main():
     ctx = gis.Context(0)
     # a stream of its own (default priority): the null stream cannot be captured as a graph
     stream = torch.cuda.Stream()
+    if a.tuning:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in a.tuning.split(","))})
     schedule = {"autotuned": False, **ctx.get_tuning()}
     if not a.no_autotune:
         best, tuned_ms = gis.autotune(ctx, wl, repeats=3, stream=stream, precision=precision)

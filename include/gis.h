@@ -178,7 +178,9 @@ typedef struct gis_tuning {
   int32_t edge_hint;       /* edges per row assumed for the first build of a solve, which
                               sizes the edge buffer (0: 2^(n+1)); too small a value costs
                               one rebuild of that round, never a wrong result (0..4096) */
-  int32_t reserved;
+  int32_t row_frontier;    /* nonzero: the frontier phase keeps one reverse entry per (row,
+                              target) also for K <= 64 inputs, instead of one per (source
+                              cell, target) with an input mask [0] (0..1) */
 } gis_tuning;
 
 /* Reads / replaces the context's schedule parameters.  GIS_E_INVAL when a

@@ -64,6 +64,7 @@ struct Counters {
   int64_t n_next;
   int32_t sweep_last;  // analysis: 1 + index of the last sweep that removed a cell
   int32_t fcount[3];   // analysis: frontier list lengths (rotating)
+  int64_t rc_entries;  // analysis: entries of the cell-grouped reverse graph
 };
 
 // Pinned host staging of a device array of T.
@@ -133,7 +134,7 @@ struct gis_ctx {
   GraphCache graphs;
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
-  DevBuf removed, rptr, rrow, rcur, rowstate, good, front;
+  DevBuf removed, rptr, rrow, rmask, rcur, rowstate, good, front;
   DevBuf bnd;
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
@@ -617,6 +618,9 @@ PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   w.good = (int32_t*)ctx->good.ptr;
   w.rowbad = (uint8_t*)ctx->rowstate.ptr;
   w.cand = (uint8_t*)ctx->good.ptr;
+  w.rsrc = (int32_t*)ctx->rrow.ptr;
+  w.rmask = (uint64_t*)ctx->rmask.ptr;
+  w.badmask = (uint64_t*)ctx->rowstate.ptr;
   w.front = (int32_t*)ctx->front.ptr;
   w.fcount = dcnt(ctx)->fcount;
   w.scan_tmp = ctx->scan_tmp.ptr;
@@ -631,13 +635,13 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
                                const uint8_t* out, int64_t n_cells, int32_t K, int32_t analysis,
                                const PruneWork& w, uint8_t* kept, uint64_t* mask, int32_t sweeps,
                                hipStream_t s, const Batch* B, const uint8_t* level,
-                               const int32_t* idx, bool after_frontier = false) {
+                               const int32_t* idx, int32_t frontier = 0) {
   // with the batch's covering index at hand, the final pass also turns the
   // removed cells into holes (the boundary selection reads them)
   return prune_final(row_ptr, col, out, n_cells, K, analysis, w, kept, mask, (K + 63) / 64,
                      dcnt(ctx)->n_kept, sweeps, B ? B->d_jobs : nullptr, B ? B->n_jobs : 0,
                      B ? B->d_stats : nullptr, B ? level : nullptr, B ? idx : nullptr,
-                     after_frontier, s);
+                     frontier, s);
 }
 
 bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
@@ -762,7 +766,11 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
   int32_t done = 0;
   bool converged = false;
   const int32_t batch = ctx->tune.sweep_batch, fbatch = ctx->tune.frontier_batch;
+  // cells can be removed before the frontier phase only by sweeps (the
+  // callers clear the removed flags before the analysis)
+  bool any_removed = ctx->first_sweeps > 0;
   if (sweeps_fit(ctx, n_edges, K)) {
+    any_removed = true;
     for (; done < kMaxSweeps && !converged; done += batch) {
       if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, done, batch, s)))
         return rc;
@@ -770,6 +778,9 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
       converged = ctx->h_counters->sweep_last < done + batch;
     }
   }
+  // the frontier phase groups reverse entries by source cell unless K > 64
+  // or the tuning asks for one entry per row
+  const bool cells = K <= 64 && !ctx->tune.row_frontier;
   if (!converged) {
     bool fresh = false;
     if ((rc = ensure(ctx->rptr, (size_t)(n_cells + 1) * 8)) ||
@@ -786,9 +797,22 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
       if ((rc = fill_i32(w.rcur, 0, (int64_t)(ctx->rcur.bytes / 4), s))) return rc;
     }
     ctx->prune_clean = false;  // until the frontier has run out
-    if ((rc = prune_frontier_start(row_ptr, col, out, n_cells, K, analysis, w, s))) return rc;
+    if (cells) {
+      // the entry count sizes the masks: read it back before the scatter
+      if ((rc = cells_start(row_ptr, col, n_cells, K, any_removed, w, s))) return rc;
+      GIS_HIP(hipMemcpyAsync(&ctx->h_counters->rc_entries, w.rptr + n_cells, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+      if ((rc = wait_stream(ctx, s))) return rc;
+      if ((rc = ensure(ctx->rmask, (size_t)ctx->h_counters->rc_entries * 8 + 16))) return rc;
+      w = prune_work(ctx, cap_edges, nullptr);
+      if ((rc = cells_scatter(row_ptr, col, out, n_cells, K, analysis, any_removed, w, s)))
+        return rc;
+    } else if ((rc = prune_frontier_start(row_ptr, col, out, n_cells, K, analysis, w, s))) {
+      return rc;
+    }
     for (int32_t t = 0;; t += fbatch) {
-      if ((rc = prune_frontier_steps(row_ptr, col, n_cells, K, analysis, w, t, fbatch, s)))
+      if ((rc = cells ? cells_steps(n_cells, K, analysis, w, t, fbatch, s)
+                      : prune_frontier_steps(row_ptr, col, n_cells, K, analysis, w, t, fbatch, s)))
         return rc;
       if ((rc = sync_counters(ctx, s))) return rc;
       if (ctx->h_counters->fcount[(t + fbatch) % 3] == 0) break;
@@ -801,7 +825,8 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
   }
   if ((rc = fill_u32((uint32_t*)dcnt(ctx)->n_kept, 0u, 4, s))) return rc;
   return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask, 0, s,
-                                B, level, idx, !converged);
+                                B, level, idx,
+                                converged ? 0 : cells ? kCellFrontier : kRowFrontier);
 }
 
 // Boundary selection + next covering of a laid-out batch (index arrays built,
@@ -1354,8 +1379,9 @@ void gis_ctx_destroy(gis_ctx* c) {
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&c->counters, &c->jobs, &c->maxerr, &c->lookback, &c->scan_tmp,
                     &c->idx_state, &c->idx_pfx,
-                    &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rcur,
-                    &c->rowstate, &c->good, &c->front, &c->bnd, &c->lvA, &c->ixA, &c->lvB, &c->ixB,
+                    &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rmask,
+                    &c->rcur, &c->rowstate, &c->good, &c->front, &c->bnd, &c->lvA, &c->ixA,
+                    &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
   for (DevBuf* b : bufs) release(*b);
   for (auto& kv : c->graphs.map)
@@ -1381,7 +1407,8 @@ int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* t) {
   auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
   if (!in(t->first_sweeps, 1, 256) || !in(t->sweep_batch, 1, 256) || t->sweep_edges < 0 ||
       !in(t->frontier_batch, 1, 256) || !in(t->sweep_blocks, 1, 65536) ||
-      !in(t->front_blocks, 1, 65536) || !in(t->edge_hint, 0, 4096))
+      !in(t->front_blocks, 1, 65536) || !in(t->edge_hint, 0, 4096) ||
+      !in(t->row_frontier, 0, 1))
     return inval("tuning field out of range");
   ctx->tune = *t;
   return GIS_OK;
@@ -1613,6 +1640,8 @@ int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
        [](gis_tuning& t, int64_t v) { t.front_blocks = (int32_t)v; }, {1024, 4096, 16384}},
       {[](const gis_tuning& t) { return (int64_t)t.use_graphs; },
        [](gis_tuning& t, int64_t v) { t.use_graphs = (int32_t)v; }, {0, 1}},
+      {[](const gis_tuning& t) { return (int64_t)t.row_frontier; },
+       [](gis_tuning& t, int64_t v) { t.row_frontier = (int32_t)v; }, {0, 1}},
   };
   for (const Field& f : fields) {
     for (int64_t v : f.values) {

@@ -1,10 +1,30 @@
 // Host launchers of the analysis, covering-index, refinement and query
-// translation units (the build kernel's unit does not include this header).
+// translation units, and device helpers of the analysis kernels (the build
+// kernel's unit does not include this header).
 #pragma once
 
 #include "gis_internal.h"
 
 namespace gis {
+
+// Appends v to list for every thread with add set, with one global atomic
+// per block (a frontier list's counter is shared by the whole device, and
+// per-wave atomics on it serialise).  Every thread of the block must call it
+// the same number of times.
+__device__ __forceinline__ void append_block(bool add, int32_t v, int32_t* list, int32_t* count) {
+  __shared__ int32_t s_cnt, s_base;
+  const uint64_t m = __ballot(add);
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int32_t woff = 0;
+  if (lane == 0 && m) woff = atomicAdd(&s_cnt, (int32_t)__popcll(m));
+  woff = __shfl(woff, 0, 64);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(count, s_cnt);
+  __syncthreads();
+  if (add) list[s_base + woff + __popcll(m & ((1ull << lane) - 1))] = v;
+}
 
 // k_prune.hip
 struct PruneWork {
@@ -18,6 +38,11 @@ struct PruneWork {
   int32_t* good;       // nonleaving: [n_cells] live rows per cell
   uint8_t* rowbad;     // controlled: [n_cells * Kp] bad-row flags (same memory as rowstate)
   uint8_t* cand;       // controlled: [n_cells] candidate flags (same memory as good)
+  // cell-grouped frontier (K <= 64): one reverse entry per (source cell,
+  // target) with the inputs whose rows meet the target as a bit mask
+  int32_t* rsrc;       // [entries] source cells (same memory as rrow)
+  uint64_t* rmask;     // [entries] input masks
+  uint64_t* badmask;   // controlled: [n_cells] bad rows of each cell (same memory as rowstate)
   int32_t* front;      // [2 * n_cells] the two frontier lists
   int32_t* fcount;     // [3] rotating list lengths
   void* scan_tmp;
@@ -47,14 +72,32 @@ int32_t prune_frontier_steps(const int64_t* row_ptr, const int32_t* col, int64_t
 // *d_nkept, and per job to stats[j].n_kept when stats is set); with
 // sweeps > 0, only if sweep sweeps-1 removed nothing.  With level (and idx)
 // set and K <= 256 it also turns every removed cell into a hole of its
-// job's covering index.  after_frontier: the frontier phase ran to its end,
-// so its per-row state gives the good rows (K <= 256; no target is read).
+// job's covering index.  frontier: kRowFrontier or kCellFrontier when that
+// frontier phase ran to its end, whose state then gives the good rows (K <=
+// 256; no target is read); 0 when the sweeps converged.
+constexpr int32_t kRowFrontier = 1, kCellFrontier = 2;
 int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
                     unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
-                    JobStats* stats, const uint8_t* level, const int32_t* idx,
-                    bool after_frontier, hipStream_t s);
+                    JobStats* stats, const uint8_t* level, const int32_t* idx, int32_t frontier,
+                    hipStream_t s);
+
+// k_frontier.hip: the frontier phase over the cell-grouped reverse graph
+// (1 <= K <= 64).  cells_start: the reverse-graph entry counts per target
+// into rcur (zero on entry) and the reverse offsets rptr (entry total at
+// rptr[n_cells]).  cells_scatter, once rsrc/rmask hold that many entries,
+// fills them (rcur is left zero) and sets the analysis state from the current
+// removed flags and the first frontier (fcount[0]).  cells_steps: frontier
+// steps t0 .. t0+count-1, with the list conventions of prune_frontier_steps.
+// any_removed: some removed flag may be set (otherwise they are not read).
+int32_t cells_start(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                    bool any_removed, const PruneWork& w, hipStream_t s);
+int32_t cells_scatter(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                      int64_t n_cells, int32_t K, int32_t analysis, bool any_removed,
+                      const PruneWork& w, hipStream_t s);
+int32_t cells_steps(int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w, int32_t t0,
+                    int32_t count, hipStream_t s);
 
 // k_index.hip, job-batched: covering indexes of every job's cell list (the
 // jobs' state arrays are cleared first by the caller).  Flags invalid lists in

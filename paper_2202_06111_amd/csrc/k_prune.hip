@@ -229,24 +229,6 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
 //   removal exactly once, in one launch per step:
 //   rowstate[r] = targets of r not yet removed, good[c] = rows of c alive.
 
-// Appends v to list for every thread with add set, with one global atomic
-// per block (a frontier list's counter is shared by the whole device, and
-// per-wave atomics on it serialise).  Every thread of the block must call it
-// the same number of times.
-__device__ __forceinline__ void append_block(bool add, int32_t v, int32_t* list, int32_t* count) {
-  __shared__ int32_t s_cnt, s_base;
-  const uint64_t m = __ballot(add);
-  const int lane = threadIdx.x & 63;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  int32_t woff = 0;
-  if (lane == 0 && m) woff = atomicAdd(&s_cnt, (int32_t)__popcll(m));
-  woff = __shfl(woff, 0, 64);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(count, s_cnt);
-  __syncthreads();
-  if (add) list[s_base + woff + __popcll(m & ((1ull << lane) - 1))] = v;
-}
 
 // controlled, initial state: a row is bad when OUT; a cell with every row
 // bad is removed; the first frontier is every removed cell (also those the
@@ -448,12 +430,14 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
                                                      const int32_t* last, int32_t sweeps,
                                                      const Job* jobs, int32_t n_jobs,
                                                      JobStats* stats, const uint8_t* level,
-                                                     const int32_t* idx, const void* rowinfo) {
+                                                     const int32_t* idx, const void* rowinfo,
+                                                     int32_t frontier) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
   if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
-  // after the frontier phase its per-row state already tells which rows are
-  // good (live-target counts, or bad-row flags at c * Kp + u); otherwise
-  // every row is evaluated against the removed flags
+  // after the frontier phase its state already tells which rows are good
+  // (live-target counts per row; controlled: bad-row flags at c * Kp + u, or
+  // a bad-row mask per cell); otherwise every row is evaluated against the
+  // removed flags
   const int32_t Kp = (K + 7) & ~7;
   __shared__ uint8_t ok[256];
   __shared__ unsigned int grp_kept;
@@ -468,6 +452,8 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
         good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
       else if (MODE == GIS_ANALYSIS_NONLEAVING)
         good = ((const uint32_t*)rowinfo)[c * K + t % K] > 0;
+      else if (frontier == kCellFrontier)
+        good = ((((const uint64_t*)rowinfo)[c] >> (t % K)) & 1) == 0;
       else
         good = ((const uint8_t*)rowinfo)[c * Kp + t % K] == 0;
     }
@@ -637,7 +623,7 @@ int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
                    int64_t n_cells, int32_t K, const PruneWork& w, uint8_t* kept, uint64_t* mask,
                    int32_t W, unsigned long long* d_nkept, int32_t sweeps, const Job* jobs,
                    int32_t n_jobs, JobStats* stats, const uint8_t* level, const int32_t* idx,
-                   const void* rowinfo, hipStream_t s) {
+                   const void* rowinfo, int32_t frontier, hipStream_t s) {
   if (K <= 256) {
     const int32_t cpb = 256 / K;
     const int64_t groups = (n_cells + cpb - 1) / cpb;
@@ -645,7 +631,7 @@ int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
     hipLaunchKernelGGL((k_prune_final<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
                        n_cells, K, cpb, (const uint8_t*)w.removed, kept, mask, W, d_nkept,
                        w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats,
-                       level, idx, rowinfo);
+                       level, idx, rowinfo, frontier);
     GIS_LAUNCH_CHECK("k_prune_final");
     return GIS_OK;
   } else {
@@ -702,19 +688,19 @@ int32_t prune_final(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
                     int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                     uint8_t* kept, uint64_t* mask, int32_t mask_words,
                     unsigned long long* d_nkept, int32_t sweeps, const Job* jobs, int32_t n_jobs,
-                    JobStats* stats, const uint8_t* level, const int32_t* idx,
-                    bool after_frontier, hipStream_t s) {
+                    JobStats* stats, const uint8_t* level, const int32_t* idx, int32_t frontier,
+                    hipStream_t s) {
   if (n_cells == 0) return GIS_OK;
   if (analysis == GIS_ANALYSIS_NONLEAVING)
-    return final_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, kept, mask,
-                                               mask_words, d_nkept, sweeps, jobs, n_jobs, stats,
-                                               level, idx,
-                                               after_frontier ? (const void*)w.rowstate : nullptr,
-                                               s);
+    return final_mode<GIS_ANALYSIS_NONLEAVING>(
+        row_ptr, col, out, n_cells, K, w, kept, mask, mask_words, d_nkept, sweeps, jobs, n_jobs,
+        stats, level, idx, frontier ? (const void*)w.rowstate : nullptr, frontier, s);
+  const void* info = frontier == kCellFrontier ? (const void*)w.badmask
+                     : frontier                ? (const void*)w.rowbad
+                                               : nullptr;
   return final_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, kept, mask,
                                              mask_words, d_nkept, sweeps, jobs, n_jobs, stats,
-                                             level, idx,
-                                             after_frontier ? (const void*)w.rowbad : nullptr, s);
+                                             level, idx, info, frontier, s);
 }
 
 }  // namespace gis

@@ -58,11 +58,11 @@ class GraphT(ctypes.Structure):
 class TuningT(ctypes.Structure):
     _fields_ = [("first_sweeps", I32), ("sweep_batch", I32), ("sweep_edges", I64),
                 ("frontier_batch", I32), ("sweep_blocks", I32), ("front_blocks", I32),
-                ("use_graphs", I32), ("edge_hint", I32), ("reserved", I32)]
+                ("use_graphs", I32), ("edge_hint", I32), ("row_frontier", I32)]
 
 
 TUNING_FIELDS = ("first_sweeps", "sweep_batch", "sweep_edges", "frontier_batch", "sweep_blocks",
-                 "front_blocks", "use_graphs", "edge_hint")
+                 "front_blocks", "use_graphs", "edge_hint", "row_frontier")
 
 
 class JobT(ctypes.Structure):

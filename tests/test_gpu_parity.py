@@ -166,6 +166,7 @@ def test_prune_deep_peel(G, ctx):
 # one-block grids all give the oracle's fixed point.
 TUNINGS = {
     "frontier_only": dict(sweep_edges=0),
+    "row_frontier_only": dict(sweep_edges=0, row_frontier=1),
     "one_sweep_per_check": dict(first_sweeps=1, sweep_batch=1),
     "tiny_grids": dict(sweep_edges=0, front_blocks=1, frontier_batch=1),
     "tiny_sweep_grid": dict(sweep_blocks=1, first_sweeps=3, sweep_batch=2),
@@ -237,7 +238,122 @@ def test_prune_wide_inputs_random_graph(G, ctx, analysis):
     assert nk == int(kept_w.sum())
 
 
-@pytest.mark.parametrize("tuning", ["frontier_only", "one_sweep_per_check", "tiny_grids"])
+def _cascade_graph(K, max_targets, seed):
+    """A seeded random graph with long removal chains: row (c, u) targets a
+    window of cells ahead of c (every id of the window twice, so rows repeat
+    targets), the last 200 cells have OUT rows without targets, every 97th
+    cell keeps one row pointing at itself, and 5% of the other rows are OUT."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_cells = 3000
+    n_rows = n_cells * K
+    cell = np.arange(n_rows) // K
+    u = np.arange(n_rows) % K
+    cnt = rng.integers(1, max_targets + 1, size=n_rows)
+    sink = cell >= n_cells - 200
+    loop = (cell % 97 == 0) & (u == 0)
+    cnt[sink] = 0
+    cnt[loop] = 1
+    row_ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    start = np.where(loop, cell, cell + 1 + (u % 3))
+    k = np.arange(row_ptr[-1]) - np.repeat(row_ptr[:-1], cnt)
+    col = np.clip(np.repeat(start, cnt) + k // 2 * 2, 0, n_cells - 1).astype(np.int32)
+    out = ((rng.random(n_rows) < 0.05) | sink).astype(np.uint8)
+    out[loop] = 0
+    return row_ptr, col, out, n_cells
+
+
+@pytest.mark.parametrize("K,max_targets,shuffled", [(1, 40, False), (2, 60, False),
+                                                    (5, 6, False), (33, 4, False),
+                                                    (64, 3, False), (5, 6, True)])
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+@pytest.mark.parametrize("row_frontier", [0, 1])
+def test_prune_frontier_cascade_graph(G, ctx, analysis, K, max_targets, shuffled, row_frontier):
+    """The frontier phase alone (up to a few hundred steps), with one reverse
+    entry per (source cell, target) or per (row, target).
+    K = 1 and K = 2 give blocks with more distinct (cell, target) pairs than
+    the block's LDS table holds (its per-edge fallback); K = 64 fills a whole
+    input mask; rows may repeat targets and (shuffled) list them in any
+    order."""
+    row_ptr, col, out, n_cells = _cascade_graph(K, max_targets, 100 + K)
+    if shuffled:
+        rng = np.random.Generator(np.random.PCG64(7))
+        for r in range(n_cells * K):
+            rng.shuffle(col[row_ptr[r]:row_ptr[r + 1]])
+    n_rows = n_cells * K
+    kept_w, mask_w, iters = oracle.prune(row_ptr, col, out, n_cells, K, analysis)
+    assert 0 < kept_w.sum() < n_cells
+    dev = ctx.dev
+    g = G.Graph(torch.as_tensor(row_ptr, device=dev), torch.as_tensor(col, device=dev),
+                torch.as_tensor(out, device=dev), n_rows, int(col.shape[0]), int(out.sum()), 0)
+    prev = ctx.set_tuning(sweep_edges=0, row_frontier=row_frontier)
+    try:
+        kept, mask, nk = G.prune(ctx, g, n_cells, K, analysis)
+    finally:
+        ctx.set_tuning(**prev)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+    assert nk == int(kept_w.sum())
+
+
+def _zigzag_chains(L):
+    """Two chains of L cells each (K = 2): row (c, 0) of every chain cell
+    targets the cell before it, row (c, 1) is OUT without targets; chain A
+    starts at a dead cell, chain B at a cell whose row 0 targets itself.
+    Consecutive chain cells sit at opposite ends of the numbering, so an
+    in-place sweep moves a removal by only a link or two and the sweeps give
+    up (after 256 of them) long before chain A has died."""
+    n_cells, K = 2 * L, 2
+    lo, hi, order = 0, n_cells - 1, []
+    for k in range(n_cells):
+        if k % 2 == 0:
+            order.append(lo)
+            lo += 1
+        else:
+            order.append(hi)
+            hi -= 1
+    order = np.array(order)
+    tgt = [[] for _ in range(n_cells * K)]
+    out = np.zeros(n_cells * K, np.uint8)
+    for chain, pos in (("A", order[0::2]), ("B", order[1::2])):
+        for k in range(L):
+            c = int(pos[k])
+            out[c * K + 1] = 1
+            if k > 0:
+                tgt[c * K].append(int(pos[k - 1]))
+            elif chain == "A":
+                out[c * K] = 1
+            else:
+                tgt[c * K].append(c)
+    cnt = np.array([len(t) for t in tgt])
+    row_ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    col = np.array([j for t in tgt for j in t], np.int32)
+    return row_ptr, col, out, n_cells, K
+
+
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+@pytest.mark.parametrize("row_frontier", [0, 1])
+def test_prune_sweeps_then_frontier(G, ctx, analysis, row_frontier):
+    """The frontier phase taking over from sweeps that have removed cells
+    already: its initial state must account for removed targets."""
+    row_ptr, col, out, n_cells, K = _zigzag_chains(1500)
+    kept_w, mask_w, iters = oracle.prune(row_ptr, col, out, n_cells, K, analysis)
+    assert iters == 1500 and kept_w.sum() == 1500
+    dev = ctx.dev
+    g = G.Graph(torch.as_tensor(row_ptr, device=dev), torch.as_tensor(col, device=dev),
+                torch.as_tensor(out, device=dev), n_cells * K, int(col.shape[0]), int(out.sum()),
+                0)
+    prev = ctx.set_tuning(row_frontier=row_frontier)
+    try:
+        kept, mask, nk = G.prune(ctx, g, n_cells, K, analysis)
+    finally:
+        ctx.set_tuning(**prev)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+    assert nk == 1500
+
+
+@pytest.mark.parametrize("tuning", ["frontier_only", "row_frontier_only", "one_sweep_per_check",
+                                    "tiny_grids"])
 def test_solve_adaptive_tunings(G, ctx, tuning):
     prev = ctx.set_tuning(**TUNINGS[tuning])
     try:
@@ -294,7 +410,8 @@ def test_tuning_rejects_out_of_range(G, ctx):
     before = ctx.get_tuning()
     for bad in (dict(first_sweeps=0), dict(sweep_batch=300), dict(sweep_edges=-1),
                 dict(front_blocks=0), dict(sweep_blocks=70000), dict(frontier_batch=0),
-                dict(edge_hint=-1), dict(edge_hint=5000)):
+                dict(edge_hint=-1), dict(edge_hint=5000), dict(row_frontier=2),
+                dict(row_frontier=-1)):
         with pytest.raises(G.GisError):
             ctx.set_tuning(**bad)
         assert ctx.get_tuning() == before
