@@ -5,8 +5,8 @@
 // targets: their images start from the same sample points.  The reverse graph
 // therefore keeps one entry per (source cell c, target j) carrying the set of
 // inputs u whose row (c, u) meets j as a 64-bit mask, instead of one entry per
-// (row, target).  On a uniform Lorenz-type grid with 21 inputs this is about a
-// tenth of the entries.  The fixed point is the one the sweeps reach (the
+// (row, target).  On a uniform Lorenz-type grid with 21 inputs this is a
+// seventeenth of the entries.  The fixed point is the one the sweeps reach (the
 // greatest fixed point of the monotone removal operator, Sec. 2.3); only the
 // order of the removals differs.
 //

@@ -439,9 +439,12 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
   // a bad-row mask per cell); otherwise every row is evaluated against the
   // removed flags
   const int32_t Kp = (K + 7) & ~7;
-  __shared__ uint8_t ok[256];
+  __shared__ uint64_t okw[5];  // the waves' good-row ballots (+ a zero word)
   __shared__ unsigned int grp_kept;
+  __shared__ CoverIndex sci;   // covering index of job s_job, for the hole marking
+  __shared__ int32_t s_job;
   const int t = threadIdx.x;
+  if (t == 0) s_job = -1;
   unsigned long long mine = 0;
   const int64_t stride = (int64_t)gridDim.x * cpb;
   for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
@@ -457,21 +460,33 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
       else
         good = ((const uint8_t*)rowinfo)[c * Kp + t % K] == 0;
     }
-    ok[t] = good ? 1 : 0;
-    if (t == 0) grp_kept = 0;
-    __syncthreads();
-    // per-job kept counts: one atomic per group when the group lies in one job
+    const uint64_t bal = __ballot(good);
+    if ((t & 63) == 0) okw[t >> 6] = bal;
+    if (t == 0) {
+      grp_kept = 0;
+      okw[4] = 0;
+    }
+    // the group's job: one atomic for its kept count, and its covering index
+    // staged in LDS for the hole marking, when the group lies in one job
     const int64_t glast = g0 + cpb - 1 < n_cells ? g0 + cpb - 1 : n_cells - 1;
-    const int32_t jfirst = stats ? job_of_cell(jobs, n_jobs, g0) : 0;
-    const bool one_job = stats && job_of_cell(jobs, n_jobs, glast) == jfirst;
+    const bool need_job = stats || level;
+    const int32_t jfirst = need_job ? job_of_cell(jobs, n_jobs, g0) : 0;
+    const bool one_job = need_job && job_of_cell(jobs, n_jobs, glast) == jfirst;
+    if (level && one_job && jfirst != s_job) stage_index(&sci, &jobs[jfirst].ci);
+    __syncthreads();
+    if (t == 0 && level && one_job) s_job = jfirst;
     if (t < cpb * W) {
       const int64_t cc = g0 + t / W;
       const int w = t % W;
       if (cc < n_cells) {
         const bool k = !removed[cc];
-        uint64_t m = 0;
-        const int j0 = (t / W) * K + w * 64;
-        for (int b = 0; b < 64 && w * 64 + b < K; ++b) m |= (uint64_t)ok[j0 + b] << b;
+        // bits [p, p + nb) of the block's ballots: the cell's rows of word w
+        const int p = (t / W) * K + w * 64;
+        const int nb = K - w * 64 < 64 ? K - w * 64 : 64;
+        const int q = p >> 6, sh = p & 63;
+        uint64_t m = okw[q] >> sh;
+        if (sh) m |= okw[q + 1] << (64 - sh);
+        if (nb < 64) m &= (1ull << nb) - 1;
         mask[cc * W + w] = m;
         if (w == 0) {
           kept[cc] = k ? 1 : 0;
@@ -483,7 +498,7 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
           // a removed cell becomes a hole of its job's covering index, which
           // the boundary selection that follows reads
           if (!k && level) {
-            const CoverIndex& ci = jobs[job_of_cell(jobs, n_jobs, cc)].ci;
+            const CoverIndex& ci = one_job ? sci : jobs[job_of_cell(jobs, n_jobs, cc)].ci;
             if (!ci.uniform) {
               const int64_t sl = cell_slot(ci, level, idx, cc);
               if (sl >= 0) ci.state[sl] = ST_HOLE;
@@ -493,7 +508,8 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
       }
     }
     __syncthreads();
-    if (t == 0 && one_job && grp_kept) atomicAdd(&stats[jfirst].n_kept, (unsigned long long)grp_kept);
+    if (t == 0 && stats && one_job && grp_kept)
+      atomicAdd(&stats[jfirst].n_kept, (unsigned long long)grp_kept);
   }
   for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
   if ((t & 63) == 0 && mine) atomicAdd(nkept, mine);
