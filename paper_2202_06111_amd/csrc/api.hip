@@ -65,6 +65,7 @@ struct Counters {
   int32_t sweep_last;  // analysis: 1 + index of the last sweep that removed a cell
   int32_t fcount[3];   // analysis: frontier list lengths (rotating)
   int64_t rc_entries;  // analysis: entries of the cell-grouped reverse graph
+  unsigned long long n_staged;  // analysis: entries appended by the one-pass build
 };
 
 // Pinned host staging of a device array of T.
@@ -134,7 +135,7 @@ struct gis_ctx {
   GraphCache graphs;
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
-  DevBuf removed, rptr, rrow, rmask, rcur, rowstate, good, front;
+  DevBuf removed, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front;
   DevBuf bnd;
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
@@ -618,7 +619,7 @@ PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   w.good = (int32_t*)ctx->good.ptr;
   w.rowbad = (uint8_t*)ctx->rowstate.ptr;
   w.cand = (uint8_t*)ctx->good.ptr;
-  w.rsrc = (int32_t*)ctx->rrow.ptr;
+  w.rsrc = (int32_t*)ctx->rsrc.ptr;
   w.rmask = (uint64_t*)ctx->rmask.ptr;
   w.badmask = (uint64_t*)ctx->rowstate.ptr;
   w.front = (int32_t*)ctx->front.ptr;
@@ -798,15 +799,35 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
     }
     ctx->prune_clean = false;  // until the frontier has run out
     if (cells) {
-      // the entry count sizes the masks: read it back before the scatter
-      if ((rc = cells_start(row_ptr, col, n_cells, K, any_removed, w, s))) return rc;
-      GIS_HIP(hipMemcpyAsync(&ctx->h_counters->rc_entries, w.rptr + n_cells, sizeof(int64_t),
-                             hipMemcpyDeviceToHost, s));
-      if ((rc = wait_stream(ctx, s))) return rc;
-      if ((rc = ensure(ctx->rmask, (size_t)ctx->h_counters->rc_entries * 8 + 16))) return rc;
-      w = prune_work(ctx, cap_edges, nullptr);
-      if ((rc = cells_scatter(row_ptr, col, out, n_cells, K, analysis, any_removed, w, s)))
+      // one pass over the edges appends the entries to a staging area (the
+      // in-row buffer, a quarter of an entry per edge); when more entries
+      // come (few inputs share targets), two passes count and place them.
+      // The entry count sizes the entry arrays: it is read back first.
+      Staged* stage = (Staged*)ctx->rrow.ptr;
+      const int64_t stage_cap = (int64_t)(ctx->rrow.bytes / sizeof(Staged));
+      if ((rc = cells_stage(row_ptr, col, out, n_cells, K, analysis, any_removed, w, stage,
+                            stage_cap, &dcnt(ctx)->n_staged, s)) ||
+          (rc = sync_counters(ctx, s)))
         return rc;
+      const int64_t staged = (int64_t)ctx->h_counters->n_staged;
+      if (staged <= stage_cap) {
+        if ((rc = ensure(ctx->rsrc, (size_t)staged * 4 + 16)) ||
+            (rc = ensure(ctx->rmask, (size_t)staged * 8 + 16)))
+          return rc;
+        w = prune_work(ctx, cap_edges, nullptr);
+        if ((rc = cells_unstage(stage, staged, n_cells, w, s))) return rc;
+      } else {
+        if ((rc = cells_start(row_ptr, col, n_cells, K, any_removed, w, s))) return rc;
+        GIS_HIP(hipMemcpyAsync(&ctx->h_counters->rc_entries, w.rptr + n_cells, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        if ((rc = wait_stream(ctx, s))) return rc;
+        if ((rc = ensure(ctx->rsrc, (size_t)ctx->h_counters->rc_entries * 4 + 16)) ||
+            (rc = ensure(ctx->rmask, (size_t)ctx->h_counters->rc_entries * 8 + 16)))
+          return rc;
+        w = prune_work(ctx, cap_edges, nullptr);
+        if ((rc = cells_scatter(row_ptr, col, out, n_cells, K, analysis, any_removed, w, s)))
+          return rc;
+      }
     } else if ((rc = prune_frontier_start(row_ptr, col, out, n_cells, K, analysis, w, s))) {
       return rc;
     }
@@ -1379,7 +1400,7 @@ void gis_ctx_destroy(gis_ctx* c) {
   (void)hipDeviceSynchronize();
   DevBuf* bufs[] = {&c->counters, &c->jobs, &c->maxerr, &c->lookback, &c->scan_tmp,
                     &c->idx_state, &c->idx_pfx,
-                    &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rmask,
+                    &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rsrc, &c->rmask,
                     &c->rcur, &c->rowstate, &c->good, &c->front, &c->bnd, &c->lvA, &c->ixA,
                     &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};

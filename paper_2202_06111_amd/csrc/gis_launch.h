@@ -96,6 +96,21 @@ int32_t cells_start(const int64_t* row_ptr, const int32_t* col, int64_t n_cells,
 int32_t cells_scatter(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                       int64_t n_cells, int32_t K, int32_t analysis, bool any_removed,
                       const PruneWork& w, hipStream_t s);
+// One pass instead of cells_start + cells_scatter: the state, the first
+// frontier and the entries appended to `stage` (any order, up to stage_cap of
+// them; *n_staged, cleared here, receives their number even past the cap,
+// when nothing past it was written and the two-pass route must be taken).
+// cells_unstage then counts them per target, scans, and places them.
+struct Staged {
+  int32_t j, c;  // target, source cell
+  uint64_t m;    // input mask
+};
+int32_t cells_stage(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                    int64_t n_cells, int32_t K, int32_t analysis, bool any_removed,
+                    const PruneWork& w, Staged* stage, int64_t stage_cap,
+                    unsigned long long* n_staged, hipStream_t s);
+int32_t cells_unstage(const Staged* stage, int64_t n_staged, int64_t n_cells, const PruneWork& w,
+                      hipStream_t s);
 int32_t cells_steps(int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w, int32_t t0,
                     int32_t count, hipStream_t s);
 

@@ -149,21 +149,47 @@ __global__ __launch_bounds__(256) void k_cells_count(const int64_t* row_ptr, con
   }
 }
 
-// The entries, at rptr[j] + (a slot counted down from deg[j]), and the
-// analysis state with the first frontier (present cells already dead).
-template <int MODE>
+// Exclusive sum of v over the block (256 threads); *total gets the sum.
+__device__ __forceinline__ int32_t block_exclusive_sum(int32_t v, int32_t* lds, int32_t& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  int32_t before = 0;
+  total = 0;
+  for (int k = 0; k < 4; ++k) {
+    before += k < wid ? lds[k] : 0;
+    total += lds[k];
+  }
+  __syncthreads();
+  return before + x - v;
+}
+
+// The analysis state with the first frontier (present cells already dead),
+// and the entries: STAGE = false, at rptr[j] + (a slot counted down from
+// deg[j]); STAGE = true, appended in any order to `stage` (one atomic per
+// block; nothing is written past stage_cap, *n_staged still counts them).
+template <int MODE, bool STAGE>
 __global__ __launch_bounds__(256) void k_cells_fill(const int64_t* row_ptr, const int32_t* col,
                                                     const uint8_t* out, int64_t n_cells,
                                                     int32_t K, int32_t cpb,
                                                     const uint8_t* removed, bool any_removed,
                                                     const int64_t* rptr, int32_t* cursor,
                                                     int32_t* rsrc, uint64_t* rmask,
+                                                    Staged* stage, int64_t stage_cap,
+                                                    unsigned long long* n_staged,
                                                     uint32_t* rowstate, int32_t* good,
                                                     uint64_t* badmask, int32_t* front,
                                                     int32_t* count) {
   __shared__ CellTable tb;
   __shared__ int s_over;
   __shared__ uint8_t ok[256];
+  __shared__ int32_t s_sum[4];
+  __shared__ unsigned long long s_base;
   const int t = threadIdx.x;
   const uint64_t full = K == 64 ? ~0ull : ((1ull << K) - 1);
   const int64_t stride = (int64_t)gridDim.x * cpb;
@@ -200,22 +226,52 @@ __global__ __launch_bounds__(256) void k_cells_fill(const int64_t* row_ptr, cons
       return true;
     });
     __syncthreads();
-    if (s_over == 0) {
+    const bool over = s_over != 0;
+    if (over) {  // one entry per present edge
+      live = 0;
+      hit_removed = false;
+      for_targets(row_ptr, col, removed, any_removed, b, [&](int32_t j, bool rm) {
+        if (rm) hit_removed = true;
+        else ++live;
+        return true;
+      });
+    }
+    if (STAGE) {
+      // this thread's entries: its table slots, or its row's present edges
+      int32_t mine = 0;
+      if (!over)
+        for (int i = t; i < kSlots; i += 256) mine += tb.key[i] != kEmpty ? 1 : 0;
+      else if (b.active)
+        mine = live;
+      int32_t total;
+      const int32_t off = block_exclusive_sum(mine, s_sum, total);
+      if (t == 0) s_base = atomicAdd(n_staged, (unsigned long long)total);
+      __syncthreads();
+      if ((int64_t)(s_base + total) <= stage_cap) {
+        Staged* dst = stage + s_base + off;
+        if (!over) {
+          for (int i = t; i < kSlots; i += 256) {
+            const uint64_t key = tb.key[i];
+            if (key != kEmpty)
+              *dst++ = Staged{(int32_t)(key >> 8), (int32_t)(g0 + (int64_t)(key & 255)),
+                              tb.mask[i]};
+          }
+        } else {
+          for_targets(row_ptr, col, removed, any_removed, b, [&](int32_t j, bool rm) {
+            if (!rm) *dst++ = Staged{j, (int32_t)b.c, bit};
+            return true;
+          });
+        }
+      }
+    } else if (!over) {
       for (int i = t; i < kSlots; i += 256) {
         const uint64_t key = tb.key[i];
         if (key != kEmpty)
           place((int32_t)(key >> 8), (int32_t)(g0 + (int64_t)(key & 255)), tb.mask[i]);
       }
-    } else {  // one entry per present edge
-      live = 0;
-      hit_removed = false;
+    } else {
       for_targets(row_ptr, col, removed, any_removed, b, [&](int32_t j, bool rm) {
-        if (rm) {
-          hit_removed = true;
-        } else {
-          ++live;
-          place(j, (int32_t)b.c, bit);
-        }
+        if (!rm) place(j, (int32_t)b.c, bit);
         return true;
       });
     }
@@ -245,6 +301,27 @@ __global__ __launch_bounds__(256) void k_cells_fill(const int64_t* row_ptr, cons
     }
     append_block(add, (int32_t)cc, front, count);
     __syncthreads();
+  }
+}
+
+// Staged entries: counts per target, then each entry at rptr[j] + (a slot
+// counted down from deg[j]).
+__global__ __launch_bounds__(256) void k_stage_count(const Staged* st, int64_t n, int32_t* deg) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&deg[st[i].j], 1);
+}
+
+__global__ __launch_bounds__(256) void k_stage_scatter(const Staged* st, int64_t n,
+                                                       const int64_t* rptr, int32_t* cursor,
+                                                       int32_t* rsrc, uint64_t* rmask) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const Staged e = st[i];
+    const int32_t k = atomicSub(&cursor[e.j], 1);
+    if (k <= 0) continue;  // more entries than counted: never expected (no store out of range)
+    rsrc[rptr[e.j] + k - 1] = e.c;
+    rmask[rptr[e.j] + k - 1] = e.m;
   }
 }
 
@@ -338,16 +415,58 @@ int32_t cells_scatter(const int64_t* row_ptr, const int32_t* col, const uint8_t*
   const int32_t cpb = 256 / K;
   const unsigned nb = group_blocks(n_cells, cpb);
   if (analysis == GIS_ANALYSIS_NONLEAVING)
-    hipLaunchKernelGGL(k_cells_fill<GIS_ANALYSIS_NONLEAVING>, dim3(nb), dim3(256), 0, s, row_ptr,
-                       col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
-                       (const int64_t*)w.rptr, w.rcur, w.rsrc, w.rmask, w.rowstate, w.good,
+    hipLaunchKernelGGL((k_cells_fill<GIS_ANALYSIS_NONLEAVING, false>), dim3(nb), dim3(256), 0, s,
+                       row_ptr, col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
+                       (const int64_t*)w.rptr, w.rcur, w.rsrc, w.rmask, (Staged*)nullptr,
+                       (int64_t)0, (unsigned long long*)nullptr, w.rowstate, w.good, w.badmask,
+                       w.front, w.fcount);
+  else
+    hipLaunchKernelGGL((k_cells_fill<GIS_ANALYSIS_CONTROLLED, false>), dim3(nb), dim3(256), 0, s,
+                       row_ptr, col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
+                       (const int64_t*)w.rptr, w.rcur, w.rsrc, w.rmask, (Staged*)nullptr,
+                       (int64_t)0, (unsigned long long*)nullptr, w.rowstate, w.good, w.badmask,
+                       w.front, w.fcount);
+  GIS_LAUNCH_CHECK("k_cells_fill");
+  return GIS_OK;
+}
+
+int32_t cells_stage(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
+                    int64_t n_cells, int32_t K, int32_t analysis, bool any_removed,
+                    const PruneWork& w, Staged* stage, int64_t stage_cap,
+                    unsigned long long* n_staged, hipStream_t s) {
+  if (K < 1 || K > 64) return GIS_E_INTERNAL;
+  int32_t rc;
+  if ((rc = fill_i32(w.fcount, 0, 3, s))) return rc;
+  if ((rc = fill_i64((int64_t*)n_staged, 0, 1, s))) return rc;
+  const int32_t cpb = 256 / K;
+  const unsigned nb = group_blocks(n_cells, cpb);
+  if (analysis == GIS_ANALYSIS_NONLEAVING)
+    hipLaunchKernelGGL((k_cells_fill<GIS_ANALYSIS_NONLEAVING, true>), dim3(nb), dim3(256), 0, s,
+                       row_ptr, col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
+                       (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                       (uint64_t*)nullptr, stage, stage_cap, n_staged, w.rowstate, w.good,
                        w.badmask, w.front, w.fcount);
   else
-    hipLaunchKernelGGL(k_cells_fill<GIS_ANALYSIS_CONTROLLED>, dim3(nb), dim3(256), 0, s, row_ptr,
-                       col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
-                       (const int64_t*)w.rptr, w.rcur, w.rsrc, w.rmask, w.rowstate, w.good,
+    hipLaunchKernelGGL((k_cells_fill<GIS_ANALYSIS_CONTROLLED, true>), dim3(nb), dim3(256), 0, s,
+                       row_ptr, col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
+                       (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                       (uint64_t*)nullptr, stage, stage_cap, n_staged, w.rowstate, w.good,
                        w.badmask, w.front, w.fcount);
   GIS_LAUNCH_CHECK("k_cells_fill");
+  return GIS_OK;
+}
+
+int32_t cells_unstage(const Staged* stage, int64_t n_staged, int64_t n_cells, const PruneWork& w,
+                      hipStream_t s) {
+  const unsigned nb = (unsigned)((n_staged + 255) / 256 < 16384 ? (n_staged + 255) / 256 + 1 : 16384);
+  hipLaunchKernelGGL(k_stage_count, dim3(nb), dim3(256), 0, s, stage, n_staged, w.rcur);
+  GIS_LAUNCH_CHECK("k_stage_count");
+  int32_t rc;
+  if ((rc = scan_exclusive_i32(w.rcur, w.rptr, n_cells, w.rptr + n_cells, w.scan_tmp, s)))
+    return rc;
+  hipLaunchKernelGGL(k_stage_scatter, dim3(nb), dim3(256), 0, s, stage, n_staged,
+                     (const int64_t*)w.rptr, w.rcur, w.rsrc, w.rmask);
+  GIS_LAUNCH_CHECK("k_stage_scatter");
   return GIS_OK;
 }
 
