@@ -68,7 +68,8 @@ struct Counters {
   unsigned long long n_staged;  // analysis: entries appended by the one-pass build
 };
 
-// Pinned host staging of a device array of T.
+// Pinned host staging of a device array of T (coherent: kernels may write
+// it directly, see sync_to_host).
 template <typename T>
 struct Pinned {
   T* h = nullptr;
@@ -78,7 +79,7 @@ struct Pinned {
     if (h) (void)hipHostFree(h);
     h = nullptr;
     n = 0;
-    hipError_t e = hipHostMalloc((void**)&h, want * sizeof(T), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void**)&h, want * sizeof(T), hipHostMallocCoherent);
     if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
     n = want;
     return GIS_OK;
@@ -116,6 +117,8 @@ struct gis_ctx {
   // read back by one copy per phase
   DevBuf counters;
   Pinned<uint8_t> h_cs;            // pinned mirror of `counters`
+  Pinned<uint32_t> h_flag;         // sequence number published after a copy into h_cs
+  uint32_t pub_seq = 0;
   Counters* h_counters = nullptr;  // views into h_cs
   JobStats* h_stats = nullptr;
   DevBuf jobs, maxerr;
@@ -308,10 +311,43 @@ int32_t wait_stream(gis_ctx* ctx, hipStream_t s) {
   return GIS_OK;
 }
 
+// Copies the first `bytes` of the counters buffer to its host mirror and
+// waits for everything enqueued before: a kernel writes the mirror and then a
+// sequence number, and the host spins on that number for up to kSpinUs before
+// it blocks in hipStreamSynchronize (a copy plus a stream synchronisation
+// costs about 4 µs more per round trip).
+constexpr int kSpinUs = 2000;
+int32_t sync_to_host(gis_ctx* ctx, size_t bytes, hipStream_t s) {
+  int32_t rc;
+  if ((rc = ctx->h_flag.ensure(16))) return rc;
+  const uint32_t seq = ++ctx->pub_seq;
+  if ((rc = publish(ctx->counters.ptr, ctx->h_cs.h, bytes, ctx->h_flag.h, seq, s))) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  bool seen = false;
+  for (uint32_t k = 0;; ++k) {
+    if (__atomic_load_n(ctx->h_flag.h, __ATOMIC_ACQUIRE) == seq) {
+      seen = true;
+      break;
+    }
+    if ((k & 255) == 255 && std::chrono::steady_clock::now() - t0 >
+                                std::chrono::microseconds(kSpinUs))
+      break;
+  }
+  ctx->wait_ms +=
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (!seen) {
+    if ((rc = wait_stream(ctx, s))) return rc;
+    if (__atomic_load_n(ctx->h_flag.h, __ATOMIC_ACQUIRE) != seq) {
+      set_error("internal: the counters did not reach the host");
+      return GIS_E_INTERNAL;
+    }
+  }
+  GIS_HIP(hipPeekAtLastError());
+  return GIS_OK;
+}
+
 int32_t sync_counters(gis_ctx* ctx, hipStream_t s) {
-  GIS_HIP(hipMemcpyAsync(ctx->h_counters, ctx->counters.ptr, sizeof(Counters),
-                         hipMemcpyDeviceToHost, s));
-  return wait_stream(ctx, s);
+  return sync_to_host(ctx, sizeof(Counters), s);
 }
 
 // ---------------------------------------------------------------- batches
@@ -463,9 +499,7 @@ int32_t zero_all(gis_ctx* ctx, const Batch& B, hipStream_t s) {
 // Copies the counters and the batch's job stats to the host (one copy) and
 // synchronises.
 int32_t sync_stats(gis_ctx* ctx, const Batch& B, hipStream_t s) {
-  GIS_HIP(hipMemcpyAsync(ctx->h_cs.h, ctx->counters.ptr, kStatsOff + sizeof(JobStats) * B.n_jobs,
-                         hipMemcpyDeviceToHost, s));
-  return wait_stream(ctx, s);
+  return sync_to_host(ctx, kStatsOff + sizeof(JobStats) * B.n_jobs, s);
 }
 
 // Builds every job's covering index (or checks full level-0 grids).  With
@@ -1378,6 +1412,7 @@ int32_t gis_ctx_create(int32_t device, gis_ctx** out) {
   if (rc) {
     release(c->counters);
     c->h_cs.free();
+    c->h_flag.free();
     delete c;
     return rc;
   }
@@ -1408,6 +1443,7 @@ void gis_ctx_destroy(gis_ctx* c) {
   for (auto& kv : c->graphs.map)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   c->h_cs.free();
+  c->h_flag.free();
   c->h_jobs.free();
   c->h_maxerr.free();
   for (int i = 0; i < 3; ++i)

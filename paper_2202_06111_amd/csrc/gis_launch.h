@@ -153,6 +153,11 @@ int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stat
 int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
                                const uint8_t* kept, JobStats* stats, hipStream_t s);
 
+// k_index.hip: copies `bytes` (a multiple of 4) of device memory into
+// host-coherent pinned memory, then stores seq into *host_flag.
+int32_t publish(const void* src, void* host_dst, size_t bytes, uint32_t* host_flag, uint32_t seq,
+                hipStream_t s);
+
 // k_query.hip
 int32_t launch_query(const CoverIndex& ci, const GridArgs& g, const uint8_t* kept,
                      const uint64_t* mask, int32_t mask_words, const double* states, int64_t n,

@@ -32,6 +32,19 @@ int32_t fill(T* p, T v, int64_t n, hipStream_t s) {
   return GIS_OK;
 }
 
+// Copies `words` 32-bit words from device memory to host-coherent pinned
+// memory, then publishes seq in the host flag (after a system-scope fence):
+// a host spinning on the flag sees the words once it sees seq.
+__global__ void k_publish(const uint32_t* src, uint32_t* dst, int32_t words, uint32_t* flag,
+                          uint32_t seq) {
+  for (int32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 __global__ void k_zero_ranges(ZeroRanges z) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int r = 0; r < z.n; ++r)
@@ -266,6 +279,14 @@ int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t 
   if (b.blocks[LK_CELLS] == 0) return GIS_OK;
   hipLaunchKernelGGL(k_mark_dropped, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept);
   GIS_LAUNCH_CHECK("k_mark_dropped");
+  return GIS_OK;
+}
+
+int32_t publish(const void* src, void* host_dst, size_t bytes, uint32_t* host_flag, uint32_t seq,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, (const uint32_t*)src,
+                     (uint32_t*)host_dst, (int32_t)((bytes + 3) / 4), host_flag, seq);
+  GIS_LAUNCH_CHECK("k_publish");
   return GIS_OK;
 }
 
