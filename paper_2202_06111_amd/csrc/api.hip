@@ -542,8 +542,14 @@ BuildArgs build_args(gis_ctx* ctx, const Batch& B, const uint8_t* level, const i
   a.n = B.n;
   a.n_blocks = B.blocks[LK_ROWS];
   a.total_rows = B.total_cells * B.K;
+  // full level-0 grids (also those whose index arrays are kept for the
+  // boundary selection) need no index walk
   a.all_uniform = 1;
-  for (const Job& J : B.jobs) a.all_uniform &= J.ci.uniform || J.n_cells == 0 ? 1 : 0;
+  for (const Job& J : B.jobs)
+    a.all_uniform &= J.n_cells == 0 || J.ci.uniform ||
+                             (J.ci.lmax == 0 && J.n_cells == prod_n0(J.grid))
+                         ? 1
+                         : 0;
   a.level = level;
   a.idx = idx;
   a.n_recheck = (unsigned long long*)&dcnt(ctx)->n_recheck;
