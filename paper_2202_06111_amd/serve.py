@@ -116,6 +116,21 @@ class Admission:
             return self._in_use
 
 
+@dataclasses.dataclass
+class Queries:
+    """A request's query states as they arrive with it: the membership and the
+    admissible-input queries, each an (N x n) float64 array in pinned host
+    memory."""
+    member_states: torch.Tensor
+    admissible_states: torch.Tensor
+
+    @staticmethod
+    def of(req: W.ServeRequest) -> "Queries":
+        states, kinds = req.queries, req.kinds
+        return Queries(torch.from_numpy(np.ascontiguousarray(states[kinds == 0])).pin_memory(),
+                       torch.from_numpy(np.ascontiguousarray(states[kinds == 1])).pin_memory())
+
+
 class Server:
     def __init__(self, n_slots: int = 4, mem_budget_bytes: int = 8 << 30, device: int = 0):
         self.n_slots = n_slots
@@ -128,8 +143,23 @@ class Server:
         for c in self.ctxs:
             c.close()
 
+    # -------------------------------------------------------------- queries
+    @staticmethod
+    def _enqueue_queries(ctx: gis.Context, sol: gis.Solution, q: Queries, stream):
+        """Copies the query states in, answers both kinds and copies the answers
+        out to pinned host memory, all enqueued on `stream` (no synchronisation)."""
+        ms = q.member_states.to(ctx.dev, non_blocking=True)
+        as_ = q.admissible_states.to(ctx.dev, non_blocking=True)
+        member = sol.query_membership(ms, stream)
+        adm = sol.query_admissible(as_, stream)
+        member_h = torch.empty(member.shape, dtype=member.dtype, pin_memory=True)
+        adm_h = torch.empty(adm.shape, dtype=adm.dtype, pin_memory=True)
+        member_h.copy_(member, non_blocking=True)
+        adm_h.copy_(adm, non_blocking=True)
+        return member_h, adm_h
+
     # -------------------------------------------------------------- one request
-    def _serve_one(self, slot: int, req: W.ServeRequest, t0: float) -> Result:
+    def _serve_one(self, slot: int, req: W.ServeRequest, q: Queries, t0: float) -> Result:
         ctx, stream = self.ctxs[slot], self.streams[slot]
         start = time.perf_counter() - t0
         wl = req.workload
@@ -137,20 +167,14 @@ class Server:
             du = gis.to_device_u(ctx, wl.u)
             sol = gis.solve(ctx, wl.system, wl.grid, du, wl.rounds, gis.workload_opts(wl), stream)
             try:
-                states = torch.as_tensor(req.queries, device=ctx.dev)
-                kinds = torch.as_tensor(req.kinds, device=ctx.dev)
-                mem_idx = torch.nonzero(kinds == 0).squeeze(1)
-                adm_idx = torch.nonzero(kinds == 1).squeeze(1)
-                member = sol.query_membership(states.index_select(0, mem_idx).contiguous(), stream)
-                adm = sol.query_admissible(states.index_select(0, adm_idx).contiguous(), stream)
-                member_h = member.cpu().numpy()
-                adm_h = adm.cpu().numpy().view(np.uint64)
+                member_h, adm_h = self._enqueue_queries(ctx, sol, q, stream)
                 info = sol.info()
+                stream.synchronize()
             finally:
                 sol.free()
         done = time.perf_counter() - t0
         return Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"], info["n_kept"],
-                      member_h, adm_h)
+                      member_h.numpy(), adm_h.numpy().view(np.uint64))
 
     @staticmethod
     def _compatible(a: W.Workload, b: W.Workload) -> bool:
@@ -158,34 +182,32 @@ class Server:
                          w.precision, w.boundary_rule, w.analysis)
         return key(a) == key(b)
 
-    def _serve_batch(self, slot: int, reqs: List[W.ServeRequest], t0: float) -> List[Result]:
+    def _serve_batch(self, slot: int, reqs: List[W.ServeRequest], qs: List[Queries],
+                     t0: float) -> List[Result]:
+        """One gis_solve_batch for the requests, then every query of the batch
+        enqueued on the slot's stream and one synchronisation."""
         ctx, stream = self.ctxs[slot], self.streams[slot]
         start = time.perf_counter() - t0
-        out = []
         with torch.cuda.stream(stream):
             sols = gis.solve_batch(ctx, [r.workload for r in reqs], stream)
             try:
-                for req, sol in zip(reqs, sols):
-                    states = torch.as_tensor(req.queries, device=ctx.dev)
-                    kinds = torch.as_tensor(req.kinds, device=ctx.dev)
-                    mem_idx = torch.nonzero(kinds == 0).squeeze(1)
-                    adm_idx = torch.nonzero(kinds == 1).squeeze(1)
-                    member = sol.query_membership(states.index_select(0, mem_idx).contiguous(), stream)
-                    adm = sol.query_admissible(states.index_select(0, adm_idx).contiguous(), stream)
-                    member_h = member.cpu().numpy()
-                    adm_h = adm.cpu().numpy().view(np.uint64)
-                    info = sol.info()
-                    done = time.perf_counter() - t0
-                    out.append(Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"],
-                                      info["n_kept"], member_h, adm_h))
+                answers = [self._enqueue_queries(ctx, sol, q, stream) for sol, q in zip(sols, qs)]
+                infos = [sol.info() for sol in sols]
+                stream.synchronize()
             finally:
                 for sol in sols:
                     sol.free()
-        return out
+        done = time.perf_counter() - t0
+        return [Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"], info["n_kept"],
+                       m.numpy(), a.numpy().view(np.uint64))
+                for req, info, (m, a) in zip(reqs, infos, answers)]
 
     def run(self, requests: List[W.ServeRequest], realtime: bool = True,
             max_batch: int = 16) -> dict:
-        """Serves the stream; returns per-request results and summary stats."""
+        """Serves the stream; returns per-request results and summary stats.
+        Each request's query states are materialised (pinned host memory)
+        before the clock starts: they arrive with the request."""
+        queries = [Queries.of(r) for r in requests]
         results: List[Optional[Result]] = [None] * len(requests)
         errors: List[BaseException] = []
         pending = collections.deque(sorted(range(len(requests)),
@@ -202,7 +224,8 @@ class Server:
 
         def worker(slot: int, idx: List[int], need: int) -> None:
             try:
-                for i, r in zip(idx, self._serve_batch(slot, [requests[i] for i in idx], t0)):
+                for i, r in zip(idx, self._serve_batch(slot, [requests[i] for i in idx],
+                                                       [queries[i] for i in idx], t0)):
                     results[i] = r
             except BaseException as e:  # reported after the run
                 errors.append(e)
@@ -261,7 +284,8 @@ def serve_alone(requests: List[W.ServeRequest], device: int = 0) -> List[Result]
     """Each request solved and queried by itself, one after the other."""
     srv = Server(n_slots=1, device=device)
     try:
+        queries = [Queries.of(r) for r in requests]
         t0 = time.perf_counter()
-        return [srv._serve_one(0, r, t0) for r in requests]
+        return [srv._serve_one(0, r, q, t0) for r, q in zip(requests, queries)]
     finally:
         srv.close()
