@@ -24,6 +24,14 @@
 // dies, and flagged removed by the step that takes it from the frontier.
 // Rows of cells already removed (by the sweeps) and edges to removed targets
 // get no entry: the initial state accounts for those targets directly.
+//
+// Building the entries: a block takes whole cells and inserts their rows'
+// (cell, target) keys into an LDS table, ORing each row's input bit into the
+// key's mask.  One pass over the edges appends the block's entries to a
+// staging area (k_cells_fill<STAGE>), which k_stage_count / a scan /
+// k_stage_scatter then group by target; when more entries come than the
+// staging area holds, a first pass counts them per target (k_cells_count) and
+// a second places them (k_cells_fill).
 #include "gis_launch.h"
 
 namespace gis {
