@@ -1696,7 +1696,7 @@ int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
       {[](const gis_tuning& t) { return (int64_t)t.sweep_batch; },
        [](gis_tuning& t, int64_t v) { t.sweep_batch = (int32_t)v; }, {4, 8, 16}},
       {[](const gis_tuning& t) { return t.sweep_edges; },
-       [](gis_tuning& t, int64_t v) { t.sweep_edges = v; }, {1 << 20, 8 << 20, 64 << 20}},
+       [](gis_tuning& t, int64_t v) { t.sweep_edges = v; }, {0, 1 << 20, 8 << 20, 64 << 20}},
       {[](const gis_tuning& t) { return (int64_t)t.sweep_blocks; },
        [](gis_tuning& t, int64_t v) { t.sweep_blocks = (int32_t)v; }, {1024, 4096, 16384}},
       {[](const gis_tuning& t) { return (int64_t)t.front_blocks; },
