@@ -474,6 +474,21 @@ def test_solve_vdp_uniform_64(G, ctx):
     _check_solve(G, ctx, W.vdp_uniform_64())
 
 
+@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1", "linear3"])
+def test_solve_uniform_frontier_from_boxes(G, ctx, name, analysis):
+    """One-round solves of full coarse grids straight into the frontier phase:
+    the reverse entries come from the rows' boxes (1 to 4 dimensions, up to
+    9 inputs), not from a table."""
+    system, grid, u, samples = SMALL[name]
+    wl = W.Workload(f"uniform_{name}", system, grid, u, samples, 0, "fp64", analysis=analysis)
+    prev = ctx.set_tuning(sweep_edges=0)
+    try:
+        _check_solve(G, ctx, wl)
+    finally:
+        ctx.set_tuning(**prev)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_recheck"])
 def test_solve_vdp_adaptive_32_r5(G, ctx, precision):
     sol, want, info = _check_solve(G, ctx, W.vdp_adaptive_32(precision), precision)
