@@ -477,9 +477,9 @@ def test_solve_vdp_uniform_64(G, ctx):
 @pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
 @pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1", "linear3"])
 def test_solve_uniform_frontier_from_boxes(G, ctx, name, analysis):
-    """One-round solves of full coarse grids straight into the frontier phase:
-    the reverse entries come from the rows' boxes (1 to 4 dimensions, up to
-    9 inputs), not from a table."""
+    """One-round solves of full coarse grids straight into the frontier phase
+    (the cell-grouped reverse graph built from a solve's job table), 1 to 4
+    dimensions, up to 9 inputs."""
     system, grid, u, samples = SMALL[name]
     wl = W.Workload(f"uniform_{name}", system, grid, u, samples, 0, "fp64", analysis=analysis)
     prev = ctx.set_tuning(sweep_edges=0)
