@@ -16,6 +16,8 @@ Parity status per function (what pins each one is in tests/test_oracle_*.py):
                   textbook non-leaving set via strongly connected components
   boundary        pinned: the 5x5 worked example of Sec. 3.1.1 and Remark 1
   subdivide/solve pinned: union preservation and monotone shrinking
+  bisect          pinned: hand-derived 2x2 example, exact halving of every
+                  kept cell, loop with nothing removed = the uniform grid
   query           pinned: brute-force point location over the cell list
 """
 from __future__ import annotations
@@ -267,6 +269,27 @@ def subdivide(grid, level, idx, kept, bnd):
     return lv[:need].copy(), ix[:need].copy()
 
 
+def bisect(grid, idx, kept, dim: int):
+    """Subdivision step of the standard algorithm (Sec. 2.1): every kept cell
+    of a level-0 covering is cut in half across dimension `dim`.  The halves
+    are the level-0 cells of the grid with twice as many cells along `dim`
+    (same box X), returned with that grid, in canonical (row-major) order."""
+    idx, kept = _c(idx, np.int32), _c(kept, np.uint8)
+    n = grid.n
+    n0 = list(grid.n0)
+    n0[dim] *= 2
+    new_grid = type(grid)(tuple(n0), tuple(grid.lo), tuple(grid.hi))
+    halves = []
+    for c in np.nonzero(kept)[0]:
+        for h in (0, 1):
+            k = [int(v) for v in idx[c]]
+            k[dim] = 2 * k[dim] + h
+            halves.append(tuple(k))
+    halves.sort()  # lexicographic on (i_0, ..., i_{n-1}): dimension 0 slowest
+    out = np.array(halves, dtype=np.int32).reshape(len(halves), n)
+    return new_grid, np.zeros(len(halves), dtype=np.uint8), out
+
+
 def query(grid, level, idx, kept, mask, states):
     lib = _load()
     level, idx, kept = _c(level, np.uint8), _c(idx, np.int32), _c(kept, np.uint8)
@@ -284,10 +307,15 @@ def query(grid, level, idx, kept, mask, states):
 
 
 def solve(system, grid, samples: str, u, rounds: int, rule: str = "shell",
-          fast_out: bool = False, keep_graphs: bool = False, analysis: str = "controlled"):
+          fast_out: bool = False, keep_graphs: bool = False, analysis: str = "controlled",
+          subdivision: str = "boundary"):
     """The iteration loop: build and prune on the coarse covering, then
-    `rounds` times subdivide the boundary cells (Sec. 3.1), rebuild and prune.
-    Stops early when nothing is kept."""
+    `rounds` times subdivide, rebuild and prune.  subdivision "boundary":
+    the 2^n children of the boundary cells (Sec. 3.1); "bisect": the
+    standard algorithm's halving of every kept cell (Sec. 2.1), across
+    dimension 0 in the first subdivision, 1 in the second, ... cyclically.
+    Stops early when nothing is kept.  The result holds the grid of the
+    final covering (the coarse grid unless cells were bisected)."""
     u = _c(u, np.float64)
     K = u.shape[0]
     level, idx = coarse_cells(grid)
@@ -296,21 +324,25 @@ def solve(system, grid, samples: str, u, rounds: int, rule: str = "shell",
     kept = mask = None
     for r in range(rounds + 1):
         if r > 0:
-            bnd = boundary(grid, level, idx, kept, rule)
-            level, idx = subdivide(grid, level, idx, kept, bnd)
-            stats[-1]["n_boundary"] = int(bnd.sum())
+            if subdivision == "bisect":
+                grid, level, idx = bisect(grid, idx, kept, (r - 1) % grid.n)
+                stats[-1]["n_boundary"] = int(kept.sum())
+            else:
+                bnd = boundary(grid, level, idx, kept, rule)
+                level, idx = subdivide(grid, level, idx, kept, bnd)
+                stats[-1]["n_boundary"] = int(bnd.sum())
         if level.shape[0] == 0:
             break
         g = build_graph(system, grid, samples, level, idx, u, fast_out=fast_out)
         kept, mask, sweeps = prune(g["row_ptr"], g["col"], g["out"], level.shape[0], K, analysis)
         stats.append({"round": r, "n_cells": int(level.shape[0]), "n_rows": int(level.shape[0] * K),
                       "n_edges": int(g["col"].shape[0]), "n_out": int(g["out"].sum()),
-                      "n_kept": int(kept.sum()), "sweeps": sweeps})
+                      "n_kept": int(kept.sum()), "sweeps": sweeps, "n0": tuple(grid.n0)})
         if keep_graphs:
             graphs.append(g)
         if kept.sum() == 0:
             break
-    res = {"level": level, "idx": idx, "kept": kept, "mask": mask, "stats": stats}
+    res = {"level": level, "idx": idx, "kept": kept, "mask": mask, "stats": stats, "grid": grid}
     if keep_graphs:
         res["graphs"] = graphs
     return res
