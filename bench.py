@@ -100,7 +100,8 @@ def cpu_baseline(wl, budget_s):
     reps, rows, t0 = 0, 0, time.perf_counter()
     while True:
         res = oracle.solve(wl.system, wl.grid, wl.samples, wl.u, wl.rounds,
-                           rule=wl.boundary_rule, analysis=wl.analysis)
+                           rule=wl.boundary_rule, analysis=wl.analysis,
+                           subdivision=wl.subdivision)
         rows += sum(s["n_rows"] for s in res["stats"])
         reps += 1
         el = time.perf_counter() - t0
@@ -214,7 +215,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "system": wl.system.kind, "grid0": list(wl.grid.n0),
                    "rounds": wl.rounds, "inputs": wl.K, "samples": wl.samples,
-                   "analysis": wl.analysis, "precision": precision,
+                   "analysis": wl.analysis, "subdivision": wl.subdivision, "precision": precision,
                    "rows_per_solve": rows // a.steps, "final_cells": last["n_cells"],
                    "final_kept": last["n_kept"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,

@@ -40,6 +40,13 @@
  * corners only, Algorithm 1 as printed).  The next covering holds the 2^n
  * children of every boundary cell and every other kept cell.
  *
+ * Standard subdivision (Sec. 2.1): every kept cell of a level-0 covering is
+ * halved across one dimension, which cycles from one iteration to the next
+ * (dimension 0 first).  The halves are the level-0 cells of the grid with
+ * twice as many cells along that dimension (same X); the widths
+ * (hi_d - lo_d) / (2 n0_d) are exactly half of (hi_d - lo_d) / n0_d, so the
+ * geometry is that of the halved cells.
+ *
  * Conventions for every function below:
  *  - Return value: a gis_status code; on failure gis_last_error() gives a
  *    message (thread-local).  Outputs are unspecified after a failure.
@@ -73,6 +80,7 @@ enum { GIS_SAMPLES_LATTICE3 = 1, GIS_SAMPLES_CORNERS_CENTER = 2 };
 enum { GIS_PREC_FP64 = 1, GIS_PREC_FP32_RECHECK = 2 };
 enum { GIS_BOUNDARY_SHELL = 1, GIS_BOUNDARY_CORNERS = 2 };
 enum { GIS_ANALYSIS_CONTROLLED = 1, GIS_ANALYSIS_NONLEAVING = 2 };
+enum { GIS_SUBDIVIDE_BOUNDARY = 0, GIS_SUBDIVIDE_BISECT = 1 };
 
 /* Vector field g of x' = g(x, u); f = nsub RK4 substeps of length dt/nsub.
  *  LINEAR (n <= 4, m <= 2): g = A x + B u, A = params[4d + j], B = params[16 + 2d + k]
@@ -104,7 +112,10 @@ typedef struct gis_opts {
   int32_t fast_out;       /* nonzero: OUT rows get no edges (analysis results unchanged) */
   int32_t timing;         /* HIP-event timings in gis_round_stats: 1 the build kernel (ms_image),
                              2 also the phases (ms_build, ms_prune, ms_subdivide); 0 none */
-  int32_t reserved[2];
+  int32_t subdivision;    /* GIS_SUBDIVIDE_*: gis_solve refines the 2^n children of the
+                             boundary cells (BOUNDARY, 0), or halves every kept cell across
+                             the cycled dimension (BISECT; boundary_rule is then unused) */
+  int32_t reserved;
   double band[4];         /* absolute recheck band per dimension; 0 = gis_solve calibrates
                              it on the round-0 covering (every row, or an evenly strided
                              sample of about 2^20 rows of larger coverings; see
@@ -150,6 +161,8 @@ typedef struct gis_round_stats {
 typedef struct gis_solve_info {
   int32_t n_rounds;        /* rounds actually run (<= requested + 1) */
   int32_t n, K, mask_words;
+  int32_t n0[4];           /* cells per dimension of the final covering's grid: the coarse
+                              grid's, doubled along each dimension a bisection cut */
   int64_t n_cells, n_kept; /* final covering and kept set */
   double band[4];          /* recheck band used (FP32 path) */
   gis_round_stats rounds[GIS_MAX_ROUNDS];
@@ -222,8 +235,20 @@ int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
                       const uint8_t* d_kept, int32_t boundary_rule, uint8_t* d_boundary,
                       gis_cells* out, void* stream);
 
+/* Standard subdivision (Sec. 2.1): halves every kept cell of `in` across
+ * dimension `dim` (0 <= dim < n).  Every kept cell must be a level-0 cell of
+ * `grid` (GIS_E_INVAL otherwise); the list's order does not matter and the
+ * cells that are not kept are ignored.  *grid_out receives the grid of the
+ * halves (grid with n0[dim] doubled, at most 2^30); out receives the halves as
+ * its level-0 cells in canonical order (2 per kept cell, duplicates of `in`
+ * merged).  Synchronises; GIS_E_CAPACITY if out->cap is too small
+ * (out->n_cells then holds the count needed). */
+int32_t gis_bisect(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in, const uint8_t* d_kept,
+                   int32_t dim, gis_grid* grid_out, gis_cells* out, void* stream);
+
 /* The iteration loop: coarse covering -> build -> prune, then `rounds` times
- * subdivide -> build -> prune; stops early when nothing is kept.  The result
+ * subdivide -> build -> prune (opts->subdivision: boundary cells or every kept
+ * cell); stops early when nothing is kept.  The result
  * stays on the device in a library-owned handle (free with gis_solution_free). */
 int32_t gis_solve(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, const double* d_u,
                   int32_t K, int32_t rounds, const gis_opts* opts, gis_solution** out,

@@ -215,7 +215,10 @@ int32_t check_opts(const gis_opts* o) {
     return inval("unknown sample scheme");
   if (o->precision != GIS_PREC_FP64 && o->precision != GIS_PREC_FP32_RECHECK)
     return inval("unknown precision");
-  if (o->boundary_rule != GIS_BOUNDARY_SHELL && o->boundary_rule != GIS_BOUNDARY_CORNERS)
+  if (o->subdivision != GIS_SUBDIVIDE_BOUNDARY && o->subdivision != GIS_SUBDIVIDE_BISECT)
+    return inval("unknown subdivision");
+  if (o->subdivision == GIS_SUBDIVIDE_BOUNDARY && o->boundary_rule != GIS_BOUNDARY_SHELL &&
+      o->boundary_rule != GIS_BOUNDARY_CORNERS)
     return inval("unknown boundary rule");
   if (o->analysis != GIS_ANALYSIS_CONTROLLED && o->analysis != GIS_ANALYSIS_NONLEAVING)
     return inval("unknown analysis");
@@ -245,6 +248,20 @@ GridArgs make_grid(const gis_grid* g) {
     a.w0[d] = (g->hi[d] - g->lo[d]) / (double)g->n0[d];
   }
   return a;
+}
+
+// The grid of the halves of a standard subdivision across dimension d: twice
+// the cells along d, the width computed as for a given grid (it is exactly
+// half the old one: the divisor only gains a factor 2).
+int32_t bisected(const GridArgs& g, int d, GridArgs* out) {
+  if (g.n0[d] > (1 << 29)) {
+    set_error("a bisection would give more than 2^30 cells along a dimension");
+    return GIS_E_UNSUPPORTED;
+  }
+  *out = g;
+  out->n0[d] = 2 * g.n0[d];
+  out->w0[d] = (g.hi[d] - g.lo[d]) / (double)out->n0[d];
+  return GIS_OK;
 }
 
 int64_t prod_n0(const GridArgs& g) {
@@ -364,6 +381,7 @@ struct Batch {
   int n = 0, K = 0;
   std::vector<Job> jobs;
   std::vector<int> lmax;
+  int bisect_dim = -1;       // >= 0: the next covering halves every kept cell across it
   int64_t total_cells = 0;
   int64_t total_slots = 0;   // index slots of the jobs with index arrays
   int64_t blocks[LK_KINDS] = {0, 0, 0, 0};
@@ -435,7 +453,13 @@ int32_t batch_layout(gis_ctx* ctx, Batch& B, const std::vector<int64_t>& n_cells
     so[j] = slot_off;
     int64_t nslots = 0;
     if (with_next[j] && J.n_cells > 0) {
-      if ((rc = layout_index(J.next, J.grid, B.lmax[j] + 1))) return rc;
+      if (B.bisect_dim >= 0) {
+        GridArgs half{};
+        if ((rc = bisected(J.grid, B.bisect_dim, &half)) || (rc = layout_index(J.next, half, 0)))
+          return rc;
+      } else if ((rc = layout_index(J.next, J.grid, B.lmax[j] + 1))) {
+        return rc;
+      }
       nslots = J.next.off[J.next.lmax + 1];
     } else {
       J.next = CoverIndex{};
@@ -891,13 +915,15 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
 }
 
 // Boundary selection + next covering of a laid-out batch (index arrays built,
-// next layouts set), enqueued only (the caller cleared the counters and job
+// next layouts set), or the halving of every kept cell when B.bisect_dim >= 0
+// (then `boundary` receives the cut flags), enqueued only (the caller cleared the counters and job
 // stats).  Writes the new global list to (lv_out, ix_out) up to cap cells.
 // holes_marked: the analysis' final pass already turned the removed cells
 // into holes of the covering index (it does for K <= 256).
 int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
                           const uint8_t* kept, int32_t rule, uint8_t* boundary, uint8_t* lv_out,
-                          int32_t* ix_out, int64_t cap, hipStream_t s, bool holes_marked = false) {
+                          int32_t* ix_out, int64_t cap, hipStream_t s, bool holes_marked = false,
+                          uint32_t* bisect_err = nullptr) {
   int32_t rc;
   const BatchArgs ba = B.args(level, idx);
   const int64_t total = next_total(B);
@@ -907,8 +933,12 @@ int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const in
       return rc;
     ctx->next_clean = false;  // until finish_subdivide has seen the compaction complete
   }
-  if (!holes_marked && (rc = batch_mark_dropped(ba, kept, s))) return rc;
-  if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
+  if (B.bisect_dim >= 0) {
+    if ((rc = batch_bisect(ba, kept, B.bisect_dim, boundary, B.d_stats, bisect_err, s))) return rc;
+  } else {
+    if (!holes_marked && (rc = batch_mark_dropped(ba, kept, s))) return rc;
+    if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
+  }
   if (total > 0) {
     if ((rc = scan_exclusive_u8((const uint8_t*)ctx->next_state.ptr, (int64_t*)ctx->pos.ptr, total,
                                 &dcnt(ctx)->n_next, ctx->scan_tmp.ptr, s)))
@@ -1032,6 +1062,7 @@ int32_t make_solution(gis_ctx* ctx, const Batch& B, int j, const uint8_t* level,
   sol->n_cells = J.n_cells;
   sol->info = info;
   sol->info.n_cells = J.n_cells;
+  for (int d = 0; d < n; ++d) sol->info.n0[d] = J.grid.n0[d];
   const int64_t nc = J.n_cells, c0 = J.cell_off;
   int32_t rc;
   auto fail = [&](int32_t code) {
@@ -1113,6 +1144,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   }
   std::vector<char> active(nj, 1);
   std::vector<char> nxt(nj, rounds > 0 ? 1 : 0);
+  // standard subdivision: round r halves the kept cells across dimension r mod n
+  const bool bisect = o.subdivision == GIS_SUBDIVIDE_BISECT;
+  B.bisect_dim = bisect ? 0 : -1;
   // round-0 covering: each job's full coarse grid
   if ((rc = ensure(ctx->lvA, (size_t)total + 16)) || (rc = ensure(ctx->ixA, (size_t)total * n * 4 + 16)))
     return rc;
@@ -1189,6 +1223,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     const bool last = r == rounds;
     if (r > 0) {
       for (int j = 0; j < nj; ++j) nxt[j] = (!last && active[j]) ? 1 : 0;
+      B.bisect_dim = bisect ? r % n : -1;
       if ((rc = batch_layout(ctx, B, cells, !last, nxt, s, false))) return fail_all(rc);
     }
     const int64_t n_cells = B.total_cells;
@@ -1371,6 +1406,10 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     next_sizes(ctx, B, n_new, cells);
     for (int j = 0; j < nj; ++j)
       if (!active[j]) cells[j] = 0;
+    if (bisect)  // the next covering lives on the halved grid
+      for (int j = 0; j < nj; ++j)
+        if (active[j] && (rc = bisected(B.jobs[j].grid, B.bisect_dim, &B.jobs[j].grid)))
+          return fail_all(rc);
     cur_is_A = !cur_is_A;
     int64_t tot = 0;
     for (int j = 0; j < nj; ++j) tot += cells[j];
@@ -1607,6 +1646,50 @@ int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
   if ((rc = sync_stats(ctx, B, s))) return rc;
   rc = finish_subdivide(ctx, B, out->cap, &n_new);
   out->n_cells = n_new;
+  return rc;
+}
+
+int32_t gis_bisect(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in, const uint8_t* d_kept,
+                   int32_t dim, gis_grid* grid_out, gis_cells* out, void* stream) {
+  if (!ctx || !grid || !in || !out || !grid_out)
+    return inval("ctx, grid, in, grid_out and out are required");
+  if (grid->n < 1 || grid->n > kMaxDim) return inval("grid dimension must be 1..4");
+  int32_t rc;
+  if ((rc = check_grid(grid, grid->n))) return rc;
+  if (dim < 0 || dim >= grid->n) return inval("dim must be 0..n-1");
+  if (in->n_cells < 0 || (in->n_cells > 0 && (!in->level || !in->idx || !d_kept)))
+    return inval("invalid input cell list");
+  if (out->cap > 0 && (!out->level || !out->idx)) return inval("output buffers missing");
+  GridArgs half{};
+  if ((rc = bisected(make_grid(grid), dim, &half))) return rc;
+  *grid_out = *grid;
+  grid_out->n0[dim] = half.n0[dim];
+  DeviceGuard g(ctx->device);
+  hipStream_t s = as_stream(stream);
+  if (in->n_cells == 0) {
+    out->n_cells = 0;
+    return GIS_OK;
+  }
+  JobSpec js{};
+  js.grid = make_grid(grid);
+  js.sys.n = grid->n;
+  Batch B;
+  if ((rc = batch_init(ctx, B, {js}, 1))) return rc;
+  B.bisect_dim = dim;
+  // no covering index is read: its arrays are laid out but left as they are
+  if ((rc = batch_layout(ctx, B, {in->n_cells}, false, {1}, s, false))) return rc;
+  if ((rc = ensure(ctx->bnd, (size_t)in->n_cells))) return rc;
+  if ((rc = zero_all(ctx, B, s))) return rc;
+  if ((rc = enqueue_subdivide(ctx, B, in->level, in->idx, d_kept, GIS_BOUNDARY_SHELL,
+                              (uint8_t*)ctx->bnd.ptr, out->level, out->idx, out->cap, s, false,
+                              &dcnt(ctx)->err)))
+    return rc;
+  if ((rc = sync_stats(ctx, B, s))) return rc;
+  int64_t n_new = 0;
+  rc = finish_subdivide(ctx, B, out->cap, &n_new);
+  out->n_cells = n_new;
+  if (rc == GIS_OK && ctx->h_counters->err)
+    return inval("a kept cell is not a level-0 cell of the grid");
   return rc;
 }
 

@@ -142,6 +142,13 @@ int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t 
 // batch_compact leaves them zero again).
 int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
                        JobStats* stats, hipStream_t s);
+// Standard subdivision (Sec. 2.1): the next-covering flags of both halves of
+// every kept cell across dimension `dim`, the next layouts being level 0 of
+// the grid with twice the cells along `dim`; split[c] = 1 for the cells cut,
+// stats[j].n_boundary counts them; kept cells not of level 0 or outside the
+// grid are skipped and counted in *err (may be null).
+int32_t batch_bisect(const BatchArgs& b, const uint8_t* kept, int32_t dim, uint8_t* split,
+                     JobStats* stats, uint32_t* err, hipStream_t s);
 // pos: exclusive scan of the batch's next-flag array; writes the new global
 // cell list (up to cap) and each job's next_start / level_start.
 int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,

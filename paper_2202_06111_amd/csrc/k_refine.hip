@@ -201,6 +201,46 @@ __global__ __launch_bounds__(256) void k_boundary(BatchArgs b, const uint8_t* ke
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_boundary, (unsigned long long)__popcll(m));
 }
 
+// Standard subdivision (Sec. 2.1): every kept cell of a level-0 covering is
+// halved across dimension `dim`.  The halves are level-0 cells of the grid
+// on which the next covering's flag array is laid out (the current grid with
+// twice the cells along `dim`); each sets its flag there, and the scan of the
+// flags numbers them canonically, as for the adaptive subdivision.  A kept
+// cell not of level 0 or outside the grid sets no flag and is counted in
+// *err (when err is given).
+__global__ void k_bisect(BatchArgs b, const uint8_t* kept, int32_t dim, uint8_t* split,
+                         JobStats* stats, uint32_t* err) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * blockDim.x + threadIdx.x;
+  const bool live = c < J.n_cells;
+  const int64_t gc = J.cell_off + c;
+  bool cut = live && kept[gc] != 0;
+  if (cut) {
+    const CoverIndex& next = J.next;
+    bool ok = b.level[gc] == 0;
+    int64_t lin = 0, stride = 1;
+    for (int d = 0; d < b.n; ++d) {
+      const int64_t halves = d == dim ? 2 : 1;
+      const int64_t k = (int64_t)b.idx[gc * b.n + d] * halves;
+      ok = ok && k >= 0 && k + halves - 1 < next.dims[0][d];
+      lin = lin * next.dims[0][d] + k;
+      if (d > dim) stride *= next.dims[0][d];
+    }
+    if (ok && next.state) {
+      next.state[next.off[0] + lin] = 1;           // lower half
+      next.state[next.off[0] + lin + stride] = 1;  // upper half
+    }
+    if (!ok) {
+      if (err) atomicAdd(err, 1u);
+      cut = false;
+    }
+  }
+  if (live) split[gc] = cut ? 1 : 0;
+  const uint64_t m = __ballot(cut);  // one atomic per wave (blocks never straddle jobs)
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_boundary, (unsigned long long)__popcll(m));
+}
+
 // pos: exclusive scan of the batch's flag array (jobs' arrays back to back).
 // Clears every flag it consumes, so the array is zero for the next call.
 // Also records each job's first new cell and the new cells before each of
@@ -295,6 +335,14 @@ int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, ui
   return GIS_OK;
 }
 
+int32_t batch_bisect(const BatchArgs& b, const uint8_t* kept, int32_t dim, uint8_t* split,
+                     JobStats* stats, uint32_t* err, hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+  hipLaunchKernelGGL(k_bisect, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, dim,
+                     split, stats, err);
+  GIS_LAUNCH_CHECK("k_bisect");
+  return GIS_OK;
+}
 
 int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,
                       int32_t* idx_out, JobStats* stats, hipStream_t s) {

@@ -24,6 +24,7 @@ SAMPLES = {W.LATTICE3: 1, W.CORNERS_CENTER: 2}
 PRECISION = {"fp64": 1, "fp32_recheck": 2}
 RULE = {W.SHELL: 1, W.CORNERS: 2}
 ANALYSIS = {"controlled": 1, "nonleaving": 2}
+SUBDIVISION = {"boundary": 0, "bisect": 1}
 STATUS = {0: "GIS_OK", 1: "GIS_E_INVAL", 2: "GIS_E_NOMEM", 3: "GIS_E_HIP", 4: "GIS_E_CAPACITY",
           5: "GIS_E_UNSUPPORTED", 6: "GIS_E_INTERNAL"}
 MAX_ROUNDS = 32
@@ -43,7 +44,8 @@ class GridT(ctypes.Structure):
 
 class OptsT(ctypes.Structure):
     _fields_ = [("samples", I32), ("precision", I32), ("boundary_rule", I32), ("analysis", I32),
-                ("fast_out", I32), ("timing", I32), ("reserved", I32 * 2), ("band", F64 * 4)]
+                ("fast_out", I32), ("timing", I32), ("subdivision", I32), ("reserved", I32),
+                ("band", F64 * 4)]
 
 
 class CellsT(ctypes.Structure):
@@ -77,7 +79,7 @@ class RoundStatsT(ctypes.Structure):
 
 
 class SolveInfoT(ctypes.Structure):
-    _fields_ = [("n_rounds", I32), ("n", I32), ("K", I32), ("mask_words", I32),
+    _fields_ = [("n_rounds", I32), ("n", I32), ("K", I32), ("mask_words", I32), ("n0", I32 * 4),
                 ("n_cells", I64), ("n_kept", I64), ("band", F64 * 4),
                 ("rounds", RoundStatsT * MAX_ROUNDS)]
 
@@ -107,6 +109,7 @@ def lib():
             "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
             "gis_subdivide": ([P, P, P, P, I32, P, P, P], I32),
+            "gis_bisect": ([P, P, P, P, I32, P, P, P], I32),
             "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
             "gis_solve_batch": ([P, I32, P, I32, I32, P, P, P], I32),
             "gis_solution_info": ([P, P], I32),
@@ -127,7 +130,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_subdivide",
+EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_subdivide", "gis_bisect",
             "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
             "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
             "gis_last_error", "gis_version")
@@ -167,7 +170,8 @@ def grid_t(grid: W.Grid) -> GridT:
 
 def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: str = W.SHELL,
            analysis: str = "controlled", fast_out: bool = False,
-           band: Optional[Sequence[float]] = None, timing: int = 0) -> OptsT:
+           band: Optional[Sequence[float]] = None, timing: int = 0,
+           subdivision: str = "boundary") -> OptsT:
     o = OptsT()
     o.samples = SAMPLES[samples]
     o.precision = PRECISION[precision]
@@ -175,6 +179,7 @@ def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: st
     o.analysis = ANALYSIS[analysis]
     o.fast_out = int(bool(fast_out))
     o.timing = int(timing)
+    o.subdivision = SUBDIVISION[subdivision]
     for d, v in enumerate([] if band is None else list(band)):
         o.band[d] = float(v)
     return o
@@ -182,7 +187,7 @@ def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: st
 
 def workload_opts(wl: W.Workload, **over) -> OptsT:
     kw = dict(samples=wl.samples, precision=wl.precision, boundary_rule=wl.boundary_rule,
-              analysis=wl.analysis)
+              analysis=wl.analysis, subdivision=wl.subdivision)
     kw.update(over)
     return opts_t(**kw)
 
@@ -340,6 +345,23 @@ def subdivide(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor
     return lv[:n], ix[:n], bnd[:n_cells]
 
 
+def bisect(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor,
+           kept: torch.Tensor, dim: int, stream=None):
+    """Standard subdivision: every kept level-0 cell halved across `dim`;
+    returns (grid of the halves, level, idx)."""
+    n_cells = int(idx.shape[0])
+    cap = max(1, 2 * int(kept.sum().item())) if n_cells else 1
+    lv = torch.empty(cap, dtype=torch.uint8, device=ctx.dev)
+    ix = torch.empty((cap, grid.n), dtype=torch.int32, device=ctx.dev)
+    cin = cells_t(level, idx)
+    cout = cells_t(lv, ix, cap)
+    gt, go = grid_t(grid), GridT()
+    _check(lib().gis_bisect(ctx.handle, ctypes.byref(gt), ctypes.byref(cin), _ptr(kept), int(dim),
+                            ctypes.byref(go), ctypes.byref(cout), _stream_ptr(stream)))
+    n = int(cout.n_cells)
+    return W.Grid(tuple(go.n0[: grid.n]), grid.lo, grid.hi), lv[:n], ix[:n]
+
+
 def images(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, samples: str,
            precision: str = "fp64", stream=None) -> torch.Tensor:
     du = to_device_u(ctx, u)
@@ -371,7 +393,7 @@ def info_dict(inf: SolveInfoT) -> dict:
         s = inf.rounds[r]
         rounds.append({k: getattr(s, k) for k, _ in RoundStatsT._fields_ if k != "reserved"})
     return {"n_rounds": inf.n_rounds, "n": inf.n, "K": inf.K, "mask_words": inf.mask_words,
-            "n_cells": inf.n_cells, "n_kept": inf.n_kept, "band": list(inf.band[: inf.n]),
+            "n0": tuple(inf.n0[: inf.n]), "n_cells": inf.n_cells, "n_kept": inf.n_kept, "band": list(inf.band[: inf.n]),
             "rounds": rounds}
 
 

@@ -73,6 +73,10 @@ class Workload:
     # paper's analysis).  Boundary-only refinement needs the latter: under the
     # controlled analysis a 32x32 Van der Pol covering keeps no cell at all.
     analysis: str = "controlled"
+    # subdivision between rounds: "boundary" (2^n children of the boundary
+    # cells, Sec. 3.1) or "bisect" (every kept cell halved across a cycled
+    # dimension, the standard algorithm of Sec. 2.1)
+    subdivision: str = "boundary"
 
     @property
     def K(self) -> int:
@@ -142,6 +146,15 @@ def vdp_adaptive_32(precision: str = "fp32_recheck") -> Workload:
     return Workload("vdp_adaptive_32x32_r5", vdp(), Grid((32, 32), *VDP_BOX),
                     evenly_spaced(-1.0, 1.0, 21), LATTICE3, 5, precision,
                     analysis="nonleaving")
+
+
+def vdp_standard_32(precision: str = "fp32_recheck") -> Workload:
+    """Van der Pol, 32x32 coarse grid, 6 rounds of the standard algorithm
+    (every kept cell halved, dimensions cycled: 256x256 cells at the end),
+    21 inputs: the baseline that the adaptive workload is compared with."""
+    return Workload("vdp_standard_32x32_r6", vdp(), Grid((32, 32), *VDP_BOX),
+                    evenly_spaced(-1.0, 1.0, 21), LATTICE3, 6, precision,
+                    analysis="nonleaving", subdivision="bisect")
 
 
 def lorenz_uniform_128() -> Workload:
@@ -230,6 +243,7 @@ def random_linear(seed: int, n: int, m: int) -> System:
 ALL = {
     "vdp_uniform_64x64": vdp_uniform_64,
     "vdp_adaptive_32x32_r5": vdp_adaptive_32,
+    "vdp_standard_32x32_r6": vdp_standard_32,
     "lorenz_uniform_128^3": lorenz_uniform_128,
     "vdp2_adaptive_32^4_r2": vdp2_adaptive_32,
     "vdp2_adaptive_32^4_r1": vdp2_adaptive_32_r1,
