@@ -16,6 +16,8 @@ Parity status per function (what pins each one is in tests/test_oracle_*.py):
                   textbook non-leaving set via strongly connected components
   boundary        pinned: the 5x5 worked example of Sec. 3.1.1 and Remark 1
   subdivide/solve pinned: union preservation and monotone shrinking
+  largest_scc     pinned: hand-built graphs, brute-force transitive closure
+                  on random small graphs, inclusion in the non-leaving set
   bisect          pinned: hand-derived 2x2 example, exact halving of every
                   kept cell, loop with nothing removed = the uniform grid
   query           pinned: brute-force point location over the cell list
@@ -231,7 +233,11 @@ def prune(row_ptr, col, out, n_cells: int, K: int, analysis: str = "controlled")
     analysis="controlled": largest set in which every cell has an input whose
     image is not OUT and whose edges all end in the set.
     analysis="nonleaving": vertices with an infinite admissible path in the
-    input-union symbolic image (Definitions 5-6)."""
+    input-union symbolic image (Definitions 5-6).
+    analysis="largest_scc": Definition 6 read literally (largest_scc)."""
+    if analysis == "largest_scc":
+        kept, mask = largest_scc(row_ptr, col, n_cells, K)
+        return kept, mask, 0
     lib = _load()
     row_ptr, col, out = _c(row_ptr, np.int64), _c(col, np.int32), _c(out, np.uint8)
     W = mask_words(K)
@@ -240,6 +246,56 @@ def prune(row_ptr, col, out, n_cells: int, K: int, analysis: str = "controlled")
     sweeps = lib.or_prune(_ptr(row_ptr), _ptr(col), _ptr(out), n_cells, K,
                           _ANALYSES[analysis], _ptr(kept), _ptr(mask), W)
     return kept, mask, int(sweeps)
+
+
+def largest_scc(row_ptr, col, n_cells: int, K: int):
+    """Definition 6 read literally (Sec. 2.3): the vertices of the largest
+    strongly connected component of the input-union symbolic image, plus
+    every vertex with a path into it.  Only components with an infinite path
+    through them count (two or more vertices, or one with an edge to itself);
+    none: the set is empty.  Equally large components: the one holding the
+    smallest cell id.  Mask bit u of a kept cell: row (cell, u) has an edge
+    into the set.  The components come from scipy's strongly connected
+    components; the rest is written out below."""
+    from collections import deque
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    row_ptr, col = _c(row_ptr, np.int64), _c(col, np.int64)
+    rows = np.arange(n_cells * K, dtype=np.int64)
+    src = np.repeat(rows // K, np.diff(row_ptr))
+    A = csr_matrix((np.ones(col.shape[0], dtype=np.int8), (src, col)), shape=(n_cells, n_cells))
+    _, label = connected_components(A, directed=True, connection="strong")
+    members = {}
+    for c in range(n_cells):
+        members.setdefault(int(label[c]), []).append(c)
+    self_loop = set(int(v) for v in src[src == col])
+    best = None
+    for comp in members.values():  # comp is ascending: comp[0] is its smallest id
+        if len(comp) < 2 and comp[0] not in self_loop:
+            continue
+        if best is None or len(comp) > len(best) or (len(comp) == len(best) and comp[0] < best[0]):
+            best = comp
+    kept = np.zeros(n_cells, dtype=np.uint8)
+    if best is not None:
+        preds = [[] for _ in range(n_cells)]
+        for a, b in zip(src.tolist(), col.tolist()):
+            preds[b].append(a)
+        todo = deque(best)
+        for c in best:
+            kept[c] = 1
+        while todo:
+            v = todo.popleft()
+            for a in preds[v]:
+                if not kept[a]:
+                    kept[a] = 1
+                    todo.append(a)
+    W = mask_words(K)
+    mask = np.zeros((n_cells, W), dtype=np.uint64)
+    for r in range(n_cells * K):
+        c, u = divmod(r, K)
+        if kept[c] and kept[col[row_ptr[r]:row_ptr[r + 1]]].any():
+            mask[c, u // 64] |= np.uint64(1) << np.uint64(u % 64)
+    return kept, mask
 
 
 def boundary(grid, level, idx, kept, rule: str = "shell") -> np.ndarray:
