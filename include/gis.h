@@ -30,6 +30,12 @@
  *   GIS_ANALYSIS_NONLEAVING  keep the cells with an infinite admissible path
  *     in the input-union symbolic image (Definitions 5-6): iterated removal of
  *     cells none of whose edges ends in the kept set.
+ *   GIS_ANALYSIS_LARGEST_SCC  Definition 6 read literally: the largest
+ *     strongly connected component of the input-union symbolic image that
+ *     holds a cycle (two or more cells, or one cell with an edge to itself),
+ *     plus every cell with a path into it; of equally large components the
+ *     one holding the smallest cell id; nothing if the graph has no cycle.
+ *     Mask bit u: row (cell, u) has an edge into the kept set.
  * The admissible-input mask of a kept cell has bit u set when row (cell, u)
  * satisfies the analysis' condition at the fixed point.
  *
@@ -79,7 +85,7 @@ enum { GIS_SYS_LINEAR = 0, GIS_SYS_VDP = 1, GIS_SYS_LORENZ = 2, GIS_SYS_VDP2 = 3
 enum { GIS_SAMPLES_LATTICE3 = 1, GIS_SAMPLES_CORNERS_CENTER = 2 };
 enum { GIS_PREC_FP64 = 1, GIS_PREC_FP32_RECHECK = 2 };
 enum { GIS_BOUNDARY_SHELL = 1, GIS_BOUNDARY_CORNERS = 2 };
-enum { GIS_ANALYSIS_CONTROLLED = 1, GIS_ANALYSIS_NONLEAVING = 2 };
+enum { GIS_ANALYSIS_CONTROLLED = 1, GIS_ANALYSIS_NONLEAVING = 2, GIS_ANALYSIS_LARGEST_SCC = 3 };
 enum { GIS_SUBDIVIDE_BOUNDARY = 0, GIS_SUBDIVIDE_BISECT = 1 };
 
 /* Vector field g of x' = g(x, u); f = nsub RK4 substeps of length dt/nsub.

@@ -139,7 +139,8 @@ struct gis_ctx {
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
   DevBuf removed, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front;
-  DevBuf bnd;
+  DevBuf bnd, scc;
+  Pinned<unsigned long long> h_scc;  // largest-component search: per-job keys and counts
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -220,7 +221,8 @@ int32_t check_opts(const gis_opts* o) {
   if (o->subdivision == GIS_SUBDIVIDE_BOUNDARY && o->boundary_rule != GIS_BOUNDARY_SHELL &&
       o->boundary_rule != GIS_BOUNDARY_CORNERS)
     return inval("unknown boundary rule");
-  if (o->analysis != GIS_ANALYSIS_CONTROLLED && o->analysis != GIS_ANALYSIS_NONLEAVING)
+  if (o->analysis != GIS_ANALYSIS_CONTROLLED && o->analysis != GIS_ANALYSIS_NONLEAVING &&
+      o->analysis != GIS_ANALYSIS_LARGEST_SCC)
     return inval("unknown analysis");
   return GIS_OK;
 }
@@ -709,6 +711,49 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
                      frontier, s);
 }
 
+// Definition 6 read literally, after the non-leaving analysis has reached
+// its fixed point (its removed flags are the start): narrows the removed
+// flags to the largest component's set and reruns the final pass (kept
+// flags, masks, kept counts, holes of the covering index).  Synchronises.
+int32_t largest_component_stage(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
+                                const uint8_t* out, int64_t n_cells, int32_t K, uint8_t* kept,
+                                uint64_t* mask, hipStream_t s, const Batch* B = nullptr,
+                                const uint8_t* level = nullptr, const int32_t* idx = nullptr) {
+  if (n_cells == 0) return GIS_OK;
+  const int32_t nj = B ? B->n_jobs : 1;
+  int32_t rc;
+  const size_t up = 256;
+  auto al = [&](size_t x) { return (x + up - 1) / up * up; };
+  const size_t o4 = al((size_t)n_cells * 4), o1 = al((size_t)n_cells);
+  if ((rc = ensure(ctx->scc, 4 * o4 + 4 * o1 + al(16 * (size_t)nj) + 256))) return rc;
+  if ((rc = ctx->h_scc.ensure(2 * (size_t)nj + 1))) return rc;
+  uint8_t* b = (uint8_t*)ctx->scc.ptr;
+  SccWork w{};
+  w.color = (int32_t*)b;
+  w.comp = (int32_t*)(b + o4);
+  w.size = (int32_t*)(b + 2 * o4);
+  w.minid = (int32_t*)(b + 3 * o4);
+  w.rem = b + 4 * o4;
+  w.bw = b + 4 * o4 + o1;
+  w.loop = b + 4 * o4 + 2 * o1;
+  w.inset = b + 4 * o4 + 3 * o1;
+  w.best = (unsigned long long*)(b + 4 * o4 + 4 * o1);
+  w.left = w.best + nj;
+  w.last = (uint32_t*)(b + 4 * o4 + 4 * o1 + al(16 * (size_t)nj));
+  w.h_best = ctx->h_scc.h;
+  w.h_last = (uint32_t*)(ctx->h_scc.h + 2 * nj);
+  uint8_t* removed = (uint8_t*)ctx->removed.ptr;
+  if ((rc = largest_component_set(row_ptr, col, n_cells, K, B ? B->d_jobs : nullptr, nj, removed,
+                                  w, s)))
+    return rc;
+  // the final pass against the narrowed removed flags; kept counts restart
+  if ((rc = fill_u32((uint32_t*)dcnt(ctx)->n_kept, 0u, 4, s))) return rc;
+  if (B && (rc = batch_clear_kept(B->d_stats, B->n_jobs, s))) return rc;
+  const PruneWork pw = prune_work(ctx, 0, nullptr);
+  return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, GIS_ANALYSIS_NONLEAVING, pw,
+                                kept, mask, 0, s, B, level, idx, 0);
+}
+
 bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
   return K <= 256 && n_edges <= ctx->tune.sweep_edges;
 }
@@ -1146,6 +1191,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   std::vector<char> nxt(nj, rounds > 0 ? 1 : 0);
   // standard subdivision: round r halves the kept cells across dimension r mod n
   const bool bisect = o.subdivision == GIS_SUBDIVIDE_BISECT;
+  // the largest-component reading runs the non-leaving analysis first
+  const bool scc = o.analysis == GIS_ANALYSIS_LARGEST_SCC;
+  const int32_t an = scc ? GIS_ANALYSIS_NONLEAVING : o.analysis;
   B.bisect_dim = bisect ? 0 : -1;
   // round-0 covering: each job's full coarse grid
   if ((rc = ensure(ctx->lvA, (size_t)total + 16)) || (rc = ensure(ctx->ixA, (size_t)total * n * 4 + 16)))
@@ -1267,10 +1315,10 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       int32_t e;
       if ((e = enqueue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.cap_edges,
                              &dcnt(ctx)->total_edges, (int64_t)(edges_per_row * (double)n_rows),
-                             o.analysis, kept, mask, s, &B, lv, ix, sweep_hint, false)))
+                             an, kept, mask, s, &B, lv, ix, sweep_hint, false)))
         return e;
       if (phases) GIS_HIP(hipEventRecord(ev[2], s));
-      if (!last && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
+      if (!last && !scc && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                           (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
                                           (int32_t*)ixN.ptr, cap, s, K <= 256)))
         return e;
@@ -1337,10 +1385,10 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
       if (phases) GIS_HIP(hipEventRecord(ev[1], s));
       if ((rc = continue_prune(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, gr.n_edges,
-                               gr.cap_edges, o.analysis, kept, mask, s, &B, lv, ix)))
+                               gr.cap_edges, an, kept, mask, s, &B, lv, ix)))
         return fail_all(rc);
       if (phases) GIS_HIP(hipEventRecord(ev[2], s));
-      if (!last && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
+      if (!last && !scc && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
                                            (int32_t*)ixN.ptr, cap, s, K <= 256)))
         return fail_all(rc);
@@ -1352,6 +1400,28 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
         GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
       }
       ms_p += ms_p2;
+      ctx->h_counters->total_edges = keep.total_edges;
+      ctx->h_counters->n_recheck = keep.n_recheck;
+      for (int j = 0; j < nj; ++j) {
+        ctx->h_stats[j].n_edges = build_stats[j].n_edges;
+        ctx->h_stats[j].n_out = build_stats[j].n_out;
+        ctx->h_stats[j].n_recheck = build_stats[j].n_recheck;
+      }
+    }
+    if (scc) {
+      // Definition 6 read literally: narrow the non-leaving fixed point to
+      // the largest component's set, then subdivide (the build's counts are
+      // kept across the stage's synchronisations)
+      const Counters keep = *ctx->h_counters;
+      std::vector<JobStats> build_stats(ctx->h_stats, ctx->h_stats + nj);
+      if ((rc = largest_component_stage(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, kept, mask, s,
+                                        &B, lv, ix)))
+        return fail_all(rc);
+      if (!last && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
+                                           (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
+                                           (int32_t*)ixN.ptr, cap, s, K <= 256)))
+        return fail_all(rc);
+      if ((rc = sync_stats(ctx, B, s))) return fail_all(rc);
       ctx->h_counters->total_edges = keep.total_edges;
       ctx->h_counters->n_recheck = keep.n_recheck;
       for (int j = 0; j < nj; ++j) {
@@ -1481,7 +1551,8 @@ void gis_ctx_destroy(gis_ctx* c) {
   DevBuf* bufs[] = {&c->counters, &c->jobs, &c->maxerr, &c->lookback, &c->scan_tmp,
                     &c->idx_state, &c->idx_pfx,
                     &c->next_state, &c->pos, &c->removed, &c->rptr, &c->rrow, &c->rsrc, &c->rmask,
-                    &c->rcur, &c->rowstate, &c->good, &c->front, &c->bnd, &c->lvA, &c->ixA,
+                    &c->rcur, &c->rowstate, &c->good, &c->front, &c->bnd, &c->scc, &c->lvA,
+                    &c->ixA,
                     &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
   for (DevBuf* b : bufs) release(*b);
@@ -1491,6 +1562,7 @@ void gis_ctx_destroy(gis_ctx* c) {
   c->h_flag.free();
   c->h_jobs.free();
   c->h_maxerr.free();
+  c->h_scc.free();
   for (int i = 0; i < 3; ++i)
     if (c->timer.ev[i]) (void)hipEventDestroy(c->timer.ev[i]);
   for (int i = 0; i < 4; ++i)
@@ -1565,7 +1637,8 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
                   int32_t analysis, uint8_t* d_kept, uint64_t* d_mask, int64_t* n_kept,
                   void* stream) {
   if (!ctx || !graph) return inval("ctx and graph are required");
-  if (analysis != GIS_ANALYSIS_CONTROLLED && analysis != GIS_ANALYSIS_NONLEAVING)
+  if (analysis != GIS_ANALYSIS_CONTROLLED && analysis != GIS_ANALYSIS_NONLEAVING &&
+      analysis != GIS_ANALYSIS_LARGEST_SCC)
     return inval("unknown analysis");
   if (n_cells < 0 || K < 1) return inval("invalid sizes");
   if (graph->n_rows != n_cells * K) return inval("graph rows != n_cells * K");
@@ -1591,13 +1664,19 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
   if (ctx->h_counters->err & 1u) return inval("graph row offsets are inconsistent");
   if (ctx->h_counters->err & 2u) return inval("graph targets are not cell ids");
   if ((rc = zero_counters(ctx, s))) return rc;
+  // the largest-component reading starts from the non-leaving fixed point
+  const bool scc = analysis == GIS_ANALYSIS_LARGEST_SCC;
+  const int32_t an = scc ? GIS_ANALYSIS_NONLEAVING : analysis;
   if ((rc = enqueue_prune(ctx, graph->row_ptr, graph->col, graph->out, n_cells, K, graph->n_edges,
-                          nullptr, graph->n_edges, analysis, d_kept, d_mask, s)))
+                          nullptr, graph->n_edges, an, d_kept, d_mask, s)))
     return rc;
   if ((rc = sync_counters(ctx, s))) return rc;
   if (!prune_converged(ctx, n_cells) &&
       (rc = continue_prune(ctx, graph->row_ptr, graph->col, graph->out, n_cells, K, graph->n_edges,
-                           graph->n_edges, analysis, d_kept, d_mask, s)))
+                           graph->n_edges, an, d_kept, d_mask, s)))
+    return rc;
+  if (scc && (rc = largest_component_stage(ctx, graph->row_ptr, graph->col, graph->out, n_cells, K,
+                                           d_kept, d_mask, s)))
     return rc;
   if ((rc = sync_counters(ctx, s))) return rc;
   if (n_kept) *n_kept = (int64_t)ctx->h_counters->n_kept[0];

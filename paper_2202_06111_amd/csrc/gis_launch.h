@@ -136,6 +136,24 @@ int32_t batch_index_build(const BatchArgs& b, uint32_t* d_err, const uint8_t* st
                           hipStream_t s);
 int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t s);
 
+// k_scc.hip: Definition 6 read literally.  Work arrays, [n_cells] each
+// unless stated; best and left are adjacent ([n_jobs] each), h_best pinned
+// host memory of [2 * n_jobs] and h_last of one word.
+struct SccWork {
+  int32_t *color, *comp, *size, *minid;
+  uint8_t *rem, *bw, *loop, *inset;
+  unsigned long long *best, *left;
+  uint32_t* last;
+  unsigned long long* h_best;
+  uint32_t* h_last;
+};
+// removed: in, the non-leaving analysis' removed flags; out, 1 for every cell
+// outside the largest component with a cycle and the cells with a path into
+// it (per job of `jobs`, or one job when jobs is null).  Synchronises s.
+int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_t n_cells,
+                              int32_t K, const Job* jobs, int32_t n_jobs, uint8_t* removed,
+                              const SccWork& w, hipStream_t s);
+
 // k_refine.hip, job-batched
 // Boundary flags of the kept cells (Sec. 3.1.1) and, for jobs with a next
 // layout, the next-covering flags (those arrays are zero on entry;
@@ -154,6 +172,8 @@ int32_t batch_bisect(const BatchArgs& b, const uint8_t* kept, int32_t dim, uint8
 int32_t batch_compact(const BatchArgs& b, const int64_t* pos, int64_t cap, uint8_t* level_out,
                       int32_t* idx_out, JobStats* stats, hipStream_t s);
 int32_t batch_coarse(const BatchArgs& b, uint8_t* level, int32_t* idx, hipStream_t s);
+// stats[j].n_kept = 0 for every job.
+int32_t batch_clear_kept(JobStats* stats, int32_t n_jobs, hipStream_t s);
 // Kept cells per job into stats[j].n_kept.
 int32_t batch_count_kept(const BatchArgs& b, const uint8_t* kept, JobStats* stats, hipStream_t s);
 // The same from the job table alone (any launch layout).

@@ -300,7 +300,20 @@ __global__ void k_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_ce
     if (kept[c]) atomicAdd(&stats[job_of_cell(jobs, n_jobs, c)].n_kept, 1ull);
 }
 
+__global__ void k_clear_kept(JobStats* stats, int32_t n_jobs) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n_jobs) stats[j].n_kept = 0;
+}
+
 }  // namespace
+
+int32_t batch_clear_kept(JobStats* stats, int32_t n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return GIS_OK;
+  hipLaunchKernelGGL(k_clear_kept, dim3((unsigned)((n_jobs + 255) / 256)), dim3(256), 0, s, stats,
+                     n_jobs);
+  GIS_LAUNCH_CHECK("k_clear_kept");
+  return GIS_OK;
+}
 
 int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
                                const uint8_t* kept, JobStats* stats, hipStream_t s) {

@@ -1,0 +1,300 @@
+// Definition 6 read literally (Sec. 2.3): the vertices of the largest
+// strongly connected component of the input-union symbolic image, plus every
+// vertex with a path into it.  Only components with a cycle count (two or
+// more cells, or one with an edge to itself); equally large components go to
+// the one holding the smallest cell id; per job of a batch.
+//
+// Every component with a cycle lies in the non-leaving set (cells with an
+// infinite path), which the caller has computed; the search starts from it.
+// Components come from max-colour propagation: each candidate cell starts
+// with its own id as colour and takes the largest colour of a candidate
+// predecessor until nothing changes, so colour(c) is the largest id that
+// reaches c.  A cell whose colour is its own id is a root; the cells of its
+// colour that reach it are its component.  Every round of the search takes
+// the components of all roots out of the candidates; it ends for a job when
+// its best component is larger than what is left of its candidates.  Then a
+// backward search from the best component gives the set.
+//
+// All passes are in-place sweeps over the rows (one thread per row, the
+// row's cell from row / K) to a fixed point, checked every few sweeps: each
+// sweep that changes something records its number, and a batch whose last
+// sweep changed nothing has converged.
+#include "gis_launch.h"
+
+namespace gis {
+
+namespace {
+
+__device__ __forceinline__ int32_t job_at(const Job* jobs, int32_t n_jobs, int64_t c) {
+  return jobs ? job_of_cell(jobs, n_jobs, c) : 0;
+}
+
+__device__ __forceinline__ int64_t first_cell(const Job* jobs, int32_t j) {
+  return jobs ? jobs[j].cell_off : 0;
+}
+
+// candidates = the non-leaving cells; no component assigned yet
+__global__ void k_scc_begin(int64_t n, const uint8_t* removed, uint8_t* rem, int32_t* comp) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    rem[c] = removed[c] ? 0 : 1;
+    comp[c] = -1;
+  }
+}
+
+// a round's start: own colours, cleared reach flags and tallies
+__global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint8_t* bw,
+                            int32_t* size, int32_t* minid, uint8_t* loop) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    color[c] = rem[c] ? (int32_t)c : -1;
+    bw[c] = 0;
+    size[c] = 0;
+    minid[c] = INT32_MAX;
+    loop[c] = 0;
+  }
+}
+
+// one sweep of max-colour propagation along the edges of candidate cells
+__global__ void k_scc_color(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
+                            const uint8_t* rem, int32_t* color, uint32_t* last, uint32_t sweep) {
+  bool changed = false;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = r / K;
+    if (!rem[c]) continue;
+    const int32_t cc = color[c];
+    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+      const int32_t v = col[e];
+      if (rem[v] && color[v] < cc) {
+        atomicMax(&color[v], cc);
+        changed = true;
+      }
+    }
+  }
+  const uint64_t m = __ballot(changed);  // one atomic per wave
+  if (m && (threadIdx.x & 63) == 0) atomicMax(last, sweep);
+}
+
+// roots: candidate cells whose colour is their own id
+__global__ void k_scc_roots(int64_t n, const uint8_t* rem, const int32_t* color, uint8_t* bw) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    bw[c] = rem[c] && color[c] == (int32_t)c ? 1 : 0;
+}
+
+// one sweep of the backward search inside each colour: a candidate cell with
+// an edge to a marked cell of its own colour reaches that colour's root
+__global__ void k_scc_back(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
+                           const uint8_t* rem, const int32_t* color, uint8_t* bw, uint32_t* last,
+                           uint32_t sweep) {
+  bool changed = false;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = r / K;
+    if (!rem[c] || bw[c]) continue;
+    const int32_t cc = color[c];
+    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+      const int32_t v = col[e];
+      if (bw[v] && color[v] == cc) {
+        bw[c] = 1;
+        changed = true;
+        break;
+      }
+    }
+  }
+  const uint64_t m = __ballot(changed);  // one atomic per wave
+  if (m && (threadIdx.x & 63) == 0) atomicMax(last, sweep);
+}
+
+// size and smallest id of every root's component; self-loops of roots
+__global__ void k_scc_tally(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
+                            const int32_t* color, const uint8_t* bw, int32_t* size, int32_t* minid,
+                            uint8_t* loop) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = r / K;
+    if (!bw[c]) continue;
+    const int32_t root = color[c];
+    if (r % K == 0) {
+      atomicAdd(&size[root], 1);
+      atomicMin(&minid[root], (int32_t)c);
+    }
+    if (root == (int32_t)c)
+      for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
+        if (col[e] == (int32_t)c) loop[c] = 1;
+  }
+}
+
+// the round's components leave the candidates (each cell keeps its
+// component's smallest id); each job's best component with a cycle is kept
+// as the key (size, -smallest id within the job)
+__global__ void k_scc_pick(int64_t n, const Job* jobs, int32_t n_jobs, uint8_t* rem,
+                           const int32_t* color, const uint8_t* bw, const int32_t* size,
+                           const int32_t* minid, const uint8_t* loop, int32_t* comp,
+                           unsigned long long* best) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (!rem[c] || !bw[c]) continue;
+    const int32_t root = color[c];
+    comp[c] = minid[root];
+    rem[c] = 0;
+    if (root == (int32_t)c && (size[c] >= 2 || loop[c])) {
+      const int32_t j = job_at(jobs, n_jobs, c);
+      const uint32_t local = (uint32_t)(minid[c] - first_cell(jobs, j));
+      const unsigned long long key =
+          ((unsigned long long)(uint32_t)size[c] << 32) | (unsigned long long)(0xFFFFFFFFu - local);
+      atomicMax(&best[j], key);
+    }
+  }
+}
+
+// candidates left per job
+__global__ void k_scc_left(int64_t n, const Job* jobs, int32_t n_jobs, const uint8_t* rem,
+                           unsigned long long* left) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    if (rem[c]) atomicAdd(&left[job_at(jobs, n_jobs, c)], 1ull);
+}
+
+// the set starts as each job's best component
+__global__ void k_scc_seed(int64_t n, const Job* jobs, int32_t n_jobs, const int32_t* comp,
+                           const unsigned long long* best, uint8_t* inset) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = job_at(jobs, n_jobs, c);
+    const unsigned long long k = best[j];
+    const int64_t want = first_cell(jobs, j) + (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
+    inset[c] = k != 0 && comp[c] >= 0 && (int64_t)comp[c] == want ? 1 : 0;
+  }
+}
+
+// one sweep of the backward search from the set over all cells
+__global__ void k_scc_reach(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
+                            uint8_t* inset, uint32_t* last, uint32_t sweep) {
+  bool changed = false;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = r / K;
+    if (inset[c]) continue;
+    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
+      if (inset[col[e]]) {
+        inset[c] = 1;
+        changed = true;
+        break;
+      }
+  }
+  const uint64_t m = __ballot(changed);  // one atomic per wave
+  if (m && (threadIdx.x & 63) == 0) atomicMax(last, sweep);
+}
+
+__global__ void k_scc_end(int64_t n, const uint8_t* inset, uint8_t* removed) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    removed[c] = inset[c] ? 0 : 1;
+}
+
+unsigned blocks_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+// Runs `sweep(id)` in batches until a batch's last sweep changed nothing;
+// at most `bound` sweeps (then the pass did not converge: internal error).
+template <typename F>
+int32_t to_fixed_point(const SccWork& w, int64_t bound, hipStream_t s, F&& sweep) {
+  int32_t batch = 4;
+  for (int64_t done = 0;;) {
+    int32_t rc = fill_u32(w.last, 0u, 1, s);
+    if (rc) return rc;
+    for (int32_t i = 1; i <= batch; ++i)
+      if ((rc = sweep((uint32_t)i))) return rc;
+    GIS_HIP(hipMemcpyAsync(w.h_last, w.last, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    GIS_HIP(hipStreamSynchronize(s));
+    done += batch;
+    if (*w.h_last < (uint32_t)batch) return GIS_OK;
+    if (done > bound) {
+      set_error("internal: a component search did not converge");
+      return GIS_E_INTERNAL;
+    }
+    if (batch < 64) batch *= 2;
+  }
+}
+
+}  // namespace
+
+int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_t n_cells,
+                              int32_t K, const Job* jobs, int32_t n_jobs, uint8_t* removed,
+                              const SccWork& w, hipStream_t s) {
+  if (n_cells == 0) return GIS_OK;
+  const int64_t n_rows = n_cells * K;
+  const unsigned gc = blocks_for(n_cells), gr = blocks_for(n_rows);
+  int32_t rc;
+  if ((rc = fill_u32((uint32_t*)w.best, 0u, 2 * (int64_t)n_jobs, s))) return rc;
+  hipLaunchKernelGGL(k_scc_begin, dim3(gc), dim3(256), 0, s, n_cells, removed, w.rem, w.comp);
+  GIS_LAUNCH_CHECK("k_scc_begin");
+  for (int64_t round = 0;; ++round) {
+    if (round > n_cells) {  // every round takes at least one component out
+      set_error("internal: the component search did not end");
+      return GIS_E_INTERNAL;
+    }
+    hipLaunchKernelGGL(k_scc_round, dim3(gc), dim3(256), 0, s, n_cells, (const uint8_t*)w.rem,
+                       w.color, w.bw, w.size, w.minid, w.loop);
+    GIS_LAUNCH_CHECK("k_scc_round");
+    rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+      hipLaunchKernelGGL(k_scc_color, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
+                         (const uint8_t*)w.rem, w.color, w.last, id);
+      GIS_LAUNCH_CHECK("k_scc_color");
+      return GIS_OK;
+    });
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scc_roots, dim3(gc), dim3(256), 0, s, n_cells, (const uint8_t*)w.rem,
+                       (const int32_t*)w.color, w.bw);
+    GIS_LAUNCH_CHECK("k_scc_roots");
+    rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+      hipLaunchKernelGGL(k_scc_back, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
+                         (const uint8_t*)w.rem, (const int32_t*)w.color, w.bw, w.last, id);
+      GIS_LAUNCH_CHECK("k_scc_back");
+      return GIS_OK;
+    });
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scc_tally, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
+                       (const int32_t*)w.color, (const uint8_t*)w.bw, w.size, w.minid, w.loop);
+    GIS_LAUNCH_CHECK("k_scc_tally");
+    hipLaunchKernelGGL(k_scc_pick, dim3(gc), dim3(256), 0, s, n_cells, jobs, n_jobs, w.rem,
+                       (const int32_t*)w.color, (const uint8_t*)w.bw, (const int32_t*)w.size,
+                       (const int32_t*)w.minid, (const uint8_t*)w.loop, w.comp, w.best);
+    GIS_LAUNCH_CHECK("k_scc_pick");
+    if ((rc = fill_u32((uint32_t*)w.left, 0u, 2 * (int64_t)n_jobs, s))) return rc;
+    hipLaunchKernelGGL(k_scc_left, dim3(gc), dim3(256), 0, s, n_cells, jobs, n_jobs,
+                       (const uint8_t*)w.rem, w.left);
+    GIS_LAUNCH_CHECK("k_scc_left");
+    GIS_HIP(hipMemcpyAsync(w.h_best, w.best, sizeof(unsigned long long) * 2 * n_jobs,
+                           hipMemcpyDeviceToHost, s));  // best and left are adjacent
+    GIS_HIP(hipStreamSynchronize(s));
+    // a job is done when nothing is left or its best component is larger
+    // than all that is left (an equally large one could hold a smaller id)
+    bool done = true;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+      const unsigned long long left = w.h_best[n_jobs + j];
+      done = done && (left == 0 || (w.h_best[j] >> 32) > left);
+    }
+    if (done) break;
+  }
+  hipLaunchKernelGGL(k_scc_seed, dim3(gc), dim3(256), 0, s, n_cells, jobs, n_jobs,
+                     (const int32_t*)w.comp, (const unsigned long long*)w.best, w.inset);
+  GIS_LAUNCH_CHECK("k_scc_seed");
+  rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+    hipLaunchKernelGGL(k_scc_reach, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K, w.inset,
+                       w.last, id);
+    GIS_LAUNCH_CHECK("k_scc_reach");
+    return GIS_OK;
+  });
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_scc_end, dim3(gc), dim3(256), 0, s, n_cells, (const uint8_t*)w.inset,
+                     removed);
+  GIS_LAUNCH_CHECK("k_scc_end");
+  return GIS_OK;
+}
+
+}  // namespace gis

@@ -23,7 +23,7 @@ KIND = {W.LINEAR: 0, W.VDP: 1, W.LORENZ: 2, W.VDP2: 3}
 SAMPLES = {W.LATTICE3: 1, W.CORNERS_CENTER: 2}
 PRECISION = {"fp64": 1, "fp32_recheck": 2}
 RULE = {W.SHELL: 1, W.CORNERS: 2}
-ANALYSIS = {"controlled": 1, "nonleaving": 2}
+ANALYSIS = {"controlled": 1, "nonleaving": 2, "largest_scc": 3}
 SUBDIVISION = {"boundary": 0, "bisect": 1}
 STATUS = {0: "GIS_OK", 1: "GIS_E_INVAL", 2: "GIS_E_NOMEM", 3: "GIS_E_HIP", 4: "GIS_E_CAPACITY",
           5: "GIS_E_UNSUPPORTED", 6: "GIS_E_INTERNAL"}
