@@ -21,6 +21,7 @@ solves; the chosen parameters are reported under "schedule".
 Prints one JSON line on stdout.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -46,6 +47,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="vdp_adaptive_32x32_r5")
     p.add_argument("--precision", default=None, help="fp64 or fp32_recheck (default: workload's)")
+    p.add_argument("--analysis", default=None,
+                   help="controlled, nonleaving or largest_scc (default: workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default schedule parameters instead of running the autotuner "
@@ -147,6 +150,8 @@ def main():
     if a.workload not in W.ALL:
         sys.exit(f"unknown workload {a.workload}; choose from {sorted(W.ALL)}")
     wl = W.ALL[a.workload]()
+    if a.analysis:
+        wl = dataclasses.replace(wl, analysis=a.analysis)
     precision = a.precision or wl.precision
     if a.copy_calibration_mib > 0:
         n = a.copy_calibration_mib << 18  # float32 elements
