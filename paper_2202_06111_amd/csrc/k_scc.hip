@@ -5,7 +5,8 @@
 // the one holding the smallest cell id; per job of a batch.
 //
 // Every component with a cycle lies in the non-leaving set (cells with an
-// infinite path), which the caller has computed; the search starts from it.
+// infinite path), which the caller has computed; the search starts from it,
+// less the cells that a backward trim shows to lie on no cycle.
 // Components come from max-colour propagation: each candidate cell starts
 // with its own id as colour and takes the largest colour of a candidate
 // predecessor until nothing changes, so colour(c) is the largest id that
@@ -18,7 +19,9 @@
 // All passes are in-place sweeps over the rows (one thread per row, the
 // row's cell from row / K) to a fixed point, checked every few sweeps: each
 // sweep that changes something records its number, and a batch whose last
-// sweep changed nothing has converged.
+// sweep changed nothing has converged.  Sweeps alternate between ascending
+// and descending row order, so that a change travels far along paths of
+// either direction within one sweep.
 #include "gis_launch.h"
 
 namespace gis {
@@ -42,6 +45,32 @@ __global__ void k_scc_begin(int64_t n, const uint8_t* removed, uint8_t* rem, int
   }
 }
 
+// backward trim, one step: mark the candidates with a candidate predecessor
+__global__ void k_scc_haspred(const int64_t* row_ptr, const int32_t* col, int64_t n_rows,
+                              int32_t K, const uint8_t* rem, uint8_t* haspred) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = r / K;
+    if (!rem[c]) continue;
+    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
+      if (rem[col[e]]) haspred[col[e]] = 1;
+  }
+}
+
+// ... and drop the candidates without one (no cycle passes through them)
+__global__ void k_scc_trim(int64_t n, uint8_t* rem, const uint8_t* haspred, uint32_t* last,
+                           uint32_t sweep) {
+  bool changed = false;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    if (rem[c] && !haspred[c]) {
+      rem[c] = 0;
+      changed = true;
+    }
+  const uint64_t m = __ballot(changed);  // one atomic per wave
+  if (m && (threadIdx.x & 63) == 0) atomicMax(last, sweep);
+}
+
 // a round's start: own colours, cleared reach flags and tallies
 __global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint8_t* bw,
                             int32_t* size, int32_t* minid, uint8_t* loop) {
@@ -59,8 +88,9 @@ __global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint8
 __global__ void k_scc_color(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
                             const uint8_t* rem, int32_t* color, uint32_t* last, uint32_t sweep) {
   bool changed = false;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-       r += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = (sweep & 1) ? q : n_rows - 1 - q;
     const int64_t c = r / K;
     if (!rem[c]) continue;
     const int32_t cc = color[c];
@@ -89,8 +119,9 @@ __global__ void k_scc_back(const int64_t* row_ptr, const int32_t* col, int64_t n
                            const uint8_t* rem, const int32_t* color, uint8_t* bw, uint32_t* last,
                            uint32_t sweep) {
   bool changed = false;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-       r += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = (sweep & 1) ? q : n_rows - 1 - q;
     const int64_t c = r / K;
     if (!rem[c] || bw[c]) continue;
     const int32_t cc = color[c];
@@ -173,8 +204,9 @@ __global__ void k_scc_seed(int64_t n, const Job* jobs, int32_t n_jobs, const int
 __global__ void k_scc_reach(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
                             uint8_t* inset, uint32_t* last, uint32_t sweep) {
   bool changed = false;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-       r += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = (sweep & 1) ? q : n_rows - 1 - q;
     const int64_t c = r / K;
     if (inset[c]) continue;
     for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
@@ -233,6 +265,22 @@ int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_
   if ((rc = fill_u32((uint32_t*)w.best, 0u, 2 * (int64_t)n_jobs, s))) return rc;
   hipLaunchKernelGGL(k_scc_begin, dim3(gc), dim3(256), 0, s, n_cells, removed, w.rem, w.comp);
   GIS_LAUNCH_CHECK("k_scc_begin");
+  // backward trim: candidates with no candidate predecessor lie on no cycle;
+  // dropping them layer by layer leaves the cycles and the cells between
+  // them (the non-leaving set's transient cells would otherwise take one
+  // search round per layer)
+  rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+    int32_t e = fill_u8(w.bw, 0, n_cells, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_scc_haspred, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
+                       (const uint8_t*)w.rem, w.bw);
+    GIS_LAUNCH_CHECK("k_scc_haspred");
+    hipLaunchKernelGGL(k_scc_trim, dim3(gc), dim3(256), 0, s, n_cells, w.rem,
+                       (const uint8_t*)w.bw, w.last, id);
+    GIS_LAUNCH_CHECK("k_scc_trim");
+    return GIS_OK;
+  });
+  if (rc) return rc;
   for (int64_t round = 0;; ++round) {
     if (round > n_cells) {  // every round takes at least one component out
       set_error("internal: the component search did not end");
