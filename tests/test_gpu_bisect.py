@@ -180,3 +180,10 @@ def test_solve_batch_standard(G, ctx):
     sols = G.solve_batch(ctx, wls)
     for wl, sol in zip(wls, sols):
         _check(G, ctx, wl, sol)
+
+
+def test_solve_standard_workload_full_size(G, ctx):
+    """The benchmarked standard-loop workload itself (Van der Pol 32x32, six
+    halvings to 256x256, 21 inputs, FP32 + FP64 recheck), whole solve."""
+    wl = W.vdp_standard_32()
+    _check(G, ctx, wl, G.solve_workload(ctx, wl))

@@ -150,3 +150,10 @@ def test_solve_batch_largest_scc(G, ctx):
                                      grid=W.Grid((12, 14), *W.VDP_BOX))]
     for wl, sol in zip(wls, G.solve_batch(ctx, wls)):
         _check_solve(G, wl, sol, ctx)
+
+
+def test_solve_largest_scc_default_workload(G, ctx):
+    """The default benchmark workload (adaptive Van der Pol 32x32, five
+    boundary rounds, 21 inputs) under the literal analysis, whole solve."""
+    wl = dataclasses.replace(W.vdp_adaptive_32(), analysis="largest_scc")
+    _check_solve(G, wl, G.solve_workload(ctx, wl), ctx)
