@@ -12,7 +12,8 @@ A second measurement, "serving", runs the mixed stream of smaller solves
 continuous-batching server and reports solves/s and p50/p99 latency.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--precision fp64|fp32_recheck] [--no-cpu-baseline]
+                       [--precision fp64|fp32_recheck]
+                       [--analysis controlled|nonleaving|largest_scc] [--no-cpu-baseline]
                        [--no-autotune] [--tuning field=value,...] [--serve-requests N]
 
 Before the warm-up, the library's autotuner picks the schedule parameters
