@@ -187,3 +187,18 @@ def test_solve_standard_workload_full_size(G, ctx):
     halvings to 256x256, 21 inputs, FP32 + FP64 recheck), whole solve."""
     wl = W.vdp_standard_32()
     _check(G, ctx, wl, G.solve_workload(ctx, wl))
+
+
+def test_bisect_cell_count_limit(G, ctx):
+    """A halving that would put more than 2^30 cells along a dimension is
+    refused before any work (GIS_E_UNSUPPORTED), and the context still works."""
+    grid = W.Grid(((1 << 29) + 1, 2), (0.0, 0.0), (1.0, 1.0))
+    idx = np.array([[5, 1]], np.int32)
+    lv = _dev(ctx, np.zeros(1), np.uint8)
+    kept = _dev(ctx, np.ones(1), np.uint8)
+    with pytest.raises(G.GisError, match="GIS_E_UNSUPPORTED"):
+        G.bisect(ctx, grid, lv, _dev(ctx, idx, np.int32), kept, 0)
+    small = W.Grid((7, 2), (0.0, 0.0), (1.0, 1.0))
+    g2, _, got = G.bisect(ctx, small, lv, _dev(ctx, idx, np.int32), kept, 1)
+    assert tuple(g2.n0) == (7, 4)
+    np.testing.assert_array_equal(_np(got), [[5, 2], [5, 3]])
