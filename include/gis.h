@@ -115,17 +115,27 @@ typedef struct gis_opts {
                              finest-level face or of the border of X */
   int32_t boundary_rule;  /* GIS_BOUNDARY_* */
   int32_t analysis;       /* GIS_ANALYSIS_* */
-  int32_t fast_out;       /* nonzero: OUT rows get no edges (analysis results unchanged) */
+  int32_t fast_out;       /* nonzero: OUT rows get no edges.  The controlled analysis gives
+                             the same kept set and masks either way (an OUT row never keeps
+                             its cell); the other analyses count an OUT row's edges, so
+                             fast_out requires analysis GIS_ANALYSIS_CONTROLLED
+                             (GIS_E_INVAL otherwise) */
   int32_t timing;         /* HIP-event timings in gis_round_stats: 1 the build kernel (ms_image),
                              2 also the phases (ms_build, ms_prune, ms_subdivide); 0 none */
   int32_t subdivision;    /* GIS_SUBDIVIDE_*: gis_solve refines the 2^n children of the
                              boundary cells (BOUNDARY, 0), or halves every kept cell across
                              the cycled dimension (BISECT; boundary_rule is then unused) */
-  int32_t reserved;
+  int32_t check_band;     /* nonzero (FP32 path of gis_solve / gis_solve_batch): each round
+                             also measures the largest |FP32 image - FP64 image| over every
+                             sample of every row (gis_round_stats.max_err_all) and fails
+                             with GIS_E_INTERNAL if it exceeds the round's band; costs
+                             about one more image pass per round */
   double band[4];         /* absolute recheck band per dimension; 0 = gis_solve calibrates
-                             it on the round-0 covering (every row, or an evenly strided
-                             sample of about 2^20 rows of larger coverings; see
-                             gis_calibrate_band, which takes every row) */
+                             it on each round's covering before that round's build:
+                             band = max(8 e, 1e-5 w_finest), e the largest |FP32 - FP64|
+                             image difference over every row of the covering, or over an
+                             evenly strided sample of about 2^20 rows of larger coverings
+                             (gis_calibrate_band takes every row) */
 } gis_opts;
 
 /* A cell list in device memory. */
@@ -160,6 +170,10 @@ typedef struct gis_round_stats {
   double ms_recheck;  /* 0: the recheck runs inside the build kernel */
   double ms_host;       /* host time of the round outside synchronisations (launches, bookkeeping) */
   double ms_host_wait;  /* host time blocked in the round's synchronisations */
+  double band[4];       /* FP32 path: recheck band of the round per dimension */
+  double max_err[4];    /* FP32 path, calibrated band: largest |FP32 - FP64| image difference
+                           over the calibration sample of the round's covering */
+  double max_err_all[4];  /* with opts.check_band: the same over every row (0 otherwise) */
 } gis_round_stats;
 
 #define GIS_MAX_ROUNDS 32
@@ -296,9 +310,10 @@ int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, co
                    int32_t K, const gis_cells* cells, int32_t samples, int32_t precision,
                    double* d_images, void* stream);
 
-/* Largest |FP32 image - FP64 image| per dimension over every sample of every
- * row of a covering (band[d] = max(floor_rel * w_finest_d, safety * that)).
- * Synchronises. */
+/* Recheck band for the FP32 path from the largest |FP32 image - FP64 image|
+ * per dimension over every sample of every row of a covering:
+ * band_out[d] = max(floor_rel * w_finest_d, safety * that largest difference),
+ * w_finest_d the cell width of the covering's finest level.  Synchronises. */
 int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
                            const double* d_u, int32_t K, const gis_cells* cells, int32_t samples,
                            double safety, double floor_rel, double* band_out, void* stream);

@@ -14,7 +14,10 @@ Parity status per function (what pins each one is in tests/test_oracle_*.py):
   prune           pinned: brute-force subset enumeration, drift/contraction
                   special cases, 1-D linear closed-form invariant interval,
                   textbook non-leaving set via strongly connected components
-  boundary        pinned: the 5x5 worked example of Sec. 3.1.1 and Remark 1
+  boundary        pinned: the 5x5 worked example of Sec. 3.1.1 and Remark 1;
+                  Algorithm 1 evaluated literally in exact rationals (enlarged
+                  cells, vertex and edge-point probes) on random mixed-level
+                  coverings with holes
   subdivide/solve pinned: union preservation and monotone shrinking
   largest_scc     pinned: hand-built graphs, brute-force transitive closure
                   on random small graphs, inclusion in the non-leaving set

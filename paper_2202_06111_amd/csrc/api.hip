@@ -224,6 +224,9 @@ int32_t check_opts(const gis_opts* o) {
   if (o->analysis != GIS_ANALYSIS_CONTROLLED && o->analysis != GIS_ANALYSIS_NONLEAVING &&
       o->analysis != GIS_ANALYSIS_LARGEST_SCC)
     return inval("unknown analysis");
+  // the non-leaving and largest-component analyses count an OUT row's edges
+  if (o->fast_out && o->analysis != GIS_ANALYSIS_CONTROLLED)
+    return inval("fast_out requires the controlled analysis");
   return GIS_OK;
 }
 
@@ -1202,43 +1205,67 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   if ((rc = batch_coarse(B.args(nullptr, nullptr), (uint8_t*)ctx->lvA.ptr, (int32_t*)ctx->ixA.ptr, s)))
     return rc;
 
-  // FP32 recheck band: calibrate each job on its coarse covering unless given
-  bool band_pending = false;
-  const double band_floor_rel = 1e-5 * ldexp(1.0, -rounds);
-  if (o.precision == GIS_PREC_FP32_RECHECK) {
-    bool need = false;
-    for (int d = 0; d < n; ++d) need |= !(o.band[d] > 0.0);
-    if (need) {
-      if ((rc = ensure(ctx->maxerr, sizeof(unsigned long long) * kMaxDim * (size_t)(nj + 1)))) return rc;
-      if ((rc = ctx->h_maxerr.ensure((size_t)kMaxDim * (nj + 1)))) return rc;
-      if ((rc = fill_u32((uint32_t*)ctx->maxerr.ptr, 0u, (int64_t)2 * kMaxDim * nj, s))) return rc;
-      BuildArgs a = build_args(ctx, B, (const uint8_t*)ctx->lvA.ptr, (const int32_t*)ctx->ixA.ptr, &o);
-      // every row of small coverings, every stride-th block of 256 rows of
-      // larger ones (about 2^20 rows)
-      const int64_t stride = (B.total_cells * K) >> 20;
-      if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, stride, s))) return rc;
-      // the device job table gets its bands on the stream; the host copy
-      // learns them at the end of round 0 (same formula, same bits)
-      if ((rc = launch_band(B.d_jobs, nj, n, (const unsigned long long*)ctx->maxerr.ptr,
-                            band_floor_rel, s)))
-        return rc;
-      GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim * nj,
-                             hipMemcpyDeviceToHost, s));
-      band_pending = true;
-    }
+  // FP32 recheck band: unless the caller gives it, each round calibrates it
+  // on its own covering before the build (an evenly strided sample of the
+  // rows, see calibrate_round); with opts.check_band every row is measured as
+  // well, and a round whose largest error exceeds its band fails.
+  bool need_band = false;
+  if (o.precision == GIS_PREC_FP32_RECHECK)
+    for (int d = 0; d < n; ++d) need_band |= !(o.band[d] > 0.0);
+  const bool check_band = o.precision == GIS_PREC_FP32_RECHECK && o.check_band != 0;
+  const double band_floor_rel = 1e-5;  // of the round's finest cell width
+  if (need_band || check_band) {
+    if ((rc = ensure(ctx->maxerr, sizeof(unsigned long long) * kMaxDim * (size_t)(2 * nj + 2)))) return rc;
+    if ((rc = ctx->h_maxerr.ensure((size_t)kMaxDim * (2 * nj + 2)))) return rc;
   }
-  // After a synchronisation: the calibrated bands of the host job table.
-  auto take_bands = [&]() {
-    if (!band_pending) return;
+  bool band_pending = false;
+  // Enqueues the calibration of the round's covering (lv, ix): the device job
+  // table gets its bands on the stream, the host learns them (same formula,
+  // same bits) after the round's synchronisation.
+  auto calibrate_round = [&](const uint8_t* lv, const int32_t* ix) -> int32_t {
+    if (!need_band && !check_band) return GIS_OK;
+    int32_t e;
+    unsigned long long* me = (unsigned long long*)ctx->maxerr.ptr;
+    if ((e = fill_u32((uint32_t*)me, 0u, (int64_t)2 * kMaxDim * 2 * nj, s))) return e;
+    BuildArgs a = build_args(ctx, B, lv, ix, &o);
+    // every row of small coverings, every stride-th block of 256 rows of
+    // larger ones (about 2^20 rows)
+    const int64_t stride = (B.total_cells * K) >> 20;
+    if ((e = launch_calibrate(a, me, stride, s))) return e;
+    if (check_band && stride > 1 && (e = launch_calibrate(a, me + (size_t)kMaxDim * nj, 1, s))) return e;
+    if (need_band && (e = launch_band(B.d_jobs, nj, n, me, band_floor_rel, s))) return e;
+    GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, me, sizeof(unsigned long long) * kMaxDim * 2 * nj,
+                           hipMemcpyDeviceToHost, s));
+    band_pending = true;
+    return GIS_OK;
+  };
+  // After the round's synchronisation: the bands of the host job table and
+  // the round's error figures.
+  auto take_bands = [&](int r, std::vector<gis_solve_info>& info) -> int32_t {
+    if (!band_pending) return GIS_OK;
     band_pending = false;
+    const int64_t stride = (B.total_cells * K) >> 20;
     for (int j = 0; j < nj; ++j)
       for (int d = 0; d < n; ++d) {
-        if (o.band[d] > 0.0) continue;
-        double e;
+        double e, ea;
         memcpy(&e, &ctx->h_maxerr.h[j * kMaxDim + d], 8);
-        const double fl = band_floor_rel * B.jobs[j].grid.w0[d];
-        B.jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
+        memcpy(&ea, &ctx->h_maxerr.h[(nj + j) * kMaxDim + d], 8);
+        if (stride <= 1) ea = e;  // the sample was every row
+        if (!(o.band[d] > 0.0)) {
+          const double fl = band_floor_rel * ldexp(B.jobs[j].grid.w0[d], -B.lmax[j]);
+          B.jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
+        }
+        gis_round_stats& st = info[j].rounds[r];
+        st.band[d] = B.jobs[j].band[d];
+        st.max_err[d] = e;
+        st.max_err_all[d] = check_band ? ea : 0.0;
+        if (check_band && !(ea <= B.jobs[j].band[d])) {
+          set_error("FP32 recheck band of round " + std::to_string(r) + ", dimension " +
+                    std::to_string(d) + " is below the largest FP32 error of the round's images");
+          return GIS_E_INTERNAL;
+        }
       }
+    return GIS_OK;
   };
 
   std::vector<gis_solve_info> info(nj);
@@ -1271,6 +1298,11 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     const bool last = r == rounds;
     if (r > 0) {
       for (int j = 0; j < nj; ++j) nxt[j] = (!last && active[j]) ? 1 : 0;
+      // bands not given by the caller are calibrated again on this round's covering
+      if (need_band)
+        for (int j = 0; j < nj; ++j)
+          for (int d = 0; d < n; ++d)
+            if (!(o.band[d] > 0.0)) B.jobs[j].band[d] = 0.0;
       B.bisect_dim = bisect ? r % n : -1;
       if ((rc = batch_layout(ctx, B, cells, !last, nxt, s, false))) return fail_all(rc);
     }
@@ -1328,15 +1360,14 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     if ((rc = clear_round())) return fail_all(rc);
     if (phases) GIS_HIP(hipEventRecord(ev[0], s));
     if ((rc = batch_index(ctx, B, lv, ix, false, s))) return fail_all(rc);
+    if ((rc = calibrate_round(lv, ix))) return fail_all(rc);
     if ((rc = enqueue_build(ctx, B, lv, ix, &o, gr, s))) return fail_all(rc);
     if (phases) GIS_HIP(hipEventRecord(ev[1], s));
     if ((rc = analyse_and_refine())) return fail_all(rc);
-    if (r == 0) {
-      take_bands();
-      for (int j = 0; j < nj; ++j)
-        for (int d = 0; d < n; ++d)
-          info[j].band[d] = o.precision == GIS_PREC_FP32_RECHECK ? B.jobs[j].band[d] : 0.0;
-    }
+    if ((rc = take_bands(r, info))) return fail_all(rc);
+    for (int j = 0; j < nj; ++j)
+      for (int d = 0; d < n; ++d)
+        info[j].band[d] = o.precision == GIS_PREC_FP32_RECHECK ? B.jobs[j].band[d] : 0.0;
     if ((rc = finish_build(ctx, B, gr))) return fail_all(rc);
     if (gr.n_edges > gr.cap_edges) {
       // grow the edge buffer and redo the round
@@ -2004,16 +2035,20 @@ int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* 
   if ((rc = fill_u32((uint32_t*)ctx->maxerr.ptr, 0u, 2 * kMaxDim, s))) return rc;
   gis_opts o{};
   o.samples = samples;
+  // the covering's finest level sets the floor's cell width
+  if ((rc = zero_counters(ctx, s))) return rc;
+  if ((rc = max_level(cells->level, cells->n_cells, &dcnt(ctx)->maxlevel, s))) return rc;
   BuildArgs a = build_args(ctx, B, cells->level, cells->idx, &o);
   if ((rc = launch_calibrate(a, (unsigned long long*)ctx->maxerr.ptr, 1, s))) return rc;
   GIS_HIP(hipMemcpyAsync(ctx->h_maxerr.h, ctx->maxerr.ptr, sizeof(unsigned long long) * kMaxDim,
                          hipMemcpyDeviceToHost, s));
-  GIS_HIP(hipStreamSynchronize(s));
+  if ((rc = sync_counters(ctx, s))) return rc;
+  const int lmax = (int)ctx->h_counters->maxlevel;
   const GridArgs ga = make_grid(grid);
   for (int d = 0; d < sys->n; ++d) {
     double e;
     memcpy(&e, &ctx->h_maxerr.h[d], 8);
-    const double fl = floor_rel * ga.w0[d];
+    const double fl = floor_rel * ldexp(ga.w0[d], -lmax);
     const double b = safety * e;
     band_out[d] = b > fl ? b : fl;
   }

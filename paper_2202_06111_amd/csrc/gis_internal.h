@@ -254,7 +254,8 @@ int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, h
 int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64_t stride,
                          hipStream_t s);
 // Writes the calibrated band into the device job table for every (job,
-// dimension) whose band is not positive there: max(8 maxerr, floor_rel w0).
+// dimension) whose band is not positive there: max(8 maxerr, floor_rel w),
+// w the finest cell width of the job's current covering.
 int32_t launch_band(Job* d_jobs, int32_t n_jobs, int32_t n, const unsigned long long* d_maxerr,
                     double floor_rel, hipStream_t s);
 

@@ -701,7 +701,8 @@ int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64
 
 namespace {
 // Recheck band of each (job, dimension) not given by the caller: eight times
-// the calibrated FP32 error, at least floor_rel of the coarse cell width.
+// the calibrated FP32 error, at least floor_rel of the finest cell width of
+// the job's current covering.
 __global__ void k_band(Job* jobs, int32_t n_jobs, int32_t n, const unsigned long long* maxerr,
                        double floor_rel) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -709,7 +710,7 @@ __global__ void k_band(Job* jobs, int32_t n_jobs, int32_t n, const unsigned long
   const int j = t / n, d = t - j * n;
   if (jobs[j].band[d] > 0.0) return;
   const double e = __longlong_as_double((long long)maxerr[j * kMaxDim + d]);
-  const double fl = floor_rel * jobs[j].grid.w0[d];
+  const double fl = floor_rel * ldexp(jobs[j].grid.w0[d], -jobs[j].ci.lmax);
   jobs[j].band[d] = 8.0 * e > fl ? 8.0 * e : fl;
 }
 }  // namespace

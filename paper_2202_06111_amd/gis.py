@@ -44,7 +44,7 @@ class GridT(ctypes.Structure):
 
 class OptsT(ctypes.Structure):
     _fields_ = [("samples", I32), ("precision", I32), ("boundary_rule", I32), ("analysis", I32),
-                ("fast_out", I32), ("timing", I32), ("subdivision", I32), ("reserved", I32),
+                ("fast_out", I32), ("timing", I32), ("subdivision", I32), ("check_band", I32),
                 ("band", F64 * 4)]
 
 
@@ -75,7 +75,8 @@ class RoundStatsT(ctypes.Structure):
     _fields_ = [("n_cells", I64), ("n_rows", I64), ("n_edges", I64), ("n_out", I64),
                 ("n_kept", I64), ("n_boundary", I64), ("n_recheck", I64), ("max_level", I32),
                 ("reserved", I32), ("ms_build", F64), ("ms_prune", F64), ("ms_subdivide", F64),
-                ("ms_image", F64), ("ms_recheck", F64), ("ms_host", F64), ("ms_host_wait", F64)]
+                ("ms_image", F64), ("ms_recheck", F64), ("ms_host", F64), ("ms_host_wait", F64),
+                ("band", F64 * 4), ("max_err", F64 * 4), ("max_err_all", F64 * 4)]
 
 
 class SolveInfoT(ctypes.Structure):
@@ -171,7 +172,7 @@ def grid_t(grid: W.Grid) -> GridT:
 def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: str = W.SHELL,
            analysis: str = "controlled", fast_out: bool = False,
            band: Optional[Sequence[float]] = None, timing: int = 0,
-           subdivision: str = "boundary") -> OptsT:
+           subdivision: str = "boundary", check_band: bool = False) -> OptsT:
     o = OptsT()
     o.samples = SAMPLES[samples]
     o.precision = PRECISION[precision]
@@ -180,6 +181,7 @@ def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: st
     o.fast_out = int(bool(fast_out))
     o.timing = int(timing)
     o.subdivision = SUBDIVISION[subdivision]
+    o.check_band = int(bool(check_band))
     for d, v in enumerate([] if band is None else list(band)):
         o.band[d] = float(v)
     return o
@@ -391,7 +393,13 @@ def info_dict(inf: SolveInfoT) -> dict:
     rounds = []
     for r in range(inf.n_rounds):
         s = inf.rounds[r]
-        rounds.append({k: getattr(s, k) for k, _ in RoundStatsT._fields_ if k != "reserved"})
+        d = {}
+        for k, t in RoundStatsT._fields_:
+            if k == "reserved":
+                continue
+            v = getattr(s, k)
+            d[k] = list(v[: inf.n]) if isinstance(t, type) and issubclass(t, ctypes.Array) else v
+        rounds.append(d)
     return {"n_rounds": inf.n_rounds, "n": inf.n, "K": inf.K, "mask_words": inf.mask_words,
             "n0": tuple(inf.n0[: inf.n]), "n_cells": inf.n_cells, "n_kept": inf.n_kept, "band": list(inf.band[: inf.n]),
             "rounds": rounds}

@@ -8,6 +8,7 @@
   n_{r+1} <= |K*_r| + (2^n - 1) |boundary_r|.
 * Point queries against brute-force point location over the cell boxes.
 """
+import itertools
 import os
 from fractions import Fraction
 
@@ -142,3 +143,91 @@ def test_query_against_point_location(oracle_lib):
         want_member = owner is not None and bool(kept[owner])
         assert bool(member[s]) == want_member, s
         assert int(adm[s, 0]) == (int(mask[owner, 0]) if want_member else 0)
+
+
+def _random_mixed_covering(rng, n0, splits):
+    """A covering with cells of several levels, made without the oracle: start
+    from the coarse grid and, `splits` times, replace a random third of the
+    cells by their 2^n children.  Returned in canonical order."""
+    n = len(n0)
+    cells = [(0,) + c for c in itertools.product(*[range(k) for k in n0])]
+    for _ in range(splits):
+        nxt = []
+        for c in cells:
+            if rng.random() < 0.35:
+                L, ix = c[0], c[1:]
+                for ch in itertools.product((0, 1), repeat=n):
+                    nxt.append((L + 1,) + tuple(2 * ix[d] + ch[d] for d in range(n)))
+            else:
+                nxt.append(c)
+        cells = nxt
+    cells.sort()
+    level = np.array([c[0] for c in cells], dtype=np.uint8)
+    idx = np.array([c[1:] for c in cells], dtype=np.int32).reshape(len(cells), n)
+    return level, idx
+
+
+def _alg1_brute_force(grid, level, idx, kept, rule):
+    """Algorithm 1 (Sec. 3.1.1) evaluated literally in exact rationals.  Each
+    kept cell is enlarged by delta = (finest cell width) / 4 per side; a probe
+    point of the enlarged box that lies in no closed kept cell (a point outside
+    X lies in none) makes the cell a boundary cell.  Probes: the 2^n vertices
+    of the enlarged box ("corners", the algorithm as printed), or for "shell"
+    also the points of the enlarged box's faces above the centres of the
+    finest-level cells along the cell's faces and edges (the edge points of
+    Remark 1, taken at every finest position)."""
+    n = grid.n
+    Lf = int(level.max())
+    lo = [Fraction(v) for v in grid.lo]
+    w0 = [(Fraction(grid.hi[d]) - Fraction(grid.lo[d])) / grid.n0[d] for d in range(n)]
+    wf = [w / 2 ** Lf for w in w0]
+    boxes = []
+    for c in range(level.shape[0]):
+        w = [w0[d] / 2 ** int(level[c]) for d in range(n)]
+        a = [lo[d] + int(idx[c, d]) * w[d] for d in range(n)]
+        boxes.append((a, [a[d] + w[d] for d in range(n)]))
+    kept_boxes = [boxes[c] for c in range(len(boxes)) if kept[c]]
+    out = np.zeros(level.shape[0], dtype=np.uint8)
+    for c in np.nonzero(kept)[0]:
+        a, b = boxes[c]
+        axes = []
+        for d in range(n):
+            delta = wf[d] / 4
+            pts = [a[d] - delta, b[d] + delta]
+            if rule == "shell":
+                m = int((b[d] - a[d]) / wf[d])
+                pts += [a[d] + (k + Fraction(1, 2)) * wf[d] for k in range(m)]
+            axes.append(pts)
+        for p in itertools.product(*axes):
+            on_face = [p[d] < a[d] or p[d] > b[d] for d in range(n)]
+            if rule == "corners" and not all(on_face):
+                continue
+            if not any(on_face):
+                continue
+            if not any(all(ka[d] <= p[d] <= kb[d] for d in range(n)) for ka, kb in kept_boxes):
+                out[c] = 1
+                break
+    return out
+
+
+@pytest.mark.parametrize("n0,splits,seed", [((5, 4), 2, 3), ((4, 4), 3, 4), ((3, 3, 2), 2, 5)])
+@pytest.mark.parametrize("rule", ["shell", "corners"])
+def test_boundary_on_mixed_level_coverings_against_algorithm_1(oracle_lib, n0, splits, seed, rule):
+    """Boundary selection on coverings whose cells have different levels, with
+    holes (dropped cells), against Algorithm 1 evaluated literally in exact
+    arithmetic.  The probes of a coarse cell next to finely refined
+    neighbours must look at finest-level positions, not at the cell's own
+    level: a dropped fine cell beside a coarse one makes it a boundary cell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(n0)
+    grid = W.Grid(n0, tuple([-1.0] * n), tuple([-1.0 + 1.25 * k for k in n0]))
+    level, idx = _random_mixed_covering(rng, n0, splits)
+    assert len(set(level.tolist())) == splits + 1
+    for trial in range(3):
+        kept = (rng.random(level.shape[0]) < 0.8).astype(np.uint8)
+        got = oracle.boundary(grid, level, idx, kept, rule)
+        want = _alg1_brute_force(grid, level, idx, kept, rule)
+        np.testing.assert_array_equal(got, want, err_msg=f"trial {trial}")
+        # the mixed levels matter: some boundary cell is coarser than the finest level
+        if trial == 0:
+            assert (want.astype(bool) & (level < level.max())).any()
