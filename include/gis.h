@@ -214,6 +214,11 @@ typedef struct gis_tuning {
   int32_t row_frontier;    /* nonzero: the frontier phase keeps one reverse entry per (row,
                               target) also for K <= 64 inputs, instead of one per (source
                               cell, target) with an input mask [0] (0..1) */
+  int32_t wit_sweeps;      /* non-leaving analysis: at most this many witness sweeps (a
+                              present target kept per cell and re-checked each sweep; any
+                              graph size, sweep_edges does not apply) before the frontier
+                              phase takes over; 0: the row sweeps and frontier phase of the
+                              controlled analysis instead [256] (0..4096) */
 } gis_tuning;
 
 /* Reads / replaces the context's schedule parameters.  GIS_E_INVAL when a

@@ -130,7 +130,8 @@ struct gis_ctx {
   uint32_t lb_epoch = 0;
   bool lb_clean = false, prune_clean = false, next_clean = false;
   int32_t first_sweeps = 0;  // sweeps of the last enqueue_prune
-  gis_tuning tune{16, 8, (int64_t)8 << 20, 16, 4096, 2048, 0, 0, 0};
+  int64_t wit_cells = 0;     // cells the witness arrays in `wit` are laid out for
+  gis_tuning tune{16, 8, (int64_t)8 << 20, 16, 4096, 2048, 0, 0, 0, 256};
   double wait_ms = 0.0;  // host time spent blocked in stream synchronisations
   // per round of the last solve: its cell count and the sweeps its analysis
   // needed (0: it did not converge within the first batch)
@@ -138,7 +139,7 @@ struct gis_ctx {
   GraphCache graphs;
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
-  DevBuf removed, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front;
+  DevBuf removed, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front, wit;
   DevBuf bnd, scc;
   Pinned<unsigned long long> h_scc;  // largest-component search: per-job keys and counts
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
@@ -693,6 +694,11 @@ PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   w.badmask = (uint64_t*)ctx->rowstate.ptr;
   w.front = (int32_t*)ctx->front.ptr;
   w.fcount = dcnt(ctx)->fcount;
+  // witness state: span starts [n + 1], witness positions [n], targets [n]
+  // (sized by ensure_witness for the current cell count)
+  w.cstart = (int64_t*)ctx->wit.ptr;
+  w.wpos = w.cstart ? w.cstart + ctx->wit_cells + 1 : nullptr;
+  w.wtgt = w.wpos ? (int32_t*)(w.wpos + ctx->wit_cells) : nullptr;
   w.scan_tmp = ctx->scan_tmp.ptr;
   w.sweep_blocks = ctx->tune.sweep_blocks;
   w.front_blocks = ctx->tune.front_blocks;
@@ -761,6 +767,20 @@ bool sweeps_fit(const gis_ctx* ctx, int64_t n_edges, int32_t K) {
   return K <= 256 && n_edges <= ctx->tune.sweep_edges;
 }
 
+// The non-leaving analysis runs witness sweeps (any graph size) unless the
+// tuning turns them off.
+bool witness_sweeps(const gis_ctx* ctx, int32_t analysis) {
+  return analysis == GIS_ANALYSIS_NONLEAVING && ctx->tune.wit_sweeps > 0;
+}
+
+// Witness arrays for n_cells cells: span starts (n + 1), positions (n), targets (n).
+int32_t ensure_witness(gis_ctx* ctx, int64_t n_cells) {
+  int32_t rc;
+  if ((rc = ensure(ctx->wit, (size_t)(2 * n_cells + 1) * 8 + (size_t)n_cells * 4 + 64))) return rc;
+  ctx->wit_cells = n_cells;
+  return GIS_OK;
+}
+
 // Runs enqueue() on stream s, through the context's graph cache when
 // tune.use_graphs is set and s is not the null stream (which cannot be
 // captured).  enqueue() may only launch kernels on s.
@@ -824,7 +844,13 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   }
   if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
   if (first <= 0) first = ctx->tune.first_sweeps;
-  ctx->first_sweeps = sweeps_fit(ctx, est_edges, K) ? first : 0;
+  const bool wit = witness_sweeps(ctx, analysis);
+  if (wit) {
+    if ((rc = ensure_witness(ctx, n_cells))) return rc;
+    ctx->first_sweeps = std::min(first, ctx->tune.wit_sweeps);
+  } else {
+    ctx->first_sweeps = sweeps_fit(ctx, est_edges, K) ? first : 0;
+  }
   if (ctx->first_sweeps == 0)
     return clear_removed ? fill_u8((uint8_t*)ctx->removed.ptr, 0, n_cells, s) : GIS_OK;
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
@@ -837,7 +863,7 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   memset(&key, 0, sizeof key);
   const void* ptrs[14] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
                           dcnt(ctx)->n_kept, B ? B->d_jobs : nullptr, B ? B->d_stats : nullptr,
-                          level, idx, nullptr};
+                          level, idx, wit ? (const void*)w.cstart : nullptr};
   memcpy(key.p, ptrs, sizeof ptrs);
   key.n_cells = n_cells;
   key.cap_edges = cap_edges;
@@ -850,7 +876,9 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   return run_cached(ctx, &key, sizeof key, s, [&]() -> int32_t {
     int32_t e;
     if (clear_removed && (e = fill_u8(w.removed, 0, n_cells, s))) return e;
-    if ((e = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps, s)))
+    if ((e = wit ? prune_wsweeps(row_ptr, col, n_cells, K, w, 0, ctx->first_sweeps, s)
+                 : prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, 0, ctx->first_sweeps,
+                                s)))
       return e;
     return prune_final_and_counts(ctx, row_ptr, col, out, n_cells, K, analysis, w, kept, mask,
                                   ctx->first_sweeps, s, B, level, idx);
@@ -874,15 +902,25 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
   const int64_t n_rows = n_cells * K;
   int32_t rc;
   PruneWork w = prune_work(ctx, cap_edges, nullptr);
-  // sweeps restart their numbering from 0 on the current removed flags
-  if ((rc = fill_i32(w.last, 0, 1, s))) return rc;
   int32_t done = 0;
   bool converged = false;
   const int32_t batch = ctx->tune.sweep_batch, fbatch = ctx->tune.frontier_batch;
   // cells can be removed before the frontier phase only by sweeps (the
   // callers clear the removed flags before the analysis)
   bool any_removed = ctx->first_sweeps > 0;
-  if (sweeps_fit(ctx, n_edges, K)) {
+  if (witness_sweeps(ctx, analysis) && ctx->first_sweeps > 0 && ctx->wit_cells == n_cells) {
+    // witness sweeps continue their numbering (their state is kept): sweep
+    // `done` runs because sweep done-1 removed a cell
+    done = ctx->first_sweeps;
+    if ((rc = fill_i32(w.last, done, 1, s))) return rc;
+    for (; done < ctx->tune.wit_sweeps && !converged; done += batch) {
+      if ((rc = prune_wsweeps(row_ptr, col, n_cells, K, w, done, batch, s))) return rc;
+      if ((rc = sync_counters(ctx, s))) return rc;
+      converged = ctx->h_counters->sweep_last < done + batch;
+    }
+  } else if (sweeps_fit(ctx, n_edges, K)) {
+    // sweeps restart their numbering from 0 on the current removed flags
+    if ((rc = fill_i32(w.last, 0, 1, s))) return rc;
     any_removed = true;
     for (; done < kMaxSweeps && !converged; done += batch) {
       if ((rc = prune_sweeps(row_ptr, col, out, n_cells, K, analysis, w, done, batch, s)))
@@ -1613,7 +1651,7 @@ int32_t gis_set_tuning(gis_ctx* ctx, const gis_tuning* t) {
   if (!in(t->first_sweeps, 1, 256) || !in(t->sweep_batch, 1, 256) || t->sweep_edges < 0 ||
       !in(t->frontier_batch, 1, 256) || !in(t->sweep_blocks, 1, 65536) ||
       !in(t->front_blocks, 1, 65536) || !in(t->edge_hint, 0, 4096) ||
-      !in(t->row_frontier, 0, 1))
+      !in(t->row_frontier, 0, 1) || !in(t->wit_sweeps, 0, 4096))
     return inval("tuning field out of range");
   ctx->tune = *t;
   return GIS_OK;
@@ -1898,6 +1936,8 @@ int32_t gis_autotune(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
        [](gis_tuning& t, int64_t v) { t.use_graphs = (int32_t)v; }, {0, 1}},
       {[](const gis_tuning& t) { return (int64_t)t.row_frontier; },
        [](gis_tuning& t, int64_t v) { t.row_frontier = (int32_t)v; }, {0, 1}},
+      {[](const gis_tuning& t) { return (int64_t)t.wit_sweeps; },
+       [](gis_tuning& t, int64_t v) { t.wit_sweeps = (int32_t)v; }, {0, 64, 256}},
   };
   for (const Field& f : fields) {
     for (int64_t v : f.values) {

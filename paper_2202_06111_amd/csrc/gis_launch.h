@@ -43,6 +43,10 @@ struct PruneWork {
   int32_t* rsrc;       // [entries] source cells (same memory as rrow)
   uint64_t* rmask;     // [entries] input masks
   uint64_t* badmask;   // controlled: [n_cells] bad rows of each cell (same memory as rowstate)
+  // nonleaving witness sweeps
+  int64_t* cstart;     // [n_cells + 1] first edge of each cell's rows (row_ptr[c * K])
+  int64_t* wpos;       // [n_cells] position of the cell's witness edge
+  int32_t* wtgt;       // [n_cells] its target
   int32_t* front;      // [2 * n_cells] the two frontier lists
   int32_t* fcount;     // [3] rotating list lengths
   void* scan_tmp;
@@ -58,6 +62,11 @@ int32_t launch_check_graph(const int64_t* row_ptr, const int32_t* col, int64_t n
 int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
                      int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                      int32_t first, int32_t count, hipStream_t s);
+// nonleaving: witness sweeps first .. first+count-1; sweep 0 must come first
+// in an analysis (it sets cstart and the first witnesses).  Converged when
+// *last < first+count.
+int32_t prune_wsweeps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                      const PruneWork& w, int32_t first, int32_t count, hipStream_t s);
 // Reverse CSR, the counters from the current removed flags, and the first
 // frontier (present cells without a good row); fcount[0] = its length.
 int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,

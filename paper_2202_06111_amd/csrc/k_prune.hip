@@ -10,7 +10,10 @@
 // Two phases:
 //   sweeps   : whole-graph passes, in place, until one removes nothing -- few
 //              launches when the removal chains are short, and no reverse
-//              graph to build;
+//              graph to build; the nonleaving reading sweeps with a witness
+//              target per cell (k_wsweep: one check per cell and sweep, each
+//              cell's edges read at most once over the whole analysis), the
+//              controlled one evaluates every row of the present cells;
 //   frontier : for long chains, a breadth-first peel over the reverse CSR
 //              (in-degree histogram -> offsets -> scatter), each step
 //              propagating the cells removed in the step before through
@@ -211,6 +214,119 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
     __syncthreads();
   }
   if (__ballot(changed) && (t & 63) == 0) atomicMax(last, s + 1);
+}
+
+// ---- nonleaving: sweeps with a witness per cell.  A present cell stays
+// present while some edge of its rows (all inputs together: the edges of
+// rows c*K .. c*K+K-1 are one contiguous span of col) ends in a present
+// cell.  Each present cell keeps the position and the id of such a target,
+// its witness.  A sweep re-checks the witness only; when it has been
+// removed, the cell looks for the next present target after it -- the
+// targets before it were removed when they were passed, and removal is
+// final -- and is removed when there is none.  Over a whole analysis each
+// cell's span is read at most once, plus one witness check per sweep, and no
+// reverse graph is built.  Sweep 0 (INIT) finds the first witnesses and
+// copies the cells' span starts out of row_ptr.
+//
+// A block takes 256 consecutive cells (odd sweeps go through the tiles in
+// reverse order, so that removals propagate in place along both
+// directions): a thread per cell checks the witness, the cells that need a
+// new one are queued in LDS, and each wave then searches one queued cell's
+// span 64 edges at a time (coalesced loads, one ballot per 64 edges).
+template <bool INIT>
+__global__ __launch_bounds__(256) void k_wsweep(const int64_t* row_ptr, const int32_t* col,
+                                                int64_t n_cells, int32_t K, uint8_t* removed,
+                                                int64_t* cstart, int64_t* wpos, int32_t* wtgt,
+                                                int32_t* last, int32_t s, const int64_t* d_total,
+                                                int64_t cap_edges) {
+  if (d_total && *d_total > cap_edges) return;  // col was not written
+  if (!INIT && *last < s) return;                // sweep s-1 removed nothing: converged
+  __shared__ int32_t q_cell[256];
+  __shared__ int64_t q_from[256], q_end[256];
+  __shared__ int32_t q_n;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  bool changed = false;
+  const int64_t tiles = (n_cells + 255) / 256;
+  for (int64_t ti = blockIdx.x; ti < tiles; ti += gridDim.x) {
+    const int64_t tile = (s & 1) ? tiles - 1 - ti : ti;
+    const int64_t c = tile * 256 + t;
+    if (t == 0) q_n = 0;
+    __syncthreads();
+    if (c < n_cells) {
+      int64_t a = 0;
+      if (INIT) {
+        a = row_ptr[c * K];
+        cstart[c] = a;
+        if (c == n_cells - 1) cstart[n_cells] = row_ptr[n_cells * K];
+      }
+      if (!removed[c]) {
+        int64_t from = 0, end = 0;
+        bool need;
+        if (INIT) {
+          end = row_ptr[(c + 1) * K];
+          from = a;
+          need = true;
+          if (a < end) {  // most cells: the first target is present
+            const int32_t j = col[a];
+            if (!removed[j]) {
+              wpos[c] = a;
+              wtgt[c] = j;
+              need = false;
+            } else {
+              from = a + 1;
+            }
+          }
+        } else {
+          need = removed[wtgt[c]] != 0;
+          if (need) {
+            from = wpos[c] + 1;
+            end = cstart[c + 1];
+          }
+        }
+        if (need) {
+          const int k = atomicAdd(&q_n, 1);
+          q_cell[k] = (int32_t)c;
+          q_from[k] = from;
+          q_end[k] = end;
+        }
+      }
+    }
+    __syncthreads();
+    const int nq = q_n;
+    for (int k = wave; k < nq; k += 4) {
+      const int32_t cq = q_cell[k];
+      const int64_t from = q_from[k], end = q_end[k];
+      int64_t pos = -1;
+      int32_t jw = -1;
+      for (int64_t p0 = from; p0 < end; p0 += 64) {
+        const int64_t p = p0 + lane;
+        int32_t j = -1;
+        bool live = false;
+        if (p < end) {
+          j = col[p];
+          live = removed[j] == 0;
+        }
+        const uint64_t m = __ballot(live);
+        if (m) {  // wave-uniform
+          const int f = __builtin_ctzll(m);
+          pos = p0 + f;
+          jw = __shfl(j, f, 64);
+          break;
+        }
+      }
+      if (lane == 0) {
+        if (pos >= 0) {
+          wpos[cq] = pos;
+          wtgt[cq] = jw;
+        } else {
+          removed[cq] = 1;
+          changed = true;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (__ballot(changed) && lane == 0) atomicMax(last, s + 1);
 }
 
 // ---- frontier phase (long removal chains): a breadth-first peel over the
@@ -680,6 +796,25 @@ int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* 
   if (analysis == GIS_ANALYSIS_NONLEAVING)
     return sweeps_mode<GIS_ANALYSIS_NONLEAVING>(row_ptr, col, out, n_cells, K, w, first, count, s);
   return sweeps_mode<GIS_ANALYSIS_CONTROLLED>(row_ptr, col, out, n_cells, K, w, first, count, s);
+}
+
+int32_t prune_wsweeps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
+                      const PruneWork& w, int32_t first, int32_t count, hipStream_t s) {
+  if (n_cells == 0 || count <= 0) return GIS_OK;
+  const int64_t tiles = (n_cells + 255) / 256;
+  const int64_t cap = w.sweep_blocks > 0 ? w.sweep_blocks : 4096;
+  const unsigned nb = (unsigned)(tiles < cap ? tiles : cap);
+  for (int32_t i = 0; i < count; ++i) {
+    const int32_t sw = first + i;
+    if (sw == 0)
+      hipLaunchKernelGGL(k_wsweep<true>, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells, K,
+                         w.removed, w.cstart, w.wpos, w.wtgt, w.last, sw, w.d_total, w.cap_edges);
+    else
+      hipLaunchKernelGGL(k_wsweep<false>, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells, K,
+                         w.removed, w.cstart, w.wpos, w.wtgt, w.last, sw, w.d_total, w.cap_edges);
+    GIS_LAUNCH_CHECK("k_wsweep");
+  }
+  return GIS_OK;
 }
 
 int32_t prune_frontier_start(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,

@@ -60,11 +60,12 @@ class GraphT(ctypes.Structure):
 class TuningT(ctypes.Structure):
     _fields_ = [("first_sweeps", I32), ("sweep_batch", I32), ("sweep_edges", I64),
                 ("frontier_batch", I32), ("sweep_blocks", I32), ("front_blocks", I32),
-                ("use_graphs", I32), ("edge_hint", I32), ("row_frontier", I32)]
+                ("use_graphs", I32), ("edge_hint", I32), ("row_frontier", I32),
+                ("wit_sweeps", I32)]
 
 
 TUNING_FIELDS = ("first_sweeps", "sweep_batch", "sweep_edges", "frontier_batch", "sweep_blocks",
-                 "front_blocks", "use_graphs", "edge_hint", "row_frontier")
+                 "front_blocks", "use_graphs", "edge_hint", "row_frontier", "wit_sweeps")
 
 
 class JobT(ctypes.Structure):

@@ -162,13 +162,17 @@ def test_prune_deep_peel(G, ctx):
 
 
 # Schedule parameters never change results: the frontier phase from the
-# start (sweep_edges = 0), one sweep or step per convergence check, and
-# one-block grids all give the oracle's fixed point.
+# start (sweep_edges = 0 and no witness sweeps), the row sweeps instead of
+# the witness sweeps for the non-leaving analysis, the frontier phase taking
+# over from a few witness sweeps, one sweep or step per convergence check,
+# and one-block grids all give the oracle's fixed point.
 TUNINGS = {
-    "frontier_only": dict(sweep_edges=0),
-    "row_frontier_only": dict(sweep_edges=0, row_frontier=1),
+    "frontier_only": dict(sweep_edges=0, wit_sweeps=0),
+    "row_frontier_only": dict(sweep_edges=0, row_frontier=1, wit_sweeps=0),
+    "row_sweeps": dict(wit_sweeps=0),
+    "witness_then_frontier": dict(wit_sweeps=2, first_sweeps=1, sweep_batch=1),
     "one_sweep_per_check": dict(first_sweeps=1, sweep_batch=1),
-    "tiny_grids": dict(sweep_edges=0, front_blocks=1, frontier_batch=1),
+    "tiny_grids": dict(sweep_edges=0, front_blocks=1, frontier_batch=1, wit_sweeps=0),
     "tiny_sweep_grid": dict(sweep_blocks=1, first_sweeps=3, sweep_batch=2),
 }
 
@@ -207,7 +211,7 @@ def test_prune_frontier_dense_rows(G, ctx, analysis):
     assert max(rp[min(b + 256, len(rp) - 1)] - rp[b] for b in range(0, len(rp) - 1, 256)) > 6144
     kept_w, mask_w, _ = oracle.prune(want["row_ptr"], want["col"], want["out"], level.shape[0],
                                      u.shape[0], analysis)
-    prev = ctx.set_tuning(sweep_edges=0)
+    prev = ctx.set_tuning(sweep_edges=0, wit_sweeps=0)
     try:
         kept, mask, nk = G.prune(ctx, g, level.shape[0], u.shape[0], analysis)
     finally:
@@ -285,9 +289,42 @@ def test_prune_frontier_cascade_graph(G, ctx, analysis, K, max_targets, shuffled
     dev = ctx.dev
     g = G.Graph(torch.as_tensor(row_ptr, device=dev), torch.as_tensor(col, device=dev),
                 torch.as_tensor(out, device=dev), n_rows, int(col.shape[0]), int(out.sum()), 0)
-    prev = ctx.set_tuning(sweep_edges=0, row_frontier=row_frontier)
+    prev = ctx.set_tuning(sweep_edges=0, row_frontier=row_frontier, wit_sweeps=0)
     try:
         kept, mask, nk = G.prune(ctx, g, n_cells, K, analysis)
+    finally:
+        ctx.set_tuning(**prev)
+    np.testing.assert_array_equal(_np(kept), kept_w)
+    np.testing.assert_array_equal(_np(mask).view(np.uint64), mask_w)
+    assert nk == int(kept_w.sum())
+
+
+@pytest.mark.parametrize("K,max_targets,shuffled", [(1, 40, False), (2, 60, False),
+                                                    (5, 6, False), (49, 9, False),
+                                                    (64, 3, False), (5, 6, True)])
+@pytest.mark.parametrize("one_per_check", [False, True])
+def test_prune_witness_cascade_graph(G, ctx, K, max_targets, shuffled, one_per_check):
+    """The non-leaving analysis by witness sweeps alone, to its fixed point
+    over removal chains of a few hundred steps: spans of up to K * 40 edges
+    searched 64 at a time, repeated and (shuffled) unordered targets, one
+    sweep per convergence check or the default batches."""
+    row_ptr, col, out, n_cells = _cascade_graph(K, max_targets, 300 + K)
+    if shuffled:
+        rng = np.random.Generator(np.random.PCG64(8))
+        for r in range(n_cells * K):
+            rng.shuffle(col[row_ptr[r]:row_ptr[r + 1]])
+    n_rows = n_cells * K
+    kept_w, mask_w, iters = oracle.prune(row_ptr, col, out, n_cells, K, "nonleaving")
+    assert 0 < kept_w.sum() < n_cells
+    dev = ctx.dev
+    g = G.Graph(torch.as_tensor(row_ptr, device=dev), torch.as_tensor(col, device=dev),
+                torch.as_tensor(out, device=dev), n_rows, int(col.shape[0]), int(out.sum()), 0)
+    tun = dict(wit_sweeps=4096)
+    if one_per_check:
+        tun.update(first_sweeps=1, sweep_batch=1)
+    prev = ctx.set_tuning(**tun)
+    try:
+        kept, mask, nk = G.prune(ctx, g, n_cells, K, "nonleaving")
     finally:
         ctx.set_tuning(**prev)
     np.testing.assert_array_equal(_np(kept), kept_w)
@@ -330,11 +367,13 @@ def _zigzag_chains(L):
     return row_ptr, col, out, n_cells, K
 
 
-@pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
+@pytest.mark.parametrize("analysis,wit_sweeps", [("controlled", 256), ("nonleaving", 256),
+                                                 ("nonleaving", 0)])
 @pytest.mark.parametrize("row_frontier", [0, 1])
-def test_prune_sweeps_then_frontier(G, ctx, analysis, row_frontier):
-    """The frontier phase taking over from sweeps that have removed cells
-    already: its initial state must account for removed targets."""
+def test_prune_sweeps_then_frontier(G, ctx, analysis, wit_sweeps, row_frontier):
+    """The frontier phase taking over from sweeps (row sweeps, or witness
+    sweeps for the non-leaving analysis) that have removed cells already: its
+    initial state must account for removed targets."""
     row_ptr, col, out, n_cells, K = _zigzag_chains(1500)
     kept_w, mask_w, iters = oracle.prune(row_ptr, col, out, n_cells, K, analysis)
     assert iters == 1500 and kept_w.sum() == 1500
@@ -342,7 +381,7 @@ def test_prune_sweeps_then_frontier(G, ctx, analysis, row_frontier):
     g = G.Graph(torch.as_tensor(row_ptr, device=dev), torch.as_tensor(col, device=dev),
                 torch.as_tensor(out, device=dev), n_cells * K, int(col.shape[0]), int(out.sum()),
                 0)
-    prev = ctx.set_tuning(row_frontier=row_frontier)
+    prev = ctx.set_tuning(row_frontier=row_frontier, wit_sweeps=wit_sweeps)
     try:
         kept, mask, nk = G.prune(ctx, g, n_cells, K, analysis)
     finally:
@@ -353,7 +392,7 @@ def test_prune_sweeps_then_frontier(G, ctx, analysis, row_frontier):
 
 
 @pytest.mark.parametrize("tuning", ["frontier_only", "row_frontier_only", "one_sweep_per_check",
-                                    "tiny_grids"])
+                                    "tiny_grids", "row_sweeps", "witness_then_frontier"])
 def test_solve_adaptive_tunings(G, ctx, tuning):
     prev = ctx.set_tuning(**TUNINGS[tuning])
     try:
@@ -411,7 +450,7 @@ def test_tuning_rejects_out_of_range(G, ctx):
     for bad in (dict(first_sweeps=0), dict(sweep_batch=300), dict(sweep_edges=-1),
                 dict(front_blocks=0), dict(sweep_blocks=70000), dict(frontier_batch=0),
                 dict(edge_hint=-1), dict(edge_hint=5000), dict(row_frontier=2),
-                dict(row_frontier=-1)):
+                dict(row_frontier=-1), dict(wit_sweeps=-1), dict(wit_sweeps=5000)):
         with pytest.raises(G.GisError):
             ctx.set_tuning(**bad)
         assert ctx.get_tuning() == before

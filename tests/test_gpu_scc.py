@@ -100,7 +100,7 @@ def test_prune_planted_components(G, ctx, seed, K):
     n, edges = _planted(seed, 8 + seed, K)
     row_ptr, col = _graph(n, K, edges)
     _prune(G, ctx, n, K, row_ptr, col)
-    _prune(G, ctx, n, K, row_ptr, col, sweep_edges=0)  # non-leaving phase on the frontier
+    _prune(G, ctx, n, K, row_ptr, col, sweep_edges=0, wit_sweeps=0)  # non-leaving phase on the frontier
 
 
 def _check_solve(G, wl, sols_or_sol, ctx):
