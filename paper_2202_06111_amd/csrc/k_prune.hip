@@ -150,8 +150,14 @@ constexpr int kBatch = 8;
 template <int MODE>
 __device__ __forceinline__ bool row_good(const int64_t* row_ptr, const int32_t* col,
                                          const uint8_t* out, const uint8_t* removed, int64_t r) {
-  const int64_t a = row_ptr[r], b = row_ptr[r + 1];
+  int64_t a = row_ptr[r];
+  const int64_t b = row_ptr[r + 1];
   if (MODE == GIS_ANALYSIS_CONTROLLED && out[r]) return false;
+  if (MODE != GIS_ANALYSIS_CONTROLLED) {
+    // most rows of a kept cell meet a present cell first: one load decides them
+    if (a < b && removed[col[a]] == 0) return true;
+    ++a;
+  }
   for (int64_t e = a; e < b; e += kBatch) {
     int32_t j[kBatch];
 #pragma unroll

@@ -51,6 +51,9 @@ class Result:
     n_kept: int
     member: np.ndarray
     admissible: np.ndarray
+    # with Server(export_results=True): the final covering, kept flags and
+    # admissible-input masks (level, idx, kept, mask), copied to the host
+    export: Optional[tuple] = None
 
     @property
     def latency_s(self) -> float:
@@ -140,9 +143,10 @@ SERVING_TUNING = {"sweep_edges": 0}
 
 class Server:
     def __init__(self, n_slots: int = 4, mem_budget_bytes: int = 8 << 30, device: int = 0,
-                 tuning: Optional[dict] = None):
+                 tuning: Optional[dict] = None, export_results: bool = False):
         self.n_slots = n_slots
         self.device = device
+        self.export_results = export_results
         self.adm = Admission(n_slots, mem_budget_bytes)
         self.ctxs = [gis.Context(device) for _ in range(n_slots)]
         for c in self.ctxs:
@@ -179,12 +183,14 @@ class Server:
             try:
                 member_h, adm_h = self._enqueue_queries(ctx, sol, q, stream)
                 info = sol.info()
+                ex = sol.export(stream) if self.export_results else None
                 stream.synchronize()
             finally:
                 sol.free()
         done = time.perf_counter() - t0
         return Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"], info["n_kept"],
-                      member_h.numpy(), adm_h.numpy().view(np.uint64))
+                      member_h.numpy(), adm_h.numpy().view(np.uint64),
+                      None if ex is None else tuple(t.cpu().numpy() for t in ex))
 
     @staticmethod
     def _compatible(a: W.Workload, b: W.Workload) -> bool:
@@ -203,14 +209,16 @@ class Server:
             try:
                 answers = [self._enqueue_queries(ctx, sol, q, stream) for sol, q in zip(sols, qs)]
                 infos = [sol.info() for sol in sols]
+                exports = [sol.export(stream) if self.export_results else None for sol in sols]
                 stream.synchronize()
             finally:
                 for sol in sols:
                     sol.free()
         done = time.perf_counter() - t0
         return [Result(req.rid, req.arrival_s, start, done, slot, info["n_cells"], info["n_kept"],
-                       m.numpy(), a.numpy().view(np.uint64))
-                for req, info, (m, a) in zip(reqs, infos, answers)]
+                       m.numpy(), a.numpy().view(np.uint64),
+                       None if ex is None else tuple(t.cpu().numpy() for t in ex))
+                for req, info, (m, a), ex in zip(reqs, infos, answers, exports)]
 
     def run(self, requests: List[W.ServeRequest], realtime: bool = True,
             max_batch: int = 16) -> dict:
@@ -290,9 +298,10 @@ class Server:
         }
 
 
-def serve_alone(requests: List[W.ServeRequest], device: int = 0) -> List[Result]:
+def serve_alone(requests: List[W.ServeRequest], device: int = 0,
+                export_results: bool = False) -> List[Result]:
     """Each request solved and queried by itself, one after the other."""
-    srv = Server(n_slots=1, device=device)
+    srv = Server(n_slots=1, device=device, export_results=export_results)
     try:
         queries = [Queries.of(r) for r in requests]
         t0 = time.perf_counter()

@@ -18,14 +18,18 @@ Digests are over the arrays' little-endian bytes.  Workloads:
   vdp2_adaptive_32^4_r2  the coupled Van der Pol solve: rounds 0 and 1 in full
                          (covering, graph, non-leaving analysis), and the round-2
                          covering, i.e. the oracle's boundary selection and
-                         subdivision (Sec. 3.1.1) of round 1's result
+                         subdivision (Sec. 3.1.1) of round 1's result; with
+                         --only vdp2r2 also round 2's graph and analysis (the
+                         graph, 62 GB, is written to files under --workdir and
+                         the oracle's analysis runs on them memory-mapped)
   serving stream         every request of the seeded serving test stream
                          (Van der Pol, grids 32^2 .. 256^2): final covering,
                          kept set, masks, and the answers to its queries
 
-Usage: python tests/golden/make_digests.py [--procs 8] [--only NAME]
+Usage: python tests/golden/make_digests.py [--procs 8] [--only NAME] [--workdir DIR]
 Takes about 10 minutes with 8 processes and about 30 GB of memory (the
-round-1 graph of the coupled Van der Pol solve has 2.75e9 edges).
+round-1 graph of the coupled Van der Pol solve has 2.75e9 edges); vdp2r2
+about an hour more and 62 GB of disk.
 """
 from __future__ import annotations
 
@@ -150,6 +154,70 @@ def vdp2(procs):
             "analysis": wl.analysis, "rounds": rounds}
 
 
+class _Sha:
+    """Running SHA-256 over the little-endian bytes of arrays fed in order."""
+
+    def __init__(self):
+        self.h = hashlib.sha256()
+
+    def feed(self, a):
+        self.h.update(np.ascontiguousarray(a).tobytes())
+
+    def hex(self):
+        return self.h.hexdigest()
+
+
+def vdp2_round2(procs, workdir):
+    """Round 2 of the coupled Van der Pol solve: the round-2 covering is
+    recomputed (rounds 0 and 1, checked against the stored digest), its
+    graph built by row ranges and streamed to files (row offsets, targets,
+    OUT flags) while the digests run, then the oracle's analysis reads the
+    files memory-mapped."""
+    wl = W.vdp2_adaptive_32()
+    level, idx = oracle.coarse_cells(wl.grid)
+    for r in range(2):
+        log(f"{wl.name}: round {r}: build {level.shape[0] * wl.K} rows (to reach round 2)")
+        g = build_graph(wl, level, idx, procs)
+        kept, mask, _ = oracle.prune(g["row_ptr"], g["col"], g["out"], level.shape[0], wl.K,
+                                     wl.analysis)
+        del g
+        bnd = oracle.boundary(wl.grid, level, idx, kept, wl.boundary_rule)
+        level, idx = oracle.subdivide(wl.grid, level, idx, kept, bnd)
+    n_cells = level.shape[0]
+    n_rows = n_cells * wl.K
+    cov = covering_entry(level, idx)
+    os.makedirs(workdir, exist_ok=True)
+    f_rp, f_col, f_out = (os.path.join(workdir, f) for f in ("row_ptr.i64", "col.i32", "out.u8"))
+    h_rp, h_col, h_out = _Sha(), _Sha(), _Sha()
+    n_chunks = 1024
+    cuts = np.linspace(0, n_rows, n_chunks + 1).astype(np.int64)
+    total = 0
+    log(f"{wl.name}: round 2: build {n_rows} rows into {workdir}")
+    ctx = mp.get_context("fork")
+    with open(f_rp, "wb") as frp, open(f_col, "wb") as fcol, open(f_out, "wb") as fout, \
+            ctx.Pool(procs, initializer=_init, initargs=(wl, level, idx)) as pool:
+        zero = np.zeros(1, dtype=np.int64)
+        frp.write(zero.tobytes())
+        h_rp.feed(zero)
+        for i, (cnt, col, out) in enumerate(pool.imap(_chunk, list(zip(cuts[:-1], cuts[1:])))):
+            rp = np.cumsum(cnt) + total
+            total = int(rp[-1]) if rp.shape[0] else total
+            for f, h, a in ((frp, h_rp, rp), (fcol, h_col, col), (fout, h_out, out)):
+                f.write(np.ascontiguousarray(a).tobytes())
+                h.feed(a)
+            if i % 64 == 0:
+                log(f"  chunk {i}/{n_chunks}: {total} edges so far")
+    graph = {"n_rows": int(n_rows), "n_edges": int(total), "row_ptr": h_rp.hex(), "col": h_col.hex(),
+             "out": h_out.hex()}
+    rp = np.memmap(f_rp, dtype=np.int64, mode="r")
+    col = np.memmap(f_col, dtype=np.int32, mode="r")
+    out = np.memmap(f_out, dtype=np.uint8, mode="r")
+    graph["n_out"] = int(np.sum(out, dtype=np.int64))
+    log(f"{wl.name}: round 2: {wl.analysis} analysis ({total} edges, memory-mapped)")
+    kept, mask, sweeps = oracle.prune(rp, col, out, n_cells, wl.K, wl.analysis)
+    return {"covering": cov, "graph": graph, wl.analysis: analysis_entry(kept, mask, sweeps)}
+
+
 def serving():
     reqs = W.serving_stream(SERVE_STREAM["n_requests"], SERVE_STREAM["rate_per_s"],
                             seed=SERVE_STREAM["seed"], n_queries=SERVE_STREAM["n_queries"])
@@ -172,7 +240,9 @@ def serving():
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--procs", type=int, default=8)
-    p.add_argument("--only", default=None, help="lorenz, vdp2 or serving")
+    p.add_argument("--only", default=None, help="lorenz, vdp2, serving or vdp2r2")
+    p.add_argument("--workdir", default=os.path.join(ROOT, "_work", "big"),
+                   help="where vdp2r2 writes the round-2 graph (62 GB)")
     a = p.parse_args()
     oracle._load()
     data = {}
@@ -183,6 +253,18 @@ def main():
             "vdp2": lambda: vdp2(a.procs)}
     keys = {"serving": "serving_stream", "lorenz": "lorenz_uniform_128^3",
             "vdp2": "vdp2_adaptive_32^4_r2"}
+    if a.only == "vdp2r2":
+        t = time.time()
+        r2 = vdp2_round2(a.procs, a.workdir)
+        entry = data["vdp2_adaptive_32^4_r2"]
+        if r2["covering"] != entry["rounds"][2]["covering"]:
+            raise SystemExit("round-2 covering differs from the stored one")
+        entry["rounds"][2] = r2
+        entry["round2_oracle_seconds"] = round(time.time() - t, 1)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        log(f"vdp2r2 done in {time.time() - t:.0f} s")
+        return
     for name, fn in jobs.items():
         if a.only and a.only != name:
             continue

@@ -1,14 +1,27 @@
-"""Full-size GPU checks on the large workloads, where the oracle cannot
-evaluate every row:
+"""Full-size GPU parity on the large workloads against digests of the CPU
+oracle's results (tests/golden/digests_fullsize.json, written by
+tests/golden/make_digests.py, which calls only oracle/ and the seeded
+generators):
 
-* the FP32-with-FP64-recheck graph equals the FP64 graph element by element
-  over the whole graph (on the device);
-* sampled rows (edges and OUT flags) equal the oracle's rows of the same
-  covering, computed one by one;
-* the kept set is the fixed point of the analysis reached from "all cells"
-  by synchronous sweeps, re-derived here with plain tensor operations on the
-  graph (a property that holds at any size).
+* Lorenz-type 128^3 (44 M rows): the graph (row offsets, targets, OUT flags)
+  of both image precisions, and kept flags and masks of both analyses;
+* coupled Van der Pol 32^4 with two boundary rounds: every round's covering,
+  graph and non-leaving analysis through the step entry points (gis_build_graph,
+  gis_prune, gis_subdivide), FP64 and FP32 with the FP64 recheck (equal
+  element by element on the device), and the whole gis_solve in both
+  precisions against the last round's digests; with every row of every round
+  checked against the recheck band.
+
+Digests are SHA-256 of the arrays' little-endian bytes, the layout of the C
+ABI (row_ptr i64, col i32, out u8, level u8, idx i32 cell-major, kept u8,
+mask u64 words).  Where a digest is absent (the oracle's round-2 graph of the
+coupled system takes an hour to produce), sampled rows are checked against
+rows the oracle computes one by one.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -20,6 +33,9 @@ from paper_2202_06111_amd import workloads as W
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
 
+DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "digests_fullsize.json")
+
 
 @pytest.fixture(scope="module")
 def G():
@@ -28,124 +44,158 @@ def G():
 
 
 @pytest.fixture(scope="module")
-def ctx(G):
-    c = G.Context(0)
-    yield c
-    c.close()
+def D():
+    with open(DIGESTS) as f:
+        return json.load(f)
 
 
-def _sample_rows_against_oracle(wl, level_np, idx_np, graph, n_sample, seed, fast_out=False):
+def _sha(t: torch.Tensor, chunk: int = 1 << 28) -> str:
+    """SHA-256 of a device tensor's bytes, copied to the host in chunks."""
+    h = hashlib.sha256()
+    flat = t.contiguous().reshape(-1).view(torch.uint8)
+    for i in range(0, flat.numel(), chunk):
+        h.update(flat[i:i + chunk].cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+def _check_covering(level, idx, want, what):
+    assert int(level.shape[0]) == want["n_cells"], what
+    assert _sha(level) == want["level"], what
+    assert _sha(idx) == want["idx"], what
+
+
+def _check_graph(g, want, what):
+    assert (g.n_rows, g.n_edges, g.n_out) == (want["n_rows"], want["n_edges"], want["n_out"]), what
+    assert _sha(g.row_ptr) == want["row_ptr"], what
+    assert _sha(g.col) == want["col"], what
+    assert _sha(g.out) == want["out"], what
+
+
+def _check_analysis(kept, mask, want, what):
+    assert int(kept.sum().item()) == want["n_kept"], what
+    assert _sha(kept) == want["kept"], what
+    assert _sha(mask) == want["mask"], what
+
+
+def _sample_rows_against_oracle(wl, level, idx, g, n_sample, seed):
+    """Edges and OUT flags of sampled rows against the oracle's rows of the
+    same covering, computed one by one."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    n_rows = graph.n_rows
-    rows = np.unique(np.concatenate([rng.integers(0, n_rows, size=n_sample),
-                                     [0, n_rows - 1]])).astype(np.int64)
-    want = oracle.build_graph(wl.system, wl.grid, wl.samples, level_np, idx_np, wl.u,
-                              fast_out=fast_out, rows=rows)
-    rp = graph.row_ptr.cpu().numpy()
-    out = graph.out.cpu().numpy()
-    col = graph.col
+    rows = np.unique(np.concatenate([rng.integers(0, g.n_rows, size=n_sample),
+                                     [0, g.n_rows - 1]])).astype(np.int64)
+    lv, ix = level.cpu().numpy(), idx.cpu().numpy()
+    want = oracle.build_graph(wl.system, wl.grid, wl.samples, lv, ix, wl.u, rows=rows)
+    rt = torch.as_tensor(rows, device=g.row_ptr.device)
+    a = g.row_ptr[rt].cpu().numpy()
+    b = g.row_ptr[rt + 1].cpu().numpy()
+    out = g.out[rt].cpu().numpy()
     pos = 0
     for i, r in enumerate(rows):
-        a, b = int(rp[r]), int(rp[r + 1])
-        got = col[a:b].cpu().numpy()
+        got = g.col[int(a[i]):int(b[i])].cpu().numpy()
         c = int(want["cnt"][i])
         np.testing.assert_array_equal(got, want["col"][pos:pos + c], err_msg=f"row {r}")
         pos += c
-        assert out[r] == want["out"][i], f"row {r}"
-    return rows
+        assert out[i] == want["out"][i], f"row {r}"
 
 
-def _fixed_point(row_ptr, col, out, n_cells, K, analysis):
-    """Synchronous sweeps K_{t+1} = {c in K_t : exists u good_t(c, u)} from every cell."""
-    dev = col.device
-    n_rows = n_cells * K
-    deg = (row_ptr[1:] - row_ptr[:-1])
-    src = torch.repeat_interleave(torch.arange(n_rows, device=dev), deg)
-    kept = torch.ones(n_cells, dtype=torch.bool, device=dev)
-    out_b = out.bool()
-    for _ in range(100000):
-        tk = kept[col.long()].to(torch.int32)
-        hit = torch.zeros(n_rows, dtype=torch.int32, device=dev).index_add_(0, src, tk)
-        if analysis == "controlled":
-            good = (~out_b) & (hit == deg.to(torch.int32))
-        else:
-            good = hit > 0
-        new = kept & good.view(n_cells, K).any(dim=1)
-        if torch.equal(new, kept):
-            return kept, good.view(n_cells, K)
-        kept = new
-    raise AssertionError("no fixed point")
-
-
-def test_lorenz_128_full_graph(G, ctx):
+def test_lorenz_128_full_graph(G, D):
+    want = D["lorenz_uniform_128^3"]["rounds"][0]
     wl = W.lorenz_uniform_128()
-    level, idx = G.coarse_cells(ctx, wl.grid)
-    band = G.calibrate_band(ctx, wl.system, wl.grid, wl.u, level, idx, wl.samples, safety=8.0,
-                            floor_rel=1e-5)
-    g32 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
-                        G.opts_t(samples=wl.samples, precision="fp32_recheck", band=band))
-    g64 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
-                        G.opts_t(samples=wl.samples, precision="fp64"))
-    print(f"lorenz 128^3: rows {g64.n_rows} edges {g64.n_edges} out {g64.n_out} "
-          f"recheck {g32.n_recheck} band {band}", flush=True)
-    assert g32.n_edges == g64.n_edges
-    assert torch.equal(g32.row_ptr, g64.row_ptr)
-    assert torch.equal(g32.col, g64.col)
-    assert torch.equal(g32.out, g64.out)
-    del g32
+    with G.Context(0) as ctx:
+        level, idx = G.coarse_cells(ctx, wl.grid)
+        _check_covering(level, idx, want["covering"], "lorenz covering")
+        band = G.calibrate_band(ctx, wl.system, wl.grid, wl.u, level, idx, wl.samples,
+                                safety=8.0, floor_rel=1e-5)
+        g64 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
+                            G.opts_t(samples=wl.samples, precision="fp64"))
+        _check_graph(g64, want["graph"], "lorenz fp64 graph")
+        g32 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
+                            G.opts_t(samples=wl.samples, precision="fp32_recheck", band=band))
+        print(f"lorenz 128^3: rows {g64.n_rows} edges {g64.n_edges} out {g64.n_out} "
+              f"recheck {g32.n_recheck} band {band}", flush=True)
+        assert torch.equal(g32.row_ptr, g64.row_ptr) and torch.equal(g32.col, g64.col)
+        assert torch.equal(g32.out, g64.out)
+        del g32
+        for analysis in ("controlled", "nonleaving"):
+            kept, mask, nk = G.prune(ctx, g64, int(level.shape[0]), wl.K, analysis)
+            _check_analysis(kept, mask, want[analysis], f"lorenz {analysis}")
+            print(f"  {analysis}: kept {nk}", flush=True)
+        del g64
     torch.cuda.empty_cache()
-    lv_np, ix_np = oracle.coarse_cells(wl.grid)
-    assert np.array_equal(level.cpu().numpy(), lv_np) and np.array_equal(idx.cpu().numpy(), ix_np)
-    _sample_rows_against_oracle(wl, lv_np, ix_np, g64, 3000, seed=1)
-    for analysis in ("controlled", "nonleaving"):
-        kept, mask, nk = G.prune(ctx, g64, lv_np.shape[0], wl.K, analysis)
-        want_kept, want_good = _fixed_point(g64.row_ptr, g64.col, g64.out, lv_np.shape[0], wl.K,
-                                            analysis)
-        assert torch.equal(kept.bool(), want_kept), analysis
-        bits = (want_good & want_kept[:, None]).to(torch.int64)
-        want_mask = (bits << torch.arange(wl.K, device=bits.device)[None, :]).sum(dim=1)
-        assert torch.equal(mask[:, 0], want_mask), analysis
-        print(f"  {analysis}: kept {nk}", flush=True)
 
 
-def test_vdp2_32_two_rounds_full_solve(G):
-    """The coupled Van der Pol workload at full size (32^4 coarse cells, two
-    boundary rounds, 49 inputs, 1.6e9 rows in the last round).  Its final
-    graph is too large to re-derive here, so the check takes sampled cells of
-    the final covering and computes their rows with the oracle, one by one,
-    against that covering: a kept cell's admissible inputs are exactly its
-    rows with a kept target, and a removed cell has no row with a kept target
-    (otherwise adding it back would give a larger fixed point)."""
+def test_vdp2_32_two_rounds_by_steps(G, D):
+    """Round by round through the step entry points, both image precisions;
+    the FP32 band is calibrated on each round's covering (every row)."""
+    want = D["vdp2_adaptive_32^4_r2"]
+    rounds = want["rounds"]
+    wl = W.vdp2_adaptive_32()
+    with G.Context(0) as ctx:
+        level, idx = G.coarse_cells(ctx, wl.grid)
+        for r in range(wl.rounds + 1):
+            wr = rounds[r]
+            _check_covering(level, idx, wr["covering"], f"round {r} covering")
+            n_cells = int(level.shape[0])
+            cap = wr["graph"]["n_edges"] if "graph" in wr else None
+            g64 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
+                                G.opts_t(samples=wl.samples, precision="fp64"), cap_edges=cap)
+            if "graph" in wr:
+                _check_graph(g64, wr["graph"], f"round {r} graph")
+            else:
+                _sample_rows_against_oracle(wl, level, idx, g64, 400, seed=40 + r)
+            band = G.calibrate_band(ctx, wl.system, wl.grid, wl.u, level, idx, wl.samples,
+                                    safety=8.0, floor_rel=1e-5)
+            g32 = G.build_graph(ctx, wl.system, wl.grid, wl.u, level, idx,
+                                G.opts_t(samples=wl.samples, precision="fp32_recheck", band=band),
+                                cap_edges=g64.n_edges)
+            print(f"vdp2 round {r}: cells {n_cells} rows {g64.n_rows} edges {g64.n_edges} "
+                  f"recheck {g32.n_recheck} band {band}", flush=True)
+            assert g32.n_edges == g64.n_edges and g32.n_out == g64.n_out
+            assert torch.equal(g32.row_ptr, g64.row_ptr) and torch.equal(g32.out, g64.out)
+            assert torch.equal(g32.col, g64.col)
+            del g32
+            torch.cuda.empty_cache()
+            kept, mask, nk = G.prune(ctx, g64, n_cells, wl.K, wl.analysis)
+            del g64
+            torch.cuda.empty_cache()
+            if wl.analysis in wr:
+                _check_analysis(kept, mask, wr[wl.analysis], f"round {r} analysis")
+            if r < wl.rounds:
+                level, idx, bnd = G.subdivide(ctx, wl.grid, level, idx, kept, wl.boundary_rule)
+                assert int(bnd.sum().item()) == wr["n_boundary"], f"round {r} boundary"
+            del kept, mask
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_recheck"])
+def test_vdp2_32_two_rounds_full_solve(G, D, precision):
+    """The whole gis_solve (the benchmarked path) against the last round's
+    digests; FP32: every row of every round is checked against its round's
+    recheck band (check_band), and the largest FP32 error stays within it."""
+    want = D["vdp2_adaptive_32^4_r2"]["rounds"]
     wl = W.vdp2_adaptive_32()
     torch.cuda.empty_cache()
-    ctx = G.Context(0)
-    try:
-        sol = G.solve(ctx, wl.system, wl.grid, wl.u, wl.rounds, G.workload_opts(wl, precision="fp64"))
+    with G.Context(0) as ctx:
+        over = dict(precision=precision)
+        if precision != "fp64":
+            over["check_band"] = True
+        sol = G.solve(ctx, wl.system, wl.grid, wl.u, wl.rounds, G.workload_opts(wl, **over))
         inf = sol.info()
-        print("vdp2 32^4 r2: " + ", ".join(
-            f"round {i}: cells {r['n_cells']} rows {r['n_rows']} edges {r['n_edges']} "
-            f"kept {r['n_kept']}" for i, r in enumerate(inf["rounds"])), flush=True)
+        for i, rs in enumerate(inf["rounds"]):
+            print(f"vdp2 solve {precision} round {i}: cells {rs['n_cells']} rows {rs['n_rows']} "
+                  f"edges {rs['n_edges']} kept {rs['n_kept']} recheck {rs['n_recheck']} "
+                  f"band {rs['band']} max_err_all {rs['max_err_all']}", flush=True)
+            assert rs["n_cells"] == want[i]["covering"]["n_cells"]
+            if "graph" in want[i]:
+                assert rs["n_edges"] == want[i]["graph"]["n_edges"]
+                assert rs["n_out"] == want[i]["graph"]["n_out"]
+            if wl.analysis in want[i]:
+                assert rs["n_kept"] == want[i][wl.analysis]["n_kept"]
+            if precision != "fp64":
+                assert all(0 < e <= b for e, b in zip(rs["max_err_all"], rs["band"])), i
         lv, ix, kept, mask = sol.export()
-        lv, ix = lv.cpu().numpy(), ix.cpu().numpy()
-        kept, mask = kept.cpu().numpy().astype(bool), mask[:, 0].cpu().numpy().view(np.uint64)
+        _check_covering(lv, ix, want[2]["covering"], "final covering")
+        if wl.analysis in want[2]:
+            _check_analysis(kept, mask, want[2][wl.analysis], "final analysis")
         sol.free()
-    finally:
-        ctx.close()
     torch.cuda.empty_cache()
-    n_cells, K = lv.shape[0], wl.K
-    assert inf["n_rounds"] == 3 and n_cells == inf["n_cells"] and 0 < kept.sum() < n_cells
-    rng = np.random.Generator(np.random.PCG64(5))
-    cells = np.unique(np.concatenate([rng.integers(0, n_cells, size=300),
-                                      rng.choice(np.flatnonzero(kept), size=150),
-                                      rng.choice(np.flatnonzero(~kept), size=150)]))
-    rows = (cells[:, None] * K + np.arange(K)[None, :]).reshape(-1)
-    want = oracle.build_graph(wl.system, wl.grid, wl.samples, lv, ix, wl.u, rows=rows)
-    starts = np.concatenate([[0], np.cumsum(want["cnt"])])
-    good = np.array([bool(kept[want["col"][starts[i]:starts[i + 1]]].any())
-                     for i in range(rows.shape[0])]).reshape(-1, K)
-    for i, c in enumerate(cells):
-        bits = np.uint64(sum(1 << u for u in range(K) if good[i, u]))
-        if kept[c]:
-            assert mask[c] == bits and bits != 0, f"cell {c}"
-        else:
-            assert not good[i].any() and mask[c] == 0, f"cell {c}"
