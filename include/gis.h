@@ -130,6 +130,13 @@ typedef struct gis_opts {
                              sample of every row (gis_round_stats.max_err_all) and fails
                              with GIS_E_INTERNAL if it exceeds the round's band; costs
                              about one more image pass per round */
+  int32_t neighbours;     /* N of the neighbourhood selection (Sec. 3.1.2, Figure 5): with
+                             GIS_SUBDIVIDE_BOUNDARY, the N kept cells whose centres lie
+                             nearest to each boundary cell's centre (Euclidean distance in
+                             state units, the cell itself not counted, equal distances by
+                             cell id) are subdivided with it; 0: boundary cells only
+                             (0..64) */
+  int32_t reserved;       /* 0 */
   double band[4];         /* absolute recheck band per dimension; 0 = gis_solve calibrates
                              it on each round's covering before that round's build:
                              band = max(8 e, 1e-5 w_finest), e the largest |FP32 - FP64|
@@ -174,6 +181,8 @@ typedef struct gis_round_stats {
   double max_err[4];    /* FP32 path, calibrated band: largest |FP32 - FP64| image difference
                            over the calibration sample of the round's covering */
   double max_err_all[4];  /* with opts.check_band: the same over every row (0 otherwise) */
+  int64_t n_selected;   /* cells subdivided after the round: the boundary cells and their
+                           neighbourhood (opts.neighbours), or the halved cells */
 } gis_round_stats;
 
 #define GIS_MAX_ROUNDS 32
@@ -253,12 +262,16 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
                   int32_t analysis, uint8_t* d_kept, uint64_t* d_mask, int64_t* n_kept,
                   void* stream);
 
-/* Boundary selection and subdivision (Sec. 3.1.1).  d_boundary [in->n_cells]
- * receives the boundary flags (may be NULL).  Synchronises; out->n_cells is the
- * new cell count, GIS_E_CAPACITY if it exceeds out->cap (nothing written). */
+
+/* Boundary selection and subdivision (Sec. 3.1.1), with the neighbourhood of
+ * the boundary cells (Sec. 3.1.2) when neighbours > 0 (0..64, GIS_E_INVAL
+ * beyond): the boundary cells and the `neighbours` kept cells nearest to each
+ * are split into their 2^n children.  d_boundary [in->n_cells] receives the
+ * boundary flags (may be NULL).  Synchronises; out->n_cells is the new cell
+ * count, GIS_E_CAPACITY if it exceeds out->cap (nothing written). */
 int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
-                      const uint8_t* d_kept, int32_t boundary_rule, uint8_t* d_boundary,
-                      gis_cells* out, void* stream);
+                      const uint8_t* d_kept, int32_t boundary_rule, int32_t neighbours,
+                      uint8_t* d_boundary, gis_cells* out, void* stream);
 
 /* Standard subdivision (Sec. 2.1): halves every kept cell of `in` across
  * dimension `dim` (0 <= dim < n).  Every kept cell must be a level-0 cell of

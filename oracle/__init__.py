@@ -14,6 +14,10 @@ Parity status per function (what pins each one is in tests/test_oracle_*.py):
   prune           pinned: brute-force subset enumeration, drift/contraction
                   special cases, 1-D linear closed-form invariant interval,
                   textbook non-leaving set via strongly connected components
+  neighbours      pinned: the 5x5 worked example of Sec. 3.1.2 (Figure 5);
+                  brute force with exact rational centre distances on
+                  dyadic mixed-level coverings; closed-form nearest cells on
+                  a grid of non-square cells
   boundary        pinned: the 5x5 worked example of Sec. 3.1.1 and Remark 1;
                   Algorithm 1 evaluated literally in exact rationals (enlarged
                   cells, vertex and edge-point probes) on random mixed-level
@@ -89,6 +93,8 @@ def _load():
         lib.or_prune.restype = I32
         lib.or_boundary.argtypes = [P, P, P, I64, P, I32, P]
         lib.or_boundary.restype = I32
+        lib.or_neighbours.argtypes = [P, P, P, I64, P, P, I32, P]
+        lib.or_neighbours.restype = I32
         lib.or_subdivide.argtypes = [P, P, P, I64, P, P, P, P, I64]
         lib.or_subdivide.restype = I64
         lib.or_query.argtypes = [P, P, P, I64, P, P, I32, P, I64, P, P]
@@ -313,6 +319,22 @@ def boundary(grid, level, idx, kept, rule: str = "shell") -> np.ndarray:
     return bnd
 
 
+def neighbours(grid, level, idx, kept, bnd, N: int) -> np.ndarray:
+    """Cells selected for subdivision with a neighbourhood (Sec. 3.1.2): the
+    boundary cells and, for each, the N kept cells with the nearest centres
+    (the cell itself excluded; equal distances ordered by cell id)."""
+    lib = _load()
+    level, idx = _c(level, np.uint8), _c(idx, np.int32)
+    kept, bnd = _c(kept, np.uint8), _c(bnd, np.uint8)
+    sel = np.zeros(level.shape[0], dtype=np.uint8)
+    g = _grid(grid)
+    rc = lib.or_neighbours(ctypes.byref(g), _ptr(level), _ptr(idx), level.shape[0], _ptr(kept),
+                           _ptr(bnd), int(N), _ptr(sel))
+    if rc != 0:
+        raise ValueError(f"oracle neighbourhood failed ({rc})")
+    return sel
+
+
 def subdivide(grid, level, idx, kept, bnd):
     lib = _load()
     level, idx = _c(level, np.uint8), _c(idx, np.int32)
@@ -367,13 +389,14 @@ def query(grid, level, idx, kept, mask, states):
 
 def solve(system, grid, samples: str, u, rounds: int, rule: str = "shell",
           fast_out: bool = False, keep_graphs: bool = False, analysis: str = "controlled",
-          subdivision: str = "boundary"):
+          subdivision: str = "boundary", nn: int = 0):
     """The iteration loop: build and prune on the coarse covering, then
     `rounds` times subdivide, rebuild and prune.  subdivision "boundary":
     the 2^n children of the boundary cells (Sec. 3.1); "bisect": the
     standard algorithm's halving of every kept cell (Sec. 2.1), across
     dimension 0 in the first subdivision, 1 in the second, ... cyclically.
-    Stops early when nothing is kept.  The result holds the grid of the
+    nn > 0 ("boundary" only): the nn kept cells nearest to each boundary cell
+    are subdivided as well (Sec. 3.1.2).  Stops early when nothing is kept.  The result holds the grid of the
     final covering (the coarse grid unless cells were bisected)."""
     u = _c(u, np.float64)
     K = u.shape[0]
@@ -388,8 +411,10 @@ def solve(system, grid, samples: str, u, rounds: int, rule: str = "shell",
                 stats[-1]["n_boundary"] = int(kept.sum())
             else:
                 bnd = boundary(grid, level, idx, kept, rule)
-                level, idx = subdivide(grid, level, idx, kept, bnd)
+                sel = neighbours(grid, level, idx, kept, bnd, nn) if nn > 0 else bnd
+                level, idx = subdivide(grid, level, idx, kept, sel)
                 stats[-1]["n_boundary"] = int(bnd.sum())
+                stats[-1]["n_selected"] = int(sel.sum())
         if level.shape[0] == 0:
             break
         g = build_graph(system, grid, samples, level, idx, u, fast_out=fast_out)

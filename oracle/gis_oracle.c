@@ -36,7 +36,10 @@
  *    adjacent to the cell, which includes the edge points of Remark 1; rule 2
  *    ("corners") probes the 2^n diagonal corners only (Algorithm 1 as
  *    printed).
- *  - Subdivision splits each boundary cell into its 2^n children.
+ *  - Subdivision splits each boundary cell into its 2^n children, and with a
+ *    neighbourhood size N > 0 also the N kept cells nearest to each boundary
+ *    cell (Sec. 3.1.2): distances between cell centres in state units, the
+ *    cell itself not counted, equal distances ordered by cell id.
  */
 #include <math.h>
 #include <stdint.h>
@@ -558,6 +561,67 @@ int64_t or_subdivide(const or_grid* g, const uint8_t* level, const int32_t* idx,
   }
   free(rec);
   return cnt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Neighbourhood of the boundary cells (Sec. 3.1.2, Figure 5): for each  */
+/* boundary cell, the N kept cells whose centres lie nearest to its      */
+/* centre, by brute force over every kept cell.                          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double d2;
+  int64_t id;
+} or_nb;
+
+static int cmp_nb(const void* x, const void* y) {
+  const or_nb* a = (const or_nb*)x;
+  const or_nb* b = (const or_nb*)y;
+  if (a->d2 != b->d2) return a->d2 < b->d2 ? -1 : 1;
+  return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+/* Squared Euclidean distance (state units) between the centres of cells a
+ * and b.  The centre of a level-L cell with index i lies at
+ * lo + (2 i + 1) w_L / 2; on the grid of half the finest width every centre
+ * is an integer point, so the difference of two centres is formed exactly
+ * there, then scaled by that half width, squared and summed over the
+ * dimensions in order.  */
+static double centre_d2(const or_grid* g, int Lstar, const uint8_t* level, const int32_t* idx,
+                        int64_t a, int64_t b) {
+  double s = 0.0;
+  for (int d = 0; d < g->n; ++d) {
+    const int64_t ca = (2 * (int64_t)idx[a * g->n + d] + 1) << (Lstar - level[a]);
+    const int64_t cb = (2 * (int64_t)idx[b * g->n + d] + 1) << (Lstar - level[b]);
+    const double t = (double)(ca - cb) * width(g, d, Lstar + 1);
+    s = s + t * t;
+  }
+  return s;
+}
+
+/* sel[c] = 1 for every boundary cell (kept and boundary[c]) and for the N
+ * kept cells nearest to some boundary cell (the cell itself not counted;
+ * equal distances ordered by cell id); 0 otherwise.  Returns 0, or -2 when
+ * out of memory. */
+int32_t or_neighbours(const or_grid* g, const uint8_t* level, const int32_t* idx, int64_t n_cells,
+                      const uint8_t* kept, const uint8_t* boundary, int32_t N, uint8_t* sel) {
+  const int Lstar = or_max_level(level, n_cells);
+  or_nb* cand = (or_nb*)malloc(sizeof(or_nb) * (size_t)(n_cells > 0 ? n_cells : 1));
+  if (!cand) return -2;
+  for (int64_t c = 0; c < n_cells; ++c) sel[c] = (kept[c] && boundary[c]) ? 1 : 0;
+  for (int64_t b = 0; b < n_cells && N > 0; ++b) {
+    if (!(kept[b] && boundary[b])) continue;
+    int64_t m = 0;
+    for (int64_t j = 0; j < n_cells; ++j) {
+      if (j == b || !kept[j]) continue;
+      cand[m].d2 = centre_d2(g, Lstar, level, idx, b, j);
+      cand[m].id = j;
+      ++m;
+    }
+    qsort(cand, (size_t)m, sizeof(or_nb), cmp_nb);
+    for (int64_t k = 0; k < m && k < N; ++k) sel[cand[k].id] = 1;
+  }
+  free(cand);
+  return 0;
 }
 
 /* ------------------------------------------------------------------ */

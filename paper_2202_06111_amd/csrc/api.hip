@@ -139,8 +139,8 @@ struct gis_ctx {
   GraphCache graphs;
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
-  DevBuf removed, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front, wit;
-  DevBuf bnd, scc;
+  DevBuf removed, rbits, rowbits, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front, wit;
+  DevBuf bnd, sel, scc;
   Pinned<unsigned long long> h_scc;  // largest-component search: per-job keys and counts
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
@@ -228,6 +228,9 @@ int32_t check_opts(const gis_opts* o) {
   // the non-leaving and largest-component analyses count an OUT row's edges
   if (o->fast_out && o->analysis != GIS_ANALYSIS_CONTROLLED)
     return inval("fast_out requires the controlled analysis");
+  if (o->neighbours < 0 || o->neighbours > 64) return inval("neighbours must be 0..64");
+  if (o->neighbours > 0 && o->subdivision != GIS_SUBDIVIDE_BOUNDARY)
+    return inval("neighbours requires the boundary subdivision");
   return GIS_OK;
 }
 
@@ -681,6 +684,10 @@ constexpr int32_t kMaxSweeps = 256;
 PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   PruneWork w{};
   w.removed = (uint8_t*)ctx->removed.ptr;
+  w.rbits = (uint32_t*)ctx->rbits.ptr;
+  w.rbits_cells = (int64_t)(ctx->rbits.bytes / 4) * 32;
+  w.rowbits = (uint64_t*)ctx->rowbits.ptr;
+  w.rowbits_rows = (int64_t)(ctx->rowbits.bytes / 8) * 64;
   w.last = &dcnt(ctx)->sweep_last;
   w.rptr = (int64_t*)ctx->rptr.ptr;
   w.rrow = (int32_t*)ctx->rrow.ptr;
@@ -842,7 +849,10 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
     set_error("a graph of more than 2^31-1 rows is not supported");
     return GIS_E_UNSUPPORTED;
   }
-  if ((rc = ensure(ctx->removed, (size_t)n_cells + 16))) return rc;
+  if ((rc = ensure(ctx->removed, (size_t)n_cells + 16)) ||
+      (rc = ensure(ctx->rbits, (size_t)(n_cells + 31) / 32 * 4 + 16)) ||
+      (rc = ensure(ctx->rowbits, (size_t)(n_cells * K + 63) / 64 * 8 + 16)))
+    return rc;
   if (first <= 0) first = ctx->tune.first_sweeps;
   const bool wit = witness_sweeps(ctx, analysis);
   if (wit) {
@@ -856,14 +866,15 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
   // the sweeps and the final pass: one launch sequence, replayed as a graph
   struct Key {
-    const void* p[14];
+    const void* p[16];
     int64_t n_cells, cap_edges;
     int32_t K, analysis, first, sweep_blocks, n_jobs, clear;
   } key;
   memset(&key, 0, sizeof key);
-  const void* ptrs[14] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
+  const void* ptrs[16] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
                           dcnt(ctx)->n_kept, B ? B->d_jobs : nullptr, B ? B->d_stats : nullptr,
-                          level, idx, wit ? (const void*)w.cstart : nullptr};
+                          level, idx, wit ? (const void*)w.cstart : nullptr, w.rbits,
+                          w.rowbits};
   memcpy(key.p, ptrs, sizeof ptrs);
   key.n_cells = n_cells;
   key.cap_edges = cap_edges;
@@ -1009,7 +1020,7 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
 int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_t* idx,
                           const uint8_t* kept, int32_t rule, uint8_t* boundary, uint8_t* lv_out,
                           int32_t* ix_out, int64_t cap, hipStream_t s, bool holes_marked = false,
-                          uint32_t* bisect_err = nullptr) {
+                          uint32_t* bisect_err = nullptr, int32_t nn = 0) {
   int32_t rc;
   const BatchArgs ba = B.args(level, idx);
   const int64_t total = next_total(B);
@@ -1023,7 +1034,14 @@ int32_t enqueue_subdivide(gis_ctx* ctx, Batch& B, const uint8_t* level, const in
     if ((rc = batch_bisect(ba, kept, B.bisect_dim, boundary, B.d_stats, bisect_err, s))) return rc;
   } else {
     if (!holes_marked && (rc = batch_mark_dropped(ba, kept, s))) return rc;
-    if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s))) return rc;
+    if ((rc = batch_boundary(ba, kept, rule, boundary, B.d_stats, s, nn == 0))) return rc;
+    if (nn > 0) {
+      // the caller sized ctx->sel for the cells
+      uint8_t* sel = (uint8_t*)ctx->sel.ptr;
+      if ((rc = fill_u8(sel, 0, B.total_cells, s)) ||
+          (rc = batch_neighbours(ba, kept, boundary, nn, sel, B.d_stats, s)))
+        return rc;
+    }
   }
   if (total > 0) {
     if ((rc = scan_exclusive_u8((const uint8_t*)ctx->next_state.ptr, (int64_t*)ctx->pos.ptr, total,
@@ -1355,7 +1373,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     if ((rc = ensure(ctx->row_ptr, (size_t)(n_rows + 1) * 8)) || (rc = ensure(ctx->out, (size_t)n_rows + 16)) ||
         (rc = ensure(ctx->col, want_col * 4)) || (rc = ensure(ctx->kept, (size_t)n_cells + 16)) ||
         (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)) ||
-        (rc = ensure(ctx->removed, (size_t)n_cells + 16)))
+        (rc = ensure(ctx->removed, (size_t)n_cells + 16)) ||
+        (rc = ensure(ctx->rbits, (size_t)(n_cells + 31) / 32 * 4 + 16)) ||
+        (rc = ensure(ctx->rowbits, (size_t)(n_rows + 63) / 64 * 8 + 16)))
       return fail_all(rc);
     // one launch clears the counters and job stats, the index states (NONE
     // is 0) and the analysis' removed flags
@@ -1375,7 +1395,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     DevBuf& lvN = cur_is_A ? ctx->lvB : ctx->lvA;
     DevBuf& ixN = cur_is_A ? ctx->ixB : ctx->ixA;
     if (!last && ((rc = ensure(lvN, (size_t)cap + 16)) || (rc = ensure(ixN, (size_t)cap * n * 4 + 16)) ||
-                  (rc = ensure(ctx->bnd, (size_t)n_cells + 16))))
+                  (rc = ensure(ctx->bnd, (size_t)n_cells + 16)) ||
+                  (o.neighbours > 0 && (rc = ensure(ctx->sel, (size_t)n_cells + 16)))))
       return fail_all(rc);
     Graph gr{(int64_t*)ctx->row_ptr.ptr, (int32_t*)ctx->col.ptr, (uint8_t*)ctx->out.ptr,
              (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f, false};
@@ -1390,7 +1411,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if (phases) GIS_HIP(hipEventRecord(ev[2], s));
       if (!last && !scc && (e = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                           (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
-                                          (int32_t*)ixN.ptr, cap, s, K <= 256)))
+                                          (int32_t*)ixN.ptr, cap, s, K <= 256, nullptr, o.neighbours)))
         return e;
       if (phases) GIS_HIP(hipEventRecord(ev[3], s));
       return sync_stats(ctx, B, s);
@@ -1459,7 +1480,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if (phases) GIS_HIP(hipEventRecord(ev[2], s));
       if (!last && !scc && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
-                                           (int32_t*)ixN.ptr, cap, s, K <= 256)))
+                                           (int32_t*)ixN.ptr, cap, s, K <= 256, nullptr, o.neighbours)))
         return fail_all(rc);
       if (phases) GIS_HIP(hipEventRecord(ev[3], s));
       if ((rc = sync_stats(ctx, B, s))) return fail_all(rc);
@@ -1488,7 +1509,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
         return fail_all(rc);
       if (!last && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,
-                                           (int32_t*)ixN.ptr, cap, s, K <= 256)))
+                                           (int32_t*)ixN.ptr, cap, s, K <= 256, nullptr, o.neighbours)))
         return fail_all(rc);
       if ((rc = sync_stats(ctx, B, s))) return fail_all(rc);
       ctx->h_counters->total_edges = keep.total_edges;
@@ -1513,6 +1534,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       st.n_recheck = (int64_t)js.n_recheck;
       st.n_kept = (int64_t)js.n_kept;
       st.n_boundary = last ? 0 : (int64_t)js.n_boundary;
+      st.n_selected = last ? 0 : o.neighbours > 0 ? (int64_t)js.n_selected : st.n_boundary;
       st.max_level = B.lmax[j];
       st.ms_build = ms_b;
       st.ms_prune = ms_p;
@@ -1532,6 +1554,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if (!active[j]) continue;
       if (last || info[j].rounds[r].n_kept == 0) {
         info[j].rounds[r].n_boundary = 0;
+        info[j].rounds[r].n_selected = 0;
         if ((rc = make_solution(ctx, B, j, lv, ix, kept, mask, info[j], &out[j], s)))
           return fail_all(rc);
         active[j] = 0;
@@ -1753,14 +1776,15 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
 }
 
 int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
-                      const uint8_t* d_kept, int32_t boundary_rule, uint8_t* d_boundary,
-                      gis_cells* out, void* stream) {
+                      const uint8_t* d_kept, int32_t boundary_rule, int32_t neighbours,
+                      uint8_t* d_boundary, gis_cells* out, void* stream) {
   if (!ctx || !grid || !in || !out) return inval("ctx, grid, in and out are required");
   if (grid->n < 1 || grid->n > kMaxDim) return inval("grid dimension must be 1..4");
   int32_t rc;
   if ((rc = check_grid(grid, grid->n))) return rc;
   if (boundary_rule != GIS_BOUNDARY_SHELL && boundary_rule != GIS_BOUNDARY_CORNERS)
     return inval("unknown boundary rule");
+  if (neighbours < 0 || neighbours > 64) return inval("neighbours must be 0..64");
   if (in->n_cells < 0 || (in->n_cells > 0 && (!in->level || !in->idx || !d_kept)))
     return inval("invalid input cell list");
   if (out->cap > 0 && (!out->level || !out->idx)) return inval("output buffers missing");
@@ -1786,10 +1810,11 @@ int32_t gis_subdivide(gis_ctx* ctx, const gis_grid* grid, const gis_cells* in,
     if ((rc = ensure(ctx->bnd, (size_t)in->n_cells))) return rc;
     bnd = (uint8_t*)ctx->bnd.ptr;
   }
+  if (neighbours > 0 && (rc = ensure(ctx->sel, (size_t)in->n_cells + 16))) return rc;
   int64_t n_new = 0;
   if ((rc = zero_all(ctx, B, s))) return rc;
   if ((rc = enqueue_subdivide(ctx, B, in->level, in->idx, d_kept, boundary_rule, bnd, out->level,
-                              out->idx, out->cap, s)))
+                              out->idx, out->cap, s, false, nullptr, neighbours)))
     return rc;
   if ((rc = sync_stats(ctx, B, s))) return rc;
   rc = finish_subdivide(ctx, B, out->cap, &n_new);

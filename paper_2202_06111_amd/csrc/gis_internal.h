@@ -156,7 +156,7 @@ struct Job {
 
 // Per-job counters, read back once per phase.
 struct JobStats {
-  unsigned long long n_out, n_kept, n_boundary, n_recheck;
+  unsigned long long n_out, n_kept, n_boundary, n_recheck, n_selected;
   int64_t n_edges;
   int64_t next_start;                   // first new cell of the job (global position)
   int64_t level_start[kMaxLevels + 1];  // new cells before each level (global position)

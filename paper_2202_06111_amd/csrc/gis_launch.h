@@ -47,6 +47,10 @@ struct PruneWork {
   int64_t* cstart;     // [n_cells + 1] first edge of each cell's rows (row_ptr[c * K])
   int64_t* wpos;       // [n_cells] position of the cell's witness edge
   int32_t* wtgt;       // [n_cells] its target
+  uint32_t* rbits;     // removed flags packed 32 to a word for the final pass, or null
+  int64_t rbits_cells; // cells rbits has room for (the final pass packs only up to that)
+  uint64_t* rowbits;   // good-row flags of the final pass, 64 rows a word, or null
+  int64_t rowbits_rows;  // rows rowbits has room for
   int32_t* front;      // [2 * n_cells] the two frontier lists
   int32_t* fcount;     // [3] rotating list lengths
   void* scan_tmp;
@@ -164,11 +168,16 @@ int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_
                               const SccWork& w, hipStream_t s);
 
 // k_refine.hip, job-batched
-// Boundary flags of the kept cells (Sec. 3.1.1) and, for jobs with a next
-// layout, the next-covering flags (those arrays are zero on entry;
-// batch_compact leaves them zero again).
+// Boundary flags of the kept cells (Sec. 3.1.1) and, with flag_next, for
+// jobs with a next layout, the next-covering flags (those arrays are zero on
+// entry; batch_compact leaves them zero again).
 int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
-                       JobStats* stats, hipStream_t s);
+                       JobStats* stats, hipStream_t s, bool flag_next = true);
+// Neighbourhood selection (Sec. 3.1.2) after batch_boundary without next
+// flags: sel (zero on entry) gets the boundary cells and the nn (1..64) kept
+// cells nearest to each, then the next-covering flags are set from sel.
+int32_t batch_neighbours(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
+                         int32_t nn, uint8_t* sel, JobStats* stats, hipStream_t s);
 // Standard subdivision (Sec. 2.1): the next-covering flags of both halves of
 // every kept cell across dimension `dim`, the next layouts being level 0 of
 // the grid with twice the cells along `dim`; split[c] = 1 for the cells cut,

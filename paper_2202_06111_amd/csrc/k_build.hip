@@ -13,8 +13,12 @@
 //      their index from an atomic ticket, publish their edge total, and the
 //      first wave sums the totals of the blocks before it 64 at a time until
 //      it meets one that has published its inclusive prefix;
-//   5. row_ptr, and the target ids written into an LDS tile and copied to col
-//      with coalesced stores, tile by tile.
+//   5. row_ptr, and the target ids: on full level-0 grids written into an LDS
+//      tile and copied to col with coalesced stores, tile by tile; on
+//      refined coverings stored by each row directly (consecutive rows' ids
+//      are adjacent in col, so the L2 cache merges them into whole lines; a
+//      tile measured 8% slower there, coupled Van der Pol round 2, while on
+//      the uniform Lorenz-type grid direct stores were 40% slower).
 //
 // Cell ids follow the canonical order of the covering (level, then row-major
 // index), so enumerating the covering index level by level, row-major inside
@@ -31,7 +35,7 @@ namespace gis {
 namespace {
 
 constexpr int kTile = 4096;   // LDS staging tile of the emitter (int32 ids, 16 KiB)
-constexpr int kCache = 6;     // runs of target ids kept in LDS per row between count and emit
+constexpr int kCache = 8;     // runs of target ids kept in LDS per row between count and emit
 
 // Look-back words: the launch's epoch in bits 40-63, a status in bits 38-39
 // and an edge total in bits 0-37.  A word written by an earlier launch
@@ -104,7 +108,7 @@ __device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverInd
 // out ascending.  The cost is one call per row of the box and level, whatever
 // the box's width and however the covering is refined inside it; the loads
 // of kRuns runs are issued together.
-constexpr int kRuns = 4;
+constexpr int kRuns = 2;
 
 template <int N, typename F>
 __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* lo,
@@ -190,10 +194,11 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
     bh[d] = R(-INFINITY);
   }
   const int S = num_samples(a.samples, N);
-  // four-dimensional systems advance two samples at a time (independent
-  // chains for a kernel whose registers allow few waves); measured: 3% faster
-  // there, slower for the smaller systems (their occupancy drops)
-  constexpr int P = N >= 4 ? 2 : 1;
+  // one sample at a time: advancing two in lockstep (independent chains)
+  // raised the four-dimensional kernel's registers from 114 to 139 and its
+  // occupancy from 4 to 3 waves per SIMD, 9% slower on the coupled Van der
+  // Pol system's last round
+  constexpr int P = 1;
   for (int q0 = 0; q0 < S; q0 += P) {
     const int np = S - q0 < P ? S - q0 : P;
     R x[P][N];
@@ -375,7 +380,7 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
 template <int KIND, int N, bool F32, bool UNI>
 __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   __shared__ CoverIndex ci;
-  __shared__ int32_t tile[kTile];
+  __shared__ int32_t tile[UNI ? kTile : 1];
   __shared__ int2 cache[UNI ? 1 : kCache * kRowBlock];
   __shared__ int64_t wsum[kRowBlock / 64];
   __shared__ int64_t s_prefix;
@@ -515,6 +520,10 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   if (live && g == a.total_rows - 1) a.row_ptr[a.total_rows] = prefix + off + c;
   if (prefix + T > a.cap_edges) return;  // capacity miss: col is not written
   const int32_t id0 = (int32_t)J.cell_off;
+  if constexpr (!UNI) {
+    if (c > 0) emit_targets<N, UNI>(ci, lo, hi, c, cache + tid, id0, 0, c, a.col + prefix + off);
+    return;
+  }
   for (int64_t w0 = 0; w0 < T; w0 += kTile) {
     const int64_t w1 = T < w0 + kTile ? T : w0 + kTile;
     const int64_t s0 = off > w0 ? off : w0;

@@ -139,6 +139,44 @@ __global__ void k_check_graph(const int64_t* row_ptr, const int32_t* col, int64_
   }
 }
 
+// Removed flags as bytes (the sweeps update them in place), or packed 32 to
+// a word for the read-only final pass: an eighth of the bytes, so that the
+// flags of a large covering (4 MB for 32 M cells) stay in the L2 cache while
+// every row looks up its targets'.
+struct ByteFlags {
+  const uint8_t* p;
+  __device__ __forceinline__ bool operator[](int64_t j) const { return p[j] != 0; }
+};
+struct BitFlags {
+  const uint32_t* w;
+  __device__ __forceinline__ bool operator[](int64_t j) const {
+    return ((w[j >> 5] >> (j & 31)) & 1u) != 0;
+  }
+};
+
+// Packs removed bytes into words of 32 flags (bit i of word k: cell 32k + i).
+__global__ __launch_bounds__(256) void k_pack_flags(const uint8_t* removed, int64_t n,
+                                                    uint32_t* bits) {
+  const int64_t words = (n + 31) / 32;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t v = 0;
+    const int64_t c0 = 32 * k;
+    if (c0 + 32 <= n && (((uintptr_t)(removed + c0)) & 15) == 0) {
+      const uint4* q = (const uint4*)(removed + c0);
+      const uint4 x = q[0], y = q[1];
+      const uint32_t b[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v |= ((b[i] >> (8 * j)) & 0xffu ? 1u : 0u) << (4 * i + j);
+    } else {
+      for (int i = 0; i < 32 && c0 + i < n; ++i) v |= (removed[c0 + i] ? 1u : 0u) << i;
+    }
+    bits[k] = v;
+  }
+}
+
 // Is row r good, given the removed flags of the cells?
 //   controlled : not OUT and no target removed;
 //   nonleaving : some target not removed.
@@ -147,15 +185,15 @@ __global__ void k_check_graph(const int64_t* row_ptr, const int32_t* col, int64_
 // than two per target.
 constexpr int kBatch = 8;
 
-template <int MODE>
+template <int MODE, typename Flags>
 __device__ __forceinline__ bool row_good(const int64_t* row_ptr, const int32_t* col,
-                                         const uint8_t* out, const uint8_t* removed, int64_t r) {
+                                         const uint8_t* out, Flags removed, int64_t r) {
   int64_t a = row_ptr[r];
   const int64_t b = row_ptr[r + 1];
   if (MODE == GIS_ANALYSIS_CONTROLLED && out[r]) return false;
   if (MODE != GIS_ANALYSIS_CONTROLLED) {
     // most rows of a kept cell meet a present cell first: one load decides them
-    if (a < b && removed[col[a]] == 0) return true;
+    if (a < b && !removed[col[a]]) return true;
     ++a;
   }
   for (int64_t e = a; e < b; e += kBatch) {
@@ -166,7 +204,7 @@ __device__ __forceinline__ bool row_good(const int64_t* row_ptr, const int32_t* 
 #pragma unroll
     for (int q = 0; q < kBatch; ++q)
       if (j[q] >= 0) {
-        const bool rm = removed[j[q]] != 0;
+        const bool rm = removed[j[q]];
         any_removed |= rm;
         any_present |= !rm;
       }
@@ -203,7 +241,7 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
     const int64_t c = g0 + t / K;
     bool good = false;
     if (t < cpb * K && c < n_cells && !removed[c])
-      good = row_good<MODE>(row_ptr, col, out, removed, c * K + t % K);
+      good = row_good<MODE>(row_ptr, col, out, ByteFlags{removed}, c * K + t % K);
     ok[t] = good ? 1 : 0;
     __syncthreads();
     if (t < cpb) {
@@ -541,11 +579,11 @@ __global__ __launch_bounds__(256) void k_front_step_nl(const int64_t* rptr, cons
 // flags (rows evaluated against the final set).  Like a sweep, a block takes
 // cpb = floor(256 / K) whole cells: a thread per row evaluates it, then a
 // thread per (cell, mask word) assembles the word.
-template <int MODE>
+template <int MODE, typename Flags>
 __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, const int32_t* col,
                                                      const uint8_t* out, int64_t n_cells,
                                                      int32_t K, int32_t cpb,
-                                                     const uint8_t* removed, uint8_t* kept,
+                                                     Flags removed, uint8_t* kept,
                                                      uint64_t* mask, int32_t W,
                                                      unsigned long long* nkept,
                                                      const int64_t* d_total, int64_t cap_edges,
@@ -637,10 +675,130 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
   if ((t & 63) == 0 && mine) atomicAdd(nkept, mine);
 }
 
+
+// The final pass in two launches (after sweeps, K <= 256): a thread per row
+// evaluates it against the packed removed flags and a ballot per wave stores
+// 64 rows' good flags (rowbits bit r = row r); then a thread per cell takes
+// its kept flag, cuts its mask words out of the row bits, counts it and
+// turns a removed cell into a hole of the covering index.  Rows are not
+// grouped by cell, so no block synchronisation or staging is needed, and
+// each wave keeps kRowsIlp rows' loads in flight: the first target of most
+// rows decides them (non-leaving analysis), so their offsets, first targets
+// and flags are fetched for all of them before any is decided.
+constexpr int kRowsIlp = 4;
+
+template <int MODE, typename Flags>
+__global__ __launch_bounds__(256) void k_row_good(const int64_t* row_ptr, const int32_t* col,
+                                                  const uint8_t* out, int64_t n_rows,
+                                                  Flags removed, uint64_t* rowbits,
+                                                  const int64_t* d_total, int64_t cap_edges,
+                                                  const int32_t* last, int32_t sweeps) {
+  if (d_total && *d_total > cap_edges) return;  // col was not written
+  if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
+  const int lane = threadIdx.x & 63;
+  const int64_t words = (n_rows + 63) / 64;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w0 = wave * kRowsIlp; w0 < words; w0 += waves * kRowsIlp) {
+    int64_t r[kRowsIlp], a[kRowsIlp], b[kRowsIlp];
+    bool good[kRowsIlp], done[kRowsIlp];
+#pragma unroll
+    for (int q = 0; q < kRowsIlp; ++q) {
+      r[q] = (w0 + q) * 64 + lane;
+      const bool in = r[q] < n_rows;
+      a[q] = in ? row_ptr[r[q]] : 0;
+      b[q] = in ? row_ptr[r[q] + 1] : 0;
+      good[q] = false;
+      done[q] = !in;
+    }
+    if (MODE != GIS_ANALYSIS_CONTROLLED) {
+      int32_t j[kRowsIlp];
+#pragma unroll
+      for (int q = 0; q < kRowsIlp; ++q) j[q] = !done[q] && a[q] < b[q] ? col[a[q]] : -1;
+#pragma unroll
+      for (int q = 0; q < kRowsIlp; ++q)
+        if (j[q] >= 0 && !removed[j[q]]) {
+          good[q] = true;
+          done[q] = true;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kRowsIlp; ++q)
+      if (!done[q]) good[q] = row_good<MODE>(row_ptr, col, out, removed, r[q]);
+#pragma unroll
+    for (int q = 0; q < kRowsIlp; ++q) {
+      const uint64_t m = __ballot(good[q]);
+      if (lane == 0 && w0 + q < words) rowbits[w0 + q] = m;
+    }
+  }
+}
+
+template <typename Flags>
+__global__ __launch_bounds__(256) void k_cell_masks(int64_t n_cells, int32_t K, Flags removed,
+                                                    const uint64_t* rowbits, uint8_t* kept,
+                                                    uint64_t* mask, int32_t W,
+                                                    unsigned long long* nkept,
+                                                    const int64_t* d_total, int64_t cap_edges,
+                                                    const int32_t* last, int32_t sweeps,
+                                                    const Job* jobs, int32_t n_jobs,
+                                                    JobStats* stats, const uint8_t* level,
+                                                    const int32_t* idx) {
+  if (d_total && *d_total > cap_edges) return;
+  if (sweeps > 0 && *last >= sweeps) return;
+  const int lane = threadIdx.x & 63;
+  for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
+       c0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    const bool live = c < n_cells;
+    const bool k = live && !removed[c];
+    if (live) {
+      kept[c] = k ? 1 : 0;
+      for (int w = 0; w < W; ++w) {
+        uint64_t m = 0;
+        if (k) {
+          const int64_t s0 = c * K + 64 * w;
+          const int len = K - 64 * w < 64 ? K - 64 * w : 64;
+          const int64_t i = s0 >> 6;
+          const int sh = (int)(s0 & 63);
+          m = rowbits[i] >> sh;
+          if (sh && sh + len > 64) m |= rowbits[i + 1] << (64 - sh);
+          if (len < 64) m &= (1ull << len) - 1;
+        }
+        mask[c * W + w] = m;
+      }
+      // a removed cell becomes a hole of its job's covering index, which the
+      // boundary selection that follows reads
+      if (!k && level) {
+        const CoverIndex& ci = jobs[job_of_cell(jobs, n_jobs, c)].ci;
+        if (!ci.uniform) {
+          const int64_t sl = cell_slot(ci, level, idx, c);
+          if (sl >= 0) ci.state[sl] = ST_HOLE;
+        }
+      }
+    }
+    // kept counts: one atomic per wave when the wave's cells lie in one job
+    const uint64_t bal = __ballot(k);
+    if (lane == 0 && bal) {
+      atomicAdd(nkept, (unsigned long long)__popcll(bal));
+      if (stats) {
+        const int64_t wc = c0 + (threadIdx.x & ~63);
+        const int64_t wl = wc + 63 < n_cells ? wc + 63 : n_cells - 1;
+        const int32_t j0 = job_of_cell(jobs, n_jobs, wc);
+        if (job_of_cell(jobs, n_jobs, wl) == j0) {
+          atomicAdd(&stats[j0].n_kept, (unsigned long long)__popcll(bal));
+        } else {
+          for (uint64_t m = bal; m; m &= m - 1)
+            atomicAdd(&stats[job_of_cell(jobs, n_jobs, wc + __builtin_ctzll(m))].n_kept, 1ull);
+        }
+      }
+    }
+  }
+}
+
 // The same for K > 256 inputs: a thread per cell.
-template <int MODE>
+template <int MODE, typename Flags>
 __global__ void k_prune_final_wide(const int64_t* row_ptr, const int32_t* col, const uint8_t* out,
-                                   int64_t n_cells, int32_t K, const uint8_t* removed,
+                                   int64_t n_cells, int32_t K, Flags removed,
                                    uint8_t* kept, uint64_t* mask, int32_t W,
                                    unsigned long long* nkept, const int64_t* d_total,
                                    int64_t cap_edges, const int32_t* last, int32_t sweeps) {
@@ -762,20 +920,57 @@ int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
                    int32_t W, unsigned long long* d_nkept, int32_t sweeps, const Job* jobs,
                    int32_t n_jobs, JobStats* stats, const uint8_t* level, const int32_t* idx,
                    const void* rowinfo, int32_t frontier, hipStream_t s) {
+  // rows are evaluated against the flags packed 32 to a word when there is
+  // room for them (w.rbits) and no frontier state gives the good rows
+  const bool packed = w.rbits && n_cells <= w.rbits_cells && !rowinfo;
+  if (packed) {
+    hipLaunchKernelGGL(k_pack_flags, dim3(grid_for((n_cells + 31) / 32)), dim3(256), 0, s,
+                       (const uint8_t*)w.removed, n_cells, w.rbits);
+    GIS_LAUNCH_CHECK("k_pack_flags");
+  }
+  const ByteFlags bytes{(const uint8_t*)w.removed};
+  const BitFlags bits{(const uint32_t*)w.rbits};
+  const int64_t n_rows = n_cells * K;
+  if (packed && K <= 256 && w.rowbits && n_rows <= w.rowbits_rows) {
+    const int64_t words = (n_rows + 63) / 64;
+    const int64_t waves = (words + kRowsIlp - 1) / kRowsIlp;
+    const unsigned nb = (unsigned)((waves + 3) / 4 < 8192 ? (waves + 3) / 4 : 8192);
+    hipLaunchKernelGGL((k_row_good<MODE, BitFlags>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
+                       n_rows, bits, w.rowbits, w.d_total, w.cap_edges, (const int32_t*)w.last,
+                       sweeps);
+    GIS_LAUNCH_CHECK("k_row_good");
+    hipLaunchKernelGGL((k_cell_masks<BitFlags>), dim3(grid_for(n_cells)), dim3(256), 0, s, n_cells,
+                       K, bits, (const uint64_t*)w.rowbits, kept, mask, W, d_nkept, w.d_total,
+                       w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats, level,
+                       idx);
+    GIS_LAUNCH_CHECK("k_cell_masks");
+    return GIS_OK;
+  }
   if (K <= 256) {
     const int32_t cpb = 256 / K;
     const int64_t groups = (n_cells + cpb - 1) / cpb;
     const unsigned nb = (unsigned)(groups < 4096 ? (groups > 0 ? groups : 1) : 4096);
-    hipLaunchKernelGGL((k_prune_final<MODE>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
-                       n_cells, K, cpb, (const uint8_t*)w.removed, kept, mask, W, d_nkept,
-                       w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats,
-                       level, idx, rowinfo, frontier);
+    if (packed)
+      hipLaunchKernelGGL((k_prune_final<MODE, BitFlags>), dim3(nb), dim3(256), 0, s, row_ptr, col,
+                         out, n_cells, K, cpb, bits, kept, mask, W, d_nkept, w.d_total,
+                         w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats, level,
+                         idx, rowinfo, frontier);
+    else
+      hipLaunchKernelGGL((k_prune_final<MODE, ByteFlags>), dim3(nb), dim3(256), 0, s, row_ptr,
+                         col, out, n_cells, K, cpb, bytes, kept, mask, W, d_nkept, w.d_total,
+                         w.cap_edges, (const int32_t*)w.last, sweeps, jobs, n_jobs, stats, level,
+                         idx, rowinfo, frontier);
     GIS_LAUNCH_CHECK("k_prune_final");
     return GIS_OK;
   } else {
-    hipLaunchKernelGGL((k_prune_final_wide<MODE>), dim3(grid_for(n_cells)), dim3(256), 0, s,
-                       row_ptr, col, out, n_cells, K, (const uint8_t*)w.removed, kept, mask, W,
-                       d_nkept, w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
+    if (packed)
+      hipLaunchKernelGGL((k_prune_final_wide<MODE, BitFlags>), dim3(grid_for(n_cells)), dim3(256),
+                         0, s, row_ptr, col, out, n_cells, K, bits, kept, mask, W, d_nkept,
+                         w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
+    else
+      hipLaunchKernelGGL((k_prune_final_wide<MODE, ByteFlags>), dim3(grid_for(n_cells)),
+                         dim3(256), 0, s, row_ptr, col, out, n_cells, K, bytes, kept, mask, W,
+                         d_nkept, w.d_total, w.cap_edges, (const int32_t*)w.last, sweeps);
     GIS_LAUNCH_CHECK("k_prune_final_wide");
   }
   // per-job kept counts for the wide variant

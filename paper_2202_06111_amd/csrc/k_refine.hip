@@ -114,7 +114,8 @@ __device__ __forceinline__ void probe_coords(int32_t rule, const int64_t* lo, in
 // over fan launch blocks, so small coverings still fill the device.
 template <int N>
 __global__ __launch_bounds__(256) void k_boundary(BatchArgs b, const uint8_t* kept, int32_t rule,
-                                                  uint8_t* boundary, JobStats* stats, int32_t fan) {
+                                                  uint8_t* boundary, JobStats* stats, int32_t fan,
+                                                  bool flag_next) {
   __shared__ CoverIndex ci;
   __shared__ int64_t s_first[256];  // first probe of each thread's cell in its wave's list
   __shared__ int64_t s_lo[N][256];
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_boundary(BatchArgs b, const uint8_t* ke
     // the next covering: the cell itself, or its 2^n children if it is a
     // boundary cell (jobs that stopped have no flag array)
     const CoverIndex& next = J.next;
-    if (kept[gc] && next.state) {
+    if (flag_next && kept[gc] && next.state) {
       const int L = b.level[gc];
       if (!bnd) {
         int64_t lin = 0;
@@ -199,6 +200,193 @@ __global__ __launch_bounds__(256) void k_boundary(BatchArgs b, const uint8_t* ke
   }
   const uint64_t m = __ballot(bnd);  // one atomic per wave (blocks never straddle jobs)
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_boundary, (unsigned long long)__popcll(m));
+}
+
+// Neighbourhood of the boundary cells (Sec. 3.1.2): the nn kept cells whose
+// centres lie nearest to a boundary cell's centre (Euclidean distance in
+// state units, the cell itself not counted, equal distances ordered by cell
+// id) are selected for subdivision with it.  sel is zero on entry; every
+// boundary cell and each of its neighbours get sel = 1 (plain stores of 1:
+// no race matters).
+//
+// A wave takes one boundary cell at a time and keeps its best nn candidates
+// sorted across its lanes (lane l holds rank l).  Candidates are the kept
+// cells meeting a box of finest-level cells around the cell, enumerated slot
+// by slot in the covering index (every kept cell is the LEAF slot of its own
+// level, so each is met once).  Every cell whose centre lies within distance
+// D of the cell's centre meets the box, D being the distance from the centre
+// to the nearest side of the box that is not a side of X; when the nn-th
+// candidate lies within D the list is final, otherwise the box grows.
+// Distances: centre offsets are integers on the grid of half the finest
+// width, scaled by that width, squared and summed dimension by dimension in
+// FP64 (the same operations in the same order for every pair).
+template <int N>
+__global__ __launch_bounds__(256) void k_neighbours(BatchArgs b, const uint8_t* kept,
+                                                    const uint8_t* boundary, int32_t nn,
+                                                    uint8_t* sel) {
+  __shared__ CoverIndex ci;
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  stage_index(&ci, &J.ci);
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = (blockIdx.x - J.blk[LK_CELLS]) * 256 + (threadIdx.x & ~63);
+  const int64_t mine = c0 + lane;
+  const bool isb = mine < J.n_cells && kept[J.cell_off + mine] && boundary[J.cell_off + mine];
+  uint64_t todo = __ballot(isb);
+  const int lmax = ci.lmax;
+  double hw[N];
+  int64_t Nf[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    hw[d] = ldexp(J.grid.w0[d], -(lmax + 1));
+    Nf[d] = ci.dims[lmax][d];
+  }
+  const double kInf = INFINITY;
+  while (todo) {
+    const int src = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int64_t gb = J.cell_off + c0 + src;
+    const int Lb = b.level[gb];
+    const int sb = lmax - Lb;
+    int64_t ib[N], cb[N];  // index, centre on the half-finest grid
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      ib[d] = b.idx[gb * N + d];
+      cb[d] = (2 * ib[d] + 1) << sb;
+    }
+    if (lane == 0) sel[gb] = 1;
+    double md2 = kInf;    // this lane's rank in the candidate list
+    int64_t mid = -1;
+    for (int64_t r = 1;; r = 2 * r + 1) {
+      md2 = kInf;
+      mid = -1;
+      int64_t lo[N], hi[N];
+      bool all_clipped = true;
+      double dlim = kInf;  // squared distance within which every centre is in the box
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        const int64_t l0 = (ib[d] << sb) - r, h0 = ((ib[d] + 1) << sb) - 1 + r;
+        lo[d] = l0 < 0 ? 0 : l0;
+        hi[d] = h0 > Nf[d] - 1 ? Nf[d] - 1 : h0;
+        if (l0 >= 0) {
+          const double t = (double)(cb[d] - 2 * lo[d]) * hw[d];
+          dlim = t * t < dlim ? t * t : dlim;
+        }
+        if (h0 <= Nf[d] - 1) {
+          const double t = (double)(2 * (hi[d] + 1) - cb[d]) * hw[d];
+          dlim = t * t < dlim ? t * t : dlim;
+        }
+        all_clipped &= l0 < 0 && h0 > Nf[d] - 1;
+      }
+      for (int L = 0; L <= lmax; ++L) {
+        const int s = lmax - L;
+        int64_t blo[N], ext[N], count = 1;
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+          blo[d] = lo[d] >> s;
+          ext[d] = (hi[d] >> s) - blo[d] + 1;
+          count *= ext[d];
+        }
+        for (int64_t k0 = 0; k0 < count; k0 += 64) {
+          const int64_t k = k0 + lane;
+          bool valid = false;
+          double d2 = kInf;
+          int64_t id = -1;
+          if (k < count) {
+            int64_t rem = k, kk[N];
+#pragma unroll
+            for (int d = N - 1; d >= 0; --d) {
+              kk[d] = blo[d] + rem % ext[d];
+              rem /= ext[d];
+            }
+            int64_t lin = 0;
+#pragma unroll
+            for (int d = 0; d < N; ++d) lin = lin * ci.dims[L][d] + kk[d];
+            // a kept cell: a LEAF slot of the index (removed cells are
+            // holes), or, on a full level-0 grid without index arrays, a
+            // cell whose kept flag is set
+            bool leaf;
+            if (ci.uniform) {
+              id = J.cell_off + lin;
+              leaf = kept[id] != 0;
+            } else {
+              const int64_t slot = ci.off[L] + lin;
+              leaf = ci.state[slot] == ST_LEAF;
+              id = J.cell_off + (int64_t)((uint64_t)ci.pfx[slot] & 0xffffffffull) - ci.pbase;
+            }
+            if (leaf) {
+              if (id != gb) {
+                valid = true;
+                d2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < N; ++d) {
+                  const double t = (double)(((2 * kk[d] + 1) << s) - cb[d]) * hw[d];
+                  d2 = d2 + t * t;
+                }
+              }
+            }
+          }
+          // insert the lanes' candidates one by one (wave-uniform loop)
+          for (uint64_t cand = __ballot(valid); cand; cand &= cand - 1) {
+            const int q = __builtin_ctzll(cand);
+            const double cd = __shfl(d2, q, 64);
+            const int64_t cid = __shfl(id, q, 64);
+            const bool less = lane < nn && (md2 < cd || (md2 == cd && mid < cid && mid >= 0));
+            const int pos = __popcll(__ballot(less));
+            if (pos < nn) {
+              const double up_d = __shfl_up(md2, 1, 64);
+              const int64_t up_i = __shfl_up(mid, 1, 64);
+              if (lane > pos && lane < nn) {
+                md2 = up_d;
+                mid = up_i;
+              } else if (lane == pos) {
+                md2 = cd;
+                mid = cid;
+              }
+            }
+          }
+        }
+      }
+      // done when the list is full and its last entry lies within dlim, or
+      // the box already spans the whole grid
+      const double last = __shfl(md2, nn - 1, 64);
+      const int64_t last_id = __shfl(mid, nn - 1, 64);
+      if (all_clipped || (last_id >= 0 && last <= dlim)) break;
+    }
+    if (lane < nn && mid >= 0) sel[mid] = 1;
+  }
+}
+
+// Next-covering flags from the selection: a selected kept cell sets the
+// flags of its 2^n children, any other kept cell its own; stats[j].n_selected
+// counts the selected cells.
+template <int N>
+__global__ __launch_bounds__(256) void k_mark_next(BatchArgs b, const uint8_t* kept,
+                                                   const uint8_t* sel, JobStats* stats) {
+  const int32_t jb = job_of_block(b.jobs, b.n_jobs, LK_CELLS, blockIdx.x);
+  const Job& J = b.jobs[jb];
+  const int64_t c = (blockIdx.x - J.blk[LK_CELLS]) * 256 + threadIdx.x;
+  const int64_t gc = J.cell_off + c;
+  const bool live = c < J.n_cells && kept[gc];
+  const uint64_t m = __ballot(live && sel[gc]);  // one atomic per wave (blocks never straddle jobs)
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(&stats[jb].n_selected, (unsigned long long)__popcll(m));
+  const CoverIndex& next = J.next;
+  if (!live || !next.state) return;
+  const int L = b.level[gc];
+  if (!sel[gc]) {
+    int64_t lin = 0;
+#pragma unroll
+    for (int d = 0; d < N; ++d) lin = lin * next.dims[L][d] + b.idx[gc * N + d];
+    next.state[next.off[L] + lin] = 1;
+    return;
+  }
+  for (int ch = 0; ch < (1 << N); ++ch) {
+    int64_t lin = 0;
+#pragma unroll
+    for (int d = 0; d < N; ++d)
+      lin = lin * next.dims[L + 1][d] + (2 * (int64_t)b.idx[gc * N + d] + ((ch >> (N - 1 - d)) & 1));
+    next.state[next.off[L + 1] + lin] = 1;
+  }
 }
 
 // Standard subdivision (Sec. 2.1): every kept cell of a level-0 covering is
@@ -336,15 +524,33 @@ int32_t batch_count_kept_cells(const Job* jobs, int32_t n_jobs, int64_t n_cells,
   }
 
 int32_t batch_boundary(const BatchArgs& b, const uint8_t* kept, int32_t rule, uint8_t* boundary,
-                       JobStats* stats, hipStream_t s) {
+                       JobStats* stats, hipStream_t s, bool flag_next) {
   if (b.blocks[LK_CELLS] == 0) return GIS_OK;
   // lanes per cell: enough waves for about four per SIMD (1024 SIMDs)
   int32_t fan = 1;
   while (fan < 16 && b.blocks[LK_CELLS] * 4 * fan < 4096) fan *= 2;
-#define GIS_CALL(N) hipLaunchKernelGGL(k_boundary<N>, dim3((unsigned)(b.blocks[LK_CELLS] * fan)), dim3(256), 0, s, b, kept, rule, boundary, stats, fan)
+#define GIS_CALL(N) hipLaunchKernelGGL(k_boundary<N>, dim3((unsigned)(b.blocks[LK_CELLS] * fan)), dim3(256), 0, s, b, kept, rule, boundary, stats, fan, flag_next)
   GIS_DIM_SWITCH(b.n, GIS_CALL)
 #undef GIS_CALL
   GIS_LAUNCH_CHECK("k_boundary");
+  return GIS_OK;
+}
+
+int32_t batch_neighbours(const BatchArgs& b, const uint8_t* kept, const uint8_t* boundary,
+                         int32_t nn, uint8_t* sel, JobStats* stats, hipStream_t s) {
+  if (b.blocks[LK_CELLS] == 0) return GIS_OK;
+  if (nn < 1 || nn > 64) {
+    set_error("neighbourhood size must be 1..64");
+    return GIS_E_UNSUPPORTED;
+  }
+#define GIS_CALL(N) hipLaunchKernelGGL(k_neighbours<N>, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, boundary, nn, sel)
+  GIS_DIM_SWITCH(b.n, GIS_CALL)
+#undef GIS_CALL
+  GIS_LAUNCH_CHECK("k_neighbours");
+#define GIS_CALL(N) hipLaunchKernelGGL(k_mark_next<N>, dim3((unsigned)b.blocks[LK_CELLS]), dim3(256), 0, s, b, kept, sel, stats)
+  GIS_DIM_SWITCH(b.n, GIS_CALL)
+#undef GIS_CALL
+  GIS_LAUNCH_CHECK("k_mark_next");
   return GIS_OK;
 }
 

@@ -45,7 +45,7 @@ class GridT(ctypes.Structure):
 class OptsT(ctypes.Structure):
     _fields_ = [("samples", I32), ("precision", I32), ("boundary_rule", I32), ("analysis", I32),
                 ("fast_out", I32), ("timing", I32), ("subdivision", I32), ("check_band", I32),
-                ("band", F64 * 4)]
+                ("neighbours", I32), ("reserved", I32), ("band", F64 * 4)]
 
 
 class CellsT(ctypes.Structure):
@@ -77,7 +77,8 @@ class RoundStatsT(ctypes.Structure):
                 ("n_kept", I64), ("n_boundary", I64), ("n_recheck", I64), ("max_level", I32),
                 ("reserved", I32), ("ms_build", F64), ("ms_prune", F64), ("ms_subdivide", F64),
                 ("ms_image", F64), ("ms_recheck", F64), ("ms_host", F64), ("ms_host_wait", F64),
-                ("band", F64 * 4), ("max_err", F64 * 4), ("max_err_all", F64 * 4)]
+                ("band", F64 * 4), ("max_err", F64 * 4), ("max_err_all", F64 * 4),
+                ("n_selected", I64)]
 
 
 class SolveInfoT(ctypes.Structure):
@@ -110,7 +111,7 @@ def lib():
             "gis_autotune": ([P, P, P, P, I32, I32, P, I32, P, P, P], I32),
             "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
-            "gis_subdivide": ([P, P, P, P, I32, P, P, P], I32),
+            "gis_subdivide": ([P, P, P, P, I32, I32, P, P, P], I32),
             "gis_bisect": ([P, P, P, P, I32, P, P, P], I32),
             "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
             "gis_solve_batch": ([P, I32, P, I32, I32, P, P, P], I32),
@@ -173,7 +174,8 @@ def grid_t(grid: W.Grid) -> GridT:
 def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: str = W.SHELL,
            analysis: str = "controlled", fast_out: bool = False,
            band: Optional[Sequence[float]] = None, timing: int = 0,
-           subdivision: str = "boundary", check_band: bool = False) -> OptsT:
+           subdivision: str = "boundary", check_band: bool = False,
+           neighbours: int = 0) -> OptsT:
     o = OptsT()
     o.samples = SAMPLES[samples]
     o.precision = PRECISION[precision]
@@ -183,6 +185,7 @@ def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: st
     o.timing = int(timing)
     o.subdivision = SUBDIVISION[subdivision]
     o.check_band = int(bool(check_band))
+    o.neighbours = int(neighbours)
     for d, v in enumerate([] if band is None else list(band)):
         o.band[d] = float(v)
     return o
@@ -190,7 +193,7 @@ def opts_t(samples: str = W.LATTICE3, precision: str = "fp64", boundary_rule: st
 
 def workload_opts(wl: W.Workload, **over) -> OptsT:
     kw = dict(samples=wl.samples, precision=wl.precision, boundary_rule=wl.boundary_rule,
-              analysis=wl.analysis, subdivision=wl.subdivision)
+              analysis=wl.analysis, subdivision=wl.subdivision, neighbours=wl.nn)
     kw.update(over)
     return opts_t(**kw)
 
@@ -332,8 +335,9 @@ def prune(ctx: Context, graph: Graph, n_cells: int, K: int, analysis: str = "con
 
 
 def subdivide(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor,
-              kept: torch.Tensor, rule: str = W.SHELL, stream=None):
-    """Boundary selection and subdivision; returns (level, idx, boundary flags)."""
+              kept: torch.Tensor, rule: str = W.SHELL, stream=None, neighbours: int = 0):
+    """Boundary selection (with the `neighbours` nearest kept cells of each
+    boundary cell) and subdivision; returns (level, idx, boundary flags)."""
     n_cells = int(level.shape[0])
     cap = max(1, int(kept.sum().item()) << grid.n) if n_cells else 1
     lv = torch.empty(cap, dtype=torch.uint8, device=ctx.dev)
@@ -343,7 +347,8 @@ def subdivide(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor
     cout = cells_t(lv, ix, cap)
     gt = grid_t(grid)
     _check(lib().gis_subdivide(ctx.handle, ctypes.byref(gt), ctypes.byref(cin), _ptr(kept),
-                               RULE[rule], _ptr(bnd), ctypes.byref(cout), _stream_ptr(stream)))
+                               RULE[rule], int(neighbours), _ptr(bnd), ctypes.byref(cout),
+                               _stream_ptr(stream)))
     n = int(cout.n_cells)
     return lv[:n], ix[:n], bnd[:n_cells]
 

@@ -77,6 +77,9 @@ class Workload:
     # cells, Sec. 3.1) or "bisect" (every kept cell halved across a cycled
     # dimension, the standard algorithm of Sec. 2.1)
     subdivision: str = "boundary"
+    # neighbourhood size N of Sec. 3.1.2: the N kept cells nearest to each
+    # boundary cell are subdivided with it (0: boundary cells only)
+    nn: int = 0
 
     @property
     def K(self) -> int:

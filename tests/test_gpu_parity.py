@@ -6,6 +6,7 @@ relative (|a - b| <= 1e-10 max(|a|, |b|, hi_d - lo_d)) -- the canonical
 operation order is expected to give 0 ulp, which is asserted separately.
 The FP32-with-FP64-recheck path must give the very same graph as FP64.
 """
+import dataclasses
 import numpy as np
 import pytest
 import torch
@@ -486,10 +487,75 @@ def test_worked_example_5x5_on_gpu(G, ctx):
         assert sorted((np.nonzero(_np(bnd))[0] + 1).tolist()) == want
 
 
+@pytest.mark.parametrize("nn", [1, 3, 7, 20, 64])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1"])
+def test_subdivide_neighbours_matches_oracle(G, ctx, name, nn):
+    """The neighbourhood selection (Sec. 3.1.2) on random mixed-level
+    coverings with removed cells: the cells split (boundary cells and the nn
+    kept cells nearest to each) and the new covering equal the oracle's."""
+    system, grid, u, samples = SMALL[name]
+    rng = np.random.Generator(np.random.PCG64(17 + nn))
+    level, idx = _adaptive_cells(rng, grid.n0, splits=5, drop_frac=0.0)
+    kept = (rng.random(level.shape[0]) < 0.97).astype(np.uint8)
+    bnd_w = oracle.boundary(grid, level, idx, kept, "shell")
+    sel_w = oracle.neighbours(grid, level, idx, kept, bnd_w, nn)
+    assert sel_w.sum() > bnd_w.sum() or sel_w.sum() == kept.sum()
+    lv_w, ix_w = oracle.subdivide(grid, level, idx, kept, sel_w)
+    dl, di = _cells(ctx, level, idx)
+    lv, ix, bnd = G.subdivide(ctx, grid, dl, di, torch.as_tensor(kept, device=ctx.dev), "shell",
+                              neighbours=nn)
+    np.testing.assert_array_equal(_np(bnd), bnd_w)
+    np.testing.assert_array_equal(_np(lv), lv_w)
+    np.testing.assert_array_equal(_np(ix), ix_w)
+
+
+def test_neighbours_worked_example_on_gpu(G, ctx):
+    """Figure 5 of Sec. 3.1.2 on the device: on the 5x5 grid of square cells
+    (B25 removed), the nearest 3 (7) kept cells of the corner cell B1 -- which
+    the boundary selection marks -- are among the cells split."""
+    grid = W.Grid((5, 5), (0.0, 0.0), (5.0, 5.0))
+    level, idx = oracle.coarse_cells(grid)
+    kept = np.ones(25, np.uint8)
+    kept[24] = 0
+    dl, di = _cells(ctx, level, idx)
+    for nn, near in ((3, [2, 6, 7]), (7, [2, 3, 6, 7, 8, 11, 12])):
+        bnd_w = oracle.boundary(grid, level, idx, kept, "shell")
+        sel_w = oracle.neighbours(grid, level, idx, kept, bnd_w, nn)
+        lv_w, ix_w = oracle.subdivide(grid, level, idx, kept, sel_w)
+        lv, ix, bnd = G.subdivide(ctx, grid, dl, di, torch.as_tensor(kept, device=ctx.dev),
+                                  "shell", neighbours=nn)
+        np.testing.assert_array_equal(_np(lv), lv_w)
+        np.testing.assert_array_equal(_np(ix), ix_w)
+        split = {int(k) for k in np.nonzero(sel_w)[0] + 1}
+        assert set(near) <= split
+
+
+@pytest.mark.parametrize("nn", [3, 7])
+def test_solve_adaptive_with_neighbourhood(G, ctx, nn):
+    """The adaptive Van der Pol workload (32x32, 5 rounds) with the
+    neighbourhood of Sec. 3.1.2: every round equals the oracle, and the
+    selection counts per round are the oracle's."""
+    wl = dataclasses.replace(W.vdp_adaptive_32("fp64"), nn=nn)
+    sol, want, info = _check_solve(G, ctx, wl, "fp64")
+    for got_r, want_r in zip(info["rounds"], want["stats"]):
+        if "n_selected" in want_r:
+            assert got_r["n_boundary"] == want_r["n_boundary"]
+            assert got_r["n_selected"] == want_r["n_selected"]
+    sol.free()
+
+
+def test_neighbours_rejected_with_bisection(G, ctx):
+    wl = dataclasses.replace(W.vdp_standard_32("fp64"), nn=3)
+    with pytest.raises(G.GisError):
+        G.solve_workload(ctx, wl)
+    with pytest.raises(G.GisError):
+        G.solve_workload(ctx, dataclasses.replace(W.vdp_adaptive_32("fp64"), nn=65))
+
+
 # ------------------------------------------------------------------ solve + queries
 def _oracle_solve(wl, **kw):
     return oracle.solve(wl.system, wl.grid, wl.samples, wl.u, wl.rounds, rule=wl.boundary_rule,
-                        analysis=wl.analysis, **kw)
+                        analysis=wl.analysis, nn=wl.nn, **kw)
 
 
 def _check_solve(G, ctx, wl, precision=None):
