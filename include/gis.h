@@ -262,6 +262,18 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
                   int32_t analysis, uint8_t* d_kept, uint64_t* d_mask, int64_t* n_kept,
                   void* stream);
 
+/* gis_prune for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kept flags, masks and count as gis_prune, computed by sweeps only in a
+ * static device workspace of about 42 MB per GPU, held until the process
+ * ends; no context.  It runs on the current device, which must be the device
+ * of `stream` and of the buffers.  Analysis GIS_ANALYSIS_CONTROLLED or
+ * GIS_ANALYSIS_NONLEAVING (GIS_E_INVAL otherwise), K <= 256 (GIS_E_INVAL),
+ * n_cells <= 2^21 (GIS_E_CAPACITY beyond).  Calls no hipMalloc/hipFree.
+ * Every call on a GPU shares its workspace: calls that overlap in time on
+ * one GPU race and must not be made.  Synchronises. */
+int32_t gis_prune_static(const gis_graph* graph, int64_t n_cells, int32_t K, int32_t analysis,
+                         uint8_t* d_kept, uint64_t* d_mask, int64_t* n_kept, void* stream);
 
 /* Boundary selection and subdivision (Sec. 3.1.1), with the neighbourhood of
  * the boundary cells (Sec. 3.1.2) when neighbours > 0 (0..64, GIS_E_INVAL

@@ -111,6 +111,7 @@ def lib():
             "gis_autotune": ([P, P, P, P, I32, I32, P, I32, P, P, P], I32),
             "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
+            "gis_prune_static": ([P, I64, I32, I32, P, P, P, P], I32),
             "gis_subdivide": ([P, P, P, P, I32, I32, P, P, P], I32),
             "gis_bisect": ([P, P, P, P, I32, P, P, P], I32),
             "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
@@ -133,7 +134,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_subdivide", "gis_bisect",
+EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_prune_static", "gis_subdivide", "gis_bisect",
             "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
             "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
             "gis_last_error", "gis_version")
@@ -331,6 +332,25 @@ def prune(ctx: Context, graph: Graph, n_cells: int, K: int, analysis: str = "con
     g = graph.graph_t()
     _check(lib().gis_prune(ctx.handle, ctypes.byref(g), n_cells, K, ANALYSIS[analysis], _ptr(kept),
                            _ptr(mask), ctypes.byref(nk), _stream_ptr(stream)))
+    return kept[:n_cells], mask[:n_cells], int(nk.value)
+
+
+def prune_static(graph: Graph, n_cells: int, K: int, analysis: str = "controlled", stream=None,
+                 kept: Optional[torch.Tensor] = None, mask: Optional[torch.Tensor] = None):
+    """gis_prune_static: the analysis without device allocation in the
+    library (its workspace is a static device array).  kept [n_cells] uint8
+    and mask [n_cells, ceil(K/64)] int64 may be passed in, so that the call
+    allocates nothing at all; returns (kept, mask, n_kept)."""
+    Wd = (K + 63) // 64
+    dev = graph.row_ptr.device
+    if kept is None:
+        kept = torch.empty(max(n_cells, 1), dtype=torch.uint8, device=dev)
+    if mask is None:
+        mask = torch.empty((max(n_cells, 1), Wd), dtype=torch.int64, device=dev)
+    nk = I64(0)
+    g = graph.graph_t()
+    _check(lib().gis_prune_static(ctypes.byref(g), n_cells, K, ANALYSIS[analysis], _ptr(kept),
+                                  _ptr(mask), ctypes.byref(nk), _stream_ptr(stream)))
     return kept[:n_cells], mask[:n_cells], int(nk.value)
 
 
