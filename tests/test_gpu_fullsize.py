@@ -14,9 +14,10 @@ generators):
 
 Digests are SHA-256 of the arrays' little-endian bytes, the layout of the C
 ABI (row_ptr i64, col i32, out u8, level u8, idx i32 cell-major, kept u8,
-mask u64 words).  Where a digest is absent (the oracle's round-2 graph of the
-coupled system takes an hour to produce), sampled rows are checked against
-rows the oracle computes one by one.
+mask u64 words).  Every round of the coupled solve has its digests (the
+oracle's round-2 graph, 1.56e9 rows and 1.2e10 edges, takes an hour on 8
+cores); where a round's graph digest is absent, sampled rows are checked
+against rows the oracle computes one by one.
 """
 import hashlib
 import json
