@@ -8,7 +8,12 @@ Liu, arXiv 2202.06111).  It shares no code with the HIP library.
 
 Parity status per function (what pins each one is in tests/test_oracle_*.py):
   step / images   pinned: RK4 closed form on linear fields, scipy integration
-                  of the stated ODEs, 4th-order error ratio
+                  of the stated ODEs, 4th-order error ratio; the CSTR field
+                  (Sec. 4.1, Eq. 4) also by the RK4 stability polynomial on
+                  its linear and isothermal special cases, its energy-balance
+                  invariant and its textbook steady state
+  exp             pinned: the C library's exp within 1 ulp, exact powers of
+                  two, overflow, underflow and NaN
   cover           pinned: exact rational brute force on dyadic grids
   build           pinned: identity-map stencil, brute-force box/cell overlap
   prune           pinned: brute-force subset enumeration, drift/contraction
@@ -42,7 +47,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gis_oracle.c")
 _LIB = os.path.join(_HERE, "libgis_oracle.so")
 
-_KINDS = {"linear": 0, "vdp": 1, "lorenz": 2, "vdp2": 3}
+_KINDS = {"linear": 0, "vdp": 1, "lorenz": 2, "vdp2": 3, "cstr": 4}
 _SCHEMES = {"lattice3": 1, "corners_center": 2}
 _RULES = {"shell": 1, "corners": 2}
 
@@ -78,6 +83,7 @@ def _load():
         P = ctypes.c_void_p
         I32, I64 = ctypes.c_int32, ctypes.c_int64
         lib.or_step.argtypes = [P, P, P, P]
+        lib.or_exp_vec.argtypes = [P, I64, P]
         lib.or_num_samples.argtypes = [I32, I32]
         lib.or_num_samples.restype = I32
         lib.or_images.argtypes = [P, P, I32, P, P, I64, P, I32, P]
@@ -145,6 +151,15 @@ def step(system, x: np.ndarray, u: np.ndarray) -> np.ndarray:
     u = _c(u, np.float64)
     y = np.zeros(system.n)
     lib.or_step(ctypes.byref(s), _ptr(x), _ptr(u), _ptr(y))
+    return y
+
+
+def exp(x: np.ndarray) -> np.ndarray:
+    """The oracle's own exponential (Cody-Waite reduction + degree-13 Taylor
+    polynomial), used by the CSTR field of Sec. 4.1."""
+    x = _c(np.atleast_1d(x), np.float64)
+    y = np.zeros_like(x)
+    _load().or_exp_vec(_ptr(x), x.size, _ptr(y))
     return y
 
 

@@ -47,7 +47,7 @@
 #include <string.h>
 
 /* ---- system kinds and sample schemes (the oracle's own numbering) ---- */
-enum { OR_LINEAR = 0, OR_VDP = 1, OR_LORENZ = 2, OR_VDP2 = 3 };
+enum { OR_LINEAR = 0, OR_VDP = 1, OR_LORENZ = 2, OR_VDP2 = 3, OR_CSTR = 4 };
 enum { OR_LATTICE3 = 1, OR_CORNERS_CENTER = 2 };
 enum { OR_SHELL = 1, OR_CORNERS = 2 };
 
@@ -62,6 +62,41 @@ typedef struct {
   int32_t n0[4];
   double lo[4], hi[4];
 } or_grid;
+
+/* ------------------------------------------------------------------ */
+/* exp(x) for the Arrhenius factor of the CSTR model (Sec. 4.1).        */
+/* ------------------------------------------------------------------ */
+/* The C library's exp is not the same function on every platform, so the
+ * oracle fixes its own: Cody-Waite reduction x = k ln2 + r with k the
+ * nearest integer to x / ln2 (ties to even) and ln2 split into its double
+ * rounding plus the remainder, |r| <= ln2 / 2; exp(r) by the Taylor
+ * polynomial of degree 13 (the first omitted term is below 5e-18 there),
+ * evaluated by Horner's rule with fused multiply-adds from the highest
+ * coefficient; then the exact scaling by 2^k.  Within 1 ulp of exp. */
+static const double EXP_INV_LN2 = 0x1.71547652b82fep+0;
+static const double EXP_LN2_HI = 0x1.62e42fefa39efp-1;
+static const double EXP_LN2_LO = 0x1.abc9e3b39803fp-56;
+static const double EXP_TAYLOR[14] = {  /* 1/j!, rounded to nearest */
+    0x1.0000000000000p+0, 0x1.0000000000000p+0, 0x1.0000000000000p-1, 0x1.5555555555555p-3,
+    0x1.5555555555555p-5, 0x1.1111111111111p-7, 0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13,
+    0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26,
+    0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+
+double or_exp(double x) {
+  if (x != x) return x;              /* NaN */
+  if (x > 709.79) return HUGE_VAL;   /* beyond the largest double */
+  if (x < -745.2) return 0.0;        /* below half the smallest subnormal */
+  const double k = rint(x * EXP_INV_LN2);
+  double r = fma(-k, EXP_LN2_HI, x);
+  r = fma(-k, EXP_LN2_LO, r);
+  double p = EXP_TAYLOR[13];
+  for (int j = 12; j >= 0; --j) p = fma(p, r, EXP_TAYLOR[j]);
+  return ldexp(p, (int)k);
+}
+
+void or_exp_vec(const double* x, int64_t n, double* y) {
+  for (int64_t i = 0; i < n; ++i) y[i] = or_exp(x[i]);
+}
 
 /* ------------------------------------------------------------------ */
 /* Vector field f of the ODE whose RK4 discretisation is Eq. (1).      */
@@ -103,6 +138,18 @@ static void field(const or_system* s, const double* x, const double* u, double* 
       dx[1] = fma(fma(-x[0], x[0], 1.0), x[1], fma(c, x[2] - x[0], u[0] - x[0]));
       dx[2] = x[3];
       dx[3] = fma(fma(-x[2], x[2], 1.0), x[3], fma(c, x[0] - x[2], u[1] - x[2]));
+      break;
+    }
+    case OR_CSTR: {
+      /* Eq. (4), state (cA, T), input Tc:
+       *   cA' = q/V (cAf - cA) - k0 exp(-(E/R) / T) cA
+       *   T'  = q/V (Tf - T) + (-dH / (rho cp)) k0 exp(-(E/R) / T) cA
+       *         + UA / (V rho cp) (Tc - T)
+       * p = (q/V, cAf, Tf, E/R, k0, -dH/(rho cp), UA/(V rho cp)). */
+      const double e = or_exp(-(p[3] / x[1]));
+      const double rate = (p[4] * e) * x[0];
+      dx[0] = fma(p[0], p[1] - x[0], -rate);
+      dx[1] = fma(p[0], p[2] - x[1], fma(p[5], rate, p[6] * (u[0] - x[1])));
       break;
     }
     default:
