@@ -81,7 +81,8 @@ typedef enum {
   GIS_E_INTERNAL = 6      /* a device-side consistency check failed */
 } gis_status;
 
-enum { GIS_SYS_LINEAR = 0, GIS_SYS_VDP = 1, GIS_SYS_LORENZ = 2, GIS_SYS_VDP2 = 3 };
+enum { GIS_SYS_LINEAR = 0, GIS_SYS_VDP = 1, GIS_SYS_LORENZ = 2, GIS_SYS_VDP2 = 3,
+       GIS_SYS_CSTR = 4 };
 enum { GIS_SAMPLES_LATTICE3 = 1, GIS_SAMPLES_CORNERS_CENTER = 2 };
 enum { GIS_PREC_FP64 = 1, GIS_PREC_FP32_RECHECK = 2 };
 enum { GIS_BOUNDARY_SHELL = 1, GIS_BOUNDARY_CORNERS = 2 };
@@ -94,7 +95,15 @@ enum { GIS_SUBDIVIDE_BOUNDARY = 0, GIS_SUBDIVIDE_BISECT = 1 };
  *  LORENZ (n = 3, m = 1):   g = (s (x2 - x1), x1 (r - x3) - x2 + u, x1 x2 - b x3),
  *                           s, r, b = params[0..2]
  *  VDP2   (n = 4, m = 2):   state (x1, v1, x2, v2),
- *                           vi' = (1 - xi^2) vi - xi + c (xj - xi) + ui, c = params[0] */
+ *                           vi' = (1 - xi^2) vi - xi + c (xj - xi) + ui, c = params[0]
+ *  CSTR   (n = 2, m = 1):   the reactor of Sec. 4.1 (Eq. 4), state (cA, T), input Tc,
+ *                           r = k0 exp(-(E/R) / T) cA,
+ *                           g = (q/V (cAf - cA) - r,
+ *                                q/V (Tf - T) + (-dH)/(rho cp) r + UA/(V rho cp) (Tc - T)),
+ *                           params[0..6] = q/V, cAf, Tf, E/R, k0, -dH/(rho cp), UA/(V rho cp);
+ *                           exp is the library's own (Cody-Waite reduction, degree-13
+ *                           Taylor polynomial, exact 2^k scaling; within 1 ulp), so FP64
+ *                           images are reproducible bit for bit */
 typedef struct gis_system {
   int32_t kind, n, m, nsub;
   double dt;
@@ -347,6 +356,13 @@ int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, co
 int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
                            const double* d_u, int32_t K, const gis_cells* cells, int32_t samples,
                            double safety, double floor_rel, double* band_out, void* stream);
+
+/* The library's FP64 exponential, the one in the CSTR field (Sec. 4.1,
+ * Eq. 4), applied elementwise for parity checks: d_y[i] = exp(d_x[i]),
+ * d_x and d_y device arrays of n doubles (they may be the same array), on
+ * the current device.  Overflow gives +inf, underflow 0 (through the
+ * subnormals), NaN stays NaN.  Synchronises. */
+int32_t gis_exp(const double* d_x, int64_t n, double* d_y, void* stream);
 
 const char* gis_last_error(void);
 const char* gis_version(void);

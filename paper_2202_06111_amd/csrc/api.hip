@@ -195,6 +195,7 @@ int32_t check_system(const gis_system* s) {
     case GIS_SYS_VDP: if (s->n != 2 || s->m != 1) return inval("VDP needs n=2, m=1"); break;
     case GIS_SYS_LORENZ: if (s->n != 3 || s->m != 1) return inval("LORENZ needs n=3, m=1"); break;
     case GIS_SYS_VDP2: if (s->n != 4 || s->m != 2) return inval("VDP2 needs n=4, m=2"); break;
+    case GIS_SYS_CSTR: if (s->n != 2 || s->m != 1) return inval("CSTR needs n=2, m=1"); break;
     default: return inval("unknown system kind");
   }
   return GIS_OK;
@@ -2078,6 +2079,16 @@ int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, co
   BuildArgs a = build_args(ctx, B, cells->level, cells->idx, &o);
   if ((rc = launch_images(a, precision, d_images, s))) return rc;
   GIS_HIP(hipStreamSynchronize(s));  // the staged job table is consumed
+  return GIS_OK;
+}
+
+int32_t gis_exp(const double* d_x, int64_t n, double* d_y, void* stream) {
+  if (n < 0) return inval("n must be >= 0");
+  if (n > 0 && (!d_x || !d_y)) return inval("d_x and d_y are required");
+  hipStream_t s = as_stream(stream);
+  int32_t rc;
+  if ((rc = launch_exp(d_x, n, d_y, s))) return rc;
+  GIS_HIP(hipStreamSynchronize(s));
   return GIS_OK;
 }
 

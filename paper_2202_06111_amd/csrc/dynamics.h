@@ -45,6 +45,62 @@ __device__ __forceinline__ float vmax(float a, float b) {
   return r;
 }
 
+// exp(x) for the Arrhenius factor of the CSTR field (Sec. 4.1).  The device
+// library's exp is not bound to any particular rounding, so the library fixes
+// its own: Cody-Waite reduction x = k ln2 + r with k = rint(x / ln2) (ties to
+// even) and ln2 split into its rounding plus the remainder, |r| <= ln2 / 2;
+// exp(r) by its Taylor polynomial of degree 13 (the first omitted term is
+// below 5e-18 there) in Horner form with fused multiply-adds from the highest
+// coefficient; then the exact scaling by 2^k.  Every step is one correctly
+// rounded IEEE operation, so the FP64 result does not depend on the machine;
+// it is within 1 ulp of exp.  The FP32 instantiation runs the same sequence
+// with binary32 constants (ln2 split at binary32) and binary32 limits.
+template <typename R>
+struct ExpConsts;
+template <>
+struct ExpConsts<double> {
+  static constexpr double inv_ln2 = 0x1.71547652b82fep+0;
+  static constexpr double ln2_hi = 0x1.62e42fefa39efp-1;
+  static constexpr double ln2_lo = 0x1.abc9e3b39803fp-56;
+  static constexpr double over = 709.79;   // beyond the largest finite value
+  static constexpr double under = -745.2;  // below half the smallest subnormal
+};
+template <>
+struct ExpConsts<float> {
+  static constexpr float inv_ln2 = 0x1.715476p+0f;
+  static constexpr float ln2_hi = 0x1.62e430p-1f;
+  static constexpr float ln2_lo = -0x1.05c610p-29f;
+  static constexpr float over = 88.73f;
+  static constexpr float under = -103.98f;
+};
+
+// 1/j!, j = 0..13, rounded to nearest binary64.
+__device__ constexpr double kExpTaylor[14] = {
+    0x1.0000000000000p+0, 0x1.0000000000000p+0, 0x1.0000000000000p-1, 0x1.5555555555555p-3,
+    0x1.5555555555555p-5, 0x1.1111111111111p-7, 0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13,
+    0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26,
+    0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+
+__device__ __forceinline__ double rintT(double v) { return __builtin_rint(v); }
+__device__ __forceinline__ float rintT(float v) { return __builtin_rintf(v); }
+__device__ __forceinline__ double ldexpT(double v, int e) { return __builtin_ldexp(v, e); }
+__device__ __forceinline__ float ldexpT(float v, int e) { return __builtin_ldexpf(v, e); }
+
+template <typename R>
+__device__ __forceinline__ R expT(R x) {
+  using C = ExpConsts<R>;
+  if (x != x) return x;
+  if (x > C::over) return R(__builtin_huge_val());
+  if (x < C::under) return R(0);
+  const R k = rintT(x * C::inv_ln2);
+  R r = fmaT(-k, C::ln2_hi, x);
+  r = fmaT(-k, C::ln2_lo, r);
+  R p = R(kExpTaylor[13]);
+#pragma unroll
+  for (int j = 12; j >= 0; --j) p = fmaT(p, r, R(kExpTaylor[j]));
+  return ldexpT(p, (int)k);
+}
+
 // Vector field g(x, u) of x' = g(x, u).  N is the state dimension; m (inputs)
 // is only a runtime value for the linear field.
 template <int KIND, int N, typename R>
@@ -65,6 +121,14 @@ __device__ __forceinline__ void field(const R* __restrict__ p, int m, const R* x
     dx[0] = p[0] * (x[1] - x[0]);
     dx[1] = fmaT(x[0], p[1] - x[2], u[0] - x[1]);
     dx[2] = fmaT(x[0], x[1], -(p[2] * x[2]));
+  } else if constexpr (KIND == GIS_SYS_CSTR) {
+    // Eq. (4), state (cA, T), input Tc; p = (q/V, cAf, Tf, E/R, k0,
+    // -dH/(rho cp), UA/(V rho cp)); the reaction rate k0 exp(-(E/R)/T) cA
+    // enters both equations.
+    const R e = expT<R>(-(p[3] / x[1]));
+    const R rate = (p[4] * e) * x[0];
+    dx[0] = fmaT(p[0], p[1] - x[0], -rate);
+    dx[1] = fmaT(p[0], p[2] - x[1], fmaT(p[5], rate, p[6] * (u[0] - x[1])));
   } else {  // GIS_SYS_VDP2, state (x1, v1, x2, v2)
     dx[0] = x[1];
     dx[1] = fmaT(fmaT(-x[0], x[0], R(1)), x[1], fmaT(p[0], x[2] - x[0], u[0] - x[0]));

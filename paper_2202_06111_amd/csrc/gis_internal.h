@@ -249,6 +249,8 @@ struct BuildArgs {
 // written only if the edge total fits in cap_edges.
 int32_t launch_build(const BuildArgs& a, int32_t precision, hipStream_t s);
 int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s);
+// The library's FP64 exponential (the CSTR field's), elementwise.
+int32_t launch_exp(const double* d_x, int64_t n, double* d_y, hipStream_t s);
 // max |y32 - y64| per job and dimension over the rows of every stride-th
 // launch block of each job (all rows when stride <= 1).
 int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64_t stride,

@@ -302,7 +302,7 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ran
 // list) as global ids into dst[0 .. p1-p0).
 template <int N, bool UNI>
 __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t* lo,
-                                             const int32_t* hi, int32_t count,
+                                             const int32_t* hi, int32_t /*count*/,
                                              const int2* cache, int32_t id0, int32_t p0,
                                              int32_t p1, int32_t* dst) {
   if (UNI || ci.uniform) {
@@ -643,6 +643,9 @@ int32_t dispatch_sys(int kind, int n, Args&&... args) {
     case GIS_SYS_VDP2:
       if (n == 4) return Launcher<GIS_SYS_VDP2, 4>::run(args...);
       break;
+    case GIS_SYS_CSTR:
+      if (n == 2) return Launcher<GIS_SYS_CSTR, 2>::run(args...);
+      break;
     case GIS_SYS_LINEAR:
       if (n == 1) return Launcher<GIS_SYS_LINEAR, 1>::run(args...);
       if (n == 2) return Launcher<GIS_SYS_LINEAR, 2>::run(args...);
@@ -701,6 +704,22 @@ int32_t launch_build(const BuildArgs& a, int32_t precision, hipStream_t s) {
 
 int32_t launch_images(const BuildArgs& a, int32_t precision, double* d_images, hipStream_t s) {
   return dispatch_sys<Images>(a.kind, a.n, a, precision, d_images, s);
+}
+
+namespace {
+__global__ void k_exp(const double* __restrict__ x, int64_t n, double* __restrict__ y) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+    y[i] = expT<double>(x[i]);
+}
+}  // namespace
+
+int32_t launch_exp(const double* d_x, int64_t n, double* d_y, hipStream_t s) {
+  if (n <= 0) return GIS_OK;
+  const int64_t blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_exp, dim3((unsigned)blocks), dim3(256), 0, s, d_x, n, d_y);
+  GIS_LAUNCH_CHECK("k_exp");
+  return GIS_OK;
 }
 
 int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64_t stride,

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_cells_fill(const int64_t* row_ptr, cons
     if (over) {  // one entry per present edge
       live = 0;
       hit_removed = false;
-      for_targets(row_ptr, col, removed, any_removed, b, [&](int32_t j, bool rm) {
+      for_targets(row_ptr, col, removed, any_removed, b, [&](int32_t, bool rm) {
         if (rm) hit_removed = true;
         else ++live;
         return true;

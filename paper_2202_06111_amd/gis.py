@@ -19,7 +19,7 @@ from . import workloads as W
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgis.so")
 
-KIND = {W.LINEAR: 0, W.VDP: 1, W.LORENZ: 2, W.VDP2: 3}
+KIND = {W.LINEAR: 0, W.VDP: 1, W.LORENZ: 2, W.VDP2: 3, W.CSTR: 4}
 SAMPLES = {W.LATTICE3: 1, W.CORNERS_CENTER: 2}
 PRECISION = {"fp64": 1, "fp32_recheck": 2}
 RULE = {W.SHELL: 1, W.CORNERS: 2}
@@ -112,6 +112,7 @@ def lib():
             "gis_build_graph": ([P, P, P, P, I32, P, P, P, P], I32),
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
             "gis_prune_static": ([P, I64, I32, I32, P, P, P, P], I32),
+            "gis_exp": ([P, I64, P, P], I32),
             "gis_subdivide": ([P, P, P, P, I32, I32, P, P, P], I32),
             "gis_bisect": ([P, P, P, P, I32, P, P, P], I32),
             "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
@@ -136,7 +137,7 @@ def lib():
 
 EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_prune_static", "gis_subdivide", "gis_bisect",
             "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
-            "gis_query_membership", "gis_query_admissible", "gis_images", "gis_calibrate_band",
+            "gis_query_membership", "gis_query_admissible", "gis_images", "gis_exp", "gis_calibrate_band",
             "gis_last_error", "gis_version")
 
 
@@ -388,6 +389,16 @@ def bisect(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor,
                             ctypes.byref(go), ctypes.byref(cout), _stream_ptr(stream)))
     n = int(cout.n_cells)
     return W.Grid(tuple(go.n0[: grid.n]), grid.lo, grid.hi), lv[:n], ix[:n]
+
+
+def exp(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """gis_exp: the library's FP64 exponential (the CSTR field's) on a
+    device float64 tensor, elementwise."""
+    x = x.contiguous()
+    assert x.dtype == torch.float64 and x.is_cuda
+    y = torch.empty_like(x)
+    _check(lib().gis_exp(_ptr(x), x.numel(), _ptr(y), _stream_ptr(stream)))
+    return y
 
 
 def images(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, samples: str,

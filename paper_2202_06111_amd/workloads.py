@@ -6,9 +6,10 @@ x+ = f(x, u) with compact state set X and input set U) and draws the
 synthetic inputs that both the HIP library and the CPU oracle consume, so the
 two sides always see bit-identical arrays.
 
-The five named workloads are the controlled Van der Pol, Lorenz-type and
-coupled Van der Pol problems used to exercise the graph-construction path;
-the paper's own CSTR example (Sec. 4.1) is not among them.
+The named workloads are the controlled Van der Pol, Lorenz-type and coupled
+Van der Pol problems used to exercise the graph-construction path, and the
+paper's own example, the continuously stirred tank reactor of Sec. 4.1
+(Eq. 4, Table 2).
 """
 from __future__ import annotations
 
@@ -22,6 +23,7 @@ LINEAR = "linear"
 VDP = "vdp"
 LORENZ = "lorenz"
 VDP2 = "vdp2"
+CSTR = "cstr"
 
 LATTICE3 = "lattice3"            # 3^n points: offsets {0, 1/2, 1} of the cell width
 CORNERS_CENTER = "corners_center"  # 2^n corners + the centre
@@ -104,6 +106,21 @@ def vdp2(coupling: float = 0.2, dt: float = 0.1, nsub: int = 4) -> System:
     return System(VDP2, 4, 2, dt, nsub, (float(coupling),))
 
 
+def cstr(dt: float = 0.1, nsub: int = 1, q: float = 100.0, V: float = 100.0,
+         cAf: float = 1.0, Tf: float = 350.0, E_over_R: float = 8750.0, k0: float = 7.2e10,
+         minus_dH: float = 5.0e4, UA: float = 5.0e4, cp: float = 0.239,
+         rho: float = 1000.0) -> System:
+    """The CSTR of Sec. 4.1 (Eq. 4), state (cA [mol/L], T [K]), input the
+    coolant temperature Tc [K]; defaults are Table 2 and the sampling interval
+    h = 0.1 min, one RK4 step per interval:
+        cA' = q/V (cAf - cA) - k0 exp(-(E/R) / T) cA
+        T'  = q/V (Tf - T) + (-dH)/(rho cp) k0 exp(-(E/R) / T) cA + UA/(V rho cp) (Tc - T)
+    Parameters packed as (q/V, cAf, Tf, E/R, k0, -dH/(rho cp), UA/(V rho cp))."""
+    return System(CSTR, 2, 1, float(dt), int(nsub),
+                  (q / V, float(cAf), float(Tf), float(E_over_R), float(k0),
+                   minus_dH / (rho * cp), UA / (V * rho * cp)))
+
+
 def linear(A: Sequence[Sequence[float]], B: Sequence[Sequence[float]], dt: float,
            nsub: int) -> System:
     """x' = A x + B u (n <= 4, m <= 2); parameters packed as A (stride 4) then B (stride 2)."""
@@ -181,6 +198,32 @@ def vdp2_adaptive_32_r1() -> Workload:
     return dataclasses.replace(wl, name="vdp2_adaptive_32^4_r1", rounds=1)
 
 
+CSTR_BOX = ((0.0, 345.0), (1.0, 355.0))   # 0 <= cA <= 1 mol/L, 345 <= T <= 355 K (Sec. 4.1)
+CSTR_U = (285.0, 315.0)                   # 285 <= Tc <= 315 K
+
+
+def cstr_adaptive(nn: int = 3, rounds: int = 10, n0: int = 8, K: int = 31,
+                  precision: str = "fp64") -> Workload:
+    """The CSTR of Sec. 4.1 with adaptive subdivision: an n0 x n0 coarse grid
+    of X, K coolant temperatures evenly spaced on U, the boundary cells and
+    their nn nearest kept cells split into 4 children per round (Sec. 3.1).
+    A round halves the finest width in both dimensions, as two iterations of
+    the standard algorithm do, so 10 rounds match the paper's 20 iterations."""
+    return Workload(f"cstr_adaptive_{n0}x{n0}_r{rounds}_n{nn}", cstr(),
+                    Grid((n0, n0), *CSTR_BOX), evenly_spaced(*CSTR_U, K), LATTICE3, rounds,
+                    precision, analysis="nonleaving", nn=nn)
+
+
+def cstr_standard(rounds: int = 20, n0: int = 8, K: int = 31,
+                  precision: str = "fp64") -> Workload:
+    """The CSTR with the standard algorithm (every kept cell halved, the cut
+    dimension cycled: Sec. 2.1; the paper's N = 1000 case of Sec. 4.2, where
+    all cells are subdivided), on the grid and inputs of cstr_adaptive."""
+    return Workload(f"cstr_standard_{n0}x{n0}_r{rounds}", cstr(), Grid((n0, n0), *CSTR_BOX),
+                    evenly_spaced(*CSTR_U, K), LATTICE3, rounds, precision,
+                    analysis="nonleaving", subdivision="bisect")
+
+
 def scaled_vdp_box(scale: float) -> Tuple[Tuple[float, ...], Tuple[float, ...]]:
     return ((-2.5 * scale, -3.0 * scale), (2.5 * scale, 3.0 * scale))
 
@@ -250,6 +293,8 @@ ALL = {
     "lorenz_uniform_128^3": lorenz_uniform_128,
     "vdp2_adaptive_32^4_r2": vdp2_adaptive_32,
     "vdp2_adaptive_32^4_r1": vdp2_adaptive_32_r1,
+    "cstr_adaptive_8x8_r10_n3": cstr_adaptive,
+    "cstr_standard_8x8_r20": cstr_standard,
 }
 
 
@@ -265,7 +310,9 @@ def canonical_flops_per_row(system: System, samples: str) -> int:
     """Algorithmic flop count of one (cell, input) image: S samples x nsub
     substeps x (4 F + 12 n), F = flops of one field evaluation in its
     canonical operation order (an FMA counts two)."""
-    F = {VDP: 6, LORENZ: 9, VDP2: 16}.get(system.kind)
+    # CSTR: the division (E/R)/T (1), exp (1 multiply, 2 + 13 FMAs: 31), the
+    # rate (2), cA' (3), T' (7); negations are free, as in the other fields
+    F = {VDP: 6, LORENZ: 9, VDP2: 16, CSTR: 44}.get(system.kind)
     if F is None:  # linear: n (m + n) FMAs
         F = 2 * system.n * (system.m + system.n)
     return sample_count(samples, system.n) * system.nsub * (4 * F + 12 * system.n)

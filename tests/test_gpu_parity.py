@@ -67,6 +67,7 @@ SMALL = {
                 W.evenly_spaced(-1, 1, 7), W.LATTICE3),
     "linear3": (W.random_linear(5, 3, 2), W.Grid((7, 6, 5), (-1.,) * 3, (1.,) * 3),
                 W.input_grid(-1, 1, 2, 2), W.LATTICE3),
+    "cstr": (W.cstr(), W.Grid((24, 20), *W.CSTR_BOX), W.evenly_spaced(285, 315, 7), W.LATTICE3),
 }
 
 
@@ -105,7 +106,7 @@ def test_build_uniform_matches_oracle(G, ctx, name):
     _check_graph(G, ctx, system, grid, u, samples, level, idx)
 
 
-@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1", "cstr"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_build_adaptive_matches_oracle(G, ctx, name, seed):
     """Mixed-level coverings with holes: edges to coarse and fine cells, holes -> OUT."""
@@ -122,7 +123,7 @@ def test_build_fast_out(G, ctx):
     _check_graph(G, ctx, system, grid, u, samples, level, idx, fast_out=True)
 
 
-@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "cstr"])
 def test_build_fp32_recheck_equals_fp64(G, ctx, name):
     system, grid, u, samples = SMALL[name]
     rng = np.random.Generator(np.random.PCG64(7))
@@ -137,7 +138,7 @@ def test_build_fp32_recheck_equals_fp64(G, ctx, name):
 
 # ------------------------------------------------------------------ prune
 @pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
-@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1", "cstr"])
 def test_prune_matches_oracle(G, ctx, name, analysis):
     system, grid, u, samples = SMALL[name]
     rng = np.random.Generator(np.random.PCG64(3))
@@ -580,7 +581,7 @@ def test_solve_vdp_uniform_64(G, ctx):
 
 
 @pytest.mark.parametrize("analysis", ["controlled", "nonleaving"])
-@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1", "linear3"])
+@pytest.mark.parametrize("name", ["vdp", "lorenz", "vdp2", "linear1", "linear3", "cstr"])
 def test_solve_uniform_frontier_from_boxes(G, ctx, name, analysis):
     """One-round solves of full coarse grids straight into the frontier phase
     (the cell-grouped reverse graph built from a solve's job table), 1 to 4
