@@ -11,6 +11,10 @@ rounds, 7x7 inputs (1.84e9 rows per solve), FP32 images with the FP64
 recheck; the same solve with plain FP64 images is timed beside it
 ("other_precision").
 
+A measurement "cstr" reruns the paper's own experiment (the reactor of
+Sec. 4.1): adaptive solves with neighbourhoods N = 0, 1, 3, 5 against the
+standard algorithm at the same finest cell width, time per solve and cells.
+
 A second measurement, "serving", runs the mixed stream of smaller solves
 (with their membership and admissible-input queries) through the
 continuous-batching server and reports solves/s and p50/p99 latency.
@@ -19,6 +23,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--precision fp64|fp32_recheck] [--other-steps N]
                        [--analysis controlled|nonleaving|largest_scc] [--no-cpu-baseline]
                        [--autotune] [--tuning field=value,...] [--serve-requests N]
+                       [--cstr-steps N]
 
 With --autotune the library's autotuner first picks the schedule parameters
 (sweep and frontier batching, grid shapes) for the workload by timing whole
@@ -67,6 +72,8 @@ def parse():
                    help="schedule parameters to start from, as field=value[,field=value...] "
                         "(fields of gis_tuning)")
     p.add_argument("--cpu-budget-s", type=float, default=15.0)
+    p.add_argument("--cstr-steps", type=int, default=3,
+                   help="solves per configuration of the reactor experiment (0: skip it)")
     p.add_argument("--serve-requests", type=int, default=1000,
                    help="requests of the Poisson pass of the serving measurement (0: skip it); "
                         "the saturation pass takes a quarter of them")
@@ -269,6 +276,48 @@ def analysis_roofline(wl, phase_infos):
             "ms_per_solve": ms / max(len(phase_infos), 1)}
 
 
+def cstr_experiment(gis, W, ctx, stream, steps, cpu_budget_s):
+    """The paper's reactor experiment (Sec. 4.1-4.2) on this GPU: adaptive
+    subdivision with neighbourhoods N = 0, 1, 3, 5 over 10 rounds against the
+    standard algorithm (every kept cell halved, the paper's N = 1000) over 20
+    halvings -- the same finest cell width -- from the same 8x8 grid with 31
+    coolant temperatures, FP64 images.  The paper reports N = 3 about 8x
+    faster than N = 1000 after 20 iterations on its CPU."""
+    def one(wl):
+        infos, el, _ = timed_solves(gis, ctx, wl, stream, "fp64", steps, 1)
+        last = infos[-1]
+        rows = sum(r["n_rows"] for r in last["rounds"])
+        return {"workload": wl.name, "ms_per_solve": 1e3 * el / steps, "rows_per_solve": rows,
+                "images_per_s": rows * steps / el, "final_cells": last["n_cells"],
+                "final_kept": last["n_kept"],
+                "cells_per_round": [r["n_cells"] for r in last["rounds"]],
+                "k_build": build_roofline(W, wl, infos, "fp64")}
+
+    res = {"grid0": [8, 8], "inputs": 31, "precision": "fp64", "steps": steps,
+           "adaptive": [{"N": nn, **one(W.cstr_adaptive(nn=nn))} for nn in (0, 1, 3, 5)],
+           "standard": one(W.cstr_standard())}
+    n3 = next(r for r in res["adaptive"] if r["N"] == 3)
+    res["standard_over_adaptive_N3"] = res["standard"]["ms_per_solve"] / n3["ms_per_solve"]
+    if cpu_budget_s > 0:
+        # the oracle on this host: whole 6-round adaptive solves (N = 3)
+        import oracle
+        oracle._load()
+        wl = W.cstr_adaptive(nn=3, rounds=6)
+        reps, rows, t0 = 0, 0, time.perf_counter()
+        while True:
+            r = oracle.solve(wl.system, wl.grid, wl.samples, wl.u, wl.rounds,
+                             analysis=wl.analysis, nn=wl.nn)
+            rows += sum(x["n_rows"] for x in r["stats"])
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= cpu_budget_s:
+                break
+        res["cpu_oracle"] = {"value": rows / el, "unit": "images/s", "cores": 1, "kind": "oracle",
+                             "sample": f"{reps} whole solve(s) of {wl.name} in {el:.1f} s, "
+                                       "single thread"}
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -359,6 +408,9 @@ def main():
             "ms_per_step": 1e3 * o_el / a.other_steps,
             "k_build": build_roofline(W, wl, o_infos, other),
             "same_edge_and_kept_counts": same}
+    if a.cstr_steps > 0:
+        res["cstr"] = cstr_experiment(gis, W, ctx, stream, a.cstr_steps,
+                                      0.0 if a.no_cpu_baseline else 5.0)
     ctx.close()
     if a.serve_requests > 0:
         res["serving"] = serving(a.serve_requests)

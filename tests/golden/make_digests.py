@@ -22,6 +22,10 @@ Digests are over the arrays' little-endian bytes.  Workloads:
                          --only vdp2r2 also round 2's graph and analysis (the
                          graph, 62 GB, is written to files under --workdir and
                          the oracle's analysis runs on them memory-mapped)
+  cstr                   the reactor of Sec. 4.1: the adaptive solve (8x8, 10
+                         rounds, N = 3) and the standard one (20 halvings):
+                         per-round counts, final covering, kept set, masks and
+                         the answers to 10^5 seeded queries
   serving stream         every request of the seeded serving test stream
                          (Van der Pol, grids 32^2 .. 256^2): final covering,
                          kept set, masks, and the answers to its queries
@@ -34,6 +38,7 @@ about an hour more and 62 GB of disk.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import multiprocessing as mp
@@ -167,6 +172,41 @@ class _Sha:
         return self.h.hexdigest()
 
 
+def build_graph_to_disk(wl, level, idx, procs, workdir, what):
+    """oracle.build_graph over every row by row ranges, streamed to files
+    under workdir (row offsets i64, targets i32, OUT flags u8) while running
+    digests are taken; returns the memory-mapped arrays and the graph entry."""
+    n_rows = level.shape[0] * wl.K
+    os.makedirs(workdir, exist_ok=True)
+    f_rp, f_col, f_out = (os.path.join(workdir, f) for f in ("row_ptr.i64", "col.i32", "out.u8"))
+    h_rp, h_col, h_out = _Sha(), _Sha(), _Sha()
+    n_chunks = 1024
+    cuts = np.linspace(0, n_rows, n_chunks + 1).astype(np.int64)
+    total = 0
+    log(f"{what}: build {n_rows} rows into {workdir}")
+    ctx = mp.get_context("fork")
+    with open(f_rp, "wb") as frp, open(f_col, "wb") as fcol, open(f_out, "wb") as fout, \
+            ctx.Pool(procs, initializer=_init, initargs=(wl, level, idx)) as pool:
+        zero = np.zeros(1, dtype=np.int64)
+        frp.write(zero.tobytes())
+        h_rp.feed(zero)
+        for i, (cnt, col, out) in enumerate(pool.imap(_chunk, list(zip(cuts[:-1], cuts[1:])))):
+            rp = np.cumsum(cnt) + total
+            total = int(rp[-1]) if rp.shape[0] else total
+            for f, h, a in ((frp, h_rp, rp), (fcol, h_col, col), (fout, h_out, out)):
+                f.write(np.ascontiguousarray(a).tobytes())
+                h.feed(a)
+            if i % 64 == 0:
+                log(f"  chunk {i}/{n_chunks}: {total} edges so far")
+    entry = {"n_rows": int(n_rows), "n_edges": int(total), "row_ptr": h_rp.hex(),
+             "col": h_col.hex(), "out": h_out.hex()}
+    rp = np.memmap(f_rp, dtype=np.int64, mode="r")
+    col = np.memmap(f_col, dtype=np.int32, mode="r") if total > 0 else np.zeros(0, np.int32)
+    out = np.memmap(f_out, dtype=np.uint8, mode="r")
+    entry["n_out"] = int(np.sum(out, dtype=np.int64))
+    return {"row_ptr": rp, "col": col, "out": out}, entry
+
+
 def vdp2_round2(procs, workdir):
     """Round 2 of the coupled Van der Pol solve: the round-2 covering is
     recomputed (rounds 0 and 1, checked against the stored digest), its
@@ -184,38 +224,75 @@ def vdp2_round2(procs, workdir):
         bnd = oracle.boundary(wl.grid, level, idx, kept, wl.boundary_rule)
         level, idx = oracle.subdivide(wl.grid, level, idx, kept, bnd)
     n_cells = level.shape[0]
-    n_rows = n_cells * wl.K
     cov = covering_entry(level, idx)
-    os.makedirs(workdir, exist_ok=True)
-    f_rp, f_col, f_out = (os.path.join(workdir, f) for f in ("row_ptr.i64", "col.i32", "out.u8"))
-    h_rp, h_col, h_out = _Sha(), _Sha(), _Sha()
-    n_chunks = 1024
-    cuts = np.linspace(0, n_rows, n_chunks + 1).astype(np.int64)
-    total = 0
-    log(f"{wl.name}: round 2: build {n_rows} rows into {workdir}")
-    ctx = mp.get_context("fork")
-    with open(f_rp, "wb") as frp, open(f_col, "wb") as fcol, open(f_out, "wb") as fout, \
-            ctx.Pool(procs, initializer=_init, initargs=(wl, level, idx)) as pool:
-        zero = np.zeros(1, dtype=np.int64)
-        frp.write(zero.tobytes())
-        h_rp.feed(zero)
-        for i, (cnt, col, out) in enumerate(pool.imap(_chunk, list(zip(cuts[:-1], cuts[1:])))):
-            rp = np.cumsum(cnt) + total
-            total = int(rp[-1]) if rp.shape[0] else total
-            for f, h, a in ((frp, h_rp, rp), (fcol, h_col, col), (fout, h_out, out)):
-                f.write(np.ascontiguousarray(a).tobytes())
-                h.feed(a)
-            if i % 64 == 0:
-                log(f"  chunk {i}/{n_chunks}: {total} edges so far")
-    graph = {"n_rows": int(n_rows), "n_edges": int(total), "row_ptr": h_rp.hex(), "col": h_col.hex(),
-             "out": h_out.hex()}
-    rp = np.memmap(f_rp, dtype=np.int64, mode="r")
-    col = np.memmap(f_col, dtype=np.int32, mode="r")
-    out = np.memmap(f_out, dtype=np.uint8, mode="r")
-    graph["n_out"] = int(np.sum(out, dtype=np.int64))
-    log(f"{wl.name}: round 2: {wl.analysis} analysis ({total} edges, memory-mapped)")
-    kept, mask, sweeps = oracle.prune(rp, col, out, n_cells, wl.K, wl.analysis)
+    g, graph = build_graph_to_disk(wl, level, idx, procs, workdir, f"{wl.name}: round 2")
+    log(f"{wl.name}: round 2: {wl.analysis} analysis ({graph['n_edges']} edges, memory-mapped)")
+    kept, mask, sweeps = oracle.prune(g["row_ptr"], g["col"], g["out"], n_cells, wl.K, wl.analysis)
     return {"covering": cov, "graph": graph, wl.analysis: analysis_entry(kept, mask, sweeps)}
+
+
+def solve_rounds(wl, procs, workdir):
+    """The loop of oracle.solve (Sec. 2.1 and Sec. 3.1) with each round's
+    graph built by row ranges in parallel processes (rounds of more than
+    2e8 rows streamed to files under workdir and analysed memory-mapped);
+    returns the final grid, covering, kept flags, masks and the per-round
+    counts."""
+    grid = wl.grid
+    level, idx = oracle.coarse_cells(grid)
+    stats, kept = [], None
+    for r in range(wl.rounds + 1):
+        if r > 0:
+            if wl.subdivision == "bisect":
+                grid, level, idx = oracle.bisect(grid, idx, kept, (r - 1) % grid.n)
+                stats[-1]["n_boundary"] = int(kept.sum())
+            else:
+                bnd = oracle.boundary(grid, level, idx, kept, wl.boundary_rule)
+                sel = oracle.neighbours(grid, level, idx, kept, bnd, wl.nn) if wl.nn > 0 else bnd
+                level, idx = oracle.subdivide(grid, level, idx, kept, sel)
+                stats[-1]["n_boundary"] = int(bnd.sum())
+                stats[-1]["n_selected"] = int(sel.sum())
+        if level.shape[0] == 0:
+            break
+        wl_r = dataclasses.replace(wl, grid=grid)
+        if level.shape[0] * wl.K > 200_000_000:
+            g, _ = build_graph_to_disk(wl_r, level, idx, procs, workdir, f"{wl.name}: round {r}")
+        else:
+            log(f"{wl.name}: round {r}: build {level.shape[0] * wl.K} rows")
+            g = build_graph(wl_r, level, idx, procs)
+        kept, mask, sweeps = oracle.prune(g["row_ptr"], g["col"], g["out"], level.shape[0], wl.K,
+                                          wl.analysis)
+        stats.append({"n_cells": int(level.shape[0]), "n_rows": int(level.shape[0] * wl.K),
+                      "n_edges": int(g["col"].shape[0]),
+                      "n_out": int(np.sum(g["out"], dtype=np.int64)),
+                      "n_kept": int(kept.sum()), "sweeps": sweeps})
+        del g
+        if kept.sum() == 0:
+            break
+    return grid, level, idx, kept, mask, stats
+
+
+# seeded query states of the CSTR solves (tests/test_gpu_fullsize.py draws the same)
+CSTR_QUERIES = dict(n=100_000, seed=9, margin=0.02)
+
+
+def cstr(procs, workdir):
+    out = {}
+    for wl in (W.cstr_adaptive(), W.cstr_standard()):
+        t = time.time()
+        grid, level, idx, kept, mask, stats = solve_rounds(wl, procs, workdir)
+        q = W.query_states(wl.grid, CSTR_QUERIES["n"], seed=CSTR_QUERIES["seed"],
+                           margin=CSTR_QUERIES["margin"])
+        member, adm = oracle.query(grid, level, idx, kept, mask, q)
+        out[wl.name] = {"cite": "Sec. 4.1 (Eq. 4, Table 2); Sec. 2.2-2.3; Sec. 3.1 (Algorithm 1, "
+                                "Remark 1, N-NN of Sec. 3.1.2) or Sec. 2.1 (halving)",
+                        "analysis": wl.analysis, "n0": list(grid.n0), "rounds": stats,
+                        "covering": covering_entry(level, idx),
+                        wl.analysis: analysis_entry(kept, mask, stats[-1]["sweeps"]),
+                        "queries": dict(CSTR_QUERIES), "member": sha(member),
+                        "admissible": sha(adm), "oracle_seconds": round(time.time() - t, 1)}
+        log(f"{wl.name}: {len(stats)} rounds, final cells {stats[-1]['n_cells']}, "
+            f"kept {stats[-1]['n_kept']}")
+    return out
 
 
 def serving():
@@ -240,9 +317,9 @@ def serving():
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--procs", type=int, default=8)
-    p.add_argument("--only", default=None, help="lorenz, vdp2, serving or vdp2r2")
+    p.add_argument("--only", default=None, help="lorenz, vdp2, serving, cstr or vdp2r2")
     p.add_argument("--workdir", default=os.path.join(ROOT, "_work", "big"),
-                   help="where vdp2r2 writes the round-2 graph (62 GB)")
+                   help="where vdp2r2 and cstr write their largest graphs (62 GB, 29 GB)")
     a = p.parse_args()
     oracle._load()
     data = {}
@@ -250,9 +327,9 @@ def main():
         with open(OUT) as f:
             data = json.load(f)
     jobs = {"serving": lambda: serving(), "lorenz": lambda: lorenz(a.procs),
-            "vdp2": lambda: vdp2(a.procs)}
+            "vdp2": lambda: vdp2(a.procs), "cstr": lambda: cstr(a.procs, a.workdir)}
     keys = {"serving": "serving_stream", "lorenz": "lorenz_uniform_128^3",
-            "vdp2": "vdp2_adaptive_32^4_r2"}
+            "vdp2": "vdp2_adaptive_32^4_r2", "cstr": "cstr"}
     if a.only == "vdp2r2":
         t = time.time()
         r2 = vdp2_round2(a.procs, a.workdir)

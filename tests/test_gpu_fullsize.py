@@ -10,7 +10,10 @@ generators):
   gis_prune, gis_subdivide), FP64 and FP32 with the FP64 recheck (equal
   element by element on the device), and the whole gis_solve in both
   precisions against the last round's digests; with every row of every round
-  checked against the recheck band.
+  checked against the recheck band;
+* the reactor of Sec. 4.1 as bench.py times it: the adaptive solve (8x8,
+  10 rounds, N = 3) and the standard one (20 halvings, 2.0e9 rows): every
+  round's counts, the final covering, kept set and masks, query answers.
 
 Digests are SHA-256 of the arrays' little-endian bytes, the layout of the C
 ABI (row_ptr i64, col i32, out u8, level u8, idx i32 cell-major, kept u8,
@@ -198,5 +201,42 @@ def test_vdp2_32_two_rounds_full_solve(G, D, precision):
         _check_covering(lv, ix, want[2]["covering"], "final covering")
         if wl.analysis in want[2]:
             _check_analysis(kept, mask, want[2][wl.analysis], "final analysis")
+        sol.free()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["cstr_adaptive_8x8_r10_n3", "cstr_standard_8x8_r20"])
+def test_cstr_full_solve(G, D, name):
+    """The reactor experiment's two solves (Sec. 4.1-4.2) as bench.py times
+    them -- 10 adaptive rounds with the N = 3 neighbourhood, and the standard
+    algorithm's 20 halvings (2.0e9 rows in all, 5.0e9 edges in its last
+    round) -- against the oracle's digests: every round's counts, the final
+    covering, kept set and masks, and the answers to 10^5 seeded queries."""
+    if "cstr" not in D or name not in D["cstr"]:
+        pytest.skip("the oracle's digests of this solve are not recorded")
+    want = D["cstr"][name]
+    wl = W.ALL[name]()
+    torch.cuda.empty_cache()
+    with G.Context(0) as ctx:
+        sol = G.solve_workload(ctx, wl)
+        inf = sol.info()
+        assert inf["n_rounds"] == len(want["rounds"])
+        assert list(inf["n0"]) == want["n0"]
+        for i, (got_r, want_r) in enumerate(zip(inf["rounds"], want["rounds"])):
+            for k in ("n_cells", "n_rows", "n_edges", "n_out", "n_kept"):
+                assert got_r[k] == want_r[k], (name, i, k, got_r[k], want_r[k])
+            for k in ("n_boundary", "n_selected"):
+                if k in want_r:
+                    assert got_r[k] == want_r[k], (name, i, k, got_r[k], want_r[k])
+        print(f"{name}: rounds {inf['n_rounds']} final cells {inf['rounds'][-1]['n_cells']} "
+              f"edges {inf['rounds'][-1]['n_edges']}", flush=True)
+        lv, ix, kept, mask = sol.export()
+        _check_covering(lv, ix, want["covering"], f"{name} covering")
+        _check_analysis(kept, mask, want[wl.analysis], f"{name} analysis")
+        qa = want["queries"]
+        states = torch.as_tensor(W.query_states(wl.grid, qa["n"], seed=qa["seed"],
+                                                margin=qa["margin"]), device=ctx.dev)
+        assert _sha(sol.query_membership(states)) == want["member"]
+        assert _sha(sol.query_admissible(states)) == want["admissible"]
         sol.free()
     torch.cuda.empty_cache()
