@@ -14,6 +14,11 @@ Parity status per function (what pins each one is in tests/test_oracle_*.py):
                   invariant and its textbook steady state
   exp             pinned: the C library's exp within 1 ulp, exact powers of
                   two, overflow, underflow and NaN
+  user fields     the caller's field code compiled for the host (gcc, FP64,
+                  no contraction); pinned: the built-in fields written as
+                  user code give the same bits, and a field outside the
+                  built-ins (Duffing) against scipy DOP853 and the 4th-order
+                  error ratio
   cover           pinned: exact rational brute force on dyadic grids
   build           pinned: identity-map stencil, brute-force box/cell overlap
   prune           pinned: brute-force subset enumeration, drift/contraction
@@ -47,7 +52,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gis_oracle.c")
 _LIB = os.path.join(_HERE, "libgis_oracle.so")
 
-_KINDS = {"linear": 0, "vdp": 1, "lorenz": 2, "vdp2": 3, "cstr": 4}
+_KINDS = {"linear": 0, "vdp": 1, "lorenz": 2, "vdp2": 3, "cstr": 4, "user": 5}
 _SCHEMES = {"lattice3": 1, "corners_center": 2}
 _RULES = {"shell": 1, "corners": 2}
 
@@ -79,11 +84,13 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(_LIB)
+        # global symbols: a user field's library calls or_exp
+        lib = ctypes.CDLL(_LIB, mode=ctypes.RTLD_GLOBAL)
         P = ctypes.c_void_p
         I32, I64 = ctypes.c_int32, ctypes.c_int64
         lib.or_step.argtypes = [P, P, P, P]
         lib.or_exp_vec.argtypes = [P, I64, P]
+        lib.or_set_user_field.argtypes = [P]
         lib.or_num_samples.argtypes = [I32, I32]
         lib.or_num_samples.restype = I32
         lib.or_images.argtypes = [P, P, I32, P, P, I64, P, I32, P]
@@ -113,7 +120,51 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+_TWIN = r'''/* CPU twin of a user field, written by oracle/__init__.py: the field's
+ * code compiled as C99 in FP64, operation by operation. */
+#include <math.h>
+typedef double R;
+double or_exp(double x);
+static double fmaT(double a, double b, double c) { return fma(a, b, c); }
+static double expT(double v) { return or_exp(v); }
+void user_field_twin(const double* p, const double* x, const double* u, double* dx) {
+  (void)p; (void)x; (void)u;
+#line 1 "user field"
+%s
+}
+'''
+_twins = {}   # body -> (library, function pointer)
+_twin_dir = None
+
+
+def _install_user_field(body: str) -> None:
+    """Compiles the body of a user field for the host (gcc, FP64, no
+    contraction, like the oracle) and installs it as the oracle's field of
+    kind "user"."""
+    global _twin_dir
+    lib = _load()
+    if body not in _twins:
+        import hashlib
+        import tempfile
+        if _twin_dir is None:
+            _twin_dir = tempfile.mkdtemp(prefix="gis_oracle_fields_")
+        key = hashlib.sha256(body.encode()).hexdigest()[:16]
+        src = os.path.join(_twin_dir, f"field_{key}.c")
+        so = os.path.join(_twin_dir, f"field_{key}.so")
+        with open(src, "w") as f:
+            f.write(_TWIN % body)
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                        "-fno-fast-math", "-o", so, src, "-lm"], check=True)
+        twin = ctypes.CDLL(so)
+        _twins[body] = (twin, ctypes.cast(twin.user_field_twin, ctypes.c_void_p).value)
+    lib.or_set_user_field(_twins[body][1])
+
+
 def _sys(system) -> _Sys:
+    if system.kind == "user":
+        if not system.source:
+            raise ValueError("the oracle needs the code of a user field")
+        _install_user_field(system.source)
     s = _Sys()
     s.kind = _KINDS[system.kind]
     s.n, s.m, s.nsub, s.dt = system.n, system.m, system.nsub, system.dt

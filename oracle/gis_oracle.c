@@ -47,7 +47,7 @@
 #include <string.h>
 
 /* ---- system kinds and sample schemes (the oracle's own numbering) ---- */
-enum { OR_LINEAR = 0, OR_VDP = 1, OR_LORENZ = 2, OR_VDP2 = 3, OR_CSTR = 4 };
+enum { OR_LINEAR = 0, OR_VDP = 1, OR_LORENZ = 2, OR_VDP2 = 3, OR_CSTR = 4, OR_USER = 5 };
 enum { OR_LATTICE3 = 1, OR_CORNERS_CENTER = 2 };
 enum { OR_SHELL = 1, OR_CORNERS = 2 };
 
@@ -97,6 +97,16 @@ double or_exp(double x) {
 void or_exp_vec(const double* x, int64_t n, double* y) {
   for (int64_t i = 0; i < n; ++i) y[i] = or_exp(x[i]);
 }
+
+/* ------------------------------------------------------------------ */
+/* A field given as code by the caller (Eq. 1 takes f as input): the     */
+/* Python side compiles its body as C into a library of its own and      */
+/* installs the function here.                                           */
+/* ------------------------------------------------------------------ */
+typedef void (*or_user_fn)(const double* p, const double* x, const double* u, double* dx);
+static or_user_fn g_user_field = 0;
+
+void or_set_user_field(or_user_fn f) { g_user_field = f; }
 
 /* ------------------------------------------------------------------ */
 /* Vector field f of the ODE whose RK4 discretisation is Eq. (1).      */
@@ -152,6 +162,13 @@ static void field(const or_system* s, const double* x, const double* u, double* 
       dx[1] = fma(p[0], p[2] - x[1], fma(p[5], rate, p[6] * (u[0] - x[1])));
       break;
     }
+    case OR_USER:
+      if (g_user_field) {
+        g_user_field(p, x, u, dx);
+        break;
+      }
+      for (int d = 0; d < s->n; ++d) dx[d] = NAN;
+      break;
     default:
       for (int d = 0; d < s->n; ++d) dx[d] = NAN;
   }
