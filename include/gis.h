@@ -65,7 +65,9 @@
 #ifndef GIS_H
 #define GIS_H
 
+#ifndef __HIPCC_RTC__  /* the library's runtime-compiled fields define the types themselves */
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -82,7 +84,7 @@ typedef enum {
 } gis_status;
 
 enum { GIS_SYS_LINEAR = 0, GIS_SYS_VDP = 1, GIS_SYS_LORENZ = 2, GIS_SYS_VDP2 = 3,
-       GIS_SYS_CSTR = 4 };
+       GIS_SYS_CSTR = 4, GIS_SYS_USER = 5 };
 enum { GIS_SAMPLES_LATTICE3 = 1, GIS_SAMPLES_CORNERS_CENTER = 2 };
 enum { GIS_PREC_FP64 = 1, GIS_PREC_FP32_RECHECK = 2 };
 enum { GIS_BOUNDARY_SHELL = 1, GIS_BOUNDARY_CORNERS = 2 };
@@ -103,7 +105,8 @@ enum { GIS_SUBDIVIDE_BOUNDARY = 0, GIS_SUBDIVIDE_BISECT = 1 };
  *                           params[0..6] = q/V, cAf, Tf, E/R, k0, -dH/(rho cp), UA/(V rho cp);
  *                           exp is the library's own (Cody-Waite reduction, degree-13
  *                           Taylor polynomial, exact 2^k scaling; within 1 ulp), so FP64
- *                           images are reproducible bit for bit */
+ *                           images are reproducible bit for bit
+ *  USER   (n <= 4, m <= 2): the context's runtime-compiled field (gis_set_user_field) */
 typedef struct gis_system {
   int32_t kind, n, m, nsub;
   double dt;
@@ -356,6 +359,25 @@ int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, co
 int32_t gis_calibrate_band(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid,
                            const double* d_u, int32_t K, const gis_cells* cells, int32_t samples,
                            double safety, double floor_rel, double* band_out, void* stream);
+
+/* The vector field of systems of kind GIS_SYS_USER in this context: the
+ * problem statement (Eq. 1) takes f as given, so the caller may supply g of
+ * x' = g(x, u) as code, which the library compiles at run time (hipRTC, about
+ * a second) together with its own graph-construction kernels -- the same RK4
+ * operation order, sample points, cover logic, recheck and emit as for the
+ * built-in fields.  `body` is C++ for the device that sets dx[0 .. n-1] from
+ * x[0 .. n-1], u[0 .. m-1] and p[0 .. 23] (gis_system.params), all of type R
+ * (double for FP64 images, float for FP32 ones); fmaT(a, b, c) (fused
+ * multiply-add) and expT(v) (the library's exp, see GIS_SYS_CSTR) may be
+ * called, and locals declared.  Compiled with -ffp-contract=off: FP64 images
+ * are reproducible bit for bit when the body uses only IEEE operations
+ * (+ - * /, fmaT) and expT.  The field replaces the context's previous one;
+ * systems of kind GIS_SYS_USER must have its n (1..4) and m (1..2)
+ * (GIS_E_INVAL at the call otherwise, and when no field is set).  With ctx
+ * NULL the body is only compiled, for gfx950, needing no device.  GIS_E_INVAL
+ * if it does not compile (the compiler's messages in gis_last_error()).
+ * Synchronises the context's device. */
+int32_t gis_set_user_field(gis_ctx* ctx, const char* body, int32_t n, int32_t m);
 
 /* The library's FP64 exponential, the one in the CSTR field (Sec. 4.1,
  * Eq. 4), applied elementwise for parity checks: d_y[i] = exp(d_x[i]),

@@ -10,12 +10,14 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "gis_launch.h"
+#include "gis_rtc.h"
 
 namespace gis {
 
@@ -145,6 +147,7 @@ struct gis_ctx {
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
   KernelTimer timer;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::unique_ptr<UserField> user;  // field of systems of kind GIS_SYS_USER
 };
 
 // A solution's arrays (covering, kept flags, masks, and the covering index
@@ -196,6 +199,7 @@ int32_t check_system(const gis_system* s) {
     case GIS_SYS_LORENZ: if (s->n != 3 || s->m != 1) return inval("LORENZ needs n=3, m=1"); break;
     case GIS_SYS_VDP2: if (s->n != 4 || s->m != 2) return inval("VDP2 needs n=4, m=2"); break;
     case GIS_SYS_CSTR: if (s->n != 2 || s->m != 1) return inval("CSTR needs n=2, m=1"); break;
+    case GIS_SYS_USER: break;  // n and m are checked against the context's field at launch
     default: return inval("unknown system kind");
   }
   return GIS_OK;
@@ -574,6 +578,8 @@ BuildArgs build_args(gis_ctx* ctx, const Batch& B, const uint8_t* level, const i
   a.fast_out = o ? o->fast_out : 0;
   a.kind = B.n_jobs ? B.jobs[0].sys.kind : 0;
   a.n = B.n;
+  a.m = B.n_jobs ? B.jobs[0].sys.m : 0;
+  a.user = ctx->user.get();
   a.n_blocks = B.blocks[LK_ROWS];
   a.total_rows = B.total_cells * B.K;
   // full level-0 grids (also those whose index arrays are kept for the
@@ -1647,8 +1653,10 @@ void gis_ctx_destroy(gis_ctx* c) {
                     &c->rcur, &c->rowstate, &c->good, &c->front, &c->bnd, &c->scc, &c->lvA,
                     &c->ixA,
                     &c->lvB, &c->ixB,
-                    &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask};
+                    &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask, &c->rbits, &c->rowbits,
+                    &c->wit, &c->sel};
   for (DevBuf* b : bufs) release(*b);
+  c->user.reset();
   for (auto& kv : c->graphs.map)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   c->h_cs.free();
@@ -2079,6 +2087,18 @@ int32_t gis_images(gis_ctx* ctx, const gis_system* sys, const gis_grid* grid, co
   BuildArgs a = build_args(ctx, B, cells->level, cells->idx, &o);
   if ((rc = launch_images(a, precision, d_images, s))) return rc;
   GIS_HIP(hipStreamSynchronize(s));  // the staged job table is consumed
+  return GIS_OK;
+}
+
+int32_t gis_set_user_field(gis_ctx* ctx, const char* body, int32_t n, int32_t m) {
+  if (!ctx) return user_field_compile(body, n, m, -1, nullptr) == GIS_OK ? GIS_OK : GIS_E_INVAL;
+  DeviceGuard g(ctx->device);
+  UserField* uf = nullptr;
+  const int32_t rc = user_field_compile(body, n, m, ctx->device, &uf);
+  if (rc) return rc;
+  // the previous field's kernels may still run on a stream of this device
+  (void)hipDeviceSynchronize();
+  ctx->user.reset(uf);
   return GIS_OK;
 }
 

@@ -10,7 +10,9 @@
 // the FP64 recheck.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "gis_internal.h"
 
@@ -101,6 +103,12 @@ __device__ __forceinline__ R expT(R x) {
   return ldexpT(p, (int)k);
 }
 
+// The field of kind GIS_SYS_USER: the caller's code, compiled at run time
+// (rtc.hip defines it in the runtime-compiled program; the static library
+// never instantiates it).  p: parameters, x: state, u: input, dx: g(x, u).
+template <typename R>
+__device__ void user_field(const R* p, const R* x, const R* u, R* dx);
+
 // Vector field g(x, u) of x' = g(x, u).  N is the state dimension; m (inputs)
 // is only a runtime value for the linear field.
 template <int KIND, int N, typename R>
@@ -121,6 +129,8 @@ __device__ __forceinline__ void field(const R* __restrict__ p, int m, const R* x
     dx[0] = p[0] * (x[1] - x[0]);
     dx[1] = fmaT(x[0], p[1] - x[2], u[0] - x[1]);
     dx[2] = fmaT(x[0], x[1], -(p[2] * x[2]));
+  } else if constexpr (KIND == GIS_SYS_USER) {
+    user_field<R>(p, x, u, dx);
   } else if constexpr (KIND == GIS_SYS_CSTR) {
     // Eq. (4), state (cA, T), input Tc; p = (q/V, cAf, Tf, E/R, k0,
     // -dH/(rho cp), UA/(V rho cp)); the reaction rate k0 exp(-(E/R)/T) cA

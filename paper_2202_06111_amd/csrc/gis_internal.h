@@ -1,12 +1,16 @@
 // Internal declarations of libgis shared by every translation unit: kernel
 // argument blocks, the covering index, device helpers, the scan, fill, copy and
 // build launchers.  The other units' launchers are declared in gis_launch.h.
+// Under hipRTC (runtime-compiled user fields, __HIPCC_RTC__) only the device
+// part is seen: argument blocks, job table and device helpers.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <string>
+#endif
 
 #include "gis.h"
 
@@ -60,6 +64,7 @@ __device__ __forceinline__ int64_t lin_index(const int32_t* dims, const int64_t*
   return lin;
 }
 
+#ifndef __HIPCC_RTC__
 // ---------------------------------------------------------------- error handling
 void set_error(const std::string& msg);
 int32_t hip_fail(hipError_t e, const char* what);
@@ -131,6 +136,7 @@ struct Gather {
   int n;
 };
 int32_t gather_copy(const Gather& g, hipStream_t s);
+#endif  // __HIPCC_RTC__
 
 // ---------------------------------------------------------------- jobs
 // A batch runs several independent solves (jobs) through the same launches.
@@ -226,7 +232,7 @@ struct BuildArgs {
   int32_t K;
   int32_t samples;        // GIS_SAMPLES_*
   int32_t fast_out;
-  int32_t kind, n;        // system kind and state dimension shared by the batch
+  int32_t kind, n, m;     // system kind, state and input dimensions shared by the batch
   int32_t all_uniform;    // every job's covering is its full level-0 grid
   int64_t n_blocks;       // launch blocks (LK_ROWS)
   int64_t total_rows;
@@ -244,7 +250,9 @@ struct BuildArgs {
   unsigned long long* n_recheck;  // rows the FP32 test sent to FP64
   uint32_t* err;          // bit 8: a look-back wait reached its time limit
   JobStats* stats;        // per-job n_edges, n_out, n_recheck (accumulated)
+  const void* user;       // host: the context's compiled user field (kind GIS_SYS_USER)
 };
+#ifndef __HIPCC_RTC__
 // Symbolic image of the batch's coverings into (row_ptr, col, out); col is
 // written only if the edge total fits in cap_edges.
 int32_t launch_build(const BuildArgs& a, int32_t precision, hipStream_t s);
@@ -260,5 +268,6 @@ int32_t launch_calibrate(const BuildArgs& a, unsigned long long* d_maxerr, int64
 // w the finest cell width of the job's current covering.
 int32_t launch_band(Job* d_jobs, int32_t n_jobs, int32_t n, const unsigned long long* d_maxerr,
                     double floor_rel, hipStream_t s);
+#endif  // __HIPCC_RTC__
 
 }  // namespace gis

@@ -19,7 +19,7 @@ from . import workloads as W
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgis.so")
 
-KIND = {W.LINEAR: 0, W.VDP: 1, W.LORENZ: 2, W.VDP2: 3, W.CSTR: 4}
+KIND = {W.LINEAR: 0, W.VDP: 1, W.LORENZ: 2, W.VDP2: 3, W.CSTR: 4, W.USER: 5}
 SAMPLES = {W.LATTICE3: 1, W.CORNERS_CENTER: 2}
 PRECISION = {"fp64": 1, "fp32_recheck": 2}
 RULE = {W.SHELL: 1, W.CORNERS: 2}
@@ -113,6 +113,7 @@ def lib():
             "gis_prune": ([P, P, I64, I32, I32, P, P, P, P], I32),
             "gis_prune_static": ([P, I64, I32, I32, P, P, P, P], I32),
             "gis_exp": ([P, I64, P, P], I32),
+            "gis_set_user_field": ([P, ctypes.c_char_p, I32, I32], I32),
             "gis_subdivide": ([P, P, P, P, I32, I32, P, P, P], I32),
             "gis_bisect": ([P, P, P, P, I32, P, P, P], I32),
             "gis_solve": ([P, P, P, P, I32, I32, P, ctypes.POINTER(P), P], I32),
@@ -137,7 +138,8 @@ def lib():
 
 EXPORTED = ("gis_ctx_create", "gis_ctx_destroy", "gis_get_tuning", "gis_set_tuning", "gis_autotune", "gis_build_graph", "gis_prune", "gis_prune_static", "gis_subdivide", "gis_bisect",
             "gis_solve", "gis_solve_batch", "gis_solution_info", "gis_solution_export", "gis_solution_free",
-            "gis_query_membership", "gis_query_admissible", "gis_images", "gis_exp", "gis_calibrate_band",
+            "gis_query_membership", "gis_query_admissible", "gis_images", "gis_exp", "gis_set_user_field",
+            "gis_calibrate_band",
             "gis_last_error", "gis_version")
 
 
@@ -156,7 +158,14 @@ def _ptr(t: Optional[torch.Tensor]) -> P:
 
 
 # ------------------------------------------------------------------ structs
-def system_t(system: W.System) -> SystemT:
+def system_t(system: W.System, ctx: Optional["Context"] = None) -> SystemT:
+    """The gis_system of a system; a system with its own field code (kind
+    "user", non-empty source) first installs that field in ctx
+    (gis_set_user_field); with an empty source the context's field is used."""
+    if system.kind == W.USER and system.source:
+        if ctx is None:
+            raise ValueError("a system with a user field needs the context it runs in")
+        ctx.use_field(system.source, system.n, system.m)
     s = SystemT()
     s.kind = KIND[system.kind]
     s.n, s.m, s.nsub, s.dt = system.n, system.m, system.nsub, system.dt
@@ -237,6 +246,17 @@ class Context:
     def dev(self) -> torch.device:
         return torch.device("cuda", self.device)
 
+    def set_user_field(self, body: str, n: int, m: int) -> None:
+        """gis_set_user_field: compiles the field body for this context's
+        device (kind GIS_SYS_USER)."""
+        _check(lib().gis_set_user_field(self.handle, body.encode(), n, m))
+        self._field = (body, n, m)
+
+    def use_field(self, body: str, n: int, m: int) -> None:
+        """Installs the field unless it is the one installed already."""
+        if getattr(self, "_field", None) != (body, n, m):
+            self.set_user_field(body, n, m)
+
     def get_tuning(self) -> dict:
         t = TuningT()
         _check(lib().gis_get_tuning(self.handle, ctypes.byref(t)))
@@ -305,7 +325,7 @@ def build_graph(ctx: Context, system: W.System, grid: W.Grid, u, level: torch.Te
     row_ptr = torch.empty(n_rows + 1, dtype=torch.int64, device=ctx.dev)
     out = torch.empty(max(n_rows, 1), dtype=torch.uint8, device=ctx.dev)
     cap = int(cap_edges if cap_edges is not None else max(16, 12 * n_rows))
-    st, gt, ct = system_t(system), grid_t(grid), cells_t(level, idx)
+    st, gt, ct = system_t(system, ctx), grid_t(grid), cells_t(level, idx)
     for attempt in range(2):
         col = torch.empty(max(cap, 1), dtype=torch.int32, device=ctx.dev)
         g = GraphT()
@@ -391,6 +411,12 @@ def bisect(ctx: Context, grid: W.Grid, level: torch.Tensor, idx: torch.Tensor,
     return W.Grid(tuple(go.n0[: grid.n]), grid.lo, grid.hi), lv[:n], ix[:n]
 
 
+def check_user_field(body: str, n: int, m: int) -> None:
+    """Compiles a field body for gfx950 without a device (gis_set_user_field
+    with no context); raises GisError with the compiler's messages."""
+    _check(lib().gis_set_user_field(None, body.encode(), n, m))
+
+
 def exp(x: torch.Tensor, stream=None) -> torch.Tensor:
     """gis_exp: the library's FP64 exponential (the CSTR field's) on a
     device float64 tensor, elementwise."""
@@ -407,7 +433,7 @@ def images(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, samples:
     K = int(du.shape[0])
     S = W.sample_count(samples, grid.n)
     out = torch.empty((int(level.shape[0]) * K, S, grid.n), dtype=torch.float64, device=ctx.dev)
-    st, gt, ct = system_t(system), grid_t(grid), cells_t(level, idx)
+    st, gt, ct = system_t(system, ctx), grid_t(grid), cells_t(level, idx)
     _check(lib().gis_images(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du), K,
                             ctypes.byref(ct), SAMPLES[samples], PRECISION[precision], _ptr(out),
                             _stream_ptr(stream)))
@@ -418,7 +444,7 @@ def calibrate_band(ctx: Context, system: W.System, grid: W.Grid, u, level, idx, 
                    safety: float = 8.0, floor_rel: float = 1e-5, stream=None) -> np.ndarray:
     du = to_device_u(ctx, u)
     band = (F64 * 4)()
-    st, gt, ct = system_t(system), grid_t(grid), cells_t(level, idx)
+    st, gt, ct = system_t(system, ctx), grid_t(grid), cells_t(level, idx)
     _check(lib().gis_calibrate_band(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du),
                                     int(du.shape[0]), ctypes.byref(ct), SAMPLES[samples], safety,
                                     floor_rel, band, _stream_ptr(stream)))
@@ -508,7 +534,7 @@ def solve(ctx: Context, system: W.System, grid: W.Grid, u, rounds: int, opts: Op
           stream=None) -> Solution:
     du = to_device_u(ctx, u)
     h = P()
-    st, gt = system_t(system), grid_t(grid)
+    st, gt = system_t(system, ctx), grid_t(grid)
     _check(lib().gis_solve(ctx.handle, ctypes.byref(st), ctypes.byref(gt), _ptr(du),
                            int(du.shape[0]), rounds, ctypes.byref(opts), ctypes.byref(h),
                            _stream_ptr(stream)))
@@ -519,7 +545,7 @@ def autotune(ctx: Context, wl: W.Workload, repeats: int = 3, stream=None, **opt_
     """Chooses ctx's schedule parameters for the workload by timing whole solves
     (gis_autotune); returns (parameters, median ms per solve)."""
     du = to_device_u(ctx, wl.u)
-    st, gt = system_t(wl.system), grid_t(wl.grid)
+    st, gt = system_t(wl.system, ctx), grid_t(wl.grid)
     opts = workload_opts(wl, **opt_over)
     best = TuningT()
     ms = F64(0.0)
@@ -536,7 +562,7 @@ class Solver:
     def __init__(self, ctx: Context, wl: W.Workload, stream=None, **opt_over):
         self.ctx = ctx
         self.du = to_device_u(ctx, wl.u)
-        self.st, self.gt = system_t(wl.system), grid_t(wl.grid)
+        self.st, self.gt = system_t(wl.system, ctx), grid_t(wl.grid)
         self.opts = workload_opts(wl, **opt_over)
         self.rounds = wl.rounds
         self.sp = _stream_ptr(stream)
@@ -564,7 +590,7 @@ def solve_batch(ctx: Context, workloads, stream=None, **opt_over) -> list:
     dus = [to_device_u(ctx, w.u) for w in wls]
     jobs = (JobT * len(wls))()
     for i, w in enumerate(wls):
-        jobs[i].sys = system_t(w.system)
+        jobs[i].sys = system_t(w.system, ctx)
         jobs[i].grid = grid_t(w.grid)
         jobs[i].d_u = _ptr(dus[i])
     outs = (P * len(wls))()

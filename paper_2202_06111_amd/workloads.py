@@ -24,6 +24,7 @@ VDP = "vdp"
 LORENZ = "lorenz"
 VDP2 = "vdp2"
 CSTR = "cstr"
+USER = "user"       # the caller's own field, given as code (see user())
 
 LATTICE3 = "lattice3"            # 3^n points: offsets {0, 1/2, 1} of the cell width
 CORNERS_CENTER = "corners_center"  # 2^n corners + the centre
@@ -41,6 +42,10 @@ class System:
     dt: float
     nsub: int
     params: Tuple[float, ...]
+    # kind "user": the body of g, setting dx[0..n-1] from x, u and p (type R,
+    # fmaT and expT available); the library compiles it for the device and
+    # the oracle compiles it for the host
+    source: str = ""
 
     def param_array(self) -> np.ndarray:
         p = np.zeros(32, dtype=np.float64)
@@ -119,6 +124,17 @@ def cstr(dt: float = 0.1, nsub: int = 1, q: float = 100.0, V: float = 100.0,
     return System(CSTR, 2, 1, float(dt), int(nsub),
                   (q / V, float(cAf), float(Tf), float(E_over_R), float(k0),
                    minus_dH / (rho * cp), UA / (V * rho * cp)))
+
+
+def user(body: str, n: int, m: int, dt: float, nsub: int,
+         params: Sequence[float] = ()) -> System:
+    """x+ = RK4^nsub(x, u) of the field whose code is `body` (Eq. 1 with the
+    caller's f): C statements setting dx[0..n-1] from x[0..n-1], u[0..m-1]
+    and p[0..23], all of type R; fmaT(a, b, c) and expT(v) may be called.
+    Written in the common subset of C and C++ (casts as (R)v), it compiles
+    both for the device and for the CPU oracle."""
+    assert 1 <= n <= 4 and 1 <= m <= 2 and len(params) <= 24
+    return System(USER, n, m, float(dt), int(nsub), tuple(float(v) for v in params), body)
 
 
 def linear(A: Sequence[Sequence[float]], B: Sequence[Sequence[float]], dt: float,
