@@ -84,26 +84,28 @@ def parse():
 
 
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "traffic_k_build.md")
-KERNEL_SOURCES = ("k_build.hip", "dynamics.h", "gis_internal.h")
+KERNEL_SOURCES = ("k_build_dev.h", "k_build.hip", "dynamics.h", "gis_internal.h")
+ANALYSIS_TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "traffic_analysis.md")
+ANALYSIS_SOURCES = ("k_prune.hip", "k_frontier.hip", "gis_internal.h")
 
 
-def kernel_sources_digest():
+def kernel_sources_digest(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2202_06111_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload, precision):
-    """HBM bytes per build-kernel launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), provided
-    it was taken for this workload and precision with the current kernel
-    sources; None otherwise."""
-    if not os.path.exists(TRAFFIC_TABLE):
+def recorded_traffic(workload, precision, table=TRAFFIC_TABLE, sources=KERNEL_SOURCES):
+    """HBM bytes per build-kernel launch (or per solve, for the analysis
+    table) from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy of known size), provided it was taken for this
+    workload and precision with the current kernel sources; None otherwise."""
+    if not os.path.exists(table):
         return None
-    digest = kernel_sources_digest()
-    with open(TRAFFIC_TABLE) as fh:
+    digest = kernel_sources_digest(sources)
+    with open(table) as fh:
         for line in fh:
             cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
             if len(cells) >= 8 and cells[0] == workload and cells[1] == precision and cells[2] == digest:
@@ -258,7 +260,7 @@ def build_roofline(W, wl, infos, precision):
             "flops_per_row": flops_row}
 
 
-def analysis_roofline(wl, phase_infos):
+def analysis_roofline(wl, phase_infos, precision):
     """The analysis (every launch from the end of the build to the start of
     the subdivision): its algorithmic bytes -- one read of the targets (4 B
     per edge) and row offsets (8 B per row), one write of the kept flags and
@@ -270,7 +272,10 @@ def analysis_roofline(wl, phase_infos):
     ms = sum(r["ms_prune"] for inf in phase_infos for r in inf["rounds"])
     achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": recorded_traffic(wl.name, precision, ANALYSIS_TRAFFIC_TABLE,
+                                        ANALYSIS_SOURCES),
+            "traffic_per": "solve",
             "kernel": f"graph analysis ({wl.analysis}), all of its launches",
             "bytes_per_solve": byts / max(len(phase_infos), 1),
             "ms_per_solve": ms / max(len(phase_infos), 1)}
@@ -357,7 +362,7 @@ def main():
     rows = sum(r["n_rows"] for inf in infos for r in inf["rounds"])
     last = infos[-1]
     broof = build_roofline(W, wl, infos, precision)
-    aroof = analysis_roofline(wl, phase_infos)
+    aroof = analysis_roofline(wl, phase_infos, precision)
     res = {
         "metric": "cell x input images/s in graph build (whole solve)",
         "value": rows / el,
