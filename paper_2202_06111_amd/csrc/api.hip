@@ -144,7 +144,10 @@ struct gis_ctx {
   DevBuf removed, rbits, rowbits, rptr, rrow, rsrc, rmask, rcur, rowstate, good, front, wit;
   DevBuf bnd, sel, scc;
   Pinned<unsigned long long> h_scc;  // largest-component search: per-job keys and counts
-  DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask;
+  DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask, first;
+  // the first-target array of the graph being analysed (written by the
+  // solve's build), or null (graphs from the caller)
+  const int32_t* cur_first = nullptr;
   KernelTimer timer;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::unique_ptr<UserField> user;  // field of systems of kind GIS_SYS_USER
@@ -566,6 +569,7 @@ struct Graph {
   int64_t n_edges, n_out, n_recheck;
   float ms_image, ms_recheck;   // with opts.timing
   bool timed;
+  int32_t* first = nullptr;     // [rows] first target of each row, or null
 };
 
 BuildArgs build_args(gis_ctx* ctx, const Batch& B, const uint8_t* level, const int32_t* idx,
@@ -630,6 +634,7 @@ int32_t enqueue_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_
   a.out = gr.out;
   a.row_ptr = gr.row_ptr;
   a.col = gr.col;
+  a.first = gr.first;
   a.cap_edges = gr.cap_edges;
   a.ticket = (uint32_t*)ctx->lookback.ptr;
   a.lb = (uint64_t*)ctx->lookback.ptr + 16;
@@ -695,6 +700,7 @@ PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   w.rbits_cells = (int64_t)(ctx->rbits.bytes / 4) * 32;
   w.rowbits = (uint64_t*)ctx->rowbits.ptr;
   w.rowbits_rows = (int64_t)(ctx->rowbits.bytes / 8) * 64;
+  w.first = ctx->cur_first;
   w.last = &dcnt(ctx)->sweep_last;
   w.rptr = (int64_t*)ctx->rptr.ptr;
   w.rrow = (int32_t*)ctx->rrow.ptr;
@@ -873,15 +879,15 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   const PruneWork w = prune_work(ctx, cap_edges, d_total);
   // the sweeps and the final pass: one launch sequence, replayed as a graph
   struct Key {
-    const void* p[16];
+    const void* p[17];
     int64_t n_cells, cap_edges;
     int32_t K, analysis, first, sweep_blocks, n_jobs, clear;
   } key;
   memset(&key, 0, sizeof key);
-  const void* ptrs[16] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
+  const void* ptrs[17] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
                           dcnt(ctx)->n_kept, B ? B->d_jobs : nullptr, B ? B->d_stats : nullptr,
                           level, idx, wit ? (const void*)w.cstart : nullptr, w.rbits,
-                          w.rowbits};
+                          w.rowbits, w.first};
   memcpy(key.p, ptrs, sizeof ptrs);
   key.n_cells = n_cells;
   key.cap_edges = cap_edges;
@@ -1227,6 +1233,11 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   const int nj = (int)specs.size();
   gis_opts o = *opts;
   const int n = specs[0].grid.n;
+  // the rounds' graphs carry first-target arrays; no later call may take them
+  struct ResetFirst {
+    gis_ctx* c;
+    ~ResetFirst() { c->cur_first = nullptr; }
+  } reset_first{ctx};
   const int32_t W = (K + 63) / 64;
   int32_t rc;
   for (int j = 0; j < nj; ++j) out[j] = nullptr;
@@ -1382,7 +1393,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
         (rc = ensure(ctx->mask, (size_t)n_cells * W * 8 + 16)) ||
         (rc = ensure(ctx->removed, (size_t)n_cells + 16)) ||
         (rc = ensure(ctx->rbits, (size_t)(n_cells + 31) / 32 * 4 + 16)) ||
-        (rc = ensure(ctx->rowbits, (size_t)(n_rows + 63) / 64 * 8 + 16)))
+        (rc = ensure(ctx->rowbits, (size_t)(n_rows + 63) / 64 * 8 + 16)) ||
+        (rc = ensure(ctx->first, (size_t)n_rows * 4 + 16)))
       return fail_all(rc);
     // one launch clears the counters and job stats, the index states (NONE
     // is 0) and the analysis' removed flags
@@ -1406,7 +1418,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
                   (o.neighbours > 0 && (rc = ensure(ctx->sel, (size_t)n_cells + 16)))))
       return fail_all(rc);
     Graph gr{(int64_t*)ctx->row_ptr.ptr, (int32_t*)ctx->col.ptr, (uint8_t*)ctx->out.ptr,
-             (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f, false};
+             (int64_t)(ctx->col.bytes / 4), 0, 0, 0, 0.f, 0.f, false, (int32_t*)ctx->first.ptr};
+    ctx->cur_first = gr.first;
     uint8_t* kept = (uint8_t*)ctx->kept.ptr;
     uint64_t* mask = (uint64_t*)ctx->mask.ptr;
     auto analyse_and_refine = [&]() -> int32_t {
@@ -1654,7 +1667,7 @@ void gis_ctx_destroy(gis_ctx* c) {
                     &c->ixA,
                     &c->lvB, &c->ixB,
                     &c->row_ptr, &c->col, &c->out, &c->kept, &c->mask, &c->rbits, &c->rowbits,
-                    &c->wit, &c->sel};
+                    &c->wit, &c->sel, &c->first};
   for (DevBuf* b : bufs) release(*b);
   c->user.reset();
   for (auto& kv : c->graphs.map)
@@ -1741,6 +1754,7 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
   if (analysis != GIS_ANALYSIS_CONTROLLED && analysis != GIS_ANALYSIS_NONLEAVING &&
       analysis != GIS_ANALYSIS_LARGEST_SCC)
     return inval("unknown analysis");
+  ctx->cur_first = nullptr;  // the caller's graph has no first-target array
   if (n_cells < 0 || K < 1) return inval("invalid sizes");
   if (graph->n_rows != n_cells * K) return inval("graph rows != n_cells * K");
   if (n_cells * (int64_t)K >= ((int64_t)1 << 31)) {

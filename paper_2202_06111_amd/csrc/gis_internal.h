@@ -242,6 +242,7 @@ struct BuildArgs {
   uint8_t* out;           // [rows] OUT flags
   int64_t* row_ptr;       // [rows + 1]
   int32_t* col;           // [cap_edges]
+  int32_t* first;         // [rows] each row's first target (-1: none), or null
   int64_t cap_edges;
   uint64_t* lb;           // [n_blocks] look-back words (tagged with `epoch`)
   uint32_t* ticket;       // block ticket: 0 before the launch, reset to 0 by the last block

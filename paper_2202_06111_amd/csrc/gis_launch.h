@@ -50,6 +50,7 @@ struct PruneWork {
   uint32_t* rbits;     // removed flags packed 32 to a word for the final pass, or null
   int64_t rbits_cells; // cells rbits has room for (the final pass packs only up to that)
   uint64_t* rowbits;   // good-row flags of the final pass, 64 rows a word, or null
+  const int32_t* first;  // [rows] each row's first target (-1: none) from the build, or null
   int64_t rowbits_rows;  // rows rowbits has room for
   int32_t* front;      // [2 * n_cells] the two frontier lists
   int32_t* fcount;     // [3] rotating list lengths

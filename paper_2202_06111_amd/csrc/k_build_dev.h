@@ -270,7 +270,7 @@ __device__ __forceinline__ bool band_safe(const Job& J, const CoverIndex& ci, co
 constexpr int64_t kLo32 = 0xffffffffll;
 
 // Edge count of a row; *hole is set when a hole of the covering meets the
-// interior range.  Per run of index slots the prefix counts give the leaves
+// interior range, *first to the local id of its first target (when it has one).  Per run of index slots the prefix counts give the leaves
 // (ids consecutive from the first) and, on rows of the interior box, the holes
 // between the interior columns.  The first kCache runs that hold leaves are
 // kept as (first local id, length) pairs with stride kRowBlock from `cache`
@@ -278,13 +278,17 @@ constexpr int64_t kLo32 = 0xffffffffll;
 // again for rows with no more runs than that.
 template <int N, bool UNI>
 __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ranges<N>& r,
-                                                 int2* cache, bool* hole) {
+                                                 int2* cache, bool* hole, int32_t* first) {
   *hole = false;
   if (r.empty) return 0;
   if (UNI || ci.uniform) {
-    int32_t c = 1;
+    int32_t c = 1, lin = 0;
 #pragma unroll
-    for (int d = 0; d < N; ++d) c *= r.hi[d] - r.lo[d] + 1;
+    for (int d = 0; d < N; ++d) {
+      c *= r.hi[d] - r.lo[d] + 1;
+      lin = lin * ci.dims[0][d] + r.lo[d];
+    }
+    *first = lin;
     return c;
   }
   int32_t c = 0, nr = 0;
@@ -293,6 +297,7 @@ __device__ __forceinline__ int32_t count_targets(const CoverIndex& ci, const Ran
                [&](int64_t p0, int64_t p1, bool inner, int64_t q0, int64_t q1) {
                  const int32_t nl = (int32_t)((p1 & kLo32) - (p0 & kLo32));
                  if (nl > 0) {
+                   if (nr == 0) *first = (int32_t)((p0 & kLo32) - ci.pbase);
                    if (nr < kCache)
                      cache[nr * kRowBlock] = make_int2((int32_t)((p0 & kLo32) - ci.pbase), nl);
                    ++nr;
@@ -414,7 +419,7 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   const bool live = lr < J.n_cells * a.K;
   const int64_t g = J.cell_off * a.K + lr;
   int32_t lo[N], hi[N];
-  int32_t c = 0;
+  int32_t c = 0, first = 0;
 #pragma unroll
   for (int d = 0; d < N; ++d) lo[d] = hi[d] = 0;
   if (live) {
@@ -438,7 +443,7 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
     if (finite) {
       const Ranges<N> rr = ranges_of<N>(J.grid, ci, bl, bh);
       bool hole;
-      c = count_targets<N, UNI>(ci, rr, UNI ? cache : cache + tid, &hole);
+      c = count_targets<N, UNI>(ci, rr, UNI ? cache : cache + tid, &hole, &first);
       out = rr.outx || hole;
       if (a.fast_out && out) c = 0;
 #pragma unroll
@@ -524,8 +529,9 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   __syncthreads();
   const int64_t prefix = s_prefix;
 
-  // ---- 5: row offsets and target ids
+  // ---- 5: row offsets, first targets and target ids
   if (live) a.row_ptr[g] = prefix + off;
+  if (live && a.first) a.first[g] = c > 0 ? (int32_t)J.cell_off + first : -1;
   if (live && g == a.total_rows - 1) a.row_ptr[a.total_rows] = prefix + off + c;
   if (prefix + T > a.cap_edges) return;  // capacity miss: col is not written
   const int32_t id0 = (int32_t)J.cell_off;

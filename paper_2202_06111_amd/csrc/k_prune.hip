@@ -606,6 +606,10 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
   const int t = threadIdx.x;
   if (t == 0) s_job = -1;
   unsigned long long mine = 0;
+  // thread 0: kept cells of job kjob counted by this block so far (flushed to
+  // the job's statistics when the job changes and at the end)
+  unsigned long long kcnt = 0;
+  int32_t kjob = -1;
   const int64_t stride = (int64_t)gridDim.x * cpb;
   for (int64_t g0 = (int64_t)blockIdx.x * cpb; g0 < n_cells; g0 += stride) {
     const int64_t c = g0 + t / K;
@@ -668,9 +672,16 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
       }
     }
     __syncthreads();
-    if (t == 0 && stats && one_job && grp_kept)
-      atomicAdd(&stats[jfirst].n_kept, (unsigned long long)grp_kept);
+    if (t == 0 && stats && one_job && grp_kept) {
+      if (jfirst != kjob) {
+        if (kcnt) atomicAdd(&stats[kjob].n_kept, kcnt);
+        kjob = jfirst;
+        kcnt = 0;
+      }
+      kcnt += grp_kept;
+    }
   }
+  if (t == 0 && kcnt) atomicAdd(&stats[kjob].n_kept, kcnt);
   for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
   if ((t & 63) == 0 && mine) atomicAdd(nkept, mine);
 }
@@ -684,15 +695,20 @@ __global__ __launch_bounds__(256) void k_prune_final(const int64_t* row_ptr, con
 // grouped by cell, so no block synchronisation or staging is needed, and
 // each wave keeps kRowsIlp rows' loads in flight: the first target of most
 // rows decides them (non-leaving analysis), so their offsets, first targets
-// and flags are fetched for all of them before any is decided.
+// and flags are fetched for all of them before any is decided.  With the
+// build's first-target array (`first`, non-leaving analysis) a row's first
+// target is one coalesced 4-byte load: the offsets and `col` are read only
+// for the rows whose first target was removed (reading `col[row_ptr[r]]`
+// instead touches every line of `col`, a row being a few dozen bytes of it).
 constexpr int kRowsIlp = 4;
 
 template <int MODE, typename Flags>
 __global__ __launch_bounds__(256) void k_row_good(const int64_t* row_ptr, const int32_t* col,
-                                                  const uint8_t* out, int64_t n_rows,
-                                                  Flags removed, uint64_t* rowbits,
-                                                  const int64_t* d_total, int64_t cap_edges,
-                                                  const int32_t* last, int32_t sweeps) {
+                                                  const uint8_t* out, const int32_t* first,
+                                                  int64_t n_rows, int32_t K, Flags removed,
+                                                  uint64_t* rowbits, const int64_t* d_total,
+                                                  int64_t cap_edges, const int32_t* last,
+                                                  int32_t sweeps) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
   if (sweeps > 0 && *last >= sweeps) return;     // the sweeps have not converged
   const int lane = threadIdx.x & 63;
@@ -700,12 +716,40 @@ __global__ __launch_bounds__(256) void k_row_good(const int64_t* row_ptr, const 
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t w0 = wave * kRowsIlp; w0 < words; w0 += waves * kRowsIlp) {
-    int64_t r[kRowsIlp], a[kRowsIlp], b[kRowsIlp];
+    int64_t r[kRowsIlp];
     bool good[kRowsIlp], done[kRowsIlp];
+    if (MODE != GIS_ANALYSIS_CONTROLLED && first) {
+      int32_t j[kRowsIlp];
+#pragma unroll
+      for (int q = 0; q < kRowsIlp; ++q) {
+        r[q] = (w0 + q) * 64 + lane;
+        // rows of removed cells need no test (their cells' masks are 0)
+        const bool in = r[q] < n_rows && !removed[r[q] / K];
+        j[q] = in ? first[r[q]] : -1;
+        good[q] = false;
+        done[q] = !in || j[q] < 0;  // a row with no target is not good
+      }
+#pragma unroll
+      for (int q = 0; q < kRowsIlp; ++q)
+        if (!done[q] && !removed[j[q]]) {
+          good[q] = true;
+          done[q] = true;
+        }
+#pragma unroll
+      for (int q = 0; q < kRowsIlp; ++q)
+        if (!done[q]) good[q] = row_good<MODE>(row_ptr, col, out, removed, r[q]);
+#pragma unroll
+      for (int q = 0; q < kRowsIlp; ++q) {
+        const uint64_t m = __ballot(good[q]);
+        if (lane == 0 && w0 + q < words) rowbits[w0 + q] = m;
+      }
+      continue;
+    }
+    int64_t a[kRowsIlp], b[kRowsIlp];
 #pragma unroll
     for (int q = 0; q < kRowsIlp; ++q) {
       r[q] = (w0 + q) * 64 + lane;
-      const bool in = r[q] < n_rows;
+      const bool in = r[q] < n_rows && !removed[r[q] / K];
       a[q] = in ? row_ptr[r[q]] : 0;
       b[q] = in ? row_ptr[r[q] + 1] : 0;
       good[q] = false;
@@ -746,11 +790,18 @@ __global__ __launch_bounds__(256) void k_cell_masks(int64_t n_cells, int32_t K, 
   if (d_total && *d_total > cap_edges) return;
   if (sweeps > 0 && *last >= sweeps) return;
   const int lane = threadIdx.x & 63;
+  // kept counts are accumulated over the grid-stride loop and added once per
+  // wave at the end (an atomic per wave and iteration on the same two
+  // counters serialised in L2: a millisecond per 10^7 cells); the wave's
+  // cells come in increasing order, so its jobs do too
+  unsigned long long mine = 0, jcnt = 0;
+  int32_t wjob = -1;
   for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < n_cells;
        c0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = c0 + threadIdx.x;
     const bool live = c < n_cells;
     const bool k = live && !removed[c];
+    mine += k ? 1 : 0;
     if (live) {
       kept[c] = k ? 1 : 0;
       for (int w = 0; w < W; ++w) {
@@ -776,23 +827,29 @@ __global__ __launch_bounds__(256) void k_cell_masks(int64_t n_cells, int32_t K, 
         }
       }
     }
-    // kept counts: one atomic per wave when the wave's cells lie in one job
+    // per-job kept counts: the wave's count joins its running count when
+    // its cells lie in one job, which is flushed when the job changes
     const uint64_t bal = __ballot(k);
-    if (lane == 0 && bal) {
-      atomicAdd(nkept, (unsigned long long)__popcll(bal));
-      if (stats) {
-        const int64_t wc = c0 + (threadIdx.x & ~63);
-        const int64_t wl = wc + 63 < n_cells ? wc + 63 : n_cells - 1;
-        const int32_t j0 = job_of_cell(jobs, n_jobs, wc);
-        if (job_of_cell(jobs, n_jobs, wl) == j0) {
-          atomicAdd(&stats[j0].n_kept, (unsigned long long)__popcll(bal));
-        } else {
-          for (uint64_t m = bal; m; m &= m - 1)
-            atomicAdd(&stats[job_of_cell(jobs, n_jobs, wc + __builtin_ctzll(m))].n_kept, 1ull);
+    if (stats && lane == 0 && bal) {
+      const int64_t wc = c0 + (threadIdx.x & ~63);
+      const int64_t wl = wc + 63 < n_cells ? wc + 63 : n_cells - 1;
+      const int32_t j0 = job_of_cell(jobs, n_jobs, wc);
+      if (job_of_cell(jobs, n_jobs, wl) == j0) {
+        if (j0 != wjob) {
+          if (jcnt) atomicAdd(&stats[wjob].n_kept, jcnt);
+          wjob = j0;
+          jcnt = 0;
         }
+        jcnt += (unsigned long long)__popcll(bal);
+      } else {
+        for (uint64_t m = bal; m; m &= m - 1)
+          atomicAdd(&stats[job_of_cell(jobs, n_jobs, wc + __builtin_ctzll(m))].n_kept, 1ull);
       }
     }
   }
+  if (stats && lane == 0 && jcnt) atomicAdd(&stats[wjob].n_kept, jcnt);
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
+  if (lane == 0 && mine) atomicAdd(nkept, mine);
 }
 
 // The same for K > 256 inputs: a thread per cell.
@@ -936,8 +993,8 @@ int32_t final_mode(const int64_t* row_ptr, const int32_t* col, const uint8_t* ou
     const int64_t waves = (words + kRowsIlp - 1) / kRowsIlp;
     const unsigned nb = (unsigned)((waves + 3) / 4 < 8192 ? (waves + 3) / 4 : 8192);
     hipLaunchKernelGGL((k_row_good<MODE, BitFlags>), dim3(nb), dim3(256), 0, s, row_ptr, col, out,
-                       n_rows, bits, w.rowbits, w.d_total, w.cap_edges, (const int32_t*)w.last,
-                       sweeps);
+                       w.first, n_rows, K, bits, w.rowbits, w.d_total, w.cap_edges,
+                       (const int32_t*)w.last, sweeps);
     GIS_LAUNCH_CHECK("k_row_good");
     hipLaunchKernelGGL((k_cell_masks<BitFlags>), dim3(grid_for(n_cells)), dim3(256), 0, s, n_cells,
                        K, bits, (const uint64_t*)w.rowbits, kept, mask, W, d_nkept, w.d_total,
