@@ -277,7 +277,7 @@ int32_t gis_prune(gis_ctx* ctx, const gis_graph* graph, int64_t n_cells, int32_t
 /* gis_prune for callers that cannot allocate device memory (code under HIP
  * graph capture, serving loops, harnesses that forbid hipMalloc): the same
  * kept flags, masks and count as gis_prune, computed by sweeps only in a
- * static device workspace of about 42 MB per GPU, held until the process
+ * static device workspace of about 26 MiB per GPU, held until the process
  * ends; no context.  It runs on the current device, which must be the device
  * of `stream` and of the buffers.  Analysis GIS_ANALYSIS_CONTROLLED or
  * GIS_ANALYSIS_NONLEAVING (GIS_E_INVAL otherwise), K <= 256 (GIS_E_INVAL),

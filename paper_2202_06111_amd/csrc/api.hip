@@ -145,8 +145,8 @@ struct gis_ctx {
   DevBuf bnd, sel, scc;
   Pinned<unsigned long long> h_scc;  // largest-component search: per-job keys and counts
   DevBuf lvA, ixA, lvB, ixB, row_ptr, col, out, kept, mask, first;
-  // the first-target array of the graph being analysed (written by the
-  // solve's build), or null (graphs from the caller)
+  // the per-row first targets of the graph being analysed
+  // (written by the solve's build), or null (graphs from the caller)
   const int32_t* cur_first = nullptr;
   KernelTimer timer;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -714,10 +714,9 @@ PruneWork prune_work(gis_ctx* ctx, int64_t cap_edges, const int64_t* d_total) {
   w.badmask = (uint64_t*)ctx->rowstate.ptr;
   w.front = (int32_t*)ctx->front.ptr;
   w.fcount = dcnt(ctx)->fcount;
-  // witness state: span starts [n + 1], witness positions [n], targets [n]
-  // (sized by ensure_witness for the current cell count)
-  w.cstart = (int64_t*)ctx->wit.ptr;
-  w.wpos = w.cstart ? w.cstart + ctx->wit_cells + 1 : nullptr;
+  // witness state: positions [n], targets [n] (sized by ensure_witness for
+  // the current cell count)
+  w.wpos = (int64_t*)ctx->wit.ptr;
   w.wtgt = w.wpos ? (int32_t*)(w.wpos + ctx->wit_cells) : nullptr;
   w.scan_tmp = ctx->scan_tmp.ptr;
   w.sweep_blocks = ctx->tune.sweep_blocks;
@@ -793,10 +792,10 @@ bool witness_sweeps(const gis_ctx* ctx, int32_t analysis) {
   return analysis == GIS_ANALYSIS_NONLEAVING && ctx->tune.wit_sweeps > 0;
 }
 
-// Witness arrays for n_cells cells: span starts (n + 1), positions (n), targets (n).
+// Witness arrays for n_cells cells: positions (n), targets (n).
 int32_t ensure_witness(gis_ctx* ctx, int64_t n_cells) {
   int32_t rc;
-  if ((rc = ensure(ctx->wit, (size_t)(2 * n_cells + 1) * 8 + (size_t)n_cells * 4 + 64))) return rc;
+  if ((rc = ensure(ctx->wit, (size_t)n_cells * 8 + (size_t)n_cells * 4 + 64))) return rc;
   ctx->wit_cells = n_cells;
   return GIS_OK;
 }
@@ -886,7 +885,7 @@ int32_t enqueue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col, 
   memset(&key, 0, sizeof key);
   const void* ptrs[17] = {row_ptr, col, out, w.removed, w.last, d_total, kept, mask,
                           dcnt(ctx)->n_kept, B ? B->d_jobs : nullptr, B ? B->d_stats : nullptr,
-                          level, idx, wit ? (const void*)w.cstart : nullptr, w.rbits,
+                          level, idx, wit ? (const void*)w.wpos : nullptr, w.rbits,
                           w.rowbits, w.first};
   memcpy(key.p, ptrs, sizeof ptrs);
   key.n_cells = n_cells;
@@ -1236,7 +1235,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   // the rounds' graphs carry first-target arrays; no later call may take them
   struct ResetFirst {
     gis_ctx* c;
-    ~ResetFirst() { c->cur_first = nullptr; }
+    ~ResetFirst() {
+      c->cur_first = nullptr;
+    }
   } reset_first{ctx};
   const int32_t W = (K + 63) / 64;
   int32_t rc;
@@ -1303,8 +1304,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     if ((e = fill_u32((uint32_t*)me, 0u, (int64_t)2 * kMaxDim * 2 * nj, s))) return e;
     BuildArgs a = build_args(ctx, B, lv, ix, &o);
     // every row of small coverings, every stride-th block of 256 rows of
-    // larger ones (about 2^20 rows)
-    const int64_t stride = (B.total_cells * K) >> 20;
+    // larger ones (about 2^16 rows: per round, 2^20 cost more than the
+    // build of the standard-algorithm Van der Pol workload)
+    const int64_t stride = (B.total_cells * K) >> 16;
     if ((e = launch_calibrate(a, me, stride, s))) return e;
     if (check_band && stride > 1 && (e = launch_calibrate(a, me + (size_t)kMaxDim * nj, 1, s))) return e;
     if (need_band && (e = launch_band(B.d_jobs, nj, n, me, band_floor_rel, s))) return e;
@@ -1318,7 +1320,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
   auto take_bands = [&](int r, std::vector<gis_solve_info>& info) -> int32_t {
     if (!band_pending) return GIS_OK;
     band_pending = false;
-    const int64_t stride = (B.total_cells * K) >> 20;
+    const int64_t stride = (B.total_cells * K) >> 16;
     for (int j = 0; j < nj; ++j)
       for (int d = 0; d < n; ++d) {
         double e, ea;

@@ -44,8 +44,7 @@ struct PruneWork {
   uint64_t* rmask;     // [entries] input masks
   uint64_t* badmask;   // controlled: [n_cells] bad rows of each cell (same memory as rowstate)
   // nonleaving witness sweeps
-  int64_t* cstart;     // [n_cells + 1] first edge of each cell's rows (row_ptr[c * K])
-  int64_t* wpos;       // [n_cells] position of the cell's witness edge
+  int64_t* wpos;       // [n_cells] position of the cell's witness edge (-1: the span's first)
   int32_t* wtgt;       // [n_cells] its target
   uint32_t* rbits;     // removed flags packed 32 to a word for the final pass, or null
   int64_t rbits_cells; // cells rbits has room for (the final pass packs only up to that)
@@ -68,7 +67,7 @@ int32_t prune_sweeps(const int64_t* row_ptr, const int32_t* col, const uint8_t* 
                      int64_t n_cells, int32_t K, int32_t analysis, const PruneWork& w,
                      int32_t first, int32_t count, hipStream_t s);
 // nonleaving: witness sweeps first .. first+count-1; sweep 0 must come first
-// in an analysis (it sets cstart and the first witnesses).  Converged when
+// in an analysis (it sets the first witnesses).  Converged when
 // *last < first+count.
 int32_t prune_wsweeps(const int64_t* row_ptr, const int32_t* col, int64_t n_cells, int32_t K,
                       const PruneWork& w, int32_t first, int32_t count, hipStream_t s);

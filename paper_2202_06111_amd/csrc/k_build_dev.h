@@ -57,10 +57,10 @@ __device__ __forceinline__ uint32_t lb_status(uint64_t w, uint32_t epoch) {
 }
 
 // ------------------------------------------------------------------ cover logic
-// Position of v on the finest grid, clamped to [-2, N + 2] (the clamp keeps
-// the integer conversion defined and never changes a clamped range).
-__device__ __forceinline__ double grid_pos(double v, double lo, double hs, int32_t N) {
-  double t = (v - lo) / hs;
+// Position t = (v - lo) / hs of v on the finest grid, clamped to [-2, N + 2]
+// (the clamp keeps the integer conversion defined and never changes a
+// clamped range).
+__device__ __forceinline__ double clamp_pos(double t, int32_t N) {
   t = t < -2.0 ? -2.0 : t;
   t = t > (double)N + 2.0 ? (double)N + 2.0 : t;
   return t;
@@ -83,8 +83,8 @@ __device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverInd
   for (int d = 0; d < N; ++d) {
     const int32_t Nd = ci.dims[L][d];
     const double hs = ldexp(g.w0[d], -L);
-    const double ta = grid_pos(bl[d], g.lo[d], hs, Nd);
-    const double tb = grid_pos(bh[d], g.lo[d], hs, Nd);
+    const double ta = clamp_pos((bl[d] - g.lo[d]) / hs, Nd);
+    const double tb = clamp_pos((bh[d] - g.lo[d]) / hs, Nd);
     int32_t rlo = (int32_t)ceil(ta) - 1, rhi = (int32_t)floor(tb);
     int32_t ilo = (int32_t)floor(ta), ihi = (int32_t)ceil(tb) - 1;
     rlo = rlo < 0 ? 0 : rlo;
@@ -181,12 +181,11 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
   }
 }
 
-// Bounding box of the sample images of local row lr of job J, in precision R.
+// Bounding box of the sample images of the row (local cell c, input j) of
+// job J, in precision R.
 template <int KIND, int N, typename R>
 __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const Rk4Consts<R>& kc,
-                                         int64_t lr, R* bl, R* bh) {
-  const int64_t c = lr / a.K;
-  const int32_t j = (int32_t)(lr - c * a.K);
+                                         int64_t c, int32_t j, R* bl, R* bh) {
   const int64_t gc = J.cell_off + c;
   const int level = a.level[gc];
   int32_t ci[N];
@@ -245,26 +244,126 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
 // the comparisons with lo and hi) is the same anywhere within band[d] of it.
 // Since |y32 - y64| <= band[d] holds for every sample image, and min/max are
 // 1-Lipschitz, the FP64 box extremes then lead to the same decisions.
+// epsr[d] = band[d] / hs_d, the band in finest cell widths, and invh[d] =
+// 1 / hs_d (the same for the whole block).  The positions are taken with the
+// reciprocal, not divided: they are within a few ulp of the cover step's
+// exact quotients, far inside the 1e-9 relative slack of the tolerances, so
+// a row found safe here is safe for the exact positions too.
 template <int N>
-__device__ __forceinline__ bool band_safe(const Job& J, const CoverIndex& ci, const float* fl,
-                                          const float* fh, double* dl, double* dh) {
+__device__ __forceinline__ bool band_safe(const Job& J, const double* epsr, const double* invh,
+                                          const float* fl, const float* fh) {
   bool safe = true;
-  const int L = ci.lmax;
 #pragma unroll
   for (int d = 0; d < N; ++d) {
-    dl[d] = (double)fl[d];
-    dh[d] = (double)fh[d];
-    const double hs = ldexp(J.grid.w0[d], -L);
-    const double eps = J.band[d];
-    const double ta = (dl[d] - J.grid.lo[d]) / hs;
-    const double tb = (dh[d] - J.grid.lo[d]) / hs;
-    const double tola = eps / hs + 1e-9 * (fabs(ta) + 1.0);
-    const double tolb = eps / hs + 1e-9 * (fabs(tb) + 1.0);
+    const double dl = (double)fl[d], dh = (double)fh[d];
+    const double ta = (dl - J.grid.lo[d]) * invh[d];
+    const double tb = (dh - J.grid.lo[d]) * invh[d];
+    const double tola = epsr[d] + 1e-9 * (fabs(ta) + 1.0);
+    const double tolb = epsr[d] + 1e-9 * (fabs(tb) + 1.0);
     safe &= fabs(ta - rint(ta)) > tola;
     safe &= fabs(tb - rint(tb)) > tolb;
-    safe &= fabs(dh[d] - J.grid.hi[d]) > eps;
+    safe &= fabs(dh - J.grid.hi[d]) > J.band[d];
   }
   return safe;
+}
+
+// FP64 image of sample q of local row lr (one RK4 trajectory).
+template <int KIND, int N>
+__device__ __forceinline__ void sample_image(const BuildArgs& a, const Job& J,
+                                             const Rk4Consts<double>& kc, int64_t lr, int q,
+                                             double* x) {
+  const int64_t c = (int64_t)((uint32_t)lr / (uint32_t)a.K);
+  const int32_t j = (int32_t)(lr - c * a.K);
+  const int64_t gc = J.cell_off + c;
+  const int level = a.level[gc];
+  int32_t ci[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
+  const int m = J.sys.m;
+  double u[2];
+  u[0] = J.u[(int64_t)j * m];
+  u[1] = m > 1 ? J.u[(int64_t)j * m + 1] : 0.0;
+  int k[N];
+  sample_offsets<N>(a.samples, q, k);
+  sample_point<N>(J.grid, level, ci, k, x);
+  rk4<KIND, N, double>(kc, m, J.sys.nsub, x, u);
+}
+
+// The FP64 redo of the rows of a wave whose FP32 box the band test could not
+// decide (lanes in `pend`), done by the whole wave: the S samples of a row
+// are spread over a group of G lanes (G the power of two >= S, at most 64;
+// 64 / G rows at a time), each lane images its samples, and the group's
+// min/max and finiteness are reduced across its lanes and handed to the
+// row's lane.  The same images and the same exact min/max as the row's own
+// sequential FP64 pass, for about a seventeenth of the wave's instructions
+// on a row of 17 samples: flagged rows are rare (a few per thousand), so a
+// wave rarely has more than one, and imaging it sample after sample kept
+// the other 63 lanes idle for a whole row's images.
+template <int KIND, int N>
+__device__ __forceinline__ void redo_rows_fp64(const BuildArgs& a, const Job& J, int64_t lr,
+                                               uint64_t pend, double* bl, double* bh,
+                                               bool& finite) {
+  const int lane = threadIdx.x & 63;
+  const int S = num_samples(a.samples, N);
+  const int G = S <= 8 ? 8 : S <= 16 ? 16 : S <= 32 ? 32 : 64;
+  const int R = 64 / G;  // rows per pass
+  const Rk4Consts<double> kc = make_consts<double>(J.sys);
+  const int grp = lane / G, q0 = lane % G;
+  while (pend) {  // wave-uniform
+    // this pass's rows: the R lowest pending lanes (-1: none)
+    int src = -1;
+    uint64_t p = pend;
+    for (int g = 0; g < R; ++g) {
+      const int f = p ? __builtin_ctzll(p) : -1;
+      if (g == grp) src = f;
+      if (p) p &= p - 1;
+    }
+    double lo[N], hi[N];
+    bool fin = true;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      lo[d] = __builtin_huge_val();
+      hi[d] = -__builtin_huge_val();
+    }
+    const int64_t rlr = __shfl(lr, src < 0 ? 0 : src, 64);
+    if (src >= 0) {
+      for (int q = q0; q < S; q += G) {
+        double x[N];
+        sample_image<KIND, N>(a, J, kc, rlr, q, x);
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+          fin &= isfinite(x[d]);
+          lo[d] = vmin(x[d], lo[d]);
+          hi[d] = vmax(x[d], hi[d]);
+        }
+      }
+    }
+    // reduce within each group of G lanes
+    for (int o = G >> 1; o > 0; o >>= 1) {
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        lo[d] = vmin(__shfl_xor(lo[d], o, 64), lo[d]);
+        hi[d] = vmax(__shfl_xor(hi[d], o, 64), hi[d]);
+      }
+      fin &= __shfl_xor((int)fin, o, 64) != 0;
+    }
+    // hand each group's result to its row's lane
+    for (int g = 0; g < R; ++g) {
+      const int f = __shfl(src, g * G, 64);  // the row group g imaged (wave-uniform)
+      if (f < 0) break;
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        const double vl = __shfl(lo[d], g * G, 64), vh = __shfl(hi[d], g * G, 64);
+        if (lane == f) {
+          bl[d] = vl;
+          bh[d] = vh;
+        }
+      }
+      const bool vf = __shfl((int)fin, g * G, 64) != 0;
+      if (lane == f) finite = vf;
+      pend &= ~(1ull << f);
+    }
+  }
 }
 
 constexpr int64_t kLo32 = 0xffffffffll;
@@ -392,12 +491,19 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
 // compiled in, which keeps the register count, and so the occupancy, of the
 // image loop higher).
 template <int KIND, int N, bool F32, bool UNI>
-__global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
+//
+// At least four waves per SIMD: the FP32 variant of four-dimensional fields
+// would otherwise take 140 VGPRs (three waves) for the registers of the
+// wave-wide FP64 redo; bounded at 128, the compiler spills about a hundred
+// bytes, on the rarely taken redo path.
+__global__ __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_build(
+    BuildArgs a) {
   __shared__ CoverIndex ci;
   __shared__ int32_t tile[UNI ? kTile : 1];
   __shared__ int2 cache[UNI ? 1 : kCache * kRowBlock];
   __shared__ int64_t wsum[kRowBlock / 64];
   __shared__ int64_t s_prefix;
+  __shared__ double s_epsr[F32 ? N : 1], s_invh[F32 ? N : 1];
   __shared__ uint32_t s_bid, s_out, s_rchk;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) {
@@ -413,31 +519,54 @@ __global__ __launch_bounds__(kRowBlock) void k_build(BuildArgs a) {
   const int64_t bid = s_bid;
   const int32_t jb = job_of_block(a.jobs, a.n_jobs, LK_ROWS, bid);
   const Job& J = a.jobs[jb];
+  if constexpr (F32) {
+    // the recheck band in finest cell widths, per dimension
+    if (tid < N) {
+      const double hs = ldexp(J.grid.w0[tid], -J.ci.lmax);
+      s_epsr[tid] = J.band[tid] / hs;
+      s_invh[tid] = 1.0 / hs;
+    }
+  }
   stage_index(&ci, &J.ci);
   // ---- 1-2: images, box, cover decision, count
   const int64_t lr = (bid - J.blk[LK_ROWS]) * kRowBlock + tid;
   const bool live = lr < J.n_cells * a.K;
   const int64_t g = J.cell_off * a.K + lr;
+  // the row's cell and input (a job has fewer than 2^31 rows: 32-bit division)
+  const int64_t lc = (int64_t)((uint32_t)lr / (uint32_t)a.K);
+  const int32_t lj = (int32_t)(lr - lc * a.K);
   int32_t lo[N], hi[N];
   int32_t c = 0, first = 0;
 #pragma unroll
   for (int d = 0; d < N; ++d) lo[d] = hi[d] = 0;
-  if (live) {
-    double bl[N], bh[N];
-    bool finite;
-    if constexpr (F32) {
+  double bl[N], bh[N];
+  bool finite = false;
+  if constexpr (F32) {
+    // FP32 images; the rows the band test cannot decide are redone in FP64
+    // by the whole wave (the FP32 box is kept meanwhile: half the registers)
+    float fl[N], fh[N];
+    if (live) {
       const Rk4Consts<float> kc = make_consts<float>(J.sys);
-      float fl[N], fh[N];
-      const bool fin32 = row_bbox<KIND, N, float>(a, J, kc, lr, fl, fh);
-      finite = fin32 && band_safe<N>(J, ci, fl, fh, bl, bh);
-      if (!finite) {
-        const Rk4Consts<double> kd = make_consts<double>(J.sys);
-        finite = row_bbox<KIND, N, double>(a, J, kd, lr, bl, bh);
-        atomicAdd(&s_rchk, 1u);
+      const bool fin32 = row_bbox<KIND, N, float>(a, J, kc, lc, lj, fl, fh);
+      finite = fin32 && band_safe<N>(J, s_epsr, s_invh, fl, fh);
+    }
+    const uint64_t pend = __ballot(live && !finite);
+    if (pend) {
+      redo_rows_fp64<KIND, N>(a, J, lr, pend, bl, bh, finite);
+      if (lane == 0) atomicAdd(&s_rchk, (uint32_t)__popcll(pend));
+    }
+    if (!((pend >> lane) & 1)) {
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        bl[d] = (double)fl[d];
+        bh[d] = (double)fh[d];
       }
-    } else {
+    }
+  }
+  if (live) {
+    if constexpr (!F32) {
       const Rk4Consts<double> kd = make_consts<double>(J.sys);
-      finite = row_bbox<KIND, N, double>(a, J, kd, lr, bl, bh);
+      finite = row_bbox<KIND, N, double>(a, J, kd, lc, lj, bl, bh);
     }
     bool out = true;
     if (finite) {

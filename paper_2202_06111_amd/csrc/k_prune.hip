@@ -269,18 +269,21 @@ __global__ __launch_bounds__(256) void k_sweep(const int64_t* row_ptr, const int
 // targets before it were removed when they were passed, and removal is
 // final -- and is removed when there is none.  Over a whole analysis each
 // cell's span is read at most once, plus one witness check per sweep, and no
-// reverse graph is built.  Sweep 0 (INIT) finds the first witnesses and
-// copies the cells' span starts out of row_ptr.
+// reverse graph is built.  Sweep 0 (INIT) finds the first witnesses.
 //
 // A block takes 256 consecutive cells (odd sweeps go through the tiles in
 // reverse order, so that removals propagate in place along both
 // directions): a thread per cell checks the witness, the cells that need a
 // new one are queued in LDS, and each wave then searches one queued cell's
 // span 64 edges at a time (coalesced loads, one ballot per 64 edges).
+//
+// A witness at the start of the cell's span is recorded as position -1, and
+// the span's bounds (row_ptr[c*K], row_ptr[(c+1)*K]) are read again only by
+// a cell whose witness died: no per-cell copy of the span starts is kept.
 template <bool INIT>
 __global__ __launch_bounds__(256) void k_wsweep(const int64_t* row_ptr, const int32_t* col,
-                                                int64_t n_cells, int32_t K, uint8_t* removed,
-                                                int64_t* cstart, int64_t* wpos, int32_t* wtgt,
+                                                int64_t n_cells, int32_t K,
+                                                uint8_t* removed, int64_t* wpos, int32_t* wtgt,
                                                 int32_t* last, int32_t s, const int64_t* d_total,
                                                 int64_t cap_edges) {
   if (d_total && *d_total > cap_edges) return;  // col was not written
@@ -296,43 +299,37 @@ __global__ __launch_bounds__(256) void k_wsweep(const int64_t* row_ptr, const in
     const int64_t c = tile * 256 + t;
     if (t == 0) q_n = 0;
     __syncthreads();
-    if (c < n_cells) {
-      int64_t a = 0;
+    if (c < n_cells && !removed[c]) {
+      int64_t from = 0, end = 0;
+      bool need;
       if (INIT) {
-        a = row_ptr[c * K];
-        cstart[c] = a;
-        if (c == n_cells - 1) cstart[n_cells] = row_ptr[n_cells * K];
-      }
-      if (!removed[c]) {
-        int64_t from = 0, end = 0;
-        bool need;
-        if (INIT) {
-          end = row_ptr[(c + 1) * K];
-          from = a;
-          need = true;
-          if (a < end) {  // most cells: the first target is present
-            const int32_t j = col[a];
-            if (!removed[j]) {
-              wpos[c] = a;
-              wtgt[c] = j;
-              need = false;
-            } else {
-              from = a + 1;
-            }
-          }
-        } else {
-          need = removed[wtgt[c]] != 0;
-          if (need) {
-            from = wpos[c] + 1;
-            end = cstart[c + 1];
+        const int64_t a = row_ptr[c * K];
+        end = row_ptr[(c + 1) * K];
+        from = a;
+        need = true;
+        if (a < end) {  // most cells: the first target is present
+          const int32_t j = col[a];
+          if (!removed[j]) {
+            wpos[c] = -1;
+            wtgt[c] = j;
+            need = false;
+          } else {
+            from = a + 1;
           }
         }
+      } else {
+        need = removed[wtgt[c]] != 0;
         if (need) {
-          const int k = atomicAdd(&q_n, 1);
-          q_cell[k] = (int32_t)c;
-          q_from[k] = from;
-          q_end[k] = end;
+          const int64_t wp = wpos[c];
+          from = (wp >= 0 ? wp : row_ptr[c * K]) + 1;
+          end = row_ptr[(c + 1) * K];
         }
+      }
+      if (need) {
+        const int k = atomicAdd(&q_n, 1);
+        q_cell[k] = (int32_t)c;
+        q_from[k] = from;
+        q_end[k] = end;
       }
     }
     __syncthreads();
@@ -1065,11 +1062,13 @@ int32_t prune_wsweeps(const int64_t* row_ptr, const int32_t* col, int64_t n_cell
   for (int32_t i = 0; i < count; ++i) {
     const int32_t sw = first + i;
     if (sw == 0)
-      hipLaunchKernelGGL(k_wsweep<true>, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells, K,
-                         w.removed, w.cstart, w.wpos, w.wtgt, w.last, sw, w.d_total, w.cap_edges);
+      hipLaunchKernelGGL(k_wsweep<true>, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells,
+                         K, w.removed, w.wpos, w.wtgt, w.last, sw, w.d_total,
+                         w.cap_edges);
     else
-      hipLaunchKernelGGL(k_wsweep<false>, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells, K,
-                         w.removed, w.cstart, w.wpos, w.wtgt, w.last, sw, w.d_total, w.cap_edges);
+      hipLaunchKernelGGL(k_wsweep<false>, dim3(nb), dim3(256), 0, s, row_ptr, col, n_cells,
+                         K, w.removed, w.wpos, w.wtgt, w.last, sw, w.d_total,
+                         w.cap_edges);
     GIS_LAUNCH_CHECK("k_wsweep");
   }
   return GIS_OK;

@@ -19,7 +19,7 @@ constexpr int64_t kStaticCells = (int64_t)1 << 21;  // largest n_cells accepted
 constexpr size_t kAlign = 256;
 constexpr size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Layout: counters, removed flags [n], span starts [n + 1], witness
+// Layout: counters, removed flags [n], witness
 // positions [n], witness targets [n], removed flags packed 32 to a word.
 struct StaticCounters {
   int32_t last;                 // 1 + index of the last sweep that removed a cell
@@ -27,11 +27,10 @@ struct StaticCounters {
   unsigned long long n_kept;    // kept cells
 };
 constexpr size_t kOffRemoved = al(sizeof(StaticCounters));
-constexpr size_t kOffCstart = kOffRemoved + al((size_t)kStaticCells);
-constexpr size_t kOffWpos = kOffCstart + al(8 * (size_t)(kStaticCells + 1));
+constexpr size_t kOffWpos = kOffRemoved + al((size_t)kStaticCells);
 constexpr size_t kOffWtgt = kOffWpos + al(8 * (size_t)kStaticCells);
 constexpr size_t kOffBits = kOffWtgt + al(4 * (size_t)kStaticCells);
-constexpr size_t kScratchBytes = kOffBits + al((size_t)kStaticCells / 8);  // about 42 MB
+constexpr size_t kScratchBytes = kOffBits + al((size_t)kStaticCells / 8);  // about 26 MiB
 
 }  // namespace
 }  // namespace gis
@@ -113,7 +112,6 @@ extern "C" int32_t gis_prune_static(const gis_graph* graph, int64_t n_cells, int
   PruneWork w{};
   w.removed = base + kOffRemoved;
   w.last = &cnt->last;
-  w.cstart = (int64_t*)(base + kOffCstart);
   w.wpos = (int64_t*)(base + kOffWpos);
   w.wtgt = (int32_t*)(base + kOffWtgt);
   w.rbits = (uint32_t*)(base + kOffBits);
