@@ -157,13 +157,21 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
           rb[q] = row + bhi[N - 1];
           in[q] = inner;
           m = q + 1;
-          int d = N - 2;
-          while (d >= 0 && k[d] == bhi[d]) {
-            k[d] = blo[d];
-            --d;
+          // advance the row odometer (unrolled: a runtime index would put
+          // k in scratch memory)
+          bool carry = true;
+#pragma unroll
+          for (int d = N - 2; d >= 0; --d) {
+            if (carry) {
+              if (k[d] == bhi[d]) {
+                k[d] = blo[d];
+              } else {
+                ++k[d];
+                carry = false;
+              }
+            }
           }
-          if (d < 0) done = true;
-          else ++k[d];
+          done = carry;
         }
       }
       int64_t p0[R], p1[R], q0[R], q1[R];
@@ -448,13 +456,21 @@ __device__ __forceinline__ void emit_targets(const CoverIndex& ci, const int32_t
       for (; p < q1; ++p) dst[p - p0] = id++;
       if (p >= p1) break;
       if constexpr (N > 1) {  // (with one dimension the run always reaches p1)
+        // next position of the box odometer (unrolled: a runtime index
+        // would put k in scratch memory); p < p1, so it does not wrap
         k[N - 1] = lo[N - 1];
-        int d = N - 2;
-        while (d > 0 && k[d] == hi[d]) {
-          k[d] = lo[d];
-          --d;
+        bool carry = true;
+#pragma unroll
+        for (int d = N - 2; d >= 0; --d) {
+          if (carry) {
+            if (d > 0 && k[d] == hi[d]) {
+              k[d] = lo[d];
+            } else {
+              ++k[d];
+              carry = false;
+            }
+          }
         }
-        ++k[d];
         id = lin_of();
       } else {
         break;
@@ -543,24 +559,26 @@ __global__ __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   bool finite = false;
   if constexpr (F32) {
     // FP32 images; the rows the band test cannot decide are redone in FP64
-    // by the whole wave (the FP32 box is kept meanwhile: half the registers)
+    // by the whole wave, which overwrites their boxes.  The FP32 box is
+    // widened to FP64 (exactly) before the redo, so that only one copy of
+    // the box is live across it.
     float fl[N], fh[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) fl[d] = fh[d] = 0.f;
     if (live) {
       const Rk4Consts<float> kc = make_consts<float>(J.sys);
       const bool fin32 = row_bbox<KIND, N, float>(a, J, kc, lc, lj, fl, fh);
       finite = fin32 && band_safe<N>(J, s_epsr, s_invh, fl, fh);
     }
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      bl[d] = (double)fl[d];
+      bh[d] = (double)fh[d];
+    }
     const uint64_t pend = __ballot(live && !finite);
     if (pend) {
       redo_rows_fp64<KIND, N>(a, J, lr, pend, bl, bh, finite);
       if (lane == 0) atomicAdd(&s_rchk, (uint32_t)__popcll(pend));
-    }
-    if (!((pend >> lane) & 1)) {
-#pragma unroll
-      for (int d = 0; d < N; ++d) {
-        bl[d] = (double)fl[d];
-        bh[d] = (double)fh[d];
-      }
     }
   }
   if (live) {
