@@ -116,8 +116,13 @@ __device__ __forceinline__ Ranges<N> ranges_of(const GridArgs& g, const CoverInd
 // Level-major, row-major order is the canonical id order, so the leaves come
 // out ascending.  The cost is one call per row of the box and level, whatever
 // the box's width and however the covering is refined inside it; the loads
-// of kRuns runs are issued together.
+// of kRuns runs are issued together.  The walk ends after a level whose slots
+// in the box are all leaves or holes: the slots below a leaf or a hole hold
+// neither, so the finer levels would add nothing (a row of a coarse cell
+// whose box lies in a coarse region stops after a few runs instead of
+// visiting every row of its box at the finest level).
 constexpr int kRuns = 2;
+constexpr int64_t kLo32 = 0xffffffffll;  // the leaf half of a prefix word
 
 template <int N, typename F>
 __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* lo,
@@ -136,6 +141,10 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
     const int32_t cl = (ilo[N - 1] >> s) - blo[N - 1];  // interior columns inside the run
     const int32_t cr = bhi[N - 1] - (ihi[N - 1] >> s);
     const int64_t base = ci.off[L];
+    int64_t slots = 1;  // slots of the box at this level, and the leaves and holes among them
+#pragma unroll
+    for (int d = 0; d < N; ++d) slots *= bhi[d] - blo[d] + 1;
+    int64_t settled = 0;
     bool done = false;
     while (!done) {
       constexpr int R = kRuns;
@@ -183,9 +192,14 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
         q1[q] = q < m && in[q] ? P[rb[q] - cr + 1] : 0;
       }
 #pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (q < m && !f(p0[q], p1[q], in[q], q0[q], q1[q])) return;
+      for (int q = 0; q < R; ++q) {
+        if (q < m) {
+          settled += ((p1[q] & kLo32) - (p0[q] & kLo32)) + ((p1[q] >> 32) - (p0[q] >> 32));
+          if (!f(p0[q], p1[q], in[q], q0[q], q1[q])) return;
+        }
+      }
     }
+    if (settled == slots) return;
   }
 }
 
@@ -374,8 +388,6 @@ __device__ __forceinline__ void redo_rows_fp64(const BuildArgs& a, const Job& J,
   }
 }
 
-constexpr int64_t kLo32 = 0xffffffffll;
-
 // Edge count of a row; *hole is set when a hole of the covering meets the
 // interior range, *first to the local id of its first target (when it has one).  Per run of index slots the prefix counts give the leaves
 // (ids consecutive from the first) and, on rows of the interior box, the holes
@@ -510,8 +522,7 @@ template <int KIND, int N, bool F32, bool UNI>
 //
 // At least four waves per SIMD: the FP32 variant of four-dimensional fields
 // would otherwise take 140 VGPRs (three waves) for the registers of the
-// wave-wide FP64 redo; bounded at 128, the compiler spills about a hundred
-// bytes, on the rarely taken redo path.
+// wave-wide FP64 redo; bounded at 128, the compiler spills two doubles.
 __global__ __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_build(
     BuildArgs a) {
   __shared__ CoverIndex ci;
