@@ -334,10 +334,20 @@ __global__ __launch_bounds__(256) void k_stage_scatter(const Staged* st, int64_t
 }
 
 // Step s: a group of kGroup lanes per frontier cell walks its in-entries.
-// Cells that die are collected in LDS and appended with one global atomic
-// per block and pass (directly, one atomic each, past kList of them).
+// The cells that die are collected in LDS.  While they are few (at most
+// kLocal, a few passes of the block), the block follows them itself, for up
+// to kDepth more generations, walking their in-entries the same way; the
+// rest goes to the next step's frontier, spread over the whole grid, with
+// one global atomic per block and pass (directly, one atomic each, past
+// kList of them).  The thin tails of the removal chains then cost a launch
+// per kDepth + 1 generations instead of one per generation.  Every dying
+// cell is still visited exactly once, by this block or by a later step; only
+// the order of the removals changes.
 constexpr int kGroup = 16;
+constexpr int kPer = 256 / kGroup;  // cells visited per pass of a block
 constexpr int kList = 1024;
+constexpr int kDepth = 16;
+constexpr int kLocal = 4 * kPer;
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_cells_step(const int64_t* rptr, const int32_t* rsrc,
@@ -346,49 +356,58 @@ __global__ __launch_bounds__(256) void k_cells_step(const int64_t* rptr, const i
                                                     uint32_t* rowstate, int32_t* good,
                                                     const int32_t* front_in, int32_t* front_out,
                                                     int32_t* counts, int32_t s) {
-  __shared__ int32_t s_list[kList];
-  __shared__ int32_t s_n, s_base;
+  __shared__ int32_t s_list[2][kList];
+  __shared__ int32_t s_n[2], s_base;
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[(s + 2) % 3] = 0;
   int32_t* cnt_out = counts + (s + 1) % 3;
   const int32_t n = counts[s % 3];
   const uint64_t full = K == 64 ? ~0ull : ((1ull << K) - 1);
-  const int t = threadIdx.x, sub = t % kGroup;
-  const int64_t per_block = 256 / kGroup;
-  auto push = [&](int32_t c) {
-    const int k = atomicAdd(&s_n, 1);
-    if (k < kList) s_list[k] = c;
+  const int t = threadIdx.x, sub = t % kGroup, slot = t / kGroup;
+  auto push = [&](int32_t c, int o) {
+    const int k = atomicAdd(&s_n[o], 1);
+    if (k < kList) s_list[o][k] = c;
     else front_out[atomicAdd(cnt_out, 1)] = c;
   };
-  for (int64_t i0 = (int64_t)blockIdx.x * per_block; i0 < n;
-       i0 += (int64_t)gridDim.x * per_block) {
-    if (t == 0) s_n = 0;
-    __syncthreads();
-    const int64_t i = i0 + t / kGroup;
-    if (i < n) {
-      const int32_t j = front_in[i];
-      if (sub == 0) removed[j] = 1;
-      const int64_t b = rptr[j + 1];
-      for (int64_t p = rptr[j] + sub; p < b; p += kGroup) {
-        const int32_t c = rsrc[p];
-        const uint64_t m = rmask[p];
-        if (MODE == GIS_ANALYSIS_NONLEAVING) {
-          for (uint64_t bits = m; bits; bits &= bits - 1) {
-            const int u = __builtin_ctzll(bits);
-            if (atomicSub(&rowstate[(int64_t)c * K + u], 1u) == 1u && atomicSub(&good[c], 1) == 1)
-              push(c);
-          }
-        } else {
-          const uint64_t old =
-              atomicOr((unsigned long long*)&badmask[c], (unsigned long long)m);
-          if (old != full && (old | m) == full) push(c);
+  // removes cell j and walks its in-entries; the cells that die go to list o
+  auto visit = [&](int32_t j, int o) {
+    if (sub == 0) removed[j] = 1;
+    const int64_t b = rptr[j + 1];
+    for (int64_t p = rptr[j] + sub; p < b; p += kGroup) {
+      const int32_t c = rsrc[p];
+      const uint64_t m = rmask[p];
+      if (MODE == GIS_ANALYSIS_NONLEAVING) {
+        for (uint64_t bits = m; bits; bits &= bits - 1) {
+          const int u = __builtin_ctzll(bits);
+          if (atomicSub(&rowstate[(int64_t)c * K + u], 1u) == 1u && atomicSub(&good[c], 1) == 1)
+            push(c, o);
         }
+      } else {
+        const uint64_t old = atomicOr((unsigned long long*)&badmask[c], (unsigned long long)m);
+        if (old != full && (old | m) == full) push(c, o);
       }
     }
+  };
+  for (int64_t i0 = (int64_t)blockIdx.x * kPer; i0 < n; i0 += (int64_t)gridDim.x * kPer) {
+    if (t == 0) s_n[0] = 0;
     __syncthreads();
-    const int32_t nl = s_n < kList ? s_n : kList;
+    const int64_t i = i0 + slot;
+    if (i < n) visit(front_in[i], 0);
+    __syncthreads();
+    int cur = 0;
+    for (int depth = 0; depth < kDepth; ++depth) {
+      const int nl = s_n[cur];  // the same in every thread
+      if (nl == 0 || nl > kLocal) break;
+      if (t == 0) s_n[cur ^ 1] = 0;
+      __syncthreads();
+      for (int k0 = 0; k0 < nl; k0 += kPer)
+        if (k0 + slot < nl) visit(s_list[cur][k0 + slot], cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+    const int32_t nl = s_n[cur] < kList ? s_n[cur] : kList;
     if (t == 0 && nl) s_base = atomicAdd(cnt_out, nl);
     __syncthreads();
-    for (int k = t; k < nl; k += 256) front_out[s_base + k] = s_list[k];
+    for (int k = t; k < nl; k += 256) front_out[s_base + k] = s_list[cur][k];
     __syncthreads();
   }
 }
