@@ -648,6 +648,17 @@ int32_t enqueue_build(gis_ctx* ctx, Batch& B, const uint8_t* level, const int32_
   return GIS_OK;
 }
 
+// Milliseconds between two events of a stream whose work the host has
+// already seen finish through the counters' sequence number: the runtime may
+// not have marked the events complete yet (hipEventElapsedTime would report
+// hipErrorNotReady), so they are waited for first, which costs nothing more.
+int32_t event_ms(hipEvent_t a, hipEvent_t b, float* ms) {
+  GIS_HIP(hipEventSynchronize(a));
+  GIS_HIP(hipEventSynchronize(b));
+  GIS_HIP(hipEventElapsedTime(ms, a, b));
+  return GIS_OK;
+}
+
 // Build figures after the stream was synchronised (counters and job stats
 // copied to the host).
 int32_t finish_build(gis_ctx* ctx, const Batch& B, Graph& gr) {
@@ -656,7 +667,8 @@ int32_t finish_build(gis_ctx* ctx, const Batch& B, Graph& gr) {
   gr.n_out = 0;
   for (int j = 0; j < B.n_jobs; ++j) gr.n_out += (int64_t)ctx->h_stats[j].n_out;
   gr.ms_image = gr.ms_recheck = 0.f;
-  if (gr.timed) GIS_HIP(hipEventElapsedTime(&gr.ms_image, ctx->timer.ev[0], ctx->timer.ev[1]));
+  int32_t rc;
+  if (gr.timed && (rc = event_ms(ctx->timer.ev[0], ctx->timer.ev[1], &gr.ms_image))) return rc;
   if (ctx->h_counters->err & 256u) {
     set_error("graph build: a block's look-back wait reached its time limit");
     return GIS_E_INTERNAL;
@@ -1467,9 +1479,9 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
     }
     float ms_b = 0.f, ms_p = 0.f, ms_sub = 0.f;
     if (phases) {
-      GIS_HIP(hipEventElapsedTime(&ms_b, ev[0], ev[1]));
-      GIS_HIP(hipEventElapsedTime(&ms_p, ev[1], ev[2]));
-      GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+      if ((rc = event_ms(ev[0], ev[1], &ms_b)) || (rc = event_ms(ev[1], ev[2], &ms_p)) ||
+          (rc = event_ms(ev[2], ev[3], &ms_sub)))
+        return fail_all(rc);
     }
     const bool conv = prune_converged(ctx, n_cells);
     if (ctx->sweep_memo.size() <= (size_t)r) ctx->sweep_memo.resize(r + 1);
@@ -1508,8 +1520,8 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       if ((rc = sync_stats(ctx, B, s))) return fail_all(rc);
       float ms_p2 = 0.f;
       if (phases) {
-        GIS_HIP(hipEventElapsedTime(&ms_p2, ev[1], ev[2]));
-        GIS_HIP(hipEventElapsedTime(&ms_sub, ev[2], ev[3]));
+        if ((rc = event_ms(ev[1], ev[2], &ms_p2)) || (rc = event_ms(ev[2], ev[3], &ms_sub)))
+          return fail_all(rc);
       }
       ms_p += ms_p2;
       ctx->h_counters->total_edges = keep.total_edges;

@@ -189,6 +189,33 @@ def test_solve_standard_workload_full_size(G, ctx):
     _check(G, ctx, wl, G.solve_workload(ctx, wl))
 
 
+def test_solve_standard_timed_frontier_schedule(G, ctx):
+    """Solves timed with HIP events (the build's, and the phases') on a
+    schedule that sends the non-leaving analysis of the larger rounds to the
+    frontier phase (no witness sweeps, row sweeps only below 2 M edges): the
+    host learns that a round has finished from the counters' sequence number,
+    not from the runtime, so the library waits for the events before it reads
+    their times.  Every call returns, with times, and equals the oracle."""
+    wl = W.vdp_standard_32()
+    prev = ctx.set_tuning(wit_sweeps=0, sweep_edges=2_000_000)
+    try:
+        first = None
+        for _ in range(4):
+            sol = G.solve_workload(ctx, wl, timing=2)
+            rounds = sol.info()["rounds"]
+            assert all(r["ms_image"] > 0 for r in rounds)
+            got = [_np(t) for t in sol.export()]
+            if first is None:
+                _check(G, ctx, wl, sol)
+                first = got
+            else:
+                for a, b in zip(got, first):
+                    np.testing.assert_array_equal(a, b)
+            sol.free()
+    finally:
+        ctx.set_tuning(**prev)
+
+
 def test_bisect_cell_count_limit(G, ctx):
     """A halving that would put more than 2^30 cells along a dimension is
     refused before any work (GIS_E_UNSUPPORTED), and the context still works."""
