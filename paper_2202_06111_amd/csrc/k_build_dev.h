@@ -128,7 +128,11 @@ template <int N, typename F>
 __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* lo,
                                           const int32_t* hi, const int32_t* ilo,
                                           const int32_t* ihi, bool interior, F&& f) {
-  const int64_t* P = ci.pfx;
+  // the index lives in global memory; its pointer comes from the block's
+  // LDS copy of the index description, so say so (global loads instead of
+  // flat ones, whose waits would also hold the LDS traffic of the walk)
+  const int64_t __attribute__((address_space(1)))* P =
+      (const int64_t __attribute__((address_space(1)))*)ci.pfx;
   for (int L = 0; L <= ci.lmax; ++L) {
     const int s = ci.lmax - L;
     int32_t blo[N], bhi[N], k[N];
@@ -203,6 +207,17 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
   }
 }
 
+// Input j of job J (m components, the second 0 when m = 1).  The input array
+// is in global memory, but its pointer is read from the job table, so the
+// loads are told so (global loads instead of flat ones).
+__device__ __forceinline__ void job_input(const Job& J, int32_t j, double* u) {
+  const double __attribute__((address_space(1)))* U =
+      (const double __attribute__((address_space(1)))*)J.u;
+  const int m = J.sys.m;
+  u[0] = U[(int64_t)j * m];
+  u[1] = m > 1 ? U[(int64_t)j * m + 1] : 0.0;
+}
+
 // Bounding box of the sample images of the row (local cell c, input j) of
 // job J, in precision R.
 template <int KIND, int N, typename R>
@@ -214,9 +229,9 @@ __device__ __forceinline__ bool row_bbox(const BuildArgs& a, const Job& J, const
 #pragma unroll
   for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
   const int m = J.sys.m;
-  R u[2];
-  u[0] = R(J.u[(int64_t)j * m]);
-  u[1] = m > 1 ? R(J.u[(int64_t)j * m + 1]) : R(0);
+  double ud[2];
+  job_input(J, j, ud);
+  const R u[2] = {R(ud[0]), R(ud[1])};
   bool finite = true;
 #pragma unroll
   for (int d = 0; d < N; ++d) {
@@ -303,8 +318,7 @@ __device__ __forceinline__ void sample_image(const BuildArgs& a, const Job& J,
   for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
   const int m = J.sys.m;
   double u[2];
-  u[0] = J.u[(int64_t)j * m];
-  u[1] = m > 1 ? J.u[(int64_t)j * m + 1] : 0.0;
+  job_input(J, j, u);
   int k[N];
   sample_offsets<N>(a.samples, q, k);
   sample_point<N>(J.grid, level, ci, k, x);
@@ -725,9 +739,9 @@ __global__ __launch_bounds__(kRowBlock) void k_images(BuildArgs a, double* out) 
 #pragma unroll
   for (int d = 0; d < N; ++d) ci[d] = a.idx[gc * N + d];
   const int m = J.sys.m;
-  R u[2];
-  u[0] = R(J.u[(int64_t)j * m]);
-  u[1] = m > 1 ? R(J.u[(int64_t)j * m + 1]) : R(0);
+  double ud[2];
+  job_input(J, j, ud);
+  const R u[2] = {R(ud[0]), R(ud[1])};
   const int S = num_samples(a.samples, N);
   for (int q = 0; q < S; ++q) {
     int k[N];
@@ -768,8 +782,7 @@ __global__ __launch_bounds__(kRowBlock) void k_calibrate(BuildArgs a, unsigned l
     const int m = J.sys.m;
     double u64[2];
     float u32[2];
-    u64[0] = J.u[(int64_t)j * m];
-    u64[1] = m > 1 ? J.u[(int64_t)j * m + 1] : 0.0;
+    job_input(J, j, u64);
     u32[0] = (float)u64[0];
     u32[1] = (float)u64[1];
     const int S = num_samples(a.samples, N);
