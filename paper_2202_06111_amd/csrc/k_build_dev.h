@@ -135,71 +135,73 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
       (const int64_t __attribute__((address_space(1)))*)ci.pfx;
   for (int L = 0; L <= ci.lmax; ++L) {
     const int s = ci.lmax - L;
-    int32_t blo[N], bhi[N], k[N];
+    // the box and its interior at this level; the rows of the box (all
+    // coordinates but the last) are enumerated by an odometer k whose slot
+    // offset `row` follows it by additions: the strides of the leading
+    // coordinates, and the span of a whole coordinate to undo on a wrap
+    int32_t blo[N], bhi[N], il[N], ih[N], k[N];
+    int64_t st[N], span[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) {
       blo[d] = lo[d] >> s;
       bhi[d] = hi[d] >> s;
+      il[d] = ilo[d] >> s;
+      ih[d] = ihi[d] >> s;
       k[d] = blo[d];
     }
-    const int32_t cl = (ilo[N - 1] >> s) - blo[N - 1];  // interior columns inside the run
-    const int32_t cr = bhi[N - 1] - (ihi[N - 1] >> s);
-    const int64_t base = ci.off[L];
-    int64_t slots = 1;  // slots of the box at this level, and the leaves and holes among them
+    st[N - 1] = 1;
 #pragma unroll
-    for (int d = 0; d < N; ++d) slots *= bhi[d] - blo[d] + 1;
-    int64_t settled = 0;
-    bool done = false;
-    while (!done) {
-      constexpr int R = kRuns;
-      int64_t ra[R], rb[R];
-      bool in[R];
-      int m = 0;
+    for (int d = N - 2; d >= 0; --d) st[d] = st[d + 1] * ci.dims[L][d + 1];
+    int64_t row = ci.off[L];
+    int64_t nrows = 1;
+    int64_t slots = bhi[N - 1] - blo[N - 1] + 1;  // slots of the box at this level
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        if (!done) {
-          int64_t lin = 0;
-          bool inner = interior;
+    for (int d = 0; d < N - 1; ++d) {
+      row += (int64_t)blo[d] * st[d];
+      span[d] = (int64_t)(bhi[d] - blo[d] + 1) * st[d];
+      nrows *= bhi[d] - blo[d] + 1;
+    }
+    slots *= nrows;
+    const int32_t cl = il[N - 1] - blo[N - 1];  // interior columns inside the run
+    const int32_t cr = bhi[N - 1] - ih[N - 1];
+    int64_t settled = 0;  // leaves and holes among the slots
+    for (int64_t t = 0; t < nrows; t += kRuns) {
+      // kRuns rows of the box; past its last row the odometer has wrapped to
+      // the first, so every address below stays inside the box's runs and
+      // the loads need no guard
+      int64_t ra[kRuns];
+      bool in[kRuns];
 #pragma unroll
-          for (int d = 0; d < N - 1; ++d) {
-            lin = lin * ci.dims[L][d] + k[d];
-            inner &= k[d] >= (ilo[d] >> s) && k[d] <= (ihi[d] >> s);
-          }
-          const int64_t row = base + lin * ci.dims[L][N - 1];
-          ra[q] = row + blo[N - 1];
-          rb[q] = row + bhi[N - 1];
-          in[q] = inner;
-          m = q + 1;
-          // advance the row odometer (unrolled: a runtime index would put
-          // k in scratch memory)
-          bool carry = true;
+      for (int q = 0; q < kRuns; ++q) {
+        bool inner = interior;
 #pragma unroll
-          for (int d = N - 2; d >= 0; --d) {
-            if (carry) {
-              if (k[d] == bhi[d]) {
-                k[d] = blo[d];
-              } else {
-                ++k[d];
-                carry = false;
-              }
-            }
-          }
-          done = carry;
+        for (int d = 0; d < N - 1; ++d) inner &= k[d] >= il[d] && k[d] <= ih[d];
+        ra[q] = row + blo[N - 1];
+        in[q] = inner;
+        bool carry = true;
+#pragma unroll
+        for (int d = N - 2; d >= 0; --d) {
+          const bool wrap = carry && k[d] == bhi[d];
+          row += carry ? st[d] : 0;
+          row -= wrap ? span[d] : 0;
+          k[d] = wrap ? blo[d] : k[d] + (carry ? 1 : 0);
+          carry = wrap;
         }
       }
-      int64_t p0[R], p1[R], q0[R], q1[R];
+      int64_t p0[kRuns], p1[kRuns], q0[kRuns], q1[kRuns];
+      const int32_t w = bhi[N - 1] - blo[N - 1];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        p0[q] = q < m ? P[ra[q]] : 0;
-        p1[q] = q < m ? P[rb[q] + 1] : 0;
-        q0[q] = q < m && in[q] ? P[ra[q] + cl] : 0;
-        q1[q] = q < m && in[q] ? P[rb[q] - cr + 1] : 0;
+      for (int q = 0; q < kRuns; ++q) {
+        p0[q] = P[ra[q]];
+        p1[q] = P[ra[q] + w + 1];
+        q0[q] = P[ra[q] + cl];
+        q1[q] = P[ra[q] + w - cr + 1];
       }
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        if (q < m) {
+      for (int q = 0; q < kRuns; ++q) {
+        if (t + q < nrows) {
           settled += ((p1[q] & kLo32) - (p0[q] & kLo32)) + ((p1[q] >> 32) - (p0[q] >> 32));
-          if (!f(p0[q], p1[q], in[q], q0[q], q1[q])) return;
+          if (!f(p0[q], p1[q], in[q], in[q] ? q0[q] : 0, in[q] ? q1[q] : 0)) return;
         }
       }
     }
