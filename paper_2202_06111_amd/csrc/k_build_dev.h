@@ -136,11 +136,12 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
   for (int L = 0; L <= ci.lmax; ++L) {
     const int s = ci.lmax - L;
     // the box and its interior at this level; the rows of the box (all
-    // coordinates but the last) are enumerated by an odometer k whose slot
-    // offset `row` follows it by additions: the strides of the leading
-    // coordinates, and the span of a whole coordinate to undo on a wrap
+    // coordinates but the last) are enumerated by an odometer k, and a
+    // pointer to the row's first slot follows it by additions: jump[d] is
+    // the pointer's move when the odometer's carry stops at coordinate d
+    // (d increments, the coordinates after it wrap back to the box's start)
     int32_t blo[N], bhi[N], il[N], ih[N], k[N];
-    int64_t st[N], span[N];
+    int64_t st[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) {
       blo[d] = lo[d] >> s;
@@ -155,47 +156,50 @@ __device__ __forceinline__ void walk_runs(const CoverIndex& ci, const int32_t* l
     int64_t row = ci.off[L];
     int64_t nrows = 1;
     int64_t slots = bhi[N - 1] - blo[N - 1] + 1;  // slots of the box at this level
+    int64_t jump[N] = {};
+    int64_t back = 0;  // the moves that wrap the coordinates after d
+#pragma unroll
+    for (int d = N - 2; d >= 0; --d) {
+      jump[d] = st[d] - back;
+      back += (int64_t)(bhi[d] - blo[d]) * st[d];
+    }
 #pragma unroll
     for (int d = 0; d < N - 1; ++d) {
       row += (int64_t)blo[d] * st[d];
-      span[d] = (int64_t)(bhi[d] - blo[d] + 1) * st[d];
       nrows *= bhi[d] - blo[d] + 1;
     }
     slots *= nrows;
-    const int32_t cl = il[N - 1] - blo[N - 1];  // interior columns inside the run
-    const int32_t cr = bhi[N - 1] - ih[N - 1];
+    const int64_t __attribute__((address_space(1)))* rp = P + row;
+    // the four prefix words of a run, relative to its row's first slot
+    const int32_t o0 = blo[N - 1], o1 = bhi[N - 1] + 1, o2 = il[N - 1], o3 = ih[N - 1] + 1;
     int64_t settled = 0;  // leaves and holes among the slots
     for (int64_t t = 0; t < nrows; t += kRuns) {
       // kRuns rows of the box; past its last row the odometer has wrapped to
       // the first, so every address below stays inside the box's runs and
       // the loads need no guard
-      int64_t ra[kRuns];
+      int64_t p0[kRuns], p1[kRuns], q0[kRuns], q1[kRuns];
       bool in[kRuns];
 #pragma unroll
       for (int q = 0; q < kRuns; ++q) {
         bool inner = interior;
 #pragma unroll
         for (int d = 0; d < N - 1; ++d) inner &= k[d] >= il[d] && k[d] <= ih[d];
-        ra[q] = row + blo[N - 1];
         in[q] = inner;
+        p0[q] = rp[o0];
+        p1[q] = rp[o1];
+        q0[q] = rp[o2];
+        q1[q] = rp[o3];
+        int64_t mv = jump[0];
         bool carry = true;
 #pragma unroll
         for (int d = N - 2; d >= 0; --d) {
           const bool wrap = carry && k[d] == bhi[d];
-          row += carry ? st[d] : 0;
-          row -= wrap ? span[d] : 0;
+          if (d > 0) mv = carry && !wrap ? jump[d] : mv;
           k[d] = wrap ? blo[d] : k[d] + (carry ? 1 : 0);
           carry = wrap;
         }
-      }
-      int64_t p0[kRuns], p1[kRuns], q0[kRuns], q1[kRuns];
-      const int32_t w = bhi[N - 1] - blo[N - 1];
-#pragma unroll
-      for (int q = 0; q < kRuns; ++q) {
-        p0[q] = P[ra[q]];
-        p1[q] = P[ra[q] + w + 1];
-        q0[q] = P[ra[q] + cl];
-        q1[q] = P[ra[q] + w - cr + 1];
+        // (a full wrap, past the box's last row, moves back to its first)
+        rp += carry ? -back : mv;
       }
 #pragma unroll
       for (int q = 0; q < kRuns; ++q) {
