@@ -45,6 +45,16 @@ namespace kbuild {
 
 constexpr int kTile = 4096;   // LDS staging tile of the emitter (int32 ids, 16 KiB)
 constexpr int kCache = 8;     // runs of target ids kept in LDS per row between count and emit
+constexpr int kStage = 512;   // ids a wave stages in LDS per coalesced store pass (refined coverings)
+
+// Orders one wave's LDS writes before its lanes' later reads (and reads
+// before later writes): the wave's memory operations at wavefront scope, no
+// block barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Look-back words: the launch's epoch in bits 40-63, a status in bits 38-39
 // and an edge total in bits 0-37.  A word written by an earlier launch
@@ -548,6 +558,7 @@ __global__ __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   __shared__ CoverIndex ci;
   __shared__ int32_t tile[UNI ? kTile : 1];
   __shared__ int2 cache[UNI ? 1 : kCache * kRowBlock];
+  __shared__ int32_t stage[UNI || N > 2 ? 1 : kStage * (kRowBlock / 64)];
   __shared__ int64_t wsum[kRowBlock / 64];
   __shared__ int64_t s_prefix;
   __shared__ double s_epsr[F32 ? N : 1], s_invh[F32 ? N : 1];
@@ -713,8 +724,38 @@ __global__ __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   if (live && g == a.total_rows - 1) a.row_ptr[a.total_rows] = prefix + off + c;
   if (prefix + T > a.cap_edges) return;  // capacity miss: col is not written
   const int32_t id0 = (int32_t)J.cell_off;
-  if constexpr (!UNI) {
+  if constexpr (!UNI && N > 2) {
+    // rows of three- and four-dimensional fields write their own targets:
+    // staging them (below) was slower there (their kernels are at the
+    // register limit already)
     if (c > 0) emit_targets<N, UNI>(ci, lo, hi, c, cache + tid, id0, 0, c, a.col + prefix + off);
+    return;
+  }
+  if constexpr (!UNI) {
+    // The wave's rows own one contiguous range of col.  It is written in
+    // chunks of kStage ids: each lane puts its ids of the chunk into the
+    // wave's LDS area, then the wave stores the chunk with consecutive lanes
+    // on consecutive ids (a row writing its own ids would spread each store
+    // instruction over the 64 rows' ranges).  Only the wave synchronises.
+    // A wave holding a row with more runs than the LDS cache keeps writes
+    // its rows' targets directly, as the rows of larger fields do: that row
+    // would walk the index again for every chunk it spans.
+    if (__ballot(c > 0 && !ci.uniform && cache[tid].y < 0)) {
+      if (c > 0) emit_targets<N, UNI>(ci, lo, hi, c, cache + tid, id0, 0, c, a.col + prefix + off);
+      return;
+    }
+    const int64_t wbeg = __shfl(off, 0, 64), wend = __shfl(off + c, 63, 64);
+    int32_t* ws = stage + wid * kStage;
+    for (int64_t ch = wbeg; ch < wend; ch += kStage) {  // wave-uniform
+      const int64_t ce = ch + kStage < wend ? ch + kStage : wend;
+      const int64_t r0 = off > ch ? off : ch, r1 = off + c < ce ? off + c : ce;
+      if (r0 < r1)
+        emit_targets<N, UNI>(ci, lo, hi, c, cache + tid, id0, (int32_t)(r0 - off),
+                             (int32_t)(r1 - off), ws + (r0 - ch));
+      wave_sync();
+      for (int64_t i = lane; i < ce - ch; i += 64) a.col[prefix + ch + i] = ws[i];
+      wave_sync();
+    }
     return;
   }
   for (int64_t w0 = 0; w0 < T; w0 += kTile) {
