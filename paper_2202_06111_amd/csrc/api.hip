@@ -1002,6 +1002,8 @@ int32_t continue_prune(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
         w = prune_work(ctx, cap_edges, nullptr);
         if ((rc = cells_unstage(stage, staged, n_cells, w, s))) return rc;
       } else {
+        // the staging pass counted the degrees of the entries it wrote
+        if ((rc = fill_i32(w.rcur, 0, (int64_t)(ctx->rcur.bytes / 4), s))) return rc;
         if ((rc = cells_start(row_ptr, col, n_cells, K, any_removed, w, s))) return rc;
         GIS_HIP(hipMemcpyAsync(&ctx->h_counters->rc_entries, w.rptr + n_cells, sizeof(int64_t),
                                hipMemcpyDeviceToHost, s));

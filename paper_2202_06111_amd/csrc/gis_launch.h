@@ -112,8 +112,10 @@ int32_t cells_scatter(const int64_t* row_ptr, const int32_t* col, const uint8_t*
 // One pass instead of cells_start + cells_scatter: the state, the first
 // frontier and the entries appended to `stage` (any order, up to stage_cap of
 // them; *n_staged, cleared here, receives their number even past the cap,
-// when nothing past it was written and the two-pass route must be taken).
-// cells_unstage then counts them per target, scans, and places them.
+// when nothing past it was written and the two-pass route must be taken),
+// their counts per target added to w.rcur (zero on entry; clear it again
+// before the two-pass route).  cells_unstage then scans the counts and
+// places the entries.
 struct Staged {
   int32_t j, c;  // target, source cell
   uint64_t m;    // input mask

@@ -28,8 +28,8 @@
 // Building the entries: a block takes whole cells and inserts their rows'
 // (cell, target) keys into an LDS table, ORing each row's input bit into the
 // key's mask.  One pass over the edges appends the block's entries to a
-// staging area (k_cells_fill<STAGE>), which k_stage_count / a scan /
-// k_stage_scatter then group by target; when more entries come than the
+// staging area (k_cells_fill<STAGE>), counting them per target as it goes,
+// and a scan and k_stage_scatter group them by target; when more entries come than the
 // staging area holds, a first pass counts them per target (k_cells_count) and
 // a second places them (k_cells_fill).
 #include "gis_launch.h"
@@ -257,16 +257,23 @@ __global__ __launch_bounds__(256) void k_cells_fill(const int64_t* row_ptr, cons
       __syncthreads();
       if ((int64_t)(s_base + total) <= stage_cap) {
         Staged* dst = stage + s_base + off;
+        // (each written entry also counts toward its target's degree in
+        // `cursor`, which the scan turns into the grouped offsets)
         if (!over) {
           for (int i = t; i < kSlots; i += 256) {
             const uint64_t key = tb.key[i];
-            if (key != kEmpty)
+            if (key != kEmpty) {
               *dst++ = Staged{(int32_t)(key >> 8), (int32_t)(g0 + (int64_t)(key & 255)),
                               tb.mask[i]};
+              atomicAdd(&cursor[(int32_t)(key >> 8)], 1);
+            }
           }
         } else {
           for_targets(row_ptr, col, removed, any_removed, b, [&](int32_t j, bool rm) {
-            if (!rm) *dst++ = Staged{j, (int32_t)b.c, bit};
+            if (!rm) {
+              *dst++ = Staged{j, (int32_t)b.c, bit};
+              atomicAdd(&cursor[j], 1);
+            }
             return true;
           });
         }
@@ -312,14 +319,8 @@ __global__ __launch_bounds__(256) void k_cells_fill(const int64_t* row_ptr, cons
   }
 }
 
-// Staged entries: counts per target, then each entry at rptr[j] + (a slot
-// counted down from deg[j]).
-__global__ __launch_bounds__(256) void k_stage_count(const Staged* st, int64_t n, int32_t* deg) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&deg[st[i].j], 1);
-}
-
+// Staged entries (their counts per target taken by the staging pass): each
+// entry at rptr[j] + (a slot counted down from deg[j]).
 __global__ __launch_bounds__(256) void k_stage_scatter(const Staged* st, int64_t n,
                                                        const int64_t* rptr, int32_t* cursor,
                                                        int32_t* rsrc, uint64_t* rmask) {
@@ -470,13 +471,13 @@ int32_t cells_stage(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
   if (analysis == GIS_ANALYSIS_NONLEAVING)
     hipLaunchKernelGGL((k_cells_fill<GIS_ANALYSIS_NONLEAVING, true>), dim3(nb), dim3(256), 0, s,
                        row_ptr, col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
-                       (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                       (const int64_t*)nullptr, w.rcur, (int32_t*)nullptr,
                        (uint64_t*)nullptr, stage, stage_cap, n_staged, w.rowstate, w.good,
                        w.badmask, w.front, w.fcount);
   else
     hipLaunchKernelGGL((k_cells_fill<GIS_ANALYSIS_CONTROLLED, true>), dim3(nb), dim3(256), 0, s,
                        row_ptr, col, out, n_cells, K, cpb, (const uint8_t*)w.removed, any_removed,
-                       (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                       (const int64_t*)nullptr, w.rcur, (int32_t*)nullptr,
                        (uint64_t*)nullptr, stage, stage_cap, n_staged, w.rowstate, w.good,
                        w.badmask, w.front, w.fcount);
   GIS_LAUNCH_CHECK("k_cells_fill");
@@ -486,8 +487,7 @@ int32_t cells_stage(const int64_t* row_ptr, const int32_t* col, const uint8_t* o
 int32_t cells_unstage(const Staged* stage, int64_t n_staged, int64_t n_cells, const PruneWork& w,
                       hipStream_t s) {
   const unsigned nb = (unsigned)((n_staged + 255) / 256 < 16384 ? (n_staged + 255) / 256 + 1 : 16384);
-  hipLaunchKernelGGL(k_stage_count, dim3(nb), dim3(256), 0, s, stage, n_staged, w.rcur);
-  GIS_LAUNCH_CHECK("k_stage_count");
+  // the degrees were counted in w.rcur by the staging pass
   int32_t rc;
   if ((rc = scan_exclusive_i32(w.rcur, w.rptr, n_cells, w.rptr + n_cells, w.scan_tmp, s)))
     return rc;
