@@ -46,7 +46,7 @@ if ROOT not in sys.path:
 
 # Published MI355X vector peaks (256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz):
 # FP64 FMA runs at full rate, 78.6 TFLOP/s.  FP32 reaches 157.3 TFLOP/s only through
-# packed (two-per-lane) FP32 instructions, which this build does not emit; its
+# packed (two-per-lane) FP32 instructions, which the kernels do not use; its
 # unpacked FP32 FMA rate is the same 78.6 TFLOP/s.
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Published MI355X HBM3E bandwidth.
@@ -326,7 +326,7 @@ def cstr_experiment(gis, W, ctx, stream, steps, cpu_budget_s):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported by this build "
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
               "(the path has no multi-GPU sharding).", file=sys.stderr)
         sys.exit(2)
     import torch

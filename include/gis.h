@@ -79,7 +79,7 @@ typedef enum {
   GIS_E_NOMEM = 2,        /* device allocation failed */
   GIS_E_HIP = 3,          /* HIP runtime error */
   GIS_E_CAPACITY = 4,     /* a caller buffer is too small; the needed size is reported */
-  GIS_E_UNSUPPORTED = 5,  /* valid request outside this build's limits */
+  GIS_E_UNSUPPORTED = 5,  /* valid request outside the library's limits */
   GIS_E_INTERNAL = 6      /* a device-side consistency check failed */
 } gis_status;
 
