@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <map>
 #include <memory>
@@ -138,6 +139,9 @@ struct gis_ctx {
   // per round of the last solve: its cell count and the sweeps its analysis
   // needed (0: it did not converge within the first batch)
   std::vector<std::pair<int64_t, int32_t>> sweep_memo;
+  // per round of the last solve: its cell count and the sweeps each pass of
+  // its largest-component search needed (trim, colour, backward, reach)
+  std::vector<std::pair<int64_t, std::array<int32_t, 4>>> scc_memo;
   GraphCache graphs;
   DevBuf lookback, scan_tmp;
   DevBuf idx_state, idx_pfx, next_state, pos;
@@ -758,14 +762,22 @@ int32_t prune_final_and_counts(gis_ctx* ctx, const int64_t* row_ptr, const int32
 int32_t largest_component_stage(gis_ctx* ctx, const int64_t* row_ptr, const int32_t* col,
                                 const uint8_t* out, int64_t n_cells, int32_t K, uint8_t* kept,
                                 uint64_t* mask, hipStream_t s, const Batch* B = nullptr,
-                                const uint8_t* level = nullptr, const int32_t* idx = nullptr) {
+                                const uint8_t* level = nullptr, const int32_t* idx = nullptr,
+                                int round = -1) {
   if (n_cells == 0) return GIS_OK;
   const int32_t nj = B ? B->n_jobs : 1;
+  // a solve's round r starts its passes at what round r of the last solve
+  // needed, when that round had as many cells
+  std::array<int32_t, 4> none{0, 0, 0, 0};
+  if (round >= 0) {
+    if (ctx->scc_memo.size() <= (size_t)round) ctx->scc_memo.resize(round + 1, {0, none});
+    if (ctx->scc_memo[round].first != n_cells) ctx->scc_memo[round] = {n_cells, none};
+  }
   int32_t rc;
   const size_t up = 256;
   auto al = [&](size_t x) { return (x + up - 1) / up * up; };
   const size_t o4 = al((size_t)n_cells * 4), o1 = al((size_t)n_cells);
-  if ((rc = ensure(ctx->scc, 4 * o4 + 4 * o1 + al(16 * (size_t)nj) + 256))) return rc;
+  if ((rc = ensure(ctx->scc, 5 * o4 + 4 * o1 + al(16 * (size_t)nj) + 256))) return rc;
   if ((rc = ctx->h_scc.ensure(2 * (size_t)nj + 1))) return rc;
   uint8_t* b = (uint8_t*)ctx->scc.ptr;
   SccWork w{};
@@ -773,15 +785,17 @@ int32_t largest_component_stage(gis_ctx* ctx, const int64_t* row_ptr, const int3
   w.comp = (int32_t*)(b + o4);
   w.size = (int32_t*)(b + 2 * o4);
   w.minid = (int32_t*)(b + 3 * o4);
-  w.rem = b + 4 * o4;
-  w.bw = b + 4 * o4 + o1;
-  w.loop = b + 4 * o4 + 2 * o1;
-  w.inset = b + 4 * o4 + 3 * o1;
-  w.best = (unsigned long long*)(b + 4 * o4 + 4 * o1);
+  w.rose = (uint32_t*)(b + 4 * o4);
+  w.rem = b + 5 * o4;
+  w.bw = b + 5 * o4 + o1;
+  w.loop = b + 5 * o4 + 2 * o1;
+  w.inset = b + 5 * o4 + 3 * o1;
+  w.best = (unsigned long long*)(b + 5 * o4 + 4 * o1);
   w.left = w.best + nj;
-  w.last = (uint32_t*)(b + 4 * o4 + 4 * o1 + al(16 * (size_t)nj));
+  w.last = (uint32_t*)(b + 5 * o4 + 4 * o1 + al(16 * (size_t)nj));
   w.h_best = ctx->h_scc.h;
   w.h_last = (uint32_t*)(ctx->h_scc.h + 2 * nj);
+  w.hint = round >= 0 ? ctx->scc_memo[round].second.data() : none.data();
   uint8_t* removed = (uint8_t*)ctx->removed.ptr;
   if ((rc = largest_component_set(row_ptr, col, n_cells, K, B ? B->d_jobs : nullptr, nj, removed,
                                   w, s)))
@@ -1541,7 +1555,7 @@ int32_t solve_batch(gis_ctx* ctx, const std::vector<JobSpec>& specs, int32_t K, 
       const Counters keep = *ctx->h_counters;
       std::vector<JobStats> build_stats(ctx->h_stats, ctx->h_stats + nj);
       if ((rc = largest_component_stage(ctx, gr.row_ptr, gr.col, gr.out, n_cells, K, kept, mask, s,
-                                        &B, lv, ix)))
+                                        &B, lv, ix, r)))
         return fail_all(rc);
       if (!last && (rc = enqueue_subdivide(ctx, B, lv, ix, kept, o.boundary_rule,
                                            (uint8_t*)ctx->bnd.ptr, (uint8_t*)lvN.ptr,

@@ -156,11 +156,13 @@ int32_t batch_mark_dropped(const BatchArgs& b, const uint8_t* kept, hipStream_t 
 // host memory of [2 * n_jobs] and h_last of one word.
 struct SccWork {
   int32_t *color, *comp, *size, *minid;
+  uint32_t* rose;  // per cell: the colour sweep that last raised its colour
   uint8_t *rem, *bw, *loop, *inset;
   unsigned long long *best, *left;
   uint32_t* last;
   unsigned long long* h_best;
   uint32_t* h_last;
+  int32_t* hint;  // host, per pass (trim, colour, backward, reach): sweeps needed, in and out
 };
 // removed: in, the non-leaving analysis' removed flags; out, 1 for every cell
 // outside the largest component with a cycle and the cells with a path into

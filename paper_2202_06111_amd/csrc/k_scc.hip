@@ -18,10 +18,14 @@
 //
 // All passes are in-place sweeps over the rows (one thread per row, the
 // row's cell from row / K) to a fixed point, checked every few sweeps: each
-// sweep that changes something records its number, and a batch whose last
-// sweep changed nothing has converged.  Sweeps alternate between ascending
-// and descending row order, so that a change travels far along paths of
-// either direction within one sweep.
+// sweep that changes something records its number (numbers grow through a
+// pass), a sweep whose predecessor changed nothing returns at once, and a
+// batch whose last sweep changed nothing has converged.  Sweeps alternate
+// between ascending and descending row order, so that a change travels far
+// along paths of either direction within one sweep.  A colour sweep takes
+// only the rows of cells whose colour rose in the previous sweep or in this
+// one (the sweep number of each cell's last rise is kept): a colour that
+// stays put has already been passed on.
 #include "gis_launch.h"
 
 namespace gis {
@@ -36,6 +40,11 @@ __device__ __forceinline__ int64_t first_cell(const Job* jobs, int32_t j) {
   return jobs ? jobs[j].cell_off : 0;
 }
 
+// sweep s - 1 changed nothing: the pass has converged
+__device__ __forceinline__ bool converged(const uint32_t* last, uint32_t sweep) {
+  return sweep > 1 && *last < sweep - 1;
+}
+
 // candidates = the non-leaving cells; no component assigned yet
 __global__ void k_scc_begin(int64_t n, const uint8_t* removed, uint8_t* rem, int32_t* comp) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
@@ -47,7 +56,9 @@ __global__ void k_scc_begin(int64_t n, const uint8_t* removed, uint8_t* rem, int
 
 // backward trim, one step: mark the candidates with a candidate predecessor
 __global__ void k_scc_haspred(const int64_t* row_ptr, const int32_t* col, int64_t n_rows,
-                              int32_t K, const uint8_t* rem, uint8_t* haspred) {
+                              int32_t K, const uint8_t* rem, uint8_t* haspred,
+                              const uint32_t* last, uint32_t sweep) {
+  if (converged(last, sweep)) return;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
        r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = r / K;
@@ -57,26 +68,31 @@ __global__ void k_scc_haspred(const int64_t* row_ptr, const int32_t* col, int64_
   }
 }
 
-// ... and drop the candidates without one (no cycle passes through them)
-__global__ void k_scc_trim(int64_t n, uint8_t* rem, const uint8_t* haspred, uint32_t* last,
+// ... and drop the candidates without one (no cycle passes through them);
+// the marks are cleared for the next sweep
+__global__ void k_scc_trim(int64_t n, uint8_t* rem, uint8_t* haspred, uint32_t* last,
                            uint32_t sweep) {
+  if (converged(last, sweep)) return;  // as k_scc_haspred of this sweep did
   bool changed = false;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (int64_t)gridDim.x * blockDim.x)
+       c += (int64_t)gridDim.x * blockDim.x) {
     if (rem[c] && !haspred[c]) {
       rem[c] = 0;
       changed = true;
     }
+    haspred[c] = 0;
+  }
   const uint64_t m = __ballot(changed);  // one atomic per wave
   if (m && (threadIdx.x & 63) == 0) atomicMax(last, sweep);
 }
 
 // a round's start: own colours, cleared reach flags and tallies
-__global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint8_t* bw,
-                            int32_t* size, int32_t* minid, uint8_t* loop) {
+__global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint32_t* rose,
+                            uint8_t* bw, int32_t* size, int32_t* minid, uint8_t* loop) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
     color[c] = rem[c] ? (int32_t)c : -1;
+    rose[c] = 0;
     bw[c] = 0;
     size[c] = 0;
     minid[c] = INT32_MAX;
@@ -84,20 +100,23 @@ __global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint8
   }
 }
 
-// one sweep of max-colour propagation along the edges of candidate cells
+// one sweep of max-colour propagation along the edges of candidate cells;
+// rose[c] is the sweep that last raised colour[c] (0: its own id)
 __global__ void k_scc_color(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
-                            const uint8_t* rem, int32_t* color, uint32_t* last, uint32_t sweep) {
+                            const uint8_t* rem, int32_t* color, uint32_t* rose, uint32_t* last,
+                            uint32_t sweep) {
+  if (converged(last, sweep)) return;
   bool changed = false;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = (sweep & 1) ? q : n_rows - 1 - q;
     const int64_t c = r / K;
-    if (!rem[c]) continue;
+    if (!rem[c] || rose[c] + 1 < sweep) continue;
     const int32_t cc = color[c];
     for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
       const int32_t v = col[e];
-      if (rem[v] && color[v] < cc) {
-        atomicMax(&color[v], cc);
+      if (rem[v] && color[v] < cc && atomicMax(&color[v], cc) < cc) {
+        rose[v] = sweep;
         changed = true;
       }
     }
@@ -118,6 +137,7 @@ __global__ void k_scc_roots(int64_t n, const uint8_t* rem, const int32_t* color,
 __global__ void k_scc_back(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
                            const uint8_t* rem, const int32_t* color, uint8_t* bw, uint32_t* last,
                            uint32_t sweep) {
+  if (converged(last, sweep)) return;
   bool changed = false;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
        q += (int64_t)gridDim.x * blockDim.x) {
@@ -203,6 +223,7 @@ __global__ void k_scc_seed(int64_t n, const Job* jobs, int32_t n_jobs, const int
 // one sweep of the backward search from the set over all cells
 __global__ void k_scc_reach(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
                             uint8_t* inset, uint32_t* last, uint32_t sweep) {
+  if (converged(last, sweep)) return;
   bool changed = false;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
        q += (int64_t)gridDim.x * blockDim.x) {
@@ -231,20 +252,28 @@ unsigned blocks_for(int64_t n) {
   return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
-// Runs `sweep(id)` in batches until a batch's last sweep changed nothing;
-// at most `bound` sweeps (then the pass did not converge: internal error).
+// Runs `sweep(id)` for id = 1, 2, ... in batches until a batch's last sweep
+// changed nothing (the sweeps after a sweep that changed nothing return at
+// once, so a batch may overshoot cheaply); at most `bound` sweeps (then the
+// pass did not converge: internal error).  The first batch is w.hint[pass]
+// (what the same pass of the same round needed in the caller's last solve)
+// plus a margin, so that most passes end at their first check; the pass
+// leaves the sweeps it needed there.
 template <typename F>
-int32_t to_fixed_point(const SccWork& w, int64_t bound, hipStream_t s, F&& sweep) {
-  int32_t batch = 4;
+int32_t to_fixed_point(const SccWork& w, int pass, int64_t bound, hipStream_t s, F&& sweep) {
+  int32_t rc = fill_u32(w.last, 0u, 1, s);
+  if (rc) return rc;
+  int32_t batch = w.hint[pass] + 4 > 8 ? w.hint[pass] + 4 : 8;
   for (int64_t done = 0;;) {
-    int32_t rc = fill_u32(w.last, 0u, 1, s);
-    if (rc) return rc;
     for (int32_t i = 1; i <= batch; ++i)
-      if ((rc = sweep((uint32_t)i))) return rc;
+      if ((rc = sweep((uint32_t)(done + i)))) return rc;
     GIS_HIP(hipMemcpyAsync(w.h_last, w.last, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     GIS_HIP(hipStreamSynchronize(s));
     done += batch;
-    if (*w.h_last < (uint32_t)batch) return GIS_OK;
+    if (*w.h_last < (uint32_t)done) {
+      w.hint[pass] = (int32_t)*w.h_last + 1;  // incl. the sweep that changed nothing
+      return GIS_OK;
+    }
     if (done > bound) {
       set_error("internal: a component search did not converge");
       return GIS_E_INTERNAL;
@@ -269,14 +298,12 @@ int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_
   // dropping them layer by layer leaves the cycles and the cells between
   // them (the non-leaving set's transient cells would otherwise take one
   // search round per layer)
-  rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
-    int32_t e = fill_u8(w.bw, 0, n_cells, s);
-    if (e) return e;
+  if ((rc = fill_u8(w.bw, 0, n_cells, s))) return rc;
+  rc = to_fixed_point(w, 0, n_cells + 1, s, [&](uint32_t id) -> int32_t {
     hipLaunchKernelGGL(k_scc_haspred, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
-                       (const uint8_t*)w.rem, w.bw);
+                       (const uint8_t*)w.rem, w.bw, (const uint32_t*)w.last, id);
     GIS_LAUNCH_CHECK("k_scc_haspred");
-    hipLaunchKernelGGL(k_scc_trim, dim3(gc), dim3(256), 0, s, n_cells, w.rem,
-                       (const uint8_t*)w.bw, w.last, id);
+    hipLaunchKernelGGL(k_scc_trim, dim3(gc), dim3(256), 0, s, n_cells, w.rem, w.bw, w.last, id);
     GIS_LAUNCH_CHECK("k_scc_trim");
     return GIS_OK;
   });
@@ -287,11 +314,11 @@ int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_
       return GIS_E_INTERNAL;
     }
     hipLaunchKernelGGL(k_scc_round, dim3(gc), dim3(256), 0, s, n_cells, (const uint8_t*)w.rem,
-                       w.color, w.bw, w.size, w.minid, w.loop);
+                       w.color, w.rose, w.bw, w.size, w.minid, w.loop);
     GIS_LAUNCH_CHECK("k_scc_round");
-    rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+    rc = to_fixed_point(w, 1, n_cells + 1, s, [&](uint32_t id) -> int32_t {
       hipLaunchKernelGGL(k_scc_color, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
-                         (const uint8_t*)w.rem, w.color, w.last, id);
+                         (const uint8_t*)w.rem, w.color, w.rose, w.last, id);
       GIS_LAUNCH_CHECK("k_scc_color");
       return GIS_OK;
     });
@@ -299,7 +326,7 @@ int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_
     hipLaunchKernelGGL(k_scc_roots, dim3(gc), dim3(256), 0, s, n_cells, (const uint8_t*)w.rem,
                        (const int32_t*)w.color, w.bw);
     GIS_LAUNCH_CHECK("k_scc_roots");
-    rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+    rc = to_fixed_point(w, 2, n_cells + 1, s, [&](uint32_t id) -> int32_t {
       hipLaunchKernelGGL(k_scc_back, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K,
                          (const uint8_t*)w.rem, (const int32_t*)w.color, w.bw, w.last, id);
       GIS_LAUNCH_CHECK("k_scc_back");
@@ -332,7 +359,7 @@ int32_t largest_component_set(const int64_t* row_ptr, const int32_t* col, int64_
   hipLaunchKernelGGL(k_scc_seed, dim3(gc), dim3(256), 0, s, n_cells, jobs, n_jobs,
                      (const int32_t*)w.comp, (const unsigned long long*)w.best, w.inset);
   GIS_LAUNCH_CHECK("k_scc_seed");
-  rc = to_fixed_point(w, n_cells + 1, s, [&](uint32_t id) -> int32_t {
+  rc = to_fixed_point(w, 3, n_cells + 1, s, [&](uint32_t id) -> int32_t {
     hipLaunchKernelGGL(k_scc_reach, dim3(gr), dim3(256), 0, s, row_ptr, col, n_rows, K, w.inset,
                        w.last, id);
     GIS_LAUNCH_CHECK("k_scc_reach");
