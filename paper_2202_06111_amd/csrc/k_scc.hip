@@ -101,28 +101,64 @@ __global__ void k_scc_round(int64_t n, const uint8_t* rem, int32_t* color, uint3
 }
 
 // one sweep of max-colour propagation along the edges of candidate cells;
-// rose[c] is the sweep that last raised colour[c] (0: its own id)
-__global__ void k_scc_color(const int64_t* row_ptr, const int32_t* col, int64_t n_rows, int32_t K,
-                            const uint8_t* rem, int32_t* color, uint32_t* rose, uint32_t* last,
-                            uint32_t sweep) {
+// rose[c] is the sweep that last raised colour[c] (0: its own id).
+//
+// A block takes 256 rows at a time.  The cells it raises are also queued in
+// LDS, and while there are any (at most kColQ; the rest wait for the next
+// sweep, which takes them through rose[]) the block passes their colours on
+// itself, for up to kColDepth generations: a colour then travels that many
+// more edges per launch.  Each step is a valid max-colour update, so the
+// fixed point is the same.
+constexpr int kColQ = 256;
+constexpr int kColDepth = 16;
+
+__global__ __launch_bounds__(256) void k_scc_color(const int64_t* row_ptr, const int32_t* col,
+                                                   int64_t n_rows, int32_t K, const uint8_t* rem,
+                                                   int32_t* color, uint32_t* rose,
+                                                   uint32_t* last, uint32_t sweep) {
   if (converged(last, sweep)) return;
+  __shared__ int32_t s_q[2][kColQ];
+  __shared__ int32_t s_n[2];
+  const int t = threadIdx.x;
   bool changed = false;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_rows;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = (sweep & 1) ? q : n_rows - 1 - q;
-    const int64_t c = r / K;
-    if (!rem[c] || rose[c] + 1 < sweep) continue;
-    const int32_t cc = color[c];
+  // passes row r's colour cc on; raised cells go to list o
+  auto pass_on = [&](int64_t r, int32_t cc, int o) {
     for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
       const int32_t v = col[e];
       if (rem[v] && color[v] < cc && atomicMax(&color[v], cc) < cc) {
         rose[v] = sweep;
         changed = true;
+        const int k = atomicAdd(&s_n[o], 1);
+        if (k < kColQ) s_q[o][k] = v;
       }
+    }
+  };
+  for (int64_t tile = blockIdx.x; tile * 256 < n_rows; tile += gridDim.x) {
+    if (t == 0) s_n[0] = 0;
+    __syncthreads();
+    const int64_t q = tile * 256 + t;
+    if (q < n_rows) {
+      const int64_t r = (sweep & 1) ? q : n_rows - 1 - q;
+      const int64_t c = r / K;
+      if (rem[c] && rose[c] + 1 >= sweep) pass_on(r, color[c], 0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int depth = 0; depth < kColDepth; ++depth) {
+      const int n = s_n[cur] < kColQ ? s_n[cur] : kColQ;  // the same in every thread
+      if (n == 0) break;
+      if (t == 0) s_n[cur ^ 1] = 0;
+      __syncthreads();
+      for (int k = t; k < n * K; k += 256) {
+        const int32_t v = s_q[cur][k / K];
+        pass_on((int64_t)v * K + k % K, color[v], cur ^ 1);
+      }
+      __syncthreads();
+      cur ^= 1;
     }
   }
   const uint64_t m = __ballot(changed);  // one atomic per wave
-  if (m && (threadIdx.x & 63) == 0) atomicMax(last, sweep);
+  if (m && (t & 63) == 0) atomicMax(last, sweep);
 }
 
 // roots: candidate cells whose colour is their own id
