@@ -103,6 +103,30 @@ def test_prune_planted_components(G, ctx, seed, K):
     _prune(G, ctx, n, K, row_ptr, col, sweep_edges=0, wit_sweeps=0)  # non-leaving phase on the frontier
 
 
+@pytest.mark.parametrize("K", [1, 2])
+def test_prune_wide_hub_and_long_ring(G, ctx, K):
+    """A hub cell with the largest id of its component and an edge to each
+    of 1,000 cells that all lead back to it (one colour sweep raises more
+    cells than a block can queue, so the rest wait for the next sweep), a
+    ring of 2,000 cells whose largest id must travel the whole ring (many
+    locally followed generations and many sweeps), and tails into both:
+    the ring is the largest component."""
+    hub = 1000
+    edges = {(hub, 0): list(range(hub))}
+    for c in range(hub):
+        edges[(c, c % K)] = [hub]
+    ring = list(range(3000, 1000, -1))  # 3000 -> 2999 -> ... -> 1001 -> 3000
+    for i, c in enumerate(ring):
+        edges[(c, i % K)] = [ring[(i + 1) % len(ring)]]
+    for t in range(3001, 3101):  # tails: into the ring, into the star, and chains of both
+        edges[(t, 0)] = [1001 + (t * 7) % 2000] if t % 3 else [t % hub]
+        if t % 5 == 0:
+            edges[(t, K - 1)] = sorted(set(edges.get((t, K - 1), []) + [t - 1]))
+    n = 3101
+    row_ptr, col = _graph(n, K, edges)
+    _prune(G, ctx, n, K, row_ptr, col)
+
+
 def _check_solve(G, wl, sols_or_sol, ctx):
     want = oracle.solve(wl.system, wl.grid, wl.samples, wl.u, wl.rounds, rule=wl.boundary_rule,
                         analysis=wl.analysis, subdivision=wl.subdivision)
