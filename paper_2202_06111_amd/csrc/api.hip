@@ -1131,7 +1131,7 @@ void next_sizes(gis_ctx* ctx, Batch& B, int64_t n_new, std::vector<int64_t>& cel
 
 // Device blocks of solutions.  A freed block is kept for the process's later
 // solutions (at most kCacheBlocks blocks and kCacheBytes bytes per device)
-// instead of going back to the driver, so a loop of solves stops allocating
+// instead of being released with hipFree, so a loop of solves stops allocating
 // after its first iterations.  Cached blocks are never returned.
 constexpr size_t kCacheBlocks = 32;
 constexpr size_t kCacheBytes = (size_t)1 << 30;
